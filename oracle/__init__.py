@@ -1,0 +1,156 @@
+"""Python wrapper of the FP64 CPU oracle (``crk_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg. The GPU library never imports or links it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "crk_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Plain optimisation, no fast-math, no FMA contraction, portable ISA.
+CXXFLAGS = ["-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+            "-ffp-contract=off"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", *CXXFLAGS, _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        D = C.POINTER(C.c_double)
+        I64 = C.POINTER(C.c_int64)
+        _lib.oracle_kernel_eval.argtypes = [C.c_int, C.c_int64, D, D, D, D]
+        _lib.oracle_neighbours.argtypes = [C.c_int64, D, D, C.c_double, C.c_int, C.c_int, I64, I64]
+        _lib.oracle_neighbours.restype = C.c_int
+        common = [C.c_int64, D, D, D, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
+                  C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
+        _lib.oracle_forward.argtypes = common + [D] * 14 + [I64]
+        _lib.oracle_forward.restype = C.c_int
+        _lib.oracle_jvp.argtypes = common + [D, D, D, C.c_double, C.c_double] + [D] * 7
+        _lib.oracle_jvp.restype = C.c_int
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _pi(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _c(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+@dataclass
+class Params:
+    box: float = 1.0
+    gamma: float = 5.0 / 3.0
+    alpha: float = 1.0
+    beta: float = 2.0
+    eps2: float = 0.01
+    n_h: float = 2.4814
+    dt_relax: float = 0.0
+    kernel: int = 0          # 0 cubic spline, 1 Wendland C4
+    h_mode: int = 1          # 0 fixed, 1 solve
+
+    def args(self):
+        return [self.box, self.gamma, self.alpha, self.beta, self.eps2, self.n_h, self.dt_relax,
+                self.kernel, self.h_mode]
+
+
+def kernel_eval(kernel: int, q):
+    q = _c(q).ravel()
+    w = np.empty_like(q)
+    dw = np.empty_like(q)
+    norm = np.zeros(1)
+    lib().oracle_kernel_eval(kernel, q.size, _p(q), _p(w), _p(dw), _p(norm))
+    return w, dw, float(norm[0])
+
+
+def neighbours(x, h, box=1.0, mode=0, kind=0, lists=False):
+    x = _c(x)
+    h = _c(h)
+    n = h.size
+    counts = np.zeros(n, dtype=np.int64)
+    rc = lib().oracle_neighbours(n, _p(x), _p(h), box, mode, kind, _pi(counts), None)
+    if rc:
+        raise RuntimeError("oracle_neighbours failed: %d" % rc)
+    if not lists:
+        return counts
+    out = np.zeros(int(counts.sum()), dtype=np.int64)
+    rc = lib().oracle_neighbours(n, _p(x), _p(h), box, mode, kind, _pi(counts), _pi(out))
+    if rc:
+        raise RuntimeError("oracle_neighbours failed: %d" % rc)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    return [out[off[i]:off[i + 1]] for i in range(n)]
+
+
+def forward(x, v, m, u, h, params: Params, nbr_mode: int = 0) -> dict:
+    """FP64 forward. Returns a dict of numpy arrays (SoA) and the pair stats."""
+    x, v, m, u, h = _c(x), _c(v), _c(m), _c(u), _c(h)
+    n = m.size
+    o = {k: np.zeros(s) for k, s in [("h", n), ("V", n), ("rho", n), ("A", n), ("B", (3, n)),
+                                      ("gradA", (3, n)), ("gradB", (9, n)), ("gradv", (9, n)),
+                                      ("P", n), ("c", n), ("accel", (3, n)), ("dudt", n),
+                                      ("scale_a", n), ("scale_u", n)]}
+    stats = np.zeros(6, dtype=np.int64)
+    rc = lib().oracle_forward(n, _p(x), _p(v), _p(m), _p(u), _p(h), *params.args(), nbr_mode,
+                              *[_p(o[k]) for k in ["h", "V", "rho", "A", "B", "gradA", "gradB",
+                                                   "gradv", "P", "c", "accel", "dudt",
+                                                   "scale_a", "scale_u"]], _pi(stats))
+    if rc:
+        raise RuntimeError("oracle_forward failed: %d" % rc)
+    o["pairs_gather"], o["pairs_force"], o["h_iters_max"], o["h_unconverged"], \
+        o["m2_singular"], o["relaxed"] = [int(s) for s in stats]
+    return o
+
+
+def jvp(x, v, m, u, h, params: Params, dx, dv, du, dalpha=0.0, dbeta=0.0,
+        nbr_mode: int = 0) -> dict:
+    """Exact directional derivative of the forward along (dx, dv, du, dalpha, dbeta)."""
+    x, v, m, u, h = _c(x), _c(v), _c(m), _c(u), _c(h)
+    dx, dv, du = _c(dx, x.shape), _c(dv, v.shape), _c(du, u.shape)
+    n = m.size
+    o = {k: np.zeros(s) for k, s in [("accel", (3, n)), ("dudt", n), ("d_accel", (3, n)),
+                                      ("d_dudt", n), ("d_h", n), ("d_V", n), ("d_rho", n)]}
+    rc = lib().oracle_jvp(n, _p(x), _p(v), _p(m), _p(u), _p(h), *params.args(), nbr_mode,
+                          _p(dx), _p(dv), _p(du), float(dalpha), float(dbeta),
+                          *[_p(o[k]) for k in ["accel", "dudt", "d_accel", "d_dudt", "d_h",
+                                               "d_V", "d_rho"]])
+    if rc:
+        raise RuntimeError("oracle_jvp failed: %d" % rc)
+    return o
+
+
+def params_for(ps, **kw) -> Params:
+    """Oracle parameters for a synth.ParticleSet (kernel radius h, n_h, h mode, box)."""
+    p = Params(box=ps.box, n_h=ps.n_h, h_mode=ps.h_mode)
+    for k, val in kw.items():
+        setattr(p, k, val)
+    return p
