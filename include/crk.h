@@ -1,0 +1,164 @@
+/*
+ * crk.h - C ABI of the MI355X CRKSPH neighbour-pair library (libcrk.so).
+ *
+ * The library evaluates, for one set of gas particles in a periodic cube,
+ * the CRKSPH hydro passes of CRK-HACC (arXiv:2511.21921):
+ *
+ *   smoothing length h   : root of the Thacker neighbour condition
+ *                          Delta_N = 1, Delta_N^3 = V n_h^3 / h^3
+ *                          (App. A.3, eq. thacker), or h held fixed;
+ *   volume V             : V_i^-1 = m_i^-1 sum_j m_j W(|x_ij|, h_i)
+ *                          (App. A.2, eq. Vg);
+ *   corrections A, B     : the reproducing-kernel coefficients of
+ *   and their gradients    W^R_ij = A_i (1 + B_i . x_ij) W_ij(h_i)
+ *                          (App. A.1, eq. RK), from the local geometric
+ *                          moments, with the 3x3 second-moment solve in FP64;
+ *   density rho          : sum m_j V_j W^R_ij / sum V_j^2 W^R_ij
+ *                          (Sec. 2.5.1, eq. rhow, gas-only form);
+ *   velocity gradient    : -sum_j V_j (v_i - v_j) (x) grad W^R_ij
+ *                          (App. A.1, eq. gradv);
+ *   accel, du/dt         : pairwise momentum and compatible energy with a
+ *                          limited artificial viscosity (Sec. 2.1), optional
+ *                          RK relaxation of a pair (App. A.1).
+ *
+ * and the reverse-mode derivative (adjoint) of a loss
+ * L = sum_i g_accel_i . accel_i + sum_i g_dudt_i dudt_i
+ * with respect to positions, velocities, internal energies and the
+ * viscosity coefficients alpha, beta.
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are structure-of-arrays in the caller's particle order:
+ *    a vector field is [3][n] (component-major), gradB is [9][n] with row
+ *    g*3+a = d_g B^a, gradv is [9][n] with row a*3+g = d_g v^a.
+ *  - Every array argument is a DEVICE pointer owned by the caller; the
+ *    library never frees or retains caller memory beyond the call.
+ *  - "Real" arrays are float in CRK_FP32 mode and double in CRK_FP64 mode;
+ *    positions, accelerations, du/dt and all gradients are always double.
+ *  - Work is enqueued on the given HIP stream (hipStream_t passed as void*,
+ *    NULL = default stream). The call may synchronise that stream to read
+ *    small control values (the largest h, overflow and capping flags).
+ *  - A crk_ctx is not thread-safe; use one context per stream.
+ *  - Status codes: CRK_OK on success; CRK_EINVAL for a null pointer,
+ *    negative n or a bad parameter; CRK_EDOMAIN when a smoothing length
+ *    reaches half the box (minimum image undefined); CRK_ENOMEM when device
+ *    memory cannot be allocated; CRK_EHIP for any other HIP runtime error;
+ *    CRK_ENOTCONV when the h solve did not converge for some particle (the
+ *    outputs are still written); CRK_ENONFINITE when check_finite is set and
+ *    an output is not finite. crk_last_error() gives a readable message.
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct crk_ctx crk_ctx;
+
+typedef enum {
+  CRK_OK = 0,
+  CRK_EINVAL = -1,
+  CRK_ENOMEM = -2,
+  CRK_EHIP = -3,
+  CRK_EDOMAIN = -4,
+  CRK_ENOTCONV = -5,
+  CRK_ENONFINITE = -6
+} crk_status;
+
+typedef enum { CRK_CUBIC_SPLINE = 0, CRK_WENDLAND_C4 = 1 } crk_kernel;
+
+/* CRK_FP32: FP32 pair arithmetic, FP64 correction solve and force/energy
+ * accumulators (the paper's single-precision force kernels, App. A.4).
+ * CRK_FP64: every step in FP64. */
+typedef enum { CRK_FP32 = 0, CRK_FP64 = 1 } crk_precision;
+
+typedef struct {
+  double box;        /* periodic cube side L > 0 */
+  double gamma;      /* adiabatic index, 5/3 (Sec. 2.4.1) */
+  double alpha;      /* viscosity linear coefficient */
+  double beta;       /* viscosity quadratic coefficient */
+  double eps2;       /* viscosity softening, e.g. 0.01 */
+  double n_h;        /* particles per kernel radius; N = 4 pi/3 n_h^3 (App. A.2) */
+  int kernel;        /* crk_kernel; support radius h (App. A.2) */
+  int precision;     /* crk_precision */
+  int h_mode;        /* 0: h is an input; 1: solve for h (input = first guess) */
+  int h_max_iter;    /* Newton/bisection iteration cap, e.g. 60 */
+  double h_rtol;     /* relative h tolerance, e.g. 1e-6 (FP32), 1e-13 (FP64) */
+  double dt_relax;   /* RK relaxation time step (App. A.1); 0 disables */
+  int store_corrections; /* 1: keep moments for the adjoint; 0: recompute them */
+  int check_finite;  /* 1: count non-finite outputs and fail with CRK_ENONFINITE */
+} crk_params;
+
+typedef struct {
+  long long n_pairs_gather; /* sum_i |{j != i : r_ij < h_i}| */
+  long long n_pairs_force;  /* sum_i |{j != i : r_ij < max(h_i, h_j)}| */
+  int h_iter_max;           /* largest Newton/bisection count */
+  int h_unconverged;        /* particles whose h solve hit the iteration cap */
+  int m2_singular;          /* particles with a singular second moment (uncorrected kernel) */
+  int relaxed;              /* particles flagged by the relaxation criterion */
+  int nonfinite;            /* non-finite outputs (check_finite only) */
+  int grid;                 /* cells per box side used by the cell list */
+} crk_stats;
+
+/* Fills *p with the defaults for the given precision. */
+void crk_default_params(crk_params *p, int precision);
+
+/* Creates a context; *ctx receives it. Validates p (box > 0, n_h > 0,
+ * kernel and precision in range). Allocates nothing on the device. */
+crk_status crk_create(crk_ctx **ctx, const crk_params *p);
+
+/* Replaces the parameters of an existing context. */
+crk_status crk_set_params(crk_ctx *ctx, const crk_params *p);
+
+/* Pre-allocates device workspace for up to n_max particles so that later
+ * calls with n <= n_max allocate only if a neighbour list outgrows it. */
+crk_status crk_reserve(crk_ctx *ctx, long long n_max);
+
+/* Releases the context and all workspace it owns. NULL is accepted. */
+crk_status crk_destroy(crk_ctx *ctx);
+
+/* Readable message of the last failing call on ctx ("" if none). */
+const char *crk_last_error(const crk_ctx *ctx);
+
+/* Forward evaluation.
+ *   x      [3][n] double  positions; wrapped into [0, box) internally
+ *   v      [3][n] Real    velocities
+ *   m      [n] Real       masses (> 0)
+ *   u      [n] Real       specific internal energies (> 0)
+ *   h      [n] Real       in: fixed h (h_mode 0) or first guess (h_mode 1);
+ *                         out: the h used (solved in h_mode 1)
+ *   V, rho [n] Real       volume and density
+ *   A      [n] Real, B [3][n], gradA [3][n], gradB [9][n]  corrections
+ *   gradv  [9][n] Real    velocity gradient
+ *   accel  [3][n] double  dv/dt from the hydro pairs
+ *   dudt   [n] double     du/dt (compatible energy)
+ *   stats  host pointer or NULL; when given, the call synchronises the
+ *          stream and fills it.
+ * n = 0 is a no-op returning CRK_OK. Input and output arrays must not
+ * overlap. The context keeps the cell list, neighbour list and the sorted
+ * intermediates for a following crk_backward. */
+crk_status crk_forward(crk_ctx *ctx, void *hip_stream, long long n, const double *x,
+                       const void *v, const void *m, const void *u, void *h, void *V,
+                       void *rho, void *A, void *B, void *gradA, void *gradB, void *gradv,
+                       double *accel, double *dudt, crk_stats *stats);
+
+/* Reverse-mode derivative of L = sum g_accel . accel + sum g_dudt dudt for
+ * the most recent crk_forward on ctx, which must have had the same n (the
+ * inputs themselves are taken from the state kept by that forward).
+ *   g_accel [3][n] double, g_dudt [n] double   loss weights (device)
+ *   g_x [3][n], g_v [3][n], g_u [n]            outputs (device, double)
+ *   g_alpha_beta [2]                            output (device, double)
+ * With h_mode 1 the smoothing lengths are functions of the positions (the
+ * implicit-function term is included); with h_mode 0 they are constants.
+ * Masses are constants. Returns CRK_EINVAL if no matching forward exists. */
+crk_status crk_backward(crk_ctx *ctx, void *hip_stream, long long n, const double *g_accel,
+                        const double *g_dudt, double *g_x, double *g_v, double *g_u,
+                        double *g_alpha_beta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRK_H */

@@ -1,0 +1,220 @@
+"""Python binding of libcrk.so: argument marshalling only.
+
+Every step of the CRKSPH path runs inside libcrk.so (HIP kernels for
+gfx950). PyTorch supplies device memory and the current stream. There is no
+fallback: if the library or a HIP device is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrk.so")
+
+CUBIC_SPLINE, WENDLAND_C4 = 0, 1
+FP32, FP64 = 0, 1
+
+STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: "CRK_EDOMAIN",
+          -5: "CRK_ENOTCONV", -6: "CRK_ENONFINITE"}
+
+
+class CrkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class crk_params(C.Structure):
+    _fields_ = [("box", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("eps2", C.c_double), ("n_h", C.c_double),
+                ("kernel", C.c_int), ("precision", C.c_int), ("h_mode", C.c_int),
+                ("h_max_iter", C.c_int), ("h_rtol", C.c_double), ("dt_relax", C.c_double),
+                ("store_corrections", C.c_int), ("check_finite", C.c_int)]
+
+
+class crk_stats(C.Structure):
+    _fields_ = [("n_pairs_gather", C.c_longlong), ("n_pairs_force", C.c_longlong),
+                ("h_iter_max", C.c_int), ("h_unconverged", C.c_int), ("m2_singular", C.c_int),
+                ("relaxed", C.c_int), ("nonfinite", C.c_int), ("grid", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
+           "crk_last_error", "crk_forward", "crk_backward"]
+
+_lib = None
+
+
+def lib():
+    """Loads libcrk.so (built by paper_2511_21921_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcrk.so is not built: run __graft_entry__.build() "
+                               "or python paper_2511_21921_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.crk_default_params.argtypes = [C.POINTER(crk_params), C.c_int]
+        L.crk_default_params.restype = None
+        L.crk_create.argtypes = [C.POINTER(P), C.POINTER(crk_params)]
+        L.crk_create.restype = C.c_int
+        L.crk_set_params.argtypes = [P, C.POINTER(crk_params)]
+        L.crk_set_params.restype = C.c_int
+        L.crk_reserve.argtypes = [P, C.c_longlong]
+        L.crk_reserve.restype = C.c_int
+        L.crk_destroy.argtypes = [P]
+        L.crk_destroy.restype = C.c_int
+        L.crk_last_error.argtypes = [P]
+        L.crk_last_error.restype = C.c_char_p
+        L.crk_forward.argtypes = [P, P, C.c_longlong] + [P] * 14 + [C.POINTER(crk_stats)]
+        L.crk_forward.restype = C.c_int
+        L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 7
+        L.crk_backward.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Params:
+    box: float = 1.0
+    gamma: float = 5.0 / 3.0
+    alpha: float = 1.0
+    beta: float = 2.0
+    eps2: float = 0.01
+    n_h: float = 2.4814
+    kernel: int = CUBIC_SPLINE
+    precision: int = FP32
+    h_mode: int = 1
+    h_max_iter: int = 60
+    h_rtol: float | None = None      # default: 1e-6 (FP32) / 1e-13 (FP64)
+    dt_relax: float = 0.0
+    store_corrections: int = 0
+    check_finite: int = 0
+
+    def to_c(self) -> crk_params:
+        p = crk_params()
+        lib().crk_default_params(C.byref(p), int(self.precision))
+        for k, _ in crk_params._fields_:
+            val = getattr(self, k)
+            if val is not None:
+                setattr(p, k, val)
+        return p
+
+    @property
+    def real(self) -> torch.dtype:
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(t: torch.Tensor, dtype, shape, name):
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+class Context:
+    """Owns one crk_ctx (device workspace, cell list and the last forward's state)."""
+
+    def __init__(self, params: Params):
+        self.params = params
+        self._cp = params.to_c()
+        h = C.c_void_p()
+        st = lib().crk_create(C.byref(h), C.byref(self._cp))
+        if st != 0:
+            raise CrkError(st, "crk_create rejected the parameters")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().crk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        cp = params.to_c()
+        self._raise(lib().crk_set_params(self._h, C.byref(cp)))
+        self.params, self._cp = params, cp
+
+    def reserve(self, n: int):
+        self._raise(lib().crk_reserve(self._h, int(n)))
+
+    def last_error(self) -> str:
+        return lib().crk_last_error(self._h).decode()
+
+    def _raise(self, st: int, allow=()):
+        if st != 0 and st not in allow:
+            raise CrkError(st, self.last_error())
+        return st
+
+    def forward(self, x: torch.Tensor, v: torch.Tensor, m: torch.Tensor, u: torch.Tensor,
+                h: torch.Tensor, stats: bool = False, out: dict | None = None) -> dict:
+        """Runs the forward passes. x is float64 [3, n]; v [3, n], m, u, h [n] are Real.
+
+        Returns a dict with h, V, rho, A, B, gradA, gradB, gradv (Real), accel,
+        dudt (float64) and, if stats is set, the crk_stats fields.
+        """
+        n = int(m.shape[0])
+        R = self.params.real
+        dev = x.device
+        _check(x, torch.float64, (3, n), "x")
+        _check(v, R, (3, n), "v")
+        for t, name in [(m, "m"), (u, "u"), (h, "h")]:
+            _check(t, R, (n,), name)
+        if out is None:
+            out = {
+                "h": h.clone(), "V": torch.empty(n, dtype=R, device=dev),
+                "rho": torch.empty(n, dtype=R, device=dev), "A": torch.empty(n, dtype=R, device=dev),
+                "B": torch.empty(3, n, dtype=R, device=dev),
+                "gradA": torch.empty(3, n, dtype=R, device=dev),
+                "gradB": torch.empty(9, n, dtype=R, device=dev),
+                "gradv": torch.empty(9, n, dtype=R, device=dev),
+                "accel": torch.empty(3, n, dtype=torch.float64, device=dev),
+                "dudt": torch.empty(n, dtype=torch.float64, device=dev)}
+        else:
+            out["h"].copy_(h)
+        st = crk_stats()
+        stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        rc = lib().crk_forward(self._h, stream, n, _ptr(x), _ptr(v), _ptr(m), _ptr(u),
+                               _ptr(out["h"]), _ptr(out["V"]), _ptr(out["rho"]), _ptr(out["A"]),
+                               _ptr(out["B"]), _ptr(out["gradA"]), _ptr(out["gradB"]),
+                               _ptr(out["gradv"]), _ptr(out["accel"]), _ptr(out["dudt"]),
+                               C.byref(st) if stats else None)
+        self._raise(rc)
+        if stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def backward(self, g_accel: torch.Tensor, g_dudt: torch.Tensor) -> dict:
+        """Adjoint of the last forward for L = sum g_accel.accel + sum g_dudt dudt."""
+        n = int(g_dudt.shape[0])
+        dev = g_dudt.device
+        _check(g_accel, torch.float64, (3, n), "g_accel")
+        _check(g_dudt, torch.float64, (n,), "g_dudt")
+        o = {"g_x": torch.empty(3, n, dtype=torch.float64, device=dev),
+             "g_v": torch.empty(3, n, dtype=torch.float64, device=dev),
+             "g_u": torch.empty(n, dtype=torch.float64, device=dev),
+             "g_alpha_beta": torch.empty(2, dtype=torch.float64, device=dev)}
+        stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        rc = lib().crk_backward(self._h, stream, n, _ptr(g_accel), _ptr(g_dudt), _ptr(o["g_x"]),
+                                _ptr(o["g_v"]), _ptr(o["g_u"]), _ptr(o["g_alpha_beta"]))
+        self._raise(rc)
+        return o

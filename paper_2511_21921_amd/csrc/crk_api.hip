@@ -1,0 +1,466 @@
+// Context, workspace and the C ABI of libcrk.so (declared in crk.h).
+//
+// A forward call: (1) reads the largest input h and picks the cell grid;
+// (2) builds the cell list (cell keys, stable radix sort, cell starts);
+// (3) gathers the particles into cell-sorted SoA records with FP32/FP64
+// offsets from their cell centre; (4) solves h (or takes it as given) and
+// the volume; (5) builds the symmetric neighbour list; (6) runs the moment,
+// correction, density and force passes. All work is enqueued on the
+// caller's stream; the host reads back three small control words (the
+// largest h, the h-solve status, the list-capacity check).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "crk.h"
+#include "crk_passes.h"
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct crk_ctx {
+  crk_params p;
+  std::string err;
+  // workspace
+  Buf keys_a, keys_b, vals_a, vals_b, cell_count, cell_start, sort_tmp, scan_tmp;
+  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, ng, ns, scr;
+  Buf cnt;
+  // adjoint workspace
+  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_grho, a_ggv, a_gP, a_gc, a_gmom, a_gab, a_coef;
+  unsigned long long* host_cnt = nullptr;
+  int list_cap = 128;
+  int scr_cap = 192;
+  // state of the last forward
+  long long n_last = -1;
+  int G = 0;
+  double ell = 0.0;
+  int precision_last = -1;
+  bool reserved_fixed = false;
+};
+
+namespace {
+
+using namespace crk;
+
+crk_status fail(crk_ctx* c, crk_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+crk_status hip_fail(crk_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? CRK_ENOMEM : CRK_EHIP, m);
+}
+
+#define CRK_HIP(call, where)                          \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+hipError_t ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.bytes = bytes;
+  return hipSuccess;
+}
+
+void release(Buf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+crk_status check_params(crk_ctx* ctx, const crk_params* p) {
+  if (!p) return fail(ctx, CRK_EINVAL, "params is NULL");
+  if (!(p->box > 0.0) || !std::isfinite(p->box)) return fail(ctx, CRK_EINVAL, "box must be > 0");
+  if (!(p->n_h > 0.0)) return fail(ctx, CRK_EINVAL, "n_h must be > 0");
+  if (!(p->gamma > 1.0)) return fail(ctx, CRK_EINVAL, "gamma must be > 1");
+  if (p->kernel != CRK_CUBIC_SPLINE && p->kernel != CRK_WENDLAND_C4)
+    return fail(ctx, CRK_EINVAL, "unknown kernel");
+  if (p->precision != CRK_FP32 && p->precision != CRK_FP64)
+    return fail(ctx, CRK_EINVAL, "unknown precision");
+  if (p->h_mode != 0 && p->h_mode != 1) return fail(ctx, CRK_EINVAL, "h_mode must be 0 or 1");
+  if (p->h_max_iter < 1) return fail(ctx, CRK_EINVAL, "h_max_iter must be >= 1");
+  if (!(p->h_rtol > 0.0)) return fail(ctx, CRK_EINVAL, "h_rtol must be > 0");
+  if (!(p->eps2 >= 0.0) || !(p->dt_relax >= 0.0))
+    return fail(ctx, CRK_EINVAL, "eps2 and dt_relax must be >= 0");
+  // the shape with only the self term must fall short of n_h^3
+  const double c0 = p->kernel == 0 ? 8.0 / kPi : 495.0 / (32.0 * kPi);
+  if (!(p->n_h * p->n_h * p->n_h > c0))
+    return fail(ctx, CRK_EINVAL, "n_h too small: the self term alone meets the neighbour target");
+  return CRK_OK;
+}
+
+size_t real_size(int precision) { return precision == CRK_FP64 ? 8 : 4; }
+
+// Per-particle workspace (independent of the neighbour-list capacity).
+hipError_t ensure_particles(crk_ctx* c, int64_t n) {
+  const size_t R = real_size(c->p.precision);
+  const int64_t npad = ((n + 63) / 64) * 64;
+  hipError_t e;
+#define ENS(b, bytes) \
+  if ((e = ensure(c->b, (size_t)(bytes))) != hipSuccess) return e
+  ENS(keys_a, 4 * npad);
+  ENS(keys_b, 4 * npad);
+  ENS(vals_a, 4 * npad);
+  ENS(vals_b, 4 * npad);
+  ENS(sort_tmp, 4 * (size_t)radix_tmp_words(n));
+  ENS(pos4, 4 * R * npad);
+  ENS(vel4, 4 * R * npad);
+  ENS(mass, R * npad);
+  ENS(uu, R * npad);
+  ENS(hbuf, R * npad);
+  ENS(Vbuf, R * npad);
+  ENS(st4, 4 * R * npad);
+  ENS(gv4, 12 * R * npad);
+  ENS(kc4, 16 * R * npad);
+  ENS(ng, 4 * npad);
+  ENS(ns, 4 * npad);
+  ENS(cnt, 8 * CNT_COUNT);
+  if (c->p.store_corrections) ENS(mom, 40 * R * npad);
+#undef ENS
+  return hipSuccess;
+}
+
+template <class R>
+State<R> make_state(crk_ctx* c, int64_t n) {
+  State<R> S;
+  S.n = n;
+  S.G = c->G;
+  S.box = c->p.box;
+  S.ell_d = c->ell;
+  S.ell = (R)c->ell;
+  S.perm = (const uint32_t*)c->vals_a.p;
+  S.keys = (const uint32_t*)c->keys_a.p;
+  S.cell_start = (const uint32_t*)c->cell_start.p;
+  S.pos4 = (R4<R>*)c->pos4.p;
+  S.vel4 = (R4<R>*)c->vel4.p;
+  S.mass = (R*)c->mass.p;
+  S.uu = (R*)c->uu.p;
+  S.hbuf = (R*)c->hbuf.p;
+  S.Vbuf = (R*)c->Vbuf.p;
+  S.st4 = (R4<R>*)c->st4.p;
+  S.gv4 = (R4<R>*)c->gv4.p;
+  S.kc4 = (R4<R>*)c->kc4.p;
+  S.mom = c->p.store_corrections ? (R*)c->mom.p : nullptr;
+  S.nlist = (uint32_t*)c->nlist.p;
+  S.ng = (int*)c->ng.p;
+  S.ns = (int*)c->ns.p;
+  S.list_cap = c->list_cap;
+  S.scr = (R*)c->scr.p;
+  S.scr_cap = c->scr_cap;
+  S.cnt = (unsigned long long*)c->cnt.p;
+  S.n_h3 = c->p.n_h * c->p.n_h * c->p.n_h;
+  S.gamma = c->p.gamma;
+  S.alpha = c->p.alpha;
+  S.beta = c->p.beta;
+  S.eps2 = c->p.eps2;
+  S.dt_relax = c->p.dt_relax;
+  S.rtol = c->p.h_rtol;
+  S.max_iter = c->p.h_max_iter;
+  return S;
+}
+
+hipError_t read_counters(crk_ctx* c, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(c->host_cnt, c->cnt.p, 8 * CNT_COUNT, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+// Largest grid with cell side >= R, at most ~2 cells per particle and
+// at most 1023 cells per side (10-bit packed coordinates).
+int choose_grid(double box, double R, int64_t n) {
+  double g = std::floor(box / R);
+  if (!(g >= 1.0)) g = 1.0;
+  g = std::min(g, 1023.0);
+  while (g > 1.0 && g * g * g > 2.0 * (double)n + 8.0) g -= 1.0;
+  return (int)g;
+}
+
+template <class R>
+crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) {
+  const int64_t ncell = (int64_t)ctx->G * ctx->G * ctx->G;
+  CRK_HIP(ensure(ctx->cell_count, 4 * (size_t)(ncell + 1)), "alloc cell counts");
+  CRK_HIP(ensure(ctx->cell_start, 4 * (size_t)(ncell + 1)), "alloc cell starts");
+  CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(ncell + 1)), "alloc scan");
+  CRK_HIP(hipMemsetAsync(ctx->cell_count.p, 0, 4 * (size_t)(ncell + 1), s), "memset");
+  launch_keys(x, n, ctx->p.box, ctx->G, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
+              (uint32_t*)ctx->cell_count.p, s);
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
+  CRK_HIP(radix_sort_pairs((uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
+                           (uint32_t*)ctx->keys_b.p, (uint32_t*)ctx->vals_b.p, n, bits,
+                           (uint32_t*)ctx->sort_tmp.p, s),
+          "radix sort");
+  CRK_HIP(exclusive_scan_u32((const uint32_t*)ctx->cell_count.p, (uint32_t*)ctx->cell_start.p,
+                             ncell + 1, (uint32_t*)ctx->scan_tmp.p, s),
+          "scan");
+  return CRK_OK;
+}
+
+template <class R>
+crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
+                        const R* m, const R* u, R* h, R* V, R* rho, void* A, void* B,
+                        void* gradA, void* gradB, R* gradv, double* accel, double* dudt,
+                        crk_stats* stats) {
+  const crk_params& P = ctx->p;
+  ctx->n_last = -1;
+  CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
+  unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+  launch_check_inputs<R>(h, m, u, n, dcnt, s);
+  CRK_HIP(hipGetLastError(), "input check launch");
+  CRK_HIP(read_counters(ctx, s), "input check");
+  if (ctx->host_cnt[CNT_BAD_INPUT])
+    return fail(ctx, CRK_EINVAL, "h, m and u must be finite and > 0");
+  const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
+  if (!(h0max < 0.5 * P.box))
+    return fail(ctx, CRK_EDOMAIN, "smoothing length must stay below half the box");
+
+  double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
+  ctx->G = choose_grid(P.box, reach, n);
+  ctx->ell = P.box / ctx->G;
+  bool solved = false;
+  for (int attempt = 0; attempt < 12 && !solved; ++attempt) {
+    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+    crk_status st = build_cells<R>(ctx, s, n, x);
+    if (st != CRK_OK) return st;
+    State<R> S = make_state<R>(ctx, n);
+    launch_gather<R>(S, x, v, m, u, h, s);
+    if (P.h_mode == 0) {
+      launch_volume<R>(S, P.kernel, s);
+      solved = true;
+      break;
+    }
+    const int64_t npad = ((n + 63) / 64) * 64;
+    CRK_HIP(ensure(ctx->scr, 2 * real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+            "alloc h scratch");
+    S = make_state<R>(ctx, n);
+    launch_hsolve<R>(S, P.kernel, s);
+    CRK_HIP(hipGetLastError(), "h solve launch");
+    CRK_HIP(read_counters(ctx, s), "h solve");
+    if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
+      ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);
+      continue;  // same grid, larger scratch
+    }
+    if (ctx->host_cnt[CNT_H_CAPPED]) {
+      if (ctx->G == 1) return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
+      // cells too small for some root: widen them and solve again
+      const int G2 = std::max(1, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
+      ctx->G = G2;
+      ctx->ell = P.box / ctx->G;
+      continue;
+    }
+    solved = true;
+  }
+  if (!solved) return fail(ctx, CRK_EHIP, "h solve: grid adaptation did not settle");
+  if (P.h_mode == 1) {
+    const double hmax = bits_to_double(ctx->host_cnt[CNT_HMAX_OUT_BITS]);
+    if (!(hmax < 0.5 * P.box))
+      return fail(ctx, CRK_EDOMAIN, "solved smoothing length reaches half the box");
+  }
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_pack<R>(S, h, V, s);
+  }
+  // neighbour list, grown until it fits
+  const int64_t npad = ((n + 63) / 64) * 64;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
+    State<R> S = make_state<R>(ctx, n);
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8, s), "memset");
+    launch_nlist<R>(S, s);
+    CRK_HIP(hipGetLastError(), "neighbour list launch");
+    CRK_HIP(read_counters(ctx, s), "neighbour list");
+    const unsigned long long need = ctx->host_cnt[CNT_LIST_OVERFLOW];
+    if (!need) break;
+    ctx->list_cap = (int)((need * 5 / 4 + 31) / 32 * 32);
+    if (attempt == 7) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
+  }
+  State<R> S = make_state<R>(ctx, n);
+  CorrOut co{A, B, gradA, gradB};
+  launch_moments<R>(S, P.kernel, co, s);
+  launch_density<R>(S, P.kernel, rho, gradv, s);
+  launch_force<R>(S, P.kernel, accel, dudt, s);
+  CRK_HIP(hipGetLastError(), "pass launch");
+  if (P.check_finite) {
+    launch_count_nonfinite_f64(accel, 3 * n, dcnt, s);
+    launch_count_nonfinite_f64(dudt, n, dcnt, s);
+    launch_count_nonfinite<R>(rho, n, dcnt, s);
+    launch_count_nonfinite<R>(h, n, dcnt, s);
+    CRK_HIP(hipGetLastError(), "finite check launch");
+  }
+  ctx->n_last = n;
+  ctx->precision_last = P.precision;
+  crk_status result = CRK_OK;
+  if (stats || P.check_finite) {
+    CRK_HIP(read_counters(ctx, s), "stats");
+    const unsigned long long* hc = ctx->host_cnt;
+    if (stats) {
+      stats->n_pairs_gather = (long long)hc[CNT_PAIRS_GATHER];
+      stats->n_pairs_force = (long long)hc[CNT_PAIRS_FORCE];
+      stats->h_iter_max = (int)hc[CNT_H_ITER_MAX];
+      stats->h_unconverged = (int)hc[CNT_H_UNCONV];
+      stats->m2_singular = (int)hc[CNT_SINGULAR];
+      stats->relaxed = (int)hc[CNT_RELAXED];
+      stats->nonfinite = (int)hc[CNT_NONFINITE];
+      stats->grid = ctx->G;
+    }
+    if (hc[CNT_H_UNCONV]) {
+      result = CRK_ENOTCONV;
+      ctx->err = "h solve reached the iteration cap for some particles";
+    }
+    if (P.check_finite && hc[CNT_NONFINITE]) {
+      result = CRK_ENONFINITE;
+      ctx->err = "non-finite outputs";
+    }
+  }
+  return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+void crk_default_params(crk_params* p, int precision) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->box = 1.0;
+  p->gamma = 5.0 / 3.0;
+  p->alpha = 1.0;
+  p->beta = 2.0;
+  p->eps2 = 0.01;
+  p->n_h = 2.4814;
+  p->kernel = CRK_CUBIC_SPLINE;
+  p->precision = precision;
+  p->h_mode = 1;
+  p->h_max_iter = 60;
+  p->h_rtol = precision == CRK_FP64 ? 1e-13 : 1e-6;
+  p->dt_relax = 0.0;
+  p->store_corrections = 0;
+  p->check_finite = 0;
+}
+
+crk_status crk_create(crk_ctx** out, const crk_params* p) {
+  if (!out) return CRK_EINVAL;
+  *out = nullptr;
+  crk_status st = check_params(nullptr, p);
+  if (st != CRK_OK) return st;
+  crk_ctx* c = new crk_ctx();
+  c->p = *p;
+  if (hipHostMalloc((void**)&c->host_cnt, 8 * CNT_COUNT, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return CRK_ENOMEM;
+  }
+  std::memset(c->host_cnt, 0, 8 * CNT_COUNT);
+  *out = c;
+  return CRK_OK;
+}
+
+crk_status crk_set_params(crk_ctx* ctx, const crk_params* p) {
+  if (!ctx) return CRK_EINVAL;
+  crk_status st = check_params(ctx, p);
+  if (st != CRK_OK) return st;
+  const bool prec_changed = p->precision != ctx->p.precision;
+  ctx->p = *p;
+  if (prec_changed) ctx->n_last = -1;
+  return CRK_OK;
+}
+
+crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
+  if (!ctx || n_max < 0) return fail(ctx, CRK_EINVAL, "bad reserve size");
+  if (n_max == 0) return CRK_OK;
+  hipError_t e = ensure_particles(ctx, n_max);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
+  const int64_t npad = ((n_max + 63) / 64) * 64;
+  e = ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap);
+  if (e == hipSuccess && ctx->p.h_mode == 1)
+    e = ensure(ctx->scr, 2 * real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
+  return CRK_OK;
+}
+
+crk_status crk_destroy(crk_ctx* c) {
+  if (!c) return CRK_OK;
+  Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_count, &c->cell_start,
+                &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
+                &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->ng, &c->ns,
+                &c->scr, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
+                &c->a_grho, &c->a_ggv, &c->a_gP, &c->a_gc, &c->a_gmom, &c->a_gab, &c->a_coef};
+  for (Buf* b : all) release(*b);
+  if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+  delete c;
+  return CRK_OK;
+}
+
+const char* crk_last_error(const crk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+crk_status crk_forward(crk_ctx* ctx, void* hip_stream, long long n, const double* x,
+                       const void* v, const void* m, const void* u, void* h, void* V, void* rho,
+                       void* A, void* B, void* gradA, void* gradB, void* gradv, double* accel,
+                       double* dudt, crk_stats* stats) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (n < 0) return fail(ctx, CRK_EINVAL, "n must be >= 0");
+  if (n == 0) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    ctx->n_last = 0;
+    return CRK_OK;
+  }
+  if (n > (1ll << 27) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^27 - 1 particles");
+  if (!x || !v || !m || !u || !h || !V || !rho || !A || !B || !gradA || !gradB || !gradv ||
+      !accel || !dudt)
+    return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (ctx->p.precision == CRK_FP64)
+    return forward_impl<double>(ctx, s, n, x, (const double*)v, (const double*)m,
+                                (const double*)u, (double*)h, (double*)V, (double*)rho, A, B,
+                                gradA, gradB, (double*)gradv, accel, dudt, stats);
+  return forward_impl<float>(ctx, s, n, x, (const float*)v, (const float*)m, (const float*)u,
+                             (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB,
+                             (float*)gradv, accel, dudt, stats);
+}
+
+crk_status crk_backward(crk_ctx* ctx, void* hip_stream, long long n, const double* g_accel,
+                        const double* g_dudt, double* g_x, double* g_v, double* g_u,
+                        double* g_alpha_beta) {
+  (void)hip_stream;
+  (void)g_accel;
+  (void)g_dudt;
+  (void)g_x;
+  (void)g_v;
+  (void)g_u;
+  (void)g_alpha_beta;
+  if (!ctx) return CRK_EINVAL;
+  if (n != ctx->n_last) return fail(ctx, CRK_EINVAL, "no forward with this n on the context");
+  return fail(ctx, CRK_EINVAL, "adjoint not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Device-side building blocks shared by the CRKSPH pass kernels: scalar
+// helpers, the two smoothing kernels (support radius h, App. A.2), the
+// corrected kernel W^R (App. A.1, eq. RK) in its packed per-particle form,
+// and the periodic pair separation from cell-relative offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crk {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------- scalars ----
+
+template <class R> struct Sc;
+template <> struct Sc<float> {
+  __device__ static inline float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
+};
+template <> struct Sc<double> {
+  __device__ static inline double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+  __device__ static inline double rcp(double x) { return 1.0 / x; }
+  __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
+};
+
+template <class R> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+template <class R> using R4 = typename Vec4<R>::T;
+
+// ------------------------------------------------------------- kernels ----
+// W(r, h) = C / h^3 w(q), q = r / h, compact support q < 1.
+// eval() returns w(q) and w'(q) (zero outside the support).
+
+template <int K> struct Shape;
+
+template <> struct Shape<0> {  // cubic spline (M4), radius h
+  static constexpr double C = 8.0 / kPi;
+  template <class R> __device__ static inline void eval(R q, R& w, R& dw) {
+    R t = R(1) - q;
+    R wi = R(1) + q * q * (R(6) * q - R(6));
+    R dwi = q * (R(18) * q - R(12));
+    R wo = R(2) * t * t * t;
+    R dwo = R(-6) * t * t;
+    bool in = q <= R(0.5);
+    bool sup = q < R(1);
+    w = sup ? (in ? wi : wo) : R(0);
+    dw = sup ? (in ? dwi : dwo) : R(0);
+  }
+  static constexpr double w0 = 1.0;
+};
+
+template <> struct Shape<1> {  // Wendland C4, radius h
+  static constexpr double C = 495.0 / (32.0 * kPi);
+  template <class R> __device__ static inline void eval(R q, R& w, R& dw) {
+    R t = R(1) - q;
+    t = t > R(0) ? t : R(0);
+    R t2 = t * t;
+    R t5 = t2 * t2 * t;
+    w = t5 * t * (R(1) + R(6) * q + R(35.0 / 3.0) * q * q);
+    dw = R(-56.0 / 3.0) * q * (R(1) + R(5) * q) * t5;
+  }
+  static constexpr double w0 = 1.0;
+};
+
+// ----------------------------------------------------- corrected kernel ----
+// Per-particle packed coefficients of W^R_ij = A (1 + B.x) W (x = x_ij):
+//   s(x)        = a + b.x            with a = A, b = A B
+//   W^R         = s W
+//   grad_i W^R  = W (c + M x) + s grad W
+// where c_g = dA_g + A B_g and M_ga = dA_g B_a + A dB_ga, which is the
+// expansion of dA (1 + B.x) W + A (dB^T x + B) W + A (1 + B.x) grad W.
+// Layout of the 16 values: [a, b0, b1, b2, c0, c1, c2, M00..M22 (row g)].
+
+template <class R> struct KC {
+  R a, b[3], c[3], M[9];
+};
+
+template <class R>
+__device__ inline void kc_load(const R* __restrict__ kc, int64_t n, int64_t i, KC<R>& k) {
+  k.a = kc[i];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) k.b[t] = kc[(1 + t) * n + i];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) k.c[t] = kc[(4 + t) * n + i];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) k.M[t] = kc[(7 + t) * n + i];
+}
+
+template <class R>
+__device__ inline void kc_plain(KC<R>& k) {
+  k.a = R(1);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) k.b[t] = k.c[t] = R(0);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) k.M[t] = R(0);
+}
+
+// W^R and grad W^R for separation x, given W and grad W.
+template <class R>
+__device__ inline void kc_apply(const KC<R>& k, const R x[3], R W, const R gW[3], R& WR,
+                                R gWR[3]) {
+  R s = k.a + k.b[0] * x[0] + k.b[1] * x[1] + k.b[2] * x[2];
+  WR = s * W;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    R t = k.c[g] + k.M[g * 3 + 0] * x[0] + k.M[g * 3 + 1] * x[1] + k.M[g * 3 + 2] * x[2];
+    gWR[g] = W * t + s * gW[g];
+  }
+}
+
+// --------------------------------------------------------- cell list ----
+// Positions are stored as offsets xi from the centre of their cell (FP64
+// difference, rounded once to Real). For a neighbour j found through
+// stencil offset d in {-1,0,1}^3 of i's cell, the periodic separation is
+// x_ij = xi_i - xi_j - d * ell, exact up to one rounding of each term.
+// A neighbour-list entry packs the sorted index of j (high 27 bits) with
+// the stencil code 9*(dz+1) + 3*(dy+1) + (dx+1) (low 5 bits).
+
+constexpr int kCodeBits = 5;
+constexpr uint32_t kCodeMask = 31u;
+constexpr int kSelfCode = 13;
+
+__device__ inline void code_offset(uint32_t code, int& dx, int& dy, int& dz) {
+  dz = int(code / 9u) - 1;
+  dy = int((code / 3u) % 3u) - 1;
+  dx = int(code % 3u) - 1;
+}
+
+template <class R>
+__device__ inline void pair_sep(const R4<R>& pi, const R4<R>& pj, uint32_t code, R ell, R x[3]) {
+  int dx, dy, dz;
+  code_offset(code, dx, dy, dz);
+  x[0] = (pi.x - pj.x) - R(dx) * ell;
+  x[1] = (pi.y - pj.y) - R(dy) * ell;
+  x[2] = (pi.z - pj.z) - R(dz) * ell;
+}
+
+// SELL layout with slices of 64 particles: entry k of sorted particle i
+// lives at ((i / 64) * cap + k) * 64 + (i % 64).
+__device__ inline int64_t sell_index(int64_t i, int cap, int k) {
+  return ((i >> 6) * (int64_t)cap + k) * 64 + (i & 63);
+}
+
+}  // namespace crk

@@ -1,0 +1,855 @@
+// Forward CRKSPH pair passes on gfx950.
+//
+// One lane owns one cell-sorted particle i; a 64-lane wave owns 64
+// consecutive particles of the cell order, so the lanes of a wave share
+// almost all of their neighbours and the gathered neighbour records stay in
+// the vector L1 / L2. Pair arithmetic is in Real (FP32 or FP64); the 3x3
+// second-moment solve and the force / energy accumulators are FP64.
+//
+// Passes (paper: arXiv:2511.21921):
+//   k_hsolve   smoothing length from the Thacker fixed point Delta_N = 1
+//              (App. A.3, eq. thacker) and the volume of App. A.2, eq. Vg;
+//   k_volume   the volume alone for fixed h;
+//   k_nlist    symmetric neighbour list r_ij < max(h_i, h_j);
+//   k_moments  geometric moments and the corrections A, B, grad A, grad B of
+//              W^R_ij = A_i (1 + B_i . x_ij) W_ij(h_i) (App. A.1, eq. RK);
+//   k_density  density (Sec. 2.5.1, eq. rhow), velocity gradient
+//              (App. A.1, eq. gradv), ideal-gas EOS and the relaxation flag
+//              exp(|div v| dt) > 8 (App. A.1);
+//   k_force    pairwise momentum and compatible energy with the limited
+//              artificial viscosity (Sec. 2.1).
+#include "crk_passes.h"
+
+namespace crk {
+namespace {
+
+template <class R>
+__device__ inline R dot3(const R a[3], const R b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ inline void wave_add_u64(unsigned long long* dst, unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+__device__ inline void wave_max_u64(unsigned long long* dst, unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = __shfl_xor(v, o, 64);
+    v = t > v ? t : v;
+  }
+  if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
+}
+
+__device__ inline unsigned long long dbits(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// ------------------------------------------------------------- inputs ----
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h,
+                                                         const R* __restrict__ m,
+                                                         const R* __restrict__ u, int64_t n,
+                                                         unsigned long long* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long hb = 0, bad = 0;
+  if (i < n) {
+    const double hv = (double)h[i];
+    const bool ok = hv > 0.0 && (double)m[i] > 0.0 && (double)u[i] > 0.0 &&
+                    hv < 1e300 && (double)u[i] < 1e300;
+    bad = ok ? 0 : 1;
+    hb = ok ? dbits(hv) : 0;
+  }
+  wave_max_u64(&cnt[CNT_HMAX_BITS], hb);
+  wave_add_u64(&cnt[CNT_BAD_INPUT], bad);
+}
+
+__device__ inline double wrap_pos(double xa, double L) {
+  double t = xa - L * floor(xa / L);
+  if (t >= L) t -= L;
+  if (t < 0.0) t = 0.0;
+  return t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, int64_t n,
+                                                 double L, int G, uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals,
+                                                 uint32_t* __restrict__ ccount) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double inv = (double)G / L;
+  int c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double t = wrap_pos(x[a * n + i], L);
+    int k = (int)(t * inv);
+    c[a] = k < G ? k : G - 1;
+  }
+  const uint32_t key = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
+  keys[i] = key;
+  vals[i] = (uint32_t)i;
+  atomicAdd(&ccount[key], 1u);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __restrict__ x,
+                                                   const R* __restrict__ v,
+                                                   const R* __restrict__ m,
+                                                   const R* __restrict__ u,
+                                                   const R* __restrict__ h) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const int64_t n = S.n;
+  const uint32_t p = S.perm[s];
+  if (p >= (uint32_t)n) return;
+  int c[3];
+  cell_coords(S.keys[s], S.G, c[0], c[1], c[2]);
+  R xi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double t = wrap_pos(x[a * n + p], S.box);
+    xi[a] = (R)(t - ((double)c[a] + 0.5) * S.ell_d);
+  }
+  R4<R> q;
+  q.x = xi[0];
+  q.y = xi[1];
+  q.z = xi[2];
+  q.w = R(0);
+  S.pos4[s] = q;
+  R4<R> w;
+  w.x = v[p];
+  w.y = v[n + p];
+  w.z = v[2 * n + p];
+  w.w = R(0);
+  S.vel4[s] = w;
+  S.mass[s] = m[p];
+  S.uu[s] = u[p];
+  S.hbuf[s] = h[p];
+}
+
+// ------------------------------------------------------------- h solve ----
+// f(h) = C (w(0) + sum_{j != i} (m_j/m_i) w(r_ij / h)) - n_h^3, which is
+// h^3 sum_j (m_j/m_i) W(r_ij, h) - n_h^3: zero exactly when Delta_N = 1.
+// Candidates within the cell side are collected once into the SELL
+// scratch; the safeguarded Newton iterations then only re-read them.
+
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool live = s < S.n;
+  unsigned long long iters = 0, unconv = 0, capped = 0, ovf = 0, hbits = 0;
+  if (live) {
+    const R4<R> pi = S.pos4[s];
+    const R mi_inv = R(1) / S.mass[s];
+    const R Rcap = S.ell;
+    const R Rcap2 = Rcap * Rcap;
+    int cnt = 0;
+    for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
+      if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
+      const R4<R> pj = S.pos4[j];
+      R x[3];
+      pair_sep<R>(pi, pj, code, S.ell, x);
+      const R r2 = dot3(x, x);
+      if (r2 < Rcap2) {
+        if (cnt < S.scr_cap) {
+          const int64_t e = sell_index(s, S.scr_cap, cnt);
+          S.scr[2 * e] = Sc<R>::sqrt(r2);
+          S.scr[2 * e + 1] = S.mass[j] * mi_inv;
+        }
+        ++cnt;
+      }
+    });
+    if (cnt > S.scr_cap) {
+      ovf = (unsigned long long)cnt;
+    } else {
+      const R C = R(Shape<K>::C);
+      const R n_h3 = R(S.n_h3);
+      auto fsum = [&](R h, R& dsum) {
+        const R hinv = R(1) / h;
+        R sum = R(Shape<K>::w0), ds = R(0);
+        for (int k = 0; k < cnt; ++k) {
+          const int64_t e = sell_index(s, S.scr_cap, k);
+          const R q = S.scr[2 * e] * hinv;
+          const R mr = S.scr[2 * e + 1];
+          R w, dw;
+          Shape<K>::eval(q, w, dw);
+          sum += mr * w;
+          ds += mr * dw * q;
+        }
+        dsum = ds;
+        return sum;
+      };
+      R h;
+      R dsum;
+      if (!(C * fsum(Rcap, dsum) - n_h3 > R(0))) {
+        capped = 1;
+        h = Rcap;
+      } else {
+        R lo = R(0), hi = Rcap;
+        h = S.hbuf[s];
+        if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
+        const R rtol = R(S.rtol);
+        bool conv = false;
+        int it = 0;
+        for (; it < S.max_iter; ++it) {
+          const R f = C * fsum(h, dsum) - n_h3;
+          const R fp = -C * dsum / h;
+          if (f > R(0)) hi = h; else lo = h;
+          R hn = (fp > R(0)) ? h - f / fp : R(0.5) * (lo + hi);
+          if (!(hn > lo && hn < hi)) hn = R(0.5) * (lo + hi);
+          const R step = hn > h ? hn - h : h - hn;
+          h = hn;
+          if (step <= rtol * h || (hi - lo) <= rtol * h) {
+            conv = true;
+            break;
+          }
+        }
+        iters = (unsigned long long)(it + 1);
+        unconv = conv ? 0 : 1;
+      }
+      const R sum = fsum(h, dsum);
+      S.hbuf[s] = h;
+      S.Vbuf[s] = h * h * h / (C * sum);
+      hbits = dbits((double)h);
+    }
+  }
+  wave_max_u64(&S.cnt[CNT_H_ITER_MAX], iters);
+  wave_add_u64(&S.cnt[CNT_H_UNCONV], unconv);
+  wave_add_u64(&S.cnt[CNT_H_CAPPED], capped);
+  wave_max_u64(&S.cnt[CNT_SCR_OVERFLOW], ovf);
+  wave_max_u64(&S.cnt[CNT_HMAX_OUT_BITS], hbits);
+}
+
+// Fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included.
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const R4<R> pi = S.pos4[s];
+  const R h = S.hbuf[s];
+  const R hinv = R(1) / h;
+  const R h2 = h * h;
+  const R mi_inv = R(1) / S.mass[s];
+  R sum = R(Shape<K>::w0);
+  for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
+    if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
+    const R4<R> pj = S.pos4[j];
+    R x[3];
+    pair_sep<R>(pi, pj, code, S.ell, x);
+    const R r2 = dot3(x, x);
+    if (r2 < h2) {
+      R w, dw;
+      Shape<K>::eval(Sc<R>::sqrt(r2) * hinv, w, dw);
+      sum += S.mass[j] * mi_inv * w;
+    }
+  });
+  S.Vbuf[s] = h * h2 / (R(Shape<K>::C) * sum);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_out,
+                                                 R* __restrict__ V_out) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const R h = S.hbuf[s], V = S.Vbuf[s];
+  S.pos4[s].w = R(1) / h;
+  S.vel4[s].w = V;
+  const uint32_t p = S.perm[s];
+  h_out[p] = h;
+  V_out[p] = V;
+}
+
+// --------------------------------------------------------- neighbour list --
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long g = 0, f = 0, ovf = 0;
+  if (s < S.n) {
+    const R4<R> pi = S.pos4[s];
+    const R hi2 = pi.w * pi.w;  // 1/h_i^2
+    int ng = 0, ns = 0;
+    const int cap = S.list_cap;
+    for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
+      if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
+      const R4<R> pj = S.pos4[j];
+      R x[3];
+      pair_sep<R>(pi, pj, code, S.ell, x);
+      const R r2 = dot3(x, x);
+      const uint32_t e = (j << kCodeBits) | code;
+      if (r2 * hi2 < R(1)) {
+        if (ng + ns < cap) S.nlist[sell_index(s, cap, ng)] = e;
+        ++ng;
+      } else if (r2 * (pj.w * pj.w) < R(1)) {
+        if (ng + ns < cap) S.nlist[sell_index(s, cap, cap - 1 - ns)] = e;
+        ++ns;
+      }
+    });
+    S.ng[s] = ng;
+    S.ns[s] = ns;
+    g = (unsigned long long)ng;
+    f = (unsigned long long)(ng + ns);
+    if (ng + ns > cap) ovf = (unsigned long long)(ng + ns);
+  }
+  wave_add_u64(&S.cnt[CNT_PAIRS_GATHER], g);
+  wave_add_u64(&S.cnt[CNT_PAIRS_FORCE], f);
+  wave_max_u64(&S.cnt[CNT_LIST_OVERFLOW], ovf);
+}
+
+// ------------------------------------------------ moments + corrections ----
+// Moments over j with r_ij < h_i, self included (V_j, h_i fixed; d_g is
+// the derivative with respect to the evaluation point x_i):
+//   m0 = sum V W, m1_a = sum V x_a W, m2_ab = sum V x_a x_b W,
+//   d_g m0 = sum V d_g W, d_g m1_a = delta_ag m0 + sum V x_a d_g W,
+//   d_g m2_ab = delta_ag m1_b + delta_bg m1_a + sum V x_a x_b d_g W.
+// Corrections from sum V W^R = 1 and sum V x W^R = 0:
+//   B = -m2^-1 m1, A = 1 / (m0 + B.m1),
+//   d_g B = -m2^-1 (d_g m1 + d_g m2 B), d_g A = -A^2 (d_g m0 + d_g B.m1 + B.d_g m1).
+
+// Symmetric-pair index of (a, b) in (xx, xy, xz, yy, yz, zz).
+__device__ inline constexpr int sym6(int a, int b) {
+  return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : (b == 0 ? a : (b == 1 ? 2 + a : 5));
+}
+
+template <class R>
+struct Moments {
+  R m0, m1[3], m2[6], dm0[3], X1[9], X2[18];
+};
+
+template <class R, int K>
+__device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<R>& M) {
+  const R4<R> pi = S.pos4[s];
+  const R hinv = pi.w;
+  const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+  const R C4 = C3 * hinv;
+  M.m0 = S.vel4[s].w * C3 * R(Shape<K>::w0);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) M.m1[t] = M.dm0[t] = R(0);
+#pragma unroll
+  for (int t = 0; t < 6; ++t) M.m2[t] = R(0);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) M.X1[t] = R(0);
+#pragma unroll
+  for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
+  const int ng = S.ng[s];
+  for (int k = 0; k < ng; ++k) {
+    const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
+    const uint32_t j = e >> kCodeBits;
+    const R4<R> pj = S.pos4[j];
+    const R Vj = S.vel4[j].w;
+    R x[3];
+    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    const R r2 = dot3(x, x);
+    const R rinv = Sc<R>::rsqrt(r2);
+    const R q = r2 * rinv * hinv;
+    R w, dw;
+    Shape<K>::eval(q, w, dw);
+    const R VW = Vj * C3 * w;
+    const R fg = Vj * C4 * dw * rinv;
+    const R Vg[3] = {fg * x[0], fg * x[1], fg * x[2]};
+    const R p6[6] = {x[0] * x[0], x[0] * x[1], x[0] * x[2], x[1] * x[1], x[1] * x[2], x[2] * x[2]};
+    M.m0 += VW;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) M.m1[a] += x[a] * VW;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) M.m2[t] += p6[t] * VW;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      M.dm0[g] += Vg[g];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) M.X1[g * 3 + a] += x[a] * Vg[g];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) M.X2[g * 6 + t] += p6[t] * Vg[g];
+    }
+  }
+}
+
+// Full moment set (40 values, FP64) from the accumulated sums.
+struct Mom64 {
+  double m0, m1[3], m2[9], dm0[3], dm1[9], dm2[27];
+};
+
+template <class R>
+__device__ inline void expand_moments(const Moments<R>& M, Mom64& D) {
+  D.m0 = (double)M.m0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    D.m1[a] = (double)M.m1[a];
+    D.dm0[a] = (double)M.dm0[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D.m2[a * 3 + b] = (double)M.m2[sym6(a, b)];
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      D.dm1[g * 3 + a] = (double)M.X1[g * 3 + a] + (a == g ? D.m0 : 0.0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        D.dm2[(g * 3 + a) * 3 + b] = (double)M.X2[g * 6 + sym6(a, b)] +
+                                     (a == g ? D.m1[b] : 0.0) + (b == g ? D.m1[a] : 0.0);
+    }
+}
+
+struct Corr64 {
+  double A, B[3], dA[3], dB[9], inv[9];
+  bool singular;
+};
+
+__device__ inline void solve_corrections(const Mom64& D, Corr64& o) {
+  const double* m2 = D.m2;
+  double cof[9];
+  cof[0] = m2[4] * m2[8] - m2[5] * m2[7];
+  cof[1] = m2[2] * m2[7] - m2[1] * m2[8];
+  cof[2] = m2[1] * m2[5] - m2[2] * m2[4];
+  cof[3] = m2[5] * m2[6] - m2[3] * m2[8];
+  cof[4] = m2[0] * m2[8] - m2[2] * m2[6];
+  cof[5] = m2[2] * m2[3] - m2[0] * m2[5];
+  cof[6] = m2[3] * m2[7] - m2[4] * m2[6];
+  cof[7] = m2[1] * m2[6] - m2[0] * m2[7];
+  cof[8] = m2[0] * m2[4] - m2[1] * m2[3];
+  const double det = m2[0] * cof[0] + m2[1] * cof[3] + m2[2] * cof[6];
+  const double tr = fabs(m2[0]) + fabs(m2[4]) + fabs(m2[8]);
+  o.singular = !(fabs(det) > 1e-12 * tr * tr * tr);
+  if (o.singular) {
+    o.A = 1.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) o.B[t] = o.dA[t] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) o.dB[t] = o.inv[t] = 0.0;
+    return;
+  }
+  const double id = 1.0 / det;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) o.inv[t] = cof[t] * id;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    o.B[a] = -(o.inv[a * 3 + 0] * D.m1[0] + o.inv[a * 3 + 1] * D.m1[1] + o.inv[a * 3 + 2] * D.m1[2]);
+  o.A = 1.0 / (D.m0 + o.B[0] * D.m1[0] + o.B[1] * D.m1[1] + o.B[2] * D.m1[2]);
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    double rhs[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      rhs[b] = D.dm1[g * 3 + b];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) rhs[b] += D.dm2[(g * 3 + b) * 3 + e] * o.B[e];
+    }
+    double t = D.dm0[g];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      o.dB[g * 3 + a] = -(o.inv[a * 3 + 0] * rhs[0] + o.inv[a * 3 + 1] * rhs[1] +
+                          o.inv[a * 3 + 2] * rhs[2]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t += o.dB[g * 3 + a] * D.m1[a] + o.B[a] * D.dm1[g * 3 + a];
+    o.dA[g] = -(o.A * o.A) * t;
+  }
+}
+
+template <class R>
+__device__ inline void store_kc(const State<R>& S, int64_t s, const Corr64& c) {
+  // packed form: a = A, b = A B, c_g = dA_g + A B_g, M_ga = dA_g B_a + A dB_ga
+  R v[16];
+  v[0] = (R)c.A;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    v[1 + t] = (R)(c.A * c.B[t]);
+    v[4 + t] = (R)(c.dA[t] + c.A * c.B[t]);
+  }
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[7 + g * 3 + a] = (R)(c.dA[g] * c.B[a] + c.A * c.dB[g * 3 + a]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    R4<R> q;
+    q.x = v[4 * t];
+    q.y = v[4 * t + 1];
+    q.z = v[4 * t + 2];
+    q.w = v[4 * t + 3];
+    S.kc4[4 * s + t] = q;
+  }
+}
+
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long sing = 0;
+  if (s < S.n) {
+    Moments<R> M;
+    accumulate_moments<R, K>(S, s, M);
+    Mom64 D;
+    expand_moments(M, D);
+    if (S.mom) {
+      const int64_t n = S.n;
+      S.mom[s] = (R)D.m0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) S.mom[(1 + t) * n + s] = M.m1[t];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) S.mom[(4 + t) * n + s] = M.m2[t];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) S.mom[(10 + t) * n + s] = M.dm0[t];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) S.mom[(13 + t) * n + s] = M.X1[t];
+#pragma unroll
+      for (int t = 0; t < 18; ++t) S.mom[(22 + t) * n + s] = M.X2[t];
+    }
+    Corr64 c;
+    solve_corrections(D, c);
+    sing = c.singular ? 1 : 0;
+    store_kc(S, s, c);
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    R* A = (R*)o.A;
+    R* B = (R*)o.B;
+    R* gA = (R*)o.gradA;
+    R* gB = (R*)o.gradB;
+    A[p] = (R)c.A;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      B[t * n + p] = (R)c.B[t];
+      gA[t * n + p] = (R)c.dA[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gB[t * n + p] = (R)c.dB[t];
+  }
+  wave_add_u64(&S.cnt[CNT_SINGULAR], sing);
+}
+
+// ------------------------------------------------ density, grad v, EOS ----
+
+template <class R>
+__device__ inline void load_kc(const State<R>& S, int64_t j, KC<R>& k) {
+  const R4<R> q0 = S.kc4[4 * j], q1 = S.kc4[4 * j + 1], q2 = S.kc4[4 * j + 2],
+              q3 = S.kc4[4 * j + 3];
+  k.a = q0.x;
+  k.b[0] = q0.y;
+  k.b[1] = q0.z;
+  k.b[2] = q0.w;
+  k.c[0] = q1.x;
+  k.c[1] = q1.y;
+  k.c[2] = q1.z;
+  k.M[0] = q1.w;
+  k.M[1] = q2.x;
+  k.M[2] = q2.y;
+  k.M[3] = q2.z;
+  k.M[4] = q2.w;
+  k.M[5] = q3.x;
+  k.M[6] = q3.y;
+  k.M[7] = q3.z;
+  k.M[8] = q3.w;
+}
+
+template <class R>
+__device__ inline void load_gv(const State<R>& S, int64_t j, R gv[9], R& relaxed) {
+  const R4<R> q0 = S.gv4[3 * j], q1 = S.gv4[3 * j + 1], q2 = S.gv4[3 * j + 2];
+  gv[0] = q0.x;
+  gv[1] = q0.y;
+  gv[2] = q0.z;
+  gv[3] = q0.w;
+  gv[4] = q1.x;
+  gv[5] = q1.y;
+  gv[6] = q1.z;
+  gv[7] = q1.w;
+  gv[8] = q2.x;
+  relaxed = q2.y;
+}
+
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ rho_out,
+                                                    R* __restrict__ gradv_out) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long nrel = 0;
+  if (s < S.n) {
+    const R4<R> pi = S.pos4[s];
+    const R4<R> vi = S.vel4[s];
+    const R hinv = pi.w;
+    const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+    const R C4 = C3 * hinv;
+    KC<R> ki;
+    load_kc(S, s, ki);
+    // self term: x = 0, W^R_ii = A_i W(0)
+    const R W0 = C3 * R(Shape<K>::w0);
+    R num = S.mass[s] * vi.w * ki.a * W0;
+    R den = vi.w * vi.w * ki.a * W0;
+    R gv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gv[t] = R(0);
+    const int ng = S.ng[s];
+    for (int k = 0; k < ng; ++k) {
+      const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
+      const uint32_t j = e >> kCodeBits;
+      const R4<R> pj = S.pos4[j];
+      const R4<R> vj = S.vel4[j];
+      const R mj = S.mass[j];
+      R x[3];
+      pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+      const R r2 = dot3(x, x);
+      const R rinv = Sc<R>::rsqrt(r2);
+      R w, dw;
+      Shape<K>::eval(r2 * rinv * hinv, w, dw);
+      const R W = C3 * w;
+      const R fg = C4 * dw * rinv;
+      const R gW[3] = {fg * x[0], fg * x[1], fg * x[2]};
+      R WR, gWR[3];
+      kc_apply(ki, x, W, gW, WR, gWR);
+      num += mj * vj.w * WR;
+      den += vj.w * vj.w * WR;
+      const R dv[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) gv[a * 3 + g] -= vj.w * dv[a] * gWR[g];
+    }
+    const R rho = num / den;
+    const R u = S.uu[s];
+    const R gam = R(S.gamma);
+    const R P = (gam - R(1)) * rho * u;
+    const R c = Sc<R>::sqrt(gam * (gam - R(1)) * u);
+    R relaxed = R(0);
+    if (S.dt_relax > 0.0) {
+      const double div = (double)gv[0] + (double)gv[4] + (double)gv[8];
+      // exp(|div v| dt) > 8  <=>  |div v| dt > ln 8
+      if (fabs(div) * S.dt_relax > 2.0794415416798357) {
+        relaxed = R(1);
+        nrel = 1;
+      }
+    }
+    R4<R> st;
+    st.x = rho;
+    st.y = P;
+    st.z = c;
+    st.w = den;
+    S.st4[s] = st;
+    R4<R> g0, g1, g2;
+    g0.x = gv[0]; g0.y = gv[1]; g0.z = gv[2]; g0.w = gv[3];
+    g1.x = gv[4]; g1.y = gv[5]; g1.z = gv[6]; g1.w = gv[7];
+    g2.x = gv[8]; g2.y = relaxed; g2.z = R(0); g2.w = R(0);
+    S.gv4[3 * s] = g0;
+    S.gv4[3 * s + 1] = g1;
+    S.gv4[3 * s + 2] = g2;
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    rho_out[p] = rho;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gradv_out[t * n + p] = gv[t];
+  }
+  wave_add_u64(&S.cnt[CNT_RELAXED], nrel);
+}
+
+// ------------------------------------------------------ force and du/dt ----
+// For j != i with r_ij < max(h_i, h_j):
+//   G_ij = grad_i W^R_ij - grad_j W^R_ji (uncorrected on both sides when
+//   either particle is relaxed),
+//   limiter phi = clamp(4 n d / (n + d)^2, 0, 1) with n = x.(grad v_i x),
+//   d = x.(grad v_j x); midpoint velocity jump
+//   v' = (v_i - phi/2 grad v_i x) - (v_j + phi/2 grad v_j x);
+//   mu_k = min(0, v'.x h_k / (r^2 + eps2 h_k^2)), Q_k = rho_k (-alpha c_k mu_k + beta mu_k^2);
+//   F_ij = -1/2 V_i V_j (P_i + P_j + Q_i + Q_j) G_ij;
+//   a_i = sum F_ij / m_i, du_i/dt = -1/(2 m_i) sum (v_i - v_j).F_ij.
+
+template <class R, int K>
+__device__ inline void side_grad(const KC<R>& k, const R x[3], R r2, R rinv, R hinv,
+                                 R out[3]) {
+  const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+  R w, dw;
+  Shape<K>::eval(r2 * rinv * hinv, w, dw);
+  const R W = C3 * w;
+  const R fg = C3 * hinv * dw * rinv;
+  const R gW[3] = {fg * x[0], fg * x[1], fg * x[2]};
+  R WR;
+  kc_apply(k, x, W, gW, WR, out);
+}
+
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict__ accel,
+                                                  double* __restrict__ dudt) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const R4<R> pi = S.pos4[s];
+  const R4<R> vi = S.vel4[s];
+  const R4<R> si = S.st4[s];
+  KC<R> ki;
+  load_kc(S, s, ki);
+  R gvi[9], reli;
+  load_gv(S, s, gvi, reli);
+  const bool relax_on = S.dt_relax > 0.0;
+  const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
+  const R hi = R(1) / pi.w;
+  double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
+  const int ng = S.ng[s], ns = S.ns[s];
+  const int cap = S.list_cap;
+  const int total = ng + ns;
+  for (int t = 0; t < total; ++t) {
+    const int slot = t < ng ? t : cap - 1 - (t - ng);
+    const uint32_t e = S.nlist[sell_index(s, cap, slot)];
+    const uint32_t j = e >> kCodeBits;
+    const R4<R> pj = S.pos4[j];
+    const R4<R> vj = S.vel4[j];
+    const R4<R> sj = S.st4[j];
+    KC<R> kj;
+    load_kc(S, j, kj);
+    R gvj[9], relj;
+    load_gv(S, j, gvj, relj);
+    R x[3];
+    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    const R r2 = dot3(x, x);
+    const R rinv = Sc<R>::rsqrt(r2);
+    KC<R> kiu = ki;
+    if (relax_on && (reli != R(0) || relj != R(0))) {
+      kc_plain(kiu);
+      kc_plain(kj);
+    }
+    R Gi[3], Gj[3];
+    side_grad<R, K>(kiu, x, r2, rinv, pi.w, Gi);
+    const R xm[3] = {-x[0], -x[1], -x[2]};
+    side_grad<R, K>(kj, xm, r2, rinv, pj.w, Gj);
+    R G[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
+    // limited artificial viscosity
+    R gix[3], gjx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gix[a] = gvi[a * 3] * x[0] + gvi[a * 3 + 1] * x[1] + gvi[a * 3 + 2] * x[2];
+      gjx[a] = gvj[a * 3] * x[0] + gvj[a * 3 + 1] * x[1] + gvj[a * 3 + 2] * x[2];
+    }
+    const R nn = dot3(x, gix), dd = dot3(x, gjx);
+    const R sum = nn + dd;
+    const R s2 = sum * sum;
+    R phi = R(0);
+    if (s2 > R(0)) {
+      phi = R(4) * nn * dd / s2;
+      phi = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+    }
+    const R hp = R(0.5) * phi;
+    const R vp[3] = {(vi.x - vj.x) - hp * (gix[0] + gjx[0]), (vi.y - vj.y) - hp * (gix[1] + gjx[1]),
+                     (vi.z - vj.z) - hp * (gix[2] + gjx[2])};
+    const R vpx = dot3(vp, x);
+    const R hj = R(1) / pj.w;
+    R mui = vpx * hi / (r2 + eps2 * hi * hi);
+    R muj = vpx * hj / (r2 + eps2 * hj * hj);
+    mui = mui < R(0) ? mui : R(0);
+    muj = muj < R(0) ? muj : R(0);
+    const R Qi = si.x * (-alpha * si.z * mui + beta * mui * mui);
+    const R Qj = sj.x * (-alpha * sj.z * muj + beta * muj * muj);
+    const R sfac = R(-0.5) * vi.w * vj.w * (si.y + sj.y + Qi + Qj);
+    const R F[3] = {sfac * G[0], sfac * G[1], sfac * G[2]};
+    const R work = (vi.x - vj.x) * F[0] + (vi.y - vj.y) * F[1] + (vi.z - vj.z) * F[2];
+    acc[0] += (double)F[0];
+    acc[1] += (double)F[1];
+    acc[2] += (double)F[2];
+    du += (double)work;
+  }
+  const int64_t n = S.n;
+  const uint32_t p = S.perm[s];
+  const double minv = 1.0 / (double)S.mass[s];
+  accel[p] = acc[0] * minv;
+  accel[n + p] = acc[1] * minv;
+  accel[2 * n + p] = acc[2] * minv;
+  dudt[p] = -0.5 * du * minv;
+}
+
+// ------------------------------------------------------------ checks -----
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, int64_t na,
+                                                      unsigned long long* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long bad = 0;
+  if (i < na) {
+    const double v = (double)a[i];
+    bad = (v - v == 0.0) ? 0 : 1;
+  }
+  wave_add_u64(&cnt[CNT_NONFINITE], bad);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launchers ----
+
+template <class R>
+void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned long long* cnt,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_check_inputs<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, h, m, u, n, cnt);
+}
+
+void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
+                 uint32_t* cell_count, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys, vals,
+                     cell_count);
+}
+
+template <class R>
+void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, const R* u,
+                   const R* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, x, v, m, u, h);
+}
+
+#define CRK_DISPATCH_K(kernel, KFN, ...)                                                 \
+  do {                                                                                   \
+    if ((kernel) == 0)                                                                   \
+      hipLaunchKernelGGL((KFN<R, 0>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, __VA_ARGS__); \
+    else                                                                                 \
+      hipLaunchKernelGGL((KFN<R, 1>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, __VA_ARGS__); \
+  } while (0)
+
+template <class R>
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {
+  CRK_DISPATCH_K(kernel, k_hsolve, S);
+}
+template <class R>
+void launch_volume(const State<R>& S, int kernel, hipStream_t s) {
+  CRK_DISPATCH_K(kernel, k_volume, S);
+}
+template <class R>
+void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, h_out, V_out);
+}
+template <class R>
+void launch_nlist(const State<R>& S, hipStream_t s) {
+  hipLaunchKernelGGL(k_nlist<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+}
+template <class R>
+void launch_moments(const State<R>& S, int kernel, CorrOut o, hipStream_t s) {
+  CRK_DISPATCH_K(kernel, k_moments, S, o);
+}
+template <class R>
+void launch_density(const State<R>& S, int kernel, R* rho_out, R* gradv_out, hipStream_t s) {
+  CRK_DISPATCH_K(kernel, k_density, S, rho_out, gradv_out);
+}
+template <class R>
+void launch_force(const State<R>& S, int kernel, double* accel, double* dudt, hipStream_t s) {
+  CRK_DISPATCH_K(kernel, k_force, S, accel, dudt);
+}
+template <class R>
+void launch_count_nonfinite(const R* a, int64_t na, unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite<R>, dim3(grid_for(na)), dim3(kBlock), 0, s, a, na, cnt);
+}
+void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long* cnt,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite<double>, dim3(grid_for(na)), dim3(kBlock), 0, s, a, na, cnt);
+}
+
+#define CRK_INSTANTIATE(R)                                                                   \
+  template void launch_check_inputs<R>(const R*, const R*, const R*, int64_t,                \
+                                       unsigned long long*, hipStream_t);                    \
+  template void launch_gather<R>(const State<R>&, const double*, const R*, const R*,         \
+                                 const R*, const R*, hipStream_t);                           \
+  template void launch_hsolve<R>(const State<R>&, int, hipStream_t);                         \
+  template void launch_volume<R>(const State<R>&, int, hipStream_t);                         \
+  template void launch_pack<R>(const State<R>&, R*, R*, hipStream_t);                        \
+  template void launch_nlist<R>(const State<R>&, hipStream_t);                               \
+  template void launch_moments<R>(const State<R>&, int, CorrOut, hipStream_t);               \
+  template void launch_density<R>(const State<R>&, int, R*, R*, hipStream_t);                \
+  template void launch_force<R>(const State<R>&, int, double*, double*, hipStream_t);        \
+  template void launch_count_nonfinite<R>(const R*, int64_t, unsigned long long*, hipStream_t);
+
+CRK_INSTANTIATE(float)
+CRK_INSTANTIATE(double)
+
+}  // namespace crk

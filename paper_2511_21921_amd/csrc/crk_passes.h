@@ -1,0 +1,89 @@
+// Launch wrappers of the forward and adjoint pass kernels (host side).
+#pragma once
+
+#include "crk_internal.h"
+#include "crk_state.h"
+
+namespace crk {
+
+// Max of positive h (as double bits) and a count of bad inputs.
+template <class R>
+void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned long long* cnt,
+                         hipStream_t s);
+
+// Cell keys of wrapped positions, identity values, and per-cell counts.
+void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
+                 uint32_t* cell_count, hipStream_t s);
+
+// Gather caller arrays into cell-sorted SoA with cell-centre offsets.
+template <class R>
+void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, const R* u,
+                   const R* h, hipStream_t s);
+
+template <class R>
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s);
+template <class R>
+void launch_volume(const State<R>& S, int kernel, hipStream_t s);
+// Stores 1/h and V into the packed records and writes h, V in caller order.
+template <class R>
+void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s);
+template <class R>
+void launch_nlist(const State<R>& S, hipStream_t s);
+
+struct CorrOut {
+  void *A, *B, *gradA, *gradB;
+};
+template <class R>
+void launch_moments(const State<R>& S, int kernel, CorrOut o, hipStream_t s);
+template <class R>
+void launch_density(const State<R>& S, int kernel, R* rho_out, R* gradv_out, hipStream_t s);
+template <class R>
+void launch_force(const State<R>& S, int kernel, double* accel, double* dudt, hipStream_t s);
+
+// Non-finite output count over a Real array and a double array.
+template <class R>
+void launch_count_nonfinite(const R* a, int64_t na, unsigned long long* cnt, hipStream_t s);
+void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long* cnt,
+                                hipStream_t s);
+
+// ---- adjoint ------------------------------------------------------------
+template <class R>
+struct AdjState {
+  // per-particle adjoint accumulators (sorted order, FP64)
+  double* gx;    // [3][n] position adjoint
+  double* gv;    // [3][n] velocity adjoint
+  double* gu;    // [n]
+  double* gh;    // [n] smoothing-length adjoint
+  double* gV;    // [n] volume adjoint
+  double* gkc;   // [16][n] adjoint of (A, B, gradA, gradB) in that order
+  double* grho;  // [n]
+  double* ggv;   // [9][n] adjoint of grad v
+  double* gP;    // [n]
+  double* gc;    // [n]
+  double* gmom;  // [40][n] adjoint of the moments
+  double* gab;   // [2][n] per-particle alpha, beta partials
+  double* coef;  // [4][n] per-particle helper coefficients between passes
+  const double* w_a;  // [3][n] loss weights, caller order
+  const double* w_u;  // [n]
+};
+
+template <class R>
+void launch_bwd_force(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
+template <class R>
+void launch_bwd_eos(const State<R>& S, const AdjState<R>& G, hipStream_t s);
+template <class R>
+void launch_bwd_density(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
+template <class R>
+void launch_bwd_corr(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
+template <class R>
+void launch_bwd_moments(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
+template <class R>
+void launch_bwd_volume_prep(const State<R>& S, const AdjState<R>& G, int kernel, int h_mode,
+                            hipStream_t s);
+template <class R>
+void launch_bwd_volume(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
+template <class R>
+void launch_bwd_finish(const State<R>& S, const AdjState<R>& G, double* g_x, double* g_v,
+                       double* g_u, double* g_ab, hipStream_t s);
+
+}  // namespace crk
