@@ -271,17 +271,29 @@ HResult solve_h(const Finder& F, const double* m, int kernel, double n_h, int64_
   }
   double lo = 0.0, hi = R, h = std::min(guess, R);
   int it = 0;
+  bool ok = false;
   for (; it < 300; ++it) {
     double dfdh;
     double f = f_of_h(kernel, n_h3, r, mr, h, &dfdh);
     if (f > 0.0) hi = h; else lo = h;
-    double hn = (dfdh > 0.0) ? h - f / dfdh : 0.5 * (lo + hi);
-    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-    double step = std::fabs(hn - h);
+    double hn = 0.5 * (lo + hi);
+    if (dfdh > 0.0) {
+      double nt = h - f / dfdh;
+      // a Newton step below the tolerance ends the solve (h sits on the root)
+      if (std::fabs(nt - h) <= rtol * h) {
+        h = std::min(std::max(nt, lo), hi);
+        ok = true;
+        break;
+      }
+      if (nt > lo && nt < hi) hn = nt;
+    }
     h = hn;
-    if (step <= rtol * h || (hi - lo) <= rtol * h) break;
+    if ((hi - lo) <= rtol * h) {
+      ok = true;
+      break;
+    }
   }
-  return {h, it + 1, it < 300};
+  return {h, it + 1, ok};
 }
 
 // ------------------------------------------------------------- the passes --
@@ -672,6 +684,15 @@ Params make_params(double box, double gamma, double alpha, double beta, double e
 }  // namespace
 
 extern "C" {
+
+// Threads the OpenMP loops use.
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Shape functions w(q), w'(q) on an array of q (pins of the kernel).
 void oracle_kernel_eval(int kernel, int64_t n, const double* q, double* w, double* dw,
