@@ -89,6 +89,7 @@ typedef struct {
   double dt_relax;   /* RK relaxation time step (App. A.1); 0 disables */
   int store_corrections; /* 1: keep moments for the adjoint; 0: recompute them */
   int check_finite;  /* 1: count non-finite outputs and fail with CRK_ENONFINITE */
+  int timing;        /* 1: time every pass with HIP events (see crk_pass_times) */
 } crk_params;
 
 typedef struct {
@@ -156,6 +157,18 @@ crk_status crk_forward(crk_ctx *ctx, void *hip_stream, long long n, const double
 crk_status crk_backward(crk_ctx *ctx, void *hip_stream, long long n, const double *g_accel,
                         const double *g_dudt, double *g_x, double *g_v, double *g_u,
                         double *g_alpha_beta);
+
+/* Per-pass device time. Passes are numbered 0 .. crk_pass_count()-1 and
+ * named by crk_pass_name(k) (NULL when k is out of range). With
+ * params.timing = 1 every pass of crk_forward / crk_backward is bracketed by
+ * HIP events recorded on the call's stream; crk_pass_times() waits for the
+ * recorded events, writes the accumulated milliseconds of each pass to
+ * ms[k] and the number of timed launches to calls[k] (host arrays of
+ * crk_pass_count() entries, either may be NULL), and clears the totals when
+ * reset != 0. */
+int crk_pass_count(void);
+const char *crk_pass_name(int k);
+crk_status crk_pass_times(crk_ctx *ctx, double *ms, long long *calls, int reset);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,8 @@ def lib():
         _lib = C.CDLL(_LIB)
         D = C.POINTER(C.c_double)
         I64 = C.POINTER(C.c_int64)
+        _lib.oracle_num_threads.argtypes = []
+        _lib.oracle_num_threads.restype = C.c_int
         _lib.oracle_kernel_eval.argtypes = [C.c_int, C.c_int64, D, D, D, D]
         _lib.oracle_neighbours.argtypes = [C.c_int64, D, D, C.c_double, C.c_int, C.c_int, I64, I64]
         _lib.oracle_neighbours.restype = C.c_int
@@ -82,6 +84,10 @@ class Params:
     def args(self):
         return [self.box, self.gamma, self.alpha, self.beta, self.eps2, self.n_h, self.dt_relax,
                 self.kernel, self.h_mode]
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
 
 
 def kernel_eval(kernel: int, q):

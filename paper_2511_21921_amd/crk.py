@@ -33,7 +33,7 @@ class crk_params(C.Structure):
                 ("beta", C.c_double), ("eps2", C.c_double), ("n_h", C.c_double),
                 ("kernel", C.c_int), ("precision", C.c_int), ("h_mode", C.c_int),
                 ("h_max_iter", C.c_int), ("h_rtol", C.c_double), ("dt_relax", C.c_double),
-                ("store_corrections", C.c_int), ("check_finite", C.c_int)]
+                ("store_corrections", C.c_int), ("check_finite", C.c_int), ("timing", C.c_int)]
 
 
 class crk_stats(C.Structure):
@@ -46,7 +46,8 @@ class crk_stats(C.Structure):
 
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
-           "crk_last_error", "crk_forward", "crk_backward"]
+           "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
+           "crk_pass_times"]
 
 _lib = None
 
@@ -76,6 +77,12 @@ def lib():
         L.crk_forward.restype = C.c_int
         L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 7
         L.crk_backward.restype = C.c_int
+        L.crk_pass_count.argtypes = []
+        L.crk_pass_count.restype = C.c_int
+        L.crk_pass_name.argtypes = [C.c_int]
+        L.crk_pass_name.restype = C.c_char_p
+        L.crk_pass_times.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
+        L.crk_pass_times.restype = C.c_int
         _lib = L
     return _lib
 
@@ -96,6 +103,7 @@ class Params:
     dt_relax: float = 0.0
     store_corrections: int = 0
     check_finite: int = 0
+    timing: int = 0
 
     def to_c(self) -> crk_params:
         p = crk_params()
@@ -202,6 +210,15 @@ class Context:
         if stats:
             out["stats"] = st.as_dict()
         return out
+
+    def pass_times(self, reset: bool = False) -> dict:
+        """Accumulated device time per pass: {name: (total_ms, launches)}."""
+        L = lib()
+        k = L.crk_pass_count()
+        ms = (C.c_double * k)()
+        calls = (C.c_longlong * k)()
+        self._raise(L.crk_pass_times(self._h, ms, calls, int(reset)))
+        return {L.crk_pass_name(i).decode(): (ms[i], calls[i]) for i in range(k)}
 
     def backward(self, g_accel: torch.Tensor, g_dudt: torch.Tensor) -> dict:
         """Adjoint of the last forward for L = sum g_accel.accel + sum g_dudt dudt."""

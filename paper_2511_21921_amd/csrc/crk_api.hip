@@ -26,12 +26,28 @@ struct Buf {
 
 }  // namespace
 
+namespace {
+enum Pass {
+  P_CELLS = 0, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
+  P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_NPASS
+};
+const char* kPassNames[P_NPASS] = {"cells", "hsolve", "nlist", "moments", "density", "force",
+                                   "bwd_force", "bwd_density", "bwd_corr", "bwd_moments",
+                                   "bwd_volume", "bwd_other"};
+}  // namespace
+
 struct crk_ctx {
   crk_params p;
+  // per-pass timing
+  hipEvent_t ev0[P_NPASS] = {}, ev1[P_NPASS] = {};
+  bool pending[P_NPASS] = {};
+  double ms_total[P_NPASS] = {};
+  long long ms_calls[P_NPASS] = {};
+  bool events_ready = false;
   std::string err;
   // workspace
   Buf keys_a, keys_b, vals_a, vals_b, cell_count, cell_start, sort_tmp, scan_tmp;
-  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, ng, ns, scr;
+  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, ng, ns, scr, cand, ccnt;
   Buf cnt;
   // adjoint workspace
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_grho, a_ggv, a_gP, a_gc, a_gmom, a_gab, a_coef;
@@ -42,6 +58,7 @@ struct crk_ctx {
   long long n_last = -1;
   int G = 0;
   double ell = 0.0;
+  double rcap = 0.0;
   int precision_last = -1;
   bool reserved_fixed = false;
 };
@@ -136,6 +153,7 @@ hipError_t ensure_particles(crk_ctx* c, int64_t n) {
   ENS(kc4, 16 * R * npad);
   ENS(ng, 4 * npad);
   ENS(ns, 4 * npad);
+  ENS(ccnt, 4 * npad);
   ENS(cnt, 8 * CNT_COUNT);
   if (c->p.store_corrections) ENS(mom, 40 * R * npad);
 #undef ENS
@@ -167,8 +185,11 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.ng = (int*)c->ng.p;
   S.ns = (int*)c->ns.p;
   S.list_cap = c->list_cap;
+  S.cand = (uint32_t*)c->cand.p;
   S.scr = (R*)c->scr.p;
+  S.ccnt = (int*)c->ccnt.p;
   S.scr_cap = c->scr_cap;
+  S.rcap = (R)c->rcap;
   S.cnt = (unsigned long long*)c->cnt.p;
   S.n_h3 = c->p.n_h * c->p.n_h * c->p.n_h;
   S.gamma = c->p.gamma;
@@ -179,6 +200,39 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.rtol = c->p.h_rtol;
   S.max_iter = c->p.h_max_iter;
   return S;
+}
+
+hipError_t harvest(crk_ctx* c, int k) {
+  if (!c->pending[k]) return hipSuccess;
+  hipError_t e = hipEventSynchronize(c->ev1[k]);
+  if (e != hipSuccess) return e;
+  float ms = 0.f;
+  e = hipEventElapsedTime(&ms, c->ev0[k], c->ev1[k]);
+  if (e != hipSuccess) return e;
+  c->ms_total[k] += ms;
+  c->ms_calls[k] += 1;
+  c->pending[k] = false;
+  return hipSuccess;
+}
+
+hipError_t tbegin(crk_ctx* c, int k, hipStream_t s) {
+  if (!c->p.timing) return hipSuccess;
+  hipError_t e;
+  if (!c->events_ready) {
+    for (int i = 0; i < P_NPASS; ++i) {
+      if ((e = hipEventCreate(&c->ev0[i])) != hipSuccess) return e;
+      if ((e = hipEventCreate(&c->ev1[i])) != hipSuccess) return e;
+    }
+    c->events_ready = true;
+  }
+  if ((e = harvest(c, k)) != hipSuccess) return e;
+  return hipEventRecord(c->ev0[k], s);
+}
+
+hipError_t tend(crk_ctx* c, int k, hipStream_t s) {
+  if (!c->p.timing) return hipSuccess;
+  c->pending[k] = true;
+  return hipEventRecord(c->ev1[k], s);
 }
 
 hipError_t read_counters(crk_ctx* c, hipStream_t s) {
@@ -246,34 +300,41 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
   ctx->G = choose_grid(P.box, reach, n);
   ctx->ell = P.box / ctx->G;
+  const int64_t npad = ((n + 63) / 64) * 64;
   bool solved = false;
   for (int attempt = 0; attempt < 12 && !solved; ++attempt) {
+    // candidates reach the cell side when h is solved, the largest h otherwise
+    ctx->rcap = P.h_mode == 1 ? ctx->ell : h0max;
     CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+    CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
     crk_status st = build_cells<R>(ctx, s, n, x);
     if (st != CRK_OK) return st;
-    State<R> S = make_state<R>(ctx, n);
-    launch_gather<R>(S, x, v, m, u, h, s);
-    if (P.h_mode == 0) {
-      launch_volume<R>(S, P.kernel, s);
-      solved = true;
-      break;
+    {
+      State<R> S = make_state<R>(ctx, n);
+      launch_gather<R>(S, x, v, m, u, h, s);
     }
-    const int64_t npad = ((n + 63) / 64) * 64;
+    CRK_HIP(tend(ctx, P_CELLS, s), "event");
+    CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
     CRK_HIP(ensure(ctx->scr, 2 * real_size(P.precision) * (size_t)npad * ctx->scr_cap),
-            "alloc h scratch");
-    S = make_state<R>(ctx, n);
-    launch_hsolve<R>(S, P.kernel, s);
+            "alloc candidates");
+    State<R> S = make_state<R>(ctx, n);
+    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+    launch_candidates<R>(S, s);
+    if (P.h_mode == 0)
+      launch_volume<R>(S, P.kernel, s);
+    else
+      launch_hsolve<R>(S, P.kernel, s);
+    CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
     CRK_HIP(read_counters(ctx, s), "h solve");
     if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
       ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);
-      continue;  // same grid, larger scratch
+      continue;  // same grid, larger candidate capacity
     }
-    if (ctx->host_cnt[CNT_H_CAPPED]) {
+    if (P.h_mode == 1 && ctx->host_cnt[CNT_H_CAPPED]) {
       if (ctx->G == 1) return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
       // cells too small for some root: widen them and solve again
-      const int G2 = std::max(1, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
-      ctx->G = G2;
+      ctx->G = std::max(1, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
       ctx->ell = P.box / ctx->G;
       continue;
     }
@@ -290,13 +351,14 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     launch_pack<R>(S, h, V, s);
   }
   // neighbour list, grown until it fits
-  const int64_t npad = ((n + 63) / 64) * 64;
   for (int attempt = 0; attempt < 8; ++attempt) {
     CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8, s), "memset");
+    CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
     launch_nlist<R>(S, s);
+    CRK_HIP(tend(ctx, P_NLIST, s), "event");
     CRK_HIP(hipGetLastError(), "neighbour list launch");
     CRK_HIP(read_counters(ctx, s), "neighbour list");
     const unsigned long long need = ctx->host_cnt[CNT_LIST_OVERFLOW];
@@ -306,9 +368,15 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   }
   State<R> S = make_state<R>(ctx, n);
   CorrOut co{A, B, gradA, gradB};
+  CRK_HIP(tbegin(ctx, P_MOMENTS, s), "event");
   launch_moments<R>(S, P.kernel, co, s);
+  CRK_HIP(tend(ctx, P_MOMENTS, s), "event");
+  CRK_HIP(tbegin(ctx, P_DENSITY, s), "event");
   launch_density<R>(S, P.kernel, rho, gradv, s);
+  CRK_HIP(tend(ctx, P_DENSITY, s), "event");
+  CRK_HIP(tbegin(ctx, P_FORCE, s), "event");
   launch_force<R>(S, P.kernel, accel, dudt, s);
+  CRK_HIP(tend(ctx, P_FORCE, s), "event");
   CRK_HIP(hipGetLastError(), "pass launch");
   if (P.check_finite) {
     launch_count_nonfinite_f64(accel, 3 * n, dcnt, s);
@@ -401,8 +469,9 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
   if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
   const int64_t npad = ((n_max + 63) / 64) * 64;
   e = ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap);
-  if (e == hipSuccess && ctx->p.h_mode == 1)
+  if (e == hipSuccess)
     e = ensure(ctx->scr, 2 * real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
+  if (e == hipSuccess) e = ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap);
   if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
   return CRK_OK;
 }
@@ -412,15 +481,39 @@ crk_status crk_destroy(crk_ctx* c) {
   Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_count, &c->cell_start,
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->ng, &c->ns,
-                &c->scr, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
+                &c->scr, &c->cand, &c->ccnt, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_grho, &c->a_ggv, &c->a_gP, &c->a_gc, &c->a_gmom, &c->a_gab, &c->a_coef};
   for (Buf* b : all) release(*b);
   if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+  if (c->events_ready)
+    for (int i = 0; i < P_NPASS; ++i) {
+      (void)hipEventDestroy(c->ev0[i]);
+      (void)hipEventDestroy(c->ev1[i]);
+    }
   delete c;
   return CRK_OK;
 }
 
 const char* crk_last_error(const crk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int crk_pass_count(void) { return P_NPASS; }
+
+const char* crk_pass_name(int k) { return (k >= 0 && k < P_NPASS) ? kPassNames[k] : nullptr; }
+
+crk_status crk_pass_times(crk_ctx* ctx, double* ms, long long* calls, int reset) {
+  if (!ctx) return CRK_EINVAL;
+  for (int k = 0; k < P_NPASS; ++k) {
+    hipError_t e = harvest(ctx, k);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pass timing");
+    if (ms) ms[k] = ctx->ms_total[k];
+    if (calls) calls[k] = ctx->ms_calls[k];
+    if (reset) {
+      ctx->ms_total[k] = 0.0;
+      ctx->ms_calls[k] = 0;
+    }
+  }
+  return CRK_OK;
+}
 
 crk_status crk_forward(crk_ctx* ctx, void* hip_stream, long long n, const double* x,
                        const void* v, const void* m, const void* u, void* h, void* V, void* rho,

@@ -130,22 +130,20 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   S.hbuf[s] = h[p];
 }
 
-// ------------------------------------------------------------- h solve ----
-// f(h) = C (w(0) + sum_{j != i} (m_j/m_i) w(r_ij / h)) - n_h^3, which is
-// h^3 sum_j (m_j/m_i) W(r_ij, h) - n_h^3: zero exactly when Delta_N = 1.
-// Candidates within the cell side are collected once into the SELL
-// scratch; the safeguarded Newton iterations then only re-read them.
+// ---------------------------------------------------------- candidates ----
+// One traversal of the 27 stencil cells per particle collects every j != i
+// with r_ij < rcap (rcap >= every h), storing the packed entry and
+// (r, m_j / m_i). The h solve, the fixed-h volume and the neighbour list all
+// read this list instead of walking the cells again.
 
-template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool live = s < S.n;
-  unsigned long long iters = 0, unconv = 0, capped = 0, ovf = 0, hbits = 0;
-  if (live) {
+  unsigned long long ovf = 0;
+  if (s < S.n) {
     const R4<R> pi = S.pos4[s];
     const R mi_inv = R(1) / S.mass[s];
-    const R Rcap = S.ell;
-    const R Rcap2 = Rcap * Rcap;
+    const R rc2 = S.rcap * S.rcap;
     int cnt = 0;
     for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
       if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
@@ -153,73 +151,102 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       R x[3];
       pair_sep<R>(pi, pj, code, S.ell, x);
       const R r2 = dot3(x, x);
-      if (r2 < Rcap2) {
+      if (r2 < rc2) {
         if (cnt < S.scr_cap) {
           const int64_t e = sell_index(s, S.scr_cap, cnt);
+          S.cand[e] = (j << kCodeBits) | code;
           S.scr[2 * e] = Sc<R>::sqrt(r2);
           S.scr[2 * e + 1] = S.mass[j] * mi_inv;
         }
         ++cnt;
       }
     });
-    if (cnt > S.scr_cap) {
-      ovf = (unsigned long long)cnt;
+    // only the stored entries are ever read; the overflow makes the host
+    // grow the capacity and run the candidate pass again
+    S.ccnt[s] = cnt < S.scr_cap ? cnt : S.scr_cap;
+    if (cnt > S.scr_cap) ovf = (unsigned long long)cnt;
+  }
+  wave_max_u64(&S.cnt[CNT_SCR_OVERFLOW], ovf);
+}
+
+// sum_k (m_k/m_i) w(r_k / h) over the candidates plus the self term w(0), and
+// dsum = sum_k (m_k/m_i) w'(q_k) q_k.
+template <class R, int K>
+__device__ inline R candidate_sum(const State<R>& S, int64_t s, int cnt, R h, R& dsum) {
+  if (cnt > S.scr_cap) cnt = S.scr_cap;
+  const R hinv = R(1) / h;
+  R sum = R(Shape<K>::w0), ds = R(0);
+  for (int k = 0; k < cnt; ++k) {
+    const int64_t e = sell_index(s, S.scr_cap, k);
+    const R q = S.scr[2 * e] * hinv;
+    const R mr = S.scr[2 * e + 1];
+    R w, dw;
+    Shape<K>::eval(q, w, dw);
+    sum += mr * w;
+    ds += mr * dw * q;
+  }
+  dsum = ds;
+  return sum;
+}
+
+// ------------------------------------------------------------- h solve ----
+// f(h) = C (w(0) + sum_{j != i} (m_j/m_i) w(r_ij / h)) - n_h^3, which is
+// h^3 sum_j (m_j/m_i) W(r_ij, h) - n_h^3: zero exactly when Delta_N = 1.
+// f is non-decreasing in h; safeguarded Newton inside a bisection bracket,
+// stopping when a Newton step falls below the tolerance.
+
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
+  if (s < S.n) {
+    const int cnt = S.ccnt[s];
+    const R C = R(Shape<K>::C);
+    const R n_h3 = R(S.n_h3);
+    const R Rcap = S.rcap;
+    R h, dsum;
+    if (!(C * candidate_sum<R, K>(S, s, cnt, Rcap, dsum) - n_h3 > R(0))) {
+      capped = 1;  // the root lies beyond the candidate radius
+      h = Rcap;
     } else {
-      const R C = R(Shape<K>::C);
-      const R n_h3 = R(S.n_h3);
-      auto fsum = [&](R h, R& dsum) {
-        const R hinv = R(1) / h;
-        R sum = R(Shape<K>::w0), ds = R(0);
-        for (int k = 0; k < cnt; ++k) {
-          const int64_t e = sell_index(s, S.scr_cap, k);
-          const R q = S.scr[2 * e] * hinv;
-          const R mr = S.scr[2 * e + 1];
-          R w, dw;
-          Shape<K>::eval(q, w, dw);
-          sum += mr * w;
-          ds += mr * dw * q;
-        }
-        dsum = ds;
-        return sum;
-      };
-      R h;
-      R dsum;
-      if (!(C * fsum(Rcap, dsum) - n_h3 > R(0))) {
-        capped = 1;
-        h = Rcap;
-      } else {
-        R lo = R(0), hi = Rcap;
-        h = S.hbuf[s];
-        if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
-        const R rtol = R(S.rtol);
-        bool conv = false;
-        int it = 0;
-        for (; it < S.max_iter; ++it) {
-          const R f = C * fsum(h, dsum) - n_h3;
-          const R fp = -C * dsum / h;
-          if (f > R(0)) hi = h; else lo = h;
-          R hn = (fp > R(0)) ? h - f / fp : R(0.5) * (lo + hi);
-          if (!(hn > lo && hn < hi)) hn = R(0.5) * (lo + hi);
-          const R step = hn > h ? hn - h : h - hn;
-          h = hn;
-          if (step <= rtol * h || (hi - lo) <= rtol * h) {
+      R lo = R(0), hi = Rcap;
+      h = S.hbuf[s];
+      if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
+      const R rtol = R(S.rtol);
+      bool conv = false;
+      int it = 0;
+      for (; it < S.max_iter; ++it) {
+        const R f = C * candidate_sum<R, K>(S, s, cnt, h, dsum) - n_h3;
+        const R fp = -C * dsum / h;
+        if (f > R(0)) hi = h; else lo = h;
+        R hn = R(0.5) * (lo + hi);
+        if (fp > R(0)) {
+          const R nt = h - f / fp;
+          const R step = nt > h ? nt - h : h - nt;
+          if (step <= rtol * h) {
+            h = nt < lo ? lo : (nt > hi ? hi : nt);
             conv = true;
             break;
           }
+          if (nt > lo && nt < hi) hn = nt;
         }
-        iters = (unsigned long long)(it + 1);
-        unconv = conv ? 0 : 1;
+        h = hn;
+        if (hi - lo <= rtol * h) {
+          conv = true;
+          break;
+        }
       }
-      const R sum = fsum(h, dsum);
-      S.hbuf[s] = h;
-      S.Vbuf[s] = h * h * h / (C * sum);
-      hbits = dbits((double)h);
+      iters = (unsigned long long)(it + 1);
+      unconv = conv ? 0 : 1;
     }
+    const R sum = candidate_sum<R, K>(S, s, cnt, h, dsum);
+    S.hbuf[s] = h;
+    S.Vbuf[s] = h * h * h / (C * sum);
+    hbits = dbits((double)h);
   }
   wave_max_u64(&S.cnt[CNT_H_ITER_MAX], iters);
   wave_add_u64(&S.cnt[CNT_H_UNCONV], unconv);
   wave_add_u64(&S.cnt[CNT_H_CAPPED], capped);
-  wave_max_u64(&S.cnt[CNT_SCR_OVERFLOW], ovf);
   wave_max_u64(&S.cnt[CNT_HMAX_OUT_BITS], hbits);
 }
 
@@ -228,25 +255,10 @@ template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (s >= S.n) return;
-  const R4<R> pi = S.pos4[s];
   const R h = S.hbuf[s];
-  const R hinv = R(1) / h;
-  const R h2 = h * h;
-  const R mi_inv = R(1) / S.mass[s];
-  R sum = R(Shape<K>::w0);
-  for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
-    if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
-    const R4<R> pj = S.pos4[j];
-    R x[3];
-    pair_sep<R>(pi, pj, code, S.ell, x);
-    const R r2 = dot3(x, x);
-    if (r2 < h2) {
-      R w, dw;
-      Shape<K>::eval(Sc<R>::sqrt(r2) * hinv, w, dw);
-      sum += S.mass[j] * mi_inv * w;
-    }
-  });
-  S.Vbuf[s] = h * h2 / (R(Shape<K>::C) * sum);
+  R dsum;
+  const R sum = candidate_sum<R, K>(S, s, S.ccnt[s], h, dsum);
+  S.Vbuf[s] = h * h * h / (R(Shape<K>::C) * sum);
 }
 
 template <class R>
@@ -273,13 +285,14 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     const R hi2 = pi.w * pi.w;  // 1/h_i^2
     int ng = 0, ns = 0;
     const int cap = S.list_cap;
-    for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
-      if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
+    const int cc = S.ccnt[s] < S.scr_cap ? S.ccnt[s] : S.scr_cap;
+    for (int k = 0; k < cc; ++k) {
+      const uint32_t e = S.cand[sell_index(s, S.scr_cap, k)];
+      const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       R x[3];
-      pair_sep<R>(pi, pj, code, S.ell, x);
+      pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
       const R r2 = dot3(x, x);
-      const uint32_t e = (j << kCodeBits) | code;
       if (r2 * hi2 < R(1)) {
         if (ng + ns < cap) S.nlist[sell_index(s, cap, ng)] = e;
         ++ng;
@@ -287,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
         if (ng + ns < cap) S.nlist[sell_index(s, cap, cap - 1 - ns)] = e;
         ++ns;
       }
-    });
+    }
     S.ng[s] = ng;
     S.ns[s] = ns;
     g = (unsigned long long)ng;
@@ -334,7 +347,7 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
   for (int t = 0; t < 9; ++t) M.X1[t] = R(0);
 #pragma unroll
   for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
-  const int ng = S.ng[s];
+  const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
   for (int k = 0; k < ng; ++k) {
     const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
     const uint32_t j = e >> kCodeBits;
@@ -581,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
     R gv[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) gv[t] = R(0);
-    const int ng = S.ng[s];
+    const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
     for (int k = 0; k < ng; ++k) {
       const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
       const uint32_t j = e >> kCodeBits;
@@ -683,8 +696,9 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
   const R hi = R(1) / pi.w;
   double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
-  const int ng = S.ng[s], ns = S.ns[s];
   const int cap = S.list_cap;
+  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
+  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
   const int total = ng + ns;
   for (int t = 0; t < total; ++t) {
     const int slot = t < ng ? t : cap - 1 - (t - ng);
@@ -799,6 +813,10 @@ void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, c
   } while (0)
 
 template <class R>
+void launch_candidates(const State<R>& S, hipStream_t s) {
+  hipLaunchKernelGGL(k_candidates<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+}
+template <class R>
 void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {
   CRK_DISPATCH_K(kernel, k_hsolve, S);
 }
@@ -840,6 +858,7 @@ void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long*
                                        unsigned long long*, hipStream_t);                    \
   template void launch_gather<R>(const State<R>&, const double*, const R*, const R*,         \
                                  const R*, const R*, hipStream_t);                           \
+  template void launch_candidates<R>(const State<R>&, hipStream_t);                          \
   template void launch_hsolve<R>(const State<R>&, int, hipStream_t);                         \
   template void launch_volume<R>(const State<R>&, int, hipStream_t);                         \
   template void launch_pack<R>(const State<R>&, R*, R*, hipStream_t);                        \

@@ -20,6 +20,9 @@ template <class R>
 void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, const R* u,
                    const R* h, hipStream_t s);
 
+// Candidates within rcap (every j != i that any later pass can need).
+template <class R>
+void launch_candidates(const State<R>& S, hipStream_t s);
 template <class R>
 void launch_hsolve(const State<R>& S, int kernel, hipStream_t s);
 template <class R>

@@ -15,7 +15,7 @@ enum Counter {
   CNT_H_ITER_MAX,
   CNT_H_UNCONV,
   CNT_H_CAPPED,
-  CNT_SCR_OVERFLOW,    // largest candidate count beyond the h-solve scratch
+  CNT_SCR_OVERFLOW,    // largest candidate count beyond the candidate capacity
   CNT_LIST_OVERFLOW,   // largest neighbour count beyond the list capacity
   CNT_SINGULAR,
   CNT_RELAXED,
@@ -50,9 +50,13 @@ struct State {
   int* ng;      // gather entries (r < h_i), stored from slot 0 upwards
   int* ns;      // scatter-only entries (h_i <= r < h_j), from slot cap-1 down
   int list_cap;
-  // h-solve scratch (SELL): candidate (r, m_j/m_i) pairs
+  // candidates within rcap of each particle (SELL, slices of 64):
+  // packed entries as in the neighbour list, and (r, m_j/m_i) pairs
+  uint32_t* cand;
   R* scr;
+  int* ccnt;
   int scr_cap;
+  R rcap;
   unsigned long long* cnt;
   // parameters
   double n_h3, gamma, alpha, beta, eps2, dt_relax, rtol;

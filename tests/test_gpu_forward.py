@@ -67,6 +67,8 @@ def test_ragged_random_masses(precision):
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
 def test_wendland_c4(precision):
+    """C4 kernel at ~100 neighbours; the first candidate pass overflows its
+    initial capacity (~310 candidates per particle), exercising the regrow path."""
     ps = synth.random_small(2000, 32)
     ps.n_h = synth.n_h_for_neighbours(100)
     _compare(ps, precision, FP64_BOUNDS if precision == FP64 else FP32_BOUNDS,
