@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import torch
 
@@ -75,7 +75,7 @@ def lib():
         L.crk_last_error.restype = C.c_char_p
         L.crk_forward.argtypes = [P, P, C.c_longlong] + [P] * 14 + [C.POINTER(crk_stats)]
         L.crk_forward.restype = C.c_int
-        L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 7
+        L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 6
         L.crk_backward.restype = C.c_int
         L.crk_pass_count.argtypes = []
         L.crk_pass_count.restype = C.c_int
@@ -145,6 +145,7 @@ class Context:
         if st != 0:
             raise CrkError(st, "crk_create rejected the parameters")
         self._h = h
+        self.generation = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -201,6 +202,7 @@ class Context:
             out["h"].copy_(h)
         st = crk_stats()
         stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        self.generation += 1
         rc = lib().crk_forward(self._h, stream, n, _ptr(x), _ptr(v), _ptr(m), _ptr(u),
                                _ptr(out["h"]), _ptr(out["V"]), _ptr(out["rho"]), _ptr(out["A"]),
                                _ptr(out["B"]), _ptr(out["gradA"]), _ptr(out["gradB"]),
@@ -235,3 +237,50 @@ class Context:
                                 _ptr(o["g_v"]), _ptr(o["g_u"]), _ptr(o["g_alpha_beta"]))
         self._raise(rc)
         return o
+
+
+class CRKSPHFunction(torch.autograd.Function):
+    """Differentiable CRKSPH evaluation through libcrk.so.
+
+    apply(x, v, u, alpha_beta, m, h0, context) returns
+    (accel, dudt, h, rho, V, A, B, gradA, gradB, gradv). Only accel and dudt
+    carry gradients; the backward returns the adjoints of x (float64
+    [3, n]), v, u (Real) and alpha_beta (a float64 tensor [2] holding the
+    viscosity coefficients). Masses and the first h guess are constants.
+    The backward runs on the state the forward left on ``context``; if
+    another forward has run on that context since, the forward is first
+    repeated from the saved inputs.
+    """
+
+    @staticmethod
+    def _run(context, x, v, u, ab, m, h0):
+        ab = ab.detach().to("cpu", torch.float64)
+        context.set_params(replace(context.params, alpha=float(ab[0]), beta=float(ab[1])))
+        return context.forward(x.detach().contiguous(), v.detach().contiguous(), m.contiguous(),
+                               u.detach().contiguous(), h0.contiguous())
+
+    @staticmethod
+    def forward(ctx, x, v, u, alpha_beta, m, h0, context):
+        out = CRKSPHFunction._run(context, x, v, u, alpha_beta, m, h0)
+        ctx.context = context
+        ctx.generation = context.generation
+        ctx.save_for_backward(x, v, u, alpha_beta, m, h0)
+        nd = [out[k] for k in ("h", "rho", "V", "A", "B", "gradA", "gradB", "gradv")]
+        ctx.mark_non_differentiable(*nd)
+        return (out["accel"], out["dudt"], *nd)
+
+    @staticmethod
+    def backward(ctx, g_accel, g_dudt, *unused):
+        context = ctx.context
+        x, v, u, ab, m, h0 = ctx.saved_tensors
+        if context.generation != ctx.generation:
+            CRKSPHFunction._run(context, x, v, u, ab, m, h0)
+        n = int(m.shape[0])
+        if g_accel is None:
+            g_accel = torch.zeros(3, n, dtype=torch.float64, device=x.device)
+        if g_dudt is None:
+            g_dudt = torch.zeros(n, dtype=torch.float64, device=x.device)
+        o = context.backward(g_accel.to(torch.float64).contiguous(),
+                             g_dudt.to(torch.float64).contiguous())
+        return (o["g_x"], o["g_v"].to(v.dtype), o["g_u"].to(u.dtype),
+                o["g_alpha_beta"].to(ab.device, ab.dtype), None, None, None)

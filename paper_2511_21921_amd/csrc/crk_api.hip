@@ -50,7 +50,7 @@ struct crk_ctx {
   Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, ng, ns, scr, cand, ccnt;
   Buf cnt;
   // adjoint workspace
-  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_grho, a_ggv, a_gP, a_gc, a_gmom, a_gab, a_coef;
+  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_grho, a_ggv, a_gmom, a_gab, a_coef;
   unsigned long long* host_cnt = nullptr;
   int list_cap = 128;
   int scr_cap = 192;
@@ -413,6 +413,60 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   return result;
 }
 
+template <class R>
+crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g_accel,
+                         const double* g_dudt, double* g_x, double* g_v, double* g_u,
+                         double* g_ab) {
+  const crk_params& P = ctx->p;
+  const size_t N = (size_t)(((n + 63) / 64) * 64);
+  CRK_HIP(ensure(ctx->a_gx, 8 * 3 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gv, 8 * 3 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gu, 8 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gh, 8 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gV, 8 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gkc, 8 * 16 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_grho, 8 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_ggv, 8 * 9 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gmom, 8 * 40 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gab, 8 * 2 * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_coef, 8 * 3 * N), "adjoint workspace");
+  State<R> S = make_state<R>(ctx, n);
+  AdjState<R> G;
+  G.gx = (double*)ctx->a_gx.p;
+  G.gv = (double*)ctx->a_gv.p;
+  G.gu = (double*)ctx->a_gu.p;
+  G.gh = (double*)ctx->a_gh.p;
+  G.gV = (double*)ctx->a_gV.p;
+  G.gkc = (double*)ctx->a_gkc.p;
+  G.grho = (double*)ctx->a_grho.p;
+  G.ggv = (double*)ctx->a_ggv.p;
+  G.gmom = (double*)ctx->a_gmom.p;
+  G.gab = (double*)ctx->a_gab.p;
+  G.coef = (double*)ctx->a_coef.p;
+  G.w_a = g_accel;
+  G.w_u = g_dudt;
+  CRK_HIP(tbegin(ctx, P_BWD_FORCE, s), "event");
+  launch_bwd_force<R>(S, G, P.kernel, s);
+  CRK_HIP(tend(ctx, P_BWD_FORCE, s), "event");
+  CRK_HIP(tbegin(ctx, P_BWD_DENSITY, s), "event");
+  launch_bwd_density<R>(S, G, P.kernel, s);
+  CRK_HIP(tend(ctx, P_BWD_DENSITY, s), "event");
+  CRK_HIP(tbegin(ctx, P_BWD_CORR, s), "event");
+  launch_bwd_corr<R>(S, G, P.kernel, s);
+  CRK_HIP(tend(ctx, P_BWD_CORR, s), "event");
+  CRK_HIP(tbegin(ctx, P_BWD_MOMENTS, s), "event");
+  launch_bwd_moments<R>(S, G, P.kernel, P.h_mode, s);
+  CRK_HIP(tend(ctx, P_BWD_MOMENTS, s), "event");
+  CRK_HIP(tbegin(ctx, P_BWD_VOLUME, s), "event");
+  launch_bwd_volume<R>(S, G, P.kernel, s);
+  CRK_HIP(tend(ctx, P_BWD_VOLUME, s), "event");
+  CRK_HIP(tbegin(ctx, P_BWD_OTHER, s), "event");
+  launch_bwd_finish<R>(S, G, g_x, g_v, g_u, g_ab, s);
+  CRK_HIP(tend(ctx, P_BWD_OTHER, s), "event");
+  CRK_HIP(hipGetLastError(), "adjoint launch");
+  return CRK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -482,7 +536,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->ng, &c->ns,
                 &c->scr, &c->cand, &c->ccnt, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
-                &c->a_grho, &c->a_ggv, &c->a_gP, &c->a_gc, &c->a_gmom, &c->a_gab, &c->a_coef};
+                &c->a_grho, &c->a_ggv, &c->a_gmom, &c->a_gab, &c->a_coef};
   for (Buf* b : all) release(*b);
   if (c->host_cnt) (void)hipHostFree(c->host_cnt);
   if (c->events_ready)
@@ -544,16 +598,23 @@ crk_status crk_forward(crk_ctx* ctx, void* hip_stream, long long n, const double
 crk_status crk_backward(crk_ctx* ctx, void* hip_stream, long long n, const double* g_accel,
                         const double* g_dudt, double* g_x, double* g_v, double* g_u,
                         double* g_alpha_beta) {
-  (void)hip_stream;
-  (void)g_accel;
-  (void)g_dudt;
-  (void)g_x;
-  (void)g_v;
-  (void)g_u;
-  (void)g_alpha_beta;
   if (!ctx) return CRK_EINVAL;
-  if (n != ctx->n_last) return fail(ctx, CRK_EINVAL, "no forward with this n on the context");
-  return fail(ctx, CRK_EINVAL, "adjoint not available in this build");
+  ctx->err.clear();
+  if (n < 0 || n != ctx->n_last)
+    return fail(ctx, CRK_EINVAL, "no forward with this n on the context");
+  if (ctx->precision_last != ctx->p.precision)
+    return fail(ctx, CRK_EINVAL, "precision changed since the forward");
+  if (!g_alpha_beta) return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (n == 0) {
+    hipError_t e = hipMemsetAsync(g_alpha_beta, 0, 16, s);
+    return e == hipSuccess ? CRK_OK : hip_fail(ctx, e, "memset");
+  }
+  if (!g_accel || !g_dudt || !g_x || !g_v || !g_u)
+    return fail(ctx, CRK_EINVAL, "null array argument");
+  if (ctx->p.precision == CRK_FP64)
+    return backward_impl<double>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
+  return backward_impl<float>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
 }
 
 }  // extern "C"

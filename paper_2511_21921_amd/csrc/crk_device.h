@@ -20,9 +20,9 @@ template <> struct Sc<float> {
   __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
 };
 template <> struct Sc<double> {
-  __device__ static inline double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
-  __device__ static inline double rcp(double x) { return 1.0 / x; }
-  __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
+  __host__ __device__ static inline double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+  __host__ __device__ static inline double rcp(double x) { return 1.0 / x; }
+  __host__ __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
 };
 
 template <class R> struct Vec4;
@@ -38,7 +38,7 @@ template <int K> struct Shape;
 
 template <> struct Shape<0> {  // cubic spline (M4), radius h
   static constexpr double C = 8.0 / kPi;
-  template <class R> __device__ static inline void eval(R q, R& w, R& dw) {
+  template <class R> __host__ __device__ static inline void eval(R q, R& w, R& dw) {
     R t = R(1) - q;
     R wi = R(1) + q * q * (R(6) * q - R(6));
     R dwi = q * (R(18) * q - R(12));
@@ -54,7 +54,7 @@ template <> struct Shape<0> {  // cubic spline (M4), radius h
 
 template <> struct Shape<1> {  // Wendland C4, radius h
   static constexpr double C = 495.0 / (32.0 * kPi);
-  template <class R> __device__ static inline void eval(R q, R& w, R& dw) {
+  template <class R> __host__ __device__ static inline void eval(R q, R& w, R& dw) {
     R t = R(1) - q;
     t = t > R(0) ? t : R(0);
     R t2 = t * t;
@@ -90,7 +90,7 @@ __device__ inline void kc_load(const R* __restrict__ kc, int64_t n, int64_t i, K
 }
 
 template <class R>
-__device__ inline void kc_plain(KC<R>& k) {
+__host__ __device__ inline void kc_plain(KC<R>& k) {
   k.a = R(1);
 #pragma unroll
   for (int t = 0; t < 3; ++t) k.b[t] = k.c[t] = R(0);
@@ -100,7 +100,7 @@ __device__ inline void kc_plain(KC<R>& k) {
 
 // W^R and grad W^R for separation x, given W and grad W.
 template <class R>
-__device__ inline void kc_apply(const KC<R>& k, const R x[3], R W, const R gW[3], R& WR,
+__host__ __device__ inline void kc_apply(const KC<R>& k, const R x[3], R W, const R gW[3], R& WR,
                                 R gWR[3]) {
   R s = k.a + k.b[0] * x[0] + k.b[1] * x[1] + k.b[2] * x[2];
   WR = s * W;

@@ -55,34 +55,28 @@ struct AdjState {
   // per-particle adjoint accumulators (sorted order, FP64)
   double* gx;    // [3][n] position adjoint
   double* gv;    // [3][n] velocity adjoint
-  double* gu;    // [n]
-  double* gh;    // [n] smoothing-length adjoint
+  double* gu;    // [n] internal-energy adjoint
+  double* gh;    // [n] smoothing-length adjoint (direct terms)
   double* gV;    // [n] volume adjoint
-  double* gkc;   // [16][n] adjoint of (A, B, gradA, gradB) in that order
+  double* gkc;   // [16][n] adjoint of the packed corrections (a, b, c, M)
   double* grho;  // [n]
   double* ggv;   // [9][n] adjoint of grad v
-  double* gP;    // [n]
-  double* gc;    // [n]
-  double* gmom;  // [40][n] adjoint of the moments
+  double* gmom;  // [40][n] adjoint of the raw moment sums
   double* gab;   // [2][n] per-particle alpha, beta partials
-  double* coef;  // [4][n] per-particle helper coefficients between passes
-  const double* w_a;  // [3][n] loss weights, caller order
-  const double* w_u;  // [n]
+  double* coef;  // [3][n] Num bar, Den bar, kappa
+  const double* w_a;  // [3][n] loss weights on accel, caller order
+  const double* w_u;  // [n] loss weights on du/dt, caller order
 };
 
 template <class R>
 void launch_bwd_force(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
 template <class R>
-void launch_bwd_eos(const State<R>& S, const AdjState<R>& G, hipStream_t s);
-template <class R>
 void launch_bwd_density(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
 template <class R>
 void launch_bwd_corr(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
 template <class R>
-void launch_bwd_moments(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
-template <class R>
-void launch_bwd_volume_prep(const State<R>& S, const AdjState<R>& G, int kernel, int h_mode,
-                            hipStream_t s);
+void launch_bwd_moments(const State<R>& S, const AdjState<R>& G, int kernel, int h_mode,
+                        hipStream_t s);
 template <class R>
 void launch_bwd_volume(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
 template <class R>

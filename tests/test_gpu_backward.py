@@ -1,0 +1,184 @@
+"""GPU adjoint of the CRKSPH passes against the FP64 oracle's exact JVPs.
+
+For L = sum w_a . accel + sum w_u du/dt, the GPU gradient contracted with a
+direction d must equal the oracle's dual-number directional derivative of
+L along d (the oracle's JVP is itself pinned by central differences in
+test_oracle.py). FP64 GPU adjoint: relative error <= 1e-9. FP32 adjoint
+(FP32 pairs, FP64 accumulators and solve): the bounds written per test.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2511_21921_amd import FP32, FP64, WENDLAND_C4, Context, CRKSPHFunction, CrkError
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+from tests import _gpu  # noqa: E402
+
+
+def _grad(ps, precision, ctx=None, **kw):
+    p = _gpu.params_for(ps, precision, **kw)
+    ctx = ctx or Context(p)
+    x, v, m, u, h = _gpu.to_dev(ps, precision)
+    out = ctx.forward(x, v, m, u, h)
+    wa = torch.tensor(ps.w_a, dtype=torch.float64, device=_gpu.DEV).contiguous()
+    wu = torch.tensor(ps.w_u, dtype=torch.float64, device=_gpu.DEV).contiguous()
+    g = ctx.backward(wa, wu)
+    torch.cuda.synchronize()
+    res = {k: t.cpu().numpy() for k, t in g.items()}
+    res["L"] = float((ps.w_a * out["accel"].cpu().numpy()).sum() +
+                     (ps.w_u * out["dudt"].cpu().numpy()).sum())
+    return res, ctx
+
+
+def _directions(ps, seed=7):
+    rng = np.random.default_rng(seed)
+    z3, z1 = np.zeros_like(ps.x), np.zeros(ps.n)
+    return [("x", rng.normal(size=ps.x.shape), z3, z1, 0.0, 0.0),
+            ("v", z3, rng.normal(size=ps.x.shape), z1, 0.0, 0.0),
+            ("u", z3, z3, rng.normal(size=ps.n) * ps.u, 0.0, 0.0),
+            ("ab", z3, z3, z1, 0.7, -0.3)]
+
+
+def _check_jvps(ps, g, tol, nbr=0, **kw):
+    p = oracle.params_for(ps, **kw)
+    worst = 0.0
+    for name, dx, dv, du, da, db in _directions(ps):
+        j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, p, dx, dv, du, da, db, nbr_mode=nbr)
+        jl = float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum())
+        gl = float((g["g_x"] * dx).sum() + (g["g_v"] * dv).sum() + (g["g_u"] * du).sum() +
+                   g["g_alpha_beta"][0] * da + g["g_alpha_beta"][1] * db)
+        rel = abs(gl - jl) / max(abs(jl), 1e-300)
+        print("  dir %-2s jvp % .10e adjoint % .10e rel %.2e" % (name, jl, gl, rel), flush=True)
+        worst = max(worst, rel)
+        assert rel <= tol, (name, rel)
+    return worst
+
+
+CASES = {
+    "fixed_h": lambda: (lambda ps: (setattr(ps, "h_mode", 0), ps)[1])(synth.random_small(400, 51)),
+    "adaptive_masses": lambda: synth.random_small(600, 52, mass_spread=0.1),
+    "sedov12_v": lambda: synth.sedov(12, k=4, with_velocity=True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 2e-4)])
+def test_adjoint_matches_oracle_jvp(case, precision, tol):
+    ps = CASES[case]()
+    if ps.w_a is None:
+        rng = np.random.default_rng(3)
+        ps.w_a, ps.w_u = rng.normal(size=(3, ps.n)), rng.normal(size=ps.n)
+    print("case %s n=%d precision=%d" % (case, ps.n, precision), flush=True)
+    g, _ = _grad(ps, precision)
+    _check_jvps(ps, g, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 2e-4)])
+def test_adjoint_wendland_c4(precision, tol):
+    ps = synth.random_small(1500, 53)
+    ps.n_h = synth.n_h_for_neighbours(100)
+    print("case C4 n=%d precision=%d" % (ps.n, precision), flush=True)
+    g, _ = _grad(ps, precision, kernel=WENDLAND_C4)
+    _check_jvps(ps, g, tol, kernel=WENDLAND_C4)
+
+
+def test_adjoint_with_relaxation_fp64():
+    ps = synth.random_small(800, 54)
+    print("case relax n=%d" % ps.n, flush=True)
+    g, _ = _grad(ps, FP64, dt_relax=3.0)
+    _check_jvps(ps, g, 1e-9, dt_relax=3.0)
+
+
+def test_alpha_beta_gradient_is_exact_difference():
+    """a and du/dt are affine in (alpha, beta): dL/dalpha = L(alpha + 1) - L(alpha)."""
+    ps = synth.sedov(16, k=4, with_velocity=True)
+    g, _ = _grad(ps, FP64)
+    La, _ = _grad(ps, FP64, alpha=2.0)
+    Lb, _ = _grad(ps, FP64, beta=3.0)
+    ga, gb = g["g_alpha_beta"]
+    assert abs(ga - (La["L"] - g["L"])) <= 1e-9 * max(abs(ga), 1e-300)
+    assert abs(gb - (Lb["L"] - g["L"])) <= 1e-9 * max(abs(gb), 1e-300)
+
+
+def test_sedov64_v_fwd_bwd_fp32_vs_fp64_and_oracle():
+    """64^3 Sedov spike with velocities: FP32 vs FP64 adjoint, oracle JVP, and central FD."""
+    ps = synth.sedov64_v()
+    print("case sedov64_v n=%d" % ps.n, flush=True)
+    g64, ctx64 = _grad(ps, FP64)
+    g32, _ = _grad(ps, FP32)
+    for k in ("g_x", "g_v", "g_u"):
+        rel = _gpu.rel_l2(g32[k], g64[k])
+        print("  fp32 vs fp64 %s relL2 %.2e" % (k, rel), flush=True)
+        assert rel < 1e-4, (k, rel)
+    assert abs(g32["g_alpha_beta"] - g64["g_alpha_beta"]).max() <= \
+        1e-4 * abs(g64["g_alpha_beta"]).max()
+    # oracle JVP along one random direction in x, v and u
+    rng = np.random.default_rng(11)
+    dx, dv = rng.normal(size=ps.x.shape), rng.normal(size=ps.x.shape)
+    du = rng.normal(size=ps.n) * ps.u
+    j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), dx, dv, du, 0.0, 0.0,
+                   nbr_mode=1)
+    jl = float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum())
+    gl = float((g64["g_x"] * dx).sum() + (g64["g_v"] * dv).sum() + (g64["g_u"] * du).sum())
+    print("  oracle jvp % .10e fp64 adjoint % .10e rel %.2e" % (jl, gl, abs(gl - jl) / abs(jl)))
+    assert abs(gl - jl) <= 1e-8 * abs(jl)
+    # central finite difference of the FP64 GPU loss along the same direction
+    eps = 1e-7
+
+    def L(sign):
+        q = synth.sedov64_v()
+        q.x, q.v, q.u = ps.x + sign * eps * dx, ps.v + sign * eps * dv, ps.u + sign * eps * du
+        out, _ = _gpu.run(q, FP64, stats=False)
+        return float((ps.w_a * out["accel"]).sum() + (ps.w_u * out["dudt"]).sum())
+
+    fd = (L(1) - L(-1)) / (2 * eps)
+    print("  central FD % .10e rel %.2e" % (fd, abs(fd - gl) / abs(gl)))
+    assert abs(fd - gl) <= 1e-5 * abs(gl)
+
+
+def test_autograd_function_and_gradcheck():
+    ps = synth.random_small(200, 55)
+    p = _gpu.params_for(ps, FP64)
+    ctx = Context(p)
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    x.requires_grad_(True)
+    v.requires_grad_(True)
+    u.requires_grad_(True)
+    ab = torch.tensor([1.0, 2.0], dtype=torch.float64, requires_grad=True)
+    wa = torch.tensor(ps.w_a, device=_gpu.DEV)
+    wu = torch.tensor(ps.w_u, device=_gpu.DEV)
+
+    def f(x_, v_, u_, ab_):
+        a, du = CRKSPHFunction.apply(x_, v_, u_, ab_, m, h, ctx)[:2]
+        return (wa * a).sum() + (wu * du).sum()
+
+    loss = f(x, v, u, ab)
+    loss.backward()
+    ref, _ = _grad(ps, FP64)
+    assert np.allclose(x.grad.cpu().numpy(), ref["g_x"], rtol=1e-12, atol=0)
+    assert np.allclose(ab.grad.numpy(), ref["g_alpha_beta"], rtol=1e-12)
+    assert torch.autograd.gradcheck(f, (x, v, u, ab), eps=1e-7, atol=1e-6, rtol=1e-5,
+                                    fast_mode=True)
+
+
+def test_backward_deterministic_and_errors():
+    ps = synth.sedov(16, k=4, with_velocity=True)
+    a, ctx = _grad(ps, FP32)
+    b, _ = _grad(ps, FP32, ctx=ctx)
+    for k in ("g_x", "g_v", "g_u", "g_alpha_beta"):
+        assert np.array_equal(a[k], b[k]), k
+    wa = torch.zeros(3, 10, dtype=torch.float64, device=_gpu.DEV)
+    wu = torch.zeros(10, dtype=torch.float64, device=_gpu.DEV)
+    with pytest.raises(CrkError) as ei:
+        ctx.backward(wa, wu)       # n differs from the last forward
+    assert ei.value.status == -1
+    fresh = Context(_gpu.params_for(ps, FP32))
+    with pytest.raises(CrkError):
+        fresh.backward(wa, wu)     # no forward yet
