@@ -5,15 +5,19 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Workload: the 64^3 = 262,144-particle Sedov-like jittered lattice (periodic
 unit box, u = 1e4 on the 27 sites nearest the centre, 1e-2 elsewhere,
-adaptive h for 64 neighbours, cubic spline), inputs resident in HBM.
-One step = one pass of the whole hot path: cell list, h solve and volume,
-neighbour list, moments + FP64 corrections, density / grad v / EOS, force and
-du/dt. value = ordered force pairs (j != i, r_ij < max(h_i, h_j)) per second
-of step wall time, FP32 pairs with FP64 solve and accumulators. The same run
-reports the plain FP64 GPU form, the error of the timed outputs against the
-FP64 oracle, the roofline of the dominant kernel (from the library's HIP-event
-pass timers on the launch stream) and the oracle timed on the host cores.
-Prints exactly one JSON line on stdout.
+adaptive h for 64 neighbours, cubic spline) with N(0, 0.1) velocities and
+N(0, 1) loss weights, inputs resident in HBM. One step = one pass of the
+whole hot path: the forward (cell list, h solve and volume, neighbour list,
+moments + FP64 corrections, density / grad v / EOS, force and du/dt) and the
+adjoint of L = sum w_a . a + sum w_u du/dt (force, density, correction,
+moment and volume adjoints). value = ordered force pairs (j != i,
+r_ij < max(h_i, h_j)) per second of step wall time, FP32 pairs with FP64
+solve and accumulators. The same run reports the forward alone on the
+zero-velocity Sedov set, the plain FP64 GPU form of both, the error of the
+timed outputs against the FP64 oracle (values and one directional
+derivative), the roofline of the dominant kernel (from the library's
+HIP-event pass timers on the launch stream) and the oracle timed on the host
+cores. Prints exactly one JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -32,14 +36,14 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic flops per ordered pair of each pair pass (FMA = 2, add/mul/
 # div/sqrt/rsqrt = 1, one branch of the piecewise kernel); see the design doc.
-FLOPS_PER_PAIR = {"force": 216, "density": 94, "moments": 109}
+FLOPS_PER_PAIR = {"force": 216, "density": 94, "moments": 109, "bwd_force": 680}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(ps, precision, steps, warmup):
+def run_gpu(ps, precision, steps, warmup, backward):
     import numpy as np
     import torch
 
@@ -50,24 +54,38 @@ def run_gpu(ps, precision, steps, warmup):
     R = p.real
     t = lambda a, dt=R: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     x, v, m, u, h = t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u), t(ps.h)
+    wa = t(ps.w_a, torch.float64) if backward else None
+    wu = t(ps.w_u, torch.float64) if backward else None
     ctx.reserve(ps.n)
     out = ctx.forward(x, v, m, u, h, stats=True)   # sizes workspace and lists
     stats = out["stats"]
-    for _ in range(warmup):
+
+    def step():
         ctx.forward(x, v, m, u, h, out=out)
+        return ctx.backward(wa, wu) if backward else None
+
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     ctx.pass_times(reset=True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.forward(x, v, m, u, h, out=out)
+        g = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     passes = ctx.pass_times(reset=True)
     res = {k: val.cpu().numpy().astype(np.float64) for k, val in out.items()
            if isinstance(val, torch.Tensor)}
+    if backward:
+        res.update({k: val.cpu().numpy() for k, val in g.items()})
     ctx.close()
     ms = (t1 - t0) * 1e3 / steps
     return ms, stats, passes, res
+
+
+def pass_ms(passes, name):
+    tot, calls = passes[name]
+    return tot / calls if calls else float("nan")
 
 
 def main():
@@ -90,35 +108,39 @@ def main():
     import synth
     from paper_2511_21921_amd import FP32, FP64
 
-    ps = synth.sedov64()
+    ps = synth.sedov64_v()
+    ps0 = synth.sedov64()
     log("workload %s n=%d" % (ps.name, ps.n))
-    ms32, st32, passes32, out32 = run_gpu(ps, FP32, args.steps, args.warmup)
+    ms32, st32, passes32, out32 = run_gpu(ps, FP32, args.steps, args.warmup, True)
     pairs = st32["n_pairs_force"]
-    log("fp32: %.3f ms/step, pairs %d, passes %s" % (ms32, pairs, passes32))
+    log("fp32 fwd+bwd: %.3f ms/step, pairs %d, passes %s" % (ms32, pairs, passes32))
     value = pairs / (ms32 * 1e-3)
-
-    def pass_ms(passes, name):
-        tot, calls = passes[name]
-        return tot / calls if calls else float("nan")
-
-    f_ms = pass_ms(passes32, "force")
-    achieved = FLOPS_PER_PAIR["force"] * pairs / (f_ms * 1e-3) / 1e12
-    breakdown = {k: round(pass_ms(passes32, k), 4) for k in
-                 ("cells", "hsolve", "nlist", "moments", "density", "force")}
-    pass_tflops = {
-        "moments": FLOPS_PER_PAIR["moments"] * st32["n_pairs_gather"] /
-        (pass_ms(passes32, "moments") * 1e-3) / 1e12,
-        "density": FLOPS_PER_PAIR["density"] * st32["n_pairs_gather"] /
-        (pass_ms(passes32, "density") * 1e-3) / 1e12,
-        "force": achieved}
+    msf, stf, passesf, outf = run_gpu(ps0, FP32, args.steps, args.warmup, False)
+    log("fp32 fwd (v = 0): %.3f ms/step" % msf)
+    names = ("cells", "hsolve", "nlist", "moments", "density", "force", "bwd_force",
+             "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume", "bwd_other")
+    breakdown = {k: round(pass_ms(passes32, k), 4) for k in names}
+    dom = max(breakdown, key=lambda k: breakdown[k] if breakdown[k] == breakdown[k] else -1)
+    flops = {"force": FLOPS_PER_PAIR["force"] * pairs,
+             "bwd_force": FLOPS_PER_PAIR["bwd_force"] * pairs,
+             "moments": FLOPS_PER_PAIR["moments"] * st32["n_pairs_gather"],
+             "density": FLOPS_PER_PAIR["density"] * st32["n_pairs_gather"]}
+    pass_tflops = {k: round(f / (pass_ms(passes32, k) * 1e-3) / 1e12, 3) for k, f in flops.items()}
+    rk = dom if dom in flops else "force"
+    r_ms = pass_ms(passes32, rk)
+    achieved = flops[rk] / (r_ms * 1e-3) / 1e12
 
     fp64 = None
     if not args.no_fp64:
-        ms64, st64, passes64, _ = run_gpu(ps, FP64, max(3, args.steps // 2), 1)
-        log("fp64: %.3f ms/step" % ms64)
+        k64 = max(3, args.steps // 2)
+        ms64, st64, passes64, _ = run_gpu(ps, FP64, k64, 1, True)
+        ms64f, _, _, _ = run_gpu(ps0, FP64, k64, 1, False)
+        log("fp64: fwd+bwd %.3f ms/step, fwd %.3f ms/step" % (ms64, ms64f))
         fp64 = {"value": st64["n_pairs_force"] / (ms64 * 1e-3), "ms_per_step": round(ms64, 4),
                 "fp32_speedup": round(ms64 / ms32, 3),
-                "pass_ms": {k: round(pass_ms(passes64, k), 4) for k in breakdown}}
+                "fwd_value": stf["n_pairs_force"] / (ms64f * 1e-3),
+                "fwd_ms_per_step": round(ms64f, 4), "fwd_fp32_speedup": round(ms64f / msf, 3),
+                "pass_ms": {k: round(pass_ms(passes64, k), 4) for k in names}}
 
     cpu = None
     errs = None
@@ -130,11 +152,24 @@ def main():
         tc = time.perf_counter() - t0
         cpu = {"value": ref["pairs_force"] / tc, "unit": "interactions/s",
                "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "whole workload once (262144 particles, %d force pairs), FP64 forward "
-                         "with grid neighbour search, %.1f s" % (ref["pairs_force"], tc)}
+               "sample": "the whole workload once: FP64 forward of all 262144 particles "
+                         "(%d force pairs, grid neighbour search), %.1f s; the oracle has no "
+                         "reverse mode, so this is a forward-only rate" % (ref["pairs_force"], tc)}
+        ref0 = oracle.forward(ps0.x, ps0.v, ps0.m, ps0.u, ps0.h, oracle.params_for(ps0),
+                              nbr_mode=1)
+        rng = np.random.default_rng(11)
+        dx, dv = rng.normal(size=ps.x.shape), rng.normal(size=ps.x.shape)
+        du = rng.normal(size=ps.n) * ps.u
+        j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), dx, dv, du, 0.0,
+                       0.0, nbr_mode=1)
+        jl = float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum())
+        gl = float((out32["g_x"] * dx).sum() + (out32["g_v"] * dv).sum() +
+                   (out32["g_u"] * du).sum())
         rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
         errs = {"accel_relL2": rel(out32["accel"], ref["accel"]),
-                "dudt_abs_max": float(np.abs(out32["dudt"]).max()),
+                "dudt_relL2": rel(out32["dudt"], ref["dudt"]),
+                "grad_jvp_rel": abs(gl - jl) / abs(jl),
+                "fwd_accel_relL2": rel(outf["accel"], ref0["accel"]),
                 "h_relmax": float(np.max(np.abs(out32["h"] / ref["h"] - 1))),
                 "rho_relmax": float(np.max(np.abs(out32["rho"] / ref["rho"] - 1))),
                 "pairs_oracle": ref["pairs_force"]}
@@ -145,15 +180,19 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sedov64: 64^3=262144-particle jittered lattice, Sedov spike, "
-                               "adaptive h (64 neighbours), cubic spline, forward passes",
+        "config": {"workload": "sedov64_v: 64^3=262144-particle jittered lattice, Sedov spike, "
+                               "N(0,0.1) velocities, adaptive h (64 neighbours), cubic spline; "
+                               "forward + adjoint of sum w_a.a + sum w_u.du/dt",
                    "n": ps.n, "pairs_force": pairs, "pairs_gather": st32["n_pairs_gather"],
-                   "step": "forward"},
-        "roofline": {"bound": "alu", "kernel": "k_force", "achieved": round(achieved, 3),
+                   "step": "forward+backward"},
+        "roofline": {"bound": "alu", "kernel": "k_" + rk, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "flops_per_pair": FLOPS_PER_PAIR["force"], "kernel_ms": round(f_ms, 4)},
-        "pass_ms": breakdown, "pass_tflops": {k: round(v, 3) for k, v in pass_tflops.items()},
+                     "flops_per_pair": FLOPS_PER_PAIR[rk], "kernel_ms": round(r_ms, 4)},
+        "fwd": {"value": stf["n_pairs_force"] / (msf * 1e-3), "ms_per_step": round(msf, 4),
+                "workload": "sedov64 (same particles, zero velocity), forward only",
+                "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:6]}},
+        "pass_ms": breakdown, "pass_tflops": pass_tflops,
         "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -47,13 +47,16 @@ struct crk_ctx {
   std::string err;
   // workspace
   Buf keys_a, keys_b, vals_a, vals_b, cell_count, cell_start, sort_tmp, scan_tmp;
-  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, ng, ns, scr, cand, ccnt;
+  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, slist, ng, ns, scr_r, scr_m,
+      cand, ccnt, cell3;
   Buf cnt;
   // adjoint workspace
-  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_grho, a_ggv, a_gmom, a_gab, a_coef;
+  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
   unsigned long long* host_cnt = nullptr;
   int list_cap = 128;
+  int slist_cap = 32;
   int scr_cap = 192;
+  int equal_mass = 0;
   // state of the last forward
   long long n_last = -1;
   int G = 0;
@@ -154,6 +157,7 @@ hipError_t ensure_particles(crk_ctx* c, int64_t n) {
   ENS(ng, 4 * npad);
   ENS(ns, 4 * npad);
   ENS(ccnt, 4 * npad);
+  ENS(cell3, 4 * npad);
   ENS(cnt, 8 * CNT_COUNT);
   if (c->p.store_corrections) ENS(mom, 40 * R * npad);
 #undef ENS
@@ -171,6 +175,7 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.perm = (const uint32_t*)c->vals_a.p;
   S.keys = (const uint32_t*)c->keys_a.p;
   S.cell_start = (const uint32_t*)c->cell_start.p;
+  S.cell3 = (uint32_t*)c->cell3.p;
   S.pos4 = (R4<R>*)c->pos4.p;
   S.vel4 = (R4<R>*)c->vel4.p;
   S.mass = (R*)c->mass.p;
@@ -182,13 +187,17 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.kc4 = (R4<R>*)c->kc4.p;
   S.mom = c->p.store_corrections ? (R*)c->mom.p : nullptr;
   S.nlist = (uint32_t*)c->nlist.p;
+  S.slist = (uint32_t*)c->slist.p;
   S.ng = (int*)c->ng.p;
   S.ns = (int*)c->ns.p;
   S.list_cap = c->list_cap;
+  S.slist_cap = c->slist_cap;
   S.cand = (uint32_t*)c->cand.p;
-  S.scr = (R*)c->scr.p;
+  S.scr_r = (R*)c->scr_r.p;
+  S.scr_m = (R*)c->scr_m.p;
   S.ccnt = (int*)c->ccnt.p;
   S.scr_cap = c->scr_cap;
+  S.equal_mass = c->equal_mass;
   S.rcap = (R)c->rcap;
   S.cnt = (unsigned long long*)c->cnt.p;
   S.n_h3 = c->p.n_h * c->p.n_h * c->p.n_h;
@@ -294,6 +303,12 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   if (ctx->host_cnt[CNT_BAD_INPUT])
     return fail(ctx, CRK_EINVAL, "h, m and u must be finite and > 0");
   const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
+  {
+    // all masses equal (to rounding) => m_j / m_i = 1 needs no storage
+    const double mmax = bits_to_double(ctx->host_cnt[CNT_MMAX_BITS]);
+    const double iinv = bits_to_double(ctx->host_cnt[CNT_MINVMAX_BITS]);
+    ctx->equal_mass = std::fabs(mmax * iinv - 1.0) <= 4e-16 ? 1 : 0;
+  }
   if (!(h0max < 0.5 * P.box))
     return fail(ctx, CRK_EDOMAIN, "smoothing length must stay below half the box");
 
@@ -315,7 +330,10 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     }
     CRK_HIP(tend(ctx, P_CELLS, s), "event");
     CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
-    CRK_HIP(ensure(ctx->scr, 2 * real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+            "alloc candidates");
+    // allocated even when unused so that no code path can read past it
+    CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
             "alloc candidates");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
@@ -350,20 +368,23 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     State<R> S = make_state<R>(ctx, n);
     launch_pack<R>(S, h, V, s);
   }
-  // neighbour list, grown until it fits
+  // neighbour lists, grown until they fit
   for (int attempt = 0; attempt < 8; ++attempt) {
     CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
+    CRK_HIP(ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap), "alloc neighbour list");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8 * 2, s), "memset");
     CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
     launch_nlist<R>(S, s);
     CRK_HIP(tend(ctx, P_NLIST, s), "event");
     CRK_HIP(hipGetLastError(), "neighbour list launch");
     CRK_HIP(read_counters(ctx, s), "neighbour list");
     const unsigned long long need = ctx->host_cnt[CNT_LIST_OVERFLOW];
-    if (!need) break;
-    ctx->list_cap = (int)((need * 5 / 4 + 31) / 32 * 32);
+    const unsigned long long sneed = ctx->host_cnt[CNT_SLIST_OVERFLOW];
+    if (!need && !sneed) break;
+    if (need) ctx->list_cap = (int)((need * 5 / 4 + 31) / 32 * 32);
+    if (sneed) ctx->slist_cap = (int)((sneed * 5 / 4 + 31) / 32 * 32);
     if (attempt == 7) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
   }
   State<R> S = make_state<R>(ctx, n);
@@ -425,11 +446,12 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   CRK_HIP(ensure(ctx->a_gh, 8 * N), "adjoint workspace");
   CRK_HIP(ensure(ctx->a_gV, 8 * N), "adjoint workspace");
   CRK_HIP(ensure(ctx->a_gkc, 8 * 16 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_grho, 8 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_ggv, 8 * 9 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gmom, 8 * 40 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gab, 8 * 2 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_coef, 8 * 3 * N), "adjoint workspace");
+  const size_t RS = real_size(P.precision);
+  CRK_HIP(ensure(ctx->a_gab, 8 * 2 * (size_t)grid_for(n)), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_wgt4, 4 * RS * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_gvc4, 12 * RS * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_mom4, 40 * RS * N), "adjoint workspace");
+  CRK_HIP(ensure(ctx->a_kap, RS * N), "adjoint workspace");
   State<R> S = make_state<R>(ctx, n);
   AdjState<R> G;
   G.gx = (double*)ctx->a_gx.p;
@@ -438,13 +460,14 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   G.gh = (double*)ctx->a_gh.p;
   G.gV = (double*)ctx->a_gV.p;
   G.gkc = (double*)ctx->a_gkc.p;
-  G.grho = (double*)ctx->a_grho.p;
-  G.ggv = (double*)ctx->a_ggv.p;
-  G.gmom = (double*)ctx->a_gmom.p;
   G.gab = (double*)ctx->a_gab.p;
-  G.coef = (double*)ctx->a_coef.p;
+  G.wgt4 = (R4<R>*)ctx->a_wgt4.p;
+  G.gvc4 = (R4<R>*)ctx->a_gvc4.p;
+  G.mom4 = (R4<R>*)ctx->a_mom4.p;
+  G.kap = (R*)ctx->a_kap.p;
   G.w_a = g_accel;
   G.w_u = g_dudt;
+  launch_bwd_prep<R>(S, G, s);
   CRK_HIP(tbegin(ctx, P_BWD_FORCE, s), "event");
   launch_bwd_force<R>(S, G, P.kernel, s);
   CRK_HIP(tend(ctx, P_BWD_FORCE, s), "event");
@@ -523,8 +546,9 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
   if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
   const int64_t npad = ((n_max + 63) / 64) * 64;
   e = ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap);
+  if (e == hipSuccess) e = ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap);
   if (e == hipSuccess)
-    e = ensure(ctx->scr, 2 * real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
+    e = ensure(ctx->scr_r, real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
   if (e == hipSuccess) e = ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap);
   if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
   return CRK_OK;
@@ -534,9 +558,9 @@ crk_status crk_destroy(crk_ctx* c) {
   if (!c) return CRK_OK;
   Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_count, &c->cell_start,
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
-                &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->ng, &c->ns,
-                &c->scr, &c->cand, &c->ccnt, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
-                &c->a_grho, &c->a_ggv, &c->a_gmom, &c->a_gab, &c->a_coef};
+                &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
+                &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
+                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap};
   for (Buf* b : all) release(*b);
   if (c->host_cnt) (void)hipHostFree(c->host_cnt);
   if (c->events_ready)

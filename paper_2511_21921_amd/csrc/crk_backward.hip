@@ -65,19 +65,17 @@ __device__ inline void load_gv4(const State<R>& S, int64_t j, R gv[9], R& relaxe
   relaxed = q2.y;
 }
 
-// Loss weights in sorted order: wa [3][n], wu [n] (FP64), kept in gx/gv
-// scratch slots of the adjoint state (see launch_bwd_force).
 template <class R>
 __device__ inline void load_side(const State<R>& S, const AdjState<R>& G, int64_t j,
                                  PairSide<R>& o, R& relaxed) {
-  const int64_t n = S.n;
   const R4<R> p = S.pos4[j];
   const R4<R> v = S.vel4[j];
   const R4<R> st = S.st4[j];
+  const R4<R> w = G.wgt4[j];
   load_kc4(S, j, o.kc);
   load_gv4(S, j, o.gv, relaxed);
   o.hinv = p.w;
-  o.h = S.hbuf[j];
+  o.h = R(1) / p.w;
   o.V = v.w;
   o.rho = st.x;
   o.P = st.y;
@@ -86,80 +84,138 @@ __device__ inline void load_side(const State<R>& S, const AdjState<R>& G, int64_
   o.v[0] = v.x;
   o.v[1] = v.y;
   o.v[2] = v.z;
-  const uint32_t q = S.perm[j];
-  o.wa[0] = (R)G.w_a[q];
-  o.wa[1] = (R)G.w_a[n + q];
-  o.wa[2] = (R)G.w_a[2 * n + q];
-  o.wu = (R)G.w_u[q];
+  o.wa[0] = w.x;
+  o.wa[1] = w.y;
+  o.wa[2] = w.z;
+  o.wu = w.w;
 }
 
 template <class R>
-__device__ inline int list_slot(int t, int ng, int cap) {
-  return t < ng ? t : cap - 1 - (t - ng);
+__device__ inline void load_gvc(const AdjState<R>& G, int64_t j, R gvb[9], R& Numb, R& Denb) {
+  const R4<R> q0 = G.gvc4[3 * j], q1 = G.gvc4[3 * j + 1], q2 = G.gvc4[3 * j + 2];
+  gvb[0] = q0.x;
+  gvb[1] = q0.y;
+  gvb[2] = q0.z;
+  gvb[3] = q0.w;
+  gvb[4] = q1.x;
+  gvb[5] = q1.y;
+  gvb[6] = q1.z;
+  gvb[7] = q1.w;
+  gvb[8] = q2.x;
+  Numb = q2.y;
+  Denb = q2.z;
+}
+
+template <class R>
+__device__ inline void load_mom(const AdjState<R>& G, int64_t j, R mb[40]) {
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    const R4<R> q = G.mom4[10 * j + t];
+    mb[4 * t] = q.x;
+    mb[4 * t + 1] = q.y;
+    mb[4 * t + 2] = q.z;
+    mb[4 * t + 3] = q.w;
+  }
+}
+
+// Loss weights gathered into sorted order.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_bwd_prep(State<R> S, AdjState<R> G) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const int64_t n = S.n;
+  const uint32_t q = S.perm[s];
+  R4<R> w;
+  w.x = (R)G.w_a[q];
+  w.y = (R)G.w_a[n + q];
+  w.z = (R)G.w_a[2 * n + q];
+  w.w = (R)G.w_u[q];
+  G.wgt4[s] = w;
 }
 
 // ------------------------------------------------------------------ B1+B2 --
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (s >= S.n) return;
-  const int64_t n = S.n;
-  PairSide<R> I, J;
-  R reli, relj;
-  load_side(S, G, s, I, reli);
-  KC<R> kci = I.kc;
-  const bool relax_on = S.dt_relax > 0.0;
-  const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
-  ForceBar<double> ob;
-  ob.zero();
-  const int cap = S.list_cap;
-  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
-  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
-  const R4<R> pi = S.pos4[s];
-  for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = S.nlist[sell_index(s, cap, list_slot<R>(t, ng, cap))];
-    const uint32_t j = e >> kCodeBits;
-    load_side(S, G, j, J, relj);
-    R x[3];
-    pair_sep<R>(pi, S.pos4[j], e & kCodeMask, S.ell, x);
-    const bool plain = relax_on && (reli != R(0) || relj != R(0));
-    if (plain) {
-      kc_plain(I.kc);
-      kc_plain(J.kc);
-    } else {
-      I.kc = kci;
+  double pa = 0.0, pb = 0.0;
+  if (s < S.n) {
+    const int64_t n = S.n;
+    PairSide<R> I, J;
+    R reli, relj;
+    load_side(S, G, s, I, reli);
+    const KC<R> kci = I.kc;
+    const bool relax_on = S.dt_relax > 0.0;
+    const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
+    ForceBar<double> ob;
+    ob.zero();
+    int ng, ns;
+    nbr_counts(S, s, ng, ns);
+    const R4<R> pi = S.pos4[s];
+    for (int t = 0; t < ng + ns; ++t) {
+      const uint32_t e = nbr_entry(S, s, t, ng);
+      const uint32_t j = e >> kCodeBits;
+      load_side(S, G, j, J, relj);
+      R x[3];
+      pair_sep<R>(pi, S.pos4[j], e & kCodeMask, S.ell, x);
+      const bool plain = relax_on && (reli != R(0) || relj != R(0));
+      if (plain) {
+        kc_plain(I.kc);
+        kc_plain(J.kc);
+      } else {
+        I.kc = kci;
+      }
+      force_pair_adj<R, double, K>(I, J, x, alpha, beta, eps2, !plain, ob);
     }
-    force_pair_adj<R, double, K>(I, J, x, alpha, beta, eps2, !plain, ob);
+    // equation of state: P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u)
+    const double gam = S.gamma;
+    const double u = (double)S.uu[s];
+    const double rhob = ob.rho + ob.P * (gam - 1.0) * u;
+    const double ub = ob.P * (gam - 1.0) * (double)I.rho +
+                      ob.c * gam * (gam - 1.0) / (2.0 * (double)I.c);
+    for (int a = 0; a < 3; ++a) {
+      G.gx[a * n + s] = ob.x[a];
+      G.gv[a * n + s] = ob.v[a];
+    }
+    G.gh[s] = ob.h;
+    G.gV[s] = ob.V;
+    G.gu[s] = ub;
+    G.gkc[s] = ob.kc.a;
+    for (int t = 0; t < 3; ++t) {
+      G.gkc[(1 + t) * n + s] = ob.kc.b[t];
+      G.gkc[(4 + t) * n + s] = ob.kc.c[t];
+    }
+    for (int t = 0; t < 9; ++t) G.gkc[(7 + t) * n + s] = ob.kc.M[t];
+    // density adjoint coefficients: rho = Num / Den
+    const double den = (double)S.st4[s].w;
+    R4<R> q0, q1, q2;
+    q0.x = (R)ob.gv[0]; q0.y = (R)ob.gv[1]; q0.z = (R)ob.gv[2]; q0.w = (R)ob.gv[3];
+    q1.x = (R)ob.gv[4]; q1.y = (R)ob.gv[5]; q1.z = (R)ob.gv[6]; q1.w = (R)ob.gv[7];
+    q2.x = (R)ob.gv[8];
+    q2.y = (R)(rhob / den);                       // Num bar
+    q2.z = (R)(-rhob * (double)I.rho / den);      // Den bar
+    q2.w = R(0);
+    G.gvc4[3 * s] = q0;
+    G.gvc4[3 * s + 1] = q1;
+    G.gvc4[3 * s + 2] = q2;
+    pa = ob.alpha;
+    pb = ob.beta;
   }
-  // equation of state: P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u)
-  const double gam = S.gamma;
-  const double u = (double)S.uu[s];
-  const double rhob = ob.rho + ob.P * (gam - 1.0) * u;
-  const double ub = ob.P * (gam - 1.0) * (double)I.rho +
-                    ob.c * gam * (gam - 1.0) / (2.0 * (double)I.c);
-  for (int a = 0; a < 3; ++a) {
-    G.gx[a * n + s] = ob.x[a];
-    G.gv[a * n + s] = ob.v[a];
+  // per-block alpha, beta partial sums (fixed tree: deterministic)
+  __shared__ double sa[kBlock], sb[kBlock];
+  sa[threadIdx.x] = pa;
+  sb[threadIdx.x] = pb;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
   }
-  G.gh[s] = ob.h;
-  G.gV[s] = ob.V;
-  G.gu[s] = ub;
-  G.grho[s] = rhob;
-  G.gkc[s] = ob.kc.a;
-  for (int t = 0; t < 3; ++t) {
-    G.gkc[(1 + t) * n + s] = ob.kc.b[t];
-    G.gkc[(4 + t) * n + s] = ob.kc.c[t];
+  if (threadIdx.x == 0) {
+    G.gab[2 * blockIdx.x] = sa[0];
+    G.gab[2 * blockIdx.x + 1] = sb[0];
   }
-  for (int t = 0; t < 9; ++t) {
-    G.gkc[(7 + t) * n + s] = ob.kc.M[t];
-    G.ggv[t * n + s] = ob.gv[t];
-  }
-  G.gab[s] = ob.alpha;
-  G.gab[n + s] = ob.beta;
-  // density adjoint coefficients: rho = Num / Den
-  const double den = (double)S.st4[s].w;
-  G.coef[s] = rhob / den;                      // Num bar
-  G.coef[n + s] = -rhob * (double)I.rho / den;  // Den bar
 }
 
 // --------------------------------------------------------------------- B3 --
@@ -173,20 +229,18 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   const R mi = S.mass[s];
   KC<R> ki;
   load_kc4(S, s, ki);
-  const R Numb = (R)G.coef[s], Denb = (R)G.coef[n + s];
-  R gvb[9];
-  for (int t = 0; t < 9; ++t) gvb[t] = (R)G.ggv[t * n + s];
+  R gvb[9], Numb, Denb;
+  load_gvc(G, s, gvb, Numb, Denb);
   KCBar<double> kb;
   kb.zero();
   double xb[3] = {0, 0, 0}, vb[3] = {0, 0, 0}, hb = 0, Vb = 0;
   R W0, dW0;
   kernel_self<R, K>(pi.w, W0, dW0);
   density_self_adj<R, double>(ki.a, mi, vi.w, W0, dW0, Numb, Denb, &kb, Vb, hb);
-  const int cap = S.list_cap;
-  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
-  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
+  int ng, ns;
+  nbr_counts(S, s, ng, ns);
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = S.nlist[sell_index(s, cap, list_slot<R>(t, ng, cap))];
+    const uint32_t e = nbr_entry(S, s, t, ng);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
@@ -205,12 +259,12 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
     if (r2 * (pj.w * pj.w) < R(1)) {
       KC<R> kj;
       load_kc4(S, j, kj);
-      R gvbj[9];
-      for (int q = 0; q < 9; ++q) gvbj[q] = (R)G.ggv[q * n + j];
+      R gvbj[9], Numbj, Denbj;
+      load_gvc(G, j, gvbj, Numbj, Denbj);
       KEval<R> ej;
       kernel_eval<R, K>(r, rinv, pj.w, ej);
-      density_rev_adj<R, double>(kj, x, r, rinv, ej, mi, vi.w, vij, (R)G.coef[j],
-                                 (R)G.coef[n + j], gvbj, xb, Vb, vb);
+      density_rev_adj<R, double>(kj, x, r, rinv, ej, mi, vi.w, vij, Numbj, Denbj, gvbj, xb, Vb,
+                                 vb);
     }
   }
   for (int a = 0; a < 3; ++a) {
@@ -240,7 +294,7 @@ __device__ inline void moments_raw(const State<R>& S, int64_t s, double raw[40])
   acc[0] = S.vel4[s].w * W0;
   const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
+    const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
     const uint32_t j = e >> kCodeBits;
     const R Vj = S.vel4[j].w;
     R x[3];
@@ -281,7 +335,15 @@ __global__ void __launch_bounds__(kBlock) k_bwd_corr(State<R> S, AdjState<R> G) 
   for (int t = 0; t < 16; ++t) kcb[t] = G.gkc[t * n + s];
   double out[40];
   corr_solve_adj(raw, kcb, out);
-  for (int t = 0; t < 40; ++t) G.gmom[t * n + s] = out[t];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    R4<R> q;
+    q.x = (R)out[4 * t];
+    q.y = (R)out[4 * t + 1];
+    q.z = (R)out[4 * t + 2];
+    q.w = (R)out[4 * t + 3];
+    G.mom4[10 * s + t] = q;
+  }
 }
 
 // ------------------------------------------------------------------ B5+B6 --
@@ -294,17 +356,16 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   const R Vi = S.vel4[s].w;
   const R mi = S.mass[s];
   R mb[40];
-  for (int t = 0; t < 40; ++t) mb[t] = (R)G.gmom[t * n + s];
+  load_mom(G, s, mb);
   R W0, dW0;
   kernel_self<R, K>(pi.w, W0, dW0);
   double Vb = (double)(mb[0] * W0), hb = (double)(mb[0] * Vi * dW0);
   double sh = (double)(mi * dW0);
   double xb[3] = {0, 0, 0};
-  const int cap = S.list_cap;
-  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
-  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
+  int ng, ns;
+  nbr_counts(S, s, ng, ns);
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = S.nlist[sell_index(s, cap, list_slot<R>(t, ng, cap))];
+    const uint32_t e = nbr_entry(S, s, t, ng);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
@@ -324,7 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
     }
     if (r2 * (pj.w * pj.w) < R(1)) {
       R mbj[40];
-      for (int q = 0; q < 40; ++q) mbj[q] = (R)G.gmom[q * n + j];
+      load_mom(G, j, mbj);
       KEval<R> ej;
       kernel_eval<R, K>(r, rinv, pj.w, ej);
       const R xm[3] = {-x[0], -x[1], -x[2]};
@@ -348,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
     const double dFdh = 3.0 * h * h * Ssum / m + h * h * h * sh / m;
     kappa += -htot * (h * h * h / m) / dFdh;
   }
-  G.coef[2 * n + s] = kappa;
+  G.kap[s] = (R)kappa;
 }
 
 // --------------------------------------------------------------------- B7 --
@@ -359,13 +420,12 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
   const int64_t n = S.n;
   const R4<R> pi = S.pos4[s];
   const R mi = S.mass[s];
-  const R ki = (R)G.coef[2 * n + s];
+  const R ki = G.kap[s];
   double xb[3] = {0, 0, 0};
-  const int cap = S.list_cap;
-  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
-  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
+  int ng, ns;
+  nbr_counts(S, s, ng, ns);
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = S.nlist[sell_index(s, cap, list_slot<R>(t, ng, cap))];
+    const uint32_t e = nbr_entry(S, s, t, ng);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
@@ -382,7 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
     if (r2 * (pj.w * pj.w) < R(1)) {
       KEval<R> ej;
       kernel_eval<R, K>(r, rinv, pj.w, ej);
-      c += (R)G.coef[2 * n + j] * mi * ej.f;
+      c += G.kap[j] * mi * ej.f;
     }
     for (int a = 0; a < 3; ++a) xb[a] += (double)(c * x[a]);
   }
@@ -406,15 +466,15 @@ __global__ void __launch_bounds__(kBlock) k_bwd_unpermute(State<R> S, AdjState<R
   g_u[p] = G.gu[s];
 }
 
-// Deterministic sum of the per-particle alpha, beta partials: one block,
+// Deterministic sum of the per-block alpha, beta partials: one block,
 // fixed strided order, fixed tree.
-__global__ void __launch_bounds__(kBlock) k_bwd_reduce_ab(const double* __restrict__ gab,
-                                                          int64_t n, double* __restrict__ out) {
+__global__ void __launch_bounds__(kBlock) k_bwd_reduce_ab(const double* __restrict__ part,
+                                                          int64_t nb, double* __restrict__ out) {
   __shared__ double sa[kBlock], sb[kBlock];
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
-    a += gab[i];
-    b += gab[n + i];
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
@@ -443,6 +503,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_reduce_ab(const double* __restri
   } while (0)
 
 template <class R>
+void launch_bwd_prep(const State<R>& S, const AdjState<R>& G, hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_prep<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, G);
+}
+template <class R>
 void launch_bwd_force(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s) {
   CRK_DISPATCH_KB(kernel, k_bwd_force, S, G);
 }
@@ -468,11 +532,12 @@ void launch_bwd_finish(const State<R>& S, const AdjState<R>& G, double* g_x, dou
                        double* g_u, double* g_ab, hipStream_t s) {
   hipLaunchKernelGGL(k_bwd_unpermute<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, G, g_x, g_v,
                      g_u);
-  hipLaunchKernelGGL(k_bwd_reduce_ab, dim3(1), dim3(kBlock), 0, s, (const double*)G.gab, S.n,
-                     g_ab);
+  hipLaunchKernelGGL(k_bwd_reduce_ab, dim3(1), dim3(kBlock), 0, s, (const double*)G.gab,
+                     (int64_t)grid_for(S.n), g_ab);
 }
 
 #define CRK_INSTANTIATE_BWD(R)                                                                 \
+  template void launch_bwd_prep<R>(const State<R>&, const AdjState<R>&, hipStream_t);          \
   template void launch_bwd_force<R>(const State<R>&, const AdjState<R>&, int, hipStream_t);    \
   template void launch_bwd_density<R>(const State<R>&, const AdjState<R>&, int, hipStream_t);  \
   template void launch_bwd_corr<R>(const State<R>&, const AdjState<R>&, int, hipStream_t);     \

@@ -138,10 +138,42 @@ __device__ inline void pair_sep(const R4<R>& pi, const R4<R>& pj, uint32_t code,
   x[2] = (pi.z - pj.z) - R(dz) * ell;
 }
 
-// SELL layout with slices of 64 particles: entry k of sorted particle i
-// lives at ((i / 64) * cap + k) * 64 + (i % 64).
-__device__ inline int64_t sell_index(int64_t i, int cap, int k) {
-  return ((i >> 6) * (int64_t)cap + k) * 64 + (i & 63);
+// Per-particle lists (candidates, neighbours) use a chunked SELL layout:
+// particles in slices of 64 (one wave), entries in chunks of 4. Chunk c of
+// particle i starts at word (((i / 64) * cap / 4 + c) * 64 + i % 64) * 4, so
+// a wave reading entry k of all its lanes touches one contiguous 1 KiB row,
+// and a lane writes its entries four at a time as one 16-byte store.
+// cap is a multiple of 4.
+__device__ inline int64_t list_index(int64_t i, int cap, int k) {
+  return ((((i >> 6) * (int64_t)(cap >> 2) + (k >> 2)) * 64 + (i & 63)) << 2) + (k & 3);
 }
+
+// Register staging of one lane's appends: four values are collected and
+// written with one 16-byte store (the whole chunk, including unused tail
+// slots at the final flush; only the counted entries are ever read).
+template <class T> struct Vec4T;
+template <> struct Vec4T<uint32_t> { using V = uint4; };
+template <> struct Vec4T<float> { using V = float4; };
+template <> struct Vec4T<double> { using V = double4; };
+
+template <class T>
+struct Stage4 {
+  T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+  __device__ inline void put(int slot, T v) {
+    v0 = slot == 0 ? v : v0;
+    v1 = slot == 1 ? v : v1;
+    v2 = slot == 2 ? v : v2;
+    v3 = slot == 3 ? v : v3;
+  }
+  // writes the chunk that holds entry k (k % 4 == 3 for a full chunk)
+  __device__ inline void flush(T* base, int64_t i, int cap, int k) const {
+    typename Vec4T<T>::V q;
+    q.x = v0;
+    q.y = v1;
+    q.z = v2;
+    q.w = v3;
+    *reinterpret_cast<typename Vec4T<T>::V*>(base + list_index(i, cap, k & ~3)) = q;
+  }
+};
 
 }  // namespace crk

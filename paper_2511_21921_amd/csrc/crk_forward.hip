@@ -55,16 +55,20 @@ __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h
                                                          const R* __restrict__ u, int64_t n,
                                                          unsigned long long* cnt) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  unsigned long long hb = 0, bad = 0;
+  unsigned long long hb = 0, bad = 0, mb = 0, ib = 0;
   if (i < n) {
-    const double hv = (double)h[i];
-    const bool ok = hv > 0.0 && (double)m[i] > 0.0 && (double)u[i] > 0.0 &&
-                    hv < 1e300 && (double)u[i] < 1e300;
+    const double hv = (double)h[i], mv = (double)m[i];
+    const bool ok = hv > 0.0 && mv > 0.0 && (double)u[i] > 0.0 && hv < 1e300 &&
+                    (double)u[i] < 1e300 && mv < 1e300;
     bad = ok ? 0 : 1;
     hb = ok ? dbits(hv) : 0;
+    mb = ok ? dbits(mv) : 0;
+    ib = ok ? dbits(1.0 / mv) : 0;
   }
   wave_max_u64(&cnt[CNT_HMAX_BITS], hb);
   wave_add_u64(&cnt[CNT_BAD_INPUT], bad);
+  wave_max_u64(&cnt[CNT_MMAX_BITS], mb);
+  wave_max_u64(&cnt[CNT_MINVMAX_BITS], ib);
 }
 
 __device__ inline double wrap_pos(double xa, double L) {
@@ -128,6 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   S.mass[s] = m[p];
   S.uu[s] = u[p];
   S.hbuf[s] = h[p];
+  S.cell3[s] = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20);
 }
 
 // ---------------------------------------------------------- candidates ----
@@ -139,32 +144,51 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  unsigned long long ovf = 0;
-  if (s < S.n) {
-    const R4<R> pi = S.pos4[s];
-    const R mi_inv = R(1) / S.mass[s];
-    const R rc2 = S.rcap * S.rcap;
-    int cnt = 0;
-    for_each_candidate(S, S.keys[s], [&](uint32_t j, uint32_t code) {
-      if (j == (uint32_t)s && code == (uint32_t)kSelfCode) return;
-      const R4<R> pj = S.pos4[j];
-      R x[3];
-      pair_sep<R>(pi, pj, code, S.ell, x);
-      const R r2 = dot3(x, x);
-      if (r2 < rc2) {
-        if (cnt < S.scr_cap) {
-          const int64_t e = sell_index(s, S.scr_cap, cnt);
-          S.cand[e] = (j << kCodeBits) | code;
-          S.scr[2 * e] = Sc<R>::sqrt(r2);
-          S.scr[2 * e + 1] = S.mass[j] * mi_inv;
+  const bool active = s < S.n;
+  const int64_t sc = active ? s : 0;
+  const R4<R> pi = S.pos4[sc];
+  const R mi_inv = R(1) / S.mass[sc];
+  const R rc2 = S.rcap * S.rcap;
+  const int cap = S.scr_cap;
+  int cnt = 0;
+  Stage4<uint32_t> se;
+  Stage4<R> sr, sm;
+  wave_traverse(S, active, S.cell3[sc],
+                [&](uint32_t j, const R4<R>& pj, R mj, int dx, int dy, int dz, bool mine) {
+    if (!mine || dx < -1 || dx > 1) return;
+    if (j == (uint32_t)s && dx == 0 && dy == 0 && dz == 0) return;
+    R x[3];
+    x[0] = (pi.x - pj.x) - R(dx) * S.ell;
+    x[1] = (pi.y - pj.y) - R(dy) * S.ell;
+    x[2] = (pi.z - pj.z) - R(dz) * S.ell;
+    const R r2 = dot3(x, x);
+    if (r2 < rc2) {
+      if (cnt < cap) {
+        const int slot = cnt & 3;
+        se.put(slot, (j << kCodeBits) | (uint32_t)(9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)));
+        sr.put(slot, Sc<R>::sqrt(r2));
+        sm.put(slot, mj * mi_inv);
+        if (slot == 3) {
+          se.flush(S.cand, s, cap, cnt);
+          sr.flush(S.scr_r, s, cap, cnt);
+          if (!S.equal_mass) sm.flush(S.scr_m, s, cap, cnt);
         }
-        ++cnt;
       }
-    });
+      ++cnt;
+    }
+  });
+  unsigned long long ovf = 0;
+  if (active) {
+    const int stored = cnt < cap ? cnt : cap;
+    if (stored & 3) {
+      se.flush(S.cand, s, cap, stored - 1);
+      sr.flush(S.scr_r, s, cap, stored - 1);
+      if (!S.equal_mass) sm.flush(S.scr_m, s, cap, stored - 1);
+    }
     // only the stored entries are ever read; the overflow makes the host
     // grow the capacity and run the candidate pass again
-    S.ccnt[s] = cnt < S.scr_cap ? cnt : S.scr_cap;
-    if (cnt > S.scr_cap) ovf = (unsigned long long)cnt;
+    S.ccnt[s] = stored;
+    if (cnt > cap) ovf = (unsigned long long)cnt;
   }
   wave_max_u64(&S.cnt[CNT_SCR_OVERFLOW], ovf);
 }
@@ -177,9 +201,9 @@ __device__ inline R candidate_sum(const State<R>& S, int64_t s, int cnt, R h, R&
   const R hinv = R(1) / h;
   R sum = R(Shape<K>::w0), ds = R(0);
   for (int k = 0; k < cnt; ++k) {
-    const int64_t e = sell_index(s, S.scr_cap, k);
-    const R q = S.scr[2 * e] * hinv;
-    const R mr = S.scr[2 * e + 1];
+    const int64_t e = list_index(s, S.scr_cap, k);
+    const R q = S.scr_r[e] * hinv;
+    const R mr = S.equal_mass ? R(1) : S.scr_m[e];
     R w, dw;
     Shape<K>::eval(q, w, dw);
     sum += mr * w;
@@ -279,37 +303,49 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  unsigned long long g = 0, f = 0, ovf = 0;
+  unsigned long long g = 0, f = 0, ovf = 0, sovf = 0;
   if (s < S.n) {
     const R4<R> pi = S.pos4[s];
     const R hi2 = pi.w * pi.w;  // 1/h_i^2
     int ng = 0, ns = 0;
-    const int cap = S.list_cap;
+    const int cap = S.list_cap, scap = S.slist_cap;
+    Stage4<uint32_t> sg, ss;
     const int cc = S.ccnt[s] < S.scr_cap ? S.ccnt[s] : S.scr_cap;
     for (int k = 0; k < cc; ++k) {
-      const uint32_t e = S.cand[sell_index(s, S.scr_cap, k)];
+      const uint32_t e = S.cand[list_index(s, S.scr_cap, k)];
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       R x[3];
       pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
       const R r2 = dot3(x, x);
       if (r2 * hi2 < R(1)) {
-        if (ng + ns < cap) S.nlist[sell_index(s, cap, ng)] = e;
+        if (ng < cap) {
+          sg.put(ng & 3, e);
+          if ((ng & 3) == 3) sg.flush(S.nlist, s, cap, ng);
+        }
         ++ng;
       } else if (r2 * (pj.w * pj.w) < R(1)) {
-        if (ng + ns < cap) S.nlist[sell_index(s, cap, cap - 1 - ns)] = e;
+        if (ns < scap) {
+          ss.put(ns & 3, e);
+          if ((ns & 3) == 3) ss.flush(S.slist, s, scap, ns);
+        }
         ++ns;
       }
     }
+    const int gst = ng < cap ? ng : cap, sst = ns < scap ? ns : scap;
+    if (gst & 3) sg.flush(S.nlist, s, cap, gst - 1);
+    if (sst & 3) ss.flush(S.slist, s, scap, sst - 1);
     S.ng[s] = ng;
     S.ns[s] = ns;
     g = (unsigned long long)ng;
     f = (unsigned long long)(ng + ns);
-    if (ng + ns > cap) ovf = (unsigned long long)(ng + ns);
+    if (ng > cap) ovf = (unsigned long long)ng;
+    if (ns > scap) sovf = (unsigned long long)ns;
   }
   wave_add_u64(&S.cnt[CNT_PAIRS_GATHER], g);
   wave_add_u64(&S.cnt[CNT_PAIRS_FORCE], f);
   wave_max_u64(&S.cnt[CNT_LIST_OVERFLOW], ovf);
+  wave_max_u64(&S.cnt[CNT_SLIST_OVERFLOW], sovf);
 }
 
 // ------------------------------------------------ moments + corrections ----
@@ -349,7 +385,7 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
   for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
   const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
+    const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R Vj = S.vel4[j].w;
@@ -596,7 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
     for (int t = 0; t < 9; ++t) gv[t] = R(0);
     const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
     for (int k = 0; k < ng; ++k) {
-      const uint32_t e = S.nlist[sell_index(s, S.list_cap, k)];
+      const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       const R4<R> vj = S.vel4[j];
@@ -696,13 +732,11 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
   const R hi = R(1) / pi.w;
   double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
-  const int cap = S.list_cap;
-  const int ng = S.ng[s] < cap ? S.ng[s] : cap;
-  const int ns = S.ns[s] < cap - ng ? S.ns[s] : cap - ng;
+  int ng, ns;
+  nbr_counts(S, s, ng, ns);
   const int total = ng + ns;
   for (int t = 0; t < total; ++t) {
-    const int slot = t < ng ? t : cap - 1 - (t - ng);
-    const uint32_t e = S.nlist[sell_index(s, cap, slot)];
+    const uint32_t e = nbr_entry(S, s, t, ng);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];

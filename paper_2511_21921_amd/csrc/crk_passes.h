@@ -59,15 +59,18 @@ struct AdjState {
   double* gh;    // [n] smoothing-length adjoint (direct terms)
   double* gV;    // [n] volume adjoint
   double* gkc;   // [16][n] adjoint of the packed corrections (a, b, c, M)
-  double* grho;  // [n]
-  double* ggv;   // [9][n] adjoint of grad v
-  double* gmom;  // [40][n] adjoint of the raw moment sums
-  double* gab;   // [2][n] per-particle alpha, beta partials
-  double* coef;  // [3][n] Num bar, Den bar, kappa
+  double* gab;   // [2][blocks] per-block alpha, beta partial sums
+  // records gathered from neighbours, packed per particle in Real:
+  R4<R>* wgt4;   // (w_a x, y, z, w_u) loss weights in sorted order
+  R4<R>* gvc4;   // 3 per particle: grad v adjoint (9), Num bar, Den bar, 0
+  R4<R>* mom4;   // 10 per particle: adjoint of the 40 raw moment sums
+  R* kap;        // [n] volume / smoothing-length coefficient kappa
   const double* w_a;  // [3][n] loss weights on accel, caller order
   const double* w_u;  // [n] loss weights on du/dt, caller order
 };
 
+template <class R>
+void launch_bwd_prep(const State<R>& S, const AdjState<R>& G, hipStream_t s);
 template <class R>
 void launch_bwd_force(const State<R>& S, const AdjState<R>& G, int kernel, hipStream_t s);
 template <class R>

@@ -16,7 +16,10 @@ enum Counter {
   CNT_H_UNCONV,
   CNT_H_CAPPED,
   CNT_SCR_OVERFLOW,    // largest candidate count beyond the candidate capacity
-  CNT_LIST_OVERFLOW,   // largest neighbour count beyond the list capacity
+  CNT_LIST_OVERFLOW,   // largest gather count beyond the list capacity
+  CNT_SLIST_OVERFLOW,  // largest scatter-only count beyond its capacity
+  CNT_MMAX_BITS,       // max mass as double bits
+  CNT_MINVMAX_BITS,    // max 1/mass as double bits
   CNT_SINGULAR,
   CNT_RELAXED,
   CNT_NONFINITE,
@@ -34,6 +37,7 @@ struct State {
   const uint32_t* perm;        // sorted -> caller index
   const uint32_t* keys;        // sorted cell keys
   const uint32_t* cell_start;  // [G^3 + 1]
+  uint32_t* cell3;             // packed cell coordinates x | y << 10 | z << 20
   // sorted particle data
   R4<R>* pos4;  // (xi_x, xi_y, xi_z, 1/h)
   R4<R>* vel4;  // (v_x, v_y, v_z, V)
@@ -45,17 +49,22 @@ struct State {
   R4<R>* gv4;   // 3 per particle: grad v rows, then (gv_22, relaxed, 0, 0)
   R4<R>* kc4;   // 4 per particle: packed corrected-kernel coefficients
   R* mom;       // [40][n] moments kept for the adjoint (may be null)
-  // neighbour list (SELL, slices of 64)
+  // neighbour lists (chunked SELL): gather entries (r < h_i) and
+  // scatter-only entries (h_i <= r < h_j)
   uint32_t* nlist;
-  int* ng;      // gather entries (r < h_i), stored from slot 0 upwards
-  int* ns;      // scatter-only entries (h_i <= r < h_j), from slot cap-1 down
+  uint32_t* slist;
+  int* ng;
+  int* ns;
   int list_cap;
-  // candidates within rcap of each particle (SELL, slices of 64):
-  // packed entries as in the neighbour list, and (r, m_j/m_i) pairs
+  int slist_cap;
+  // candidates within rcap of each particle (chunked SELL): packed entries,
+  // r, and m_j/m_i (the last only when the masses differ)
   uint32_t* cand;
-  R* scr;
+  R* scr_r;
+  R* scr_m;
   int* ccnt;
   int scr_cap;
+  int equal_mass;
   R rcap;
   unsigned long long* cnt;
   // parameters
@@ -94,6 +103,112 @@ __device__ inline void for_each_candidate(const State<R>& S, uint32_t key, F&& f
       }
     }
   }
+}
+
+// Wave broadcast of lane k's value (k wave-uniform).
+__device__ inline float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ inline double bcast(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+
+// Wave-cooperative traversal. The lanes of a wave hold consecutive sorted
+// particles, so they sit in a few neighbouring cells of one or two cell
+// rows. For each row group the wave walks the union of the lanes' 3x3x3
+// stencils: for each (dz, dy) the cells x = lo-1 .. hi+1 of a row are
+// contiguous in the cell order, so they form one particle range (plus one
+// cell more on each side where the row wraps periodically). Each range is
+// read in coalesced 64-wide tiles (one candidate per lane) and every
+// candidate is broadcast to the wave with readlane. f(j, pj, mj, dx, dy, dz,
+// mine) receives the candidate's record and mass, the lane's own cell
+// offset to it (dx may leave [-1, 1]: such candidates are more than a cell
+// side away and the caller drops them) and whether the lane belongs to the
+// current row group.
+template <class R, class F>
+__device__ inline void wave_traverse(const State<R>& S, bool active, uint32_t c3, F&& f) {
+  const int G = S.G;
+  const int lane = threadIdx.x & 63;
+  const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
+  const int row = active ? cz * G + cy : -1;
+  uint64_t remaining = __ballot(active);
+  while (remaining) {
+    const int leader = __ffsll((unsigned long long)remaining) - 1;
+    const int grow = __builtin_amdgcn_readfirstlane(__shfl(row, leader, 64));
+    const bool mine = active && row == grow && ((remaining >> lane) & 1ull);
+    remaining &= ~__ballot(mine);
+    int lo = mine ? cx : G, hi = mine ? cx : -1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    const int gy = grow % G, gz = grow / G;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int z = wrap_cell(gz + dz, G);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int y = wrap_cell(gy + dy, G);
+        const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
+        for (int seg = 0; seg < 3; ++seg) {
+          int xa, xb, shift;
+          if (seg == 0) {
+            xa = lo - 1 > 0 ? lo - 1 : 0;
+            xb = hi + 1 < G - 1 ? hi + 1 : G - 1;
+            shift = 0;
+          } else if (seg == 1) {
+            if (lo - 1 >= 0) continue;
+            xa = xb = G - 1;
+            shift = -G;
+          } else {
+            if (hi + 1 <= G - 1) continue;
+            xa = xb = 0;
+            shift = G;
+          }
+          const uint32_t b = S.cell_start[rowbase + (uint32_t)xa];
+          uint32_t e = S.cell_start[rowbase + (uint32_t)xb + 1];
+          if (e > (uint32_t)S.n) e = (uint32_t)S.n;
+          for (uint32_t t0 = b; t0 < e; t0 += 64) {
+            const uint32_t jl = t0 + (uint32_t)lane;
+            const bool ok = jl < e;
+            const uint32_t jc = ok ? jl : b;
+            const R4<R> pl = S.pos4[jc];
+            const R ml = S.mass[jc];
+            const int xl = (int)(S.cell3[jc] & 1023u) + shift;
+            const int cnt = (int)(e - t0 < 64u ? e - t0 : 64u);
+            for (int k = 0; k < cnt; ++k) {
+              R4<R> pj;
+              pj.x = bcast(pl.x, k);
+              pj.y = bcast(pl.y, k);
+              pj.z = bcast(pl.z, k);
+              pj.w = bcast(pl.w, k);
+              const R mj = bcast(ml, k);
+              const int dx = bcast(xl, k) - cx;
+              f(t0 + (uint32_t)k, pj, mj, dx, dy, dz, mine);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Entry t of particle s's symmetric neighbour list: gather part first.
+template <class R>
+__device__ inline uint32_t nbr_entry(const State<R>& S, int64_t s, int t, int ng) {
+  return t < ng ? S.nlist[list_index(s, S.list_cap, t)]
+                : S.slist[list_index(s, S.slist_cap, t - ng)];
+}
+
+template <class R>
+__device__ inline void nbr_counts(const State<R>& S, int64_t s, int& ng, int& ns) {
+  ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
+  ns = S.ns[s] < S.slist_cap ? S.ns[s] : S.slist_cap;
 }
 
 }  // namespace crk
