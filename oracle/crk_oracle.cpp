@@ -30,6 +30,13 @@
 // Kernels have compact support of radius h (App. A.2 and its footnote): the
 // cubic spline (M4) and the Wendland C4 kernel.
 //
+// Parity unpinned: the paper cites, but does not print, the exact form of
+// the viscosity limiter and of the compatible-energy work split. The forms
+// used here (step 7) are readings; the tests pin their invariants (exact
+// momentum and energy conservation, Q = 0 for exactly linear flow, affinity
+// in alpha and beta, the textbook SPH limit with A = 1, B = 0), not the forms
+// themselves.
+//
 // Neighbour search is either an O(N^2) minimum-image brute force or a simple
 // uniform grid written here and checked against the brute force.
 //
