@@ -90,6 +90,10 @@ typedef struct {
   int store_corrections; /* 1: keep moments for the adjoint; 0: recompute them */
   int check_finite;  /* 1: count non-finite outputs and fail with CRK_ENONFINITE */
   int timing;        /* 1: time every pass with HIP events (see crk_pass_times) */
+  int search;        /* neighbour search: 0 automatic, 1 periodic cell list sized to the
+                        largest h, 2 tree of Morton-ordered 64-particle leaves (for smoothing
+                        lengths spanning orders of magnitude); automatic uses the cell list
+                        unless its candidate lists would exceed 1024 entries per particle */
 } crk_params;
 
 typedef struct {

@@ -33,7 +33,8 @@ class crk_params(C.Structure):
                 ("beta", C.c_double), ("eps2", C.c_double), ("n_h", C.c_double),
                 ("kernel", C.c_int), ("precision", C.c_int), ("h_mode", C.c_int),
                 ("h_max_iter", C.c_int), ("h_rtol", C.c_double), ("dt_relax", C.c_double),
-                ("store_corrections", C.c_int), ("check_finite", C.c_int), ("timing", C.c_int)]
+                ("store_corrections", C.c_int), ("check_finite", C.c_int), ("timing", C.c_int),
+                ("search", C.c_int)]
 
 
 class crk_stats(C.Structure):
@@ -104,6 +105,7 @@ class Params:
     store_corrections: int = 0
     check_finite: int = 0
     timing: int = 0
+    search: int = 0                  # 0 automatic, 1 cell list, 2 tree
 
     def to_c(self) -> crk_params:
         p = crk_params()

@@ -50,6 +50,12 @@ struct crk_ctx {
   Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, slist, ng, ns, scr_r, scr_m,
       cand, ccnt, cell3;
   Buf cnt;
+  // tree path
+  Buf rad, todo, tslot, nlo, nhi, lvl, wrow, lrow;
+  uint32_t host_rows[2] = {};
+  int lvl_off[40] = {}, lvl_cnt[40] = {};
+  int nlevels = 0;
+  int lattice = 0;
   // adjoint workspace
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
   unsigned long long* host_cnt = nullptr;
@@ -121,6 +127,7 @@ crk_status check_params(crk_ctx* ctx, const crk_params* p) {
     return fail(ctx, CRK_EINVAL, "unknown precision");
   if (p->h_mode != 0 && p->h_mode != 1) return fail(ctx, CRK_EINVAL, "h_mode must be 0 or 1");
   if (p->h_max_iter < 1) return fail(ctx, CRK_EINVAL, "h_max_iter must be >= 1");
+  if (p->search < 0 || p->search > 2) return fail(ctx, CRK_EINVAL, "search must be 0, 1 or 2");
   if (!(p->h_rtol > 0.0)) return fail(ctx, CRK_EINVAL, "h_rtol must be > 0");
   if (!(p->eps2 >= 0.0) || !(p->dt_relax >= 0.0))
     return fail(ctx, CRK_EINVAL, "eps2 and dt_relax must be >= 0");
@@ -194,10 +201,24 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.slist_cap = c->slist_cap;
   S.cand = (uint32_t*)c->cand.p;
   S.scr_r = (R*)c->scr_r.p;
-  S.scr_m = (R*)c->scr_m.p;
+  S.scr_m = c->equal_mass ? (R*)c->scr_r.p : (R*)c->scr_m.p;  // never read when equal
   S.ccnt = (int*)c->ccnt.p;
   S.scr_cap = c->scr_cap;
   S.equal_mass = c->equal_mass;
+  S.lattice = c->lattice;
+  S.rad = c->lattice ? (R*)c->rad.p : nullptr;
+  S.rlo = c->lattice ? (R*)c->rad.p + ((n + 63) / 64) * 64 : nullptr;
+  S.rhi = c->lattice ? (R*)c->rad.p + 2 * ((n + 63) / 64) * 64 : nullptr;
+  S.todo = c->lattice ? (int*)c->todo.p : nullptr;
+  S.cslot = c->lattice ? (const uint32_t*)c->tslot.p : nullptr;
+  S.shrink = c->p.h_mode == 1 ? 1 : 0;
+  S.nlo = (float4*)c->nlo.p;
+  S.nhi = (float4*)c->nhi.p;
+  S.grow = c->lattice ? (const uint32_t*)c->lrow.p : nullptr;
+  S.srow = c->lattice ? (const uint32_t*)c->lrow.p + (n + 63) / 64 + 1 : nullptr;
+  S.lvl_off = (const int*)c->lvl.p;
+  S.lvl_cnt = c->lvl.p ? (const int*)c->lvl.p + 40 : nullptr;
+  S.nlevels = c->nlevels;
   S.rcap = (R)c->rcap;
   S.cnt = (unsigned long long*)c->cnt.p;
   S.n_h3 = c->p.n_h * c->p.n_h * c->p.n_h;
@@ -287,6 +308,148 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) 
   return CRK_OK;
 }
 
+// Tree path: Morton order over the 1024^3 lattice, leaves = waves, per-particle
+// candidate radii adapted until every h is bracketed; then the tree is rebuilt
+// with the solved h for the symmetric neighbour list.
+template <class R>
+crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
+                      const R* m, const R* u, const R* h) {
+  const crk_params& P = ctx->p;
+  unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
+  const int64_t npad = ((n + 63) / 64) * 64;
+  ctx->lattice = 1;
+  ctx->G = 1024;
+  ctx->ell = P.box / 1024.0;
+  {
+    // room for ~5x the expected neighbour count (4 pi / 3) n_h^3 before a radius shrinks
+    const double expect = 4.18879 * P.n_h * P.n_h * P.n_h;
+    const int want = std::max(320, (int)((5.0 * expect + 31.0) / 32.0) * 32);
+    if (ctx->scr_cap < want) ctx->scr_cap = want;
+  }
+  // levels of the implicit tree over the leaves
+  const int nleaf = (int)((n + 63) / 64);
+  ctx->nlevels = 0;
+  int off = 0;
+  for (int c = nleaf;; c = (c + 1) / 2) {
+    ctx->lvl_off[ctx->nlevels] = off;
+    ctx->lvl_cnt[ctx->nlevels] = c;
+    off += c;
+    ++ctx->nlevels;
+    if (c == 1) break;
+  }
+  CRK_HIP(ensure(ctx->nlo, 16 * (size_t)off), "alloc tree");
+  CRK_HIP(ensure(ctx->nhi, 16 * (size_t)off), "alloc tree");
+  CRK_HIP(ensure(ctx->lvl, 4 * 80), "alloc tree");
+  CRK_HIP(ensure(ctx->rad, 3 * real_size(P.precision) * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->todo, 4 * (size_t)(npad + 1)), "alloc tree");
+  CRK_HIP(ensure(ctx->tslot, 4 * (size_t)(npad + 1)), "alloc tree");
+  CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
+  int lv[80];
+  for (int t = 0; t < 40; ++t) {
+    lv[t] = ctx->lvl_off[t];
+    lv[40 + t] = ctx->lvl_cnt[t];
+  }
+  CRK_HIP(hipMemcpyAsync(ctx->lvl.p, lv, sizeof(lv), hipMemcpyHostToDevice, s), "tree levels");
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+  CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
+  launch_morton(x, n, P.box, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p, s);
+  CRK_HIP(radix_sort_pairs((uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
+                           (uint32_t*)ctx->keys_b.p, (uint32_t*)ctx->vals_b.p, n, 30,
+                           (uint32_t*)ctx->sort_tmp.p, s),
+          "radix sort");
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_gather<R>(S, x, v, m, u, h, s);
+    launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
+    launch_init_radius<R>(S, P.h_mode, s);
+  }
+  CRK_HIP(tend(ctx, P_CELLS, s), "event");
+  // scratch slots of the unsolved particles: exclusive scan of the todo
+  // flags (todo[n] = 0, so slot[n] is their number)
+  int* todo = (int*)ctx->todo.p;
+  uint32_t* slot = (uint32_t*)ctx->tslot.p;
+  auto rank_todo = [&]() -> hipError_t {
+    hipError_t e = exclusive_scan_u32((const uint32_t*)todo, slot, n + 1,
+                                      (uint32_t*)ctx->scan_tmp.p, s);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(&ctx->host_rows[0], slot + n, 4, hipMemcpyDeviceToHost, s);
+  };
+  CRK_HIP(hipMemsetAsync(todo + n, 0, 4, s), "memset");
+  CRK_HIP(rank_todo(), "scan");
+  CRK_HIP(hipStreamSynchronize(s), "scan");
+  bool solved = false;
+  for (int round = 0; round < 40 && !solved; ++round) {
+    const size_t nt = ((size_t)ctx->host_rows[0] + 63) / 64 * 64;
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED, 0, 8 * 2, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY, 0, 8, s), "memset");
+    CRK_HIP(ensure(ctx->cand, 4 * 4), "alloc candidates");
+    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * nt * ctx->scr_cap), "alloc candidates");
+    if (!ctx->equal_mass)
+      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * nt * ctx->scr_cap),
+              "alloc candidates");
+    State<R> S = make_state<R>(ctx, n);
+    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+    launch_candidates_tree<R>(S, s);
+    if (P.h_mode == 0)
+      launch_volume<R>(S, P.kernel, s);
+    else
+      launch_hsolve<R>(S, P.kernel, s);
+    CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
+    CRK_HIP(hipGetLastError(), "h solve launch");
+    CRK_HIP(rank_todo(), "scan");
+    CRK_HIP(read_counters(ctx, s), "h solve");
+    if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
+      // more candidates than the capacity at the smallest admissible radius
+      // (or at the fixed h): grow it and run the unsolved particles again
+      ctx->scr_cap = std::max(
+          ctx->scr_cap, (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32));
+      continue;
+    }
+    solved = P.h_mode == 0 || (ctx->host_cnt[CNT_RETRY] == 0 && ctx->host_cnt[CNT_H_CAPPED] == 0);
+  }
+  if (!solved) return fail(ctx, CRK_EHIP, "tree h solve did not settle");
+  return CRK_OK;
+}
+
+// Tree path neighbour lists with per-wave capacities: count walk, scan of the
+// per-wave chunk rows into offsets, then the fill walk into lists sized to
+// the total.
+template <class R>
+crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
+  unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
+  const int64_t nw = (n + 63) / 64;
+  CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(nw + 1)), "alloc neighbour list");
+  CRK_HIP(ensure(ctx->lrow, 4 * 2 * (size_t)(nw + 1)), "alloc neighbour list");
+  CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(nw + 1)), "alloc scan");
+  uint32_t* wg = (uint32_t*)ctx->wrow.p;
+  uint32_t* ws = wg + nw + 1;
+  uint32_t* lg = (uint32_t*)ctx->lrow.p;
+  uint32_t* ls = lg + nw + 1;
+  CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
+  CRK_HIP(hipMemsetAsync(wg + nw, 0, 4, s), "memset");
+  CRK_HIP(hipMemsetAsync(ws + nw, 0, 4, s), "memset");
+  CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_nlist_tree<R>(S, false, wg, ws, s);
+  }
+  CRK_HIP(exclusive_scan_u32(wg, lg, nw + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
+  CRK_HIP(exclusive_scan_u32(ws, ls, nw + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
+  CRK_HIP(hipMemcpyAsync(&ctx->host_rows[0], lg + nw, 4, hipMemcpyDeviceToHost, s), "rows");
+  CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], ls + nw, 4, hipMemcpyDeviceToHost, s), "rows");
+  CRK_HIP(read_counters(ctx, s), "neighbour list");
+  // a row is one 4-entry chunk of all 64 lanes of a wave
+  CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
+  CRK_HIP(ensure(ctx->slist, 4 * 256 * (size_t)ctx->host_rows[1]), "alloc neighbour list");
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_nlist_tree<R>(S, true, wg, ws, s);
+  }
+  CRK_HIP(tend(ctx, P_NLIST, s), "event");
+  CRK_HIP(hipGetLastError(), "neighbour list launch");
+  return CRK_OK;
+}
+
 template <class R>
 crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
                         const R* m, const R* u, R* h, R* V, R* rho, void* A, void* B,
@@ -315,9 +478,11 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
   ctx->G = choose_grid(P.box, reach, n);
   ctx->ell = P.box / ctx->G;
+  ctx->lattice = 0;
   const int64_t npad = ((n + 63) / 64) * 64;
   bool solved = false;
-  for (int attempt = 0; attempt < 12 && !solved; ++attempt) {
+  bool use_tree = P.search == 2;
+  for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
     // candidates reach the cell side when h is solved, the largest h otherwise
     ctx->rcap = P.h_mode == 1 ? ctx->ell : h0max;
     CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
@@ -332,9 +497,9 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
     CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
             "alloc candidates");
-    // allocated even when unused so that no code path can read past it
-    CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
-            "alloc candidates");
+    if (!ctx->equal_mass)
+      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+              "alloc candidates");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     launch_candidates<R>(S, s);
@@ -346,6 +511,10 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     CRK_HIP(hipGetLastError(), "h solve launch");
     CRK_HIP(read_counters(ctx, s), "h solve");
     if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
+      if (P.search == 0 && ctx->host_cnt[CNT_SCR_OVERFLOW] > 1024) {
+        use_tree = true;  // clustered: the cell list would need huge candidate lists
+        break;
+      }
       ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);
       continue;  // same grid, larger candidate capacity
     }
@@ -358,6 +527,11 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     }
     solved = true;
   }
+  if (use_tree) {
+    crk_status st = tree_solve<R>(ctx, s, n, x, v, m, u, h);
+    if (st != CRK_OK) return st;
+    solved = true;
+  }
   if (!solved) return fail(ctx, CRK_EHIP, "h solve: grid adaptation did not settle");
   if (P.h_mode == 1) {
     const double hmax = bits_to_double(ctx->host_cnt[CNT_HMAX_OUT_BITS]);
@@ -367,25 +541,32 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   {
     State<R> S = make_state<R>(ctx, n);
     launch_pack<R>(S, h, V, s);
+    if (ctx->lattice)  // node boxes with the solved h for the symmetric search
+      launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
   }
-  // neighbour lists, grown until they fit
-  for (int attempt = 0; attempt < 8; ++attempt) {
-    CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
-    CRK_HIP(ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap), "alloc neighbour list");
-    State<R> S = make_state<R>(ctx, n);
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8 * 2, s), "memset");
-    CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
-    launch_nlist<R>(S, s);
-    CRK_HIP(tend(ctx, P_NLIST, s), "event");
-    CRK_HIP(hipGetLastError(), "neighbour list launch");
-    CRK_HIP(read_counters(ctx, s), "neighbour list");
-    const unsigned long long need = ctx->host_cnt[CNT_LIST_OVERFLOW];
-    const unsigned long long sneed = ctx->host_cnt[CNT_SLIST_OVERFLOW];
-    if (!need && !sneed) break;
-    if (need) ctx->list_cap = (int)((need * 5 / 4 + 31) / 32 * 32);
-    if (sneed) ctx->slist_cap = (int)((sneed * 5 / 4 + 31) / 32 * 32);
-    if (attempt == 7) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
+  if (ctx->lattice) {
+    crk_status st = tree_lists<R>(ctx, s, n);
+    if (st != CRK_OK) return st;
+  } else {
+    // neighbour lists, grown until they fit
+    for (int attempt = 0; attempt < 8; ++attempt) {
+      CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
+      CRK_HIP(ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap), "alloc neighbour list");
+      State<R> S = make_state<R>(ctx, n);
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8 * 2, s), "memset");
+      CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
+      launch_nlist<R>(S, s);
+      CRK_HIP(tend(ctx, P_NLIST, s), "event");
+      CRK_HIP(hipGetLastError(), "neighbour list launch");
+      CRK_HIP(read_counters(ctx, s), "neighbour list");
+      const unsigned long long need = ctx->host_cnt[CNT_LIST_OVERFLOW];
+      const unsigned long long sneed = ctx->host_cnt[CNT_SLIST_OVERFLOW];
+      if (!need && !sneed) break;
+      if (need) ctx->list_cap = (int)((need * 5 / 4 + 31) / 32 * 32);
+      if (sneed) ctx->slist_cap = (int)((sneed * 5 / 4 + 31) / 32 * 32);
+      if (attempt == 7) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
+    }
   }
   State<R> S = make_state<R>(ctx, n);
   CorrOut co{A, B, gradA, gradB};
@@ -560,7 +741,8 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
-                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap};
+                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap,
+                &c->rad, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_cnt) (void)hipHostFree(c->host_cnt);
   if (c->events_ready)

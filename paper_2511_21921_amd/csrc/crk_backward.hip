@@ -148,15 +148,15 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
     const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
     ForceBar<double> ob;
     ob.zero();
-    int ng, ns;
-    nbr_counts(S, s, ng, ns);
+    const NbrRef nb = nbr_ref(S, s);
+    const int ng = nb.ng, ns = nb.ns;
     const R4<R> pi = S.pos4[s];
     for (int t = 0; t < ng + ns; ++t) {
-      const uint32_t e = nbr_entry(S, s, t, ng);
+      const uint32_t e = nbr_entry(S, nb, t);
       const uint32_t j = e >> kCodeBits;
       load_side(S, G, j, J, relj);
       R x[3];
-      pair_sep<R>(pi, S.pos4[j], e & kCodeMask, S.ell, x);
+      pair_x(S, s, pi, S.pos4[j], e, x);
       const bool plain = relax_on && (reli != R(0) || relj != R(0));
       if (plain) {
         kc_plain(I.kc);
@@ -237,15 +237,15 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   R W0, dW0;
   kernel_self<R, K>(pi.w, W0, dW0);
   density_self_adj<R, double>(ki.a, mi, vi.w, W0, dW0, Numb, Denb, &kb, Vb, hb);
-  int ng, ns;
-  nbr_counts(S, s, ng, ns);
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, s, t, ng);
+    const uint32_t e = nbr_entry(S, nb, t);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
     R x[3];
-    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;
@@ -292,13 +292,14 @@ __device__ inline void moments_raw(const State<R>& S, int64_t s, double raw[40])
   R W0, dW0;
   kernel_self<R, K>(hinv, W0, dW0);
   acc[0] = S.vel4[s].w * W0;
-  const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
+    const uint32_t e = S.nlist[slot_at(nb.gb, k)];
     const uint32_t j = e >> kCodeBits;
     const R Vj = S.vel4[j].w;
     R x[3];
-    pair_sep<R>(pi, S.pos4[j], e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, S.pos4[j], e, x);
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     R w, dw;
@@ -362,14 +363,14 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   double Vb = (double)(mb[0] * W0), hb = (double)(mb[0] * Vi * dW0);
   double sh = (double)(mi * dW0);
   double xb[3] = {0, 0, 0};
-  int ng, ns;
-  nbr_counts(S, s, ng, ns);
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, s, t, ng);
+    const uint32_t e = nbr_entry(S, nb, t);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
-    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;
@@ -422,14 +423,14 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
   const R mi = S.mass[s];
   const R ki = G.kap[s];
   double xb[3] = {0, 0, 0};
-  int ng, ns;
-  nbr_counts(S, s, ng, ns);
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, s, t, ng);
+    const uint32_t e = nbr_entry(S, nb, t);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
-    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;

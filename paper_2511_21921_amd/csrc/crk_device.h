@@ -148,6 +148,16 @@ __device__ inline int64_t list_index(int64_t i, int cap, int k) {
   return ((((i >> 6) * (int64_t)(cap >> 2) + (k >> 2)) * 64 + (i & 63)) << 2) + (k & 3);
 }
 
+// The same layout with a per-wave capacity: the wave of particle i starts at
+// chunk row row0 (a row = one 4-entry chunk of all 64 lanes = 256 words).
+// slot_base gives the word of entry 0 of particle i, slot_at that of entry k.
+__device__ inline int64_t slot_base(int64_t row0, int64_t i) {
+  return (row0 * 64 + (i & 63)) << 2;
+}
+__device__ inline int64_t slot_at(int64_t base, int k) {
+  return base + ((int64_t)(k >> 2) << 8) + (k & 3);
+}
+
 // Register staging of one lane's appends: four values are collected and
 // written with one 16-byte store (the whole chunk, including unused tail
 // slots at the final flush; only the counted entries are ever read).
@@ -173,6 +183,15 @@ struct Stage4 {
     q.z = v2;
     q.w = v3;
     *reinterpret_cast<typename Vec4T<T>::V*>(base + list_index(i, cap, k & ~3)) = q;
+  }
+  // the same for a list addressed by its slot_base b
+  __device__ inline void flush_at(T* base, int64_t b, int k) const {
+    typename Vec4T<T>::V q;
+    q.x = v0;
+    q.y = v1;
+    q.z = v2;
+    q.w = v3;
+    *reinterpret_cast<typename Vec4T<T>::V*>(base + slot_at(b, k & ~3)) = q;
   }
 };
 

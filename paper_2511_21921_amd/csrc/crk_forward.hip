@@ -110,11 +110,13 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   const uint32_t p = S.perm[s];
   if (p >= (uint32_t)n) return;
   int c[3];
-  cell_coords(S.keys[s], S.G, c[0], c[1], c[2]);
   R xi[3];
+  const double inv = (double)S.G / S.box;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double t = wrap_pos(x[a * n + p], S.box);
+    const int k = (int)(t * inv);
+    c[a] = k < S.G ? k : S.G - 1;
     xi[a] = (R)(t - ((double)c[a] + 0.5) * S.ell_d);
   }
   R4<R> q;
@@ -196,12 +198,12 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
 // sum_k (m_k/m_i) w(r_k / h) over the candidates plus the self term w(0), and
 // dsum = sum_k (m_k/m_i) w'(q_k) q_k.
 template <class R, int K>
-__device__ inline R candidate_sum(const State<R>& S, int64_t s, int cnt, R h, R& dsum) {
+__device__ inline R candidate_sum(const State<R>& S, int64_t q, int cnt, R h, R& dsum) {
   if (cnt > S.scr_cap) cnt = S.scr_cap;
   const R hinv = R(1) / h;
   R sum = R(Shape<K>::w0), ds = R(0);
   for (int k = 0; k < cnt; ++k) {
-    const int64_t e = list_index(s, S.scr_cap, k);
+    const int64_t e = list_index(q, S.scr_cap, k);
     const R q = S.scr_r[e] * hinv;
     const R mr = S.equal_mass ? R(1) : S.scr_m[e];
     R w, dw;
@@ -223,15 +225,27 @@ template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
-  if (s < S.n) {
+  // tree path: only particles still to solve, whose candidate pass fitted
+  const bool work = s < S.n && (!S.todo || (S.todo[s] && S.ccnt[s] >= 0));
+  if (work) {
     const int cnt = S.ccnt[s];
+    const int64_t q = scratch_slot(S, s);
     const R C = R(Shape<K>::C);
     const R n_h3 = R(S.n_h3);
-    const R Rcap = S.rcap;
+    const R Rcap = S.rad ? S.rad[s] : S.rcap;
     R h, dsum;
-    if (!(C * candidate_sum<R, K>(S, s, cnt, Rcap, dsum) - n_h3 > R(0))) {
+    bool cap_hit = false;
+    if (!(C * candidate_sum<R, K>(S, q, cnt, Rcap, dsum) - n_h3 > R(0))) {
       capped = 1;  // the root lies beyond the candidate radius
+      cap_hit = true;
       h = Rcap;
+      if (S.rad) {
+        // next radius: halfway (in log r) to the smallest known overflowing
+        // radius, else 1.6x
+        const R up = S.rhi[s];
+        S.rlo[s] = Rcap;
+        S.rad[s] = up > R(1.0001) * Rcap ? Sc<R>::sqrt(Rcap * up) : R(1.6) * Rcap;
+      }
     } else {
       R lo = R(0), hi = Rcap;
       h = S.hbuf[s];
@@ -240,7 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       bool conv = false;
       int it = 0;
       for (; it < S.max_iter; ++it) {
-        const R f = C * candidate_sum<R, K>(S, s, cnt, h, dsum) - n_h3;
+        const R f = C * candidate_sum<R, K>(S, q, cnt, h, dsum) - n_h3;
         const R fp = -C * dsum / h;
         if (f > R(0)) hi = h; else lo = h;
         R hn = R(0.5) * (lo + hi);
@@ -263,10 +277,13 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       iters = (unsigned long long)(it + 1);
       unconv = conv ? 0 : 1;
     }
-    const R sum = candidate_sum<R, K>(S, s, cnt, h, dsum);
-    S.hbuf[s] = h;
-    S.Vbuf[s] = h * h * h / (C * sum);
-    hbits = dbits((double)h);
+    if (!cap_hit) {
+      const R sum = candidate_sum<R, K>(S, q, cnt, h, dsum);
+      S.hbuf[s] = h;
+      S.Vbuf[s] = h * h * h / (C * sum);
+      hbits = dbits((double)h);
+      if (S.todo) S.todo[s] = 0;
+    }
   }
   wave_max_u64(&S.cnt[CNT_H_ITER_MAX], iters);
   wave_add_u64(&S.cnt[CNT_H_UNCONV], unconv);
@@ -281,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   if (s >= S.n) return;
   const R h = S.hbuf[s];
   R dsum;
-  const R sum = candidate_sum<R, K>(S, s, S.ccnt[s], h, dsum);
+  const R sum = candidate_sum<R, K>(S, scratch_slot(S, s), S.ccnt[s], h, dsum);
   S.Vbuf[s] = h * h * h / (R(Shape<K>::C) * sum);
 }
 
@@ -316,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       R x[3];
-      pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+      pair_x(S, s, pi, pj, e, x);
       const R r2 = dot3(x, x);
       if (r2 * hi2 < R(1)) {
         if (ng < cap) {
@@ -383,14 +400,15 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
   for (int t = 0; t < 9; ++t) M.X1[t] = R(0);
 #pragma unroll
   for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
-  const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
+    const uint32_t e = S.nlist[slot_at(nb.gb, k)];
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R Vj = S.vel4[j].w;
     R x[3];
-    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     const R q = r2 * rinv * hinv;
@@ -630,15 +648,16 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
     R gv[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) gv[t] = R(0);
-    const int ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
+    const NbrRef nb = nbr_ref(S, s);
+    const int ng = nb.ng;
     for (int k = 0; k < ng; ++k) {
-      const uint32_t e = S.nlist[list_index(s, S.list_cap, k)];
+      const uint32_t e = S.nlist[slot_at(nb.gb, k)];
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       const R4<R> vj = S.vel4[j];
       const R mj = S.mass[j];
       R x[3];
-      pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+      pair_x(S, s, pi, pj, e, x);
       const R r2 = dot3(x, x);
       const R rinv = Sc<R>::rsqrt(r2);
       R w, dw;
@@ -732,11 +751,11 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
   const R hi = R(1) / pi.w;
   double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
-  int ng, ns;
-  nbr_counts(S, s, ng, ns);
+  const NbrRef nb = nbr_ref(S, s);
+  const int ng = nb.ng, ns = nb.ns;
   const int total = ng + ns;
   for (int t = 0; t < total; ++t) {
-    const uint32_t e = nbr_entry(S, s, t, ng);
+    const uint32_t e = nbr_entry(S, nb, t);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
@@ -746,7 +765,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
     R gvj[9], relj;
     load_gv(S, j, gvj, relj);
     R x[3];
-    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     KC<R> kiu = ki;

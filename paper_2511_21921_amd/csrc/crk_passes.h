@@ -15,6 +15,20 @@ void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
                  uint32_t* cell_count, hipStream_t s);
 
+// Morton keys over the 1024^3 lattice (tree path) and identity values.
+void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint32_t* vals,
+                   hipStream_t s);
+// Leaf boxes (with the largest h of each leaf, from h) and the node levels.
+template <class R>
+void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const int* host_cnt,
+                       hipStream_t s);
+template <class R>
+void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
+template <class R>
+void launch_candidates_tree(const State<R>& S, hipStream_t s);
+template <class R>
+void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws, hipStream_t s);
+
 // Gather caller arrays into cell-sorted SoA with cell-centre offsets.
 template <class R>
 void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, const R* u,

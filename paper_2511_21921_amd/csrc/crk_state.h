@@ -20,6 +20,7 @@ enum Counter {
   CNT_SLIST_OVERFLOW,  // largest scatter-only count beyond its capacity
   CNT_MMAX_BITS,       // max mass as double bits
   CNT_MINVMAX_BITS,    // max 1/mass as double bits
+  CNT_RETRY,           // particles whose candidate radius shrank (tree path)
   CNT_SINGULAR,
   CNT_RELAXED,
   CNT_NONFINITE,
@@ -30,7 +31,8 @@ enum Counter {
 template <class R>
 struct State {
   int64_t n;
-  int G;              // cells per side
+  int G;              // cells per side (lattice cells per side when lattice = 1)
+  int lattice;        // 0: cell list with stencil codes; 1: tree over a fine lattice
   double box, ell_d;  // box side and cell side (FP64)
   R ell;              // cell side in Real
   // cell list
@@ -57,6 +59,11 @@ struct State {
   int* ns;
   int list_cap;
   int slist_cap;
+  // per-wave capacities (tree path): chunk-row offset of every wave's gather
+  // and scatter-only lists, one entry per wave plus the total; null when
+  // every wave has list_cap / slist_cap
+  const uint32_t* grow;
+  const uint32_t* srow;
   // candidates within rcap of each particle (chunked SELL): packed entries,
   // r, and m_j/m_i (the last only when the masses differ)
   uint32_t* cand;
@@ -66,6 +73,19 @@ struct State {
   int scr_cap;
   int equal_mass;
   R rcap;
+  R* rad;             // per-particle candidate radius (tree path) or null
+  R* rlo;             // largest radius known to hold the h root beyond it (0: none)
+  R* rhi;             // smallest radius known to overflow the candidate capacity (0: none)
+  int* todo;          // per-particle "h not solved yet" flag (tree path) or null
+  const uint32_t* cslot;  // candidate scratch slot of each unsolved particle, or null
+  int shrink;         // tree path: adapt the radius of an overflowing particle
+  // tree over waves of 64 Morton-sorted particles (tree path): node boxes
+  // (x, y, z, h_max) low corner and (x, y, z, -) high corner per level
+  float4* nlo;
+  float4* nhi;
+  const int* lvl_off;  // node offset of each level (level 0 = leaves)
+  const int* lvl_cnt;  // node count of each level
+  int nlevels;
   unsigned long long* cnt;
   // parameters
   double n_h3, gamma, alpha, beta, eps2, dt_relax, rtol;
@@ -198,17 +218,70 @@ __device__ inline void wave_traverse(const State<R>& S, bool active, uint32_t c3
   }
 }
 
-// Entry t of particle s's symmetric neighbour list: gather part first.
+// Periodic separation x_ij = x_i - x_j. Cell-list path: from the stencil
+// code of the list entry. Lattice path: from both particles' lattice
+// coordinates, the difference wrapped to the nearest periodic image.
 template <class R>
-__device__ inline uint32_t nbr_entry(const State<R>& S, int64_t s, int t, int ng) {
-  return t < ng ? S.nlist[list_index(s, S.list_cap, t)]
-                : S.slist[list_index(s, S.slist_cap, t - ng)];
+__device__ inline void pair_x(const State<R>& S, int64_t s, const R4<R>& pi, const R4<R>& pj,
+                              uint32_t e, R x[3]) {
+  if (!S.lattice) {
+    pair_sep<R>(pi, pj, e & kCodeMask, S.ell, x);
+    return;
+  }
+  const uint32_t a = S.cell3[s], b = S.cell3[e >> kCodeBits];
+  const int G = S.G, half = S.G >> 1;
+  int d[3] = {(int)(a & 1023u) - (int)(b & 1023u),
+              (int)((a >> 10) & 1023u) - (int)((b >> 10) & 1023u),
+              (int)(a >> 20) - (int)(b >> 20)};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) d[t] = d[t] < -half ? d[t] + G : (d[t] >= half ? d[t] - G : d[t]);
+  x[0] = (pi.x - pj.x) + R(d[0]) * S.ell;
+  x[1] = (pi.y - pj.y) + R(d[1]) * S.ell;
+  x[2] = (pi.z - pj.z) + R(d[2]) * S.ell;
 }
 
+// Row of the candidate scratch that particle s uses: its own index, or on the
+// tree path its rank among the particles still unsolved in this round.
 template <class R>
-__device__ inline void nbr_counts(const State<R>& S, int64_t s, int& ng, int& ns) {
-  ng = S.ng[s] < S.list_cap ? S.ng[s] : S.list_cap;
-  ns = S.ns[s] < S.slist_cap ? S.ns[s] : S.slist_cap;
+__device__ inline int64_t scratch_slot(const State<R>& S, int64_t s) {
+  return S.cslot ? (int64_t)S.cslot[s] : s;
+}
+
+// Where particle s's symmetric neighbour list lives: the gather part
+// (r < h_s) and the scatter-only part (h_s <= r < h_j), with their lengths.
+struct NbrRef {
+  int64_t gb, sb;
+  int ng, ns;
+};
+
+template <class R>
+__device__ inline NbrRef nbr_ref(const State<R>& S, int64_t s) {
+  const int64_t w = s >> 6;
+  int64_t g0, s0;
+  int gcap, scap;
+  if (S.grow) {
+    g0 = S.grow[w];
+    s0 = S.srow[w];
+    gcap = (int)(S.grow[w + 1] - S.grow[w]) * 4;
+    scap = (int)(S.srow[w + 1] - S.srow[w]) * 4;
+  } else {
+    g0 = w * (S.list_cap >> 2);
+    s0 = w * (S.slist_cap >> 2);
+    gcap = S.list_cap;
+    scap = S.slist_cap;
+  }
+  NbrRef r;
+  r.gb = slot_base(g0, s);
+  r.sb = slot_base(s0, s);
+  r.ng = S.ng[s] < gcap ? S.ng[s] : gcap;
+  r.ns = S.ns[s] < scap ? S.ns[s] : scap;
+  return r;
+}
+
+// Entry t of the symmetric list: gather part first.
+template <class R>
+__device__ inline uint32_t nbr_entry(const State<R>& S, const NbrRef& r, int t) {
+  return t < r.ng ? S.nlist[slot_at(r.gb, t)] : S.slist[slot_at(r.sb, t - r.ng)];
 }
 
 }  // namespace crk

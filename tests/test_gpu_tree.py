@@ -1,0 +1,76 @@
+"""GPU parity of the tree neighbour search (clustered particle sets).
+
+The tree path (Morton-ordered 64-particle leaves over a 1024^3 lattice) must
+give the same results as the cell-list path and the oracle: the same bounds
+as test_gpu_forward.py, forced on uniform inputs and chosen automatically on
+Plummer-clump inputs whose smoothing lengths span more than an order of
+magnitude.
+"""
+import numpy as np
+import pytest
+
+import synth
+from paper_2511_21921_amd import FP32, FP64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+from tests import _gpu  # noqa: E402
+from tests.test_gpu_forward import FP32_BOUNDS, FP64_BOUNDS, _compare  # noqa: E402
+
+TREE = 2
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_tree_forced_on_lattice_fixed_h(precision):
+    ps = synth.lattice16()
+    g, o, _ = _compare(ps, precision, FP64_BOUNDS if precision == FP64 else FP32_BOUNDS,
+                       search=TREE)
+    assert g["stats"]["n_pairs_force"] == o["pairs_force"]
+    assert g["stats"]["grid"] == 1024
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_tree_forced_adaptive_random_masses(precision):
+    ps = synth.random_small(3001, 61, mass_spread=0.1)
+    _compare(ps, precision, FP64_BOUNDS if precision == FP64 else FP32_BOUNDS, search=TREE)
+
+
+def _clumps(n, nc, seed):
+    ps = synth.plummer_clumps(n, nc, seed)
+    rng = np.random.default_rng(seed)
+    ps.w_a, ps.w_u = rng.normal(size=(3, ps.n)), rng.normal(size=ps.n)
+    return ps
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_clustered_switches_to_tree_and_matches_oracle(precision):
+    ps = _clumps(20000, 8, 62)
+    g, o, e = _compare(ps, precision, FP64_BOUNDS if precision == FP64 else FP32_BOUNDS, nbr=1)
+    hr = o["h"].max() / o["h"].min()
+    print("h range %.1f, grid %d" % (hr, g["stats"]["grid"]))
+    assert hr > 30
+    assert g["stats"]["grid"] == 1024          # automatic choice of the tree path
+    assert g["stats"]["h_unconverged"] == 0
+    if precision == FP64:
+        assert g["stats"]["n_pairs_force"] == o["pairs_force"]
+
+
+def test_clustered_adjoint_fp64_matches_oracle_jvp():
+    from tests.test_gpu_backward import _check_jvps, _grad
+    ps = _clumps(6000, 4, 63)
+    print("case clumps n=%d" % ps.n, flush=True)
+    g, _ = _grad(ps, FP64, search=TREE)
+    _check_jvps(ps, g, 1e-9)
+
+
+def test_tree_and_cell_list_agree_fp64():
+    ps = synth.sedov(16, k=4, with_velocity=True)
+    a, _ = _gpu.run(ps, FP64, search=1)
+    b, _ = _gpu.run(ps, FP64, search=TREE)
+    for k in ("h", "V", "rho", "accel", "dudt"):
+        assert np.abs(a[k] - b[k]).max() <= 1e-11 * np.abs(a[k]).max(), k
+    assert a["stats"]["n_pairs_force"] == b["stats"]["n_pairs_force"]
