@@ -51,7 +51,7 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, todo, tslot, nlo, nhi, lvl, wrow, lrow;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow;
   uint32_t host_rows[2] = {};
   int lvl_off[40] = {}, lvl_cnt[40] = {};
   int nlevels = 0;
@@ -207,10 +207,10 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.equal_mass = c->equal_mass;
   S.lattice = c->lattice;
   S.rad = c->lattice ? (R*)c->rad.p : nullptr;
-  S.rlo = c->lattice ? (R*)c->rad.p + ((n + 63) / 64) * 64 : nullptr;
-  S.rhi = c->lattice ? (R*)c->rad.p + 2 * ((n + 63) / 64) * 64 : nullptr;
+  S.need = c->lattice ? (int*)c->need.p : nullptr;
   S.todo = c->lattice ? (int*)c->todo.p : nullptr;
   S.cslot = c->lattice ? (const uint32_t*)c->tslot.p : nullptr;
+  S.vrow = c->lattice ? (const uint32_t*)c->wrow.p + ((n + 63) / 64) + 1 : nullptr;
   S.shrink = c->p.h_mode == 1 ? 1 : 0;
   S.nlo = (float4*)c->nlo.p;
   S.nhi = (float4*)c->nhi.p;
@@ -340,9 +340,11 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(ensure(ctx->nlo, 16 * (size_t)off), "alloc tree");
   CRK_HIP(ensure(ctx->nhi, 16 * (size_t)off), "alloc tree");
   CRK_HIP(ensure(ctx->lvl, 4 * 80), "alloc tree");
-  CRK_HIP(ensure(ctx->rad, 3 * real_size(P.precision) * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->rad, real_size(P.precision) * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->todo, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->tslot, 4 * (size_t)(npad + 1)), "alloc tree");
+  CRK_HIP(ensure(ctx->need, 4 * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(npad / 64 + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
   int lv[80];
   for (int t = 0; t < 40; ++t) {
@@ -364,49 +366,51 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     launch_init_radius<R>(S, P.h_mode, s);
   }
   CRK_HIP(tend(ctx, P_CELLS, s), "event");
-  // scratch slots of the unsolved particles: exclusive scan of the todo
-  // flags (todo[n] = 0, so slot[n] is their number)
+  // Rounds over the particles still unsolved. Each round ranks them (scan of
+  // the todo flags, todo[n] = 0), sizes every group of 64 ranks to the
+  // largest capacity request in it, runs the candidate walk and the h solve
+  // (or the volume for fixed h) on them, and stops when none is left.
   int* todo = (int*)ctx->todo.p;
   uint32_t* slot = (uint32_t*)ctx->tslot.p;
-  auto rank_todo = [&]() -> hipError_t {
-    hipError_t e = exclusive_scan_u32((const uint32_t*)todo, slot, n + 1,
-                                      (uint32_t*)ctx->scan_tmp.p, s);
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(&ctx->host_rows[0], slot + n, 4, hipMemcpyDeviceToHost, s);
-  };
+  const int64_t ngrp = npad / 64;
+  uint32_t* grows = (uint32_t*)ctx->wrow.p;  // per-group rows, then their offsets
+  uint32_t* goff = grows + ngrp + 1;
   CRK_HIP(hipMemsetAsync(todo + n, 0, 4, s), "memset");
-  CRK_HIP(rank_todo(), "scan");
-  CRK_HIP(hipStreamSynchronize(s), "scan");
   bool solved = false;
-  for (int round = 0; round < 40 && !solved; ++round) {
-    const size_t nt = ((size_t)ctx->host_rows[0] + 63) / 64 * 64;
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED, 0, 8 * 2, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY, 0, 8, s), "memset");
-    CRK_HIP(ensure(ctx->cand, 4 * 4), "alloc candidates");
-    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * nt * ctx->scr_cap), "alloc candidates");
+  for (int round = 0; round < 40; ++round) {
+    CRK_HIP(exclusive_scan_u32((const uint32_t*)todo, slot, n + 1, (uint32_t*)ctx->scan_tmp.p,
+                               s),
+            "scan");
+    CRK_HIP(hipMemcpyAsync(&ctx->host_rows[0], slot + n, 4, hipMemcpyDeviceToHost, s), "rows");
+    CRK_HIP(hipMemsetAsync(grows, 0, 4 * (size_t)(ngrp + 1), s), "memset");
+    {
+      State<R> S = make_state<R>(ctx, n);
+      launch_slot_rows<R>(S, grows, s);
+    }
+    CRK_HIP(exclusive_scan_u32(grows, goff, ngrp + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
+    CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], goff + ngrp, 4, hipMemcpyDeviceToHost, s), "rows");
+    CRK_HIP(hipStreamSynchronize(s), "scan");
+    if (ctx->host_rows[0] == 0) {
+      solved = true;
+      break;
+    }
+    const size_t words = 256 * (size_t)ctx->host_rows[1];  // a row: 4 entries of 64 slots
+    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * words), "alloc candidates");
     if (!ctx->equal_mass)
-      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * nt * ctx->scr_cap),
-              "alloc candidates");
+      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * words), "alloc candidates");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED, 0, 8, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY, 0, 8, s), "memset");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
-    launch_candidates_tree<R>(S, s);
+    launch_candidates_tree<R>(S, P.kernel, s);
     if (P.h_mode == 0)
       launch_volume<R>(S, P.kernel, s);
     else
       launch_hsolve<R>(S, P.kernel, s);
     CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
-    CRK_HIP(rank_todo(), "scan");
-    CRK_HIP(read_counters(ctx, s), "h solve");
-    if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
-      // more candidates than the capacity at the smallest admissible radius
-      // (or at the fixed h): grow it and run the unsolved particles again
-      ctx->scr_cap = std::max(
-          ctx->scr_cap, (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32));
-      continue;
-    }
-    solved = P.h_mode == 0 || (ctx->host_cnt[CNT_RETRY] == 0 && ctx->host_cnt[CNT_H_CAPPED] == 0);
   }
+  CRK_HIP(read_counters(ctx, s), "h solve");
   if (!solved) return fail(ctx, CRK_EHIP, "tree h solve did not settle");
   return CRK_OK;
 }
@@ -742,7 +746,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap,
-                &c->rad, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
+                &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_cnt) (void)hipHostFree(c->host_cnt);
   if (c->events_ready)

@@ -198,12 +198,11 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
 // sum_k (m_k/m_i) w(r_k / h) over the candidates plus the self term w(0), and
 // dsum = sum_k (m_k/m_i) w'(q_k) q_k.
 template <class R, int K>
-__device__ inline R candidate_sum(const State<R>& S, int64_t q, int cnt, R h, R& dsum) {
-  if (cnt > S.scr_cap) cnt = S.scr_cap;
+__device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h, R& dsum) {
   const R hinv = R(1) / h;
   R sum = R(Shape<K>::w0), ds = R(0);
   for (int k = 0; k < cnt; ++k) {
-    const int64_t e = list_index(q, S.scr_cap, k);
+    const int64_t e = slot_at(base, k);
     const R q = S.scr_r[e] * hinv;
     const R mr = S.equal_mass ? R(1) : S.scr_m[e];
     R w, dw;
@@ -228,8 +227,9 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
   // tree path: only particles still to solve, whose candidate pass fitted
   const bool work = s < S.n && (!S.todo || (S.todo[s] && S.ccnt[s] >= 0));
   if (work) {
-    const int cnt = S.ccnt[s];
-    const int64_t q = scratch_slot(S, s);
+    int scap;
+    const int64_t q = scratch_base(S, s, scap);
+    const int cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
     const R C = R(Shape<K>::C);
     const R n_h3 = R(S.n_h3);
     const R Rcap = S.rad ? S.rad[s] : S.rcap;
@@ -240,11 +240,10 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       cap_hit = true;
       h = Rcap;
       if (S.rad) {
-        // next radius: halfway (in log r) to the smallest known overflowing
-        // radius, else 1.6x
-        const R up = S.rhi[s];
-        S.rlo[s] = Rcap;
-        S.rad[s] = up > R(1.0001) * Rcap ? Sc<R>::sqrt(Rcap * up) : R(1.6) * Rcap;
+        // tree path: grow the radius by what the candidate count suggests
+        const double g = grow_factor(S.n_h3, cnt);
+        S.rad[s] = (R)((double)Rcap * g);
+        S.need[s] = max(S.need[s], need_after_growth(cnt, g));
       }
     } else {
       R lo = R(0), hi = Rcap;
@@ -296,10 +295,14 @@ template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (s >= S.n) return;
+  if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
   const R h = S.hbuf[s];
+  int scap;
+  const int64_t base = scratch_base(S, s, scap);
   R dsum;
-  const R sum = candidate_sum<R, K>(S, scratch_slot(S, s), S.ccnt[s], h, dsum);
+  const R sum = candidate_sum<R, K>(S, base, S.ccnt[s] < scap ? S.ccnt[s] : scap, h, dsum);
   S.Vbuf[s] = h * h * h / (R(Shape<K>::C) * sum);
+  if (S.todo) S.todo[s] = 0;
 }
 
 template <class R>

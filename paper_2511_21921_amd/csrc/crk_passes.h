@@ -25,7 +25,9 @@ void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const
 template <class R>
 void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
 template <class R>
-void launch_candidates_tree(const State<R>& S, hipStream_t s);
+void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s);
+template <class R>
+void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 template <class R>
 void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws, hipStream_t s);
 

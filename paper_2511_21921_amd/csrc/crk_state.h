@@ -74,10 +74,13 @@ struct State {
   int equal_mass;
   R rcap;
   R* rad;             // per-particle candidate radius (tree path) or null
-  R* rlo;             // largest radius known to hold the h root beyond it (0: none)
-  R* rhi;             // smallest radius known to overflow the candidate capacity (0: none)
+  int* need;          // per-particle candidate capacity request (tree path) or null
   int* todo;          // per-particle "h not solved yet" flag (tree path) or null
-  const uint32_t* cslot;  // candidate scratch slot of each unsolved particle, or null
+  // tree path: rank of each particle among the unsolved ones (its scratch
+  // slot), and the chunk-row offset of every group of 64 slots, whose
+  // capacity is the largest request in the group; null on the cell path
+  const uint32_t* cslot;
+  const uint32_t* vrow;
   int shrink;         // tree path: adapt the radius of an overflowing particle
   // tree over waves of 64 Morton-sorted particles (tree path): node boxes
   // (x, y, z, h_max) low corner and (x, y, z, -) high corner per level
@@ -240,11 +243,34 @@ __device__ inline void pair_x(const State<R>& S, int64_t s, const R4<R>& pi, con
   x[2] = (pi.z - pj.z) + R(d[2]) * S.ell;
 }
 
-// Row of the candidate scratch that particle s uses: its own index, or on the
-// tree path its rank among the particles still unsolved in this round.
+// Tree path radius growth when the h root lies beyond the radius: by the
+// factor that would bring the candidate count to the target (4 pi / 3) n_h^3
+// at the density seen, x1.1, kept within [1.25, 4].
+__device__ inline double grow_factor(double n_h3, int cnt) {
+  const double g = 1.1 * cbrt(4.18879020478639098 * n_h3 / (double)(cnt > 1 ? cnt : 1));
+  return g < 1.25 ? 1.25 : (g > 4.0 ? 4.0 : g);
+}
+
+// Capacity to request for the grown radius: the count scaled by the volume,
+// with 30% room, in whole 4-entry chunks.
+__device__ inline int need_after_growth(int cnt, double g) {
+  const double v = 1.3 * (double)(cnt > 1 ? cnt : 1) * g * g * g;
+  const int c = v < 1e8 ? (int)v : 100000000;
+  return (c + 3) & ~3;
+}
+
+// First word and capacity of particle s's candidate scratch: slot s with the
+// uniform capacity on the cell path; on the tree path its rank among the
+// particles still unsolved, with the capacity of its group of 64 ranks.
 template <class R>
-__device__ inline int64_t scratch_slot(const State<R>& S, int64_t s) {
-  return S.cslot ? (int64_t)S.cslot[s] : s;
+__device__ inline int64_t scratch_base(const State<R>& S, int64_t s, int& cap) {
+  if (!S.cslot) {
+    cap = S.scr_cap;
+    return slot_base((s >> 6) * (int64_t)(S.scr_cap >> 2), s);
+  }
+  const int64_t q = S.cslot[s], w = q >> 6;
+  cap = (int)(S.vrow[w + 1] - S.vrow[w]) * 4;
+  return slot_base(S.vrow[w], q);
 }
 
 // Where particle s's symmetric neighbour list lives: the gather part

@@ -86,68 +86,48 @@ __global__ void __launch_bounds__(kBlock) k_tree_up(float4* nlo, float4* nhi, in
   nhi[off_p + k] = hi;
 }
 
-// First candidate radius of every particle from the density of its leaf:
-// h0 = n_h (leaf box volume / leaf count)^(1/3), and the fixed h when h is
-// an input.
+// Absolute position of a sorted particle (FP32, the rounding of the node
+// boxes) from its lattice cell and its offset from the cell centre.
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (s >= S.n) return;
-  R r;
-  if (h_mode == 0) {
-    r = S.hbuf[s];
-  } else {
-    const int64_t leaf = s >> 6;
-    const float4 lo = S.nlo[leaf], hi = S.nhi[leaf];
-    const int64_t cnt = ((leaf + 1) * 64 < S.n ? (leaf + 1) * 64 : S.n) - leaf * 64;
-    const double pad = 0.5 * S.ell_d;  // a leaf of coincident lattice cells has no volume
-    const double vol = ((double)(hi.x - lo.x) + pad) * ((double)(hi.y - lo.y) + pad) *
-                       ((double)(hi.z - lo.z) + pad);
-    const double h0 = cbrt(S.n_h3 * vol / (double)cnt);
-    r = (R)fmin(h0, 0.45 * S.box);
-  }
-  S.rad[s] = r;
-  S.rlo[s] = R(0);
-  S.rhi[s] = R(0);
-  S.todo[s] = 1;
+__device__ inline void abs_pos(const State<R>& S, uint32_t c3, const R4<R>& p, float a[3]) {
+  const float ell = (float)S.ell;
+  a[0] = ((float)(c3 & 1023u) + 0.5f) * ell + (float)p.x;
+  a[1] = ((float)((c3 >> 10) & 1023u) + 0.5f) * ell + (float)p.y;
+  a[2] = ((float)(c3 >> 20) + 0.5f) * ell + (float)p.z;
 }
 
-__device__ inline float box_gap2(float4 alo, float4 ahi, float4 blo, float4 bhi, float L) {
-  const float al[3] = {alo.x, alo.y, alo.z}, ah[3] = {ahi.x, ahi.y, ahi.z};
-  const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
+// Squared periodic distance from point a to the box [lo, hi] (both in the
+// unit cell [0, L] up to rounding).
+__device__ inline float point_gap2(const float a[3], float4 lo, float4 hi, float L) {
+  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
   float g2 = 0.f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float best = 3e30f;
-#pragma unroll
-    for (int k = -1; k <= 1; ++k) {
-      const float sh = (float)k * L;
-      const float g = fmaxf(0.f, fmaxf(bl[a] + sh - ah[a], al[a] - (bh[a] + sh)));
-      best = fminf(best, g);
-    }
-    g2 += best * best;
+  for (int t = 0; t < 3; ++t) {
+    const float d1 = l[t] - a[t], d2 = a[t] - h[t];
+    float g = 0.f;
+    if (d1 > 0.f) g = fminf(d1, a[t] + L - h[t]);       // left of the box, or its image
+    else if (d2 > 0.f) g = fminf(d2, l[t] + L - a[t]);  // right of the box, or its image
+    g2 += g * g;
   }
   return g2;
 }
 
-// Stackless walk of the implicit binary tree for the wave's own leaf. A node
-// is entered when its box comes within radius of the leaf box, radius =
-// max(qr, node h_max) when use_node_h, else qr. f(leaf) is called for every
-// leaf reached. All control flow is wave-uniform.
-template <class R, class F>
-__device__ inline void tree_walk(const State<R>& S, int64_t wave, float qr, bool use_node_h,
-                                 F&& f) {
-  const float4 qlo = S.nlo[wave], qhi = S.nhi[wave];
-  const float L = (float)S.box;
+// Radius widened against the FP32 rounding of positions and node boxes.
+__device__ inline float pad_radius(float r, float L) { return r * 1.00001f + 4e-6f * L; }
+
+// Stackless walk of the implicit binary tree. A node is entered when
+// need(lo, hi) holds for any lane of the wave (each lane tests its own
+// sphere against the node box); f(leaf) is called for every leaf reached.
+// All control flow is wave-uniform.
+template <class R, class N, class F>
+__device__ inline void tree_walk(const State<R>& S, N&& need, F&& f) {
   const int top = S.nlevels - 1;
   int level = top, k = 0;
   while (true) {
     bool visit = false;
     if (k < S.lvl_cnt[level]) {
-      const float4 lo = S.nlo[S.lvl_off[level] + k], hi = S.nhi[S.lvl_off[level] + k];
-      float r = use_node_h ? fmaxf(qr, lo.w) : qr;
-      r = r * 1.00001f + 4e-6f * L;  // conservative against FP32 rounding of the boxes
-      visit = box_gap2(qlo, qhi, lo, hi, L) < r * r;
+      const int64_t node = S.lvl_off[level] + k;
+      visit = __ballot(need(S.nlo[node], S.nhi[node])) != 0ull;
     }
     if (visit && level > 0) {
       --level;
@@ -199,64 +179,141 @@ __device__ inline void leaf_tile(const State<R>& S, int64_t leaf, F&& f) {
   }
 }
 
-// Candidates of every unsolved particle within its own radius ri. When they
-// overflow the capacity, counts at seven smaller radii ri q^k (k = 1..7, down
-// to the largest radius rlo known to be too small for the h root, else by
-// 0.6 per step) give the largest radius that fits, which the next round uses.
-// Only when nothing above rlo fits is the capacity itself too small: the
-// count just above rlo is reported for the host to grow it.
+// First candidate radius of every particle, kept small so that the first
+// walk stays cheap (particles whose h root lies beyond it grow it in later
+// rounds): the least of the h that the target count would need at the
+// density of the particle's 8 nearest leaf-mates, n_h r_8 (4 pi / 24)^(1/3),
+// at the density of its leaf box, and 1.5x that of the mean density. The
+// caller's h is kept instead (x1.05) when it lies within a factor 2 of that
+// estimate (a previous step's h). With fixed h the radius is h.
 template <class R>
+__global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if ((s & ~(int64_t)63) >= S.n) return;
+  const bool active = s < S.n;
+  const int64_t sc = active ? s : 0;
+  const int64_t leaf = sc >> 6;
+  R r = S.hbuf[sc];
+  if (h_mode != 0) {
+    const R4<R> pi = S.pos4[sc];
+    const uint32_t ci = S.cell3[sc];
+    float d[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) d[t] = 3e30f;
+    leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
+      (void)mj;
+      if (j == (uint32_t)sc) return;
+      R x[3];
+      lattice_sep(S, pi, ci, pj, cj, x);
+      float v = (float)(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {  // keep the 8 smallest, sorted
+        const float lo = fminf(d[t], v);
+        v = fmaxf(d[t], v);
+        d[t] = lo;
+      }
+    });
+    const int64_t b = leaf * 64;
+    const int64_t cnt = (b + 64 < S.n ? b + 64 : S.n) - b;
+    const float4 lo = S.nlo[leaf], hi = S.nhi[leaf];
+    const double pad = 0.5 * S.ell_d;  // coincident lattice cells have no volume
+    const double vol = ((double)(hi.x - lo.x) + pad) * ((double)(hi.y - lo.y) + pad) *
+                       ((double)(hi.z - lo.z) + pad);
+    double est = cbrt(S.n_h3 * vol / (double)cnt);
+    if (cnt >= 9)  // (4 pi / 24)^(1/3)
+      est = fmin(est, cbrt(S.n_h3) * sqrt((double)d[7]) * 0.80599597700823482);
+    est = fmin(est, 1.5 * cbrt(S.n_h3 / (double)S.n) * S.box);
+    const double g = (double)r;
+    const double h0 = (g > 0.5 * est && g < 2.0 * est) ? 1.05 * g : est;
+    r = (R)fmin(h0, 0.45 * S.box);
+  }
+  if (active) {
+    S.rad[s] = r;
+    S.need[s] = S.scr_cap;
+    S.todo[s] = 1;
+  }
+}
+
+// Candidates of every unsolved particle within its own radius ri, written to
+// its scratch slot. A particle whose candidates overflow its capacity also
+// gets, from the same walk, the counts and the h-root test
+// f(r) = C (w(0) + sum_j (m_j/m_i) w(r_ij / r)) - n_h^3 > 0 at ri and at four
+// smaller radii ri 0.75^k: the next round uses the smallest of these radii
+// that holds the root, with exactly the capacity its count needs, or, when
+// none does, a radius grown from the count. With fixed h only the capacity
+// is raised. Sums over the candidates that did fit are taken afterwards from
+// the scratch, so particles that fit pay only for the counts.
+template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
-  constexpr int kBins = 7;
+  constexpr int kBins = 4;
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];
   const R ri = mine ? S.rad[sc] : R(0);
-  float qr = (float)ri;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) qr = fmaxf(qr, __shfl_xor(qr, o, 64));
-  qr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(qr)));
-  const int64_t wave = __builtin_amdgcn_readfirstlane((int)(s >> 6));
-  unsigned long long retry = 0, ovf = 0;
+  unsigned long long retry = 0;
   if (__ballot(mine) != 0ull) {
     const R4<R> pi = S.pos4[sc];
     const uint32_t ci = S.cell3[sc];
     const R mi_inv = R(1) / S.mass[sc];
     const R r2cap = ri * ri;
-    const int64_t qs = scratch_slot(S, sc);
-    const R lo = (mine && S.shrink) ? S.rlo[sc] : R(0);
-    const double q = lo > R(0) ? pow((double)lo / (double)ri, 1.0 / (kBins + 1)) : 0.6;
-    R rk[kBins], t2[kBins];
+    int cap = 0;
+    int64_t base = 0;
+    if (mine) base = scratch_base(S, sc, cap);
+    R rk[kBins], t2[kBins], ik[kBins], fk[kBins];
     int hk[kBins];
     {
-      double r = (double)ri;
+      R r = ri;
 #pragma unroll
       for (int k = 0; k < kBins; ++k) {
-        r *= q;
-        rk[k] = (R)r;
-        t2[k] = rk[k] * rk[k];
+        r *= R(0.75);
+        rk[k] = r;
+        t2[k] = r * r;
+        ik[k] = R(1) / r;
+        fk[k] = R(Shape<K>::w0);
         hk[k] = 0;
       }
     }
-    const int cap = S.scr_cap;
+    const R iri = mine ? R(1) / ri : R(0);
+    R fi = R(Shape<K>::w0);
+    // adds the f sums of one candidate at ri and at the smaller radii
+    auto add_sums = [&](R r, R mr) {
+      R w, dw;
+      Shape<K>::eval(r * iri, w, dw);
+      fi += mr * w;
+#pragma unroll
+      for (int k = 0; k < kBins; ++k) {
+        Shape<K>::eval(r * ik[k], w, dw);
+        fk[k] += mr * w;
+      }
+    };
     int cnt = 0;
     Stage4<R> sr, sm;
-    tree_walk(S, wave, qr, false, [&](int64_t leaf) {
+    float P[3];
+    abs_pos(S, ci, pi, P);
+    const float L = (float)S.box;
+    const float rp = mine ? pad_radius((float)ri, L) : -1.f;
+    const float rp2 = rp * rp;
+    auto need = [&](float4 lo, float4 hi) { return mine && point_gap2(P, lo, hi, L) < rp2; };
+    tree_walk(S, need, [&](int64_t leaf) {
       leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
         if (!mine || j == (uint32_t)s) return;
         R x[3];
         lattice_sep(S, pi, ci, pj, cj, x);
         const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         if (r2 < r2cap) {
+          const R r = Sc<R>::sqrt(r2);
+          const R mr = mj * mi_inv;
           if (cnt < cap) {
             const int slot = cnt & 3;
-            sr.put(slot, Sc<R>::sqrt(r2));
-            sm.put(slot, mj * mi_inv);
+            sr.put(slot, r);
+            sm.put(slot, mr);
             if (slot == 3) {
-              sr.flush(S.scr_r, qs, cap, cnt);
-              if (!S.equal_mass) sm.flush(S.scr_m, qs, cap, cnt);
+              sr.flush_at(S.scr_r, base, cnt);
+              if (!S.equal_mass) sm.flush_at(S.scr_m, base, cnt);
             }
+          } else if (S.shrink) {
+            add_sums(r, mr);
           }
           ++cnt;
 #pragma unroll
@@ -266,47 +323,58 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
     });
     if (mine) {
       if (cnt > cap && S.shrink) {
-        int kfit = -1;
+        for (int k = 0; k < cap; ++k) {  // the candidates that fitted
+          const int64_t e = slot_at(base, k);
+          add_sums(S.scr_r[e], S.equal_mass ? R(1) : S.scr_m[e]);
+        }
+        const R C = R(Shape<K>::C), n_h3 = R(S.n_h3);
+        R rs = R(0);
+        int ns = 0;
+        if (C * fi - n_h3 > R(0)) {
+          rs = ri;
+          ns = cnt;
+        }
 #pragma unroll
-        for (int k = kBins - 1; k >= 0; --k)
-          if (hk[k] <= cap) kfit = k;  // counts fall with k: the first fit is the largest
-        if (kfit >= 0) {
-          S.rad[s] = rk[kfit];
-          S.rhi[s] = kfit == 0 ? ri : rk[kfit - 1];
-        } else {
-          const R last = rk[kBins - 1];
-          S.rhi[s] = last;
-          if (lo > R(0) && last < R(1.01) * lo) {
-            S.rad[s] = last;  // fits once the capacity has grown
-            ovf = (unsigned long long)hk[kBins - 1];
-          } else {
-            S.rad[s] = lo > R(0) ? Sc<R>::sqrt(lo * last) : R(0.6) * last;
+        for (int k = 0; k < kBins; ++k)  // radii fall with k: keep the last one holding the root
+          if (C * fk[k] - n_h3 > R(0)) {
+            rs = rk[k];
+            ns = hk[k];
           }
+        if (rs > R(0)) {
+          S.rad[s] = rs;
+          S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
+        } else {  // the root lies beyond ri
+          const double g = grow_factor(S.n_h3, cnt);
+          S.rad[s] = (R)((double)ri * g);
+          S.need[s] = need_after_growth(cnt, g);
         }
         S.ccnt[s] = -1;
         retry = 1;
       } else if (cnt > cap) {
-        S.ccnt[s] = cap;  // fixed h: the host grows the capacity and reruns
-        ovf = (unsigned long long)cnt;
+        S.need[s] = (cnt + 3) & ~3;  // fixed h: exactly the capacity it needs
+        S.ccnt[s] = -1;
+        retry = 1;
       } else {
         if (cnt & 3) {
-          sr.flush(S.scr_r, qs, cap, cnt - 1);
-          if (!S.equal_mass) sm.flush(S.scr_m, qs, cap, cnt - 1);
+          sr.flush_at(S.scr_r, base, cnt - 1);
+          if (!S.equal_mass) sm.flush_at(S.scr_m, base, cnt - 1);
         }
         S.ccnt[s] = cnt;
       }
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    retry += __shfl_xor(retry, o, 64);
-    const unsigned long long a = __shfl_xor(ovf, o, 64);
-    ovf = a > ovf ? a : ovf;
-  }
-  if ((threadIdx.x & 63) == 0) {
-    if (retry) atomicAdd(&S.cnt[CNT_RETRY], retry);
-    if (ovf) atomicMax(&S.cnt[CNT_SCR_OVERFLOW], ovf);
-  }
+  for (int o = 32; o > 0; o >>= 1) retry += __shfl_xor(retry, o, 64);
+  if ((threadIdx.x & 63) == 0 && retry) atomicAdd(&S.cnt[CNT_RETRY], retry);
+}
+
+// Capacity of every group of 64 scratch slots, in chunk rows: the largest
+// request of the unsolved particles ranked into it (rows zeroed beforehand).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __restrict__ rows) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n || !S.todo[s]) return;
+  atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 3) >> 2));
 }
 
 // Symmetric neighbour lists r_ij < max(h_i, h_j) by a walk with node radius
@@ -325,7 +393,6 @@ __global__ void __launch_bounds__(kBlock) k_nlist_tree(State<R> S, uint32_t* __r
   const uint32_t ci = S.cell3[sc];
   const R hi2 = pi.w * pi.w;
   const int64_t wave = __builtin_amdgcn_readfirstlane((int)(s >> 6));
-  const float qr = S.nlo[wave].w;  // largest h of the wave's own leaf
   int ng = 0, ns = 0, cap = 0, scap = 0;
   int64_t gb = 0, sb = 0;
   if (FILL) {
@@ -335,7 +402,16 @@ __global__ void __launch_bounds__(kBlock) k_nlist_tree(State<R> S, uint32_t* __r
     sb = slot_base(S.srow[wave], s);
   }
   Stage4<uint32_t> sg, ss;
-  tree_walk(S, wave, qr, true, [&](int64_t leaf) {
+  float P[3];
+  abs_pos(S, ci, pi, P);
+  const float L = (float)S.box;
+  const float hl = active ? (float)(R(1) / pi.w) : -1.f;
+  // lane i needs node boxes within max(h_i, node h_max): r_ij < max(h_i, h_j)
+  auto need = [&](float4 lo, float4 hi) {
+    const float r = pad_radius(fmaxf(hl, lo.w), L);
+    return active && point_gap2(P, lo, hi, L) < r * r;
+  };
+  tree_walk(S, need, [&](int64_t leaf) {
     leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
       (void)mj;
       if (!active || j == (uint32_t)s) return;
@@ -413,8 +489,16 @@ void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s) {
 }
 
 template <class R>
-void launch_candidates_tree(const State<R>& S, hipStream_t s) {
-  hipLaunchKernelGGL(k_candidates_tree<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s) {
+  if (kernel == 0)
+    hipLaunchKernelGGL((k_candidates_tree<R, 0>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  else
+    hipLaunchKernelGGL((k_candidates_tree<R, 1>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+}
+
+template <class R>
+void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_rows<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, rows);
 }
 
 template <class R>
@@ -431,7 +515,8 @@ void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws,
   template void launch_tree_build<R>(const State<R>&, const R*, const int*, const int*,      \
                                      hipStream_t);                                           \
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
-  template void launch_candidates_tree<R>(const State<R>&, hipStream_t);                     \
+  template void launch_candidates_tree<R>(const State<R>&, int, hipStream_t);                \
+  template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
   template void launch_nlist_tree<R>(const State<R>&, bool, uint32_t*, uint32_t*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
