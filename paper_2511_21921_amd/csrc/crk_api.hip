@@ -295,7 +295,7 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) 
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(ncell + 1)), "alloc scan");
   CRK_HIP(hipMemsetAsync(ctx->cell_count.p, 0, 4 * (size_t)(ncell + 1), s), "memset");
   launch_keys(x, n, ctx->p.box, ctx->G, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
-              (uint32_t*)ctx->cell_count.p, s);
+              (uint32_t*)ctx->cell_count.p, (unsigned long long*)ctx->cnt.p, s);
   int bits = 1;
   while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
   CRK_HIP(radix_sort_pairs((uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
@@ -415,9 +415,11 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   return CRK_OK;
 }
 
-// Tree path neighbour lists with per-wave capacities: count walk, scan of the
-// per-wave chunk rows into offsets, then the fill walk into lists sized to
-// the total.
+// Tree path neighbour lists with per-wave capacities. Gather lists by one
+// walk, each wave sized from the candidate counts of the h solve (they hold
+// every r < h_i; 4 entries of room for rounding), rerun with the exact
+// counts if that falls short. Scatter-only lists by transposing the gather
+// lists: count, per-wave offsets, fill, sort.
 template <class R>
 crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
@@ -429,25 +431,48 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   uint32_t* ws = wg + nw + 1;
   uint32_t* lg = (uint32_t*)ctx->lrow.p;
   uint32_t* ls = lg + nw + 1;
-  CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
-  CRK_HIP(hipMemsetAsync(wg + nw, 0, 4, s), "memset");
-  CRK_HIP(hipMemsetAsync(ws + nw, 0, 4, s), "memset");
+  int* ng = (int*)ctx->ng.p;
+  int* ns = (int*)ctx->ns.p;
+  int* fillc = (int*)ctx->need.p;  // free once h is solved
+  // chunk rows per wave -> offsets -> host total; a row is 4 entries of 64 lanes
+  auto offsets = [&](const int* c, int extra, uint32_t* rows, uint32_t* off,
+                     uint32_t* host) -> hipError_t {
+    hipError_t e = hipMemsetAsync(rows + nw, 0, 4, s);
+    if (e != hipSuccess) return e;
+    launch_wave_rows(c, n, extra, rows, s);
+    e = exclusive_scan_u32(rows, off, nw + 1, (uint32_t*)ctx->scan_tmp.p, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host, off + nw, 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  };
   CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
-  {
-    State<R> S = make_state<R>(ctx, n);
-    launch_nlist_tree<R>(S, false, wg, ws, s);
+  CRK_HIP(offsets((const int*)ctx->ccnt.p, 4, wg, lg, &ctx->host_rows[0]), "list rows");
+  for (int attempt = 0;; ++attempt) {
+    CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8, s), "memset");
+    {
+      State<R> S = make_state<R>(ctx, n);
+      launch_gather_tree<R>(S, s);
+    }
+    CRK_HIP(hipGetLastError(), "neighbour list launch");
+    CRK_HIP(read_counters(ctx, s), "neighbour list");
+    if (!ctx->host_cnt[CNT_LIST_OVERFLOW]) break;
+    if (attempt == 1) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
+    CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");  // exact counts
   }
-  CRK_HIP(exclusive_scan_u32(wg, lg, nw + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
-  CRK_HIP(exclusive_scan_u32(ws, ls, nw + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
-  CRK_HIP(hipMemcpyAsync(&ctx->host_rows[0], lg + nw, 4, hipMemcpyDeviceToHost, s), "rows");
-  CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], ls + nw, 4, hipMemcpyDeviceToHost, s), "rows");
-  CRK_HIP(read_counters(ctx, s), "neighbour list");
-  // a row is one 4-entry chunk of all 64 lanes of a wave
-  CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
-  CRK_HIP(ensure(ctx->slist, 4 * 256 * (size_t)ctx->host_rows[1]), "alloc neighbour list");
+  CRK_HIP(hipMemsetAsync(ns, 0, 4 * (size_t)nw * 64, s), "memset");
   {
     State<R> S = make_state<R>(ctx, n);
-    launch_nlist_tree<R>(S, true, wg, ws, s);
+    launch_scatter_tree<R>(S, false, fillc, s);
+  }
+  CRK_HIP(offsets(ns, 0, ws, ls, &ctx->host_rows[1]), "list rows");
+  CRK_HIP(ensure(ctx->slist, 4 * 256 * (size_t)ctx->host_rows[1]), "alloc neighbour list");
+  CRK_HIP(hipMemsetAsync(fillc, 0, 4 * (size_t)nw * 64, s), "memset");
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_scatter_tree<R>(S, true, fillc, s);
   }
   CRK_HIP(tend(ctx, P_NLIST, s), "event");
   CRK_HIP(hipGetLastError(), "neighbour list launch");
@@ -493,6 +518,16 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
     crk_status st = build_cells<R>(ctx, s, n, x);
     if (st != CRK_OK) return st;
+    if (P.search == 0 && attempt == 0) {
+      // a cell holding more than 1024 particles means strong clustering:
+      // the cell list would need huge candidate lists there
+      CRK_HIP(read_counters(ctx, s), "cell occupancy");
+      if (ctx->host_cnt[CNT_CELL_MAX] > 1024) {
+        use_tree = true;
+        CRK_HIP(tend(ctx, P_CELLS, s), "event");
+        break;
+      }
+    }
     {
       State<R> S = make_state<R>(ctx, n);
       launch_gather<R>(S, x, v, m, u, h, s);

@@ -81,21 +81,25 @@ __device__ inline double wrap_pos(double xa, double L) {
 __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, int64_t n,
                                                  double L, int G, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals,
-                                                 uint32_t* __restrict__ ccount) {
+                                                 uint32_t* __restrict__ ccount,
+                                                 unsigned long long* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double inv = (double)G / L;
-  int c[3];
+  unsigned long long occ = 0;
+  if (i < n) {
+    const double inv = (double)G / L;
+    int c[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double t = wrap_pos(x[a * n + i], L);
-    int k = (int)(t * inv);
-    c[a] = k < G ? k : G - 1;
+    for (int a = 0; a < 3; ++a) {
+      const double t = wrap_pos(x[a * n + i], L);
+      int k = (int)(t * inv);
+      c[a] = k < G ? k : G - 1;
+    }
+    const uint32_t key = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+    occ = (unsigned long long)atomicAdd(&ccount[key], 1u) + 1ull;  // occupancy so far
   }
-  const uint32_t key = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
-  keys[i] = key;
-  vals[i] = (uint32_t)i;
-  atomicAdd(&ccount[key], 1u);
+  wave_max_u64(&cnt[CNT_CELL_MAX], occ);
 }
 
 template <class R>
@@ -849,9 +853,9 @@ void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned
 }
 
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
-                 uint32_t* cell_count, hipStream_t s) {
+                 uint32_t* cell_count, unsigned long long* cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys, vals,
-                     cell_count);
+                     cell_count, cnt);
 }
 
 template <class R>

@@ -13,7 +13,7 @@ void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned
 
 // Cell keys of wrapped positions, identity values, and per-cell counts.
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
-                 uint32_t* cell_count, hipStream_t s);
+                 uint32_t* cell_count, unsigned long long* cnt, hipStream_t s);
 
 // Morton keys over the 1024^3 lattice (tree path) and identity values.
 void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint32_t* vals,
@@ -29,7 +29,10 @@ void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s);
 template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 template <class R>
-void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws, hipStream_t s);
+void launch_gather_tree(const State<R>& S, hipStream_t s);
+void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s);
+template <class R>
+void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s);
 
 // Gather caller arrays into cell-sorted SoA with cell-centre offsets.
 template <class R>

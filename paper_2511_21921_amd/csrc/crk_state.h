@@ -20,11 +20,12 @@ enum Counter {
   CNT_SLIST_OVERFLOW,  // largest scatter-only count beyond its capacity
   CNT_MMAX_BITS,       // max mass as double bits
   CNT_MINVMAX_BITS,    // max 1/mass as double bits
-  CNT_RETRY,           // particles whose candidate radius shrank (tree path)
+  CNT_RETRY,           // particles that need another candidate round (tree path)
   CNT_SINGULAR,
   CNT_RELAXED,
   CNT_NONFINITE,
   CNT_HMAX_OUT_BITS,   // max solved h as double bits
+  CNT_CELL_MAX,        // largest cell occupancy of the cell list
   CNT_COUNT
 };
 

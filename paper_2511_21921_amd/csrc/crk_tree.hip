@@ -377,14 +377,12 @@ __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __re
   atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 3) >> 2));
 }
 
-// Symmetric neighbour lists r_ij < max(h_i, h_j) by a walk with node radius
-// max(own leaf h_max, node h_max). Two passes over the same walk: COUNT stores
-// the list lengths and every wave's capacity in chunk rows (its longest list,
-// rounded up to 4 entries); after a scan of those into S.grow / S.srow, FILL
-// writes the entries. Both passes visit the same pairs in the same order.
-template <class R, bool FILL>
-__global__ void __launch_bounds__(kBlock) k_nlist_tree(State<R> S, uint32_t* __restrict__ wg,
-                                                       uint32_t* __restrict__ ws) {
+// Gather lists r_ij < h_i by a walk with each lane's own h. Every wave's
+// capacity (S.grow) comes from an upper bound of its counts; the counts are
+// stored in full, so an overflow (the host checks the largest) can be
+// rerun with exact capacities. Entries come in ascending j.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_gather_tree(State<R> S) {
   const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if ((s & ~(int64_t)63) >= S.n) return;  // whole wave past the end: it has no leaf
   const bool active = s < S.n;
@@ -392,25 +390,17 @@ __global__ void __launch_bounds__(kBlock) k_nlist_tree(State<R> S, uint32_t* __r
   const R4<R> pi = S.pos4[sc];
   const uint32_t ci = S.cell3[sc];
   const R hi2 = pi.w * pi.w;
-  const int64_t wave = __builtin_amdgcn_readfirstlane((int)(s >> 6));
-  int ng = 0, ns = 0, cap = 0, scap = 0;
-  int64_t gb = 0, sb = 0;
-  if (FILL) {
-    cap = (int)(S.grow[wave + 1] - S.grow[wave]) * 4;
-    scap = (int)(S.srow[wave + 1] - S.srow[wave]) * 4;
-    gb = slot_base(S.grow[wave], s);
-    sb = slot_base(S.srow[wave], s);
-  }
-  Stage4<uint32_t> sg, ss;
+  const int64_t wave = sc >> 6;
+  const int cap = (int)(S.grow[wave + 1] - S.grow[wave]) * 4;
+  const int64_t gb = slot_base(S.grow[wave], sc);
+  int ng = 0;
+  Stage4<uint32_t> sg;
   float P[3];
   abs_pos(S, ci, pi, P);
   const float L = (float)S.box;
-  const float hl = active ? (float)(R(1) / pi.w) : -1.f;
-  // lane i needs node boxes within max(h_i, node h_max): r_ij < max(h_i, h_j)
-  auto need = [&](float4 lo, float4 hi) {
-    const float r = pad_radius(fmaxf(hl, lo.w), L);
-    return active && point_gap2(P, lo, hi, L) < r * r;
-  };
+  const float rp = active ? pad_radius((float)(R(1) / pi.w), L) : -1.f;
+  const float rp2 = rp * rp;
+  auto need = [&](float4 lo, float4 hi) { return active && point_gap2(P, lo, hi, L) < rp2; };
   tree_walk(S, need, [&](int64_t leaf) {
     leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
       (void)mj;
@@ -418,53 +408,108 @@ __global__ void __launch_bounds__(kBlock) k_nlist_tree(State<R> S, uint32_t* __r
       R x[3];
       lattice_sep(S, pi, ci, pj, cj, x);
       const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-      const uint32_t e = j << kCodeBits;
       if (r2 * hi2 < R(1)) {
-        if (FILL && ng < cap) {
-          sg.put(ng & 3, e);
+        if (ng < cap) {
+          sg.put(ng & 3, j << kCodeBits);
           if ((ng & 3) == 3) sg.flush_at(S.nlist, gb, ng);
         }
         ++ng;
-      } else if (r2 * (pj.w * pj.w) < R(1)) {
-        if (FILL && ns < scap) {
-          ss.put(ns & 3, e);
-          if ((ns & 3) == 3) ss.flush_at(S.slist, sb, ns);
-        }
-        ++ns;
       }
     });
   });
-  if (FILL) {
-    if (active) {
-      const int gst = ng < cap ? ng : cap, sst = ns < scap ? ns : scap;
-      if (gst & 3) sg.flush_at(S.nlist, gb, gst - 1);
-      if (sst & 3) ss.flush_at(S.slist, sb, sst - 1);
-    }
-    return;
-  }
-  unsigned long long g = 0, f = 0;
-  int mg = 0, ms = 0;
+  unsigned long long g = 0, ovf = 0;
   if (active) {
+    const int st = ng < cap ? ng : cap;
+    if (st & 3) sg.flush_at(S.nlist, gb, st - 1);
     S.ng[s] = ng;
-    S.ns[s] = ns;
     g = (unsigned long long)ng;
-    f = (unsigned long long)(ng + ns);
-    mg = ng;
-    ms = ns;
+    if (ng > cap) ovf = (unsigned long long)ng;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     g += __shfl_xor(g, o, 64);
-    f += __shfl_xor(f, o, 64);
-    mg = max(mg, __shfl_xor(mg, o, 64));
-    ms = max(ms, __shfl_xor(ms, o, 64));
+    const unsigned long long a = __shfl_xor(ovf, o, 64);
+    ovf = a > ovf ? a : ovf;
   }
   if ((threadIdx.x & 63) == 0) {
-    wg[wave] = (uint32_t)((mg + 3) >> 2);
-    ws[wave] = (uint32_t)((ms + 3) >> 2);
     if (g) atomicAdd(&S.cnt[CNT_PAIRS_GATHER], g);
-    if (f) atomicAdd(&S.cnt[CNT_PAIRS_FORCE], f);
+    if (ovf) atomicMax(&S.cnt[CNT_LIST_OVERFLOW], ovf);
   }
+}
+
+// Per-wave capacity in chunk rows from per-particle counts: the largest of
+// its lanes' cnt[s] + extra, rounded up to 4 entries.
+__global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cnt, int64_t n,
+                                                      int extra, uint32_t* __restrict__ rows) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if ((s & ~(int64_t)63) >= n) return;
+  int c = s < n ? cnt[s] + extra : 0;
+  c = c > 0 ? c : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_xor(c, o, 64));
+  if ((threadIdx.x & 63) == 0) rows[s >> 6] = (uint32_t)((c + 3) >> 2);
+}
+
+// Scatter-only part of the symmetric list by transposing the gather lists:
+// j belongs to i's scatter-only list when i is in j's gather list
+// (r_ij < h_j) but j is not in i's (r_ij >= h_i). The separation is the same
+// expression with both signs flipped, so r_ij^2 is bit-identical from both
+// sides. COUNT adds to ns[i]; FILL appends j at fillc[i] (unordered, sorted
+// afterwards).
+template <class R, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __restrict__ fillc) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= S.n) return;
+  const R4<R> pj = S.pos4[s];
+  const uint32_t cj = S.cell3[s];
+  const int64_t w = s >> 6;
+  const int ng = S.ng[s];
+  const int64_t gb = slot_base(S.grow[w], s);
+  for (int k = 0; k < ng; ++k) {
+    const uint32_t i = S.nlist[slot_at(gb, k)] >> kCodeBits;
+    const R4<R> pi = S.pos4[i];
+    R x[3];
+    lattice_sep(S, pi, S.cell3[i], pj, cj, x);
+    const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    if (!(r2 * (pi.w * pi.w) < R(1))) {
+      if (FILL) {
+        const int t = atomicAdd(&fillc[i], 1);
+        const int64_t wi = (int64_t)(i >> 6);
+        const int scap = (int)(S.srow[wi + 1] - S.srow[wi]) * 4;
+        if (t < scap) S.slist[slot_at(slot_base(S.srow[wi], i), t)] = (uint32_t)s << kCodeBits;
+      } else {
+        atomicAdd(&S.ns[i], 1);
+      }
+    }
+  }
+}
+
+// Sorts every scatter-only list by j (insertion sort; the lists are short),
+// giving the order a walk would produce and making runs reproducible; counts
+// the force pairs.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S) {
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long f = 0;
+  if (s < S.n) {
+    const int64_t w = s >> 6;
+    const int scap = (int)(S.srow[w + 1] - S.srow[w]) * 4;
+    const int ns = S.ns[s] < scap ? S.ns[s] : scap;
+    const int64_t sb = slot_base(S.srow[w], s);
+    for (int a = 1; a < ns; ++a) {
+      const uint32_t v = S.slist[slot_at(sb, a)];
+      int b = a - 1;
+      while (b >= 0 && S.slist[slot_at(sb, b)] > v) {
+        S.slist[slot_at(sb, b + 1)] = S.slist[slot_at(sb, b)];
+        --b;
+      }
+      S.slist[slot_at(sb, b + 1)] = v;
+    }
+    f = (unsigned long long)(S.ng[s] + S.ns[s]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
+  if ((threadIdx.x & 63) == 0 && f) atomicAdd(&S.cnt[CNT_PAIRS_FORCE], f);
 }
 
 }  // namespace
@@ -502,13 +547,24 @@ void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s) {
 }
 
 template <class R>
-void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws, hipStream_t s) {
-  if (fill)
-    hipLaunchKernelGGL((k_nlist_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, wg,
-                       ws);
-  else
-    hipLaunchKernelGGL((k_nlist_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, wg,
-                       ws);
+void launch_gather_tree(const State<R>& S, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_tree<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+}
+
+void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_wave_rows, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, extra, rows);
+}
+
+template <class R>
+void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s) {
+  if (fill) {
+    hipLaunchKernelGGL((k_scatter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
+                       fillc);
+    hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  } else {
+    hipLaunchKernelGGL((k_scatter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
+                       fillc);
+  }
 }
 
 #define CRK_INSTANTIATE_TREE(R)                                                               \
@@ -517,7 +573,8 @@ void launch_nlist_tree(const State<R>& S, bool fill, uint32_t* wg, uint32_t* ws,
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
   template void launch_candidates_tree<R>(const State<R>&, int, hipStream_t);                \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
-  template void launch_nlist_tree<R>(const State<R>&, bool, uint32_t*, uint32_t*, hipStream_t);
+  template void launch_gather_tree<R>(const State<R>&, hipStream_t);                         \
+  template void launch_scatter_tree<R>(const State<R>&, bool, int*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
 CRK_INSTANTIATE_TREE(double)
