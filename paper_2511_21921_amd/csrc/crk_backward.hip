@@ -121,7 +121,7 @@ __device__ inline void load_mom(const AdjState<R>& G, int64_t j, R mb[40]) {
 // Loss weights gathered into sorted order.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_bwd_prep(State<R> S, AdjState<R> G) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const uint32_t q = S.perm[s];
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_prep(State<R> S, AdjState<R> G) 
 // ------------------------------------------------------------------ B1+B2 --
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   double pa = 0.0, pb = 0.0;
   if (s < S.n) {
     const int64_t n = S.n;
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
 // --------------------------------------------------------------------- B3 --
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> G) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const R4<R> pi = S.pos4[s];
@@ -323,7 +323,7 @@ __device__ inline void moments_raw(const State<R>& S, int64_t s, double raw[40])
 
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_corr(State<R> S, AdjState<R> G) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   double raw[40];
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_corr(State<R> S, AdjState<R> G) 
 // ------------------------------------------------------------------ B5+B6 --
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> G, int h_mode) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const R4<R> pi = S.pos4[s];
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
 // --------------------------------------------------------------------- B7 --
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const R4<R> pi = S.pos4[s];
@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_unpermute(State<R> S, AdjState<R
                                                           double* __restrict__ g_x,
                                                           double* __restrict__ g_v,
                                                           double* __restrict__ g_u) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const uint32_t p = S.perm[s];

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h
                                                          const R* __restrict__ m,
                                                          const R* __restrict__ u, int64_t n,
                                                          unsigned long long* cnt) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = particle_id();
   unsigned long long hb = 0, bad = 0, mb = 0, ib = 0;
   if (i < n) {
     const double hv = (double)h[i], mv = (double)m[i];
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, i
                                                  uint32_t* __restrict__ vals,
                                                  uint32_t* __restrict__ ccount,
                                                  unsigned long long* __restrict__ cnt) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = particle_id();
   unsigned long long occ = 0;
   if (i < n) {
     const double inv = (double)G / L;
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
                                                    const R* __restrict__ m,
                                                    const R* __restrict__ u,
                                                    const R* __restrict__ h) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
   const uint32_t p = S.perm[s];
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
   const R4<R> pi = S.pos4[sc];
@@ -226,7 +226,7 @@ __device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h,
 
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
   // tree path: only particles still to solve, whose candidate pass fitted
   const bool work = s < S.n && (!S.todo || (S.todo[s] && S.ccnt[s] >= 0));
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
 // Fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included.
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
   const R h = S.hbuf[s];
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_out,
                                                  R* __restrict__ V_out) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const R h = S.hbuf[s], V = S.Vbuf[s];
   S.pos4[s].w = R(1) / h;
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   unsigned long long g = 0, f = 0, ovf = 0, sovf = 0;
   if (s < S.n) {
     const R4<R> pi = S.pos4[s];
@@ -553,7 +553,7 @@ __device__ inline void store_kc(const State<R>& S, int64_t s, const Corr64& c) {
 
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   unsigned long long sing = 0;
   if (s < S.n) {
     Moments<R> M;
@@ -638,7 +638,7 @@ __device__ inline void load_gv(const State<R>& S, int64_t j, R gv[9], R& relaxed
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ rho_out,
                                                     R* __restrict__ gradv_out) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   unsigned long long nrel = 0;
   if (s < S.n) {
     const R4<R> pi = S.pos4[s];
@@ -745,7 +745,7 @@ __device__ inline void side_grad(const KC<R>& k, const R x[3], R r2, R rinv, R h
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict__ accel,
                                                   double* __restrict__ dudt) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
@@ -833,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, int64_t na,
                                                       unsigned long long* cnt) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = particle_id();
   unsigned long long bad = 0;
   if (i < na) {
     const double v = (double)a[i];

@@ -244,6 +244,18 @@ __device__ inline void pair_x(const State<R>& S, int64_t s, const R4<R>& pi, con
   x[2] = (pi.z - pj.z) + R(d[2]) * S.ell;
 }
 
+// Index of this thread's particle, with the block index remapped so that
+// each of the 8 XCDs (which receive blocks round-robin, block b on XCD
+// b mod 8) processes one contiguous eighth of the blocks: particles that
+// are close in the sorted order, and so share neighbours, then share that
+// XCD's L2 instead of being fetched by all eight.
+__device__ inline int64_t particle_id() {
+  const int64_t B = gridDim.x, b = blockIdx.x;
+  const int64_t q = B >> 3, r = B & 7, x = b & 7, i = b >> 3;
+  const int64_t blk = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+  return blk * kBlock + threadIdx.x;
+}
+
 // Tree path radius growth when the h root lies beyond the radius: by the
 // factor that would bring the candidate count to the target (4 pi / 3) n_h^3
 // at the density seen, x1.1, kept within [1.25, 4].

@@ -34,7 +34,7 @@ __device__ inline double wrap01(double xa, double L) {
 __global__ void __launch_bounds__(kBlock) k_morton(const double* __restrict__ x, int64_t n,
                                                    double L, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = particle_id();
   if (i >= n) return;
   const double inv = 1024.0 / L;
   uint32_t c[3];
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k_morton(const double* __restrict__ x,
 // Leaf boxes (absolute positions, FP32) and the largest h of each leaf.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __restrict__ h) {
-  const int64_t leaf = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t leaf = particle_id();
   const int nleaf = S.lvl_cnt[0];
   if (leaf >= nleaf) return;
   const int64_t b = leaf * 64, e = (b + 64 < S.n) ? b + 64 : S.n;
@@ -188,7 +188,7 @@ __device__ inline void leaf_tile(const State<R>& S, int64_t leaf, F&& f) {
 // estimate (a previous step's h). With fixed h the radius is h.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if ((s & ~(int64_t)63) >= S.n) return;
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
   constexpr int kBins = 4;
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
 // request of the unsolved particles ranked into it (rows zeroed beforehand).
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __restrict__ rows) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n || !S.todo[s]) return;
   atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 3) >> 2));
 }
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __re
 // rerun with exact capacities. Entries come in ascending j.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_gather_tree(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if ((s & ~(int64_t)63) >= S.n) return;  // whole wave past the end: it has no leaf
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_tree(State<R> S) {
 // its lanes' cnt[s] + extra, rounded up to 4 entries.
 __global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cnt, int64_t n,
                                                       int extra, uint32_t* __restrict__ rows) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if ((s & ~(int64_t)63) >= n) return;
   int c = s < n ? cnt[s] + extra : 0;
   c = c > 0 ? c : 0;
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cn
 // afterwards).
 template <class R, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __restrict__ fillc) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   if (s >= S.n) return;
   const R4<R> pj = S.pos4[s];
   const uint32_t cj = S.cell3[s];
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __rest
 // the force pairs.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S) {
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s = particle_id();
   unsigned long long f = 0;
   if (s < S.n) {
     const int64_t w = s >> 6;
