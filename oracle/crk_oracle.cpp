@@ -659,15 +659,23 @@ int prepare(const Params& P, int64_t n, const double* x, const double* m, const 
     std::vector<int64_t> nb;
     S.F.within(i, S.h[i], nb);
     S.lists.gather[i] = nb;
-    S.F.within(i, std::max(S.h[i], hmax), nb);
+  }
+  // Symmetric lists, r_ij < max(h_i, h_j): j is in i's list exactly when
+  // j is in i's gather list (r_ij < h_i) or i is in j's (r_ij < h_j). The
+  // second part is the transpose of the gather lists; min_image gives the
+  // same r_ij^2 from both sides. Ascending j, self excluded.
+  std::vector<std::vector<int64_t>> incoming(n);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i : S.lists.gather[j])
+      if (i != j) incoming[i].push_back(j);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
     std::vector<int64_t> sy;
-    double d[3], s[3];
-    for (int64_t j : nb) {
-      if (j == i) continue;
-      double r2 = min_image(S.X.data(), n, i, j, L, d, s);
-      double R = std::max(S.h[i], S.h[j]);
-      if (r2 < R * R) sy.push_back(j);
-    }
+    for (int64_t j : S.lists.gather[i])
+      if (j != i) sy.push_back(j);
+    sy.insert(sy.end(), incoming[i].begin(), incoming[i].end());
+    std::sort(sy.begin(), sy.end());
+    sy.erase(std::unique(sy.begin(), sy.end()), sy.end());
     S.lists.sym[i] = sy;
   }
   return 0;
