@@ -1,0 +1,105 @@
+"""Oracle values of sampled particles of a large set, computed one by one.
+
+The forward outputs of particle i depend only on particles within a few
+smoothing lengths: its force neighbours j (r_ij < max(h_i, h_j)), their and
+its own gather neighbours k (r < h), and the gather neighbourhoods that fix
+h_k and V_k. The oracle is run on the union of balls around the sampled
+particles; a sample is accepted only when every particle on that chain has
+its whole gather neighbourhood inside the subset, so its oracle values equal
+those of the full set exactly (the oracle's own subset h is self-checking:
+a missing neighbour could only make it larger). Balls that fail are widened.
+"""
+import numpy as np
+from scipy.spatial import cKDTree
+
+import oracle
+
+
+def _dependency_set(tree_sub, xs, h, i):
+    """Indices (into the subset) whose h and gather neighbourhoods i depends on."""
+    hi = h[i]
+    cand = tree_sub.query_ball_point(xs[i], h.max())
+    d = xs[cand] - xs[i]
+    d -= np.round(d)
+    r = np.sqrt((d * d).sum(1))
+    cand = np.asarray(cand)
+    force = cand[(r < np.maximum(hi, h[cand]))]
+    first = np.union1d(force, [i])
+    dep = set(first.tolist())
+    for j in first:
+        dep.update(tree_sub.query_ball_point(xs[j], h[j]))
+    return np.fromiter(dep, dtype=np.int64)
+
+
+def complete_subsets(ps, samples, params, grow=1.5, max_rounds=6, start=4.0, want=None,
+                     max_size=None):
+    """For sampled indices, balls of the full set on which the oracle's outputs
+    at the sample are exact, and those outputs.
+
+    samples are tried in order; with want, the first `want` that complete
+    within max_size particles are kept (a candidate deep in a very massive
+    clump would need a subset the oracle takes minutes on).
+    Returns (kept samples, list of subset index arrays, dict of sample outputs
+    with the samples on the last axis)."""
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    tree = cKDTree(x, boxsize=1.0)
+    k = min(65, ps.n)
+    r64 = tree.query(x[samples], k=k)[0][:, k - 1]
+    kept, subsets, per = [], [], []
+    for s_idx, g in enumerate(samples):
+        if want is not None and len(kept) == want:
+            break
+        radius = start * r64[s_idx]
+        for _ in range(max_rounds):
+            sub = np.asarray(tree.query_ball_point(x[g], radius), dtype=np.int64)
+            if max_size is not None and sub.size > max_size:
+                break
+            h0 = ps.h[sub]
+            if params.h_mode == 1:
+                # starting guess only (the root does not depend on it): the
+                # distance to the 64th nearest particle, from the positions
+                h0 = tree.query(x[sub], k=k)[0][:, k - 1] * ps.box
+            o = oracle.forward(ps.x[:, sub], ps.v[:, sub], ps.m[sub], ps.u[sub], h0, params,
+                               nbr_mode=1)
+            xs = x[sub]
+            h = o["h"] / ps.box
+            tsub = cKDTree(xs, boxsize=1.0)
+            i = int(np.nonzero(sub == g)[0][0])
+            dep = _dependency_set(tsub, xs, h, i)
+            # complete: the full set has no particle within h_q of q that the subset lacks
+            nfull = tree.query_ball_point(xs[dep], h[dep] * (1 + 1e-9), return_length=True)
+            nsub = tsub.query_ball_point(xs[dep], h[dep] * (1 + 1e-9), return_length=True)
+            if np.all(nfull == nsub):
+                kept.append(g)
+                subsets.append(sub)
+                per.append({key: v[..., i] for key, v in o.items()
+                            if isinstance(v, np.ndarray) and v.shape[-1:] == (sub.size,)})
+                break
+            radius *= grow
+        else:
+            raise RuntimeError("sampled oracle: sample %d still incomplete" % g)
+    if want is not None and len(kept) < want:
+        raise RuntimeError("sampled oracle: only %d of %d samples completed" % (len(kept), want))
+    out = {key: np.stack([p[key] for p in per], axis=-1) for key in per[0]}
+    return np.asarray(kept, dtype=np.int64), subsets, out
+
+
+def localized_jvp(ps, samples, subsets, params, w_a, w_u, dirs):
+    """Oracle directional derivative of L = sum_{i in samples} w_a_i . a_i + w_u_i du_i/dt.
+
+    Every sample's outputs are exact on the union U of its complete subsets,
+    and depend on no particle outside U, so the oracle's JVP on U along a
+    direction supported on U equals the JVP of the full set. dirs(U) gives
+    (dx, dv, du, dalpha, dbeta) on U. Returns (jvp, U, the direction)."""
+    U = np.unique(np.concatenate(subsets))
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    tree = cKDTree(x, boxsize=1.0)
+    h0 = ps.h[U]
+    if params.h_mode == 1:
+        k = min(65, ps.n)
+        h0 = tree.query(x[U], k=k)[0][:, k - 1] * ps.box
+    d = dirs(U)
+    j = oracle.jvp(ps.x[:, U], ps.v[:, U], ps.m[U], ps.u[U], h0, params, *d, nbr_mode=1)
+    pos = np.searchsorted(U, samples)
+    val = float((w_a * j["d_accel"][:, pos]).sum() + (w_u * j["d_dudt"][pos]).sum())
+    return val, U, d
