@@ -131,7 +131,7 @@ __host__ __device__ inline void corr_adj(const KC<R>& k, const R x[3], R r, R ri
 
 template <class R>
 struct AVFwd {
-  R gix[3], gjx[3], nn, dd, s2, phi, vp[3], vpx, Di, Dj, mui, muj;
+  R gix[3], gjx[3], nn, dd, s2, phi, vp[3], vpx, Di, Dj, iDi, iDj, mui, muj;
   bool phi_active, mui_on, muj_on;
 };
 
@@ -150,7 +150,7 @@ __host__ __device__ inline void av_fwd(const R gvi[9], const R gvj[9], const R v
   o.phi = R(0);
   o.phi_active = false;
   if (o.s2 > R(0)) {
-    const R p = R(4) * o.nn * o.dd / o.s2;
+    const R p = Sc<R>::div(R(4) * o.nn * o.dd, o.s2);
     o.phi = p < R(0) ? R(0) : (p > R(1) ? R(1) : p);
     o.phi_active = p > R(0) && p < R(1);
   }
@@ -159,7 +159,9 @@ __host__ __device__ inline void av_fwd(const R gvi[9], const R gvj[9], const R v
   o.vpx = o.vp[0] * x[0] + o.vp[1] * x[1] + o.vp[2] * x[2];
   o.Di = r2 + eps2 * hi * hi;
   o.Dj = r2 + eps2 * hj * hj;
-  const R mi = o.vpx * hi / o.Di, mj = o.vpx * hj / o.Dj;
+  o.iDi = Sc<R>::rcp(o.Di);
+  o.iDj = Sc<R>::rcp(o.Dj);
+  const R mi = o.vpx * hi * o.iDi, mj = o.vpx * hj * o.iDj;
   o.mui_on = mi < R(0);
   o.muj_on = mj < R(0);
   o.mui = o.mui_on ? mi : R(0);
@@ -171,9 +173,9 @@ __host__ __device__ inline void av_fwd(const R gvi[9], const R gvj[9], const R v
 template <class R>
 struct PairSide {
   KC<R> kc;      // packed corrections (plain when the pair is relaxed)
-  R hinv, h, V, rho, P, c, m;
+  R hinv, h, V, rho, P, c;
   R v[3], gv[9];
-  R wa[3], wu;   // loss weights
+  R wam[3], wum;  // loss weights over the mass: w_a / m and w_u / (2 m)
 };
 
 template <class A>
@@ -214,9 +216,9 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   const R Qj = J.rho * (-alpha * J.c * av.muj + beta * av.muj * av.muj);
   const R Pi = I.P + J.P + Qi + Qj;
   const R sig = R(-0.5) * I.V * J.V * Pi;
-  const R lam = I.wu / (R(2) * I.m) + J.wu / (R(2) * J.m);
+  const R lam = I.wum + J.wum;
   R w[3];
-  for (int a = 0; a < 3; ++a) w[a] = I.wa[a] / I.m - J.wa[a] / J.m - vij[a] * lam;
+  for (int a = 0; a < 3; ++a) w[a] = I.wam[a] - J.wam[a] - vij[a] * lam;
   // L = sig G.w
   const R gsig = G[0] * w[0] + G[1] * w[1] + G[2] * w[2];
   for (int a = 0; a < 3; ++a) ob.v[a] += (A)(-lam * sig * G[a]);  // explicit v_ij in w
@@ -234,11 +236,11 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   }
   if (av.muj_on) mubar_j = Pibar * J.rho * (-alpha * J.c + R(2) * beta * av.muj);
   // mu_k = vpx h_k / D_k, D_k = r^2 + eps2 h_k^2
-  const R vpxbar = mubar_i * I.h / av.Di + mubar_j * J.h / av.Dj;
-  const R r2bar = -(mubar_i * av.vpx * I.h / (av.Di * av.Di) +
-                    mubar_j * av.vpx * J.h / (av.Dj * av.Dj));
+  const R vpxbar = mubar_i * I.h * av.iDi + mubar_j * J.h * av.iDj;
+  const R r2bar = -(mubar_i * av.vpx * I.h * av.iDi * av.iDi +
+                    mubar_j * av.vpx * J.h * av.iDj * av.iDj);
   // d mu_i / d h_i, with h = 1/hinv
-  ob.h += (A)(mubar_i * av.vpx * (r2 - eps2 * I.h * I.h) / (av.Di * av.Di));
+  ob.h += (A)(mubar_i * av.vpx * (r2 - eps2 * I.h * I.h) * av.iDi * av.iDi);
   R xb[3];
   for (int a = 0; a < 3; ++a) xb[a] = R(2) * r2bar * x[a] + vpxbar * av.vp[a];
   R vpb[3] = {vpxbar * x[0], vpxbar * x[1], vpxbar * x[2]};
@@ -250,9 +252,9 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   for (int a = 0; a < 3; ++a) gixb[a] = gjxb[a] = R(-0.5) * av.phi * vpb[a];
   if (av.phi_active) {
     const R s = av.nn + av.dd;
-    const R s3 = s * s * s;
-    const R nnb = phibar * R(4) * av.dd * (av.dd - av.nn) / s3;
-    const R ddb = phibar * R(4) * av.nn * (av.nn - av.dd) / s3;
+    const R is3 = Sc<R>::rcp(s * s * s);
+    const R nnb = phibar * R(4) * av.dd * (av.dd - av.nn) * is3;
+    const R ddb = phibar * R(4) * av.nn * (av.nn - av.dd) * is3;
     for (int a = 0; a < 3; ++a) {
       xb[a] += nnb * av.gix[a] + ddb * av.gjx[a];
       gixb[a] += nnb * x[a];

@@ -75,19 +75,18 @@ __device__ inline void load_side(const State<R>& S, const AdjState<R>& G, int64_
   load_kc4(S, j, o.kc);
   load_gv4(S, j, o.gv, relaxed);
   o.hinv = p.w;
-  o.h = R(1) / p.w;
+  o.h = Sc<R>::rcp(p.w);
   o.V = v.w;
   o.rho = st.x;
   o.P = st.y;
   o.c = st.z;
-  o.m = S.mass[j];
   o.v[0] = v.x;
   o.v[1] = v.y;
   o.v[2] = v.z;
-  o.wa[0] = w.x;
-  o.wa[1] = w.y;
-  o.wa[2] = w.z;
-  o.wu = w.w;
+  o.wam[0] = w.x;
+  o.wam[1] = w.y;
+  o.wam[2] = w.z;
+  o.wum = w.w;
 }
 
 template <class R>
@@ -125,11 +124,13 @@ __global__ void __launch_bounds__(kBlock) k_bwd_prep(State<R> S, AdjState<R> G) 
   if (s >= S.n) return;
   const int64_t n = S.n;
   const uint32_t q = S.perm[s];
+  // the force adjoint uses the weights only as w_a / m and w_u / (2 m)
+  const R m = S.mass[s];
   R4<R> w;
-  w.x = (R)G.w_a[q];
-  w.y = (R)G.w_a[n + q];
-  w.z = (R)G.w_a[2 * n + q];
-  w.w = (R)G.w_u[q];
+  w.x = (R)G.w_a[q] / m;
+  w.y = (R)G.w_a[n + q] / m;
+  w.z = (R)G.w_a[2 * n + q] / m;
+  w.w = (R)G.w_u[q] / (R(2) * m);
   G.wgt4[s] = w;
 }
 
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
     const int ng = nb.ng, ns = nb.ns;
     const R4<R> pi = S.pos4[s];
     for (int t = 0; t < ng + ns; ++t) {
-      const uint32_t e = nbr_entry(S, nb, t);
+      const uint32_t e = nbr_entry1(S, nb, t);
       const uint32_t j = e >> kCodeBits;
       load_side(S, G, j, J, relj);
       R x[3];
@@ -238,9 +239,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   kernel_self<R, K>(pi.w, W0, dW0);
   density_self_adj<R, double>(ki.a, mi, vi.w, W0, dW0, Numb, Denb, &kb, Vb, hb);
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t);
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
@@ -293,9 +295,10 @@ __device__ inline void moments_raw(const State<R>& S, int64_t s, double raw[40])
   kernel_self<R, K>(hinv, W0, dW0);
   acc[0] = S.vel4[s].w * W0;
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[slot_at(nb.gb, k)];
+    const uint32_t e = gather_entry(S, nb, k, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R Vj = S.vel4[j].w;
     R x[3];
@@ -364,9 +367,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   double sh = (double)(mi * dW0);
   double xb[3] = {0, 0, 0};
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t);
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
@@ -424,9 +428,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
   const R ki = G.kap[s];
   double xb[3] = {0, 0, 0};
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
   for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t);
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];

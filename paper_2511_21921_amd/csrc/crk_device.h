@@ -17,12 +17,15 @@ template <class R> struct Sc;
 template <> struct Sc<float> {
   __device__ static inline float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
   __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
+  __device__ static inline float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  // a / b through the hardware reciprocal (about 1 ulp): FP32 pair arithmetic
+  __device__ static inline float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 template <> struct Sc<double> {
   __host__ __device__ static inline double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
   __host__ __device__ static inline double rcp(double x) { return 1.0 / x; }
   __host__ __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
+  __host__ __device__ static inline double div(double a, double b) { return a / b; }
 };
 
 template <class R> struct Vec4;

@@ -49,26 +49,57 @@ __device__ inline unsigned long long dbits(double d) {
 
 // ------------------------------------------------------------- inputs ----
 
+// Grid-stride over the inputs; each block reduces in LDS and issues one
+// atomic per counter (per-wave atomics on four shared addresses serialise).
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h,
                                                          const R* __restrict__ m,
                                                          const R* __restrict__ u, int64_t n,
                                                          unsigned long long* cnt) {
-  const int64_t i = particle_id();
   unsigned long long hb = 0, bad = 0, mb = 0, ib = 0;
-  if (i < n) {
-    const double hv = (double)h[i], mv = (double)m[i];
-    const bool ok = hv > 0.0 && mv > 0.0 && (double)u[i] > 0.0 && hv < 1e300 &&
-                    (double)u[i] < 1e300 && mv < 1e300;
-    bad = ok ? 0 : 1;
-    hb = ok ? dbits(hv) : 0;
-    mb = ok ? dbits(mv) : 0;
-    ib = ok ? dbits(1.0 / mv) : 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double hv = (double)h[i], mv = (double)m[i], uv = (double)u[i];
+    const bool ok = hv > 0.0 && mv > 0.0 && uv > 0.0 && hv < 1e300 && uv < 1e300 && mv < 1e300;
+    bad += ok ? 0 : 1;
+    if (ok) {
+      const unsigned long long a = dbits(hv), b = dbits(mv), c = dbits(1.0 / mv);
+      hb = a > hb ? a : hb;  // positive doubles order as their bit patterns
+      mb = b > mb ? b : mb;
+      ib = c > ib ? c : ib;
+    }
   }
-  wave_max_u64(&cnt[CNT_HMAX_BITS], hb);
-  wave_add_u64(&cnt[CNT_BAD_INPUT], bad);
-  wave_max_u64(&cnt[CNT_MMAX_BITS], mb);
-  wave_max_u64(&cnt[CNT_MINVMAX_BITS], ib);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bad += __shfl_xor(bad, o, 64);
+    unsigned long long t = __shfl_xor(hb, o, 64);
+    hb = t > hb ? t : hb;
+    t = __shfl_xor(mb, o, 64);
+    mb = t > mb ? t : mb;
+    t = __shfl_xor(ib, o, 64);
+    ib = t > ib ? t : ib;
+  }
+  __shared__ unsigned long long part[kBlock / 64][4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[w][0] = hb;
+    part[w][1] = bad;
+    part[w][2] = mb;
+    part[w][3] = ib;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kBlock / 64; ++k) {
+      hb = part[k][0] > hb ? part[k][0] : hb;
+      bad += part[k][1];
+      mb = part[k][2] > mb ? part[k][2] : mb;
+      ib = part[k][3] > ib ? part[k][3] : ib;
+    }
+    if (hb) atomicMax(&cnt[CNT_HMAX_BITS], hb);
+    if (bad) atomicAdd(&cnt[CNT_BAD_INPUT], bad);
+    if (mb) atomicMax(&cnt[CNT_MMAX_BITS], mb);
+    if (ib) atomicMax(&cnt[CNT_MINVMAX_BITS], ib);
+  }
 }
 
 __device__ inline double wrap_pos(double xa, double L) {
@@ -159,30 +190,52 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   int cnt = 0;
   Stage4<uint32_t> se;
   Stage4<R> sr, sm;
-  wave_traverse(S, active, S.cell3[sc],
-                [&](uint32_t j, const R4<R>& pj, R mj, int dx, int dy, int dz, bool mine) {
-    if (!mine || dx < -1 || dx > 1) return;
-    if (j == (uint32_t)s && dx == 0 && dy == 0 && dz == 0) return;
-    R x[3];
-    x[0] = (pi.x - pj.x) - R(dx) * S.ell;
-    x[1] = (pi.y - pj.y) - R(dy) * S.ell;
-    x[2] = (pi.z - pj.z) - R(dz) * S.ell;
-    const R r2 = dot3(x, x);
-    if (r2 < rc2) {
-      if (cnt < cap) {
-        const int slot = cnt & 3;
-        se.put(slot, (j << kCodeBits) | (uint32_t)(9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)));
-        sr.put(slot, Sc<R>::sqrt(r2));
-        sm.put(slot, mj * mi_inv);
-        if (slot == 3) {
-          se.flush(S.cand, s, cap, cnt);
-          sr.flush(S.scr_r, s, cap, cnt);
-          if (!S.equal_mass) sm.flush(S.scr_m, s, cap, cnt);
+  // Each lane walks its own 27 stencil cells: the lanes of a wave sit in one
+  // or two cells, so they load the same candidates at the same time (the
+  // loads coalesce) and no broadcast is needed.
+  if (active) {
+    const uint32_t c3 = S.cell3[s];
+    const int G = S.G;
+    const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int z = wrap_cell(cz + dz, G);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int y = wrap_cell(cy + dy, G);
+        const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const uint32_t c = rowbase + (uint32_t)wrap_cell(cx + dx, G);
+          const uint32_t code = (uint32_t)(9 * (dz + 1) + 3 * (dy + 1) + (dx + 1));
+          const R ox = R(dx) * S.ell, oy = R(dy) * S.ell, oz = R(dz) * S.ell;
+          const uint32_t b = S.cell_start[c];
+          uint32_t e = S.cell_start[c + 1];
+          if (e > (uint32_t)S.n) e = (uint32_t)S.n;
+          for (uint32_t j = b; j < e; ++j) {
+            if (j == (uint32_t)s && code == 13u) continue;
+            const R4<R> pj = S.pos4[j];
+            R x[3];
+            x[0] = (pi.x - pj.x) - ox;
+            x[1] = (pi.y - pj.y) - oy;
+            x[2] = (pi.z - pj.z) - oz;
+            const R r2 = dot3(x, x);
+            if (r2 < rc2) {
+              if (cnt < cap) {
+                const int slot = cnt & 3;
+                se.put(slot, (j << kCodeBits) | code);
+                sr.put(slot, Sc<R>::sqrt(r2));
+                if (!S.equal_mass) sm.put(slot, S.mass[j] * mi_inv);
+                if (slot == 3) {
+                  se.flush(S.cand, s, cap, cnt);
+                  sr.flush(S.scr_r, s, cap, cnt);
+                  if (!S.equal_mass) sm.flush(S.scr_m, s, cap, cnt);
+                }
+              }
+              ++cnt;
+            }
+          }
         }
       }
-      ++cnt;
     }
-  });
+  }
   unsigned long long ovf = 0;
   if (active) {
     const int stored = cnt < cap ? cnt : cap;
@@ -237,12 +290,20 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
     const R C = R(Shape<K>::C);
     const R n_h3 = R(S.n_h3);
     const R Rcap = S.rad ? S.rad[s] : S.rcap;
-    R h, dsum;
+    const R rtol = R(S.rtol);
+    R h = S.hbuf[s];
+    if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
+    R dsum, sum = candidate_sum<R, K>(S, q, cnt, h, dsum);
+    R f = C * sum - n_h3;
+    // the bracket [0, Rcap] holds the root only if f(Rcap) > 0; that needs
+    // its own pass, taken only when the starting h is below the root
     bool cap_hit = false;
-    if (!(C * candidate_sum<R, K>(S, q, cnt, Rcap, dsum) - n_h3 > R(0))) {
+    if (!(f > R(0))) {
+      R ds2;
+      cap_hit = !(C * candidate_sum<R, K>(S, q, cnt, Rcap, ds2) - n_h3 > R(0));
+    }
+    if (cap_hit) {
       capped = 1;  // the root lies beyond the candidate radius
-      cap_hit = true;
-      h = Rcap;
       if (S.rad) {
         // tree path: grow the radius by what the candidate count suggests
         const double g = grow_factor(S.n_h3, cnt);
@@ -251,40 +312,41 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       }
     } else {
       R lo = R(0), hi = Rcap;
-      h = S.hbuf[s];
-      if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
-      const R rtol = R(S.rtol);
       bool conv = false;
       int it = 0;
-      for (; it < S.max_iter; ++it) {
-        const R f = C * candidate_sum<R, K>(S, q, cnt, h, dsum) - n_h3;
+      R hn = h;
+      for (;;) {
         const R fp = -C * dsum / h;
         if (f > R(0)) hi = h; else lo = h;
-        R hn = R(0.5) * (lo + hi);
+        hn = R(0.5) * (lo + hi);
         if (fp > R(0)) {
           const R nt = h - f / fp;
           const R step = nt > h ? nt - h : h - nt;
           if (step <= rtol * h) {
-            h = nt < lo ? lo : (nt > hi ? hi : nt);
+            hn = nt < lo ? lo : (nt > hi ? hi : nt);
             conv = true;
             break;
           }
           if (nt > lo && nt < hi) hn = nt;
         }
-        h = hn;
-        if (hi - lo <= rtol * h) {
+        if (hi - lo <= rtol * hn) {
           conv = true;
           break;
         }
+        if (++it >= S.max_iter) break;
+        h = hn;
+        sum = candidate_sum<R, K>(S, q, cnt, h, dsum);
+        f = C * sum - n_h3;
       }
       iters = (unsigned long long)(it + 1);
       unconv = conv ? 0 : 1;
-    }
-    if (!cap_hit) {
-      const R sum = candidate_sum<R, K>(S, q, cnt, h, dsum);
-      S.hbuf[s] = h;
-      S.Vbuf[s] = h * h * h / (C * sum);
-      hbits = dbits((double)h);
+      // V at the final h from the last sums: the step is below the
+      // tolerance, so the first-order term leaves an error of order rtol^2
+      // (an unconverged h gets its own pass)
+      const R sum_f = conv ? sum - dsum / h * (hn - h) : candidate_sum<R, K>(S, q, cnt, hn, dsum);
+      S.hbuf[s] = hn;
+      S.Vbuf[s] = hn * hn * hn / (C * sum_f);
+      hbits = dbits((double)hn);
       if (S.todo) S.todo[s] = 0;
     }
   }
@@ -408,9 +470,10 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
 #pragma unroll
   for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng;
   for (int k = 0; k < ng; ++k) {
-    const uint32_t e = S.nlist[slot_at(nb.gb, k)];
+    const uint32_t e = gather_entry(S, nb, k, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R Vj = S.vel4[j].w;
@@ -656,9 +719,10 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 9; ++t) gv[t] = R(0);
     const NbrRef nb = nbr_ref(S, s);
+    uint4 ebuf;
     const int ng = nb.ng;
     for (int k = 0; k < ng; ++k) {
-      const uint32_t e = S.nlist[slot_at(nb.gb, k)];
+      const uint32_t e = gather_entry(S, nb, k, ebuf);
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       const R4<R> vj = S.vel4[j];
@@ -759,10 +823,11 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const R hi = R(1) / pi.w;
   double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
   const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
   const int total = ng + ns;
   for (int t = 0; t < total; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t);
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
@@ -797,16 +862,16 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
     const R s2 = sum * sum;
     R phi = R(0);
     if (s2 > R(0)) {
-      phi = R(4) * nn * dd / s2;
+      phi = Sc<R>::div(R(4) * nn * dd, s2);
       phi = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
     }
     const R hp = R(0.5) * phi;
     const R vp[3] = {(vi.x - vj.x) - hp * (gix[0] + gjx[0]), (vi.y - vj.y) - hp * (gix[1] + gjx[1]),
                      (vi.z - vj.z) - hp * (gix[2] + gjx[2])};
     const R vpx = dot3(vp, x);
-    const R hj = R(1) / pj.w;
-    R mui = vpx * hi / (r2 + eps2 * hi * hi);
-    R muj = vpx * hj / (r2 + eps2 * hj * hj);
+    const R hj = Sc<R>::rcp(pj.w);
+    R mui = Sc<R>::div(vpx * hi, r2 + eps2 * hi * hi);
+    R muj = Sc<R>::div(vpx * hj, r2 + eps2 * hj * hj);
     mui = mui < R(0) ? mui : R(0);
     muj = muj < R(0) ? muj : R(0);
     const R Qi = si.x * (-alpha * si.z * mui + beta * mui * mui);
@@ -849,7 +914,9 @@ __global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, i
 template <class R>
 void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned long long* cnt,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_check_inputs<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, h, m, u, n, cnt);
+  const unsigned blocks = grid_for(n) < 1024u ? grid_for(n) : 1024u;
+  hipLaunchKernelGGL(k_check_inputs<R>, dim3(blocks > 0 ? blocks : 1), dim3(kBlock), 0, s, h, m, u,
+                     n, cnt);
 }
 
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,

@@ -80,7 +80,7 @@ struct AdjState {
   double* gkc;   // [16][n] adjoint of the packed corrections (a, b, c, M)
   double* gab;   // [2][blocks] per-block alpha, beta partial sums
   // records gathered from neighbours, packed per particle in Real:
-  R4<R>* wgt4;   // (w_a x, y, z, w_u) loss weights in sorted order
+  R4<R>* wgt4;   // (w_a / m, w_u / (2 m)) loss weights over the mass, sorted order
   R4<R>* gvc4;   // 3 per particle: grad v adjoint (9), Num bar, Den bar, 0
   R4<R>* mom4;   // 10 per particle: adjoint of the 40 raw moment sums
   R* kap;        // [n] volume / smoothing-length coefficient kappa

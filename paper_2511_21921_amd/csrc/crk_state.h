@@ -317,10 +317,32 @@ __device__ inline NbrRef nbr_ref(const State<R>& S, int64_t s) {
   return r;
 }
 
-// Entry t of the symmetric list: gather part first.
+// Entry t of the symmetric list, gather part first, for t = 0, 1, 2, ... in
+// order: each 4-entry chunk is read with one 16-byte load into buf.
 template <class R>
-__device__ inline uint32_t nbr_entry(const State<R>& S, const NbrRef& r, int t) {
+__device__ inline uint32_t nbr_entry(const State<R>& S, const NbrRef& r, int t, uint4& buf) {
+  const bool g = t < r.ng;
+  const int k = g ? t : t - r.ng;
+  if ((k & 3) == 0)
+    buf = *reinterpret_cast<const uint4*>(g ? S.nlist + slot_at(r.gb, k)
+                                            : S.slist + slot_at(r.sb, k));
+  const int q = k & 3;
+  return q == 0 ? buf.x : (q == 1 ? buf.y : (q == 2 ? buf.z : buf.w));
+}
+
+// Entry t of the symmetric list with a 4-byte load of its own (for kernels
+// that cannot spare the registers of the chunk buffer).
+template <class R>
+__device__ inline uint32_t nbr_entry1(const State<R>& S, const NbrRef& r, int t) {
   return t < r.ng ? S.nlist[slot_at(r.gb, t)] : S.slist[slot_at(r.sb, t - r.ng)];
+}
+
+// Entry k of the gather list alone, for k = 0, 1, 2, ... in order.
+template <class R>
+__device__ inline uint32_t gather_entry(const State<R>& S, const NbrRef& r, int k, uint4& buf) {
+  if ((k & 3) == 0) buf = *reinterpret_cast<const uint4*>(S.nlist + slot_at(r.gb, k));
+  const int q = k & 3;
+  return q == 0 ? buf.x : (q == 1 ? buf.y : (q == 2 ? buf.z : buf.w));
 }
 
 }  // namespace crk
