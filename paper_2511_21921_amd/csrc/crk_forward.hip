@@ -253,19 +253,31 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
 }
 
 // sum_k (m_k/m_i) w(r_k / h) over the candidates plus the self term w(0), and
-// dsum = sum_k (m_k/m_i) w'(q_k) q_k.
+// dsum = sum_k (m_k/m_i) w'(q_k) q_k. The list is read a 4-entry chunk (one
+// 16- or 32-byte load) at a time.
 template <class R, int K>
 __device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h, R& dsum) {
   const R hinv = R(1) / h;
   R sum = R(Shape<K>::w0), ds = R(0);
-  for (int k = 0; k < cnt; ++k) {
+  for (int k = 0; k < cnt; k += 4) {
     const int64_t e = slot_at(base, k);
-    const R q = S.scr_r[e] * hinv;
-    const R mr = S.equal_mass ? R(1) : S.scr_m[e];
-    R w, dw;
-    Shape<K>::eval(q, w, dw);
-    sum += mr * w;
-    ds += mr * dw * q;
+    const R4<R> rq = *reinterpret_cast<const R4<R>*>(S.scr_r + e);
+    R4<R> mq;
+    if (S.equal_mass) {
+      mq.x = mq.y = mq.z = mq.w = R(1);
+    } else {
+      mq = *reinterpret_cast<const R4<R>*>(S.scr_m + e);
+    }
+    const R rr[4] = {rq.x, rq.y, rq.z, rq.w}, mm[4] = {mq.x, mq.y, mq.z, mq.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (k + t >= cnt) break;
+      const R q = rr[t] * hinv;
+      R w, dw;
+      Shape<K>::eval(q, w, dw);
+      sum += mm[t] * w;
+      ds += mm[t] * dw * q;
+    }
   }
   dsum = ds;
   return sum;
@@ -397,8 +409,11 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     const int cap = S.list_cap, scap = S.slist_cap;
     Stage4<uint32_t> sg, ss;
     const int cc = S.ccnt[s] < S.scr_cap ? S.ccnt[s] : S.scr_cap;
+    uint4 cb;
     for (int k = 0; k < cc; ++k) {
-      const uint32_t e = S.cand[list_index(s, S.scr_cap, k)];
+      if ((k & 3) == 0) cb = *reinterpret_cast<const uint4*>(S.cand + list_index(s, S.scr_cap, k));
+      const int q = k & 3;
+      const uint32_t e = q == 0 ? cb.x : (q == 1 ? cb.y : (q == 2 ? cb.z : cb.w));
       const uint32_t j = e >> kCodeBits;
       const R4<R> pj = S.pos4[j];
       R x[3];
