@@ -34,9 +34,41 @@ METRIC = "CRKSPH pair interactions/s (fwd, fwd+bwd) FP32 vs FP64 at rel err ≤1
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic flops per ordered pair of each pair pass (FMA = 2, add/mul/
-# div/sqrt/rsqrt = 1, one branch of the piecewise kernel); see the design doc.
-FLOPS_PER_PAIR = {"force": 216, "density": 94, "moments": 109, "bwd_force": 680}
+# Algorithmic flops per unit of each pair pass (FMA = 2, add/mul/div/sqrt/
+# rsqrt = 1, one branch of the piecewise kernel): (flops, unit).
+FLOPS_PER_PAIR = {"force": (216, "pairs_force"), "bwd_force": (680, "pairs_force"),
+                  "moments": (109, "pairs_gather"), "density": (94, "pairs_gather")}
+# Passes timed around exactly one kernel (the others group several).
+SINGLE_KERNEL = ("candidates", "hsolve", "nlist", "moments", "density", "force", "bwd_force",
+                 "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sedov64_v_fp32_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the library's kernel sources, as recorded with the traffic counters."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2511_21921_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel: str):
+    """HBM bytes per launch of kernel from the committed FETCH_SIZE / WRITE_SIZE counters,
+    each scaled by its plain-copy calibration; None when the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            line = next(l for l in fh if l.startswith("traffic-json:"))
+    except (OSError, StopIteration):
+        return None
+    t = json.loads(line.split(":", 1)[1])
+    k = t["kernels"].get(kernel)
+    if k is None or t["source_sha256"] != kernel_source_hash():
+        return None
+    return 1024.0 * (k["fetch_kib"] * t["fetch_factor"] + k["write_kib"] * t["write_factor"])
 
 
 def log(*a):
@@ -95,6 +127,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with two plain 256 MiB device copies (untimed), the reference "
+                         "for scaling the HBM byte counters of a profiling run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,18 +152,17 @@ def main():
     value = pairs / (ms32 * 1e-3)
     msf, stf, passesf, outf = run_gpu(ps0, FP32, args.steps, args.warmup, False)
     log("fp32 fwd (v = 0): %.3f ms/step" % msf)
-    names = ("cells", "hsolve", "nlist", "moments", "density", "force", "bwd_force",
-             "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume", "bwd_other")
+    names = ("cells", "candidates", "hsolve", "nlist", "moments", "density", "force",
+             "bwd_force", "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume", "bwd_other")
     breakdown = {k: round(pass_ms(passes32, k), 4) for k in names}
-    dom = max(breakdown, key=lambda k: breakdown[k] if breakdown[k] == breakdown[k] else -1)
-    flops = {"force": FLOPS_PER_PAIR["force"] * pairs,
-             "bwd_force": FLOPS_PER_PAIR["bwd_force"] * pairs,
-             "moments": FLOPS_PER_PAIR["moments"] * st32["n_pairs_gather"],
-             "density": FLOPS_PER_PAIR["density"] * st32["n_pairs_gather"]}
+    flops = {k: f * st32["n_" + unit] for k, (f, unit) in FLOPS_PER_PAIR.items()}
     pass_tflops = {k: round(f / (pass_ms(passes32, k) * 1e-3) / 1e12, 3) for k, f in flops.items()}
-    rk = dom if dom in flops else "force"
+    # dominant kernel: the longest single-kernel pass of the step
+    largest = max(SINGLE_KERNEL, key=lambda k: breakdown[k] if breakdown[k] == breakdown[k] else -1)
+    rk = largest if largest in flops else max(flops, key=lambda k: breakdown[k])
     r_ms = pass_ms(passes32, rk)
     achieved = flops[rk] / (r_ms * 1e-3) / 1e12
+    traffic = traffic_bytes("k_" + rk)
 
     fp64 = None
     if not args.no_fp64:
@@ -147,14 +181,19 @@ def main():
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)
-        t0 = time.perf_counter()
-        ref = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), nbr_mode=1)
-        tc = time.perf_counter() - t0
-        cpu = {"value": ref["pairs_force"] / tc, "unit": "interactions/s",
+        # repeat the whole-workload forward until about 10 s of CPU work (at most 10 times)
+        reps, tc = 0, 0.0
+        while reps < 10 and (reps == 0 or tc < 10.0):
+            t0 = time.perf_counter()
+            ref = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), nbr_mode=1)
+            tc += time.perf_counter() - t0
+            reps += 1
+        cpu = {"value": reps * ref["pairs_force"] / tc, "unit": "interactions/s",
                "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "the whole workload once: FP64 forward of all 262144 particles "
-                         "(%d force pairs, grid neighbour search), %.1f s; the oracle has no "
-                         "reverse mode, so this is a forward-only rate" % (ref["pairs_force"], tc)}
+               "sample": "the whole workload, %d times: FP64 forward of all 262144 particles "
+                         "(%d force pairs, grid neighbour search), %.1f s in all; the oracle has "
+                         "no reverse mode, so this is a forward-only rate"
+                         % (reps, ref["pairs_force"], tc)}
         ref0 = oracle.forward(ps0.x, ps0.v, ps0.m, ps0.u, ps0.h, oracle.params_for(ps0),
                               nbr_mode=1)
         rng = np.random.default_rng(11)
@@ -187,15 +226,24 @@ def main():
                    "step": "forward+backward"},
         "roofline": {"bound": "alu", "kernel": "k_" + rk, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "flops_per_pair": FLOPS_PER_PAIR[rk], "kernel_ms": round(r_ms, 4)},
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "flops_per_unit": FLOPS_PER_PAIR[rk][0], "unit_count": FLOPS_PER_PAIR[rk][1],
+                     "kernel_ms": round(r_ms, 4), "largest_pass": largest},
         "fwd": {"value": stf["n_pairs_force"] / (msf * 1e-3), "ms_per_step": round(msf, 4),
                 "workload": "sedov64 (same particles, zero velocity), forward only",
-                "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:6]}},
+                "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
         "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calibration_copy:
+        import torch
+        a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

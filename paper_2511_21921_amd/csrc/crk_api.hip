@@ -28,12 +28,13 @@ struct Buf {
 
 namespace {
 enum Pass {
-  P_CELLS = 0, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
+  P_CELLS = 0, P_CAND, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
   P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_NPASS
 };
-const char* kPassNames[P_NPASS] = {"cells", "hsolve", "nlist", "moments", "density", "force",
-                                   "bwd_force", "bwd_density", "bwd_corr", "bwd_moments",
-                                   "bwd_volume", "bwd_other"};
+const char* kPassNames[P_NPASS] = {"cells",     "candidates",  "hsolve",      "nlist",
+                                   "moments",   "density",     "force",       "bwd_force",
+                                   "bwd_density", "bwd_corr",  "bwd_moments", "bwd_volume",
+                                   "bwd_other"};
 }  // namespace
 
 struct crk_ctx {
@@ -401,8 +402,10 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED, 0, 8, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY, 0, 8, s), "memset");
     State<R> S = make_state<R>(ctx, n);
-    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+    CRK_HIP(tbegin(ctx, P_CAND, s), "event");
     launch_candidates_tree<R>(S, P.kernel, s);
+    CRK_HIP(tend(ctx, P_CAND, s), "event");
+    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     if (P.h_mode == 0)
       launch_volume<R>(S, P.kernel, s);
     else
@@ -540,8 +543,10 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
               "alloc candidates");
     State<R> S = make_state<R>(ctx, n);
-    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+    CRK_HIP(tbegin(ctx, P_CAND, s), "event");
     launch_candidates<R>(S, s);
+    CRK_HIP(tend(ctx, P_CAND, s), "event");
+    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     if (P.h_mode == 0)
       launch_volume<R>(S, P.kernel, s);
     else
