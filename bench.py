@@ -162,7 +162,8 @@ def main():
     rk = largest if largest in flops else max(flops, key=lambda k: breakdown[k])
     r_ms = pass_ms(passes32, rk)
     achieved = flops[rk] / (r_ms * 1e-3) / 1e12
-    traffic = traffic_bytes("k_" + rk)
+    kname = "k_" + rk
+    traffic = traffic_bytes(kname)
 
     fp64 = None
     if not args.no_fp64:
@@ -224,7 +225,7 @@ def main():
                                "forward + adjoint of sum w_a.a + sum w_u.du/dt",
                    "n": ps.n, "pairs_force": pairs, "pairs_gather": st32["n_pairs_gather"],
                    "step": "forward+backward"},
-        "roofline": {"bound": "alu", "kernel": "k_" + rk, "achieved": round(achieved, 3),
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": None if traffic is None else round(traffic),

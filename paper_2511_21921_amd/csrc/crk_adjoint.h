@@ -95,10 +95,10 @@ struct KCBar {
 
 // Given WRbar and gbar (adjoints of W^R and of the corrected gradient g at
 // separation x), accumulate into kcb (if non-null), xb and hb.
-template <class R, class A>
+template <class R, class A, class AK = A>
 __host__ __device__ inline void corr_adj(const KC<R>& k, const R x[3], R r, R rinv,
                                          const KEval<R>& e, R WRbar, const R gbar[3],
-                                         KCBar<A>* kcb, A xb[3], A& hb) {
+                                         KCBar<AK>* kcb, A xb[3], A& hb) {
   const R s = k.a + k.b[0] * x[0] + k.b[1] * x[1] + k.b[2] * x[2];
   R t[3];
   for (int gg = 0; gg < 3; ++gg)
@@ -110,11 +110,11 @@ __host__ __device__ inline void corr_adj(const KC<R>& k, const R x[3], R r, R ri
   // t = c + M x
   R tb[3] = {e.W * gbar[0], e.W * gbar[1], e.W * gbar[2]};
   if (kcb) {
-    kcb->a += (A)sbar;
+    kcb->a += (AK)sbar;
     for (int a = 0; a < 3; ++a) {
-      kcb->b[a] += (A)(sbar * x[a]);
-      kcb->c[a] += (A)tb[a];
-      for (int gg = 0; gg < 3; ++gg) kcb->M[gg * 3 + a] += (A)(tb[gg] * x[a]);
+      kcb->b[a] += (AK)(sbar * x[a]);
+      kcb->c[a] += (AK)tb[a];
+      for (int gg = 0; gg < 3; ++gg) kcb->M[gg * 3 + a] += (AK)(tb[gg] * x[a]);
     }
   }
   // x: from M x, from s = a + b.x, from f x, and from r in W and f
@@ -285,10 +285,10 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
 // Numb = rhob / Den and Denb = -rhob rho / Den.
 
 // Own term (i gathers j at x = x_ij with i's corrections and h_i).
-template <class R, class A>
+template <class R, class A, class AK = A>
 __host__ __device__ inline void density_own_adj(const KC<R>& ki, const R x[3], R r, R rinv,
                                                 const KEval<R>& e, R mj, R Vj, const R vij[3],
-                                                R Numb, R Denb, const R gvb[9], KCBar<A>* kcb,
+                                                R Numb, R Denb, const R gvb[9], KCBar<AK>* kcb,
                                                 A xb[3], A& hb, A vb[3]) {
   R WR, g[3];
   corr_fwd(ki, x, e, WR, g);
@@ -298,7 +298,7 @@ __host__ __device__ inline void density_own_adj(const KC<R>& ki, const R x[3], R
     gb[gg] = -Vj * (gvb[gg] * vij[0] + gvb[3 + gg] * vij[1] + gvb[6 + gg] * vij[2]);
   for (int a = 0; a < 3; ++a)
     vb[a] += (A)(-Vj * (gvb[a * 3] * g[0] + gvb[a * 3 + 1] * g[1] + gvb[a * 3 + 2] * g[2]));
-  corr_adj<R, A>(ki, x, r, rinv, e, WRb, gb, kcb, xb, hb);
+  corr_adj<R, A, AK>(ki, x, r, rinv, e, WRb, gb, kcb, xb, hb);
 }
 
 // Reverse term: neighbour j gathers i at x_ji = -x_ij with j's corrections
@@ -330,12 +330,12 @@ __host__ __device__ inline void density_rev_adj(const KC<R>& kj, const R x[3], R
 }
 
 // Self term of i's density sums: m_i V_i A_i W(0), V_i^2 A_i W(0).
-template <class R, class A>
+template <class R, class A, class AK = A>
 __host__ __device__ inline void density_self_adj(R a, R mi, R Vi, R W0, R dW0dh, R Numb, R Denb,
-                                                 KCBar<A>* kcb, A& Vb, A& hb) {
+                                                 KCBar<AK>* kcb, A& Vb, A& hb) {
   const R w = Numb * mi * Vi + Denb * Vi * Vi;
   Vb += (A)((Numb * mi + Denb * R(2) * Vi) * a * W0);
-  if (kcb) kcb->a += (A)(w * W0);
+  if (kcb) kcb->a += (AK)(w * W0);
   hb += (A)(w * a * dW0dh);
 }
 

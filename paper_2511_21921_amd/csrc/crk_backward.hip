@@ -149,11 +149,12 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
     const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
     ForceBar<double> ob;
     ob.zero();
+    __shared__ uint4 eslot[kBlock];  // the lane's list chunk (registers are scarce here)
     const NbrRef nb = nbr_ref(S, s);
     const int ng = nb.ng, ns = nb.ns;
     const R4<R> pi = S.pos4[s];
     for (int t = 0; t < ng + ns; ++t) {
-      const uint32_t e = nbr_entry1(S, nb, t);
+      const uint32_t e = nbr_entry_lds(S, nb, t, &eslot[threadIdx.x]);
       const uint32_t j = e >> kCodeBits;
       load_side(S, G, j, J, relj);
       R x[3];
@@ -232,17 +233,24 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   load_kc4(S, s, ki);
   R gvb[9], Numb, Denb;
   load_gvc(G, s, gvb, Numb, Denb);
-  KCBar<double> kb;
+  // the 16 correction adjoints of the own sums accumulate in the working
+  // precision (64 gather pairs; they feed the FP64 correction adjoint), which
+  // keeps this kernel at 4 waves per SIMD in FP32
+  KCBar<R> kb;
   kb.zero();
   double xb[3] = {0, 0, 0}, vb[3] = {0, 0, 0}, hb = 0, Vb = 0;
   R W0, dW0;
   kernel_self<R, K>(pi.w, W0, dW0);
-  density_self_adj<R, double>(ki.a, mi, vi.w, W0, dW0, Numb, Denb, &kb, Vb, hb);
+  density_self_adj<R, double, R>(ki.a, mi, vi.w, W0, dW0, Numb, Denb, &kb, Vb, hb);
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
-  for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t, ebuf);
+  // Two passes over the list so that the particle's own corrections and
+  // accumulators and the neighbour's records are not live together: own
+  // sums (gather part), then the particle's share in its neighbours' sums
+  // (every j with r < h_j).
+  for (int t = 0; t < ng; ++t) {
+    const uint32_t e = gather_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     const R4<R> vj = S.vel4[j];
@@ -252,35 +260,44 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;
     const R vij[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
-    if (t < ng) {
-      KEval<R> ev;
-      kernel_eval<R, K>(r, rinv, pi.w, ev);
-      density_own_adj<R, double>(ki, x, r, rinv, ev, S.mass[j], vj.w, vij, Numb, Denb, gvb, &kb,
-                                 xb, hb, vb);
-    }
-    if (r2 * (pj.w * pj.w) < R(1)) {
-      KC<R> kj;
-      load_kc4(S, j, kj);
-      R gvbj[9], Numbj, Denbj;
-      load_gvc(G, j, gvbj, Numbj, Denbj);
-      KEval<R> ej;
-      kernel_eval<R, K>(r, rinv, pj.w, ej);
-      density_rev_adj<R, double>(kj, x, r, rinv, ej, mi, vi.w, vij, Numbj, Denbj, gvbj, xb, Vb,
-                                 vb);
-    }
+    KEval<R> ev;
+    kernel_eval<R, K>(r, rinv, pi.w, ev);
+    density_own_adj<R, double, R>(ki, x, r, rinv, ev, S.mass[j], vj.w, vij, Numb, Denb, gvb,
+                                  &kb, xb, hb, vb);
+  }
+  G.gh[s] += hb;
+  G.gkc[s] += (double)kb.a;
+  for (int q = 0; q < 3; ++q) {
+    G.gkc[(1 + q) * n + s] += (double)kb.b[q];
+    G.gkc[(4 + q) * n + s] += (double)kb.c[q];
+  }
+  for (int q = 0; q < 9; ++q) G.gkc[(7 + q) * n + s] += (double)kb.M[q];
+  for (int t = 0; t < ng + ns; ++t) {
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
+    const uint32_t j = e >> kCodeBits;
+    const R4<R> pj = S.pos4[j];
+    R x[3];
+    pair_x(S, s, pi, pj, e, x);
+    const R r2 = dot3b(x, x);
+    if (!(r2 * (pj.w * pj.w) < R(1))) continue;
+    const R rinv = Sc<R>::rsqrt(r2);
+    const R r = r2 * rinv;
+    const R4<R> vj = S.vel4[j];
+    const R vij[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
+    KC<R> kj;
+    load_kc4(S, j, kj);
+    R gvbj[9], Numbj, Denbj;
+    load_gvc(G, j, gvbj, Numbj, Denbj);
+    KEval<R> ej;
+    kernel_eval<R, K>(r, rinv, pj.w, ej);
+    density_rev_adj<R, double>(kj, x, r, rinv, ej, mi, vi.w, vij, Numbj, Denbj, gvbj, xb, Vb,
+                               vb);
   }
   for (int a = 0; a < 3; ++a) {
     G.gx[a * n + s] += xb[a];
     G.gv[a * n + s] += vb[a];
   }
-  G.gh[s] += hb;
   G.gV[s] += Vb;
-  G.gkc[s] += kb.a;
-  for (int q = 0; q < 3; ++q) {
-    G.gkc[(1 + q) * n + s] += kb.b[q];
-    G.gkc[(4 + q) * n + s] += kb.c[q];
-  }
-  for (int q = 0; q < 9; ++q) G.gkc[(7 + q) * n + s] += kb.M[q];
 }
 
 // --------------------------------------------------------------------- B4 --
@@ -369,8 +386,11 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;
   const int ng = nb.ng, ns = nb.ns;
-  for (int t = 0; t < ng + ns; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t, ebuf);
+  // Own moment sums first (gather part), then the particle's share in its
+  // neighbours' sums: the two sets of 40 moment adjoints are never live
+  // together.
+  for (int t = 0; t < ng; ++t) {
+    const uint32_t e = gather_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
     const R4<R> pj = S.pos4[j];
     R x[3];
@@ -378,27 +398,34 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;
-    if (t < ng) {
-      KEval<R> ev;
-      kernel_eval<R, K>(r, rinv, pi.w, ev);
-      R gx[3], gh;
-      mom_pair_adj<R>(mb, x, rinv, ev, gx, gh);
-      const R Vj = S.vel4[j].w;
-      for (int a = 0; a < 3; ++a) xb[a] += (double)(Vj * gx[a]);
-      hb += (double)(Vj * gh);
-      sh += (double)(S.mass[j] * ev.dWdh);
-    }
-    if (r2 * (pj.w * pj.w) < R(1)) {
-      R mbj[40];
-      load_mom(G, j, mbj);
-      KEval<R> ej;
-      kernel_eval<R, K>(r, rinv, pj.w, ej);
-      const R xm[3] = {-x[0], -x[1], -x[2]};
-      R gx[3], gh;
-      const R l = mom_pair_adj<R>(mbj, xm, rinv, ej, gx, gh);
-      Vb += (double)l;
-      for (int a = 0; a < 3; ++a) xb[a] -= (double)(Vi * gx[a]);
-    }
+    KEval<R> ev;
+    kernel_eval<R, K>(r, rinv, pi.w, ev);
+    R gx[3], gh;
+    mom_pair_adj<R>(mb, x, rinv, ev, gx, gh);
+    const R Vj = S.vel4[j].w;
+    for (int a = 0; a < 3; ++a) xb[a] += (double)(Vj * gx[a]);
+    hb += (double)(Vj * gh);
+    sh += (double)(S.mass[j] * ev.dWdh);
+  }
+  for (int t = 0; t < ng + ns; ++t) {
+    const uint32_t e = nbr_entry(S, nb, t, ebuf);
+    const uint32_t j = e >> kCodeBits;
+    const R4<R> pj = S.pos4[j];
+    R x[3];
+    pair_x(S, s, pi, pj, e, x);
+    const R r2 = dot3b(x, x);
+    if (!(r2 * (pj.w * pj.w) < R(1))) continue;
+    const R rinv = Sc<R>::rsqrt(r2);
+    const R r = r2 * rinv;
+    R mbj[40];
+    load_mom(G, j, mbj);
+    KEval<R> ej;
+    kernel_eval<R, K>(r, rinv, pj.w, ej);
+    const R xm[3] = {-x[0], -x[1], -x[2]};
+    R gx[3], gh;
+    const R l = mom_pair_adj<R>(mbj, xm, rinv, ej, gx, gh);
+    Vb += (double)l;
+    for (int a = 0; a < 3; ++a) xb[a] -= (double)(Vi * gx[a]);
   }
   for (int a = 0; a < 3; ++a) G.gx[a * n + s] += xb[a];
   const double hbt = G.gh[s] + hb;

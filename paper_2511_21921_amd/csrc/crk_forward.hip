@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const R hi = R(1) / pi.w;
   double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
   const NbrRef nb = nbr_ref(S, s);
-  uint4 ebuf;
+  uint4 ebuf;  // at 3 waves per SIMD this beats 4 waves with the chunk in LDS
   const int ng = nb.ng, ns = nb.ns;
   const int total = ng + ns;
   for (int t = 0; t < total; ++t) {

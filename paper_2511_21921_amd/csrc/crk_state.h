@@ -330,6 +330,19 @@ __device__ inline uint32_t nbr_entry(const State<R>& S, const NbrRef& r, int t, 
   return q == 0 ? buf.x : (q == 1 ? buf.y : (q == 2 ? buf.z : buf.w));
 }
 
+// Entry t of the symmetric list, reading each 4-entry chunk with one 16-byte
+// load into the lane's own LDS slot (no barrier: a lane touches only its
+// slot). The chunk then holds no registers across the pair computation.
+template <class R>
+__device__ inline uint32_t nbr_entry_lds(const State<R>& S, const NbrRef& r, int t, uint4* slot) {
+  const bool g = t < r.ng;
+  const int k = g ? t : t - r.ng;
+  if ((k & 3) == 0)
+    *slot = *reinterpret_cast<const uint4*>(g ? S.nlist + slot_at(r.gb, k)
+                                              : S.slist + slot_at(r.sb, k));
+  return reinterpret_cast<const uint32_t*>(slot)[k & 3];
+}
+
 // Entry t of the symmetric list with a 4-byte load of its own (for kernels
 // that cannot spare the registers of the chunk buffer).
 template <class R>
