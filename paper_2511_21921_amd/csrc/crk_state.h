@@ -96,38 +96,7 @@ struct State {
   int max_iter;
 };
 
-// Decoded cell coordinates are packed 10 bits per axis (G <= 1024).
-__device__ inline void cell_coords(uint32_t key, int G, int& cx, int& cy, int& cz) {
-  cx = (int)(key % (uint32_t)G);
-  uint32_t t = key / (uint32_t)G;
-  cy = (int)(t % (uint32_t)G);
-  cz = (int)(t / (uint32_t)G);
-}
-
 __device__ inline int wrap_cell(int c, int G) { return c < 0 ? c + G : (c >= G ? c - G : c); }
-
-// Calls f(j, code) for every particle j of the 27 stencil cells around the
-// cell of key, in a fixed order (dz, dy, dx; then sorted order in a cell).
-template <class R, class F>
-__device__ inline void for_each_candidate(const State<R>& S, uint32_t key, F&& f) {
-  int cx, cy, cz;
-  cell_coords(key, S.G, cx, cy, cz);
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int z = wrap_cell(cz + dz, S.G);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int y = wrap_cell(cy + dy, S.G);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = wrap_cell(cx + dx, S.G);
-        const uint32_t c = ((uint32_t)z * S.G + (uint32_t)y) * S.G + (uint32_t)xx;
-        const uint32_t code = (uint32_t)(9 * (dz + 1) + 3 * (dy + 1) + (dx + 1));
-        const uint32_t b = S.cell_start[c];
-        uint32_t e = S.cell_start[c + 1];
-        if (e > (uint32_t)S.n) e = (uint32_t)S.n;
-        for (uint32_t j = b; j < e; ++j) f(j, code);
-      }
-    }
-  }
-}
 
 // Wave broadcast of lane k's value (k wave-uniform).
 __device__ inline float bcast(float v, int k) {
@@ -139,88 +108,6 @@ __device__ inline double bcast(double v, int k) {
   return __hiloint2double(hi, lo);
 }
 __device__ inline int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
-
-// Wave-cooperative traversal. The lanes of a wave hold consecutive sorted
-// particles, so they sit in a few neighbouring cells of one or two cell
-// rows. For each row group the wave walks the union of the lanes' 3x3x3
-// stencils: for each (dz, dy) the cells x = lo-1 .. hi+1 of a row are
-// contiguous in the cell order, so they form one particle range (plus one
-// cell more on each side where the row wraps periodically). Each range is
-// read in coalesced 64-wide tiles (one candidate per lane) and every
-// candidate is broadcast to the wave with readlane. f(j, pj, mj, dx, dy, dz,
-// mine) receives the candidate's record and mass, the lane's own cell
-// offset to it (dx may leave [-1, 1]: such candidates are more than a cell
-// side away and the caller drops them) and whether the lane belongs to the
-// current row group.
-template <class R, class F>
-__device__ inline void wave_traverse(const State<R>& S, bool active, uint32_t c3, F&& f) {
-  const int G = S.G;
-  const int lane = threadIdx.x & 63;
-  const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
-  const int row = active ? cz * G + cy : -1;
-  uint64_t remaining = __ballot(active);
-  while (remaining) {
-    const int leader = __ffsll((unsigned long long)remaining) - 1;
-    const int grow = __builtin_amdgcn_readfirstlane(__shfl(row, leader, 64));
-    const bool mine = active && row == grow && ((remaining >> lane) & 1ull);
-    remaining &= ~__ballot(mine);
-    int lo = mine ? cx : G, hi = mine ? cx : -1;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const int a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
-      lo = a < lo ? a : lo;
-      hi = b > hi ? b : hi;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    hi = __builtin_amdgcn_readfirstlane(hi);
-    const int gy = grow % G, gz = grow / G;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int z = wrap_cell(gz + dz, G);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int y = wrap_cell(gy + dy, G);
-        const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
-        for (int seg = 0; seg < 3; ++seg) {
-          int xa, xb, shift;
-          if (seg == 0) {
-            xa = lo - 1 > 0 ? lo - 1 : 0;
-            xb = hi + 1 < G - 1 ? hi + 1 : G - 1;
-            shift = 0;
-          } else if (seg == 1) {
-            if (lo - 1 >= 0) continue;
-            xa = xb = G - 1;
-            shift = -G;
-          } else {
-            if (hi + 1 <= G - 1) continue;
-            xa = xb = 0;
-            shift = G;
-          }
-          const uint32_t b = S.cell_start[rowbase + (uint32_t)xa];
-          uint32_t e = S.cell_start[rowbase + (uint32_t)xb + 1];
-          if (e > (uint32_t)S.n) e = (uint32_t)S.n;
-          for (uint32_t t0 = b; t0 < e; t0 += 64) {
-            const uint32_t jl = t0 + (uint32_t)lane;
-            const bool ok = jl < e;
-            const uint32_t jc = ok ? jl : b;
-            const R4<R> pl = S.pos4[jc];
-            const R ml = S.mass[jc];
-            const int xl = (int)(S.cell3[jc] & 1023u) + shift;
-            const int cnt = (int)(e - t0 < 64u ? e - t0 : 64u);
-            for (int k = 0; k < cnt; ++k) {
-              R4<R> pj;
-              pj.x = bcast(pl.x, k);
-              pj.y = bcast(pl.y, k);
-              pj.z = bcast(pl.z, k);
-              pj.w = bcast(pl.w, k);
-              const R mj = bcast(ml, k);
-              const int dx = bcast(xl, k) - cx;
-              f(t0 + (uint32_t)k, pj, mj, dx, dy, dz, mine);
-            }
-          }
-        }
-      }
-    }
-  }
-}
 
 // Periodic separation x_ij = x_i - x_j. Cell-list path: from the stencil
 // code of the list entry. Lattice path: from both particles' lattice
