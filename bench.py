@@ -13,7 +13,8 @@ adjoint of L = sum w_a . a + sum w_u du/dt (force, density, correction,
 moment and volume adjoints). value = ordered force pairs (j != i,
 r_ij < max(h_i, h_j)) per second of step wall time, FP32 pairs with FP64
 solve and accumulators. The same run reports the forward alone on the
-zero-velocity Sedov set, the plain FP64 GPU form of both, the error of the
+zero-velocity Sedov set, the same particles at the paper's gas resolution
+(Wendland C4, n_h = 4, ~268 neighbours), the plain FP64 GPU form, the error of the
 timed outputs against the FP64 oracle (values and one directional
 derivative), the roofline of the dominant kernel (from the library's
 HIP-event pass timers on the launch stream) and the oracle timed on the host
@@ -75,13 +76,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(ps, precision, steps, warmup, backward):
+def run_gpu(ps, precision, steps, warmup, backward, kernel=0):
     import numpy as np
     import torch
 
     from paper_2511_21921_amd import Context, Params
     dev = torch.device("cuda:0")
-    p = Params(box=ps.box, n_h=ps.n_h, h_mode=ps.h_mode, precision=precision, timing=1)
+    p = Params(box=ps.box, n_h=ps.n_h, h_mode=ps.h_mode, precision=precision, timing=1,
+               kernel=kernel)
     ctx = Context(p)
     R = p.real
     t = lambda a, dt=R: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -165,6 +167,17 @@ def main():
     kname = "k_" + rk
     traffic = traffic_bytes(kname)
 
+    # the paper's production resolution: Wendland C4, n_h = 4 (~268 neighbours)
+    psc = synth.at_resolution(ps, 4.0)
+    msc, stc, passesc, outc = run_gpu(psc, FP32, max(3, args.steps // 2), args.warmup, True,
+                                      kernel=1)
+    log("fp32 C4 n_h=4 fwd+bwd: %.3f ms/step" % msc)
+    c4 = {"value": stc["n_pairs_force"] / (msc * 1e-3), "ms_per_step": round(msc, 4),
+          "workload": "sedov64_v particles with the Wendland C4 kernel at n_h = 4 (~268 "
+                      "neighbours, the paper's gas resolution), forward + adjoint",
+          "pairs_force": stc["n_pairs_force"],
+          "pass_ms": {k: round(pass_ms(passesc, k), 4) for k in names}}
+
     fp64 = None
     if not args.no_fp64:
         k64 = max(3, args.steps // 2)
@@ -214,6 +227,12 @@ def main():
                 "rho_relmax": float(np.max(np.abs(out32["rho"] / ref["rho"] - 1))),
                 "pairs_oracle": ref["pairs_force"]}
         log("errors", errs)
+        refc = oracle.forward(psc.x, psc.v, psc.m, psc.u, psc.h,
+                              oracle.params_for(psc, kernel=1), nbr_mode=1)
+        c4["errors"] = {"accel_relL2": rel(outc["accel"], refc["accel"]),
+                        "dudt_relL2": rel(outc["dudt"], refc["dudt"]),
+                        "pairs_oracle": refc["pairs_force"]}
+        log("C4 errors", c4["errors"])
 
     line = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
@@ -235,7 +254,7 @@ def main():
                 "workload": "sedov64 (same particles, zero velocity), forward only",
                 "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
+        "c4_268": c4, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     if args.calibration_copy:

@@ -522,10 +522,12 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     crk_status st = build_cells<R>(ctx, s, n, x);
     if (st != CRK_OK) return st;
     if (P.search == 0 && attempt == 0) {
-      // a cell holding more than 1024 particles means strong clustering:
-      // the cell list would need huge candidate lists there
+      // a cell holding more than 1024 particles and 16x the mean occupancy
+      // means strong clustering: the cell list would need huge candidate
+      // lists there (a high resolution alone raises every cell alike)
       CRK_HIP(read_counters(ctx, s), "cell occupancy");
-      if (ctx->host_cnt[CNT_CELL_MAX] > 1024) {
+      const double mean_occ = (double)n / ((double)ctx->G * ctx->G * ctx->G);
+      if ((double)ctx->host_cnt[CNT_CELL_MAX] > std::max(1024.0, 16.0 * mean_occ)) {
         use_tree = true;
         CRK_HIP(tend(ctx, P_CELLS, s), "event");
         break;
@@ -555,8 +557,13 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     CRK_HIP(hipGetLastError(), "h solve launch");
     CRK_HIP(read_counters(ctx, s), "h solve");
     if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
-      if (P.search == 0 && ctx->host_cnt[CNT_SCR_OVERFLOW] > 1024) {
-        use_tree = true;  // clustered: the cell list would need huge candidate lists
+      // clustered: some particle has far more candidates than the mean
+      // density gives within the candidate radius (rcap <= ell)
+      const double expect = 4.18879 * ctx->rcap * ctx->rcap * ctx->rcap * (double)n /
+                            (P.box * P.box * P.box);
+      if (P.search == 0 &&
+          (double)ctx->host_cnt[CNT_SCR_OVERFLOW] > std::max(1024.0, 16.0 * expect)) {
+        use_tree = true;
         break;
       }
       ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);

@@ -28,6 +28,7 @@ workload k.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass, field
 
@@ -122,6 +123,15 @@ def sedov64(k: int = 2) -> ParticleSet:
 
 def sedov64_v(k: int = 4) -> ParticleSet:
     return _sedov(64, k, True)
+
+
+def at_resolution(ps: ParticleSet, n_h: float) -> ParticleSet:
+    """The same particles with n_h particles per kernel radius (first h guess scaled to match).
+
+    n_h = 4 is the paper's production resolution for gas (about 268 neighbours)."""
+    q = dataclasses.replace(ps, h=ps.h * (n_h / ps.n_h), n_h=n_h, meta=dict(ps.meta))
+    q.name = "%s_nh%g" % (ps.name, n_h)
+    return q
 
 
 def sedov(n_side: int, k: int = 2, with_velocity: bool = False) -> ParticleSet:
