@@ -507,16 +507,17 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   if (!(h0max < 0.5 * P.box))
     return fail(ctx, CRK_EDOMAIN, "smoothing length must stay below half the box");
 
+  // candidates reach two cell sides (a 5x5x5 stencil walked with culling)
   double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
-  ctx->G = choose_grid(P.box, reach, n);
+  ctx->G = choose_grid(P.box, 0.5 * reach, n);
   ctx->ell = P.box / ctx->G;
   ctx->lattice = 0;
   const int64_t npad = ((n + 63) / 64) * 64;
   bool solved = false;
   bool use_tree = P.search == 2;
   for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
-    // candidates reach the cell side when h is solved, the largest h otherwise
-    ctx->rcap = P.h_mode == 1 ? ctx->ell : h0max;
+    // candidates reach two cell sides when h is solved, the largest h otherwise
+    ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : h0max;
     CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
     CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
     crk_status st = build_cells<R>(ctx, s, n, x);
@@ -838,7 +839,7 @@ crk_status crk_forward(crk_ctx* ctx, void* hip_stream, long long n, const double
     ctx->n_last = 0;
     return CRK_OK;
   }
-  if (n > (1ll << 27) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^27 - 1 particles");
+  if (n > (1ll << 25) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^25 - 1 particles");
   if (!x || !v || !m || !u || !h || !V || !rho || !A || !B || !gradA || !gradB || !gradv ||
       !accel || !dudt)
     return fail(ctx, CRK_EINVAL, "null array argument");

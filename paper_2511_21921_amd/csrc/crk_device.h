@@ -117,19 +117,24 @@ __host__ __device__ inline void kc_apply(const KC<R>& k, const R x[3], R W, cons
 // --------------------------------------------------------- cell list ----
 // Positions are stored as offsets xi from the centre of their cell (FP64
 // difference, rounded once to Real). For a neighbour j found through
-// stencil offset d in {-1,0,1}^3 of i's cell, the periodic separation is
+// stencil offset d in {-2,...,2}^3 of i's cell (cells are at least half the
+// candidate radius wide), the periodic separation is
 // x_ij = xi_i - xi_j - d * ell, exact up to one rounding of each term.
-// A neighbour-list entry packs the sorted index of j (high 27 bits) with
-// the stencil code 9*(dz+1) + 3*(dy+1) + (dx+1) (low 5 bits).
+// A neighbour-list entry packs the sorted index of j (high 25 bits) with
+// the stencil code 25*(dz+2) + 5*(dy+2) + (dx+2) (low 7 bits).
 
-constexpr int kCodeBits = 5;
-constexpr uint32_t kCodeMask = 31u;
-constexpr int kSelfCode = 13;
+constexpr int kCodeBits = 7;
+constexpr uint32_t kCodeMask = 127u;
+constexpr int kSelfCode = 62;  // d = (0, 0, 0)
+
+__device__ inline uint32_t stencil_code(int dx, int dy, int dz) {
+  return (uint32_t)(25 * (dz + 2) + 5 * (dy + 2) + (dx + 2));
+}
 
 __device__ inline void code_offset(uint32_t code, int& dx, int& dy, int& dz) {
-  dz = int(code / 9u) - 1;
-  dy = int((code / 3u) % 3u) - 1;
-  dx = int(code % 3u) - 1;
+  dz = int(code / 25u) - 2;
+  dy = int((code / 5u) % 5u) - 2;
+  dx = int(code % 5u) - 2;
 }
 
 template <class R>

@@ -173,10 +173,10 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 }
 
 // ---------------------------------------------------------- candidates ----
-// One traversal of the 27 stencil cells per particle collects every j != i
-// with r_ij < rcap (rcap >= every h), storing the packed entry and
-// (r, m_j / m_i). The h solve, the fixed-h volume and the neighbour list all
-// read this list instead of walking the cells again.
+// One traversal of the stencil cells per particle collects every j != i
+// with r_ij < rcap (rcap >= every h, at most two cell sides), storing the
+// packed entry and (r, m_j / m_i). The h solve, the fixed-h volume and the
+// neighbour list all read this list instead of walking the cells again.
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
@@ -190,27 +190,40 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   int cnt = 0;
   Stage4<uint32_t> se;
   Stage4<R> sr, sm;
-  // Each lane walks its own 27 stencil cells: the lanes of a wave sit in one
-  // or two cells, so they load the same candidates at the same time (the
-  // loads coalesce) and no broadcast is needed.
+  // Each lane walks the cells of its own 5x5x5 stencil that come within the
+  // candidate radius of the particle (whole planes, rows and cells beyond
+  // it are skipped): the lanes of a wave sit in one or two cells, so they
+  // load the same candidates at the same time and the loads coalesce.
   if (active) {
     const uint32_t c3 = S.cell3[s];
     const int G = S.G;
     const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
-    for (int dz = -1; dz <= 1; ++dz) {
+    const R ell = S.ell;
+    // squared distance from the particle to the slab of offset d along one axis
+    auto gap2 = [&](R xi, int d) {
+      const R lo = (R(d) - R(0.5)) * ell - xi, hi = xi - (R(d) + R(0.5)) * ell;
+      const R g = lo > hi ? lo : hi;
+      return g > R(0) ? g * g : R(0);
+    };
+    for (int dz = -2; dz <= 2; ++dz) {
+      const R gz = gap2(pi.z, dz);
+      if (!(gz < rc2)) continue;
       const int z = wrap_cell(cz + dz, G);
-      for (int dy = -1; dy <= 1; ++dy) {
+      for (int dy = -2; dy <= 2; ++dy) {
+        const R gyz = gz + gap2(pi.y, dy);
+        if (!(gyz < rc2)) continue;
         const int y = wrap_cell(cy + dy, G);
         const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
-        for (int dx = -1; dx <= 1; ++dx) {
+        for (int dx = -2; dx <= 2; ++dx) {
+          if (!(gyz + gap2(pi.x, dx) < rc2)) continue;
           const uint32_t c = rowbase + (uint32_t)wrap_cell(cx + dx, G);
-          const uint32_t code = (uint32_t)(9 * (dz + 1) + 3 * (dy + 1) + (dx + 1));
-          const R ox = R(dx) * S.ell, oy = R(dy) * S.ell, oz = R(dz) * S.ell;
+          const uint32_t code = stencil_code(dx, dy, dz);
+          const R ox = R(dx) * ell, oy = R(dy) * ell, oz = R(dz) * ell;
           const uint32_t b = S.cell_start[c];
           uint32_t e = S.cell_start[c + 1];
           if (e > (uint32_t)S.n) e = (uint32_t)S.n;
           for (uint32_t j = b; j < e; ++j) {
-            if (j == (uint32_t)s && code == 13u) continue;
+            if (j == (uint32_t)s && code == (uint32_t)kSelfCode) continue;
             const R4<R> pj = S.pos4[j];
             R x[3];
             x[0] = (pi.x - pj.x) - ox;
