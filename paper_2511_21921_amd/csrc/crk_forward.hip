@@ -416,29 +416,34 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
   const int64_t s = particle_id();
   unsigned long long g = 0, f = 0, ovf = 0, sovf = 0;
   if (s < S.n) {
-    const R4<R> pi = S.pos4[s];
-    const R hi2 = pi.w * pi.w;  // 1/h_i^2
+    // Classified by the stored candidate distance r: it is the same value
+    // from both sides of a pair (the separation is computed with both signs
+    // flipped), so j lands in i's scatter-only list exactly when i is in j's
+    // gather list, and only h_j has to be gathered.
+    const R hi = S.hbuf[s];
     int ng = 0, ns = 0;
     const int cap = S.list_cap, scap = S.slist_cap;
     Stage4<uint32_t> sg, ss;
     const int cc = S.ccnt[s] < S.scr_cap ? S.ccnt[s] : S.scr_cap;
     uint4 cb;
+    R4<R> rb;
     for (int k = 0; k < cc; ++k) {
-      if ((k & 3) == 0) cb = *reinterpret_cast<const uint4*>(S.cand + list_index(s, S.scr_cap, k));
+      if ((k & 3) == 0) {
+        const int64_t c = list_index(s, S.scr_cap, k);
+        cb = *reinterpret_cast<const uint4*>(S.cand + c);
+        rb = *reinterpret_cast<const R4<R>*>(S.scr_r + c);
+      }
       const int q = k & 3;
       const uint32_t e = q == 0 ? cb.x : (q == 1 ? cb.y : (q == 2 ? cb.z : cb.w));
+      const R r = q == 0 ? rb.x : (q == 1 ? rb.y : (q == 2 ? rb.z : rb.w));
       const uint32_t j = e >> kCodeBits;
-      const R4<R> pj = S.pos4[j];
-      R x[3];
-      pair_x(S, s, pi, pj, e, x);
-      const R r2 = dot3(x, x);
-      if (r2 * hi2 < R(1)) {
+      if (r < hi) {
         if (ng < cap) {
           sg.put(ng & 3, e);
           if ((ng & 3) == 3) sg.flush(S.nlist, s, cap, ng);
         }
         ++ng;
-      } else if (r2 * (pj.w * pj.w) < R(1)) {
+      } else if (r < S.hbuf[j]) {
         if (ns < scap) {
           ss.put(ns & 3, e);
           if ((ns & 3) == 3) ss.flush(S.slist, s, scap, ns);

@@ -74,3 +74,32 @@ def test_tree_and_cell_list_agree_fp64():
     for k in ("h", "V", "rho", "accel", "dudt"):
         assert np.abs(a[k] - b[k]).max() <= 1e-11 * np.abs(a[k]).max(), k
     assert a["stats"]["n_pairs_force"] == b["stats"]["n_pairs_force"]
+
+
+@pytest.mark.parametrize("n", [37, 64, 129])
+def test_tree_tiny_and_ragged(n):
+    """One partial leaf, exactly one leaf, and a ragged third leaf.
+
+    With 14 neighbours and so few particles a sixth of the moment matrices
+    are singular and several more are nearly so; rounding in the inverse is
+    amplified by their condition numbers, so the bounds are ten times the
+    well-conditioned FP64 ones.
+    """
+    ps = synth.random_small(n, 80 + n, n_ngb=14, mass_spread=0.1)
+    _compare(ps, FP64, {k: 10 * b for k, b in FP64_BOUNDS.items()}, search=TREE)
+
+
+def test_tree_fixed_h_unequal_masses():
+    ps = synth.random_small(2000, 90, mass_spread=0.1)
+    ps.h_mode = 0
+    g, o, _ = _compare(ps, FP64, FP64_BOUNDS, search=TREE)
+    assert g["stats"]["n_pairs_force"] == o["pairs_force"]
+
+
+def test_tree_empty_input():
+    ps = synth.random_small(300, 91)
+    g, ctx = _gpu.run(ps, FP32, search=TREE)
+    x, v, m, u, h = _gpu.to_dev(ps, FP32)
+    out = ctx.forward(x[:, :0].contiguous(), v[:, :0].contiguous(), m[:0], u[:0], h[:0],
+                      stats=True)
+    assert out["stats"]["n_pairs_force"] == 0
