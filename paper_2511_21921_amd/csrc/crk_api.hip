@@ -47,7 +47,7 @@ struct crk_ctx {
   bool events_ready = false;
   std::string err;
   // workspace
-  Buf keys_a, keys_b, vals_a, vals_b, cell_count, cell_start, sort_tmp, scan_tmp;
+  Buf keys_a, keys_b, vals_a, vals_b, cell_start, sort_tmp, scan_tmp;
   Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, slist, ng, ns, scr_r, scr_m,
       cand, ccnt, cell3;
   Buf cnt;
@@ -59,7 +59,8 @@ struct crk_ctx {
   int lattice = 0;
   // adjoint workspace
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
-  unsigned long long* host_cnt = nullptr;
+  unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
+  unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
   int slist_cap = 32;
   int scr_cap = 192;
@@ -166,7 +167,7 @@ hipError_t ensure_particles(crk_ctx* c, int64_t n) {
   ENS(ns, 4 * npad);
   ENS(ccnt, 4 * npad);
   ENS(cell3, 4 * npad);
-  ENS(cnt, 8 * CNT_COUNT);
+  ENS(cnt, 8 * CNT_COUNT * kCntSpread);
   if (c->p.store_corrections) ENS(mom, 40 * R * npad);
 #undef ENS
   return hipSuccess;
@@ -266,10 +267,26 @@ hipError_t tend(crk_ctx* c, int k, hipStream_t s) {
   return hipEventRecord(c->ev1[k], s);
 }
 
+// Copies the counter slots to the host and folds each counter's slots.
 hipError_t read_counters(crk_ctx* c, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(c->host_cnt, c->cnt.p, 8 * CNT_COUNT, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(c->host_raw, c->cnt.p, 8 * CNT_COUNT * kCntSpread,
+                                hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < CNT_COUNT; ++k) {
+    const bool is_max = k == CNT_HMAX_BITS || k == CNT_H_ITER_MAX || k == CNT_SCR_OVERFLOW ||
+                        k == CNT_LIST_OVERFLOW || k == CNT_SLIST_OVERFLOW ||
+                        k == CNT_MMAX_BITS || k == CNT_MINVMAX_BITS ||
+                        k == CNT_HMAX_OUT_BITS || k == CNT_CELL_MAX;
+    unsigned long long v = 0;
+    for (int t = 0; t < kCntSpread; ++t) {
+      const unsigned long long x = c->host_raw[k * kCntSpread + t];
+      v = is_max ? (x > v ? x : v) : v + x;
+    }
+    c->host_cnt[k] = v;
+  }
+  return hipSuccess;
 }
 
 double bits_to_double(unsigned long long b) {
@@ -291,21 +308,17 @@ int choose_grid(double box, double R, int64_t n) {
 template <class R>
 crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) {
   const int64_t ncell = (int64_t)ctx->G * ctx->G * ctx->G;
-  CRK_HIP(ensure(ctx->cell_count, 4 * (size_t)(ncell + 1)), "alloc cell counts");
   CRK_HIP(ensure(ctx->cell_start, 4 * (size_t)(ncell + 1)), "alloc cell starts");
-  CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(ncell + 1)), "alloc scan");
-  CRK_HIP(hipMemsetAsync(ctx->cell_count.p, 0, 4 * (size_t)(ncell + 1), s), "memset");
-  launch_keys(x, n, ctx->p.box, ctx->G, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
-              (uint32_t*)ctx->cell_count.p, (unsigned long long*)ctx->cnt.p, s);
+  launch_keys(x, n, ctx->p.box, ctx->G, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p, s);
   int bits = 1;
   while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
   CRK_HIP(radix_sort_pairs((uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
                            (uint32_t*)ctx->keys_b.p, (uint32_t*)ctx->vals_b.p, n, bits,
                            (uint32_t*)ctx->sort_tmp.p, s),
           "radix sort");
-  CRK_HIP(exclusive_scan_u32((const uint32_t*)ctx->cell_count.p, (uint32_t*)ctx->cell_start.p,
-                             ncell + 1, (uint32_t*)ctx->scan_tmp.p, s),
-          "scan");
+  launch_cell_bounds((const uint32_t*)ctx->keys_a.p, n, ncell, (uint32_t*)ctx->cell_start.p,
+                     (unsigned long long*)ctx->cnt.p, s);
+  CRK_HIP(hipGetLastError(), "cell bounds launch");
   return CRK_OK;
 }
 
@@ -353,7 +366,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     lv[40 + t] = ctx->lvl_cnt[t];
   }
   CRK_HIP(hipMemcpyAsync(ctx->lvl.p, lv, sizeof(lv), hipMemcpyHostToDevice, s), "tree levels");
-  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
   CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
   launch_morton(x, n, P.box, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p, s);
   CRK_HIP(radix_sort_pairs((uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p,
@@ -395,12 +408,12 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       solved = true;
       break;
     }
-    const size_t words = 256 * (size_t)ctx->host_rows[1];  // a row: 4 entries of 64 slots
+    const size_t words = 1024 * (size_t)ctx->host_rows[1];  // a row: 16 entries of 64 slots
     CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * words), "alloc candidates");
     if (!ctx->equal_mass)
       CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * words), "alloc candidates");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED, 0, 8, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY, 0, 8, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED * kCntSpread, 0, 8 * kCntSpread, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);
     CRK_HIP(tbegin(ctx, P_CAND, s), "event");
     launch_candidates_tree<R>(S, P.kernel, s);
@@ -453,8 +466,8 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   CRK_HIP(offsets((const int*)ctx->ccnt.p, 4, wg, lg, &ctx->host_rows[0]), "list rows");
   for (int attempt = 0;; ++attempt) {
     CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     {
       State<R> S = make_state<R>(ctx, n);
       launch_gather_tree<R>(S, s);
@@ -491,7 +504,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   ctx->n_last = -1;
   CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
-  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
   launch_check_inputs<R>(h, m, u, n, dcnt, s);
   CRK_HIP(hipGetLastError(), "input check launch");
   CRK_HIP(read_counters(ctx, s), "input check");
@@ -518,7 +531,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
     // candidates reach two cell sides when h is solved, the largest h otherwise
     ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : h0max;
-    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT, s), "memset");
+    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
     CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
     crk_status st = build_cells<R>(ctx, s, n, x);
     if (st != CRK_OK) return st;
@@ -571,9 +584,12 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       continue;  // same grid, larger candidate capacity
     }
     if (P.h_mode == 1 && ctx->host_cnt[CNT_H_CAPPED]) {
-      if (ctx->G == 1) return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
-      // cells too small for some root: widen them and solve again
-      ctx->G = std::max(1, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
+      // a root beyond a candidate radius of half the box breaks h < box / 2
+      if (ctx->rcap >= 0.5 * P.box)
+        return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
+      // cells too small for some root: widen them (to no fewer than 2 per
+      // side, which the row wrap of the stencil walk assumes) and solve again
+      ctx->G = std::max(2, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
       ctx->ell = P.box / ctx->G;
       continue;
     }
@@ -605,8 +621,8 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
       CRK_HIP(ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap), "alloc neighbour list");
       State<R> S = make_state<R>(ctx, n);
-      CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER, 0, 8 * 2, s), "memset");
-      CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW, 0, 8 * 2, s), "memset");
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
       CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
       launch_nlist<R>(S, s);
       CRK_HIP(tend(ctx, P_NLIST, s), "event");
@@ -753,11 +769,12 @@ crk_status crk_create(crk_ctx** out, const crk_params* p) {
   if (st != CRK_OK) return st;
   crk_ctx* c = new crk_ctx();
   c->p = *p;
-  if (hipHostMalloc((void**)&c->host_cnt, 8 * CNT_COUNT, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->host_raw, 8 * CNT_COUNT * kCntSpread, hipHostMallocDefault) !=
+      hipSuccess) {
     delete c;
     return CRK_ENOMEM;
   }
-  std::memset(c->host_cnt, 0, 8 * CNT_COUNT);
+  std::memset(c->host_raw, 0, 8 * CNT_COUNT * kCntSpread);
   *out = c;
   return CRK_OK;
 }
@@ -789,14 +806,14 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
 
 crk_status crk_destroy(crk_ctx* c) {
   if (!c) return CRK_OK;
-  Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_count, &c->cell_start,
+  Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_start,
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
-  if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+  if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)
     for (int i = 0; i < P_NPASS; ++i) {
       (void)hipEventDestroy(c->ev0[i]);

@@ -201,6 +201,45 @@ struct Stage4 {
     q.w = v3;
     *reinterpret_cast<typename Vec4T<T>::V*>(base + slot_at(b, k & ~3)) = q;
   }
+  // the same for a candidate list addressed by its group_base b
+  __device__ inline void flush_group(T* base, int64_t b, int k) const;
 };
+
+// Candidate scratch: a lane's entries in groups of 16 held contiguously (64
+// bytes of 4-byte entries), the groups of a wave's 64 lanes side by side (a
+// row of 1024 entries). A lane fills a group with four 16-byte stores a few
+// candidates apart, so each line is complete while it is still in the L2;
+// with the 4-entry chunks of all lanes interleaved, lanes that advance at
+// different speeds left lines half written and HBM took several partial
+// writes per line. Readers take a whole group (four 16-byte loads) at once.
+__device__ inline int64_t group_base(int64_t row0, int64_t i) {
+  return (row0 * 64 + (i & 63)) << 4;
+}
+__device__ inline int64_t group_at(int64_t base, int k) {
+  return base + ((int64_t)(k >> 4) << 10) + (k & 15);
+}
+
+template <class T>
+__device__ inline void Stage4<T>::flush_group(T* base, int64_t b, int k) const {
+  typename Vec4T<T>::V q;
+  q.x = v0;
+  q.y = v1;
+  q.z = v2;
+  q.w = v3;
+  *reinterpret_cast<typename Vec4T<T>::V*>(base + group_at(b, k & ~3)) = q;
+}
+
+// the 16 entries of the group that starts at p (four vector loads)
+template <class T>
+__device__ inline void load_group(const T* p, T v[16]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const typename Vec4T<T>::V q = reinterpret_cast<const typename Vec4T<T>::V*>(p)[c];
+    v[4 * c] = q.x;
+    v[4 * c + 1] = q.y;
+    v[4 * c + 2] = q.z;
+    v[4 * c + 3] = q.w;
+  }
+}
 
 }  // namespace crk

@@ -95,10 +95,10 @@ __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h
       mb = part[k][2] > mb ? part[k][2] : mb;
       ib = part[k][3] > ib ? part[k][3] : ib;
     }
-    if (hb) atomicMax(&cnt[CNT_HMAX_BITS], hb);
-    if (bad) atomicAdd(&cnt[CNT_BAD_INPUT], bad);
-    if (mb) atomicMax(&cnt[CNT_MMAX_BITS], mb);
-    if (ib) atomicMax(&cnt[CNT_MINVMAX_BITS], ib);
+    if (hb) atomicMax(cnt_at(cnt, CNT_HMAX_BITS), hb);
+    if (bad) atomicAdd(cnt_at(cnt, CNT_BAD_INPUT), bad);
+    if (mb) atomicMax(cnt_at(cnt, CNT_MMAX_BITS), mb);
+    if (ib) atomicMax(cnt_at(cnt, CNT_MINVMAX_BITS), ib);
   }
 }
 
@@ -111,26 +111,56 @@ __device__ inline double wrap_pos(double xa, double L) {
 
 __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, int64_t n,
                                                  double L, int G, uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals,
-                                                 uint32_t* __restrict__ ccount,
-                                                 unsigned long long* __restrict__ cnt) {
+                                                 uint32_t* __restrict__ vals) {
   const int64_t i = particle_id();
-  unsigned long long occ = 0;
-  if (i < n) {
-    const double inv = (double)G / L;
-    int c[3];
+  if (i >= n) return;
+  const double inv = (double)G / L;
+  int c[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double t = wrap_pos(x[a * n + i], L);
-      int k = (int)(t * inv);
-      c[a] = k < G ? k : G - 1;
-    }
-    const uint32_t key = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
-    keys[i] = key;
-    vals[i] = (uint32_t)i;
-    occ = (unsigned long long)atomicAdd(&ccount[key], 1u) + 1ull;  // occupancy so far
+  for (int a = 0; a < 3; ++a) {
+    const double t = wrap_pos(x[a * n + i], L);
+    int k = (int)(t * inv);
+    c[a] = k < G ? k : G - 1;
   }
-  wave_max_u64(&cnt[CNT_CELL_MAX], occ);
+  keys[i] = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
+  vals[i] = (uint32_t)i;
+}
+
+// cell_start[c] = first sorted position whose key is >= c, for c = 0..ncell
+// (a binary search of the sorted keys per cell; no atomics). The largest
+// occupancy start[c + 1] - start[c] is reduced per block into one atomic.
+__global__ void __launch_bounds__(kBlock) k_cell_bounds(const uint32_t* __restrict__ keys,
+                                                        int64_t n, int64_t ncell,
+                                                        uint32_t* __restrict__ start,
+                                                        unsigned long long* __restrict__ cnt) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  auto lower = [&](int64_t v) {
+    int64_t lo = 0, hi = n;  // keys[lo - 1] < v <= keys[hi]
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)keys[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  unsigned long long occ = 0;
+  if (c <= ncell) {
+    const int64_t b = lower(c);
+    start[c] = (uint32_t)b;
+    if (c < ncell) occ = (unsigned long long)(lower(c + 1) - b);
+  }
+  __shared__ unsigned long long red[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = __shfl_xor(occ, o, 64);
+    occ = t > occ ? t : occ;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = occ;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int w = 0; w < kBlock / 64; ++w) m = red[w] > m ? red[w] : m;
+    if (m) atomicMax(cnt_at(cnt, CNT_CELL_MAX), m);
+  }
 }
 
 template <class R>
@@ -158,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   q.x = xi[0];
   q.y = xi[1];
   q.z = xi[2];
-  q.w = R(0);
+  q.w = R(c[0]);  // the cell's x index until the h solve is done (then 1/h)
   S.pos4[s] = q;
   R4<R> w;
   w.x = v[p];
@@ -177,119 +207,196 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 // with r_ij < rcap (rcap >= every h, at most two cell sides), storing the
 // packed entry and (r, m_j / m_i). The h solve, the fixed-h volume and the
 // neighbour list all read this list instead of walking the cells again.
+// EM: all masses equal (m_j / m_i = 1 is not stored).
 
-template <class R>
+template <class R, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   const int64_t s = particle_id();
-  const bool active = s < S.n;
-  const int64_t sc = active ? s : 0;
-  const R4<R> pi = S.pos4[sc];
-  const R mi_inv = R(1) / S.mass[sc];
+  if (s >= S.n) return;
+  const R4<R> pi = S.pos4[s];
+  const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
   const R rc2 = S.rcap * S.rcap;
-  const int cap = S.scr_cap;
+  int cap;
+  const int64_t base = scratch_base(S, s, cap);
   int cnt = 0;
-  Stage4<uint32_t> se;
-  Stage4<R> sr, sm;
   // Each lane walks the cells of its own 5x5x5 stencil that come within the
-  // candidate radius of the particle (whole planes, rows and cells beyond
-  // it are skipped): the lanes of a wave sit in one or two cells, so they
-  // load the same candidates at the same time and the loads coalesce.
-  if (active) {
-    const uint32_t c3 = S.cell3[s];
-    const int G = S.G;
-    const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
-    const R ell = S.ell;
-    // squared distance from the particle to the slab of offset d along one axis
-    auto gap2 = [&](R xi, int d) {
-      const R lo = (R(d) - R(0.5)) * ell - xi, hi = xi - (R(d) + R(0.5)) * ell;
-      const R g = lo > hi ? lo : hi;
-      return g > R(0) ? g * g : R(0);
-    };
-    for (int dz = -2; dz <= 2; ++dz) {
-      const R gz = gap2(pi.z, dz);
-      if (!(gz < rc2)) continue;
-      const int z = wrap_cell(cz + dz, G);
-      for (int dy = -2; dy <= 2; ++dy) {
-        const R gyz = gz + gap2(pi.y, dy);
-        if (!(gyz < rc2)) continue;
-        const int y = wrap_cell(cy + dy, G);
-        const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
-        for (int dx = -2; dx <= 2; ++dx) {
-          if (!(gyz + gap2(pi.x, dx) < rc2)) continue;
-          const uint32_t c = rowbase + (uint32_t)wrap_cell(cx + dx, G);
-          const uint32_t code = stencil_code(dx, dy, dz);
-          const R ox = R(dx) * ell, oy = R(dy) * ell, oz = R(dz) * ell;
-          const uint32_t b = S.cell_start[c];
-          uint32_t e = S.cell_start[c + 1];
-          if (e > (uint32_t)S.n) e = (uint32_t)S.n;
-          for (uint32_t j = b; j < e; ++j) {
-            if (j == (uint32_t)s && code == (uint32_t)kSelfCode) continue;
-            const R4<R> pj = S.pos4[j];
-            R x[3];
-            x[0] = (pi.x - pj.x) - ox;
-            x[1] = (pi.y - pj.y) - oy;
-            x[2] = (pi.z - pj.z) - oz;
-            const R r2 = dot3(x, x);
-            if (r2 < rc2) {
-              if (cnt < cap) {
-                const int slot = cnt & 3;
-                se.put(slot, (j << kCodeBits) | code);
-                sr.put(slot, Sc<R>::sqrt(r2));
-                if (!S.equal_mass) sm.put(slot, S.mass[j] * mi_inv);
-                if (slot == 3) {
-                  se.flush(S.cand, s, cap, cnt);
-                  sr.flush(S.scr_r, s, cap, cnt);
-                  if (!S.equal_mass) sm.flush(S.scr_m, s, cap, cnt);
-                }
-              }
-              ++cnt;
+  // candidate radius of the particle (planes and rows beyond it are skipped).
+  // In a row the cells within reach form one run of dx (the distance to a
+  // cell is convex in dx), and consecutive cells of a row hold consecutive
+  // particles, so the run is one contiguous range of particles (split where
+  // the row wraps), read four at a time with the loads in flight together.
+  // A particle's cell within the run comes from the x index kept in pos4.w.
+  // Accepted candidates are shifted into four registers per array and
+  // written as one 16-byte store per array every fourth one: the lanes of a
+  // wave run their tests in step, so whatever the accept path costs, the
+  // wave pays at almost every test (shifting needs no slot selects).
+  const uint32_t c3 = S.cell3[s];
+  const int G = S.G;
+  const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
+  const R ell = S.ell;
+  const uint32_t n = (uint32_t)S.n;
+  uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+  R r0 = R(0), r1 = R(0), r2s = R(0), r3 = R(0);
+  R m0 = R(0), m1 = R(0), m2 = R(0), m3 = R(0);
+  auto flush = [&](int k) {  // the chunk of entries k & ~3 .. (k & ~3) + 3
+    const int64_t q = group_at(base, k & ~3);
+    *reinterpret_cast<uint4*>(S.cand + q) = make_uint4(e0, e1, e2, e3);
+    R4<R> t;
+    t.x = r0;
+    t.y = r1;
+    t.z = r2s;
+    t.w = r3;
+    *reinterpret_cast<R4<R>*>(S.scr_r + q) = t;
+    if (!EM) {
+      t.x = m0;
+      t.y = m1;
+      t.z = m2;
+      t.w = m3;
+      *reinterpret_cast<R4<R>*>(S.scr_m + q) = t;
+    }
+  };
+  // squared distance from the particle to the slab of offset d along one axis
+  auto gap2 = [&](R xi, int d) {
+    const R lo = (R(d) - R(0.5)) * ell - xi, hi = xi - (R(d) + R(0.5)) * ell;
+    const R g = lo > hi ? lo : hi;
+    return g > R(0) ? g * g : R(0);
+  };
+  // cells dx = d0 .. d1 of the row, stored from cell c0 (x index x0) on; the
+  // particle itself can only turn up in the row through its own cell
+  auto walk = [&](uint32_t c0, int x0, int d0, int d1, int dy, int dz, auto own_row) {
+    const uint32_t b = S.cell_start[c0];
+    uint32_t e = S.cell_start[c0 + (uint32_t)(d1 - d0 + 1)];
+    if (e > n) e = n;
+    // x offset of cell x of the run: (x - x0 + d0) ell; stencil code likewise
+    const int xoff = d0 - x0;
+    const int code0 = (int)stencil_code(0, dy, dz);
+    const R oy = R(dy) * ell, oz = R(dz) * ell;
+    for (uint32_t j0 = b; j0 < e; j0 += 4) {
+      R4<R> pj[4];
+      R mj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t j = j0 + u < e ? j0 + u : e - 1;
+        pj[u] = S.pos4[j];
+        if (!EM) mj[u] = S.mass[j];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of their first use
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t j = j0 + u;
+        const int dx = (int)pj[u].w + xoff;
+        R x[3];
+        x[0] = (pi.x - pj[u].x) - R(dx) * ell;
+        x[1] = (pi.y - pj[u].y) - oy;
+        x[2] = (pi.z - pj[u].z) - oz;
+        const R r2 = dot3(x, x);
+        bool ok = j < e && r2 < rc2;
+        if (decltype(own_row)::value) ok = ok && !(j == (uint32_t)s && dx == 0);
+        if (ok) {
+          if (cnt < cap) {
+            e0 = e1;
+            e1 = e2;
+            e2 = e3;
+            e3 = (j << kCodeBits) | (uint32_t)(code0 + dx);
+            r0 = r1;
+            r1 = r2s;
+            r2s = r3;
+            r3 = Sc<R>::sqrt(r2);
+            if (!EM) {
+              m0 = m1;
+              m1 = m2;
+              m2 = m3;
+              m3 = mj[u] * mi_inv;
             }
+            if ((cnt & 3) == 3) flush(cnt);
           }
+          ++cnt;
         }
       }
     }
-  }
-  unsigned long long ovf = 0;
-  if (active) {
-    const int stored = cnt < cap ? cnt : cap;
-    if (stored & 3) {
-      se.flush(S.cand, s, cap, stored - 1);
-      sr.flush(S.scr_r, s, cap, stored - 1);
-      if (!S.equal_mass) sm.flush(S.scr_m, s, cap, stored - 1);
+  };
+  for (int dz = -2; dz <= 2; ++dz) {
+    const R gz = gap2(pi.z, dz);
+    if (!(gz < rc2)) continue;
+    const int z = wrap_cell(cz + dz, G);
+    for (int dy = -2; dy <= 2; ++dy) {
+      const R gyz = gz + gap2(pi.y, dy);
+      if (!(gyz < rc2)) continue;
+      const int y = wrap_cell(cy + dy, G);
+      const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
+      int dlo = 3, dhi = -3;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx)
+        if (gyz + gap2(pi.x, dx) < rc2) {
+          dlo = dx < dlo ? dx : dlo;
+          dhi = dx;
+        }
+      // the run split where the row wraps (G >= 2): x < 0, 0 <= x < G, x >= G
+      const int a1 = min(dhi, -cx - 1);
+      const int b0 = max(dlo, -cx), b1 = min(dhi, G - 1 - cx);
+      const int c0 = max(dlo, G - cx);
+      auto row = [&](auto own_row) {
+        if (dlo <= a1)
+          walk(rowbase + (uint32_t)(cx + dlo + G), cx + dlo + G, dlo, a1, dy, dz, own_row);
+        if (b0 <= b1) walk(rowbase + (uint32_t)(cx + b0), cx + b0, b0, b1, dy, dz, own_row);
+        if (c0 <= dhi)
+          walk(rowbase + (uint32_t)(cx + c0 - G), cx + c0 - G, c0, dhi, dy, dz, own_row);
+      };
+      if (dy == 0 && dz == 0)
+        row(std::true_type());
+      else
+        row(std::false_type());
     }
-    // only the stored entries are ever read; the overflow makes the host
-    // grow the capacity and run the candidate pass again
-    S.ccnt[s] = stored;
-    if (cnt > cap) ovf = (unsigned long long)cnt;
   }
-  wave_max_u64(&S.cnt[CNT_SCR_OVERFLOW], ovf);
+  {
+    // the last partial chunk: its m entries are the newest m in the registers
+    const int st = cnt < cap ? cnt : cap, m = st & 3;
+    if (m) {
+      if (m == 1) {
+        e0 = e3;
+        r0 = r3;
+        m0 = m3;
+      } else if (m == 2) {
+        e0 = e2; e1 = e3;
+        r0 = r2s; r1 = r3;
+        m0 = m2; m1 = m3;
+      } else {
+        e0 = e1; e1 = e2; e2 = e3;
+        r0 = r1; r1 = r2s; r2s = r3;
+        m0 = m1; m1 = m2; m2 = m3;
+      }
+      flush(st - 1);
+    }
+  }
+  // only the stored entries are ever read; the overflow makes the host grow
+  // the capacity and run the candidate pass again
+  S.ccnt[s] = cnt < cap ? cnt : cap;
+  if (cnt > cap) atomicMax(cnt_at(S.cnt, CNT_SCR_OVERFLOW), (unsigned long long)cnt);
 }
 
 // sum_k (m_k/m_i) w(r_k / h) over the candidates plus the self term w(0), and
-// dsum = sum_k (m_k/m_i) w'(q_k) q_k. The list is read a 4-entry chunk (one
-// 16- or 32-byte load) at a time.
+// dsum = sum_k (m_k/m_i) w'(q_k) q_k. The list is read a 16-entry group at a
+// time, its loads issued together.
 template <class R, int K>
 __device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h, R& dsum) {
   const R hinv = R(1) / h;
   R sum = R(Shape<K>::w0), ds = R(0);
-  for (int k = 0; k < cnt; k += 4) {
-    const int64_t e = slot_at(base, k);
-    const R4<R> rq = *reinterpret_cast<const R4<R>*>(S.scr_r + e);
-    R4<R> mq;
-    if (S.equal_mass) {
-      mq.x = mq.y = mq.z = mq.w = R(1);
-    } else {
-      mq = *reinterpret_cast<const R4<R>*>(S.scr_m + e);
-    }
-    const R rr[4] = {rq.x, rq.y, rq.z, rq.w}, mm[4] = {mq.x, mq.y, mq.z, mq.w};
+  for (int k = 0; k < cnt; k += 16) {
+    const int64_t e = group_at(base, k);
+    R rr[16], mm[16];
+    load_group(S.scr_r + e, rr);
+    if (!S.equal_mass) load_group(S.scr_m + e, mm);
+    const int left = cnt - k;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (k + t >= cnt) break;
-      const R q = rr[t] * hinv;
+    for (int t = 0; t < 16; ++t) {
+      // entries past the count are moved outside the support (w = w' = 0)
+      const bool in = t < left;
+      const R q = in ? rr[t] * hinv : R(2);
       R w, dw;
       Shape<K>::eval(q, w, dw);
-      sum += mm[t] * w;
-      ds += mm[t] * dw * q;
+      const R mt = S.equal_mass ? R(1) : (in ? mm[t] : R(0));
+      sum += mt * w;
+      ds += mt * dw * q;
     }
   }
   dsum = ds;
@@ -375,10 +482,10 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       if (S.todo) S.todo[s] = 0;
     }
   }
-  wave_max_u64(&S.cnt[CNT_H_ITER_MAX], iters);
-  wave_add_u64(&S.cnt[CNT_H_UNCONV], unconv);
-  wave_add_u64(&S.cnt[CNT_H_CAPPED], capped);
-  wave_max_u64(&S.cnt[CNT_HMAX_OUT_BITS], hbits);
+  wave_max_u64(cnt_at(S.cnt, CNT_H_ITER_MAX), iters);
+  wave_add_u64(cnt_at(S.cnt, CNT_H_UNCONV), unconv);
+  wave_add_u64(cnt_at(S.cnt, CNT_H_CAPPED), capped);
+  wave_max_u64(cnt_at(S.cnt, CNT_HMAX_OUT_BITS), hbits);
 }
 
 // Fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included.
@@ -424,31 +531,36 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     int ng = 0, ns = 0;
     const int cap = S.list_cap, scap = S.slist_cap;
     Stage4<uint32_t> sg, ss;
-    const int cc = S.ccnt[s] < S.scr_cap ? S.ccnt[s] : S.scr_cap;
-    uint4 cb;
-    R4<R> rb;
-    for (int k = 0; k < cc; ++k) {
-      if ((k & 3) == 0) {
-        const int64_t c = list_index(s, S.scr_cap, k);
-        cb = *reinterpret_cast<const uint4*>(S.cand + c);
-        rb = *reinterpret_cast<const R4<R>*>(S.scr_r + c);
-      }
-      const int q = k & 3;
-      const uint32_t e = q == 0 ? cb.x : (q == 1 ? cb.y : (q == 2 ? cb.z : cb.w));
-      const R r = q == 0 ? rb.x : (q == 1 ? rb.y : (q == 2 ? rb.z : rb.w));
-      const uint32_t j = e >> kCodeBits;
-      if (r < hi) {
-        if (ng < cap) {
-          sg.put(ng & 3, e);
-          if ((ng & 3) == 3) sg.flush(S.nlist, s, cap, ng);
+    int ccap;
+    const int64_t base = scratch_base(S, s, ccap);
+    const int cc = S.ccnt[s] < ccap ? S.ccnt[s] : ccap;
+    for (int k = 0; k < cc; k += 16) {
+      const int64_t c = group_at(base, k);
+      uint32_t ee[16];
+      R rr[16], hj[16];
+      load_group(S.cand + c, ee);
+      load_group(S.scr_r + c, rr);
+      // h_j only where the pair is not a gather pair of i, all loads at once
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        hj[t] = (k + t < cc && !(rr[t] < hi)) ? S.hbuf[ee[t] >> kCodeBits] : R(0);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const bool in = k + t < cc;
+        const uint32_t e = ee[t];
+        if (in && rr[t] < hi) {
+          if (ng < cap) {
+            sg.put(ng & 3, e);
+            if ((ng & 3) == 3) sg.flush(S.nlist, s, cap, ng);
+          }
+          ++ng;
+        } else if (in && rr[t] < hj[t]) {
+          if (ns < scap) {
+            ss.put(ns & 3, e);
+            if ((ns & 3) == 3) ss.flush(S.slist, s, scap, ns);
+          }
+          ++ns;
         }
-        ++ng;
-      } else if (r < S.hbuf[j]) {
-        if (ns < scap) {
-          ss.put(ns & 3, e);
-          if ((ns & 3) == 3) ss.flush(S.slist, s, scap, ns);
-        }
-        ++ns;
       }
     }
     const int gst = ng < cap ? ng : cap, sst = ns < scap ? ns : scap;
@@ -461,10 +573,10 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     if (ng > cap) ovf = (unsigned long long)ng;
     if (ns > scap) sovf = (unsigned long long)ns;
   }
-  wave_add_u64(&S.cnt[CNT_PAIRS_GATHER], g);
-  wave_add_u64(&S.cnt[CNT_PAIRS_FORCE], f);
-  wave_max_u64(&S.cnt[CNT_LIST_OVERFLOW], ovf);
-  wave_max_u64(&S.cnt[CNT_SLIST_OVERFLOW], sovf);
+  wave_add_u64(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
+  wave_add_u64(cnt_at(S.cnt, CNT_PAIRS_FORCE), f);
+  wave_max_u64(cnt_at(S.cnt, CNT_LIST_OVERFLOW), ovf);
+  wave_max_u64(cnt_at(S.cnt, CNT_SLIST_OVERFLOW), sovf);
 }
 
 // ------------------------------------------------ moments + corrections ----
@@ -689,7 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) gB[t * n + p] = (R)c.dB[t];
   }
-  wave_add_u64(&S.cnt[CNT_SINGULAR], sing);
+  wave_add_u64(cnt_at(S.cnt, CNT_SINGULAR), sing);
 }
 
 // ------------------------------------------------ density, grad v, EOS ----
@@ -812,7 +924,7 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 9; ++t) gradv_out[t * n + p] = gv[t];
   }
-  wave_add_u64(&S.cnt[CNT_RELAXED], nrel);
+  wave_add_u64(cnt_at(S.cnt, CNT_RELAXED), nrel);
 }
 
 // ------------------------------------------------------ force and du/dt ----
@@ -937,7 +1049,7 @@ __global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, i
     const double v = (double)a[i];
     bad = (v - v == 0.0) ? 0 : 1;
   }
-  wave_add_u64(&cnt[CNT_NONFINITE], bad);
+  wave_add_u64(cnt_at(cnt, CNT_NONFINITE), bad);
 }
 
 }  // namespace
@@ -953,9 +1065,14 @@ void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned
 }
 
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
-                 uint32_t* cell_count, unsigned long long* cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys, vals,
-                     cell_count, cnt);
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys, vals);
+}
+
+void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,
+                        unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_bounds, dim3((unsigned)((ncell + kBlock) / kBlock)), dim3(kBlock), 0,
+                     s, keys, n, ncell, start, cnt);
 }
 
 template <class R>
@@ -974,7 +1091,10 @@ void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, c
 
 template <class R>
 void launch_candidates(const State<R>& S, hipStream_t s) {
-  hipLaunchKernelGGL(k_candidates<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  if (S.equal_mass)
+    hipLaunchKernelGGL((k_candidates<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  else
+    hipLaunchKernelGGL((k_candidates<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
 }
 template <class R>
 void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {

@@ -6,7 +6,7 @@
 
 namespace crk {
 
-// Slots of the device counter array (unsigned long long).
+// Counters of one evaluation (unsigned long long, kCntSpread slots each).
 enum Counter {
   CNT_HMAX_BITS = 0,   // max input h as double bits
   CNT_BAD_INPUT,       // h <= 0, m <= 0 or u <= 0
@@ -28,6 +28,16 @@ enum Counter {
   CNT_CELL_MAX,        // largest cell occupancy of the cell list
   CNT_COUNT
 };
+
+// Every counter lives in kCntSpread slots; a block adds to the slot of its
+// index modulo kCntSpread and the host folds the slots (sum, or max for the
+// maxima). Atomics on one address serialise in the memory-side atomic unit,
+// and a per-wave counter of a kernel whose waves all end together would
+// queue thousands of them behind its last wave.
+constexpr int kCntSpread = 64;
+__device__ inline unsigned long long* cnt_at(unsigned long long* cnt, int c) {
+  return cnt + c * kCntSpread + (blockIdx.x & (kCntSpread - 1));
+}
 
 template <class R>
 struct State {
@@ -65,8 +75,9 @@ struct State {
   // every wave has list_cap / slist_cap
   const uint32_t* grow;
   const uint32_t* srow;
-  // candidates within rcap of each particle (chunked SELL): packed entries,
-  // r, and m_j/m_i (the last only when the masses differ)
+  // candidates within rcap of each particle (16-entry groups, group_base):
+  // packed entries, r, and m_j/m_i (the last only when the masses differ);
+  // scr_cap is a multiple of 16
   uint32_t* cand;
   R* scr_r;
   R* scr_m;
@@ -78,7 +89,7 @@ struct State {
   int* need;          // per-particle candidate capacity request (tree path) or null
   int* todo;          // per-particle "h not solved yet" flag (tree path) or null
   // tree path: rank of each particle among the unsolved ones (its scratch
-  // slot), and the chunk-row offset of every group of 64 slots, whose
+  // slot), and the group-row offset of every group of 64 slots, whose
   // capacity is the largest request in the group; null on the cell path
   const uint32_t* cslot;
   const uint32_t* vrow;
@@ -166,11 +177,11 @@ template <class R>
 __device__ inline int64_t scratch_base(const State<R>& S, int64_t s, int& cap) {
   if (!S.cslot) {
     cap = S.scr_cap;
-    return slot_base((s >> 6) * (int64_t)(S.scr_cap >> 2), s);
+    return group_base((s >> 6) * (int64_t)(S.scr_cap >> 4), s);
   }
   const int64_t q = S.cslot[s], w = q >> 6;
-  cap = (int)(S.vrow[w + 1] - S.vrow[w]) * 4;
-  return slot_base(S.vrow[w], q);
+  cap = (int)(S.vrow[w + 1] - S.vrow[w]) * 16;
+  return group_base(S.vrow[w], q);
 }
 
 // Where particle s's symmetric neighbour list lives: the gather part

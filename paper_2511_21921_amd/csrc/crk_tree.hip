@@ -309,8 +309,8 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
             sr.put(slot, r);
             sm.put(slot, mr);
             if (slot == 3) {
-              sr.flush_at(S.scr_r, base, cnt);
-              if (!S.equal_mass) sm.flush_at(S.scr_m, base, cnt);
+              sr.flush_group(S.scr_r, base, cnt);
+              if (!S.equal_mass) sm.flush_group(S.scr_m, base, cnt);
             }
           } else if (S.shrink) {
             add_sums(r, mr);
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
     if (mine) {
       if (cnt > cap && S.shrink) {
         for (int k = 0; k < cap; ++k) {  // the candidates that fitted
-          const int64_t e = slot_at(base, k);
+          const int64_t e = group_at(base, k);
           add_sums(S.scr_r[e], S.equal_mass ? R(1) : S.scr_m[e]);
         }
         const R C = R(Shape<K>::C), n_h3 = R(S.n_h3);
@@ -356,8 +356,8 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
         retry = 1;
       } else {
         if (cnt & 3) {
-          sr.flush_at(S.scr_r, base, cnt - 1);
-          if (!S.equal_mass) sm.flush_at(S.scr_m, base, cnt - 1);
+          sr.flush_group(S.scr_r, base, cnt - 1);
+          if (!S.equal_mass) sm.flush_group(S.scr_m, base, cnt - 1);
         }
         S.ccnt[s] = cnt;
       }
@@ -365,16 +365,17 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) retry += __shfl_xor(retry, o, 64);
-  if ((threadIdx.x & 63) == 0 && retry) atomicAdd(&S.cnt[CNT_RETRY], retry);
+  if ((threadIdx.x & 63) == 0 && retry) atomicAdd(cnt_at(S.cnt, CNT_RETRY), retry);
 }
 
-// Capacity of every group of 64 scratch slots, in chunk rows: the largest
-// request of the unsolved particles ranked into it (rows zeroed beforehand).
+// Capacity of every group of 64 scratch slots, in rows of 16-entry groups:
+// the largest request of the unsolved particles ranked into it (rows zeroed
+// beforehand).
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __restrict__ rows) {
   const int64_t s = particle_id();
   if (s >= S.n || !S.todo[s]) return;
-  atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 3) >> 2));
+  atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 15) >> 4));
 }
 
 // Gather lists r_ij < h_i by a walk with each lane's own h. Every wave's
@@ -432,8 +433,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_tree(State<R> S) {
     ovf = a > ovf ? a : ovf;
   }
   if ((threadIdx.x & 63) == 0) {
-    if (g) atomicAdd(&S.cnt[CNT_PAIRS_GATHER], g);
-    if (ovf) atomicMax(&S.cnt[CNT_LIST_OVERFLOW], ovf);
+    if (g) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
+    if (ovf) atomicMax(cnt_at(S.cnt, CNT_LIST_OVERFLOW), ovf);
   }
 }
 
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S) {
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
-  if ((threadIdx.x & 63) == 0 && f) atomicAdd(&S.cnt[CNT_PAIRS_FORCE], f);
+  if ((threadIdx.x & 63) == 0 && f) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_FORCE), f);
 }
 
 }  // namespace
