@@ -90,10 +90,12 @@ typedef struct {
   int store_corrections; /* 1: keep moments for the adjoint; 0: recompute them */
   int check_finite;  /* 1: count non-finite outputs and fail with CRK_ENONFINITE */
   int timing;        /* 1: time every pass with HIP events (see crk_pass_times) */
-  int search;        /* neighbour search: 0 automatic, 1 periodic cell list sized to the
-                        largest h, 2 tree of Morton-ordered 64-particle leaves (for smoothing
-                        lengths spanning orders of magnitude); automatic uses the cell list
-                        unless its candidate lists would exceed 1024 entries per particle */
+  int search;        /* neighbour search: 0 automatic, 1 periodic cell list (cells of at least
+                        0.625 x the largest h, a 5x5x5 stencil), 2 tree of Morton-ordered
+                        64-particle leaves (for smoothing lengths spanning orders of
+                        magnitude); automatic uses the cell list unless a cell holds more
+                        than max(1024, 16 x the mean occupancy) particles or a particle more
+                        than max(1024, 16 x the expected count) candidates */
 } crk_params;
 
 typedef struct {
@@ -105,6 +107,8 @@ typedef struct {
   int relaxed;              /* particles flagged by the relaxation criterion */
   int nonfinite;            /* non-finite outputs (check_finite only) */
   int grid;                 /* cells per box side used by the cell list */
+  int speculative;          /* 1: this forward ran on the previous one's cell-list geometry
+                               and was accepted by its single end-of-call check */
 } crk_stats;
 
 /* Fills *p with the defaults for the given precision. */
@@ -141,6 +145,13 @@ const char *crk_last_error(const crk_ctx *ctx);
  *   dudt   [n] double     du/dt (compatible energy)
  *   stats  host pointer or NULL; when given, the call synchronises the
  *          stream and fills it.
+ * Host reads: a forward reads device counters to size the cell list and its
+ * lists (input check, clustering test, h solve, list capacities). After a
+ * forward that settled on the cell list at its first grid, the next one with
+ * the same n and precision launches every pass with that geometry and reads
+ * the counters once at the end; when they show that the careful order would
+ * have chosen differently (another grid, clustering, an overflow, a capped h
+ * root), it runs again the careful way. Either way the outputs are the same.
  * n = 0 is a no-op returning CRK_OK. Input and output arrays must not
  * overlap. The context keeps the cell list, neighbour list and the sorted
  * intermediates for a following crk_backward. */

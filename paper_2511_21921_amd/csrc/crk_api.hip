@@ -72,6 +72,15 @@ struct crk_ctx {
   double rcap = 0.0;
   int precision_last = -1;
   bool reserved_fixed = false;
+  // Cell-list geometry of the last forward that settled on its first
+  // attempt; the next forward with the same n and precision launches every
+  // pass with it and checks once at the end that it still holds.
+  bool spec_ok = false;
+  long long spec_n = -1;
+  int spec_prec = -1;
+  int spec_G = 0;
+  double spec_rcap = 0.0;
+  int spec_em = 0;
 };
 
 namespace {
@@ -278,7 +287,8 @@ hipError_t read_counters(crk_ctx* c, hipStream_t s) {
     const bool is_max = k == CNT_HMAX_BITS || k == CNT_H_ITER_MAX || k == CNT_SCR_OVERFLOW ||
                         k == CNT_LIST_OVERFLOW || k == CNT_SLIST_OVERFLOW ||
                         k == CNT_MMAX_BITS || k == CNT_MINVMAX_BITS ||
-                        k == CNT_HMAX_OUT_BITS || k == CNT_CELL_MAX;
+                        k == CNT_HMAX_OUT_BITS || k == CNT_CELL_MAX ||
+                        k == CNT_TOO_DENSE;
     unsigned long long v = 0;
     for (int t = 0; t < kCntSpread; ++t) {
       const unsigned long long x = c->host_raw[k * kCntSpread + t];
@@ -306,7 +316,8 @@ int choose_grid(double box, double R, int64_t n) {
 }
 
 template <class R>
-crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) {
+crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
+                       unsigned long long occ_limit) {
   const int64_t ncell = (int64_t)ctx->G * ctx->G * ctx->G;
   CRK_HIP(ensure(ctx->cell_start, 4 * (size_t)(ncell + 1)), "alloc cell starts");
   launch_keys(x, n, ctx->p.box, ctx->G, (uint32_t*)ctx->keys_a.p, (uint32_t*)ctx->vals_a.p, s);
@@ -317,7 +328,7 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x) 
                            (uint32_t*)ctx->sort_tmp.p, s),
           "radix sort");
   launch_cell_bounds((const uint32_t*)ctx->keys_a.p, n, ncell, (uint32_t*)ctx->cell_start.p,
-                     (unsigned long long*)ctx->cnt.p, s);
+                     occ_limit, (unsigned long long*)ctx->cnt.p, s);
   CRK_HIP(hipGetLastError(), "cell bounds launch");
   return CRK_OK;
 }
@@ -495,6 +506,108 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   return CRK_OK;
 }
 
+// One forward on the cell list with the geometry of the previous one (grid,
+// candidate radius, equal-mass form, capacities): every pass is launched
+// with no host read in between, and a single read of the counters at the
+// end checks that the careful path would have taken exactly this attempt
+// (same grid from this input's largest h, same mass form, no cell beyond
+// the clustering limit, no candidate or list overflow, no capped h root).
+// Then the results are the careful path's, bit for bit; otherwise
+// *accepted stays false and the caller runs the careful path.
+template <class R>
+crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
+                        const R* m, const R* u, R* h, R* V, R* rho, void* A, void* B,
+                        void* gradA, void* gradB, R* gradv, double* accel, double* dudt,
+                        bool* accepted) {
+  const crk_params& P = ctx->p;
+  *accepted = false;
+  unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
+  launch_check_inputs<R>(h, m, u, n, dcnt, s);
+  ctx->G = ctx->spec_G;
+  ctx->ell = P.box / ctx->G;
+  ctx->lattice = 0;
+  ctx->rcap = ctx->spec_rcap;
+  ctx->equal_mass = ctx->spec_em;
+  const int64_t npad = ((n + 63) / 64) * 64;
+  const double ncell = (double)ctx->G * ctx->G * ctx->G;
+  const double occ_rule = std::max(1024.0, 16.0 * (double)n / ncell);
+  CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
+  crk_status st = build_cells<R>(ctx, s, n, x,
+                                 P.search == 0 ? (unsigned long long)occ_rule : ~0ull);
+  if (st != CRK_OK) return st;
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_gather<R>(S, x, v, m, u, h, s);
+  }
+  CRK_HIP(tend(ctx, P_CELLS, s), "event");
+  CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
+  CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+          "alloc candidates");
+  if (!ctx->equal_mass)
+    CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+            "alloc candidates");
+  CRK_HIP(ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap), "alloc neighbour list");
+  CRK_HIP(ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap), "alloc neighbour list");
+  State<R> S = make_state<R>(ctx, n);
+  CRK_HIP(tbegin(ctx, P_CAND, s), "event");
+  launch_candidates<R>(S, s);
+  CRK_HIP(tend(ctx, P_CAND, s), "event");
+  CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+  if (P.h_mode == 0)
+    launch_volume<R>(S, P.kernel, s);
+  else
+    launch_hsolve<R>(S, P.kernel, s);
+  CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
+  // the caller's h is an input until this evaluation is accepted: h and V
+  // are written to the caller only then
+  launch_pack<R>(S, (R*)nullptr, (R*)nullptr, s);
+  CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
+  launch_nlist<R>(S, s);
+  CRK_HIP(tend(ctx, P_NLIST, s), "event");
+  CorrOut co{A, B, gradA, gradB};
+  CRK_HIP(tbegin(ctx, P_MOMENTS, s), "event");
+  launch_moments<R>(S, P.kernel, co, s);
+  CRK_HIP(tend(ctx, P_MOMENTS, s), "event");
+  CRK_HIP(tbegin(ctx, P_DENSITY, s), "event");
+  launch_density<R>(S, P.kernel, rho, gradv, s);
+  CRK_HIP(tend(ctx, P_DENSITY, s), "event");
+  CRK_HIP(tbegin(ctx, P_FORCE, s), "event");
+  launch_force<R>(S, P.kernel, accel, dudt, s);
+  CRK_HIP(tend(ctx, P_FORCE, s), "event");
+  if (P.check_finite) {
+    launch_count_nonfinite_f64(accel, 3 * n, dcnt, s);
+    launch_count_nonfinite_f64(dudt, n, dcnt, s);
+    launch_count_nonfinite<R>(rho, n, dcnt, s);
+    launch_count_nonfinite<R>(h, n, dcnt, s);
+  }
+  CRK_HIP(hipGetLastError(), "pass launch");
+  CRK_HIP(read_counters(ctx, s), "speculative forward");
+  const unsigned long long* hc = ctx->host_cnt;
+  if (hc[CNT_BAD_INPUT]) return CRK_OK;  // the careful path reports it
+  const double h0max = bits_to_double(hc[CNT_HMAX_BITS]);
+  if (!(h0max < 0.5 * P.box)) return CRK_OK;
+  const double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
+  if (choose_grid(P.box, 0.5 * reach, n) != ctx->G) return CRK_OK;
+  // fixed h: any radius >= this input's largest h gives the same sums
+  if (P.h_mode == 0 && !(h0max <= ctx->rcap)) return CRK_OK;
+  const double mmax = bits_to_double(hc[CNT_MMAX_BITS]);
+  const double iinv = bits_to_double(hc[CNT_MINVMAX_BITS]);
+  if ((std::fabs(mmax * iinv - 1.0) <= 4e-16 ? 1 : 0) != ctx->equal_mass) return CRK_OK;
+  if (hc[CNT_TOO_DENSE] || hc[CNT_SCR_OVERFLOW] || hc[CNT_LIST_OVERFLOW] ||
+      hc[CNT_SLIST_OVERFLOW])
+    return CRK_OK;
+  if (P.search == 0 && (double)hc[CNT_CELL_MAX] > occ_rule) return CRK_OK;
+  if (P.h_mode == 1) {
+    if (hc[CNT_H_CAPPED]) return CRK_OK;
+    if (!(bits_to_double(hc[CNT_HMAX_OUT_BITS]) < 0.5 * P.box)) return CRK_OK;
+  }
+  launch_pack<R>(S, h, V, s);
+  CRK_HIP(hipGetLastError(), "pack launch");
+  *accepted = true;
+  return CRK_OK;
+}
+
 template <class R>
 crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
                         const R* m, const R* u, R* h, R* V, R* rho, void* A, void* B,
@@ -504,117 +617,135 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   ctx->n_last = -1;
   CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
-  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-  launch_check_inputs<R>(h, m, u, n, dcnt, s);
-  CRK_HIP(hipGetLastError(), "input check launch");
-  CRK_HIP(read_counters(ctx, s), "input check");
-  if (ctx->host_cnt[CNT_BAD_INPUT])
-    return fail(ctx, CRK_EINVAL, "h, m and u must be finite and > 0");
-  const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
-  {
-    // all masses equal (to rounding) => m_j / m_i = 1 needs no storage
-    const double mmax = bits_to_double(ctx->host_cnt[CNT_MMAX_BITS]);
-    const double iinv = bits_to_double(ctx->host_cnt[CNT_MINVMAX_BITS]);
-    ctx->equal_mass = std::fabs(mmax * iinv - 1.0) <= 4e-16 ? 1 : 0;
-  }
-  if (!(h0max < 0.5 * P.box))
-    return fail(ctx, CRK_EDOMAIN, "smoothing length must stay below half the box");
-
-  // candidates reach two cell sides (a 5x5x5 stencil walked with culling)
-  double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
-  ctx->G = choose_grid(P.box, 0.5 * reach, n);
-  ctx->ell = P.box / ctx->G;
-  ctx->lattice = 0;
-  const int64_t npad = ((n + 63) / 64) * 64;
-  bool solved = false;
-  bool use_tree = P.search == 2;
-  for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
-    // candidates reach two cell sides when h is solved, the largest h otherwise
-    ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : h0max;
-    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-    CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
-    crk_status st = build_cells<R>(ctx, s, n, x);
+  bool accepted = false;
+  if (ctx->spec_ok && ctx->spec_n == n && ctx->spec_prec == P.precision && P.search != 2) {
+    crk_status st = forward_fast<R>(ctx, s, n, x, v, m, u, h, V, rho, A, B, gradA, gradB, gradv,
+                                    accel, dudt, &accepted);
     if (st != CRK_OK) return st;
-    if (P.search == 0 && attempt == 0) {
-      // a cell holding more than 1024 particles and 16x the mean occupancy
-      // means strong clustering: the cell list would need huge candidate
-      // lists there (a high resolution alone raises every cell alike)
-      CRK_HIP(read_counters(ctx, s), "cell occupancy");
-      const double mean_occ = (double)n / ((double)ctx->G * ctx->G * ctx->G);
-      if ((double)ctx->host_cnt[CNT_CELL_MAX] > std::max(1024.0, 16.0 * mean_occ)) {
-        use_tree = true;
-        CRK_HIP(tend(ctx, P_CELLS, s), "event");
-        break;
+  }
+  ctx->spec_ok = false;
+  if (!accepted) {
+    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
+    launch_check_inputs<R>(h, m, u, n, dcnt, s);
+    CRK_HIP(hipGetLastError(), "input check launch");
+    CRK_HIP(read_counters(ctx, s), "input check");
+    if (ctx->host_cnt[CNT_BAD_INPUT])
+      return fail(ctx, CRK_EINVAL, "h, m and u must be finite and > 0");
+    const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
+    {
+      // all masses equal (to rounding) => m_j / m_i = 1 needs no storage
+      const double mmax = bits_to_double(ctx->host_cnt[CNT_MMAX_BITS]);
+      const double iinv = bits_to_double(ctx->host_cnt[CNT_MINVMAX_BITS]);
+      ctx->equal_mass = std::fabs(mmax * iinv - 1.0) <= 4e-16 ? 1 : 0;
+    }
+    if (!(h0max < 0.5 * P.box))
+      return fail(ctx, CRK_EDOMAIN, "smoothing length must stay below half the box");
+
+    // candidates reach two cell sides (a 5x5x5 stencil walked with culling)
+    double reach = P.h_mode == 1 ? 1.25 * h0max : h0max;
+    ctx->G = choose_grid(P.box, 0.5 * reach, n);
+    const int G0 = ctx->G;
+    ctx->ell = P.box / ctx->G;
+    ctx->lattice = 0;
+    const int64_t npad = ((n + 63) / 64) * 64;
+    bool solved = false;
+    bool use_tree = P.search == 2;
+    for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
+      // candidates reach two cell sides when h is solved, the largest h otherwise
+      ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : h0max;
+      CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
+      CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
+      crk_status st = build_cells<R>(ctx, s, n, x, ~0ull);
+      if (st != CRK_OK) return st;
+      if (P.search == 0 && attempt == 0) {
+        // a cell holding more than 1024 particles and 16x the mean occupancy
+        // means strong clustering: the cell list would need huge candidate
+        // lists there (a high resolution alone raises every cell alike)
+        CRK_HIP(read_counters(ctx, s), "cell occupancy");
+        const double mean_occ = (double)n / ((double)ctx->G * ctx->G * ctx->G);
+        if ((double)ctx->host_cnt[CNT_CELL_MAX] > std::max(1024.0, 16.0 * mean_occ)) {
+          use_tree = true;
+          CRK_HIP(tend(ctx, P_CELLS, s), "event");
+          break;
+        }
       }
+      {
+        State<R> S = make_state<R>(ctx, n);
+        launch_gather<R>(S, x, v, m, u, h, s);
+      }
+      CRK_HIP(tend(ctx, P_CELLS, s), "event");
+      CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
+      CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+              "alloc candidates");
+      if (!ctx->equal_mass)
+        CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
+                "alloc candidates");
+      State<R> S = make_state<R>(ctx, n);
+      CRK_HIP(tbegin(ctx, P_CAND, s), "event");
+      launch_candidates<R>(S, s);
+      CRK_HIP(tend(ctx, P_CAND, s), "event");
+      CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
+      if (P.h_mode == 0)
+        launch_volume<R>(S, P.kernel, s);
+      else
+        launch_hsolve<R>(S, P.kernel, s);
+      CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
+      CRK_HIP(hipGetLastError(), "h solve launch");
+      CRK_HIP(read_counters(ctx, s), "h solve");
+      if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
+        // clustered: some particle has far more candidates than the mean
+        // density gives within the candidate radius (rcap <= ell)
+        const double expect = 4.18879 * ctx->rcap * ctx->rcap * ctx->rcap * (double)n /
+                              (P.box * P.box * P.box);
+        if (P.search == 0 &&
+            (double)ctx->host_cnt[CNT_SCR_OVERFLOW] > std::max(1024.0, 16.0 * expect)) {
+          use_tree = true;
+          break;
+        }
+        ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);
+        continue;  // same grid, larger candidate capacity
+      }
+      if (P.h_mode == 1 && ctx->host_cnt[CNT_H_CAPPED]) {
+        // a root beyond a candidate radius of half the box breaks h < box / 2
+        if (ctx->rcap >= 0.5 * P.box)
+          return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
+        // cells too small for some root: widen them (to no fewer than 2 per
+        // side, which the row wrap of the stencil walk assumes) and solve again
+        ctx->G = std::max(2, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
+        ctx->ell = P.box / ctx->G;
+        continue;
+      }
+      solved = true;
+    }
+    if (use_tree) {
+      crk_status st = tree_solve<R>(ctx, s, n, x, v, m, u, h);
+      if (st != CRK_OK) return st;
+      solved = true;
+    }
+    if (!solved) return fail(ctx, CRK_EHIP, "h solve: grid adaptation did not settle");
+    if (!ctx->lattice && ctx->G == G0) {
+      // settled on the first grid: the next forward may speculate with it
+      ctx->spec_ok = true;
+      ctx->spec_n = n;
+      ctx->spec_prec = P.precision;
+      ctx->spec_G = ctx->G;
+      ctx->spec_rcap = ctx->rcap;
+      ctx->spec_em = ctx->equal_mass;
+    }
+    if (P.h_mode == 1) {
+      const double hmax = bits_to_double(ctx->host_cnt[CNT_HMAX_OUT_BITS]);
+      if (!(hmax < 0.5 * P.box))
+        return fail(ctx, CRK_EDOMAIN, "solved smoothing length reaches half the box");
     }
     {
       State<R> S = make_state<R>(ctx, n);
-      launch_gather<R>(S, x, v, m, u, h, s);
+      launch_pack<R>(S, h, V, s);
+      if (ctx->lattice)  // node boxes with the solved h for the symmetric search
+        launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
     }
-    CRK_HIP(tend(ctx, P_CELLS, s), "event");
-    CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
-    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
-            "alloc candidates");
-    if (!ctx->equal_mass)
-      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * (size_t)npad * ctx->scr_cap),
-              "alloc candidates");
-    State<R> S = make_state<R>(ctx, n);
-    CRK_HIP(tbegin(ctx, P_CAND, s), "event");
-    launch_candidates<R>(S, s);
-    CRK_HIP(tend(ctx, P_CAND, s), "event");
-    CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
-    if (P.h_mode == 0)
-      launch_volume<R>(S, P.kernel, s);
-    else
-      launch_hsolve<R>(S, P.kernel, s);
-    CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
-    CRK_HIP(hipGetLastError(), "h solve launch");
-    CRK_HIP(read_counters(ctx, s), "h solve");
-    if (ctx->host_cnt[CNT_SCR_OVERFLOW]) {
-      // clustered: some particle has far more candidates than the mean
-      // density gives within the candidate radius (rcap <= ell)
-      const double expect = 4.18879 * ctx->rcap * ctx->rcap * ctx->rcap * (double)n /
-                            (P.box * P.box * P.box);
-      if (P.search == 0 &&
-          (double)ctx->host_cnt[CNT_SCR_OVERFLOW] > std::max(1024.0, 16.0 * expect)) {
-        use_tree = true;
-        break;
-      }
-      ctx->scr_cap = (int)(((ctx->host_cnt[CNT_SCR_OVERFLOW] * 5) / 4 + 31) / 32 * 32);
-      continue;  // same grid, larger candidate capacity
-    }
-    if (P.h_mode == 1 && ctx->host_cnt[CNT_H_CAPPED]) {
-      // a root beyond a candidate radius of half the box breaks h < box / 2
-      if (ctx->rcap >= 0.5 * P.box)
-        return fail(ctx, CRK_EDOMAIN, "h solve needs h beyond half the box");
-      // cells too small for some root: widen them (to no fewer than 2 per
-      // side, which the row wrap of the stencil walk assumes) and solve again
-      ctx->G = std::max(2, std::min(ctx->G - 1, (int)std::floor(ctx->G / 1.5)));
-      ctx->ell = P.box / ctx->G;
-      continue;
-    }
-    solved = true;
-  }
-  if (use_tree) {
-    crk_status st = tree_solve<R>(ctx, s, n, x, v, m, u, h);
-    if (st != CRK_OK) return st;
-    solved = true;
-  }
-  if (!solved) return fail(ctx, CRK_EHIP, "h solve: grid adaptation did not settle");
-  if (P.h_mode == 1) {
-    const double hmax = bits_to_double(ctx->host_cnt[CNT_HMAX_OUT_BITS]);
-    if (!(hmax < 0.5 * P.box))
-      return fail(ctx, CRK_EDOMAIN, "solved smoothing length reaches half the box");
-  }
-  {
-    State<R> S = make_state<R>(ctx, n);
-    launch_pack<R>(S, h, V, s);
-    if (ctx->lattice)  // node boxes with the solved h for the symmetric search
-      launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
-  }
-  if (ctx->lattice) {
-    crk_status st = tree_lists<R>(ctx, s, n);
-    if (st != CRK_OK) return st;
+    if (ctx->lattice) {
+      crk_status st = tree_lists<R>(ctx, s, n);
+      if (st != CRK_OK) return st;
   } else {
     // neighbour lists, grown until they fit
     for (int attempt = 0; attempt < 8; ++attempt) {
@@ -655,11 +786,15 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     launch_count_nonfinite<R>(h, n, dcnt, s);
     CRK_HIP(hipGetLastError(), "finite check launch");
   }
+  if (stats || P.check_finite) CRK_HIP(read_counters(ctx, s), "stats");
+  } else {
+    // the speculative forward was accepted; its read holds every counter
+    ctx->spec_ok = true;
+  }
   ctx->n_last = n;
   ctx->precision_last = P.precision;
   crk_status result = CRK_OK;
   if (stats || P.check_finite) {
-    CRK_HIP(read_counters(ctx, s), "stats");
     const unsigned long long* hc = ctx->host_cnt;
     if (stats) {
       stats->n_pairs_gather = (long long)hc[CNT_PAIRS_GATHER];
@@ -670,6 +805,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       stats->relaxed = (int)hc[CNT_RELAXED];
       stats->nonfinite = (int)hc[CNT_NONFINITE];
       stats->grid = ctx->G;
+      stats->speculative = accepted ? 1 : 0;
     }
     if (hc[CNT_H_UNCONV]) {
       result = CRK_ENOTCONV;
@@ -786,6 +922,7 @@ crk_status crk_set_params(crk_ctx* ctx, const crk_params* p) {
   const bool prec_changed = p->precision != ctx->p.precision;
   ctx->p = *p;
   if (prec_changed) ctx->n_last = -1;
+  ctx->spec_ok = false;  // box, h mode, search or kernel may differ
   return CRK_OK;
 }
 

@@ -128,10 +128,12 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, i
 
 // cell_start[c] = first sorted position whose key is >= c, for c = 0..ncell
 // (a binary search of the sorted keys per cell; no atomics). The largest
-// occupancy start[c + 1] - start[c] is reduced per block into one atomic.
+// occupancy start[c + 1] - start[c] is reduced per block into one atomic;
+// a block whose largest occupancy exceeds occ_limit raises CNT_TOO_DENSE.
 __global__ void __launch_bounds__(kBlock) k_cell_bounds(const uint32_t* __restrict__ keys,
                                                         int64_t n, int64_t ncell,
                                                         uint32_t* __restrict__ start,
+                                                        unsigned long long occ_limit,
                                                         unsigned long long* __restrict__ cnt) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   auto lower = [&](int64_t v) {
@@ -160,6 +162,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_bounds(const uint32_t* __restri
     unsigned long long m = 0;
     for (int w = 0; w < kBlock / 64; ++w) m = red[w] > m ? red[w] : m;
     if (m) atomicMax(cnt_at(cnt, CNT_CELL_MAX), m);
+    if (m > occ_limit) atomicMax(cnt_at(cnt, CNT_TOO_DENSE), 1ull);
   }
 }
 
@@ -211,6 +214,9 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 
 template <class R, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
+  // a speculative cell list found too dense (strong clustering): the host
+  // discards this evaluation and takes the tree, so skip the quadratic walk
+  if (__ballot(S.cnt[CNT_TOO_DENSE * kCntSpread + (threadIdx.x & 63)] != 0ull)) return;
   const int64_t s = particle_id();
   if (s >= S.n) return;
   const R4<R> pi = S.pos4[s];
@@ -511,6 +517,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
   const R h = S.hbuf[s], V = S.Vbuf[s];
   S.pos4[s].w = R(1) / h;
   S.vel4[s].w = V;
+  if (!h_out) return;  // caller's h is still an input (a speculative forward)
   const uint32_t p = S.perm[s];
   h_out[p] = h;
   V_out[p] = V;
@@ -1070,9 +1077,9 @@ void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, 
 }
 
 void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,
-                        unsigned long long* cnt, hipStream_t s) {
+                        unsigned long long occ_limit, unsigned long long* cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_bounds, dim3((unsigned)((ncell + kBlock) / kBlock)), dim3(kBlock), 0,
-                     s, keys, n, ncell, start, cnt);
+                     s, keys, n, ncell, start, occ_limit, cnt);
 }
 
 template <class R>

@@ -15,7 +15,7 @@ void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
                  hipStream_t s);
 void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,
-                        unsigned long long* cnt, hipStream_t s);
+                        unsigned long long occ_limit, unsigned long long* cnt, hipStream_t s);
 
 // Morton keys over the 1024^3 lattice (tree path) and identity values.
 void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint32_t* vals,
