@@ -178,10 +178,11 @@ struct PairSide {
   R wam[3], wum;  // loss weights over the mass: w_a / m and w_u / (2 m)
 };
 
-template <class A>
+template <class A, class AK = A>
 struct ForceBar {  // i-side adjoints of one force pass
-  A x[3], v[3], h, V, rho, P, c, gv[9], alpha, beta;
-  KCBar<A> kc;
+  A x[3], v[3], h, V, rho, P, c, alpha, beta;
+  AK gv[9];      // sums feeding the density adjoint's coefficients
+  KCBar<AK> kc;  // sums feeding the correction adjoint
   __host__ __device__ void zero() {
     for (int t = 0; t < 3; ++t) x[t] = v[t] = 0;
     h = V = rho = P = c = alpha = beta = 0;
@@ -194,10 +195,12 @@ struct ForceBar {  // i-side adjoints of one force pass
 // lambda = gU_i/(2 m_i) + gU_j/(2 m_j)), which is the pair's whole share of
 // L. Accumulates the derivatives with respect to i's quantities; the pair
 // is seen from j's side by j's own call. corrected = false for a relaxed pair.
-template <class R, class A, int K>
+// The pair's several terms in x, v and h are summed in the working precision
+// and enter the accumulators once per pair.
+template <class R, class A, class AK, int K>
 __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairSide<R>& J,
                                                const R x[3], R alpha, R beta, R eps2,
-                                               bool corrected, ForceBar<A>& ob) {
+                                               bool corrected, ForceBar<A, AK>& ob) {
   const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
   const R rinv = Sc<R>::rsqrt(r2);
   const R r = r2 * rinv;
@@ -221,7 +224,8 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   for (int a = 0; a < 3; ++a) w[a] = I.wam[a] - J.wam[a] - vij[a] * lam;
   // L = sig G.w
   const R gsig = G[0] * w[0] + G[1] * w[1] + G[2] * w[2];
-  for (int a = 0; a < 3; ++a) ob.v[a] += (A)(-lam * sig * G[a]);  // explicit v_ij in w
+  R vb[3];
+  for (int a = 0; a < 3; ++a) vb[a] = -lam * sig * G[a];  // explicit v_ij in w
   ob.V += (A)(gsig * R(-0.5) * J.V * Pi);
   const R Pibar = gsig * R(-0.5) * I.V * J.V;
   ob.P += (A)Pibar;
@@ -240,11 +244,11 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   const R r2bar = -(mubar_i * av.vpx * I.h * av.iDi * av.iDi +
                     mubar_j * av.vpx * J.h * av.iDj * av.iDj);
   // d mu_i / d h_i, with h = 1/hinv
-  ob.h += (A)(mubar_i * av.vpx * (r2 - eps2 * I.h * I.h) * av.iDi * av.iDi);
+  R hb = mubar_i * av.vpx * (r2 - eps2 * I.h * I.h) * av.iDi * av.iDi;
   R xb[3];
   for (int a = 0; a < 3; ++a) xb[a] = R(2) * r2bar * x[a] + vpxbar * av.vp[a];
   R vpb[3] = {vpxbar * x[0], vpxbar * x[1], vpxbar * x[2]};
-  for (int a = 0; a < 3; ++a) ob.v[a] += (A)vpb[a];
+  for (int a = 0; a < 3; ++a) ob.v[a] += (A)(vb[a] + vpb[a]);
   // vp = v_ij - phi/2 (gix + gjx)
   const R phibar = R(-0.5) * (vpb[0] * (av.gix[0] + av.gjx[0]) + vpb[1] * (av.gix[1] + av.gjx[1]) +
                               vpb[2] * (av.gix[2] + av.gjx[2]));
@@ -264,18 +268,18 @@ __host__ __device__ inline void force_pair_adj(const PairSide<R>& I, const PairS
   // gix = grad v_i x, gjx = grad v_j x
   for (int a = 0; a < 3; ++a)
     for (int g = 0; g < 3; ++g) {
-      ob.gv[a * 3 + g] += (A)(gixb[a] * x[g]);
+      ob.gv[a * 3 + g] += (AK)(gixb[a] * x[g]);
       xb[g] += gixb[a] * I.gv[a * 3 + g] + gjxb[a] * J.gv[a * 3 + g];
     }
-  for (int a = 0; a < 3; ++a) ob.x[a] += (A)xb[a];
   // G = Gi(x) - Gj(-x); Gbar = sig w
   const R Gb[3] = {sig * w[0], sig * w[1], sig * w[2]};
-  corr_adj<R, A>(I.kc, x, r, rinv, ei, R(0), Gb, corrected ? &ob.kc : nullptr, ob.x, ob.h);
+  corr_adj<R, R, AK>(I.kc, x, r, rinv, ei, R(0), Gb, corrected ? &ob.kc : nullptr, xb, hb);
   // j side: d/dx_i of -Gj(-x) = +dGj/dx_ji . Gbar
-  A xj[3] = {0, 0, 0};
-  A hj_dummy = 0;
-  corr_adj<R, A>(J.kc, xm, r, rinv, ej, R(0), Gb, (KCBar<A>*)nullptr, xj, hj_dummy);
-  for (int a = 0; a < 3; ++a) ob.x[a] += xj[a];
+  R xj[3] = {0, 0, 0};
+  R hj_dummy = 0;
+  corr_adj<R, R, AK>(J.kc, xm, r, rinv, ej, R(0), Gb, (KCBar<AK>*)nullptr, xj, hj_dummy);
+  for (int a = 0; a < 3; ++a) ob.x[a] += (A)(xb[a] + xj[a]);
+  ob.h += (A)hb;
 }
 
 

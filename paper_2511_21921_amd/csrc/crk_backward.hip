@@ -147,7 +147,10 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
     const KC<R> kci = I.kc;
     const bool relax_on = S.dt_relax > 0.0;
     const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
-    ForceBar<double> ob;
+    // x, v, h, V and the EOS adjoints accumulate in FP64; the 16 correction
+    // and 9 velocity-gradient adjoint sums (one term per pair) in the
+    // working precision, like the density adjoint's own correction sums
+    ForceBar<double, R> ob;
     ob.zero();
     __shared__ uint4 eslot[kBlock];  // the lane's list chunk (registers are scarce here)
     const NbrRef nb = nbr_ref(S, s);
@@ -166,7 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
       } else {
         I.kc = kci;
       }
-      force_pair_adj<R, double, K>(I, J, x, alpha, beta, eps2, !plain, ob);
+      force_pair_adj<R, double, R, K>(I, J, x, alpha, beta, eps2, !plain, ob);
     }
     // equation of state: P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u)
     const double gam = S.gamma;
