@@ -160,3 +160,46 @@ def params_for(ps, **kw) -> Params:
     for k, val in kw.items():
         setattr(p, k, val)
     return p
+
+
+# ------------------------------------------------------------ time step --
+# One kick-drift-kick cycle on a single timestep level, App. A.4 (the KDK
+# update) with the smoothing-length evolution of App. A.3: the Thacker
+# estimate h^T = h (1 - lambda + lambda Delta_N), Delta_N^3 = V n_h^3 / h^3,
+# gives hdot^T = (h^T - h) / dt; continuity gives hdot^cont = h div(v) / 3;
+# each drift of dt updates h <- h exp(hdot dt / h). Positions accumulate in
+# FP64 (App. A.4, last paragraph). The evaluation at the end of the step
+# takes the predicted velocity and energy v^1/2 + a^0 dt / 2, u^1/2 +
+# du^0 dt / 2 (the paper leaves the velocity of that evaluation open).
+
+def kdk_step(x, v, m, u, h, prev: dict, params: Params, dt: float, lam: float,
+             nbr_mode: int = 0) -> dict:
+    """One KDK step from the state (x, v, u, h) and the evaluation prev at it.
+
+    prev holds accel, dudt, V and gradv of the forward at (x, v, u, h) with h
+    fixed. Returns the new x, v, u, h and the forward at the new state (its
+    accel, dudt, V, gradv serve as prev of the next step).
+    """
+    if params.h_mode != 0:
+        raise ValueError("the time-integrated smoothing length needs h_mode = 0")
+    x, v, m, u, h = _c(x), _c(v), _c(m), _c(u), _c(h)
+    a0, du0 = _c(prev["accel"]), _c(prev["dudt"])
+    # first kick
+    v_half = v + 0.5 * dt * a0
+    u_half = u + 0.5 * dt * du0
+    # hdot from the evaluation at the start of the step
+    div_v = prev["gradv"][0] + prev["gradv"][4] + prev["gradv"][8]
+    delta_n = params.n_h * np.cbrt(prev["V"]) / h
+    h_thacker = h * (1.0 - lam + lam * delta_n)
+    hdot = (h_thacker - h) / dt + h * div_v / 3.0
+    # drift
+    x_new = np.mod(x + dt * v_half, params.box)
+    h_new = h * np.exp(hdot * dt / h)
+    # evaluation at the end of the step, then the second kick
+    o = forward(x_new, v_half + 0.5 * dt * a0, m, u_half + 0.5 * dt * du0, h_new, params,
+                nbr_mode=nbr_mode)
+    o["x"] = x_new
+    o["v"] = v_half + 0.5 * dt * o["accel"]
+    o["u"] = u_half + 0.5 * dt * o["dudt"]
+    o["h"] = h_new
+    return o
