@@ -173,6 +173,36 @@ crk_status crk_backward(crk_ctx *ctx, void *hip_stream, long long n, const doubl
                         const double *g_dudt, double *g_x, double *g_v, double *g_u,
                         double *g_alpha_beta);
 
+/* One kick-drift-kick step of length dt on a single timestep level (App. A.4
+ * KDK update), with the smoothing length integrated by the combined Thacker
+ * and continuity rate and its exponential update (App. A.3):
+ *   v^1/2 = v + a dt/2, u^1/2 = u + (du/dt) dt/2;
+ *   x <- x + v^1/2 dt in double, wrapped into [0, box);
+ *   Delta_N = n_h V^(1/3) / h, h^T = h (1 - lambda + lambda Delta_N),
+ *   hdot = (h^T - h)/dt + h div(v)/3, h <- h exp(hdot dt / h);
+ *   the forward at (x, v^1/2 + a dt/2, m, u^1/2 + (du/dt) dt/2, h), h fixed;
+ *   v = v^1/2 + a^1 dt/2, u = u^1/2 + (du/dt)^1 dt/2.
+ * The context must have h_mode 0 (h is integrated here, not solved).
+ *   dt             > 0, finite
+ *   thacker_lambda the Thacker weight lambda in [0, 1]
+ *   x [3][n] double, v [3][n] Real, u [n] Real, h [n] Real   in/out: the state,
+ *                  advanced by dt
+ *   m [n] Real     in
+ *   V [n], gradv [9][n] Real, accel [3][n], dudt [n] double  in: the forward at
+ *                  the current state (a crk_forward or crk_kdk_step on these
+ *                  arrays); out: the forward at the new state
+ *   rho, A, B, gradA, gradB   out, as in crk_forward
+ * All arrays are device memory, caller-owned, in the caller's order; the
+ * context's workspace holds the predicted velocity and energy. The forward
+ * state is kept for crk_backward, which then differentiates the end-of-step
+ * evaluation. Errors: CRK_EINVAL for h_mode != 0, a bad dt or lambda, null
+ * arrays or n above 2^25 - 1; otherwise those of crk_forward (after an error
+ * the arrays may hold a partly advanced state). n = 0 is a no-op. */
+crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
+                        double thacker_lambda, double *x, void *v, const void *m, void *u,
+                        void *h, void *V, void *rho, void *A, void *B, void *gradA, void *gradB,
+                        void *gradv, double *accel, double *dudt, crk_stats *stats);
+
 /* Per-pass device time. Passes are numbered 0 .. crk_pass_count()-1 and
  * named by crk_pass_name(k) (NULL when k is out of range). With
  * params.timing = 1 every pass of crk_forward / crk_backward is bracketed by

@@ -49,7 +49,7 @@ class crk_stats(C.Structure):
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
            "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
-           "crk_pass_times"]
+           "crk_pass_times", "crk_kdk_step"]
 
 _lib = None
 
@@ -79,6 +79,9 @@ def lib():
         L.crk_forward.restype = C.c_int
         L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 6
         L.crk_backward.restype = C.c_int
+        L.crk_kdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 14 +
+                                   [C.POINTER(crk_stats)])
+        L.crk_kdk_step.restype = C.c_int
         L.crk_pass_count.argtypes = []
         L.crk_pass_count.restype = C.c_int
         L.crk_pass_name.argtypes = [C.c_int]
@@ -211,6 +214,35 @@ class Context:
                                _ptr(out["B"]), _ptr(out["gradA"]), _ptr(out["gradB"]),
                                _ptr(out["gradv"]), _ptr(out["accel"]), _ptr(out["dudt"]),
                                C.byref(st) if stats else None)
+        self._raise(rc)
+        if stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def kdk_step(self, x: torch.Tensor, v: torch.Tensor, m: torch.Tensor, u: torch.Tensor,
+                 out: dict, dt: float, lam: float = 0.5, stats: bool = False) -> dict:
+        """One kick-drift-kick step (crk_kdk_step): advances x, v, u and out["h"]
+        in place by dt and replaces out (the dict of the forward at the current
+        state, as returned by forward or kdk_step) by the forward at the new
+        state. The context must have h_mode 0."""
+        n = int(m.shape[0])
+        R = self.params.real
+        _check(x, torch.float64, (3, n), "x")
+        _check(v, R, (3, n), "v")
+        for t, name in [(m, "m"), (u, "u"), (out["h"], "h"), (out["V"], "V")]:
+            _check(t, R, (n,), name)
+        _check(out["gradv"], R, (9, n), "gradv")
+        _check(out["accel"], torch.float64, (3, n), "accel")
+        _check(out["dudt"], torch.float64, (n,), "dudt")
+        st = crk_stats()
+        stream = C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+        self.generation += 1
+        rc = lib().crk_kdk_step(self._h, stream, n, float(dt), float(lam), _ptr(x), _ptr(v),
+                                _ptr(m), _ptr(u), _ptr(out["h"]), _ptr(out["V"]),
+                                _ptr(out["rho"]), _ptr(out["A"]), _ptr(out["B"]),
+                                _ptr(out["gradA"]), _ptr(out["gradB"]), _ptr(out["gradv"]),
+                                _ptr(out["accel"]), _ptr(out["dudt"]),
+                                C.byref(st) if stats else None)
         self._raise(rc)
         if stats:
             out["stats"] = st.as_dict()

@@ -29,12 +29,13 @@ struct Buf {
 namespace {
 enum Pass {
   P_CELLS = 0, P_CAND, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
-  P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_NPASS
+  P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_STEP,
+  P_NPASS
 };
 const char* kPassNames[P_NPASS] = {"cells",     "candidates",  "hsolve",      "nlist",
                                    "moments",   "density",     "force",       "bwd_force",
                                    "bwd_density", "bwd_corr",  "bwd_moments", "bwd_volume",
-                                   "bwd_other"};
+                                   "bwd_other", "step"};
 }  // namespace
 
 struct crk_ctx {
@@ -59,6 +60,8 @@ struct crk_ctx {
   int lattice = 0;
   // adjoint workspace
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
+  // time step: the velocity and energy predicted for the end-of-step evaluation
+  Buf vpred, upred;
   unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
   unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
@@ -651,8 +654,10 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     bool solved = false;
     bool use_tree = P.search == 2;
     for (int attempt = 0; attempt < 12 && !solved && !use_tree; ++attempt) {
-      // candidates reach two cell sides when h is solved, the largest h otherwise
-      ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : h0max;
+      // candidates reach two cell sides when h is solved; with fixed h 10 %
+      // beyond the largest h (within two cell sides), so that the next
+      // forward may speculate on this geometry while h grows a little
+      ctx->rcap = P.h_mode == 1 ? 2.0 * ctx->ell : std::min(2.0 * ctx->ell, 1.1 * h0max);
       CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
       CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
       crk_status st = build_cells<R>(ctx, s, n, x, ~0ull);
@@ -875,6 +880,33 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   return CRK_OK;
 }
 
+// One kick-drift-kick step (App. A.4) with the Thacker/continuity smoothing
+// length (App. A.3): first kick, drift and h update, the forward at the new
+// state with the predicted velocity and energy, second kick.
+template <class R>
+crk_status step_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double lam, double* x,
+                     R* v, const R* m, R* u, R* h, R* V, R* rho, void* A, void* B, void* gradA,
+                     void* gradB, R* gradv, double* accel, double* dudt, crk_stats* stats) {
+  const crk_params& P = ctx->p;
+  const size_t N = (size_t)n;
+  CRK_HIP(ensure(ctx->vpred, sizeof(R) * 3 * N), "step workspace");
+  CRK_HIP(ensure(ctx->upred, sizeof(R) * N), "step workspace");
+  R* vp = (R*)ctx->vpred.p;
+  R* up = (R*)ctx->upred.p;
+  CRK_HIP(tbegin(ctx, P_STEP, s), "event");
+  launch_kick_drift<R>(n, dt, lam, P.n_h, P.box, x, v, u, h, V, gradv, accel, dudt, vp, up, s);
+  CRK_HIP(tend(ctx, P_STEP, s), "event");
+  CRK_HIP(hipGetLastError(), "kick-drift launch");
+  crk_status st = forward_impl<R>(ctx, s, n, x, vp, m, up, h, V, rho, A, B, gradA, gradB, gradv,
+                                  accel, dudt, stats);
+  if (st != CRK_OK && st != CRK_ENOTCONV && st != CRK_ENONFINITE) return st;
+  CRK_HIP(tbegin(ctx, P_STEP, s), "event");
+  launch_kick_close<R>(n, dt, v, u, accel, dudt, s);
+  CRK_HIP(tend(ctx, P_STEP, s), "event");
+  CRK_HIP(hipGetLastError(), "kick launch");
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -947,7 +979,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
-                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap,
+                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
@@ -1027,6 +1059,37 @@ crk_status crk_backward(crk_ctx* ctx, void* hip_stream, long long n, const doubl
   if (ctx->p.precision == CRK_FP64)
     return backward_impl<double>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
   return backward_impl<float>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
+}
+
+crk_status crk_kdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
+                        double thacker_lambda, double* x, void* v, const void* m, void* u,
+                        void* h, void* V, void* rho, void* A, void* B, void* gradA, void* gradB,
+                        void* gradv, double* accel, double* dudt, crk_stats* stats) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (ctx->p.h_mode != 0)
+    return fail(ctx, CRK_EINVAL, "the time step integrates h: the context needs h_mode 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, CRK_EINVAL, "dt must be finite and > 0");
+  if (!(thacker_lambda >= 0.0 && thacker_lambda <= 1.0))
+    return fail(ctx, CRK_EINVAL, "thacker_lambda must lie in [0, 1]");
+  if (n < 0) return fail(ctx, CRK_EINVAL, "n must be >= 0");
+  if (n == 0) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    ctx->n_last = 0;
+    return CRK_OK;
+  }
+  if (n > (1ll << 25) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^25 - 1 particles");
+  if (!x || !v || !m || !u || !h || !V || !rho || !A || !B || !gradA || !gradB || !gradv ||
+      !accel || !dudt)
+    return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (ctx->p.precision == CRK_FP64)
+    return step_impl<double>(ctx, s, n, dt, thacker_lambda, x, (double*)v, (const double*)m,
+                             (double*)u, (double*)h, (double*)V, (double*)rho, A, B, gradA, gradB,
+                             (double*)gradv, accel, dudt, stats);
+  return step_impl<float>(ctx, s, n, dt, thacker_lambda, x, (float*)v, (const float*)m, (float*)u,
+                          (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB, (float*)gradv,
+                          accel, dudt, stats);
 }
 
 }  // extern "C"

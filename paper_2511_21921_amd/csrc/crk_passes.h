@@ -107,4 +107,13 @@ template <class R>
 void launch_bwd_finish(const State<R>& S, const AdjState<R>& G, double* g_x, double* g_v,
                        double* g_u, double* g_ab, hipStream_t s);
 
+// time step (caller order, elementwise)
+template <class R>
+void launch_kick_drift(int64_t n, double dt, double lam, double n_h, double box, double* x, R* v,
+                       R* u, R* h, const R* V, const R* gradv, const double* accel,
+                       const double* dudt, R* vp, R* up, hipStream_t s);
+template <class R>
+void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, const double* dudt,
+                       hipStream_t s);
+
 }  // namespace crk
