@@ -117,6 +117,52 @@ def run_gpu(ps, precision, steps, warmup, backward, kernel=0):
     return ms, stats, passes, res
 
 
+# algorithmic HBM bytes per particle of the step's two elementwise kernels
+# (FP32 state, FP64 positions and forces): first kick + drift + h update reads
+# x 24, v 12, u 4, h 4, V 4, div v 12, a 24, du/dt 8 and writes x 24, v 12,
+# u 4, h 4, predicted v 12 and u 4; the second kick reads v 12, u 4, a 24,
+# du/dt 8 and writes v 12, u 4
+STEP_BYTES_PER_PARTICLE = 92 + 60 + 48 + 16
+
+
+def run_kdk(ps, steps, warmup, dt):
+    """KDK steps (crk_kdk_step, FP32) from ps with h fixed at its solved value."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2511_21921_amd import FP32, Context, Params
+    dev = torch.device("cuda:0")
+    t = lambda a, dtype=torch.float32: torch.tensor(np.ascontiguousarray(a), dtype=dtype,
+                                                    device=dev)
+    # h: the solved smoothing lengths of the initial state
+    p1 = Params(box=ps.box, n_h=ps.n_h, h_mode=1, precision=FP32)
+    c1 = Context(p1)
+    o1 = c1.forward(t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u), t(ps.h))
+    h0 = o1["h"].clone()
+    c1.close()
+    p = dataclasses.replace(p1, h_mode=0, timing=1)
+    ctx = Context(p)
+    x, v, m, u = t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u)
+    ctx.reserve(ps.n)
+    out = ctx.forward(x, v, m, u, h0, stats=True)
+    for _ in range(warmup):
+        ctx.kdk_step(x, v, m, u, out, dt)
+    torch.cuda.synchronize()
+    ctx.pass_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.kdk_step(x, v, m, u, out, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    passes = ctx.pass_times(reset=True)
+    st = ctx.kdk_step(x, v, m, u, out, dt, stats=True)["stats"]
+    torch.cuda.synchronize()
+    ctx.close()
+    return (t1 - t0) * 1e3 / steps, st, passes
+
+
 def pass_ms(passes, name):
     tot, calls = passes[name]
     return tot / calls if calls else float("nan")
@@ -181,6 +227,23 @@ def main():
                           "neighbours, the paper's gas resolution), forward + adjoint",
               "pairs_force": stc["n_pairs_force"],
               "pass_ms": {k: round(pass_ms(passesc, k), 4) for k in names}}
+
+    # time integration around the passes: kick-drift-kick steps at fixed h
+    # (the Thacker/continuity rate); dt is small enough that the ambient gas next
+    # to the Sedov spike (u = 1e-2, du/dt up to ~1e4 from its half of the
+    # pair work) stays positive over the timed steps
+    msk, stk, passesk = run_kdk(ps, args.steps, args.warmup, 1e-9)
+    step_us = pass_ms(passesk, "step") * 1e3  # two update launches per step
+    kdk = {"ms_per_step": round(msk, 4), "value": stk["n_pairs_force"] / (msk * 1e-3),
+           "unit": "interactions/s",
+           "workload": "sedov64_v, kick-drift-kick steps (dt = 1e-9, lambda = 0.5) with h "
+                       "integrated by the Thacker/continuity rate from the solved h",
+           "speculative_forwards": stk["speculative"],
+           "update_kernels": {"us_per_step": round(2 * step_us, 2),
+                              "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
+                              "GBps": round(STEP_BYTES_PER_PARTICLE * ps.n /
+                                            (2 * step_us * 1e-6) / 1e9, 1)}}
+    log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
 
     fp64 = None
     if not args.no_fp64:
@@ -259,7 +322,7 @@ def main():
                 "workload": "sedov64 (same particles, zero velocity), forward only",
                 "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "c4_268": c4, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
+        "c4_268": c4, "kdk_step": kdk, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     if args.calibration_copy:
