@@ -203,3 +203,138 @@ def kdk_step(x, v, m, u, h, prev: dict, params: Params, dt: float, lam: float,
     o["u"] = u_half + 0.5 * dt * o["dudt"]
     o["h"] = h_new
     return o
+
+
+# ------------------------------------------------------------- cooling --
+# Exact integration of du/dt = -s Lambda / rho over dt (Sec. 2.2, exact
+# integration) for a source function tabulated at log-spaced energies and
+# interpolated by piecewise power laws. The composition is folded into the
+# table: Lambda(u; rho) = rho^2 lam(u), so du/dt = -rho lam(u) (cooling where
+# lam > 0, heating where lam < 0). Each particle is anchored at u_a = u^0, so
+# I(u^0) = 0 and I(u^1) = Lambda_a dt / (u_a rho); I is accumulated bin by bin
+# from the anchor in the direction of evolution (down for cooling, up for
+# heating) with the per-bin closed form, and the final bin is inverted.
+# A bin where lam changes sign holds the equilibrium: there the source is
+# held at the larger of the two edge magnitudes, in the direction of the
+# anchor's side, and u stops at the zero of the linear interpolant. Below
+# the first node or above the last, u is clamped to the table.
+
+class CoolingTable:
+    """lam_k at u_k = 10^(log10_u0 + k dex), k = 0 .. K-1."""
+
+    def __init__(self, log10_u0: float, dex: float, lam):
+        self.lu0, self.dex = float(log10_u0), float(dex)
+        self.lam = np.asarray(lam, dtype=np.float64)
+        self.K = self.lam.size
+
+    def u(self, k):
+        return 10.0 ** (self.lu0 + k * self.dex)
+
+    def slope(self, k):
+        """alpha_k of bin [u_k, u_k+1] (same-sign edges)."""
+        return np.log(self.lam[k + 1] / self.lam[k]) / np.log(self.u(k + 1) / self.u(k))
+
+    def lam_at(self, u):
+        k = min(max(int(np.floor((np.log10(u) - self.lu0) / self.dex)), 0), self.K - 2)
+        lk, lk1 = self.lam[k], self.lam[k + 1]
+        if lk * lk1 <= 0.0:  # the equilibrium bin: linear
+            return lk + (lk1 - lk) * (u - self.u(k)) / (self.u(k + 1) - self.u(k))
+        return lk * (u / self.u(k)) ** self.slope(k)
+
+
+def _I_in_bin(tab, k, u, Ik, s, la, ua):
+    """I(u) in power-law bin k from I_k = I(u_k), eq. (Iu); la = |lam(u_a)|."""
+    uk, lk = tab.u(k), abs(tab.lam[k])
+    a = tab.slope(k)
+    c = s * la * uk / (lk * ua)
+    if a == 1.0:
+        return Ik + c * (-np.log(u / uk))
+    # [1 - (u/u_k)^(1 - a)] / (1 - a), written with expm1 so that slopes
+    # near 1 keep their accuracy (the same function, tending to -ln(u/u_k))
+    return Ik + c * (-np.expm1((1.0 - a) * np.log(u / uk)) / (1.0 - a))
+
+
+def _I_inverse(tab, k, I, Ik, s, la, ua):
+    """u in power-law bin k with I(u) = I, eq. (Iinv)."""
+    uk, lk = tab.u(k), abs(tab.lam[k])
+    a = tab.slope(k)
+    c = s * lk * ua / (la * uk)
+    if a == 1.0:
+        return uk * np.exp(-c * (I - Ik))
+    # [1 - (I - I_k)(1 - a) c]^(1 / (1 - a)) with log1p (same reason)
+    return uk * np.exp(np.log1p(-(I - Ik) * (1.0 - a) * c) / (1.0 - a))
+
+
+def cool(tab: CoolingTable, u0, rho, dt: float):
+    """u^1 of every particle after dt (FP64, one particle at a time)."""
+    u0 = np.asarray(u0, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    out = np.empty_like(u0)
+    lo, hi = tab.u(0), tab.u(tab.K - 1)
+    for i in range(u0.size):
+        u = min(max(u0[i], lo), hi)
+        left = rho[i] * dt   # rho times the time still to integrate
+        # a particle that starts on the outer side of an unstable zero leaves
+        # its bin and is anchored again at the bin edge (at most once per side)
+        for _ in range(3):
+            u, left = _cool_from(tab, u, left)
+            if left <= 0.0:
+                break
+        out[i] = u
+    return out
+
+
+def _bin_of(tab, u):
+    return min(max(int(np.floor((np.log10(u) - tab.lu0) / tab.dex)), 0), tab.K - 2)
+
+
+def _equilibrium_bin(tab, k, u, left):
+    """Bin k holds the sign change: constant source of the larger edge
+    magnitude (left = rho t). Toward the zero of the linear interpolant u
+    stops there; away from it (an unstable zero) u runs to the bin edge and
+    the time still left is returned."""
+    uk, uk1 = tab.u(k), tab.u(k + 1)
+    lk, lk1 = tab.lam[k], tab.lam[k + 1]
+    ueq = uk - lk * (uk1 - uk) / (lk1 - lk) if lk1 != lk else uk
+    lin = lk + (lk1 - lk) * (u - uk) / (uk1 - uk)
+    mag = max(abs(lk), abs(lk1))
+    if lin == 0.0 or mag == 0.0:
+        return u, 0.0
+    down = lin > 0.0                  # cooling moves u down
+    target = ueq if (ueq < u) == down else (uk if down else uk1)
+    dist = abs(u - target)
+    if mag * left <= dist:
+        return (u - mag * left if down else u + mag * left), 0.0
+    if target == ueq:
+        return ueq, 0.0
+    return target, left - dist / mag
+
+
+def _cool_from(tab, ua, left):
+    """Integrate from the anchor u_a for rho t = left; returns (u, left')."""
+    k = _bin_of(tab, ua)
+    if tab.lam[k] * tab.lam[k + 1] <= 0.0:
+        return _equilibrium_bin(tab, k, ua, left)
+    la = abs(tab.lam_at(ua))          # Lambda_a / rho^2
+    s = 1.0 if tab.lam[k] > 0.0 else -1.0   # +1 cooling, -1 heating
+    I1 = la * left / ua               # I(u^1) = Lambda_a dt / (u_a rho), with I(u^0) = 0
+    Ik = -_I_in_bin(tab, k, ua, 0.0, s, la, ua)   # I_k of the anchor's bin
+    while True:
+        # the far edge of bin k in the direction of evolution, and I there
+        if s > 0:
+            edge, Iedge = tab.u(k), Ik
+        else:
+            edge, Iedge = tab.u(k + 1), _I_in_bin(tab, k, tab.u(k + 1), Ik, s, la, ua)
+        if Iedge >= I1:
+            return _I_inverse(tab, k, I1, Ik, s, la, ua), 0.0
+        kn = k - 1 if s > 0 else k + 1
+        if kn < 0 or kn > tab.K - 2:
+            return edge, 0.0          # clamped at the end of the table
+        if tab.lam[kn] * tab.lam[kn + 1] <= 0.0:
+            # the equilibrium bin, entered toward its zero: rho t left is
+            # (I1 - I(edge)) u_a / |lam_a|
+            return _equilibrium_bin(tab, kn, edge, (I1 - Iedge) * ua / la)
+        # I_k of the next bin: for cooling its upper edge is the edge just
+        # reached, for heating its lower edge
+        Ik = Iedge - _I_in_bin(tab, kn, edge, 0.0, s, la, ua) if s > 0 else Iedge
+        k = kn
