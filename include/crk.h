@@ -203,6 +203,30 @@ crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
                         void *h, void *V, void *rho, void *A, void *B, void *gradA, void *gradB,
                         void *gradv, double *accel, double *dudt, crk_stats *stats);
 
+/* Tabulated source function of the exact-integration cooling (Sec. 2.2,
+ * exact integration): lam[k] at u_k = 10^(log10_u0 + k dex), k = 0 .. K-1,
+ * interpolated by piecewise power laws between nodes of the same sign. The
+ * composition is folded into the table: Lambda(u; rho) = rho^2 lam(u), so
+ * that du/dt = -Lambda / rho = -rho lam(u); lam > 0 cools, lam < 0 heats, and
+ * a bin whose end values differ in sign holds an equilibrium. lam is a host
+ * array, copied (the call synchronises the stream). The context keeps one
+ * table; a new call replaces it. Errors: CRK_EINVAL for K < 2, dex <= 0,
+ * non-finite values or energies beyond 10^(+-300). */
+crk_status crk_cooling_table(crk_ctx *ctx, void *hip_stream, int K, double log10_u0, double dex,
+                             const double *lam);
+
+/* Integrates du/dt = -rho lam(u) exactly over dt for n particles (the table
+ * of crk_cooling_table), each with its own anchor u_a = u^0 and fixed rho:
+ *   rho [n] Real  in (device), u [n] Real  in/out (device), caller's order.
+ * Energies outside the table are clamped to its ends. In a sign-change bin
+ * the source is held at the larger edge magnitude and u stops at the zero of
+ * the linear interpolant when it moves toward it; moving away from an
+ * unstable zero it leaves the bin and continues. Arithmetic is FP64 in both
+ * precisions. Errors: CRK_EINVAL without a table, for dt < 0 or not finite,
+ * null arrays; n = 0 is a no-op. */
+crk_status crk_cool(crk_ctx *ctx, void *hip_stream, long long n, double dt, const void *rho,
+                    void *u);
+
 /* Per-pass device time. Passes are numbered 0 .. crk_pass_count()-1 and
  * named by crk_pass_name(k) (NULL when k is out of range). With
  * params.timing = 1 every pass of crk_forward / crk_backward is bracketed by

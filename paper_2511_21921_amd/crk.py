@@ -49,7 +49,7 @@ class crk_stats(C.Structure):
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
            "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
-           "crk_pass_times", "crk_kdk_step"]
+           "crk_pass_times", "crk_kdk_step", "crk_cooling_table", "crk_cool"]
 
 _lib = None
 
@@ -82,6 +82,11 @@ def lib():
         L.crk_kdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 14 +
                                    [C.POINTER(crk_stats)])
         L.crk_kdk_step.restype = C.c_int
+        L.crk_cooling_table.argtypes = [P, P, C.c_int, C.c_double, C.c_double,
+                                        C.POINTER(C.c_double)]
+        L.crk_cooling_table.restype = C.c_int
+        L.crk_cool.argtypes = [P, P, C.c_longlong, C.c_double, P, P]
+        L.crk_cool.restype = C.c_int
         L.crk_pass_count.argtypes = []
         L.crk_pass_count.restype = C.c_int
         L.crk_pass_name.argtypes = [C.c_int]
@@ -247,6 +252,26 @@ class Context:
         if stats:
             out["stats"] = st.as_dict()
         return out
+
+    def cooling_table(self, log10_u0: float, dex: float, lam) -> None:
+        """Sets the tabulated source function lam(u_k), u_k = 10^(log10_u0 + k dex)
+        of the exact-integration cooling (crk_cooling_table); lam is host data."""
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self._raise(lib().crk_cooling_table(self._h, stream, int(a.size), float(log10_u0),
+                                            float(dex),
+                                            a.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def cool(self, rho: torch.Tensor, u: torch.Tensor, dt: float) -> torch.Tensor:
+        """Integrates du/dt = -rho lam(u) exactly over dt, u in place (crk_cool)."""
+        n = int(u.shape[0])
+        R = self.params.real
+        _check(rho, R, (n,), "rho")
+        _check(u, R, (n,), "u")
+        stream = C.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)
+        self._raise(lib().crk_cool(self._h, stream, n, float(dt), _ptr(rho), _ptr(u)))
+        return u
 
     def pass_times(self, reset: bool = False) -> dict:
         """Accumulated device time per pass: {name: (total_ms, launches)}."""

@@ -30,12 +30,12 @@ namespace {
 enum Pass {
   P_CELLS = 0, P_CAND, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
   P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_STEP,
-  P_NPASS
+  P_COOL, P_NPASS
 };
 const char* kPassNames[P_NPASS] = {"cells",     "candidates",  "hsolve",      "nlist",
                                    "moments",   "density",     "force",       "bwd_force",
                                    "bwd_density", "bwd_corr",  "bwd_moments", "bwd_volume",
-                                   "bwd_other", "step"};
+                                   "bwd_other", "step", "cool"};
 }  // namespace
 
 struct crk_ctx {
@@ -62,6 +62,11 @@ struct crk_ctx {
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
   // time step: the velocity and energy predicted for the end-of-step evaluation
   Buf vpred, upred;
+  // cooling table: lam at the nodes, per-bin slope, prefix integrals within
+  // each run of same-sign bins, each bin's run (int2), per-bin integrals
+  Buf cool_lam, cool_slope, cool_G, cool_run, cool_binint;
+  int cool_K = 0;
+  double cool_lu0 = 0.0, cool_dex = 0.0;
   unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
   unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
@@ -980,6 +985,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
+                &c->cool_lam, &c->cool_slope, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
@@ -1090,6 +1096,61 @@ crk_status crk_kdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
   return step_impl<float>(ctx, s, n, dt, thacker_lambda, x, (float*)v, (const float*)m, (float*)u,
                           (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB, (float*)gradv,
                           accel, dudt, stats);
+}
+
+crk_status crk_cooling_table(crk_ctx* ctx, void* hip_stream, int K, double log10_u0, double dex,
+                             const double* lam) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (K < 2 || !lam) return fail(ctx, CRK_EINVAL, "a cooling table needs K >= 2 values");
+  if (!(dex > 0.0) || !std::isfinite(dex) || !std::isfinite(log10_u0))
+    return fail(ctx, CRK_EINVAL, "cooling table spacing must be finite and > 0");
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(lam[k])) return fail(ctx, CRK_EINVAL, "cooling table values must be finite");
+  if (!std::isfinite(log10_u0 + (K - 1) * dex) || std::fabs(log10_u0) > 300.0 ||
+      std::fabs(log10_u0 + (K - 1) * dex) > 300.0)
+    return fail(ctx, CRK_EINVAL, "cooling table energies out of the double range");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t kk = (size_t)K;
+  CRK_HIP(ensure(ctx->cool_lam, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_slope, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_G, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_run, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_binint, 8 * kk), "cooling table");
+  CRK_HIP(hipMemcpyAsync(ctx->cool_lam.p, lam, 8 * kk, hipMemcpyHostToDevice, s), "cooling table");
+  launch_cool_prepare(K, log10_u0, dex, (const double*)ctx->cool_lam.p, (double*)ctx->cool_slope.p,
+                      (double*)ctx->cool_G.p, ctx->cool_run.p, (double*)ctx->cool_binint.p, s);
+  CRK_HIP(hipGetLastError(), "cooling table launch");
+  // the host copy of lam is read by the copy above: finish it before returning
+  CRK_HIP(hipStreamSynchronize(s), "cooling table");
+  ctx->cool_K = K;
+  ctx->cool_lu0 = log10_u0;
+  ctx->cool_dex = dex;
+  return CRK_OK;
+}
+
+crk_status crk_cool(crk_ctx* ctx, void* hip_stream, long long n, double dt, const void* rho,
+                    void* u) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (ctx->cool_K < 2) return fail(ctx, CRK_EINVAL, "no cooling table on the context");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(ctx, CRK_EINVAL, "dt must be finite and >= 0");
+  if (n < 0) return fail(ctx, CRK_EINVAL, "n must be >= 0");
+  if (n == 0) return CRK_OK;
+  if (!rho || !u) return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  CRK_HIP(tbegin(ctx, P_COOL, s), "event");
+  if (ctx->p.precision == CRK_FP64)
+    launch_cool<double>(ctx->cool_K, ctx->cool_lu0, ctx->cool_dex, (const double*)ctx->cool_lam.p,
+                        (const double*)ctx->cool_slope.p, (const double*)ctx->cool_G.p,
+                        ctx->cool_run.p, n, dt, (const double*)rho, (double*)u, s);
+  else
+    launch_cool<float>(ctx->cool_K, ctx->cool_lu0, ctx->cool_dex, (const double*)ctx->cool_lam.p,
+                       (const double*)ctx->cool_slope.p, (const double*)ctx->cool_G.p,
+                       ctx->cool_run.p, n, dt, (const float*)rho, (float*)u, s);
+  CRK_HIP(tend(ctx, P_COOL, s), "event");
+  CRK_HIP(hipGetLastError(), "cooling launch");
+  return CRK_OK;
 }
 
 }  // extern "C"

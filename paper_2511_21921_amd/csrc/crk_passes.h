@@ -116,4 +116,12 @@ template <class R>
 void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, const double* dudt,
                        hipStream_t s);
 
+// exact-integration cooling (caller order, elementwise); run holds int2 per bin
+void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
+                         double* G, void* run, double* binint, hipStream_t s);
+template <class R>
+void launch_cool(int K, double lu0, double dex, const double* lam, const double* slope,
+                 const double* G, const void* run, int64_t n, double dt, const R* rho, R* u,
+                 hipStream_t s);
+
 }  // namespace crk
