@@ -163,6 +163,39 @@ def run_kdk(ps, steps, warmup, dt):
     return (t1 - t0) * 1e3 / steps, st, passes
 
 
+COOL_BYTES_PER_PARTICLE = 12  # FP32: read u and rho, write u
+
+
+def run_cool(n, steps, warmup, seed=11):
+    """Exact-integration cooling of n FP32 particles over a synthetic table:
+    0.004 dex nodes over eight decades, a broken power law with a stable zero
+    (heating below it, cooling above)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_21921_amd import FP32, Context, Params
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    dex, lu0 = 0.004, -3.0
+    K = int(round(8 / dex)) + 1
+    uk = 10 ** (lu0 + dex * np.arange(K))
+    lam = (uk ** 1.5 - 0.1 ** 1.5) * np.exp(np.cumsum(rng.normal(0.0, 0.01, K)))
+    ctx = Context(Params(precision=FP32, timing=1))
+    ctx.cooling_table(lu0, dex, lam)
+    u = torch.tensor(10 ** rng.uniform(-2.5, 4.5, n), dtype=torch.float32, device=dev)
+    rho = torch.tensor(10 ** rng.uniform(-1, 1, n), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        ctx.cool(rho, u, 1e-3)
+    torch.cuda.synchronize()
+    ctx.pass_times(reset=True)
+    for _ in range(steps):
+        ctx.cool(rho, u, 1e-3)
+    torch.cuda.synchronize()
+    us = pass_ms(ctx.pass_times(reset=True), "cool") * 1e3
+    ctx.close()
+    return us, K
+
+
 def pass_ms(passes, name):
     tot, calls = passes[name]
     return tot / calls if calls else float("nan")
@@ -245,6 +278,18 @@ def main():
                                             (2 * step_us * 1e-6) / 1e9, 1)}}
     log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
 
+    # exact-integration cooling (Sec. 2.2), 2^24 particles
+    ncool = 1 << 24
+    cus, ck = run_cool(ncool, args.steps, args.warmup)
+    cool = {"us_per_launch": round(cus, 2), "value": ncool / (cus * 1e-6), "unit": "particles/s",
+            "workload": "2^24 FP32 particles, u log-uniform over 7 decades, rho over 2; table of "
+                        "%d nodes at 0.004 dex, a broken power law with a stable zero" % ck,
+            "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
+                    "GBps": round(COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6) / 1e9, 1),
+                    "frac_of_8TBps": round(COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6) / 8e12,
+                                           3)}}
+    log("cooling: %.1f us for %d particles" % (cus, ncool))
+
     fp64 = None
     if not args.no_fp64:
         k64 = max(3, args.steps // 2)
@@ -322,7 +367,7 @@ def main():
                 "workload": "sedov64 (same particles, zero velocity), forward only",
                 "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "c4_268": c4, "kdk_step": kdk, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
+        "c4_268": c4, "kdk_step": kdk, "cooling": cool, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     if args.calibration_copy:
