@@ -338,3 +338,73 @@ def _cool_from(tab, ua, left):
         # reached, for heating its lower edge
         Ik = Iedge - _I_in_bin(tab, kn, edge, 0.0, s, la, ua) if s > 0 else Iedge
         k = kn
+
+
+# ---------------------------------------------------------- deposition --
+# Subgrid sources (stars, winds, black holes) coupling to the gas, App. A.2
+# eq. (Vsg) and the SPH-weighted deposition of Sec. 2.5 / 2.6 / 2.7 (eqs.
+# windmetal and Anorm, starmetal and stellarmom, AGNE):
+#   V_s^-1 = sum over gas j and the source itself of W(|x_sj|, h_j) (the
+#     scatter definition: each gas neighbour's own h; the self term takes h_s);
+#   h_s = n_h,s V_s^(1/3), so the self term is C w(0) / (n_h,s^3 V_s) and
+#     V_s = (1 - C w(0) / n_h,s^3) / (sum over gas of W(|x_sj|, h_j));
+#   A_s^-1 = sum over eligible gas j of V_j W(|x_sj|, h_s) (gather: h_s);
+#   gas j receives A_s V_j W(|x_sj|, h_s) of each deposited amount of every
+#     source s (mass, metal mass, energy), and the mass carries the source's
+#     velocity: v_j <- (m_j v_j + sum_s dm_js v_s) / (m_j + sum_s dm_js);
+#     u_j <- (m_j u_j + dE_j) / (m_j + dm_j) (the deposited energy is added to
+#     the internal energy of the grown particle).
+# Gas with metallicity above z_max or mass above m_max is not eligible (it
+# neither receives nor enters A). All minimum-image separations, box L.
+
+def _kernel_w(kernel, r, h):
+    q = np.asarray(r / h, dtype=np.float64)
+    w, _, norm = kernel_eval(kernel, q)
+    return norm * w.reshape(q.shape) / h ** 3
+
+
+def deposit(gas: dict, src: dict, n_h_s: float, kernel: int = 1, box: float = 1.0,
+            z_max: float = np.inf, m_max: float = np.inf) -> dict:
+    """gas: x [3][n], h, V, m, v [3][n], mZ, u; src: x [3][s], dM, dMZ, dE, v [3][s].
+    Returns the updated gas fields and the sources' V, h and A (A = 0 when a
+    source has no eligible gas in reach: it deposits nothing)."""
+    xg, hg, Vg = _c(gas["x"]), _c(gas["h"]), _c(gas["V"])
+    m, v, mZ, u = _c(gas["m"]), _c(gas["v"]), _c(gas["mZ"]), _c(gas["u"])
+    xs = _c(src["x"])
+    ns = xs.shape[1]
+    elig = (mZ <= z_max * m) & (m <= m_max)
+    _, _, norm = kernel_eval(kernel, np.zeros(1))
+    w0 = kernel_eval(kernel, np.zeros(1))[0][0]
+    self_frac = norm * w0 / n_h_s ** 3
+    if not self_frac < 1.0:
+        raise ValueError("n_h,s^3 must exceed C w(0): the self term alone would exceed 1/V_s")
+    Vs, hs, As = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+    dm = np.zeros_like(m)
+    dmz = np.zeros_like(m)
+    de = np.zeros_like(m)
+    dp = np.zeros_like(v)
+    for s in range(ns):
+        d = xg - xs[:, s:s + 1]
+        d -= box * np.round(d / box)
+        r = np.sqrt((d * d).sum(0))
+        inside = r < hg
+        sg = _kernel_w(kernel, r[inside], hg[inside]).sum()
+        if not sg > 0.0:
+            continue
+        Vs[s] = (1.0 - self_frac) / sg
+        hs[s] = n_h_s * np.cbrt(Vs[s])
+        near = (r < hs[s]) & elig
+        wt = Vg[near] * _kernel_w(kernel, r[near], hs[s])
+        tot = wt.sum()
+        if not tot > 0.0:
+            continue
+        As[s] = 1.0 / tot
+        f = As[s] * wt
+        dm[near] += f * src["dM"][s]
+        dmz[near] += f * src["dMZ"][s]
+        de[near] += f * src["dE"][s]
+        dp[:, near] += np.outer(src["v"][:, s], f * src["dM"][s])
+    out = {"m": m + dm, "mZ": mZ + dmz, "V_s": Vs, "h_s": hs, "A_s": As}
+    out["v"] = (m * v + dp) / out["m"]
+    out["u"] = (m * u + de) / out["m"]
+    return out
