@@ -227,6 +227,41 @@ crk_status crk_cooling_table(crk_ctx *ctx, void *hip_stream, int K, double log10
 crk_status crk_cool(crk_ctx *ctx, void *hip_stream, long long n, double dt, const void *rho,
                     void *u);
 
+/* Subgrid deposition (App. A.2 eq. (Vsg); Secs. 2.5-2.7 eqs. (windmetal),
+ * (Anorm), (starmetal), (stellarmom), (AGNE)): n_src point sources hand mass
+ * dM, metal mass dMZ and energy dE to the gas around them, in one call.
+ *   Source volume: V_s = (1 - C w(0) / n_h_src^3) / sum_j W(|x_sj|, h_j), the
+ *     SPH sum over gas j with |x_sj| < h_j plus the source's own term at
+ *     h_s = n_h_src V_s^(1/3) (the fixed point in closed form).
+ *   Normalisation: A_s = 1 / sum over eligible gas j with |x_sj| < h_s of
+ *     V_j W(|x_sj|, h_s); gas is eligible when mZ_j <= z_max m_j and
+ *     m_j <= m_max (pass +inf for no limit). A source with no eligible gas in
+ *     reach gets A_s = 0 and deposits nothing; one with no gas at all in reach
+ *     also gets V_s = h_s = 0.
+ *   Deposition: gas j gains f_sj = A_s V_j W(|x_sj|, h_s) of dM, dMZ and dE of
+ *     every source s; the mass arrives with the source velocity v_s
+ *     (momentum conserved: v_j <- (m_j v_j + sum f dM v_s) / m_j'), the energy
+ *     becomes specific energy of the grown particle (u_j <- (m_j u_j +
+ *     sum f dE) / m_j'). Totals are conserved to rounding.
+ * Arrays are device memory in the caller's order; Real is float or double by
+ * the context precision; positions are double, periodic in the box:
+ *   x_gas [3][n_gas], h_gas, V_gas [n_gas] in (V from crk_forward);
+ *   m_gas, mZ_gas, u_gas [n_gas], v_gas [3][n_gas] in/out;
+ *   x_src [3][n_src], dM, dMZ, dE [n_src], v_src [3][n_src] in;
+ *   V_src, h_src, A_src [n_src] out.
+ * Each gas particle gathers its sources (no float atomics; reproducible).
+ * Arithmetic is FP64 in both precisions; the kernel shape is the context's.
+ * The call reads two maxima back to the host (synchronises the stream).
+ * Errors: CRK_EINVAL for negative counts, null arrays, n_h_src^3 <= C w(0),
+ * NaN limits, gas h not finite or <= 0; CRK_EDOMAIN when a gas or source
+ * smoothing length reaches half the box. n_src = 0 is a no-op. */
+crk_status crk_deposit(crk_ctx *ctx, void *hip_stream, long long n_gas, const double *x_gas,
+                       const void *h_gas, const void *V_gas, void *m_gas, void *v_gas,
+                       void *mZ_gas, void *u_gas, long long n_src, const double *x_src,
+                       const void *dM, const void *dMZ, const void *dE, const void *v_src,
+                       double n_h_src, double z_max, double m_max, void *V_src, void *h_src,
+                       void *A_src);
+
 /* Per-pass device time. Passes are numbered 0 .. crk_pass_count()-1 and
  * named by crk_pass_name(k) (NULL when k is out of range). With
  * params.timing = 1 every pass of crk_forward / crk_backward is bracketed by

@@ -49,7 +49,8 @@ class crk_stats(C.Structure):
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
            "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
-           "crk_pass_times", "crk_kdk_step", "crk_cooling_table", "crk_cool"]
+           "crk_pass_times", "crk_kdk_step", "crk_cooling_table", "crk_cool",
+           "crk_deposit"]
 
 _lib = None
 
@@ -87,6 +88,9 @@ def lib():
         L.crk_cooling_table.restype = C.c_int
         L.crk_cool.argtypes = [P, P, C.c_longlong, C.c_double, P, P]
         L.crk_cool.restype = C.c_int
+        L.crk_deposit.argtypes = ([P, P, C.c_longlong] + [P] * 7 + [C.c_longlong] + [P] * 5
+                                  + [C.c_double] * 3 + [P] * 3)
+        L.crk_deposit.restype = C.c_int
         L.crk_pass_count.argtypes = []
         L.crk_pass_count.restype = C.c_int
         L.crk_pass_name.argtypes = [C.c_int]
@@ -272,6 +276,32 @@ class Context:
         stream = C.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)
         self._raise(lib().crk_cool(self._h, stream, n, float(dt), _ptr(rho), _ptr(u)))
         return u
+
+    def deposit(self, gas: dict, src: dict, n_h_src: float, z_max: float = float("inf"),
+                m_max: float = float("inf")) -> dict:
+        """Subgrid deposition (crk_deposit). gas: x [3][n] float64, h, V [n] and
+        m, mZ, u [n], v [3][n] (updated in place); src: x [3][s] float64, dM,
+        dMZ, dE [s], v [3][s]. Returns the sources' V, h and A."""
+        R = self.params.real
+        ng = int(gas["m"].shape[0])
+        ns = int(src["dM"].shape[0])
+        dev = gas["m"].device
+        _check(gas["x"], torch.float64, (3, ng), "gas x")
+        for k in ("h", "V", "m", "mZ", "u"):
+            _check(gas[k], R, (ng,), "gas " + k)
+        _check(gas["v"], R, (3, ng), "gas v")
+        _check(src["x"], torch.float64, (3, ns), "source x")
+        for k in ("dM", "dMZ", "dE"):
+            _check(src[k], R, (ns,), "source " + k)
+        _check(src["v"], R, (3, ns), "source v")
+        out = {k: torch.empty(ns, dtype=R, device=dev) for k in ("V", "h", "A")}
+        stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        self._raise(lib().crk_deposit(
+            self._h, stream, ng, _ptr(gas["x"]), _ptr(gas["h"]), _ptr(gas["V"]), _ptr(gas["m"]),
+            _ptr(gas["v"]), _ptr(gas["mZ"]), _ptr(gas["u"]), ns, _ptr(src["x"]), _ptr(src["dM"]),
+            _ptr(src["dMZ"]), _ptr(src["dE"]), _ptr(src["v"]), float(n_h_src), float(z_max),
+            float(m_max), _ptr(out["V"]), _ptr(out["h"]), _ptr(out["A"])))
+        return out
 
     def pass_times(self, reset: bool = False) -> dict:
         """Accumulated device time per pass: {name: (total_ms, launches)}."""

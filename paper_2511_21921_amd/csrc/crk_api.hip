@@ -30,12 +30,13 @@ namespace {
 enum Pass {
   P_CELLS = 0, P_CAND, P_HSOLVE, P_NLIST, P_MOMENTS, P_DENSITY, P_FORCE,
   P_BWD_FORCE, P_BWD_DENSITY, P_BWD_CORR, P_BWD_MOMENTS, P_BWD_VOLUME, P_BWD_OTHER, P_STEP,
-  P_COOL, P_NPASS
+  P_COOL, P_DEPOSIT, P_NPASS
 };
 const char* kPassNames[P_NPASS] = {"cells",     "candidates",  "hsolve",      "nlist",
                                    "moments",   "density",     "force",       "bwd_force",
                                    "bwd_density", "bwd_corr",  "bwd_moments", "bwd_volume",
-                                   "bwd_other", "step", "cool"};
+                                   "bwd_other", "step", "cool",
+                                   "deposit"};
 }  // namespace
 
 struct crk_ctx {
@@ -67,6 +68,8 @@ struct crk_ctx {
   Buf cool_lam, cool_slope, cool_G, cool_run, cool_binint;
   int cool_K = 0;
   double cool_lu0 = 0.0, cool_dex = 0.0;
+  // subgrid deposition: one sorted point grid at a time and its counters
+  Buf dep_keys_a, dep_keys_b, dep_vals_a, dep_vals_b, dep_start, dep_tmp, dep_cnt;
   unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
   unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
@@ -912,6 +915,110 @@ crk_status step_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double l
   return st;
 }
 
+// Subgrid deposition (App. A.2 eq. (Vsg); eqs. (windmetal), (Anorm),
+// (starmetal), (stellarmom), (AGNE)): sorts n points into a periodic grid
+// of cells at least `radius` wide (one cell when fewer than 3 fit a side).
+crk_status dep_grid(crk_ctx* ctx, hipStream_t s, const double* x, int64_t n, double radius,
+                    int& G) {
+  const double box = ctx->p.box;
+  G = choose_grid(box, radius * (1.0 + 1e-9), n);
+  if (G < 3) G = 1;
+  const int64_t ncell = (int64_t)G * G * G;
+  CRK_HIP(ensure(ctx->dep_start, 4 * (size_t)(ncell + 1)), "deposition grid");
+  launch_point_keys(x, n, box, G, (uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p, s);
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
+  CRK_HIP(radix_sort_pairs((uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p,
+                           (uint32_t*)ctx->dep_keys_b.p, (uint32_t*)ctx->dep_vals_b.p, n, bits,
+                           (uint32_t*)ctx->dep_tmp.p, s),
+          "deposition sort");
+  launch_cell_bounds((const uint32_t*)ctx->dep_keys_a.p, n, ncell, (uint32_t*)ctx->dep_start.p,
+                     ~0ull, (unsigned long long*)ctx->dep_cnt.p, s);
+  CRK_HIP(hipGetLastError(), "deposition grid launch");
+  return CRK_OK;
+}
+
+// the largest value of one max counter of the deposition counters
+crk_status dep_read_max(crk_ctx* ctx, hipStream_t s, int slot, double& v) {
+  CRK_HIP(hipMemcpyAsync(ctx->host_raw, (unsigned long long*)ctx->dep_cnt.p + slot * kCntSpread,
+                         8 * kCntSpread, hipMemcpyDeviceToHost, s),
+          "deposition counters");
+  CRK_HIP(hipStreamSynchronize(s), "deposition counters");
+  unsigned long long b = 0;
+  for (int t = 0; t < kCntSpread; ++t) b = ctx->host_raw[t] > b ? ctx->host_raw[t] : b;
+  v = bits_to_double(b);
+  return CRK_OK;
+}
+
+template <class R>
+crk_status deposit_impl(crk_ctx* ctx, hipStream_t s, int64_t ng, const double* xg, const R* hg,
+                        const R* Vg, R* mg, R* vg, R* mZg, R* ug, int64_t ns, const double* xs,
+                        const R* dM, const R* dMZ, const R* dE, const R* vs, double n_h_s,
+                        double z_max, double m_max, R* Vs, R* hs, R* As) {
+  const crk_params& P = ctx->p;
+  const double box = P.box;
+  const double w0 = P.kernel == CRK_CUBIC_SPLINE ? Shape<0>::C * Shape<0>::w0
+                                                 : Shape<1>::C * Shape<1>::w0;
+  const double self_frac = w0 / (n_h_s * n_h_s * n_h_s);
+  if (!(self_frac < 1.0))
+    return fail(ctx, CRK_EINVAL, "n_h,s^3 must exceed C w(0): the self term alone exceeds 1/V_s");
+  if (ns == 0) return CRK_OK;
+  if (ng == 0) {
+    CRK_HIP(hipMemsetAsync(Vs, 0, sizeof(R) * ns, s), "deposition");
+    CRK_HIP(hipMemsetAsync(hs, 0, sizeof(R) * ns, s), "deposition");
+    CRK_HIP(hipMemsetAsync(As, 0, sizeof(R) * ns, s), "deposition");
+    return CRK_OK;
+  }
+  const int64_t nmax = std::max(ng, ns);
+  CRK_HIP(ensure(ctx->dep_keys_a, 4 * (size_t)nmax), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_keys_b, 4 * (size_t)nmax), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_vals_a, 4 * (size_t)nmax), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_vals_b, 4 * (size_t)nmax), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_tmp, 4 * (size_t)radix_tmp_words(nmax)), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_cnt, 8 * CNT_COUNT * (size_t)kCntSpread), "deposition workspace");
+  unsigned long long* cnt = (unsigned long long*)ctx->dep_cnt.p;
+  CRK_HIP(tbegin(ctx, P_DEPOSIT, s), "event");
+  CRK_HIP(hipMemsetAsync(cnt, 0, 8 * CNT_COUNT * (size_t)kCntSpread, s), "deposition");
+  // the gas search radius of eq. (Vsg): the largest gas h
+  launch_max_bits<R>(hg, ng, cnt, CNT_HMAX_BITS, s);
+  CRK_HIP(hipGetLastError(), "deposition launch");
+  double hmax = 0.0;
+  if (crk_status st = dep_read_max(ctx, s, CNT_HMAX_BITS, hmax)) return st;
+  if (!std::isfinite(hmax)) return fail(ctx, CRK_EINVAL, "gas h must be finite and > 0");
+  if (!(hmax < 0.5 * box))
+    return fail(ctx, CRK_EDOMAIN, "gas smoothing length must stay below half the box");
+  int G = 1;
+  if (crk_status st = dep_grid(ctx, s, xg, ng, hmax, G)) return st;
+  launch_dep_volume<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
+                       (const uint32_t*)ctx->dep_vals_a.p, xg, ng, hg, xs, ns, self_frac, n_h_s,
+                       Vs, hs, cnt, s);
+  CRK_HIP(hipGetLastError(), "deposition launch");
+  double hsmax = 0.0;
+  if (crk_status st = dep_read_max(ctx, s, CNT_HMAX_OUT_BITS, hsmax)) return st;
+  if (!std::isfinite(hsmax)) return fail(ctx, CRK_ENONFINITE, "source volume is not finite");
+  if (hsmax == 0.0) {  // no source has gas in reach: nothing moves
+    CRK_HIP(hipMemsetAsync(As, 0, sizeof(R) * ns, s), "deposition");
+    CRK_HIP(tend(ctx, P_DEPOSIT, s), "event");
+    return CRK_OK;
+  }
+  if (!(hsmax < 0.5 * box))
+    return fail(ctx, CRK_EDOMAIN, "source smoothing length must stay below half the box");
+  // the normalisation of eq. (Anorm) searches the gas within h_s
+  if (crk_status st = dep_grid(ctx, s, xg, ng, hsmax, G)) return st;
+  launch_dep_norm<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
+                     (const uint32_t*)ctx->dep_vals_a.p, xg, ng, Vg, mg, mZg, xs, ns, hs, z_max,
+                     m_max, As, s);
+  CRK_HIP(hipGetLastError(), "deposition launch");
+  // every gas particle gathers the sources within their h_s
+  if (crk_status st = dep_grid(ctx, s, xs, ns, hsmax, G)) return st;
+  launch_dep_gather<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
+                       (const uint32_t*)ctx->dep_vals_a.p, xg, ng, Vg, mg, vg, mZg, ug, xs, ns,
+                       hs, As, dM, dMZ, dE, vs, z_max, m_max, s);
+  CRK_HIP(hipGetLastError(), "deposition launch");
+  CRK_HIP(tend(ctx, P_DEPOSIT, s), "event");
+  return CRK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -986,6 +1093,8 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
                 &c->cool_lam, &c->cool_slope, &c->cool_G, &c->cool_run, &c->cool_binint,
+                &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
+                &c->dep_tmp, &c->dep_cnt,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
@@ -1151,6 +1260,40 @@ crk_status crk_cool(crk_ctx* ctx, void* hip_stream, long long n, double dt, cons
   CRK_HIP(tend(ctx, P_COOL, s), "event");
   CRK_HIP(hipGetLastError(), "cooling launch");
   return CRK_OK;
+}
+
+crk_status crk_deposit(crk_ctx* ctx, void* hip_stream, long long n_gas, const double* x_gas,
+                       const void* h_gas, const void* V_gas, void* m_gas, void* v_gas,
+                       void* mZ_gas, void* u_gas, long long n_src, const double* x_src,
+                       const void* dM, const void* dMZ, const void* dE, const void* v_src,
+                       double n_h_src, double z_max, double m_max, void* V_src, void* h_src,
+                       void* A_src) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (n_gas < 0 || n_src < 0) return fail(ctx, CRK_EINVAL, "counts must be >= 0");
+  if (n_gas > 0xffffffffLL || n_src > 0xffffffffLL)
+    return fail(ctx, CRK_EINVAL, "counts must fit 32-bit indices");
+  if (!(n_h_src > 0.0) || !std::isfinite(n_h_src))
+    return fail(ctx, CRK_EINVAL, "n_h_src must be finite and > 0");
+  if (std::isnan(z_max) || std::isnan(m_max))
+    return fail(ctx, CRK_EINVAL, "z_max and m_max must not be NaN");
+  if (n_src > 0 && (!x_src || !dM || !dMZ || !dE || !v_src || !V_src || !h_src || !A_src))
+    return fail(ctx, CRK_EINVAL, "null source array");
+  if (n_src > 0 && n_gas > 0 &&
+      (!x_gas || !h_gas || !V_gas || !m_gas || !v_gas || !mZ_gas || !u_gas))
+    return fail(ctx, CRK_EINVAL, "null gas array");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (ctx->p.precision == CRK_FP64)
+    return deposit_impl<double>(ctx, s, n_gas, x_gas, (const double*)h_gas, (const double*)V_gas,
+                                (double*)m_gas, (double*)v_gas, (double*)mZ_gas, (double*)u_gas,
+                                n_src, x_src, (const double*)dM, (const double*)dMZ,
+                                (const double*)dE, (const double*)v_src, n_h_src, z_max, m_max,
+                                (double*)V_src, (double*)h_src, (double*)A_src);
+  return deposit_impl<float>(ctx, s, n_gas, x_gas, (const float*)h_gas, (const float*)V_gas,
+                             (float*)m_gas, (float*)v_gas, (float*)mZ_gas, (float*)u_gas, n_src,
+                             x_src, (const float*)dM, (const float*)dMZ, (const float*)dE,
+                             (const float*)v_src, n_h_src, z_max, m_max, (float*)V_src,
+                             (float*)h_src, (float*)A_src);
 }
 
 }  // extern "C"

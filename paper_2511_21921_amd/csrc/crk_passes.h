@@ -116,6 +116,28 @@ template <class R>
 void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, const double* dudt,
                        hipStream_t s);
 
+// subgrid deposition: point grids and the three gathers (caller order)
+void launch_point_keys(const double* x, int64_t n, double box, int G, uint32_t* keys,
+                       uint32_t* vals, hipStream_t s);
+template <class R>
+void launch_max_bits(const R* a, int64_t n, unsigned long long* cnt, int slot, hipStream_t s);
+template <class R>
+void launch_dep_volume(int kernel, int G, double ell, double box, const uint32_t* start,
+                       const uint32_t* perm, const double* xg, int64_t ng, const R* hg,
+                       const double* xs, int64_t ns, double self_frac, double n_h_s, R* Vs, R* hs,
+                       unsigned long long* cnt, hipStream_t s);
+template <class R>
+void launch_dep_norm(int kernel, int G, double ell, double box, const uint32_t* start,
+                     const uint32_t* perm, const double* xg, int64_t ng, const R* Vg, const R* mg,
+                     const R* mZg, const double* xs, int64_t ns, const R* hs, double z_max,
+                     double m_max, R* As, hipStream_t s);
+template <class R>
+void launch_dep_gather(int kernel, int G, double ell, double box, const uint32_t* start,
+                       const uint32_t* perm, const double* xg, int64_t ng, const R* Vg, R* mg,
+                       R* vg, R* mZg, R* ug, const double* xs, int64_t ns, const R* hs,
+                       const R* As, const R* dM, const R* dMZ, const R* dE, const R* vs,
+                       double z_max, double m_max, hipStream_t s);
+
 // exact-integration cooling (caller order, elementwise); run holds int2 per bin
 void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
                          double* G, void* run, double* binint, hipStream_t s);
