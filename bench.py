@@ -196,6 +196,42 @@ def run_cool(n, steps, warmup, seed=11):
     return us, K
 
 
+def run_deposit(ng, ns, steps, warmup, seed=12):
+    """Subgrid deposition of ns FP32 sources into ng FP32 gas particles, both
+    uniform in the box; gas h for ~32 neighbours with a 20% spread, volumes
+    1/ng; the sources hand over mass, metals, energy and momentum."""
+    import numpy as np
+    import torch
+
+    from paper_2511_21921_amd import FP32, Context, Params, WENDLAND_C4
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    f = dict(dtype=torch.float32, device=dev)
+    h0 = (32 / (4 * np.pi / 3) / ng) ** (1 / 3)
+    gas = {"x": torch.tensor(rng.uniform(0, 1, (3, ng)), dtype=torch.float64, device=dev),
+           "h": torch.tensor(h0 * (1 + 0.2 * rng.uniform(-1, 1, ng)), **f),
+           "V": torch.full((ng,), 1.0 / ng, **f), "m": torch.full((ng,), 1.0 / ng, **f),
+           "mZ": torch.full((ng,), 0.01 / ng, **f), "u": torch.ones(ng, **f),
+           "v": torch.tensor(rng.normal(0, 0.1, (3, ng)), **f)}
+    src = {"x": torch.tensor(rng.uniform(0, 1, (3, ns)), dtype=torch.float64, device=dev),
+           "dM": torch.full((ns,), 1e-3 / ng, **f), "dMZ": torch.full((ns,), 1e-5 / ng, **f),
+           "dE": torch.full((ns,), 1e-3 / ng, **f),
+           "v": torch.tensor(rng.normal(0, 0.1, (3, ns)), **f)}
+    ctx = Context(Params(precision=FP32, kernel=WENDLAND_C4, timing=1))
+    for _ in range(warmup):
+        ctx.deposit(gas, src, 2.25)
+    torch.cuda.synchronize()
+    ctx.pass_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.deposit(gas, src, 2.25)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e6
+    dev_us = pass_ms(ctx.pass_times(reset=True), "deposit") * 1e3
+    ctx.close()
+    return wall, dev_us
+
+
 def pass_ms(passes, name):
     tot, calls = passes[name]
     return tot / calls if calls else float("nan")
@@ -290,6 +326,15 @@ def main():
                                            3)}}
     log("cooling: %.1f us for %d particles" % (cus, ncool))
 
+    # subgrid deposition (App. A.2 eq. (Vsg), eq. (Anorm)): 2^21 gas, 2^16 sources
+    ngas, nsrc = 1 << 21, 1 << 16
+    dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
+    dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
+           "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
+           "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 uniform "
+                       "sources, Wendland C4, n_h,s = 2.25; three grid builds, two host reads"}
+    log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
+
     fp64 = None
     if not args.no_fp64:
         k64 = max(3, args.steps // 2)
@@ -367,7 +412,8 @@ def main():
                 "workload": "sedov64 (same particles, zero velocity), forward only",
                 "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "c4_268": c4, "kdk_step": kdk, "cooling": cool, "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
+        "c4_268": c4, "kdk_step": kdk, "cooling": cool, "deposit": dep,
+        "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     if args.calibration_copy:

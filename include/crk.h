@@ -249,9 +249,13 @@ crk_status crk_cool(crk_ctx *ctx, void *hip_stream, long long n, double dt, cons
  *   m_gas, mZ_gas, u_gas [n_gas], v_gas [3][n_gas] in/out;
  *   x_src [3][n_src], dM, dMZ, dE [n_src], v_src [3][n_src] in;
  *   V_src, h_src, A_src [n_src] out.
- * Each gas particle gathers its sources (no float atomics; reproducible).
- * Arithmetic is FP64 in both precisions; the kernel shape is the context's.
- * The call reads two maxima back to the host (synchronises the stream).
+ * Sources search one grid of the gas (cells at least the largest gas h) with
+ * a stencil as wide as their own radius; their receivers are listed, sorted
+ * by gas index (stable) and summed per gas particle in source order: no
+ * float atomics, reproducible results. Arithmetic is FP64 in both
+ * precisions; the kernel shape is the context's. The call reads counters
+ * back to the host twice (synchronises the stream); workspace grows with
+ * the number of source-gas pairs (CRK_ENOMEM beyond 2^31).
  * Errors: CRK_EINVAL for negative counts, null arrays, n_h_src^3 <= C w(0),
  * NaN limits, gas h not finite or <= 0; CRK_EDOMAIN when a gas or source
  * smoothing length reaches half the box. n_src = 0 is a no-op. */

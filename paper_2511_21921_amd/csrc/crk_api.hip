@@ -70,6 +70,8 @@ struct crk_ctx {
   double cool_lu0 = 0.0, cool_dex = 0.0;
   // subgrid deposition: one sorted point grid at a time and its counters
   Buf dep_keys_a, dep_keys_b, dep_vals_a, dep_vals_b, dep_start, dep_tmp, dep_cnt;
+  Buf dep_npair, dep_off, dep_first, dep_pj_a, dep_pj_b, dep_ps_a, dep_ps_b, dep_ptmp, dep_p4,
+      dep_pv, dep_sp;
   unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
   unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
@@ -916,38 +918,29 @@ crk_status step_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double l
 }
 
 // Subgrid deposition (App. A.2 eq. (Vsg); eqs. (windmetal), (Anorm),
-// (starmetal), (stellarmom), (AGNE)): sorts n points into a periodic grid
-// of cells at least `radius` wide (one cell when fewer than 3 fit a side).
-crk_status dep_grid(crk_ctx* ctx, hipStream_t s, const double* x, int64_t n, double radius,
-                    int& G) {
-  const double box = ctx->p.box;
-  G = choose_grid(box, radius * (1.0 + 1e-9), n);
-  if (G < 3) G = 1;
-  const int64_t ncell = (int64_t)G * G * G;
-  CRK_HIP(ensure(ctx->dep_start, 4 * (size_t)(ncell + 1)), "deposition grid");
-  launch_point_keys(x, n, box, G, (uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p, s);
-  int bits = 1;
-  while (bits < 31 && ((int64_t)1 << bits) < ncell) ++bits;
-  CRK_HIP(radix_sort_pairs((uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p,
-                           (uint32_t*)ctx->dep_keys_b.p, (uint32_t*)ctx->dep_vals_b.p, n, bits,
-                           (uint32_t*)ctx->dep_tmp.p, s),
-          "deposition sort");
-  launch_cell_bounds((const uint32_t*)ctx->dep_keys_a.p, n, ncell, (uint32_t*)ctx->dep_start.p,
-                     ~0ull, (unsigned long long*)ctx->dep_cnt.p, s);
-  CRK_HIP(hipGetLastError(), "deposition grid launch");
+// (starmetal), (stellarmom), (AGNE)): folds the deposition counters (max
+// slots for the *_BITS counters, sums otherwise) after a read-back.
+crk_status dep_read(crk_ctx* ctx, hipStream_t s, unsigned long long* out) {
+  CRK_HIP(hipMemcpyAsync(ctx->host_raw, ctx->dep_cnt.p, 8 * CNT_COUNT * kCntSpread,
+                         hipMemcpyDeviceToHost, s),
+          "deposition counters");
+  CRK_HIP(hipStreamSynchronize(s), "deposition counters");
+  for (int k = 0; k < CNT_COUNT; ++k) {
+    const bool is_max = k == CNT_HMAX_BITS || k == CNT_HMAX_OUT_BITS;
+    unsigned long long v = 0;
+    for (int t = 0; t < kCntSpread; ++t) {
+      const unsigned long long x = ctx->host_raw[k * kCntSpread + t];
+      v = is_max ? (x > v ? x : v) : v + x;
+    }
+    out[k] = v;
+  }
   return CRK_OK;
 }
 
-// the largest value of one max counter of the deposition counters
-crk_status dep_read_max(crk_ctx* ctx, hipStream_t s, int slot, double& v) {
-  CRK_HIP(hipMemcpyAsync(ctx->host_raw, (unsigned long long*)ctx->dep_cnt.p + slot * kCntSpread,
-                         8 * kCntSpread, hipMemcpyDeviceToHost, s),
-          "deposition counters");
-  CRK_HIP(hipStreamSynchronize(s), "deposition counters");
-  unsigned long long b = 0;
-  for (int t = 0; t < kCntSpread; ++t) b = ctx->host_raw[t] > b ? ctx->host_raw[t] : b;
-  v = bits_to_double(b);
-  return CRK_OK;
+int bits_for(int64_t n) {
+  int b = 1;
+  while (b < 31 && ((int64_t)1 << b) < n) ++b;
+  return b;
 }
 
 template <class R>
@@ -969,52 +962,84 @@ crk_status deposit_impl(crk_ctx* ctx, hipStream_t s, int64_t ng, const double* x
     CRK_HIP(hipMemsetAsync(As, 0, sizeof(R) * ns, s), "deposition");
     return CRK_OK;
   }
-  const int64_t nmax = std::max(ng, ns);
-  CRK_HIP(ensure(ctx->dep_keys_a, 4 * (size_t)nmax), "deposition workspace");
-  CRK_HIP(ensure(ctx->dep_keys_b, 4 * (size_t)nmax), "deposition workspace");
-  CRK_HIP(ensure(ctx->dep_vals_a, 4 * (size_t)nmax), "deposition workspace");
-  CRK_HIP(ensure(ctx->dep_vals_b, 4 * (size_t)nmax), "deposition workspace");
-  CRK_HIP(ensure(ctx->dep_tmp, 4 * (size_t)radix_tmp_words(nmax)), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_keys_a, 4 * (size_t)ng), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_keys_b, 4 * (size_t)ng), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_vals_a, 4 * (size_t)ng), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_vals_b, 4 * (size_t)ng), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_first, 4 * (size_t)(ng + 1)), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_npair, 4 * (size_t)ns), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_off, 4 * (size_t)ns), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_tmp, 4 * (size_t)std::max(radix_tmp_words(ng), scan_tmp_words(ns))),
+          "deposition workspace");
   CRK_HIP(ensure(ctx->dep_cnt, 8 * CNT_COUNT * (size_t)kCntSpread), "deposition workspace");
   unsigned long long* cnt = (unsigned long long*)ctx->dep_cnt.p;
+  unsigned long long folded[CNT_COUNT];
   CRK_HIP(tbegin(ctx, P_DEPOSIT, s), "event");
   CRK_HIP(hipMemsetAsync(cnt, 0, 8 * CNT_COUNT * (size_t)kCntSpread, s), "deposition");
   // the gas search radius of eq. (Vsg): the largest gas h
   launch_max_bits<R>(hg, ng, cnt, CNT_HMAX_BITS, s);
   CRK_HIP(hipGetLastError(), "deposition launch");
-  double hmax = 0.0;
-  if (crk_status st = dep_read_max(ctx, s, CNT_HMAX_BITS, hmax)) return st;
+  if (crk_status st = dep_read(ctx, s, folded)) return st;
+  const double hmax = bits_to_double(folded[CNT_HMAX_BITS]);
   if (!std::isfinite(hmax)) return fail(ctx, CRK_EINVAL, "gas h must be finite and > 0");
   if (!(hmax < 0.5 * box))
     return fail(ctx, CRK_EDOMAIN, "gas smoothing length must stay below half the box");
-  int G = 1;
-  if (crk_status st = dep_grid(ctx, s, xg, ng, hmax, G)) return st;
-  launch_dep_volume<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
-                       (const uint32_t*)ctx->dep_vals_a.p, xg, ng, hg, xs, ns, self_frac, n_h_s,
-                       Vs, hs, cnt, s);
+  // the gas grid: cells at least the largest gas h
+  const int G = choose_grid(box, hmax * (1.0 + 1e-9), ng);
+  const int64_t ncell = (int64_t)G * G * G;
+  CRK_HIP(ensure(ctx->dep_start, 4 * (size_t)(ncell + 1)), "deposition grid");
+  launch_point_keys(xg, ng, box, G, (uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p,
+                    s);
+  CRK_HIP(radix_sort_pairs((uint32_t*)ctx->dep_keys_a.p, (uint32_t*)ctx->dep_vals_a.p,
+                           (uint32_t*)ctx->dep_keys_b.p, (uint32_t*)ctx->dep_vals_b.p, ng,
+                           bits_for(ncell), (uint32_t*)ctx->dep_tmp.p, s),
+          "deposition sort");
+  launch_cell_bounds((const uint32_t*)ctx->dep_keys_a.p, ng, ncell, (uint32_t*)ctx->dep_start.p,
+                     ~0ull, cnt, s);
+  CRK_HIP(ensure(ctx->dep_p4, 32 * (size_t)ng), "deposition workspace");
+  CRK_HIP(ensure(ctx->dep_pv, 16 * (size_t)ng), "deposition workspace");
+  // the sort's second key buffer is free again: it holds the ranks
+  launch_dep_pack<R>((const uint32_t*)ctx->dep_vals_a.p, (uint32_t*)ctx->dep_keys_b.p, xg, ng, hg,
+                     Vg, mg, mZg, z_max, m_max, ctx->dep_p4.p, ctx->dep_pv.p, s);
+  const DepGrid grid{G, box, hmax, (const uint32_t*)ctx->dep_start.p,
+                     (const uint32_t*)ctx->dep_vals_a.p, ctx->dep_p4.p, ctx->dep_pv.p};
+  launch_dep_volume<R>(P.kernel, grid, xs, ns, self_frac, n_h_s, Vs, hs, s);
+  uint32_t* npair = (uint32_t*)ctx->dep_npair.p;
+  CRK_HIP(ensure(ctx->dep_sp, 96 * (size_t)ns), "deposition workspace");
+  launch_dep_norm<R>(P.kernel, grid, xs, ns, hs, dM, dMZ, dE, vs, As, ctx->dep_sp.p, npair, cnt, s);
   CRK_HIP(hipGetLastError(), "deposition launch");
-  double hsmax = 0.0;
-  if (crk_status st = dep_read_max(ctx, s, CNT_HMAX_OUT_BITS, hsmax)) return st;
+  if (crk_status st = dep_read(ctx, s, folded)) return st;
+  const double hsmax = bits_to_double(folded[CNT_HMAX_OUT_BITS]);
+  const unsigned long long npairs = folded[CNT_PAIRS_GATHER];
   if (!std::isfinite(hsmax)) return fail(ctx, CRK_ENONFINITE, "source volume is not finite");
-  if (hsmax == 0.0) {  // no source has gas in reach: nothing moves
-    CRK_HIP(hipMemsetAsync(As, 0, sizeof(R) * ns, s), "deposition");
-    CRK_HIP(tend(ctx, P_DEPOSIT, s), "event");
-    return CRK_OK;
-  }
   if (!(hsmax < 0.5 * box))
     return fail(ctx, CRK_EDOMAIN, "source smoothing length must stay below half the box");
-  // the normalisation of eq. (Anorm) searches the gas within h_s
-  if (crk_status st = dep_grid(ctx, s, xg, ng, hsmax, G)) return st;
-  launch_dep_norm<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
-                     (const uint32_t*)ctx->dep_vals_a.p, xg, ng, Vg, mg, mZg, xs, ns, hs, z_max,
-                     m_max, As, s);
-  CRK_HIP(hipGetLastError(), "deposition launch");
-  // every gas particle gathers the sources within their h_s
-  if (crk_status st = dep_grid(ctx, s, xs, ns, hsmax, G)) return st;
-  launch_dep_gather<R>(P.kernel, G, box / G, box, (const uint32_t*)ctx->dep_start.p,
-                       (const uint32_t*)ctx->dep_vals_a.p, xg, ng, Vg, mg, vg, mZg, ug, xs, ns,
-                       hs, As, dM, dMZ, dE, vs, z_max, m_max, s);
-  CRK_HIP(hipGetLastError(), "deposition launch");
+  if (npairs > 0x7fffffffull) return fail(ctx, CRK_ENOMEM, "more than 2^31 source-gas pairs");
+  if (npairs > 0) {
+    // receivers of every source at its offset, grouped by gas index (stable:
+    // source order within a gas particle), then one sum per gas particle
+    const int64_t np = (int64_t)npairs;
+    CRK_HIP(ensure(ctx->dep_pj_a, 4 * (size_t)np), "deposition pairs");
+    CRK_HIP(ensure(ctx->dep_pj_b, 4 * (size_t)np), "deposition pairs");
+    CRK_HIP(ensure(ctx->dep_ps_a, 4 * (size_t)np), "deposition pairs");
+    CRK_HIP(ensure(ctx->dep_ps_b, 4 * (size_t)np), "deposition pairs");
+    CRK_HIP(ensure(ctx->dep_ptmp, 4 * (size_t)radix_tmp_words(np)), "deposition pairs");
+    CRK_HIP(exclusive_scan_u32(npair, (uint32_t*)ctx->dep_off.p, ns, (uint32_t*)ctx->dep_tmp.p,
+                               s),
+            "deposition scan");
+    launch_dep_pairs<R>(grid, xs, ns, hs, npair, (const uint32_t*)ctx->dep_off.p,
+                        (uint32_t*)ctx->dep_pj_a.p, (uint32_t*)ctx->dep_ps_a.p, s);
+    CRK_HIP(radix_sort_pairs((uint32_t*)ctx->dep_pj_a.p, (uint32_t*)ctx->dep_ps_a.p,
+                             (uint32_t*)ctx->dep_pj_b.p, (uint32_t*)ctx->dep_ps_b.p, np,
+                             bits_for(ng), (uint32_t*)ctx->dep_ptmp.p, s),
+            "deposition pair sort");
+    launch_cell_bounds((const uint32_t*)ctx->dep_pj_a.p, np, ng, (uint32_t*)ctx->dep_first.p,
+                       ~0ull, cnt, s);
+    launch_dep_apply<R>(P.kernel, xg, ng, Vg, mg, vg, mZg, ug, ctx->dep_sp.p,
+                        (const uint32_t*)ctx->dep_first.p, (const uint32_t*)ctx->dep_ps_a.p, box,
+                        s);
+    CRK_HIP(hipGetLastError(), "deposition launch");
+  }
   CRK_HIP(tend(ctx, P_DEPOSIT, s), "event");
   return CRK_OK;
 }
@@ -1094,7 +1119,9 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
                 &c->cool_lam, &c->cool_slope, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
-                &c->dep_tmp, &c->dep_cnt,
+                &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,
+                &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
+                &c->dep_p4, &c->dep_pv, &c->dep_sp,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);

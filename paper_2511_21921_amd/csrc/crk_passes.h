@@ -116,27 +116,41 @@ template <class R>
 void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, const double* dudt,
                        hipStream_t s);
 
-// subgrid deposition: point grids and the three gathers (caller order)
+// subgrid deposition: the gas grid, the source passes, the pair list and
+// the per-gas sums (caller order)
 void launch_point_keys(const double* x, int64_t n, double box, int G, uint32_t* keys,
                        uint32_t* vals, hipStream_t s);
 template <class R>
 void launch_max_bits(const R* a, int64_t n, unsigned long long* cnt, int slot, hipStream_t s);
+// the sorted gas of one deposition call (p4: double4 x, y, z, h per gas)
+struct DepGrid {
+  int G;
+  double box;
+  double hmax;            // the largest gas h
+  const uint32_t* start;  // [G^3 + 1]
+  const uint32_t* perm;   // [n] sorted -> caller index
+  const void* p4;         // [n] double4
+  const void* pv;         // [n] double2: V (-1 where the gas may not receive), 1 / h
+};
 template <class R>
-void launch_dep_volume(int kernel, int G, double ell, double box, const uint32_t* start,
-                       const uint32_t* perm, const double* xg, int64_t ng, const R* hg,
-                       const double* xs, int64_t ns, double self_frac, double n_h_s, R* Vs, R* hs,
-                       unsigned long long* cnt, hipStream_t s);
+void launch_dep_pack(const uint32_t* perm, uint32_t* rank, const double* xg, int64_t ng,
+                     const R* hg, const R* Vg, const R* mg, const R* mZg, double z_max,
+                     double m_max, void* p4, void* pv, hipStream_t s);
 template <class R>
-void launch_dep_norm(int kernel, int G, double ell, double box, const uint32_t* start,
-                     const uint32_t* perm, const double* xg, int64_t ng, const R* Vg, const R* mg,
-                     const R* mZg, const double* xs, int64_t ns, const R* hs, double z_max,
-                     double m_max, R* As, hipStream_t s);
+void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t ns,
+                       double self_frac, double n_h_s, R* Vs, R* hs, hipStream_t s);
 template <class R>
-void launch_dep_gather(int kernel, int G, double ell, double box, const uint32_t* start,
-                       const uint32_t* perm, const double* xg, int64_t ng, const R* Vg, R* mg,
-                       R* vg, R* mZg, R* ug, const double* xs, int64_t ns, const R* hs,
-                       const R* As, const R* dM, const R* dMZ, const R* dE, const R* vs,
-                       double z_max, double m_max, hipStream_t s);
+void launch_dep_norm(int kernel, const DepGrid& d, const double* xs, int64_t ns, const R* hs,
+                     const R* dM, const R* dMZ, const R* dE, const R* vs, R* As, void* sp,
+                     uint32_t* npair, unsigned long long* cnt, hipStream_t s);
+template <class R>
+void launch_dep_pairs(const DepGrid& d, const double* xs, int64_t ns, const R* hs,
+                      const uint32_t* npair, const uint32_t* off, uint32_t* pj, uint32_t* ps,
+                      hipStream_t s);
+template <class R>
+void launch_dep_apply(int kernel, const double* xg, int64_t ng, const R* Vg, R* mg, R* vg, R* mZg,
+                      R* ug, const void* sp, const uint32_t* first, const uint32_t* ps, double box,
+                      hipStream_t s);
 
 // exact-integration cooling (caller order, elementwise); run holds int2 per bin
 void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
