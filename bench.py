@@ -332,7 +332,7 @@ def main():
     dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
            "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
            "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 uniform "
-                       "sources, Wendland C4, n_h,s = 2.25; three grid builds, two host reads"}
+                       "sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair sort, two host reads"}
     log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
 
     fp64 = None

@@ -66,26 +66,26 @@ __device__ inline double min_image2(double ax, double ay, double az, double4 b,
 // row cut to the cells whose gap in x is within what remains of r. Gaps are
 // taken slightly short, so the pruning only ever keeps more. When the
 // stencil would wrap onto itself (2k+1 >= G) the whole grid is visited, each
-// cell once. All lanes call f(q, valid) together (q a sorted index), 64
-// candidates at a time, in the same order on every run.
+// cell once. Each lane sets up one row (one or two contiguous ranges of the
+// sorted order, so the cell starts of 64 rows load at once); the wave then
+// runs through the rows' candidates 64 at a time across row boundaries. All
+// lanes call f(q, valid) together (q a sorted index), in the same order on
+// every run.
 template <class F>
 __device__ inline void wave_near(const PointGrid& g, double x, double y, double z, double r,
                                  F&& f) {
   const int G = g.G;
   const int lane = threadIdx.x & 63;
-  auto range = [&](int c0, int c1) {
-    const uint32_t a = g.start[c0], b = g.start[c1];
-    for (uint32_t q0 = a; q0 < b; q0 += 64) {
-      const uint32_t q = q0 + lane;
-      const bool valid = q < b;
-      f(valid ? q : 0u, valid);
-    }
-  };
   const double cw = g.box / G;  // cell width
   const double rc = r / cw * (1.0 + 1e-9);  // the radius in cells, with a margin
   const int k = (int)ceil(rc);
   if (2 * k + 1 >= G) {
-    range(0, G * G * G);  // the sorted order runs through all cells
+    // the sorted order runs through all cells
+    const uint32_t b = g.start[G * G * G];
+    for (uint32_t q0 = 0; q0 < b; q0 += 64) {
+      const uint32_t q = q0 + lane;
+      f(q < b ? q : 0u, q < b);
+    }
     return;
   }
   // the point in cell units: cell index and offset inside the cell
@@ -108,27 +108,59 @@ __device__ inline void wave_near(const PointGrid& g, double x, double y, double 
     return v > 1e-9 ? v - 1e-9 : 0.0;
   };
   const double rc2 = rc * rc;
-  for (int dz = -k; dz <= k; ++dz) {
-    const double gz = gap(dz, fz);
-    if (gz * gz >= rc2) continue;
-    for (int dy = -k; dy <= k; ++dy) {
-      const double gy = gap(dy, fy);
+  const int side = 2 * k + 1, nrows = side * side;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    // this lane's row: dz, dy = row index / side, row index % side (minus k)
+    uint32_t a1 = 0, n1 = 0, a2 = 0, n2 = 0;
+    const int ri = r0 + lane;
+    if (ri < nrows) {
+      const int dz = ri / side - k, dy = ri % side - k;
+      const double gz = gap(dz, fz), gy = gap(dy, fy);
       const double gyz = gy * gy + gz * gz;
-      if (gyz >= rc2) continue;
-      const double rx = sqrt(rc2 - gyz);
-      int dpos = (int)ceil(rx + fx + 1e-9) - 1;
-      int dneg = (int)ceil(rx + 1.0 - fx + 1e-9) - 1;
-      dpos = dpos > k ? k : (dpos < 0 ? 0 : dpos);
-      dneg = dneg > k ? k : (dneg < 0 ? 0 : dneg);
-      const int span = dneg + dpos + 1;
-      const int row = ((iz + dz + G) % G * G + (iy + dy + G) % G) * G;
-      const int x0 = (ix - dneg + G) % G;
-      if (x0 + span <= G) {
-        range(row + x0, row + x0 + span);
-      } else {
-        range(row + x0, row + G);
-        range(row, row + x0 + span - G);
+      if (gyz < rc2) {
+        const double rx = sqrt(rc2 - gyz);
+        int dpos = (int)ceil(rx + fx + 1e-9) - 1;
+        int dneg = (int)ceil(rx + 1.0 - fx + 1e-9) - 1;
+        dpos = dpos > k ? k : (dpos < 0 ? 0 : dpos);
+        dneg = dneg > k ? k : (dneg < 0 ? 0 : dneg);
+        const int span = dneg + dpos + 1;
+        const int row = ((iz + dz + G) % G * G + (iy + dy + G) % G) * G;
+        const int x0 = (ix - dneg + G) % G;
+        if (x0 + span <= G) {
+          a1 = g.start[row + x0];
+          n1 = g.start[row + x0 + span] - a1;
+        } else {
+          a1 = g.start[row + x0];
+          n1 = g.start[row + G] - a1;
+          a2 = g.start[row];
+          n2 = g.start[row + x0 + span - G] - a2;
+        }
       }
+    }
+    // exclusive prefix of the rows' candidate counts over the lanes
+    const uint32_t len = n1 + n2;
+    uint32_t pre = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(pre, o, 64);
+      if (lane >= o) pre += t;
+    }
+    const uint32_t total = __shfl(pre, 63, 64);
+    pre -= len;
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+      const uint32_t c = c0 + lane;
+      // the row holding candidate c: the last lane whose prefix is <= c
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const uint32_t p = __shfl(pre, lo + step, 64);
+        if (p <= c) lo += step;
+      }
+      const uint32_t o = c - __shfl(pre, lo, 64);
+      const uint32_t b1 = __shfl(a1, lo, 64), m1 = __shfl(n1, lo, 64);
+      const uint32_t b2 = __shfl(a2, lo, 64);
+      const bool valid = c < total;
+      f(valid ? (o < m1 ? b1 + o : b2 + (o - m1)) : 0u, valid);
     }
   }
 }
@@ -211,12 +243,11 @@ __global__ void __launch_bounds__(kBlock) k_dep_pack(const uint32_t* __restrict_
 }
 
 constexpr int kWaves = kBlock / 64;  // sources per block in the source passes
-
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_dep_volume(PointGrid gas, const double* __restrict__ xs,
-                                                       int64_t ns,
-                                                       double self_frac, double n_h_s,
-                                                       R* __restrict__ Vs, R* __restrict__ hs) {
+__global__ void __launch_bounds__(kBlock)
+    k_dep_volume(PointGrid gas, const double* __restrict__ xs,
+                 int64_t ns, double self_frac, double n_h_s, R* __restrict__ Vs,
+                 R* __restrict__ hs) {
   const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (s >= ns) return;  // whole waves
   double sum = 0.0;
@@ -243,16 +274,12 @@ __global__ void __launch_bounds__(kBlock) k_dep_volume(PointGrid gas, const doub
 // A_s and the number of receivers of every source; the largest h_s (double
 // bits, CNT_HMAX_OUT_BITS) and the total receiver count (CNT_PAIRS_GATHER).
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_dep_norm(PointGrid gas, const double* __restrict__ xs,
-                                                     int64_t ns, const R* __restrict__ hs,
-                                                     const R* __restrict__ dM,
-                                                     const R* __restrict__ dMZ,
-                                                     const R* __restrict__ dE,
-                                                     const R* __restrict__ vs,
-                                                     R* __restrict__ As,
-                                                     double4* __restrict__ sp,
-                                                     uint32_t* __restrict__ npair,
-                                                     unsigned long long* __restrict__ cnt) {
+__global__ void __launch_bounds__(kBlock)
+    k_dep_norm(PointGrid gas, const double* __restrict__ xs,
+               int64_t ns, const R* __restrict__ hs, const R* __restrict__ dM,
+               const R* __restrict__ dMZ, const R* __restrict__ dE, const R* __restrict__ vs,
+               R* __restrict__ As, double4* __restrict__ sp, uint32_t* __restrict__ npair,
+               unsigned long long* __restrict__ cnt) {
   const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (s >= ns) return;  // whole waves
   const double h = (double)hs[s];
@@ -298,12 +325,11 @@ __global__ void __launch_bounds__(kBlock) k_dep_norm(PointGrid gas, const double
 // writes each source's receivers (gas index, source index) at its offset,
 // in the order of the traversal of k_dep_norm
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_dep_pairs(PointGrid gas, const double* __restrict__ xs,
-                                                      int64_t ns, const R* __restrict__ hs,
-                                                      const uint32_t* __restrict__ npair,
-                                                      const uint32_t* __restrict__ off,
-                                                      uint32_t* __restrict__ pj,
-                                                      uint32_t* __restrict__ ps) {
+__global__ void __launch_bounds__(kBlock)
+    k_dep_pairs(PointGrid gas, const double* __restrict__ xs,
+                int64_t ns, const R* __restrict__ hs, const uint32_t* __restrict__ npair,
+                const uint32_t* __restrict__ off, uint32_t* __restrict__ pj,
+                uint32_t* __restrict__ ps) {
   const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (s >= ns) return;  // whole waves
   const uint32_t c = npair[s];
@@ -394,8 +420,7 @@ void launch_dep_pack(const uint32_t* perm, uint32_t* rank, const double* xg, int
 }
 
 template <class R>
-void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t ns,
-                       double self_frac, double n_h_s, R* Vs, R* hs, hipStream_t s) {
+void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t ns, double self_frac, double n_h_s, R* Vs, R* hs, hipStream_t s) {
   PointGrid g{d.G, d.box, 1.0 / d.box, d.hmax, d.start, d.perm, (const double4*)d.p4,
               (const double2*)d.pv};
   CRK_DEP_DISPATCH(kernel, k_dep_volume, ns * 64, g, xs, ns, self_frac, n_h_s, Vs, hs);

@@ -137,8 +137,7 @@ void launch_dep_pack(const uint32_t* perm, uint32_t* rank, const double* xg, int
                      const R* hg, const R* Vg, const R* mg, const R* mZg, double z_max,
                      double m_max, void* p4, void* pv, hipStream_t s);
 template <class R>
-void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t ns,
-                       double self_frac, double n_h_s, R* Vs, R* hs, hipStream_t s);
+void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t ns, double self_frac, double n_h_s, R* Vs, R* hs, hipStream_t s);
 template <class R>
 void launch_dep_norm(int kernel, const DepGrid& d, const double* xs, int64_t ns, const R* hs,
                      const R* dM, const R* dMZ, const R* dE, const R* vs, R* As, void* sp,
