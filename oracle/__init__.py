@@ -49,6 +49,9 @@ def lib():
                   C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
         _lib.oracle_forward.argtypes = common + [D] * 14 + [I64]
         _lib.oracle_forward.restype = C.c_int
+        _lib.oracle_forward_passive.argtypes = (common + [C.POINTER(C.c_uint8)] + [D] * 7
+                                                + [D] * 14 + [I64])
+        _lib.oracle_forward_passive.restype = C.c_int
         _lib.oracle_jvp.argtypes = common + [D, D, D, C.c_double, C.c_double] + [D] * 7
         _lib.oracle_jvp.restype = C.c_int
     return _lib
@@ -117,8 +120,17 @@ def neighbours(x, h, box=1.0, mode=0, kind=0, lists=False):
     return [out[off[i]:off[i + 1]] for i in range(n)]
 
 
-def forward(x, v, m, u, h, params: Params, nbr_mode: int = 0) -> dict:
-    """FP64 forward. Returns a dict of numpy arrays (SoA) and the pair stats."""
+PASSIVE_KEYS = ("V", "A", "B", "gradA", "gradB", "rho", "gradv")
+
+
+def forward(x, v, m, u, h, params: Params, nbr_mode: int = 0, passive: dict = None) -> dict:
+    """FP64 forward. Returns a dict of numpy arrays (SoA) and the pair stats.
+
+    passive: optional stored state of the particles that are passive in a
+    timestep hierarchy: "mask" (True = passive) and their V, A, B, gradA,
+    gradB, rho, gradv (caller layouts, all particles; only the masked ones
+    are read). Those particles keep these values; their P and c follow
+    from rho and u; their other outputs carry no meaning."""
     x, v, m, u, h = _c(x), _c(v), _c(m), _c(u), _c(h)
     n = m.size
     o = {k: np.zeros(s) for k, s in [("h", n), ("V", n), ("rho", n), ("A", n), ("B", (3, n)),
@@ -126,10 +138,21 @@ def forward(x, v, m, u, h, params: Params, nbr_mode: int = 0) -> dict:
                                       ("P", n), ("c", n), ("accel", (3, n)), ("dudt", n),
                                       ("scale_a", n), ("scale_u", n)]}
     stats = np.zeros(6, dtype=np.int64)
-    rc = lib().oracle_forward(n, _p(x), _p(v), _p(m), _p(u), _p(h), *params.args(), nbr_mode,
-                              *[_p(o[k]) for k in ["h", "V", "rho", "A", "B", "gradA", "gradB",
-                                                   "gradv", "P", "c", "accel", "dudt",
-                                                   "scale_a", "scale_u"]], _pi(stats))
+    outs = [_p(o[k]) for k in ["h", "V", "rho", "A", "B", "gradA", "gradB", "gradv", "P", "c",
+                               "accel", "dudt", "scale_a", "scale_u"]]
+    if passive is None:
+        rc = lib().oracle_forward(n, _p(x), _p(v), _p(m), _p(u), _p(h), *params.args(),
+                                  nbr_mode, *outs, _pi(stats))
+    else:
+        mask = np.ascontiguousarray(passive["mask"], dtype=np.uint8)
+        if mask.shape != (n,):
+            raise ValueError("passive mask must have shape (n,)")
+        shapes = {"V": n, "A": n, "B": (3, n), "gradA": (3, n), "gradB": (9, n), "rho": n,
+                  "gradv": (9, n)}
+        st = [_c(passive[k], shapes[k]) for k in PASSIVE_KEYS]
+        rc = lib().oracle_forward_passive(
+            n, _p(x), _p(v), _p(m), _p(u), _p(h), *params.args(), nbr_mode,
+            mask.ctypes.data_as(C.POINTER(C.c_uint8)), *[_p(a) for a in st], *outs, _pi(stats))
     if rc:
         raise RuntimeError("oracle_forward failed: %d" % rc)
     o["pairs_gather"], o["pairs_force"], o["h_iters_max"], o["h_unconverged"], \
@@ -203,6 +226,93 @@ def kdk_step(x, v, m, u, h, prev: dict, params: Params, dt: float, lam: float,
     o["u"] = u_half + 0.5 * dt * o["dudt"]
     o["h"] = h_new
     return o
+
+
+# ------------------------------------------------- timestep hierarchy --
+# One big step dt of the hierarchical KDK integrator, App. A.4, on
+# power-of-two levels: a particle of level L is active on intervals
+# dt_a = dt / 2^L and all particles drift on the smallest interval
+# dt_min = dt / 2^Lmax. At the start of its interval a particle takes its
+# first kick and its hdot (App. A.3: Thacker plus continuity, with dt_a);
+# every substep drifts every particle, x on the piecewise-parabolic path
+# v_j = v^1/2 + a^0 (t_elapsed + (dt_min - dt_a) / 2) (FP64), h by
+# h exp(hdot dt_min / h), and updates the passive state V = (h / n_h)^3,
+# rho <- rho exp(-div v dt_min); at the end of each substep the particles
+# whose interval ends are evaluated (the others passive, with their stored
+# V, rho, corrections and grad v), kicked a second time and, unless the big
+# step is over, open their next interval. The evaluation takes each
+# particle's velocity and energy at that time under its constant a^0 and
+# du^0 (the predicted values of the single-level step, R14, for the active
+# ones). Levels stay fixed over the big step (the limiter that refines them
+# mid-step is not part of this).
+
+def hkdk_step(x, v, m, u, h, prev: dict, levels, params: Params, dt: float, lam: float,
+              nbr_mode: int = 0, trace: list = None) -> dict:
+    """One big step of the hierarchy from the synchronised state (x, v, u, h).
+
+    prev holds the evaluation at that state with h fixed (accel, dudt, V,
+    rho, A, B, gradA, gradB, gradv). levels: int per particle, >= 0.
+    Returns the synchronised x, v, u, h and each particle's latest
+    evaluation (the prev of the next big step). trace, when given, collects
+    per substep the passive mask and the x, h, V, rho the evaluation used.
+    """
+    if params.h_mode != 0:
+        raise ValueError("the time-integrated smoothing length needs h_mode = 0")
+    levels = np.asarray(levels, dtype=np.int64)
+    if levels.min() < 0:
+        raise ValueError("levels must be >= 0")
+    x, v, m, u, h = _c(x).copy(), _c(v).copy(), _c(m), _c(u).copy(), _c(h).copy()
+    lmax = int(levels.max())
+    nsub = 1 << lmax
+    dt_min = dt / nsub
+    per = np.left_shift(1, lmax - levels)  # substeps per active interval
+    dta = per * dt_min
+    st = {k: _c(prev[k]).copy() for k in ("accel", "dudt") + PASSIVE_KEYS}
+    vh = np.empty_like(v)
+    uh = np.empty_like(u)
+    hdot = np.empty_like(h)
+
+    def open_interval(sel):
+        vh[:, sel] = v[:, sel] + 0.5 * dta[sel] * st["accel"][:, sel]
+        uh[sel] = u[sel] + 0.5 * dta[sel] * st["dudt"][sel]
+        g = st["gradv"]
+        div_v = g[0, sel] + g[4, sel] + g[8, sel]
+        delta_n = params.n_h * np.cbrt(st["V"][sel]) / h[sel]
+        h_thacker = h[sel] * (1.0 - lam + lam * delta_n)
+        hdot[sel] = (h_thacker - h[sel]) / dta[sel] + h[sel] * div_v / 3.0
+
+    open_interval(np.ones(m.size, dtype=bool))
+    for j in range(nsub):
+        start = (j // per) * per  # substep that opened each particle's interval
+        elapsed = (j - start) * dt_min
+        # drift
+        v_j = vh + st["accel"] * (elapsed + 0.5 * (dt_min - dta))
+        x = np.mod(x + v_j * dt_min, params.box)
+        h = h * np.exp(hdot * dt_min / h)
+        g = st["gradv"]
+        st["V"] = (h / params.n_h) ** 3
+        st["rho"] = st["rho"] * np.exp(-(g[0] + g[4] + g[8]) * dt_min)
+        # evaluation for the particles whose interval ends now
+        j_end = j + 1
+        active = (j_end % per) == 0
+        t_rel = (j_end - start) * dt_min - 0.5 * dta  # time since the half kick's centre
+        v_p = vh + st["accel"] * t_rel
+        u_p = uh + st["dudt"] * t_rel
+        pas = dict({k: st[k] for k in PASSIVE_KEYS}, mask=~active)
+        if trace is not None:
+            trace.append({"passive": ~active, "x": x.copy(), "h": h.copy(),
+                          "V": st["V"].copy(), "rho": st["rho"].copy()})
+        o = forward(x, v_p, m, u_p, h, params, nbr_mode=nbr_mode, passive=pas)
+        # second kick of the active particles; their evaluation is stored
+        v[:, active] = vh[:, active] + 0.5 * dta[active] * o["accel"][:, active]
+        u[active] = uh[active] + 0.5 * dta[active] * o["dudt"][active]
+        for k in ("accel", "dudt") + PASSIVE_KEYS:
+            st[k][..., active] = o[k][..., active]
+        if j_end < nsub:
+            open_interval(active)
+    out = dict(st)
+    out.update(x=x, v=v, u=u, h=h)
+    return out
 
 
 # ------------------------------------------------------------- cooling --

@@ -340,11 +340,22 @@ void corrected(const T& A, const T B[3], const T dA[3], const T dB[9], const T x
   }
 }
 
+// Stored state of passive particles in a timestep hierarchy (App. A.3, A.4):
+// particles that are not updating forces this substep keep the corrections of
+// their last evaluation and carry V and rho from the passive updates; their
+// velocity gradient is the one of their last evaluation. Caller layouts.
+struct Passive {
+  const uint8_t* mask = nullptr;  // [n] 1 = passive
+  const double *V = nullptr, *A = nullptr, *B = nullptr, *dA = nullptr, *dB = nullptr,
+               *rho = nullptr, *gv = nullptr;
+  bool at(int64_t i) const { return mask && mask[i]; }
+};
+
 template <class T>
 void run_passes(const Params& P, const T& alpha, const T& beta, int64_t n,
                 const std::vector<T>& x, const std::vector<T>& v, const std::vector<double>& m,
                 const std::vector<T>& u, const std::vector<T>& h, const Lists& Lst,
-                Fields<T>& out) {
+                Fields<T>& out, const Passive& pas = Passive()) {
   const double L = P.box;
   const int K = P.kernel;
   const double C = knorm(K);
@@ -383,6 +394,8 @@ void run_passes(const Params& P, const T& alpha, const T& beta, int64_t n,
     }
     out.V[i] = m[i] / s;
   }
+  for (int64_t i = 0; i < n; ++i)
+    if (pas.at(i)) out.V[i] = T(pas.V[i]);
 
   // Moments and corrections (App. A.1, eq. RK; reproducing conditions).
 #pragma omp parallel for schedule(dynamic, 64)
@@ -472,9 +485,32 @@ void run_passes(const Params& P, const T& alpha, const T& beta, int64_t n,
     for (int k = 0; k < 9; ++k) out.dB[k * n + i] = dB[k];
   }
 
+  for (int64_t i = 0; i < n; ++i)
+    if (pas.at(i)) {
+      out.singular[i] = 0;
+      out.A[i] = T(pas.A[i]);
+      for (int a = 0; a < 3; ++a) {
+        out.B[a * n + i] = T(pas.B[a * n + i]);
+        out.dA[a * n + i] = T(pas.dA[a * n + i]);
+      }
+      for (int k = 0; k < 9; ++k) out.dB[k * n + i] = T(pas.dB[k * n + i]);
+    }
+
   // Density (Sec. 2.5.1, eq. rhow) and velocity gradient (App. A.1, eq. gradv).
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
+    if (pas.at(i)) {
+      // passive: the carried density and the gradient of the last evaluation
+      out.rho[i] = T(pas.rho[i]);
+      for (int k = 0; k < 9; ++k) out.gv[k * n + i] = T(pas.gv[k * n + i]);
+      out.P[i] = (P.gamma - 1.0) * out.rho[i] * u[i];
+      out.c[i] = sqrt(P.gamma * (P.gamma - 1.0) * u[i]);
+      if (P.dt_relax > 0.0) {
+        double div = pas.gv[i] + pas.gv[4 * n + i] + pas.gv[8 * n + i];
+        out.relaxed[i] = std::exp(std::fabs(div) * P.dt_relax) > 8.0 ? 1 : 0;
+      }
+      continue;
+    }
     T Ai = out.A[i], Bi[3], dAi[3], dBi[9];
     for (int a = 0; a < 3; ++a) {
       Bi[a] = out.B[a * n + i];
@@ -696,6 +732,53 @@ Params make_params(double box, double gamma, double alpha, double beta, double e
   return P;
 }
 
+int forward_impl(int64_t n, const double* x, const double* v, const double* m, const double* u,
+                 const double* h_in, double box, double gamma, double alpha, double beta,
+                 double eps2, double n_h, double dt_relax, int kernel, int h_mode, int nbr_mode,
+                 double* h, double* V, double* rho, double* A, double* B, double* gradA,
+                 double* gradB, double* gradv, double* Pr, double* cs, double* accel,
+                 double* dudt, double* scale_a, double* scale_u, int64_t* stats,
+                 const Passive& pas) {
+  Params P = make_params(box, gamma, alpha, beta, eps2, n_h, dt_relax, kernel, h_mode);
+  if (n <= 0 || !(box > 0.0)) return -1;
+  Setup S;
+  int rc = prepare(P, n, x, m, h_in, nbr_mode, 1e-14, S);
+  if (rc) return rc;
+  std::vector<double> X(S.X), Vv(v, v + 3 * n), U(u, u + n), M(m, m + n);
+  Fields<double> f;
+  run_passes<double>(P, P.alpha, P.beta, n, X, Vv, M, U, S.h, S.lists, f, pas);
+  std::memcpy(h, f.h.data(), n * 8);
+  std::memcpy(V, f.V.data(), n * 8);
+  std::memcpy(rho, f.rho.data(), n * 8);
+  std::memcpy(A, f.A.data(), n * 8);
+  std::memcpy(B, f.B.data(), 3 * n * 8);
+  std::memcpy(gradA, f.dA.data(), 3 * n * 8);
+  std::memcpy(gradB, f.dB.data(), 9 * n * 8);
+  std::memcpy(gradv, f.gv.data(), 9 * n * 8);
+  std::memcpy(Pr, f.P.data(), n * 8);
+  std::memcpy(cs, f.c.data(), n * 8);
+  std::memcpy(accel, f.acc.data(), 3 * n * 8);
+  std::memcpy(dudt, f.dudt.data(), n * 8);
+  std::memcpy(scale_a, f.sa.data(), n * 8);
+  std::memcpy(scale_u, f.su.data(), n * 8);
+  int64_t ng = 0, ns = 0, itmax = 0, unc = 0, sing = 0, rel = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    ng += (int64_t)S.lists.gather[i].size() - 1;
+    ns += (int64_t)S.lists.sym[i].size();
+    itmax = std::max<int64_t>(itmax, S.iters[i]);
+    unc += S.conv[i] ? 0 : 1;
+    sing += f.singular[i];
+    rel += f.relaxed[i];
+  }
+  stats[0] = ng;
+  stats[1] = ns;
+  stats[2] = itmax;
+  stats[3] = unc;
+  stats[4] = sing;
+  stats[5] = rel;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -748,44 +831,37 @@ int oracle_forward(int64_t n, const double* x, const double* v, const double* m,
                    double* h, double* V, double* rho, double* A, double* B, double* gradA,
                    double* gradB, double* gradv, double* Pr, double* cs, double* accel,
                    double* dudt, double* scale_a, double* scale_u, int64_t* stats) {
-  Params P = make_params(box, gamma, alpha, beta, eps2, n_h, dt_relax, kernel, h_mode);
-  if (n <= 0 || !(box > 0.0)) return -1;
-  Setup S;
-  int rc = prepare(P, n, x, m, h_in, nbr_mode, 1e-14, S);
-  if (rc) return rc;
-  std::vector<double> X(S.X), Vv(v, v + 3 * n), U(u, u + n), M(m, m + n);
-  Fields<double> f;
-  run_passes<double>(P, P.alpha, P.beta, n, X, Vv, M, U, S.h, S.lists, f);
-  std::memcpy(h, f.h.data(), n * 8);
-  std::memcpy(V, f.V.data(), n * 8);
-  std::memcpy(rho, f.rho.data(), n * 8);
-  std::memcpy(A, f.A.data(), n * 8);
-  std::memcpy(B, f.B.data(), 3 * n * 8);
-  std::memcpy(gradA, f.dA.data(), 3 * n * 8);
-  std::memcpy(gradB, f.dB.data(), 9 * n * 8);
-  std::memcpy(gradv, f.gv.data(), 9 * n * 8);
-  std::memcpy(Pr, f.P.data(), n * 8);
-  std::memcpy(cs, f.c.data(), n * 8);
-  std::memcpy(accel, f.acc.data(), 3 * n * 8);
-  std::memcpy(dudt, f.dudt.data(), n * 8);
-  std::memcpy(scale_a, f.sa.data(), n * 8);
-  std::memcpy(scale_u, f.su.data(), n * 8);
-  int64_t ng = 0, ns = 0, itmax = 0, unc = 0, sing = 0, rel = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    ng += (int64_t)S.lists.gather[i].size() - 1;
-    ns += (int64_t)S.lists.sym[i].size();
-    itmax = std::max<int64_t>(itmax, S.iters[i]);
-    unc += S.conv[i] ? 0 : 1;
-    sing += f.singular[i];
-    rel += f.relaxed[i];
-  }
-  stats[0] = ng;
-  stats[1] = ns;
-  stats[2] = itmax;
-  stats[3] = unc;
-  stats[4] = sing;
-  stats[5] = rel;
-  return 0;
+  return forward_impl(n, x, v, m, u, h_in, box, gamma, alpha, beta, eps2, n_h, dt_relax, kernel,
+                      h_mode, nbr_mode, h, V, rho, A, B, gradA, gradB, gradv, Pr, cs, accel, dudt,
+                      scale_a, scale_u, stats, Passive());
+}
+
+// The forward with passive particles (mask != 0) taking their V, A, B,
+// grad A, grad B, rho and grad v from the given arrays (caller layouts);
+// their P and c follow from that rho and their u. Outputs of passive
+// particles other than those are computed but carry no meaning.
+int oracle_forward_passive(int64_t n, const double* x, const double* v, const double* m,
+                           const double* u, const double* h_in, double box, double gamma,
+                           double alpha, double beta, double eps2, double n_h, double dt_relax,
+                           int kernel, int h_mode, int nbr_mode, const uint8_t* mask,
+                           const double* pV, const double* pA, const double* pB,
+                           const double* pgradA, const double* pgradB, const double* prho,
+                           const double* pgradv, double* h, double* V, double* rho, double* A,
+                           double* B, double* gradA, double* gradB, double* gradv, double* Pr,
+                           double* cs, double* accel, double* dudt, double* scale_a,
+                           double* scale_u, int64_t* stats) {
+  Passive pas;
+  pas.mask = mask;
+  pas.V = pV;
+  pas.A = pA;
+  pas.B = pB;
+  pas.dA = pgradA;
+  pas.dB = pgradB;
+  pas.rho = prho;
+  pas.gv = pgradv;
+  return forward_impl(n, x, v, m, u, h_in, box, gamma, alpha, beta, eps2, n_h, dt_relax, kernel,
+                      h_mode, nbr_mode, h, V, rho, A, B, gradA, gradB, gradv, Pr, cs, accel, dudt,
+                      scale_a, scale_u, stats, pas);
 }
 
 // Forward-mode derivative (JVP) along one direction (dx, dv, du, dalpha,
