@@ -203,6 +203,41 @@ crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
                         void *h, void *V, void *rho, void *A, void *B, void *gradA, void *gradB,
                         void *gradv, double *accel, double *dudt, crk_stats *stats);
 
+/* One big step dt of the hierarchical kick-drift-kick integrator on
+ * power-of-two timestep levels (App. A.4; h, V and rho as in App. A.3).
+ * Particle i of level L_i (levels [n] int, device, 0 <= L_i <= 30) is active
+ * on intervals dt_a = dt / 2^L_i; all particles drift on dt_min =
+ * dt / 2^Lmax, Lmax the largest level. Per particle and interval:
+ *   open:  v^1/2 = v + a^0 dt_a/2, u^1/2 = u + (du/dt)^0 dt_a/2,
+ *          hdot = (h^T - h)/dt_a + h div(v)/3 from its latest evaluation;
+ *   every substep, every particle: x <- x + v_j dt_min in double on the
+ *          parabola v_j = v^1/2 + a^0 (t_elapsed + (dt_min - dt_a)/2),
+ *          h <- h exp(hdot dt_min / h), V <- (h/n_h)^3,
+ *          rho <- rho exp(-div(v) dt_min);
+ *   at each substep end, one forward at the predicted velocities and
+ *          energies v^1/2 + a^0 t, u^1/2 + (du/dt)^0 t (t from the centre of
+ *          the interval) in which the particles whose interval does not end
+ *          are passive: they skip the volume, moment, density and force sums
+ *          and keep V, rho, grad v and A, B, grad A, grad B from these arrays;
+ *   close (interval end): v = v^1/2 + a^1 dt_a/2, u = u^1/2 + (du/dt)^1 dt_a/2,
+ *          and the particle's evaluation (accel, dudt, V, rho, A, B, gradA,
+ *          gradB, gradv) is stored in the arrays.
+ * Levels stay fixed during the call; every interval ends at dt, so the state
+ * returned is synchronised. Arrays as in crk_kdk_step, all in/out: on entry
+ * the evaluation at the current state (every particle), on return each
+ * particle's latest evaluation (all at the new state). With every level 0
+ * this is crk_kdk_step up to rounding. The context needs h_mode 0; its
+ * workspace holds the half-kicked state and hdot. After a call with Lmax > 0
+ * crk_backward is not available (the last evaluation had passive
+ * particles). Errors: CRK_EINVAL for h_mode != 0, a bad dt or lambda, levels
+ * outside [0, 30], null arrays or n above 2^25 - 1; otherwise those of
+ * crk_forward. n = 0 is a no-op. */
+crk_status crk_hkdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
+                         double thacker_lambda, const int *levels, double *x, void *v,
+                         const void *m, void *u, void *h, void *V, void *rho, void *A, void *B,
+                         void *gradA, void *gradB, void *gradv, double *accel, double *dudt,
+                         crk_stats *stats);
+
 /* Tabulated source function of the exact-integration cooling (Sec. 2.2,
  * exact integration): lam[k] at u_k = 10^(log10_u0 + k dex), k = 0 .. K-1,
  * interpolated by piecewise power laws between nodes of the same sign. The

@@ -310,7 +310,9 @@ def hkdk_step(x, v, m, u, h, prev: dict, levels, params: Params, dt: float, lam:
             st[k][..., active] = o[k][..., active]
         if j_end < nsub:
             open_interval(active)
-    out = dict(st)
+    # every interval ends at dt: the last evaluation had every particle active
+    out = dict(o)
+    out.update(st)
     out.update(x=x, v=v, u=u, h=h)
     return out
 

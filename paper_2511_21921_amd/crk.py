@@ -49,7 +49,7 @@ class crk_stats(C.Structure):
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
            "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
-           "crk_pass_times", "crk_kdk_step", "crk_cooling_table", "crk_cool",
+           "crk_pass_times", "crk_kdk_step", "crk_hkdk_step", "crk_cooling_table", "crk_cool",
            "crk_deposit"]
 
 _lib = None
@@ -83,6 +83,9 @@ def lib():
         L.crk_kdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 14 +
                                    [C.POINTER(crk_stats)])
         L.crk_kdk_step.restype = C.c_int
+        L.crk_hkdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 15 +
+                                    [C.POINTER(crk_stats)])
+        L.crk_hkdk_step.restype = C.c_int
         L.crk_cooling_table.argtypes = [P, P, C.c_int, C.c_double, C.c_double,
                                         C.POINTER(C.c_double)]
         L.crk_cooling_table.restype = C.c_int
@@ -252,6 +255,38 @@ class Context:
                                 _ptr(out["gradA"]), _ptr(out["gradB"]), _ptr(out["gradv"]),
                                 _ptr(out["accel"]), _ptr(out["dudt"]),
                                 C.byref(st) if stats else None)
+        self._raise(rc)
+        if stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def hkdk_step(self, x: torch.Tensor, v: torch.Tensor, m: torch.Tensor, u: torch.Tensor,
+                  out: dict, levels: torch.Tensor, dt: float, lam: float = 0.5,
+                  stats: bool = False) -> dict:
+        """One big step of the power-of-two timestep hierarchy (crk_hkdk_step):
+        levels is an int32 device tensor [n]; x, v, u and out are advanced in
+        place as in kdk_step, out holding each particle's latest evaluation."""
+        n = int(m.shape[0])
+        R = self.params.real
+        _check(x, torch.float64, (3, n), "x")
+        _check(v, R, (3, n), "v")
+        _check(levels, torch.int32, (n,), "levels")
+        for t, name in [(m, "m"), (u, "u"), (out["h"], "h"), (out["V"], "V"),
+                        (out["rho"], "rho"), (out["A"], "A")]:
+            _check(t, R, (n,), name)
+        for k, rows in [("B", 3), ("gradA", 3), ("gradB", 9), ("gradv", 9)]:
+            _check(out[k], R, (rows, n), k)
+        _check(out["accel"], torch.float64, (3, n), "accel")
+        _check(out["dudt"], torch.float64, (n,), "dudt")
+        st = crk_stats()
+        stream = C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+        self.generation += 1
+        rc = lib().crk_hkdk_step(self._h, stream, n, float(dt), float(lam), _ptr(levels), _ptr(x),
+                                 _ptr(v), _ptr(m), _ptr(u), _ptr(out["h"]), _ptr(out["V"]),
+                                 _ptr(out["rho"]), _ptr(out["A"]), _ptr(out["B"]),
+                                 _ptr(out["gradA"]), _ptr(out["gradB"]), _ptr(out["gradv"]),
+                                 _ptr(out["accel"]), _ptr(out["dudt"]),
+                                 C.byref(st) if stats else None)
         self._raise(rc)
         if stats:
             out["stats"] = st.as_dict()

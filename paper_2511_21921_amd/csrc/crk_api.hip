@@ -63,6 +63,16 @@ struct crk_ctx {
   Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
   // time step: the velocity and energy predicted for the end-of-step evaluation
   Buf vpred, upred;
+  // timestep hierarchy: half-kicked velocity and energy, hdot, and the
+  // evaluation of the substep (its accel and du/dt before the close)
+  Buf hl_vh, hl_uh, hl_hdot, hl_acc, hl_du;
+  // levels and stored state seen by the passes during a hierarchical
+  // substep (null levels: every particle active)
+  const int* hl_levels = nullptr;
+  int hl_lmax = 0;
+  long long hl_jend = 0;
+  const void *hl_V = nullptr, *hl_rho = nullptr, *hl_gv = nullptr, *hl_A = nullptr,
+             *hl_B = nullptr, *hl_gA = nullptr, *hl_gB = nullptr;
   // cooling table: lam at the nodes, per-bin slope, prefix integrals within
   // each run of same-sign bins, each bin's run (int2), per-bin integrals
   Buf cool_lam, cool_slope, cool_G, cool_run, cool_binint;
@@ -253,6 +263,16 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.dt_relax = c->p.dt_relax;
   S.rtol = c->p.h_rtol;
   S.max_iter = c->p.h_max_iter;
+  S.levels = c->hl_levels;
+  S.lev_max = c->hl_lmax;
+  S.jend = c->hl_jend;
+  S.pV = (const R*)c->hl_V;
+  S.prho = (const R*)c->hl_rho;
+  S.pgv = (const R*)c->hl_gv;
+  S.pA = (const R*)c->hl_A;
+  S.pB = (const R*)c->hl_B;
+  S.pgA = (const R*)c->hl_gA;
+  S.pgB = (const R*)c->hl_gB;
   return S;
 }
 
@@ -917,6 +937,83 @@ crk_status step_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double l
   return st;
 }
 
+// One big step of the power-of-two timestep hierarchy (App. A.4; App. A.3
+// for h, V and rho): open every interval, then per substep drift all
+// particles, predict their velocity and energy, evaluate with the particles
+// whose interval does not end passive (they keep their stored state), close
+// the active ones and open their next interval.
+template <class R>
+crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double lam,
+                      const int* levels, double* x, R* v, const R* m, R* u, R* h, R* V, R* rho,
+                      void* A, void* B, void* gradA, void* gradB, R* gradv, double* accel,
+                      double* dudt, crk_stats* stats) {
+  const crk_params& P = ctx->p;
+  const size_t N = (size_t)n;
+  CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
+  unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
+  CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
+  launch_level_range(levels, n, dcnt, s);
+  CRK_HIP(hipGetLastError(), "level launch");
+  CRK_HIP(read_counters(ctx, s), "levels");
+  if (ctx->host_cnt[CNT_BAD_INPUT]) return fail(ctx, CRK_EINVAL, "levels must lie in [0, 30]");
+  const int lmax = (int)ctx->host_cnt[CNT_H_ITER_MAX];
+  const int64_t nsub = (int64_t)1 << lmax;
+  const double dt_min = dt / (double)nsub;
+  CRK_HIP(ensure(ctx->vpred, sizeof(R) * 3 * N), "step workspace");
+  CRK_HIP(ensure(ctx->upred, sizeof(R) * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_vh, sizeof(R) * 3 * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_uh, sizeof(R) * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_hdot, 8 * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_acc, 8 * 3 * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_du, 8 * N), "step workspace");
+  R* vp = (R*)ctx->vpred.p;
+  R* up = (R*)ctx->upred.p;
+  R* vh = (R*)ctx->hl_vh.p;
+  R* uh = (R*)ctx->hl_uh.p;
+  double* hdot = (double*)ctx->hl_hdot.p;
+  double* acc1 = (double*)ctx->hl_acc.p;
+  double* du1 = (double*)ctx->hl_du.p;
+  CRK_HIP(tbegin(ctx, P_STEP, s), "event");
+  launch_hier_open<R>(n, levels, lmax, 0, dt_min, lam, P.n_h, v, u, h, V, gradv, accel, dudt,
+                      vh, uh, hdot, s);
+  CRK_HIP(tend(ctx, P_STEP, s), "event");
+  crk_status result = CRK_OK;
+  for (int64_t j = 0; j < nsub; ++j) {
+    const int64_t jend = j + 1;
+    CRK_HIP(tbegin(ctx, P_STEP, s), "event");
+    launch_hier_drift<R>(n, levels, lmax, j, dt_min, P.n_h, P.box, x, vh, accel, h, hdot, V, rho,
+                         gradv, s);
+    launch_hier_predict<R>(n, levels, lmax, jend, dt_min, vh, uh, accel, dudt, vp, up, s);
+    CRK_HIP(tend(ctx, P_STEP, s), "event");
+    CRK_HIP(hipGetLastError(), "hierarchy launch");
+    ctx->hl_levels = levels;
+    ctx->hl_lmax = lmax;
+    ctx->hl_jend = jend;
+    ctx->hl_V = V;
+    ctx->hl_rho = rho;
+    ctx->hl_gv = gradv;
+    ctx->hl_A = A;
+    ctx->hl_B = B;
+    ctx->hl_gA = gradA;
+    ctx->hl_gB = gradB;
+    crk_status st = forward_impl<R>(ctx, s, n, x, vp, m, up, h, V, rho, A, B, gradA, gradB,
+                                    gradv, acc1, du1, stats);
+    ctx->hl_levels = nullptr;
+    if (st != CRK_OK && st != CRK_ENOTCONV && st != CRK_ENONFINITE) return st;
+    if (st != CRK_OK) result = st;
+    CRK_HIP(tbegin(ctx, P_STEP, s), "event");
+    launch_hier_close<R>(n, levels, lmax, jend, dt_min, v, u, vh, uh, acc1, du1, accel, dudt, s);
+    if (jend < nsub)
+      launch_hier_open<R>(n, levels, lmax, jend, dt_min, lam, P.n_h, v, u, h, V, gradv, accel,
+                          dudt, vh, uh, hdot, s);
+    CRK_HIP(tend(ctx, P_STEP, s), "event");
+    CRK_HIP(hipGetLastError(), "hierarchy launch");
+  }
+  // the last evaluation had passive particles (unless lmax = 0): no adjoint
+  if (lmax > 0) ctx->n_last = -1;
+  return result;
+}
+
 // Subgrid deposition (App. A.2 eq. (Vsg); eqs. (windmetal), (Anorm),
 // (starmetal), (stellarmom), (AGNE)): folds the deposition counters (max
 // slots for the *_BITS counters, sums otherwise) after a read-back.
@@ -1117,6 +1214,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
+                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du,
                 &c->cool_lam, &c->cool_slope, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,
@@ -1232,6 +1330,38 @@ crk_status crk_kdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
   return step_impl<float>(ctx, s, n, dt, thacker_lambda, x, (float*)v, (const float*)m, (float*)u,
                           (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB, (float*)gradv,
                           accel, dudt, stats);
+}
+
+crk_status crk_hkdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
+                         double thacker_lambda, const int* levels, double* x, void* v,
+                         const void* m, void* u, void* h, void* V, void* rho, void* A, void* B,
+                         void* gradA, void* gradB, void* gradv, double* accel, double* dudt,
+                         crk_stats* stats) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (ctx->p.h_mode != 0)
+    return fail(ctx, CRK_EINVAL, "the time step integrates h: the context needs h_mode 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, CRK_EINVAL, "dt must be finite and > 0");
+  if (!(thacker_lambda >= 0.0 && thacker_lambda <= 1.0))
+    return fail(ctx, CRK_EINVAL, "thacker_lambda must lie in [0, 1]");
+  if (n < 0) return fail(ctx, CRK_EINVAL, "n must be >= 0");
+  if (n == 0) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    ctx->n_last = 0;
+    return CRK_OK;
+  }
+  if (n > (1ll << 25) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^25 - 1 particles");
+  if (!levels || !x || !v || !m || !u || !h || !V || !rho || !A || !B || !gradA || !gradB ||
+      !gradv || !accel || !dudt)
+    return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (ctx->p.precision == CRK_FP64)
+    return hstep_impl<double>(ctx, s, n, dt, thacker_lambda, levels, x, (double*)v,
+                              (const double*)m, (double*)u, (double*)h, (double*)V, (double*)rho,
+                              A, B, gradA, gradB, (double*)gradv, accel, dudt, stats);
+  return hstep_impl<float>(ctx, s, n, dt, thacker_lambda, levels, x, (float*)v, (const float*)m,
+                           (float*)u, (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB,
+                           (float*)gradv, accel, dudt, stats);
 }
 
 crk_status crk_cooling_table(crk_ctx* ctx, void* hip_stream, int K, double log10_u0, double dex,

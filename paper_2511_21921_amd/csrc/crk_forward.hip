@@ -500,6 +500,10 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
   if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
+  if (is_passive(S, S.perm[s])) {  // V comes from the stored state (k_pack)
+    if (S.todo) S.todo[s] = 0;
+    return;
+  }
   const R h = S.hbuf[s];
   int scap;
   const int64_t base = scratch_base(S, s, scap);
@@ -514,11 +518,12 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
                                                  R* __restrict__ V_out) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
-  const R h = S.hbuf[s], V = S.Vbuf[s];
+  const uint32_t p = S.perm[s];
+  const bool pas = is_passive(S, p);
+  const R h = S.hbuf[s], V = pas ? S.pV[p] : S.Vbuf[s];
   S.pos4[s].w = R(1) / h;
   S.vel4[s].w = V;
-  if (!h_out) return;  // caller's h is still an input (a speculative forward)
-  const uint32_t p = S.perm[s];
+  if (!h_out || pas) return;  // an input still (a speculative forward), or stored
   h_out[p] = h;
   V_out[p] = V;
 }
@@ -770,7 +775,21 @@ template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
   const int64_t s = particle_id();
   unsigned long long sing = 0;
-  if (s < S.n) {
+  if (s < S.n && is_passive(S, S.perm[s])) {
+    // the corrections of the particle's last evaluation
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    Corr64 c;
+    c.A = (double)S.pA[p];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      c.B[t] = (double)S.pB[t * n + p];
+      c.dA[t] = (double)S.pgA[t * n + p];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c.dB[t] = (double)S.pgB[t * n + p];
+    store_kc(S, s, c);
+  } else if (s < S.n) {
     Moments<R> M;
     accumulate_moments<R, K>(S, s, M);
     Mom64 D;
@@ -855,7 +874,36 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
                                                     R* __restrict__ gradv_out) {
   const int64_t s = particle_id();
   unsigned long long nrel = 0;
-  if (s < S.n) {
+  if (s < S.n && is_passive(S, S.perm[s])) {
+    // the carried density and the gradient of the last evaluation; P and c
+    // from that density and the particle's u
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    const R rho = S.prho[p];
+    R gv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gv[t] = S.pgv[t * n + p];
+    const R u = S.uu[s];
+    const R gam = R(S.gamma);
+    R relaxed = R(0);
+    if (S.dt_relax > 0.0) {
+      const double div = (double)gv[0] + (double)gv[4] + (double)gv[8];
+      if (fabs(div) * S.dt_relax > 2.0794415416798357) relaxed = R(1);
+    }
+    R4<R> st;
+    st.x = rho;
+    st.y = (gam - R(1)) * rho * u;
+    st.z = Sc<R>::sqrt(gam * (gam - R(1)) * u);
+    st.w = R(0);
+    S.st4[s] = st;
+    R4<R> g0, g1, g2;
+    g0.x = gv[0]; g0.y = gv[1]; g0.z = gv[2]; g0.w = gv[3];
+    g1.x = gv[4]; g1.y = gv[5]; g1.z = gv[6]; g1.w = gv[7];
+    g2.x = gv[8]; g2.y = relaxed; g2.z = R(0); g2.w = R(0);
+    S.gv4[3 * s] = g0;
+    S.gv4[3 * s + 1] = g1;
+    S.gv4[3 * s + 2] = g2;
+  } else if (s < S.n) {
     const R4<R> pi = S.pos4[s];
     const R4<R> vi = S.vel4[s];
     const R hinv = pi.w;
@@ -977,7 +1025,8 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;  // at 3 waves per SIMD this beats 4 waves with the chunk in LDS
   const int ng = nb.ng, ns = nb.ns;
-  const int total = ng + ns;
+  // passive particles keep their acceleration: nothing to sum
+  const int total = is_passive(S, S.perm[s]) ? 0 : ng + ns;
   for (int t = 0; t < total; ++t) {
     const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;

@@ -116,6 +116,26 @@ template <class R>
 void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, const double* dudt,
                        hipStream_t s);
 
+// timestep hierarchy (caller order, elementwise)
+template <class R>
+void launch_hier_open(int64_t n, const int* levels, int lmax, int64_t jend, double dt_min,
+                      double lam, double n_h, const R* v, const R* u, const R* h, const R* V,
+                      const R* gradv, const double* accel, const double* dudt, R* vh, R* uh,
+                      double* hdot, hipStream_t s);
+template <class R>
+void launch_hier_drift(int64_t n, const int* levels, int lmax, int64_t j, double dt_min,
+                       double n_h, double box, double* x, const R* vh, const double* accel, R* h,
+                       const double* hdot, R* V, R* rho, const R* gradv, hipStream_t s);
+template <class R>
+void launch_hier_predict(int64_t n, const int* levels, int lmax, int64_t jend, double dt_min,
+                         const R* vh, const R* uh, const double* accel, const double* dudt, R* vp,
+                         R* up, hipStream_t s);
+template <class R>
+void launch_hier_close(int64_t n, const int* levels, int lmax, int64_t jend, double dt_min, R* v,
+                       R* u, const R* vh, const R* uh, const double* acc1, const double* du1,
+                       double* accel, double* dudt, hipStream_t s);
+void launch_level_range(const int* levels, int64_t n, unsigned long long* cnt, hipStream_t s);
+
 // subgrid deposition: the gas grid, the source passes, the pair list and
 // the per-gas sums (caller order)
 void launch_point_keys(const double* x, int64_t n, double box, int G, uint32_t* keys,

@@ -106,7 +106,30 @@ struct State {
   // parameters
   double n_h3, gamma, alpha, beta, eps2, dt_relax, rtol;
   int max_iter;
+  // timestep hierarchy (App. A.3, A.4; levels null: every particle active).
+  // A particle of level L is passive at the end of substep jend unless
+  // 2^(lev_max - L) divides jend. Passive particles skip the volume, moment,
+  // density and force sums and take V, rho, grad v and the corrections A, B,
+  // grad A, grad B from these caller-order arrays (their state of the last
+  // evaluation, V and rho updated while passive).
+  const int* levels;
+  int lev_max;
+  long long jend;
+  const R* pV;
+  const R* prho;
+  const R* pgv;
+  const R* pA;
+  const R* pB;
+  const R* pgA;
+  const R* pgB;
 };
+
+template <class R>
+__device__ inline bool is_passive(const State<R>& S, uint32_t p) {
+  if (!S.levels) return false;
+  const long long per = 1ll << (S.lev_max - S.levels[p]);
+  return (S.jend & (per - 1)) != 0;
+}
 
 __device__ inline int wrap_cell(int c, int G) { return c < 0 ? c + G : (c >= G ? c - G : c); }
 

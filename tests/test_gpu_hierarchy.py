@@ -1,0 +1,140 @@
+"""The hierarchical KDK step on the GPU (crk_hkdk_step) against the oracle's
+(App. A.4 power-of-two levels; App. A.3 passive h, V and rho).
+
+Two big steps from the same state on both sides, levels 0, 1 and 2 mixed
+(four substeps per big step, passive particles in every evaluation but the
+last), compared after each big step: the synchronised state (x, v, u, h) and
+the last evaluation (every particle active there), on the set and step size of
+the single-level step's test. Bounds: FP64 1e-11, the single evaluation's
+(measured ~1e-14); FP32 the forward's single-evaluation bounds and 1e-5 on
+the state (four substeps of FP32 roundings of v^1/2, u^1/2, h and of the
+passive V and rho; measured <= 2.5e-6). A wrong passive state shows at
+1e-3 and above. Also:
+all levels 0 is crk_kdk_step and one level L everywhere is 2^L single-level
+steps of dt / 2^L (up to the rounding of the two h-update forms), in FP64
+and FP32, and the argument errors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2511_21921_amd import FP32, FP64, Context, CrkError
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+from tests import _gpu  # noqa: E402
+from tests.test_gpu_forward import FP32_BOUNDS, FP64_BOUNDS  # noqa: E402
+
+STATE_BOUND = {FP64: 1e-11, FP32: 1e-5}
+
+
+def _start(n, seed):
+    ps = synth.random_small(n, seed, mass_spread=0.1)
+    ps.h = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps))["h"]
+    ps.h_mode = 0
+    return ps
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _state_errors(x, v, u, out, o):
+    dx = np.abs(_np(x) - o["x"])
+    dx = np.minimum(dx, 1.0 - dx)  # periodic
+    return {"x": dx.max(), "v": np.abs(_np(v) - o["v"]).max() / np.abs(o["v"]).max(),
+            "u": np.max(np.abs(_np(u) / o["u"] - 1)),
+            "h": np.max(np.abs(_np(out["h"]) / o["h"] - 1))}
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_two_big_steps_match_the_oracle(precision):
+    ps = _start(3000, 301)
+    print("case random3000 levels 0-2 precision=%d" % precision, flush=True)
+    # the single-level step's regime (its test's set and step): no particle's
+    # u changes by more than ~2 % per step, so FP32 force errors (~1e-5 of
+    # sum |F_ij| / m) are not amplified by near-vanishing energies
+    dt, lam = 2e-4, 0.5
+    lev = np.random.default_rng(312).integers(0, 3, ps.n)
+    lev[0] = 2
+    p = oracle.params_for(ps)
+    ctx = Context(_gpu.params_for(ps, precision))
+    x, v, m, u, h = _gpu.to_dev(ps, precision)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    ox, ov, ou, oh = ps.x.copy(), ps.v.copy(), ps.u.copy(), ps.h.copy()
+    prev = oracle.forward(ox, ov, ps.m, ou, oh, p)
+    bounds = FP64_BOUNDS if precision == FP64 else FP32_BOUNDS
+    for it in range(2):
+        out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam, stats=True)
+        torch.cuda.synchronize()
+        o = oracle.hkdk_step(ox, ov, ps.m, ou, oh, prev, lev, p, dt, lam)
+        ox, ov, ou, oh, prev = o["x"], o["v"], o["u"], o["h"], o
+        st = _state_errors(x, v, u, out, o)
+        g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+        e = _gpu.errors(g, o, o["h"])
+        print("big step", it, {k: "%.2e" % val for k, val in st.items()},
+              {k: "%.2e" % val for k, val in e.items()}, flush=True)
+        for k, val in st.items():
+            assert val <= STATE_BOUND[precision], (it, k, val)
+        for k, b in bounds.items():
+            assert e[k] <= b, (it, k, e[k], b)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_one_level_everywhere_is_repeated_single_level_steps(precision):
+    ps = _start(2000, 313)
+    print("case random2000 uniform levels precision=%d" % precision, flush=True)
+    dt, lam = 4e-4, 0.5
+    tol = 1e-11 if precision == FP64 else 1e-6
+    for L in (0, 2):
+        runs = []
+        for hier in (True, False):
+            ctx = Context(_gpu.params_for(ps, precision))
+            x, v, m, u, h = _gpu.to_dev(ps, precision)
+            out = ctx.forward(x, v, m, u, h)
+            if hier:
+                levels = torch.full((ps.n,), L, dtype=torch.int32, device=x.device)
+                out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam)
+            else:
+                for _ in range(1 << L):
+                    out = ctx.kdk_step(x, v, m, u, out, dt / (1 << L), lam)
+            torch.cuda.synchronize()
+            runs.append({"x": _np(x), "v": _np(v), "u": _np(u), "h": _np(out["h"]),
+                         "accel": _np(out["accel"]), "rho": _np(out["rho"])})
+        a, b = runs
+        dx = np.abs(a["x"] - b["x"])
+        assert np.minimum(dx, 1 - dx).max() < tol * 1e-2, L
+        for k in ("v", "u", "h", "accel", "rho"):
+            err = np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()
+            print("  L=%d %s %.2e" % (L, k, err), flush=True)
+            assert err < tol, (L, k, err)
+
+
+def test_hierarchy_errors():
+    ps = _start(500, 314)
+    ctx = Context(_gpu.params_for(ps, FP64))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    out = ctx.forward(x, v, m, u, h)
+    bad = torch.full((ps.n,), 31, dtype=torch.int32, device=x.device)
+    with pytest.raises(CrkError):
+        ctx.hkdk_step(x, v, m, u, out, bad, 1e-4)
+    bad[:] = 0
+    bad[7] = -1
+    with pytest.raises(CrkError):
+        ctx.hkdk_step(x, v, m, u, out, bad, 1e-4)
+    lev = torch.zeros(ps.n, dtype=torch.int32, device=x.device)
+    with pytest.raises(CrkError):
+        ctx.hkdk_step(x, v, m, u, out, lev, -1.0)
+    lev[3] = 1
+    ctx.hkdk_step(x, v, m, u, out, lev, 1e-4)
+    torch.cuda.synchronize()
+    # the last evaluation had passive particles: no adjoint of it
+    with pytest.raises(CrkError):
+        ctx.backward(torch.zeros(3, ps.n, dtype=torch.float64, device=x.device),
+                     torch.zeros(ps.n, dtype=torch.float64, device=x.device))
