@@ -163,6 +163,56 @@ def run_kdk(ps, steps, warmup, dt):
     return (t1 - t0) * 1e3 / steps, st, passes
 
 
+def run_hkdk(ps, steps, warmup, dt):
+    """One big step of the timestep hierarchy (crk_hkdk_step, FP32) from ps with
+    h fixed at its solved value; levels from the sound speed, level =
+    clip(ceil(log2(c / median c)), 0, 3) (the hot core on level 3: eight
+    substeps). Also times the same span as eight single-level steps of dt/8.
+    Returns ms per big step, ms per eight single-level steps, the level counts."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2511_21921_amd import FP32, Context, Params
+    dev = torch.device("cuda:0")
+    t = lambda a, dtype=torch.float32: torch.tensor(np.ascontiguousarray(a), dtype=dtype,
+                                                    device=dev)
+    p1 = Params(box=ps.box, n_h=ps.n_h, h_mode=1, precision=FP32)
+    c1 = Context(p1)
+    o1 = c1.forward(t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u), t(ps.h))
+    h0 = o1["h"].clone()
+    c1.close()
+    gam = p1.gamma
+    c = np.sqrt(gam * (gam - 1.0) * ps.u)
+    lev = np.clip(np.ceil(np.log2(c / np.median(c))), 0, 3).astype(np.int32)
+    levels = t(lev, torch.int32)
+    p = dataclasses.replace(p1, h_mode=0)
+    res = []
+    for hier in (True, False):
+        ctx = Context(p)
+        x, v, m, u = t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u)
+        ctx.reserve(ps.n)
+        out = ctx.forward(x, v, m, u, h0.clone())
+
+        def one():
+            if hier:
+                ctx.hkdk_step(x, v, m, u, out, levels, dt)
+            else:
+                for _ in range(8):
+                    ctx.kdk_step(x, v, m, u, out, dt / 8)
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        res.append((time.perf_counter() - t0) * 1e3 / steps)
+        ctx.close()
+    return res[0], res[1], np.bincount(lev, minlength=4).tolist()
+
+
 COOL_BYTES_PER_PARTICLE = 12  # FP32: read u and rho, write u
 
 
@@ -314,6 +364,17 @@ def main():
                                             (2 * step_us * 1e-6) / 1e9, 1)}}
     log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
 
+    # timestep hierarchy (App. A.4): one big step on levels 0-3
+    hk = max(2, args.steps // 4)
+    msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
+    hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
+            "levels_0_1_2_3": hcount,
+            "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(c / median "
+                        "c)), 0, 3) (the hot core on level 3: eight substeps, passive particles "
+                        "skip the pair sums), against eight single-level steps of dt / 8"}
+    log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
+        % (msh, ms8, hcount))
+
     # exact-integration cooling (Sec. 2.2), 2^24 particles
     ncool = 1 << 24
     cus, ck = run_cool(ncool, args.steps, args.warmup)
@@ -412,7 +473,7 @@ def main():
                 "workload": "sedov64 (same particles, zero velocity), forward only",
                 "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
         "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "c4_268": c4, "kdk_step": kdk, "cooling": cool, "deposit": dep,
+        "c4_268": c4, "kdk_step": kdk, "hkdk_step": hkdk, "cooling": cool, "deposit": dep,
         "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

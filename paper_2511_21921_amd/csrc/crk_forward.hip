@@ -219,6 +219,10 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   if (__ballot(S.cnt[CNT_TOO_DENSE * kCntSpread + (threadIdx.x & 63)] != 0ull)) return;
   const int64_t s = particle_id();
   if (s >= S.n) return;
+  if (is_passive(S, S.perm[s])) {  // no sums of its own this substep
+    S.ccnt[s] = 0;
+    return;
+  }
   const R4<R> pi = S.pos4[s];
   const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
   const R rc2 = S.rcap * S.rcap;
@@ -545,7 +549,8 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     Stage4<uint32_t> sg, ss;
     int ccap;
     const int64_t base = scratch_base(S, s, ccap);
-    const int cc = S.ccnt[s] < ccap ? S.ccnt[s] : ccap;
+    // passive particles keep no lists (their force is not summed)
+    const int cc = is_passive(S, S.perm[s]) ? 0 : (S.ccnt[s] < ccap ? S.ccnt[s] : ccap);
     for (int k = 0; k < cc; k += 16) {
       const int64_t c = group_at(base, k);
       uint32_t ee[16];

@@ -108,10 +108,11 @@ struct State {
   int max_iter;
   // timestep hierarchy (App. A.3, A.4; levels null: every particle active).
   // A particle of level L is passive at the end of substep jend unless
-  // 2^(lev_max - L) divides jend. Passive particles skip the volume, moment,
-  // density and force sums and take V, rho, grad v and the corrections A, B,
-  // grad A, grad B from these caller-order arrays (their state of the last
-  // evaluation, V and rho updated while passive).
+  // 2^(lev_max - L) divides jend. Passive particles collect no candidates or
+  // lists, skip the volume, moment, density and force sums and take V, rho,
+  // grad v and the corrections A, B, grad A, grad B from these caller-order
+  // arrays (their state of the last evaluation, V and rho updated while
+  // passive).
   const int* levels;
   int lev_max;
   long long jend;
