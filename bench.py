@@ -294,6 +294,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the time-step, hierarchy, cooling and deposition fields "
+                         "(profiling runs of the forward + adjoint)")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the Wendland C4 n_h = 4 field (profiling runs of one workload)")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -347,54 +350,60 @@ def main():
               "pairs_force": stc["n_pairs_force"],
               "pass_ms": {k: round(pass_ms(passesc, k), 4) for k in names}}
 
-    # time integration around the passes: kick-drift-kick steps at fixed h
-    # (the Thacker/continuity rate); dt is small enough that the ambient gas next
-    # to the Sedov spike (u = 1e-2, du/dt up to ~1e4 from its half of the
-    # pair work) stays positive over the timed steps
-    msk, stk, passesk = run_kdk(ps, args.steps, args.warmup, 1e-9)
-    step_us = pass_ms(passesk, "step") * 1e3  # two update launches per step
-    kdk = {"ms_per_step": round(msk, 4), "value": stk["n_pairs_force"] / (msk * 1e-3),
-           "unit": "interactions/s",
-           "workload": "sedov64_v, kick-drift-kick steps (dt = 1e-9, lambda = 0.5) with h "
-                       "integrated by the Thacker/continuity rate from the solved h",
-           "speculative_forwards": stk["speculative"],
-           "update_kernels": {"us_per_step": round(2 * step_us, 2),
-                              "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
-                              "GBps": round(STEP_BYTES_PER_PARTICLE * ps.n /
-                                            (2 * step_us * 1e-6) / 1e9, 1)}}
-    log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
+    kdk = hkdk = cool = dep = None
+    if not args.no_extras:
+        # time integration around the passes: kick-drift-kick steps at fixed h
+        # (the Thacker/continuity rate); dt is small enough that the ambient gas next
+        # to the Sedov spike (u = 1e-2, du/dt up to ~1e4 from its half of the
+        # pair work) stays positive over the timed steps
+        msk, stk, passesk = run_kdk(ps, args.steps, args.warmup, 1e-9)
+        step_us = pass_ms(passesk, "step") * 1e3  # two update launches per step
+        kdk = {"ms_per_step": round(msk, 4), "value": stk["n_pairs_force"] / (msk * 1e-3),
+               "unit": "interactions/s",
+               "workload": "sedov64_v, kick-drift-kick steps (dt = 1e-9, lambda = 0.5) with h "
+                           "integrated by the Thacker/continuity rate from the solved h",
+               "speculative_forwards": stk["speculative"],
+               "update_kernels": {"us_per_step": round(2 * step_us, 2),
+                                  "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
+                                  "GBps": round(STEP_BYTES_PER_PARTICLE * ps.n /
+                                                (2 * step_us * 1e-6) / 1e9, 1)}}
+        log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
 
-    # timestep hierarchy (App. A.4): one big step on levels 0-3
-    hk = max(2, args.steps // 4)
-    msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
-    hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
-            "levels_0_1_2_3": hcount,
-            "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(c / median "
-                        "c)), 0, 3) (the hot core on level 3: eight substeps, passive particles "
-                        "skip the pair sums), against eight single-level steps of dt / 8"}
-    log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
-        % (msh, ms8, hcount))
+        # timestep hierarchy (App. A.4): one big step on levels 0-3
+        hk = max(2, args.steps // 4)
+        msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
+        hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
+                "levels_0_1_2_3": hcount,
+                "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(c / "
+                            "median c)), 0, 3) (the hot core on level 3: eight substeps, "
+                            "passive particles skip the pair sums), against eight "
+                            "single-level steps of dt / 8"}
+        log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
+            % (msh, ms8, hcount))
 
-    # exact-integration cooling (Sec. 2.2), 2^24 particles
-    ncool = 1 << 24
-    cus, ck = run_cool(ncool, args.steps, args.warmup)
-    cool = {"us_per_launch": round(cus, 2), "value": ncool / (cus * 1e-6), "unit": "particles/s",
-            "workload": "2^24 FP32 particles, u log-uniform over 7 decades, rho over 2; table of "
-                        "%d nodes at 0.004 dex, a broken power law with a stable zero" % ck,
-            "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
-                    "GBps": round(COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6) / 1e9, 1),
-                    "frac_of_8TBps": round(COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6) / 8e12,
-                                           3)}}
-    log("cooling: %.1f us for %d particles" % (cus, ncool))
+        # exact-integration cooling (Sec. 2.2), 2^24 particles
+        ncool = 1 << 24
+        cus, ck = run_cool(ncool, args.steps, args.warmup)
+        cool_bps = COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6)
+        cool = {"us_per_launch": round(cus, 2), "value": ncool / (cus * 1e-6),
+                "unit": "particles/s",
+                "workload": "2^24 FP32 particles, u log-uniform over 7 decades, rho over 2; "
+                            "table of %d nodes at 0.004 dex, a broken power law with a stable "
+                            "zero" % ck,
+                "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
+                        "GBps": round(cool_bps / 1e9, 1),
+                        "frac_of_8TBps": round(cool_bps / 8e12, 3)}}
+        log("cooling: %.1f us for %d particles" % (cus, ncool))
 
-    # subgrid deposition (App. A.2 eq. (Vsg), eq. (Anorm)): 2^21 gas, 2^16 sources
-    ngas, nsrc = 1 << 21, 1 << 16
-    dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
-    dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
-           "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
-           "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 uniform "
-                       "sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair sort, two host reads"}
-    log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
+        # subgrid deposition (App. A.2 eq. (Vsg), eq. (Anorm)): 2^21 gas, 2^16 sources
+        ngas, nsrc = 1 << 21, 1 << 16
+        dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
+        dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
+               "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
+               "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 "
+                           "uniform sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair "
+                           "sort, two host reads"}
+        log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
 
     fp64 = None
     if not args.no_fp64:
