@@ -179,3 +179,36 @@ def test_deposit_large_sampled_and_conserving():
     assert abs((got["m"] * got["u"]).sum() - e0 - src["dE"].sum()) < 1e-12 * e0
     p = (got["m"] * got["v"]).sum(1) - (gas["m"] * gas["v"]).sum(1)
     assert np.abs(p - (src["dM"] * src["v"]).sum(1)).max() < 1e-13
+
+
+def test_deposit_bench_size_sampled_and_conserving():
+    # the bench's configuration: 2^21 FP32 gas (~32 neighbours, h spread 20 %),
+    # 2^16 uniform sources, Wendland C4
+    ng, ns = 1 << 21, 1 << 16
+    rng = np.random.default_rng(21)
+    h0 = (32 / (4 * np.pi / 3) / ng) ** (1 / 3)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    gas = {"x": rng.uniform(0, 1, (3, ng)), "h": f32(h0 * (1 + 0.2 * rng.uniform(-1, 1, ng))),
+           "V": f32(np.full(ng, 1.0 / ng)), "m": f32(np.full(ng, 1.0 / ng)),
+           "mZ": f32(np.full(ng, 0.01 / ng)), "u": f32(np.ones(ng)),
+           "v": f32(rng.normal(0, 0.1, (3, ng)))}
+    src = {"x": rng.uniform(0, 1, (3, ns)), "dM": f32(np.full(ns, 1e-3 / ng)),
+           "dMZ": f32(np.full(ns, 1e-5 / ng)), "dE": f32(np.full(ns, 1e-3 / ng)),
+           "v": f32(rng.normal(0, 0.1, (3, ns)))}
+    print("case bench-size gas %d src %d FP32" % (ng, ns), flush=True)
+    ctx = Context(Params(precision=FP32, kernel=1))
+    got = _run(ctx, gas, src, torch.float32)
+    idx = np.random.default_rng(22).choice(ns, 24, replace=False)
+    sub = {k: v[..., idx] for k, v in src.items()}
+    want = oracle.deposit(gas, sub, N_HS, kernel=1)
+    for k in ("V_s", "h_s", "A_s"):
+        err = np.max(np.abs(got[k][idx] / want[k] - 1))
+        print("  %s sampled max rel err %.2e" % (k, err), flush=True)
+        assert err <= 1e-6, k
+    assert np.all(got["A_s"] > 0)
+    # totals in FP64 of the FP32 results: each grown value carries one FP32 rounding
+    m0 = gas["m"].sum()
+    assert abs(got["m"].sum() - m0 - src["dM"].sum()) < 1e-6 * src["dM"].sum() + 1e-7 * m0
+    e0 = (gas["m"] * gas["u"]).sum()
+    de = (got["m"] * got["u"]).sum() - e0
+    assert abs(de - src["dE"].sum()) < 1e-3 * src["dE"].sum() + 1e-7 * e0

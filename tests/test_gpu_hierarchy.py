@@ -44,6 +44,14 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+class _Progress(list):
+    """A trace that prints a line per substep of the oracle's big step."""
+
+    def append(self, item):
+        print("  oracle substep %d" % (len(self) + 1), flush=True)
+        super().append(None)
+
+
 def _state_errors(x, v, u, out, o):
     dx = np.abs(_np(x) - o["x"])
     dx = np.minimum(dx, 1.0 - dx)  # periodic
@@ -138,3 +146,40 @@ def test_hierarchy_errors():
     with pytest.raises(CrkError):
         ctx.backward(torch.zeros(3, ps.n, dtype=torch.float64, device=x.device),
                      torch.zeros(ps.n, dtype=torch.float64, device=x.device))
+
+
+def test_sedov64_v_big_step_at_full_size():
+    # the bench's configuration: 262,144 particles, the hot core on level 3
+    # (eight substeps), FP32 on the GPU against the FP64 oracle
+    ps = synth.sedov64_v()
+    print("case sedov64_v levels from c, one big step FP32", flush=True)
+    p1 = oracle.params_for(ps)
+    # the oracle's grid neighbour search (its brute force is quadratic in n)
+    h = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p1, nbr_mode=1)["h"]
+    print("  oracle h solved", flush=True)
+    ps.h, ps.h_mode = h, 0
+    p = oracle.params_for(ps)
+    c = np.sqrt(p.gamma * (p.gamma - 1.0) * ps.u)
+    lev = np.clip(np.ceil(np.log2(c / np.median(c))), 0, 3).astype(np.int64)
+    assert lev.max() == 3 and (lev == 3).sum() == 27
+    dt, lam = 8e-9, 0.5
+    ctx = Context(_gpu.params_for(ps, FP32))
+    x, v, m, u, hh = _gpu.to_dev(ps, FP32)
+    out = ctx.forward(x, v, m, u, hh)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam)
+    torch.cuda.synchronize()
+    print("  GPU step done", flush=True)
+    prev = oracle.forward(ps.x, ps.v, ps.m, ps.u, h, p, nbr_mode=1)
+    trace = _Progress()
+    o = oracle.hkdk_step(ps.x, ps.v, ps.m, ps.u, h, prev, lev, p, dt, lam, nbr_mode=1,
+                         trace=trace)
+    st = _state_errors(x, v, u, out, o)
+    g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+    e = _gpu.errors(g, o, o["h"])
+    print({k: "%.2e" % val for k, val in st.items()}, {k: "%.2e" % val for k, val in e.items()},
+          flush=True)
+    for k, val in st.items():
+        assert val <= STATE_BOUND[FP32], (k, val)
+    for k, b in FP32_BOUNDS.items():
+        assert e[k] <= b, (k, e[k], b)
