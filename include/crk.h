@@ -231,7 +231,9 @@ crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
  * crk_backward is not available (the last evaluation had passive
  * particles). Errors: CRK_EINVAL for h_mode != 0, a bad dt or lambda, levels
  * outside [0, 30], null arrays or n above 2^25 - 1; otherwise those of
- * crk_forward. n = 0 is a no-op. */
+ * crk_forward, from any substep (after such an error the arrays may hold a
+ * partly advanced state). The call reads the device a few times per substep
+ * (the level range once, then the forward's checks). n = 0 is a no-op. */
 crk_status crk_hkdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
                          double thacker_lambda, const int *levels, double *x, void *v,
                          const void *m, void *u, void *h, void *V, void *rho, void *A, void *B,
