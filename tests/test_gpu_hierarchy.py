@@ -183,3 +183,30 @@ def test_sedov64_v_big_step_at_full_size():
         assert val <= STATE_BOUND[FP32], (k, val)
     for k, b in FP32_BOUNDS.items():
         assert e[k] <= b, (k, e[k], b)
+
+
+def test_big_step_on_the_tree_search_path():
+    # the tree (the search for strongly clustered sets) with passive particles
+    ps = _start(3000, 301)
+    print("case random3000 levels 0-2 tree search FP64", flush=True)
+    dt, lam = 2e-4, 0.5
+    lev = np.random.default_rng(315).integers(0, 3, ps.n)
+    lev[0] = 2
+    p = oracle.params_for(ps)
+    ctx = Context(_gpu.params_for(ps, FP64, search=2))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam)
+    torch.cuda.synchronize()
+    prev = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p)
+    o = oracle.hkdk_step(ps.x, ps.v, ps.m, ps.u, ps.h, prev, lev, p, dt, lam)
+    st = _state_errors(x, v, u, out, o)
+    g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+    e = _gpu.errors(g, o, o["h"])
+    print({k: "%.2e" % val for k, val in st.items()}, {k: "%.2e" % val for k, val in e.items()},
+          flush=True)
+    for k, val in st.items():
+        assert val <= STATE_BOUND[FP64], (k, val)
+    for k, b in FP64_BOUNDS.items():
+        assert e[k] <= b, (k, e[k], b)
