@@ -14,40 +14,54 @@
 // constant source of the larger edge magnitude, u stopped at the zero of the
 // linear interpolant when moving toward it; moving away (an unstable zero) it
 // runs to the bin edge and continues in the neighbouring run. The table ends
-// clamp u. Arithmetic is FP64 in both precisions (u and rho are Real).
+// clamp u. Arithmetic is FP64 in both precisions (u and rho are Real), in log
+// space where it can be: ln(u / u_k) = ln 10 (log10 u - log10 u_k) from the
+// one log10 of the bin lookup, and the inverse as exp(ln u_k + ...), so that a
+// particle in a run costs four transcendentals (log10, expm1, log1p, exp).
+#include <cmath>
+
 #include "crk_internal.h"
 
 namespace crk {
 namespace {
 
+constexpr double kLn10 = 2.302585092994045684;
+
 struct CoolTab {
   int K;
   double lu0, dex;
+  double u_lo, u_hi;    // the first and last node energies
   const double* lam;    // [K]
+  const double* c;      // [K - 1] u_k / lam_k of each power-law bin (0 for a sign-change bin)
   const double* slope;  // [K - 1] power-law slope of each bin (0 for a sign-change bin)
   const double* G;      // [K] prefix integral within the node's run (see above)
   const int2* run;      // [K - 1] first and last bin of the bin's run ({-1, -1}: sign change)
 };
 
+__device__ inline double node_lnu(const CoolTab& T, int k) {
+  return kLn10 * (T.lu0 + (double)k * T.dex);
+}
+
 __device__ inline double node_u(const CoolTab& T, int k) {
   return exp10(T.lu0 + (double)k * T.dex);
 }
 
-__device__ inline int bin_of(const CoolTab& T, double u) {
-  int k = (int)floor((log10(u) - T.lu0) / T.dex);
+__device__ inline int bin_of(const CoolTab& T, double lg) {
+  int k = (int)floor((lg - T.lu0) / T.dex);
   return k < 0 ? 0 : (k > T.K - 2 ? T.K - 2 : k);
 }
 
-// int from u_k to u of du / lam inside power-law bin k
-__device__ inline double in_bin(const CoolTab& T, int k, double uk, double u) {
-  const double a = T.slope[k], l = log(u / uk), c = uk / T.lam[k];
+// int from u_k to u of du / lam inside power-law bin k, l = ln(u / u_k)
+__device__ inline double in_bin(const CoolTab& T, int k, double l) {
+  const double a = T.slope[k], c = T.c[k];
   return a == 1.0 ? c * l : c * expm1((1.0 - a) * l) / (1.0 - a);
 }
 
 // u in power-law bin k with int from u_k to u of du / lam = g
-__device__ inline double in_bin_inverse(const CoolTab& T, int k, double uk, double g) {
-  const double a = T.slope[k], y = g * T.lam[k] / uk;
-  return a == 1.0 ? uk * exp(y) : uk * exp(log1p((1.0 - a) * y) / (1.0 - a));
+__device__ inline double in_bin_inverse(const CoolTab& T, int k, double g) {
+  const double a = T.slope[k], y = g / T.c[k];
+  const double t = a == 1.0 ? y : log1p((1.0 - a) * y) / (1.0 - a);
+  return exp(node_lnu(T, k) + t);
 }
 
 // Sign-change bin k: returns u and sets left (rho t still to integrate).
@@ -76,13 +90,14 @@ __device__ inline double equilibrium_bin(const CoolTab& T, int k, double u, doub
 
 // One phase from the anchor u: the run of same-sign bins, or the sign-change bin.
 __device__ inline double cool_phase(const CoolTab& T, double u, double& left) {
-  const int k = bin_of(T, u);
+  const double lg = log10(u);
+  const int k = bin_of(T, lg);
   const int2 run = T.run[k];
   if (run.x < 0) return equilibrium_bin(T, k, u, left);
-  const bool cooling = T.lam[k] > 0.0;
-  const double uk = node_u(T, k);
+  const bool cooling = T.c[k] > 0.0;
   // G(u^1) = G(u^0) - rho dt; G rises with u where lam > 0, falls where lam < 0
-  const double target = T.G[k] + in_bin(T, k, uk, u) - left;
+  const double l = kLn10 * (lg - T.lu0 - (double)k * T.dex);
+  const double target = T.G[k] + in_bin(T, k, l) - left;
   // nodes of the run: run.x .. run.y + 1 (G = 0 at run.x); the motion runs
   // out of the run past its lowest (cooling) or highest (heating) node
   const int end_node = cooling ? run.x : run.y + 1;
@@ -106,7 +121,17 @@ __device__ inline double cool_phase(const CoolTab& T, double u, double& left) {
     if (before) lo = mid; else hi = mid - 1;
   }
   left = 0.0;
-  return in_bin_inverse(T, lo, node_u(T, lo), target - T.G[lo]);
+  return in_bin_inverse(T, lo, target - T.G[lo]);
+}
+
+template <class R>
+__device__ inline void cool_one(const CoolTab& T, int64_t i, double dt, const R* rho, R* u) {
+  double ui = (double)u[i];
+  ui = ui < T.u_lo ? T.u_lo : (ui > T.u_hi ? T.u_hi : ui);
+  double left = (double)rho[i] * dt;
+  // an unstable zero sends u out of its bin once; each side ends in a run
+  for (int phase = 0; phase < 3 && left > 0.0; ++phase) ui = cool_phase(T, ui, left);
+  u[i] = (R)ui;
 }
 
 template <class R>
@@ -114,37 +139,69 @@ __global__ void __launch_bounds__(kBlock) k_cool(CoolTab T, int64_t n, double dt
                                                  const R* __restrict__ rho, R* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  double ui = (double)u[i];
-  const double lo = node_u(T, 0), hi = node_u(T, T.K - 1);
-  ui = ui < lo ? lo : (ui > hi ? hi : ui);
-  double left = (double)rho[i] * dt;
-  // an unstable zero sends u out of its bin once; each side ends in a run
-  for (int phase = 0; phase < 3 && left > 0.0; ++phase) ui = cool_phase(T, ui, left);
-  u[i] = (R)ui;
+  cool_one(T, i, dt, rho, u);
 }
 
-// Table preparation, one block: slopes and runs per bin, then the prefix
-// integrals within every run (run starts get G = 0).
+// The same with the per-bin table copied into LDS once per block (persistent
+// blocks striding over the particles): the bin lookup and the binary search
+// read LDS instead of waiting on the L2 at every dependent step. The table
+// takes 32 bytes per node (c, slope, G, run); lam, read only in sign-change
+// bins, stays in global memory.
+constexpr int kCoolBlock = 1024;
+
+template <class R>
+__global__ void __launch_bounds__(kCoolBlock) k_cool_lds(CoolTab Tg, int64_t n, double dt,
+                                                         const R* __restrict__ rho,
+                                                         R* __restrict__ u) {
+  extern __shared__ double table[];
+  const int K = Tg.K;
+  double* c = table;
+  double* slope = c + K;
+  double* G = slope + K;
+  int2* run = (int2*)(G + K);
+  for (int k = threadIdx.x; k < K; k += kCoolBlock) {
+    G[k] = Tg.G[k];
+    if (k < K - 1) {
+      c[k] = Tg.c[k];
+      slope[k] = Tg.slope[k];
+      run[k] = Tg.run[k];
+    }
+  }
+  __syncthreads();
+  CoolTab T = Tg;
+  T.c = c;
+  T.slope = slope;
+  T.G = G;
+  T.run = run;
+  for (int64_t i = (int64_t)blockIdx.x * kCoolBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kCoolBlock)
+    cool_one(T, i, dt, rho, u);
+}
+
+// Table preparation, one block: slopes, c = u_k / lam_k and runs per bin,
+// then the prefix integrals within every run (run starts get G = 0).
 __global__ void __launch_bounds__(kBlock) k_cool_prepare(int K, double lu0, double dex,
                                                          const double* __restrict__ lam,
                                                          double* __restrict__ slope,
+                                                         double* __restrict__ c,
                                                          double* __restrict__ G,
                                                          int2* __restrict__ run,
                                                          double* __restrict__ binint) {
-  CoolTab T{K, lu0, dex, lam, slope, G, run};
+  CoolTab T{K, lu0, dex, 0.0, 0.0, lam, c, slope, G, run};
   for (int k = threadIdx.x; k < K - 1; k += kBlock) {
     const double lk = lam[k], lk1 = lam[k + 1];
     if (lk * lk1 > 0.0) {
-      const double uk = node_u(T, k), uk1 = node_u(T, k + 1);
-      slope[k] = log(lk1 / lk) / log(uk1 / uk);
+      slope[k] = log(lk1 / lk) / (kLn10 * dex);
+      c[k] = node_u(T, k) / lk;
     } else {
       slope[k] = 0.0;
+      c[k] = 0.0;
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < K - 1; k += kBlock) {
     const bool pl = lam[k] * lam[k + 1] > 0.0;
-    binint[k] = pl ? in_bin(T, k, node_u(T, k), node_u(T, k + 1)) : 0.0;
+    binint[k] = pl ? in_bin(T, k, kLn10 * dex) : 0.0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -177,24 +234,34 @@ __global__ void __launch_bounds__(kBlock) k_cool_prepare(int K, double lu0, doub
 }  // namespace
 
 void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
-                         double* G, void* run, double* binint, hipStream_t s) {
-  hipLaunchKernelGGL(k_cool_prepare, dim3(1), dim3(kBlock), 0, s, K, lu0, dex, lam, slope, G,
+                         double* c, double* G, void* run, double* binint, hipStream_t s) {
+  hipLaunchKernelGGL(k_cool_prepare, dim3(1), dim3(kBlock), 0, s, K, lu0, dex, lam, slope, c, G,
                      (int2*)run, binint);
 }
 
 template <class R>
-void launch_cool(int K, double lu0, double dex, const double* lam, const double* slope,
-                 const double* G, const void* run, int64_t n, double dt, const R* rho, R* u,
-                 hipStream_t s) {
-  CoolTab T{K, lu0, dex, lam, slope, G, (const int2*)run};
-  hipLaunchKernelGGL(k_cool<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, T, n, dt, rho, u);
+void launch_cool(int K, double lu0, double dex, const double* lam, const double* c,
+                 const double* slope, const double* G, const void* run, int64_t n, double dt,
+                 const R* rho, R* u, hipStream_t s) {
+  const double u_lo = std::pow(10.0, lu0), u_hi = std::pow(10.0, lu0 + (K - 1) * dex);
+  CoolTab T{K, lu0, dex, u_lo, u_hi, lam, c, slope, G, (const int2*)run};
+  const size_t lds = 32 * (size_t)K;
+  if (lds <= 65536) {
+    // two blocks of 1024 per compute unit over the 256 units, or fewer
+    const int64_t want = (n + kCoolBlock - 1) / kCoolBlock;
+    const int64_t blocks = want < 512 ? want : 512;
+    hipLaunchKernelGGL(k_cool_lds<R>, dim3((unsigned)blocks), dim3(kCoolBlock), lds, s, T, n, dt,
+                       rho, u);
+  } else {
+    hipLaunchKernelGGL(k_cool<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, T, n, dt, rho, u);
+  }
 }
 
 template void launch_cool<float>(int, double, double, const double*, const double*,
-                                 const double*, const void*, int64_t, double, const float*,
-                                 float*, hipStream_t);
+                                 const double*, const double*, const void*, int64_t, double,
+                                 const float*, float*, hipStream_t);
 template void launch_cool<double>(int, double, double, const double*, const double*,
-                                  const double*, const void*, int64_t, double, const double*,
-                                  double*, hipStream_t);
+                                  const double*, const double*, const void*, int64_t, double,
+                                  const double*, double*, hipStream_t);
 
 }  // namespace crk
