@@ -105,3 +105,29 @@ def test_cooling_million_particles_sampled():
     want = oracle.cool(oracle.CoolingTable(LU0, DEX, lam), u0[idx], rho[idx], dt)
     assert np.max(np.abs(got[idx] / want - 1)) <= 1e-11
     assert np.all(np.isfinite(got)) and got.min() >= UK[0] and got.max() <= UK[-1]
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_cooling_table_beyond_the_lds_size(precision):
+    # 3001 nodes (0.002 dex over six decades): more than the LDS copy holds,
+    # so the table is read from global memory; same arithmetic
+    dex = 0.002
+    k = int(round(6 / dex)) + 1
+    uk = 10 ** (LU0 + dex * np.arange(k))
+    rng = np.random.default_rng(8)
+    lam = A * (uk ** 1.5 - 3.0 ** 1.5) * np.exp(np.cumsum(rng.normal(0, 0.01, k)))
+    u0, rho = _particles(1500, 9)
+    print("case %d nodes precision=%d" % (k, precision), flush=True)
+    R = torch.float64 if precision == FP64 else torch.float32
+    u0 = u0.astype(np.float32).astype(np.float64) if precision == FP32 else u0
+    rho = rho.astype(np.float32).astype(np.float64) if precision == FP32 else rho
+    ctx = Context(Params(precision=precision))
+    ctx.cooling_table(LU0, dex, lam)
+    u = torch.tensor(u0, dtype=R, device=DEV)
+    ctx.cool(torch.tensor(rho, dtype=R, device=DEV), u, 0.05)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy().astype(np.float64)
+    want = oracle.cool(oracle.CoolingTable(LU0, dex, lam), u0, rho, 0.05)
+    err = np.max(np.abs(got / want - 1))
+    print("  max rel err %.2e" % err, flush=True)
+    assert err <= (1e-11 if precision == FP64 else 2e-7)
