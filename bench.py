@@ -165,10 +165,11 @@ def run_kdk(ps, steps, warmup, dt):
 
 def run_hkdk(ps, steps, warmup, dt):
     """One big step of the timestep hierarchy (crk_hkdk_step, FP32) from ps with
-    h fixed at its solved value; levels from the sound speed, level =
-    clip(ceil(log2(c / median c)), 0, 3) (the hot core on level 3: eight
-    substeps). Also times the same span as eight single-level steps of dt/8.
-    Returns ms per big step, ms per eight single-level steps, the level counts."""
+    h fixed at its solved value; levels from the signal speed s = c + |v|,
+    level = clip(ceil(log2(s / median s)), 0, 3) (half the particles on level
+    1, the hot core on level 3: eight substeps). Also times the same span as
+    eight single-level steps of dt/8. Returns ms per big step, ms per eight
+    single-level steps, the level counts."""
     import dataclasses
 
     import numpy as np
@@ -184,8 +185,8 @@ def run_hkdk(ps, steps, warmup, dt):
     h0 = o1["h"].clone()
     c1.close()
     gam = p1.gamma
-    c = np.sqrt(gam * (gam - 1.0) * ps.u)
-    lev = np.clip(np.ceil(np.log2(c / np.median(c))), 0, 3).astype(np.int32)
+    sig = np.sqrt(gam * (gam - 1.0) * ps.u) + np.sqrt((ps.v ** 2).sum(0))
+    lev = np.clip(np.ceil(np.log2(sig / np.median(sig))), 0, 3).astype(np.int32)
     levels = t(lev, torch.int32)
     p = dataclasses.replace(p1, h_mode=0)
     res = []
@@ -374,10 +375,10 @@ def main():
         msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
         hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
                 "levels_0_1_2_3": hcount,
-                "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(c / "
-                            "median c)), 0, 3) (the hot core on level 3: eight substeps, "
-                            "passive particles skip the pair sums), against eight "
-                            "single-level steps of dt / 8"}
+                "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(s / "
+                            "median s)), 0, 3), s = c + |v| (eight substeps; passive "
+                            "particles skip the pair sums), against eight single-level "
+                            "steps of dt / 8"}
         log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
             % (msh, ms8, hcount))
 

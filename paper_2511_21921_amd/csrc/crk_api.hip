@@ -65,7 +65,7 @@ struct crk_ctx {
   Buf vpred, upred;
   // timestep hierarchy: half-kicked velocity and energy, hdot, and the
   // evaluation of the substep (its accel and du/dt before the close)
-  Buf hl_vh, hl_uh, hl_hdot, hl_acc, hl_du;
+  Buf hl_vh, hl_uh, hl_hdot, hl_acc, hl_du, hl_need;
   // levels and stored state seen by the passes during a hierarchical
   // substep (null levels: every particle active)
   const int* hl_levels = nullptr;
@@ -273,6 +273,7 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.pB = (const R*)c->hl_B;
   S.pgA = (const R*)c->hl_gA;
   S.pgB = (const R*)c->hl_gB;
+  S.needed = c->hl_levels && !c->lattice ? (uint8_t*)c->hl_need.p : nullptr;
   return S;
 }
 
@@ -966,6 +967,7 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
   CRK_HIP(ensure(ctx->hl_hdot, 8 * N), "step workspace");
   CRK_HIP(ensure(ctx->hl_acc, 8 * 3 * N), "step workspace");
   CRK_HIP(ensure(ctx->hl_du, 8 * N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_need, N), "step workspace");
   R* vp = (R*)ctx->vpred.p;
   R* up = (R*)ctx->upred.p;
   R* vh = (R*)ctx->hl_vh.p;
@@ -996,6 +998,8 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
     ctx->hl_B = B;
     ctx->hl_gA = gradA;
     ctx->hl_gB = gradB;
+    // the neighbour-list pass marks the passive partners of active particles
+    CRK_HIP(hipMemsetAsync(ctx->hl_need.p, 0, N, s), "memset");
     crk_status st = forward_impl<R>(ctx, s, n, x, vp, m, up, h, V, rho, A, B, gradA, gradB,
                                     gradv, acc1, du1, stats);
     ctx->hl_levels = nullptr;
@@ -1214,7 +1218,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
-                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du,
+                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need,
                 &c->cool_lam, &c->cool_slope, &c->cool_c, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,

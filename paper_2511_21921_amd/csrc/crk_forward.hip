@@ -571,12 +571,14 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
             if ((ng & 3) == 3) sg.flush(S.nlist, s, cap, ng);
           }
           ++ng;
+          if (S.needed) S.needed[e >> kCodeBits] = 1;
         } else if (in && rr[t] < hj[t]) {
           if (ns < scap) {
             ss.put(ns & 3, e);
             if ((ns & 3) == 3) ss.flush(S.slist, s, scap, ns);
           }
           ++ns;
+          if (S.needed) S.needed[e >> kCodeBits] = 1;
         }
       }
     }
@@ -781,19 +783,22 @@ __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
   const int64_t s = particle_id();
   unsigned long long sing = 0;
   if (s < S.n && is_passive(S, S.perm[s])) {
-    // the corrections of the particle's last evaluation
-    const int64_t n = S.n;
-    const uint32_t p = S.perm[s];
-    Corr64 c;
-    c.A = (double)S.pA[p];
+    if (!S.needed || S.needed[s]) {
+      // the corrections of the particle's last evaluation, where a force
+      // pair of an active particle reads them
+      const int64_t n = S.n;
+      const uint32_t p = S.perm[s];
+      Corr64 c;
+      c.A = (double)S.pA[p];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      c.B[t] = (double)S.pB[t * n + p];
-      c.dA[t] = (double)S.pgA[t * n + p];
+      for (int t = 0; t < 3; ++t) {
+        c.B[t] = (double)S.pB[t * n + p];
+        c.dA[t] = (double)S.pgA[t * n + p];
+      }
+#pragma unroll
+      for (int t = 0; t < 9; ++t) c.dB[t] = (double)S.pgB[t * n + p];
+      store_kc(S, s, c);
     }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) c.dB[t] = (double)S.pgB[t * n + p];
-    store_kc(S, s, c);
   } else if (s < S.n) {
     Moments<R> M;
     accumulate_moments<R, K>(S, s, M);
@@ -879,7 +884,9 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
                                                     R* __restrict__ gradv_out) {
   const int64_t s = particle_id();
   unsigned long long nrel = 0;
-  if (s < S.n && is_passive(S, S.perm[s])) {
+  if (s < S.n && is_passive(S, S.perm[s]) && S.needed && !S.needed[s]) {
+    // a passive particle no active one reads this substep: nothing to pack
+  } else if (s < S.n && is_passive(S, S.perm[s])) {
     // the carried density and the gradient of the last evaluation; P and c
     // from that density and the particle's u
     const int64_t n = S.n;
@@ -1016,6 +1023,8 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
                                                   double* __restrict__ dudt) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
+  // passive particles keep their acceleration: nothing to sum or write
+  if (is_passive(S, S.perm[s])) return;
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
   const R4<R> si = S.st4[s];
@@ -1030,8 +1039,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;  // at 3 waves per SIMD this beats 4 waves with the chunk in LDS
   const int ng = nb.ng, ns = nb.ns;
-  // passive particles keep their acceleration: nothing to sum
-  const int total = is_passive(S, S.perm[s]) ? 0 : ng + ns;
+  const int total = ng + ns;
   for (int t = 0; t < total; ++t) {
     const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;

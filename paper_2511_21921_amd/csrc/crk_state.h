@@ -112,7 +112,7 @@ struct State {
   // lists, skip the volume, moment, density and force sums and take V, rho,
   // grad v and the corrections A, B, grad A, grad B from these caller-order
   // arrays (their state of the last evaluation, V and rho updated while
-  // passive).
+  // passive) when an active particle's force pair reads them.
   const int* levels;
   int lev_max;
   long long jend;
@@ -123,6 +123,10 @@ struct State {
   const R* pB;
   const R* pgA;
   const R* pgB;
+  // per sorted particle, set by the neighbour-list pass for the active
+  // particles and their list partners: the passive particles whose stored
+  // state a force pair reads (null: every particle's state is packed)
+  uint8_t* needed;
 };
 
 template <class R>

@@ -149,19 +149,20 @@ def test_hierarchy_errors():
 
 
 def test_sedov64_v_big_step_at_full_size():
-    # the bench's configuration: 262,144 particles, the hot core on level 3
-    # (eight substeps), FP32 on the GPU against the FP64 oracle
+    # the bench's configuration: 262,144 particles on levels from the signal
+    # speed c + |v| (half on level 1, the hot core on level 3: eight
+    # substeps), FP32 on the GPU against the FP64 oracle
     ps = synth.sedov64_v()
-    print("case sedov64_v levels from c, one big step FP32", flush=True)
+    print("case sedov64_v levels from c + |v|, one big step FP32", flush=True)
     p1 = oracle.params_for(ps)
     # the oracle's grid neighbour search (its brute force is quadratic in n)
     h = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p1, nbr_mode=1)["h"]
     print("  oracle h solved", flush=True)
     ps.h, ps.h_mode = h, 0
     p = oracle.params_for(ps)
-    c = np.sqrt(p.gamma * (p.gamma - 1.0) * ps.u)
-    lev = np.clip(np.ceil(np.log2(c / np.median(c))), 0, 3).astype(np.int64)
-    assert lev.max() == 3 and (lev == 3).sum() == 27
+    sig = np.sqrt(p.gamma * (p.gamma - 1.0) * ps.u) + np.sqrt((ps.v ** 2).sum(0))
+    lev = np.clip(np.ceil(np.log2(sig / np.median(sig))), 0, 3).astype(np.int64)
+    assert lev.max() == 3 and (lev == 3).sum() == 27 and (lev == 1).sum() > 100000
     dt, lam = 8e-9, 0.5
     ctx = Context(_gpu.params_for(ps, FP32))
     x, v, m, u, hh = _gpu.to_dev(ps, FP32)
