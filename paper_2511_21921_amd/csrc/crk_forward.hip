@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   if (__ballot(S.cnt[CNT_TOO_DENSE * kCntSpread + (threadIdx.x & 63)] != 0ull)) return;
   const int64_t s = particle_id();
   if (s >= S.n) return;
-  if (is_passive(S, S.perm[s])) {  // no sums of its own this substep
+  if (is_passive(S, s)) {  // no sums of its own this substep
     S.ccnt[s] = 0;
     return;
   }
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
   if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
-  if (is_passive(S, S.perm[s])) {  // V comes from the stored state (k_pack)
+  if (is_passive(S, s)) {  // V comes from the stored state (k_pack)
     if (S.todo) S.todo[s] = 0;
     return;
   }
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
   const int64_t s = particle_id();
   if (s >= S.n) return;
   const uint32_t p = S.perm[s];
-  const bool pas = is_passive(S, p);
+  const bool pas = is_passive(S, s);
   const R h = S.hbuf[s], V = pas ? S.pV[p] : S.Vbuf[s];
   S.pos4[s].w = R(1) / h;
   S.vel4[s].w = V;
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     int ccap;
     const int64_t base = scratch_base(S, s, ccap);
     // passive particles keep no lists (their force is not summed)
-    const int cc = is_passive(S, S.perm[s]) ? 0 : (S.ccnt[s] < ccap ? S.ccnt[s] : ccap);
+    const int cc = is_passive(S, s) ? 0 : (S.ccnt[s] < ccap ? S.ccnt[s] : ccap);
     for (int k = 0; k < cc; k += 16) {
       const int64_t c = group_at(base, k);
       uint32_t ee[16];
@@ -782,7 +782,7 @@ template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
   const int64_t s = particle_id();
   unsigned long long sing = 0;
-  if (s < S.n && is_passive(S, S.perm[s])) {
+  if (s < S.n && is_passive(S, s)) {
     if (!S.needed || S.needed[s]) {
       // the corrections of the particle's last evaluation, where a force
       // pair of an active particle reads them
@@ -884,9 +884,10 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
                                                     R* __restrict__ gradv_out) {
   const int64_t s = particle_id();
   unsigned long long nrel = 0;
-  if (s < S.n && is_passive(S, S.perm[s]) && S.needed && !S.needed[s]) {
+  const bool pas = s < S.n && is_passive(S, s);
+  if (pas && S.needed && !S.needed[s]) {
     // a passive particle no active one reads this substep: nothing to pack
-  } else if (s < S.n && is_passive(S, S.perm[s])) {
+  } else if (pas) {
     // the carried density and the gradient of the last evaluation; P and c
     // from that density and the particle's u
     const int64_t n = S.n;
@@ -1024,7 +1025,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const int64_t s = particle_id();
   if (s >= S.n) return;
   // passive particles keep their acceleration: nothing to sum or write
-  if (is_passive(S, S.perm[s])) return;
+  if (is_passive(S, s)) return;
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
   const R4<R> si = S.st4[s];

@@ -129,10 +129,11 @@ struct State {
   uint8_t* needed;
 };
 
+// whether sorted particle s is passive (reads nothing without a hierarchy)
 template <class R>
-__device__ inline bool is_passive(const State<R>& S, uint32_t p) {
+__device__ inline bool is_passive(const State<R>& S, int64_t s) {
   if (!S.levels) return false;
-  const long long per = 1ll << (S.lev_max - S.levels[p]);
+  const long long per = 1ll << (S.lev_max - S.levels[S.perm[s]]);
   return (S.jend & (per - 1)) != 0;
 }
 
