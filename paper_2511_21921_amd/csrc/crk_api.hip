@@ -265,7 +265,7 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.max_iter = c->p.h_max_iter;
   S.levels = c->hl_levels;
   S.lev_max = c->hl_lmax;
-  S.jend = c->hl_jend;
+  S.jend = (int)c->hl_jend;
   S.pV = (const R*)c->hl_V;
   S.prho = (const R*)c->hl_rho;
   S.pgv = (const R*)c->hl_gv;

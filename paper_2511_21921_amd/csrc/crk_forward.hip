@@ -1019,13 +1019,15 @@ __device__ inline void side_grad(const KC<R>& k, const R x[3], R r2, R rinv, R h
   kc_apply(k, x, W, gW, WR, out);
 }
 
-template <class R, int K>
+// HIER: a substep of the timestep hierarchy (the passive particles keep their
+// acceleration: nothing to sum or write); a separate instance, so that the
+// ordinary forward's code is not shaped by the extra branch
+template <class R, int K, bool HIER>
 __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict__ accel,
                                                   double* __restrict__ dudt) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
-  // passive particles keep their acceleration: nothing to sum or write
-  if (is_passive(S, s)) return;
+  if (HIER && is_passive(S, s)) return;
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
   const R4<R> si = S.st4[s];
@@ -1192,7 +1194,18 @@ void launch_density(const State<R>& S, int kernel, R* rho_out, R* gradv_out, hip
 }
 template <class R>
 void launch_force(const State<R>& S, int kernel, double* accel, double* dudt, hipStream_t s) {
-  CRK_DISPATCH_K(kernel, k_force, S, accel, dudt);
+  const dim3 grid(grid_for(S.n)), block(kBlock);
+  if (S.levels) {
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_force<R, 0, true>), grid, block, 0, s, S, accel, dudt);
+    else
+      hipLaunchKernelGGL((k_force<R, 1, true>), grid, block, 0, s, S, accel, dudt);
+  } else {
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_force<R, 0, false>), grid, block, 0, s, S, accel, dudt);
+    else
+      hipLaunchKernelGGL((k_force<R, 1, false>), grid, block, 0, s, S, accel, dudt);
+  }
 }
 template <class R>
 void launch_count_nonfinite(const R* a, int64_t na, unsigned long long* cnt, hipStream_t s) {

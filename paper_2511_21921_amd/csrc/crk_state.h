@@ -115,7 +115,7 @@ struct State {
   // passive) when an active particle's force pair reads them.
   const int* levels;
   int lev_max;
-  long long jend;
+  int jend;  // substep end, at most 2^30
   const R* pV;
   const R* prho;
   const R* pgv;
@@ -134,7 +134,7 @@ template <class R>
 __device__ inline bool is_passive(const State<R>& S, int64_t s) {
   if (!S.levels) return false;
   const long long per = 1ll << (S.lev_max - S.levels[S.perm[s]]);
-  return (S.jend & (per - 1)) != 0;
+  return ((long long)S.jend & (per - 1)) != 0;
 }
 
 __device__ inline int wrap_cell(int c, int G) { return c < 0 ? c + G : (c >= G ? c - G : c); }
