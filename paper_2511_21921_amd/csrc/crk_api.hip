@@ -988,6 +988,9 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
     launch_hier_predict<R>(n, levels, lmax, jend, dt_min, vh, uh, accel, dudt, vp, up, s);
     CRK_HIP(tend(ctx, P_STEP, s), "event");
     CRK_HIP(hipGetLastError(), "hierarchy launch");
+    // the neighbour-list pass marks the passive partners of active particles
+    CRK_HIP(hipMemsetAsync(ctx->hl_need.p, 0, N, s), "memset");
+    // the passes see the levels and the stored state during this forward only
     ctx->hl_levels = levels;
     ctx->hl_lmax = lmax;
     ctx->hl_jend = jend;
@@ -998,8 +1001,6 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
     ctx->hl_B = B;
     ctx->hl_gA = gradA;
     ctx->hl_gB = gradB;
-    // the neighbour-list pass marks the passive partners of active particles
-    CRK_HIP(hipMemsetAsync(ctx->hl_need.p, 0, N, s), "memset");
     crk_status st = forward_impl<R>(ctx, s, n, x, vp, m, up, h, V, rho, A, B, gradA, gradB,
                                     gradv, acc1, du1, stats);
     ctx->hl_levels = nullptr;
