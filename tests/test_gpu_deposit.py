@@ -212,3 +212,15 @@ def test_deposit_bench_size_sampled_and_conserving():
     e0 = (gas["m"] * gas["u"]).sum()
     de = (got["m"] * got["u"]).sum() - e0
     assert abs(de - src["dE"].sum()) < 1e-3 * src["dE"].sum() + 1e-7 * e0
+
+
+def test_deposit_sources_on_gas_particles_and_more_sources_than_gas():
+    gas, src = _case(2000, 2500, 0.16, 18, False)
+    # every fifth source sits exactly on a gas particle (r = 0 pairs)
+    src["x"][:, ::5] = gas["x"][:, :500]
+    print("case coincident sources, 2500 sources on 2000 gas", flush=True)
+    ctx = Context(Params(precision=FP64, kernel=1))
+    got = _run(ctx, gas, src, torch.float64)
+    want = oracle.deposit(gas, src, N_HS, kernel=1)
+    assert np.all(want["A_s"] > 0)
+    _compare(got, want, gas, 1e-12)

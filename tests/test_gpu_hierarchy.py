@@ -211,3 +211,28 @@ def test_big_step_on_the_tree_search_path():
         assert val <= STATE_BOUND[FP64], (k, val)
     for k, b in FP64_BOUNDS.items():
         assert e[k] <= b, (k, e[k], b)
+
+
+def test_deep_hierarchy_sixteen_substeps():
+    ps = _start(1000, 316)
+    print("case random1000 levels 0-4 FP64", flush=True)
+    dt, lam = 4e-4, 0.5
+    lev = np.random.default_rng(317).integers(0, 5, ps.n)
+    lev[0] = 4
+    p = oracle.params_for(ps)
+    ctx = Context(_gpu.params_for(ps, FP64))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam)
+    torch.cuda.synchronize()
+    prev = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p)
+    o = oracle.hkdk_step(ps.x, ps.v, ps.m, ps.u, ps.h, prev, lev, p, dt, lam)
+    st = _state_errors(x, v, u, out, o)
+    g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+    e = _gpu.errors(g, o, o["h"])
+    print({k: "%.2e" % val for k, val in st.items()}, flush=True)
+    for k, val in st.items():
+        assert val <= STATE_BOUND[FP64], (k, val)
+    for k, b in FP64_BOUNDS.items():
+        assert e[k] <= b, (k, e[k], b)
