@@ -81,7 +81,7 @@ struct crk_ctx {
   // subgrid deposition: one sorted point grid at a time and its counters
   Buf dep_keys_a, dep_keys_b, dep_vals_a, dep_vals_b, dep_start, dep_tmp, dep_cnt;
   Buf dep_npair, dep_off, dep_first, dep_pj_a, dep_pj_b, dep_ps_a, dep_ps_b, dep_ptmp, dep_p4,
-      dep_pv, dep_sp;
+      dep_pv, dep_sp, dep_slot;
   unsigned long long host_cnt[crk::CNT_COUNT] = {};  // folded counters
   unsigned long long* host_raw = nullptr;  // the device slots (pinned)
   int list_cap = 128;
@@ -1108,7 +1108,9 @@ crk_status deposit_impl(crk_ctx* ctx, hipStream_t s, int64_t ng, const double* x
   launch_dep_volume<R>(P.kernel, grid, xs, ns, self_frac, n_h_s, Vs, hs, s);
   uint32_t* npair = (uint32_t*)ctx->dep_npair.p;
   CRK_HIP(ensure(ctx->dep_sp, 96 * (size_t)ns), "deposition workspace");
-  launch_dep_norm<R>(P.kernel, grid, xs, ns, hs, dM, dMZ, dE, vs, As, ctx->dep_sp.p, npair, cnt, s);
+  CRK_HIP(ensure(ctx->dep_slot, 4 * 64 * (size_t)ns), "deposition workspace");
+  launch_dep_norm<R>(P.kernel, grid, xs, ns, hs, dM, dMZ, dE, vs, As, ctx->dep_sp.p, npair,
+                     (uint32_t*)ctx->dep_slot.p, cnt, s);
   CRK_HIP(hipGetLastError(), "deposition launch");
   if (crk_status st = dep_read(ctx, s, folded)) return st;
   const double hsmax = bits_to_double(folded[CNT_HMAX_OUT_BITS]);
@@ -1129,8 +1131,9 @@ crk_status deposit_impl(crk_ctx* ctx, hipStream_t s, int64_t ng, const double* x
     CRK_HIP(exclusive_scan_u32(npair, (uint32_t*)ctx->dep_off.p, ns, (uint32_t*)ctx->dep_tmp.p,
                                s),
             "deposition scan");
-    launch_dep_pairs<R>(grid, xs, ns, hs, npair, (const uint32_t*)ctx->dep_off.p,
-                        (uint32_t*)ctx->dep_pj_a.p, (uint32_t*)ctx->dep_ps_a.p, s);
+    launch_dep_pairs<R>(grid, xs, ns, hs, npair, (const uint32_t*)ctx->dep_slot.p,
+                        (const uint32_t*)ctx->dep_off.p, (uint32_t*)ctx->dep_pj_a.p,
+                        (uint32_t*)ctx->dep_ps_a.p, s);
     CRK_HIP(radix_sort_pairs((uint32_t*)ctx->dep_pj_a.p, (uint32_t*)ctx->dep_ps_a.p,
                              (uint32_t*)ctx->dep_pj_b.p, (uint32_t*)ctx->dep_ps_b.p, np,
                              bits_for(ng), (uint32_t*)ctx->dep_ptmp.p, s),
@@ -1224,7 +1227,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
-                &c->dep_p4, &c->dep_pv, &c->dep_sp,
+                &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);

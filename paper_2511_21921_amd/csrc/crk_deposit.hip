@@ -14,8 +14,9 @@
 // a large h_s costs only itself. Cells along x are adjacent in the sorted
 // order, so each row of the stencil is one or two contiguous ranges that
 // the wave's lanes share. The normalisation pass counts each source's
-// receivers; a second traversal writes the (gas, source) pairs in source
-// order, a stable sort by gas index groups them, and each gas particle sums
+// receivers and keeps the first 64 of them; the (gas, source) pairs are then
+// written in source order (a source with more receivers walks its cells
+// again), a stable sort by gas index groups them, and each gas particle sums
 // its contributions in source order. No float atomics: results are
 // reproducible. Arithmetic is FP64.
 #include "crk_passes.h"
@@ -271,38 +272,48 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// receivers kept per source by the normalisation pass (more: the pair pass
+// walks that source's cells again)
+constexpr int kSlot = 64;
+
 // A_s and the number of receivers of every source; the largest h_s (double
 // bits, CNT_HMAX_OUT_BITS) and the total receiver count (CNT_PAIRS_GATHER).
+// The first kSlot receivers (gas caller index) go to the source's slot, in
+// traversal order.
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock)
     k_dep_norm(PointGrid gas, const double* __restrict__ xs,
                int64_t ns, const R* __restrict__ hs, const R* __restrict__ dM,
                const R* __restrict__ dMZ, const R* __restrict__ dE, const R* __restrict__ vs,
                R* __restrict__ As, double4* __restrict__ sp, uint32_t* __restrict__ npair,
-               unsigned long long* __restrict__ cnt) {
+               uint32_t* __restrict__ slot, unsigned long long* __restrict__ cnt) {
   const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (s >= ns) return;  // whole waves
   const double h = (double)hs[s];
+  const int lane = threadIdx.x & 63;
   double sum = 0.0;
-  uint32_t c = 0;
+  uint32_t c = 0;  // receivers so far (the same in every lane)
+  uint32_t* my_slot = slot + s * kSlot;
   // beyond half the box the nearest image is not unique: the host rejects
   // the call, and the search here is skipped
   const double sx = xs[s], sy = xs[ns + s], sz = xs[2 * ns + s];
   const double inv_h = 1.0 / h;
   if (h > 0.0 && h < 0.5 * gas.box)
     wave_near(gas, sx, sy, sz, h, [&](uint32_t q, bool valid) {
-      if (!valid) return;
-      const double r2 = min_image2(sx, sy, sz, gas.p4[q], gas);
-      const double V = gas.pv[q].x;
-      if (r2 < h * h && V >= 0.0) {
-        sum += V * kernel_W_inv<K>(sqrt(r2), inv_h);
-        ++c;
+      bool in = false;
+      if (valid) {
+        const double r2 = min_image2(sx, sy, sz, gas.p4[q], gas);
+        const double V = gas.pv[q].x;
+        in = r2 < h * h && V >= 0.0;
+        if (in) sum += V * kernel_W_inv<K>(sqrt(r2), inv_h);
       }
+      const unsigned long long m = __ballot(in);
+      const uint32_t at = c + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (in && at < (uint32_t)kSlot) my_slot[at] = gas.perm[q];
+      c += (uint32_t)__popcll(m);
     });
   sum = wave_sum(sum);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0) {
+  if (lane == 0) {
     const bool on = sum > 0.0;
     const R A = (R)(on ? 1.0 / sum : 0.0);
     As[s] = A;
@@ -322,21 +333,29 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// writes each source's receivers (gas index, source index) at its offset,
-// in the order of the traversal of k_dep_norm
+// writes each source's receivers (gas index, source index) at its offset, in
+// the traversal order of k_dep_norm: copied from the source's slot, or, for
+// a source with more than kSlot receivers, found by the same traversal
 template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_dep_pairs(PointGrid gas, const double* __restrict__ xs,
                 int64_t ns, const R* __restrict__ hs, const uint32_t* __restrict__ npair,
-                const uint32_t* __restrict__ off, uint32_t* __restrict__ pj,
-                uint32_t* __restrict__ ps) {
+                const uint32_t* __restrict__ slot, const uint32_t* __restrict__ off,
+                uint32_t* __restrict__ pj, uint32_t* __restrict__ ps) {
   const int64_t s = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (s >= ns) return;  // whole waves
   const uint32_t c = npair[s];
   if (c == 0) return;
-  const double h = (double)hs[s];
   const uint32_t o = off[s];
   const int lane = threadIdx.x & 63;
+  if (c <= (uint32_t)kSlot) {
+    if ((uint32_t)lane < c) {
+      pj[o + lane] = slot[s * kSlot + lane];
+      ps[o + lane] = (uint32_t)s;
+    }
+    return;
+  }
+  const double h = (double)hs[s];
   uint32_t t = 0;  // pairs written so far (the same in every lane)
   const double sx = xs[s], sy = xs[ns + s], sz = xs[2 * ns + s];
   wave_near(gas, sx, sy, sz, h, [&](uint32_t q, bool valid) {
@@ -429,21 +448,21 @@ void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t n
 template <class R>
 void launch_dep_norm(int kernel, const DepGrid& d, const double* xs, int64_t ns, const R* hs,
                      const R* dM, const R* dMZ, const R* dE, const R* vs, R* As, void* sp,
-                     uint32_t* npair, unsigned long long* cnt, hipStream_t s) {
+                     uint32_t* npair, uint32_t* slot, unsigned long long* cnt, hipStream_t s) {
   PointGrid g{d.G, d.box, 1.0 / d.box, d.hmax, d.start, d.perm, (const double4*)d.p4,
               (const double2*)d.pv};
   CRK_DEP_DISPATCH(kernel, k_dep_norm, ns * 64, g, xs, ns, hs, dM, dMZ, dE, vs, As,
-                   (double4*)sp, npair, cnt);
+                   (double4*)sp, npair, slot, cnt);
 }
 
 template <class R>
 void launch_dep_pairs(const DepGrid& d, const double* xs, int64_t ns, const R* hs,
-                      const uint32_t* npair, const uint32_t* off, uint32_t* pj, uint32_t* ps,
-                      hipStream_t s) {
+                      const uint32_t* npair, const uint32_t* slot, const uint32_t* off,
+                      uint32_t* pj, uint32_t* ps, hipStream_t s) {
   PointGrid g{d.G, d.box, 1.0 / d.box, d.hmax, d.start, d.perm, (const double4*)d.p4,
               (const double2*)d.pv};
   hipLaunchKernelGGL(k_dep_pairs<R>, dim3(grid_for(ns * 64)), dim3(kBlock), 0, s, g, xs, ns, hs,
-                     npair, off, pj, ps);
+                     npair, slot, off, pj, ps);
 }
 
 template <class R>
@@ -463,10 +482,10 @@ void launch_dep_apply(int kernel, const double* xg, int64_t ng, const R* Vg, R* 
                                      double, R*, R*, hipStream_t);                             \
   template void launch_dep_norm<R>(int, const DepGrid&, const double*, int64_t, const R*,     \
                                    const R*, const R*, const R*, const R*, R*, void*,          \
-                                   uint32_t*, unsigned long long*, hipStream_t);               \
+                                   uint32_t*, uint32_t*, unsigned long long*, hipStream_t);    \
   template void launch_dep_pairs<R>(const DepGrid&, const double*, int64_t, const R*,         \
-                                    const uint32_t*, const uint32_t*, uint32_t*, uint32_t*,    \
-                                    hipStream_t);                                              \
+                                    const uint32_t*, const uint32_t*, const uint32_t*,         \
+                                    uint32_t*, uint32_t*, hipStream_t);                        \
   template void launch_dep_apply<R>(int, const double*, int64_t, const R*, R*, R*, R*, R*,    \
                                     const void*, const uint32_t*, const uint32_t*, double,     \
                                     hipStream_t);

@@ -161,11 +161,11 @@ void launch_dep_volume(int kernel, const DepGrid& d, const double* xs, int64_t n
 template <class R>
 void launch_dep_norm(int kernel, const DepGrid& d, const double* xs, int64_t ns, const R* hs,
                      const R* dM, const R* dMZ, const R* dE, const R* vs, R* As, void* sp,
-                     uint32_t* npair, unsigned long long* cnt, hipStream_t s);
+                     uint32_t* npair, uint32_t* slot, unsigned long long* cnt, hipStream_t s);
 template <class R>
 void launch_dep_pairs(const DepGrid& d, const double* xs, int64_t ns, const R* hs,
-                      const uint32_t* npair, const uint32_t* off, uint32_t* pj, uint32_t* ps,
-                      hipStream_t s);
+                      const uint32_t* npair, const uint32_t* slot, const uint32_t* off,
+                      uint32_t* pj, uint32_t* ps, hipStream_t s);
 template <class R>
 void launch_dep_apply(int kernel, const double* xg, int64_t ng, const R* Vg, R* mg, R* vg, R* mZg,
                       R* ug, const void* sp, const uint32_t* first, const uint32_t* ps, double box,
