@@ -236,3 +236,31 @@ def test_deep_hierarchy_sixteen_substeps():
         assert val <= STATE_BOUND[FP64], (k, val)
     for k, b in FP64_BOUNDS.items():
         assert e[k] <= b, (k, e[k], b)
+
+
+def test_big_step_with_relaxation():
+    # relaxation on (exp(|div v| dt_relax) > 8): passive particles take their
+    # flag from the stored grad v, active ones from the new evaluation
+    ps = _start(1500, 318)
+    print("case random1500 levels 0-2 relaxation FP64", flush=True)
+    dt, lam = 2e-4, 0.5
+    lev = np.random.default_rng(319).integers(0, 3, ps.n)
+    lev[0] = 2
+    p = oracle.params_for(ps, dt_relax=3.0)
+    ctx = Context(_gpu.params_for(ps, FP64, dt_relax=3.0))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam, stats=True)
+    torch.cuda.synchronize()
+    prev = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p)
+    assert 0 < prev["relaxed"] < ps.n
+    o = oracle.hkdk_step(ps.x, ps.v, ps.m, ps.u, ps.h, prev, lev, p, dt, lam)
+    st = _state_errors(x, v, u, out, o)
+    g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+    e = _gpu.errors(g, o, o["h"])
+    print({k: "%.2e" % val for k, val in st.items()}, out["stats"]["relaxed"], flush=True)
+    for k, val in st.items():
+        assert val <= STATE_BOUND[FP64], (k, val)
+    for k, b in FP64_BOUNDS.items():
+        assert e[k] <= b, (k, e[k], b)
