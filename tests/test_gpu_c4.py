@@ -46,3 +46,13 @@ def test_c4_268_adjoint(precision, tol):
     print("case C4 n_h=4 n=%d precision=%d" % (ps.n, precision), flush=True)
     g, _ = _grad(ps, precision, kernel=WENDLAND_C4)
     _check_jvps(ps, g, tol, nbr=1, kernel=WENDLAND_C4)
+
+
+def test_c4_268_forward_at_full_size():
+    # the bench's C4 configuration: sedov64_v at n_h = 4 (262,144 particles,
+    # ~268 neighbours), FP32 against the oracle with its grid search
+    ps = synth.at_resolution(synth.sedov64_v(), 4.0)
+    print("case sedov64_v C4 n_h=4 FP32", flush=True)
+    g, o, _ = _compare(ps, FP32, C4_FP32_BOUNDS, nbr=1, kernel=WENDLAND_C4)
+    assert abs(g["stats"]["n_pairs_force"] - o["pairs_force"]) <= 1e-6 * o["pairs_force"]
+    assert g["stats"]["h_unconverged"] == 0
