@@ -75,7 +75,7 @@ struct crk_ctx {
              *hl_B = nullptr, *hl_gA = nullptr, *hl_gB = nullptr;
   // cooling table: lam at the nodes, per-bin slope, prefix integrals within
   // each run of same-sign bins, each bin's run (int2), per-bin integrals
-  Buf cool_lam, cool_slope, cool_c, cool_G, cool_run, cool_binint;
+  Buf cool_lam, cool_oma, cool_co, cool_G, cool_run, cool_binint;
   int cool_K = 0;
   double cool_lu0 = 0.0, cool_dex = 0.0;
   // subgrid deposition: one sorted point grid at a time and its counters
@@ -1223,7 +1223,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
                 &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
                 &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need,
-                &c->cool_lam, &c->cool_slope, &c->cool_c, &c->cool_G, &c->cool_run, &c->cool_binint,
+                &c->cool_lam, &c->cool_oma, &c->cool_co, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
@@ -1387,14 +1387,14 @@ crk_status crk_cooling_table(crk_ctx* ctx, void* hip_stream, int K, double log10
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t kk = (size_t)K;
   CRK_HIP(ensure(ctx->cool_lam, 8 * kk), "cooling table");
-  CRK_HIP(ensure(ctx->cool_slope, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_oma, 8 * kk), "cooling table");
   CRK_HIP(ensure(ctx->cool_G, 8 * kk), "cooling table");
   CRK_HIP(ensure(ctx->cool_run, 8 * kk), "cooling table");
   CRK_HIP(ensure(ctx->cool_binint, 8 * kk), "cooling table");
-  CRK_HIP(ensure(ctx->cool_c, 8 * kk), "cooling table");
+  CRK_HIP(ensure(ctx->cool_co, 8 * kk), "cooling table");
   CRK_HIP(hipMemcpyAsync(ctx->cool_lam.p, lam, 8 * kk, hipMemcpyHostToDevice, s), "cooling table");
-  launch_cool_prepare(K, log10_u0, dex, (const double*)ctx->cool_lam.p, (double*)ctx->cool_slope.p,
-                      (double*)ctx->cool_c.p, (double*)ctx->cool_G.p, ctx->cool_run.p,
+  launch_cool_prepare(K, log10_u0, dex, (const double*)ctx->cool_lam.p, (double*)ctx->cool_oma.p,
+                      (double*)ctx->cool_co.p, (double*)ctx->cool_G.p, ctx->cool_run.p,
                       (double*)ctx->cool_binint.p, s);
   CRK_HIP(hipGetLastError(), "cooling table launch");
   // the host copy of lam is read by the copy above: finish it before returning
@@ -1418,12 +1418,12 @@ crk_status crk_cool(crk_ctx* ctx, void* hip_stream, long long n, double dt, cons
   CRK_HIP(tbegin(ctx, P_COOL, s), "event");
   if (ctx->p.precision == CRK_FP64)
     launch_cool<double>(ctx->cool_K, ctx->cool_lu0, ctx->cool_dex, (const double*)ctx->cool_lam.p,
-                        (const double*)ctx->cool_c.p, (const double*)ctx->cool_slope.p,
+                        (const double*)ctx->cool_co.p, (const double*)ctx->cool_oma.p,
                         (const double*)ctx->cool_G.p, ctx->cool_run.p, n, dt, (const double*)rho,
                         (double*)u, s);
   else
     launch_cool<float>(ctx->cool_K, ctx->cool_lu0, ctx->cool_dex, (const double*)ctx->cool_lam.p,
-                       (const double*)ctx->cool_c.p, (const double*)ctx->cool_slope.p,
+                       (const double*)ctx->cool_co.p, (const double*)ctx->cool_oma.p,
                        (const double*)ctx->cool_G.p, ctx->cool_run.p, n, dt, (const float*)rho,
                        (float*)u, s);
   CRK_HIP(tend(ctx, P_COOL, s), "event");

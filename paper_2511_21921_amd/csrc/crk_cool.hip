@@ -27,13 +27,17 @@ namespace {
 
 constexpr double kLn10 = 2.302585092994045684;
 
+// Per power-law bin k with slope a_k and c_k = u_k / lam_k (the in-bin integral
+// is c_k ln(u / u_k) for a_k = 1, else c_k expm1((1 - a_k) ln(u / u_k)) / (1 - a_k))
+// the table holds oma_k = 1 - a_k and co_k = c_k / oma_k (c_k where oma_k = 0),
+// so that the integral and its inverse need no division but the last one.
 struct CoolTab {
   int K;
-  double lu0, dex;
+  double lu0, dex, inv_dex;
   double u_lo, u_hi;    // the first and last node energies
   const double* lam;    // [K]
-  const double* c;      // [K - 1] u_k / lam_k of each power-law bin (0 for a sign-change bin)
-  const double* slope;  // [K - 1] power-law slope of each bin (0 for a sign-change bin)
+  const double* co;     // [K - 1] c_k / (1 - a_k), or c_k (0 for a sign-change bin)
+  const double* oma;    // [K - 1] 1 - a_k (0 for a sign-change bin)
   const double* G;      // [K] prefix integral within the node's run (see above)
   const int2* run;      // [K - 1] first and last bin of the bin's run ({-1, -1}: sign change)
 };
@@ -47,21 +51,28 @@ __device__ inline double node_u(const CoolTab& T, int k) {
 }
 
 __device__ inline int bin_of(const CoolTab& T, double lg) {
-  int k = (int)floor((lg - T.lu0) / T.dex);
+  int k = (int)floor((lg - T.lu0) * T.inv_dex);
   return k < 0 ? 0 : (k > T.K - 2 ? T.K - 2 : k);
 }
 
 // int from u_k to u of du / lam inside power-law bin k, l = ln(u / u_k)
 __device__ inline double in_bin(const CoolTab& T, int k, double l) {
-  const double a = T.slope[k], c = T.c[k];
-  return a == 1.0 ? c * l : c * expm1((1.0 - a) * l) / (1.0 - a);
+  const double oma = T.oma[k], co = T.co[k];
+  return oma == 0.0 ? co * l : co * expm1(oma * l);
 }
 
-// u in power-law bin k with int from u_k to u of du / lam = g
+// u in power-law bin k with int from u_k to u of du / lam = g:
+// ln(u / u_k) = g / c_k, or log1p(g (1 - a_k) / c_k) / (1 - a_k)
 __device__ inline double in_bin_inverse(const CoolTab& T, int k, double g) {
-  const double a = T.slope[k], y = g / T.c[k];
-  const double t = a == 1.0 ? y : log1p((1.0 - a) * y) / (1.0 - a);
+  const double oma = T.oma[k], y = g / T.co[k];
+  const double t = oma == 0.0 ? y : log1p(y) / oma;
   return exp(node_lnu(T, k) + t);
+}
+
+// lam > 0 in power-law bin k (c_k has the sign of lam_k)
+__device__ inline bool bin_cools(const CoolTab& T, int k) {
+  const double oma = T.oma[k], co = T.co[k];
+  return (oma == 0.0 ? co : co * oma) > 0.0;
 }
 
 // Sign-change bin k: returns u and sets left (rho t still to integrate).
@@ -94,7 +105,7 @@ __device__ inline double cool_phase(const CoolTab& T, double u, double& left) {
   const int k = bin_of(T, lg);
   const int2 run = T.run[k];
   if (run.x < 0) return equilibrium_bin(T, k, u, left);
-  const bool cooling = T.c[k] > 0.0;
+  const bool cooling = bin_cools(T, k);
   // G(u^1) = G(u^0) - rho dt; G rises with u where lam > 0, falls where lam < 0
   const double l = kLn10 * (lg - T.lu0 - (double)k * T.dex);
   const double target = T.G[k] + in_bin(T, k, l) - left;
@@ -145,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_cool(CoolTab T, int64_t n, double dt
 // The same with the per-bin table copied into LDS once per block (persistent
 // blocks striding over the particles): the bin lookup and the binary search
 // read LDS instead of waiting on the L2 at every dependent step. The table
-// takes 32 bytes per node (c, slope, G, run); lam, read only in sign-change
+// takes 32 bytes per node (co, oma, G, run); lam, read only in sign-change
 // bins, stays in global memory.
 constexpr int kCoolBlock = 1024;
 
@@ -155,22 +166,22 @@ __global__ void __launch_bounds__(kCoolBlock) k_cool_lds(CoolTab Tg, int64_t n, 
                                                          R* __restrict__ u) {
   extern __shared__ double table[];
   const int K = Tg.K;
-  double* c = table;
-  double* slope = c + K;
-  double* G = slope + K;
+  double* co = table;
+  double* oma = co + K;
+  double* G = oma + K;
   int2* run = (int2*)(G + K);
   for (int k = threadIdx.x; k < K; k += kCoolBlock) {
     G[k] = Tg.G[k];
     if (k < K - 1) {
-      c[k] = Tg.c[k];
-      slope[k] = Tg.slope[k];
+      co[k] = Tg.co[k];
+      oma[k] = Tg.oma[k];
       run[k] = Tg.run[k];
     }
   }
   __syncthreads();
   CoolTab T = Tg;
-  T.c = c;
-  T.slope = slope;
+  T.co = co;
+  T.oma = oma;
   T.G = G;
   T.run = run;
   for (int64_t i = (int64_t)blockIdx.x * kCoolBlock + threadIdx.x; i < n;
@@ -178,24 +189,27 @@ __global__ void __launch_bounds__(kCoolBlock) k_cool_lds(CoolTab Tg, int64_t n, 
     cool_one(T, i, dt, rho, u);
 }
 
-// Table preparation, one block: slopes, c = u_k / lam_k and runs per bin,
-// then the prefix integrals within every run (run starts get G = 0).
+// Table preparation, one block: slope a_k and c_k = u_k / lam_k per bin, kept
+// as oma_k = 1 - a_k and co_k, and the runs; then the prefix integrals within
+// every run (run starts get G = 0).
 __global__ void __launch_bounds__(kBlock) k_cool_prepare(int K, double lu0, double dex,
                                                          const double* __restrict__ lam,
-                                                         double* __restrict__ slope,
-                                                         double* __restrict__ c,
+                                                         double* __restrict__ oma,
+                                                         double* __restrict__ co,
                                                          double* __restrict__ G,
                                                          int2* __restrict__ run,
                                                          double* __restrict__ binint) {
-  CoolTab T{K, lu0, dex, 0.0, 0.0, lam, c, slope, G, run};
+  CoolTab T{K, lu0, dex, 1.0 / dex, 0.0, 0.0, lam, co, oma, G, run};
   for (int k = threadIdx.x; k < K - 1; k += kBlock) {
     const double lk = lam[k], lk1 = lam[k + 1];
     if (lk * lk1 > 0.0) {
-      slope[k] = log(lk1 / lk) / (kLn10 * dex);
-      c[k] = node_u(T, k) / lk;
+      const double om = 1.0 - log(lk1 / lk) / (kLn10 * dex);
+      const double c = node_u(T, k) / lk;
+      oma[k] = om;
+      co[k] = om == 0.0 ? c : c / om;
     } else {
-      slope[k] = 0.0;
-      c[k] = 0.0;
+      oma[k] = 0.0;
+      co[k] = 0.0;
     }
   }
   __syncthreads();
@@ -233,18 +247,18 @@ __global__ void __launch_bounds__(kBlock) k_cool_prepare(int K, double lu0, doub
 
 }  // namespace
 
-void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
-                         double* c, double* G, void* run, double* binint, hipStream_t s) {
-  hipLaunchKernelGGL(k_cool_prepare, dim3(1), dim3(kBlock), 0, s, K, lu0, dex, lam, slope, c, G,
+void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* oma,
+                         double* co, double* G, void* run, double* binint, hipStream_t s) {
+  hipLaunchKernelGGL(k_cool_prepare, dim3(1), dim3(kBlock), 0, s, K, lu0, dex, lam, oma, co, G,
                      (int2*)run, binint);
 }
 
 template <class R>
-void launch_cool(int K, double lu0, double dex, const double* lam, const double* c,
-                 const double* slope, const double* G, const void* run, int64_t n, double dt,
+void launch_cool(int K, double lu0, double dex, const double* lam, const double* co,
+                 const double* oma, const double* G, const void* run, int64_t n, double dt,
                  const R* rho, R* u, hipStream_t s) {
   const double u_lo = std::pow(10.0, lu0), u_hi = std::pow(10.0, lu0 + (K - 1) * dex);
-  CoolTab T{K, lu0, dex, u_lo, u_hi, lam, c, slope, G, (const int2*)run};
+  CoolTab T{K, lu0, dex, 1.0 / dex, u_lo, u_hi, lam, co, oma, G, (const int2*)run};
   const size_t lds = 32 * (size_t)K;
   if (lds <= 65536) {
     // two blocks of 1024 per compute unit over the 256 units, or fewer

@@ -172,11 +172,11 @@ void launch_dep_apply(int kernel, const double* xg, int64_t ng, const R* Vg, R* 
                       hipStream_t s);
 
 // exact-integration cooling (caller order, elementwise); run holds int2 per bin
-void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* slope,
-                         double* c, double* G, void* run, double* binint, hipStream_t s);
+void launch_cool_prepare(int K, double lu0, double dex, const double* lam, double* oma,
+                         double* co, double* G, void* run, double* binint, hipStream_t s);
 template <class R>
-void launch_cool(int K, double lu0, double dex, const double* lam, const double* c,
-                 const double* slope, const double* G, const void* run, int64_t n, double dt,
+void launch_cool(int K, double lu0, double dex, const double* lam, const double* co,
+                 const double* oma, const double* G, const void* run, int64_t n, double dt,
                  const R* rho, R* u, hipStream_t s);
 
 }  // namespace crk
