@@ -12,14 +12,14 @@ passive V and rho; measured <= 2.5e-6). A wrong passive state shows at
 1e-3 and above. Also:
 all levels 0 is crk_kdk_step and one level L everywhere is 2^L single-level
 steps of dt / 2^L (up to the rounding of the two h-update forms), in FP64
-and FP32, and the argument errors.
+and FP32; one big step with the Wendland C4 kernel (FP64); the argument errors.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from paper_2511_21921_amd import FP32, FP64, Context, CrkError
+from paper_2511_21921_amd import FP32, FP64, WENDLAND_C4, Context, CrkError
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,38 @@ def test_two_big_steps_match_the_oracle(precision):
             assert val <= STATE_BOUND[precision], (it, k, val)
         for k, b in bounds.items():
             assert e[k] <= b, (it, k, e[k], b)
+
+
+def test_big_step_with_the_wendland_c4_kernel():
+    # the hierarchy's instances of the passes for the C4 kernel, ~100
+    # neighbours, h solved with that kernel before the step; FP64
+    ps = synth.random_small(2000, 321, n_ngb=100.0, mass_spread=0.1)
+    ps.h = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h,
+                          oracle.params_for(ps, kernel=WENDLAND_C4))["h"]
+    ps.h_mode = 0
+    print("case random2000 C4 levels 0-2 FP64", flush=True)
+    dt, lam = 2e-4, 0.5
+    lev = np.random.default_rng(322).integers(0, 3, ps.n)
+    lev[0] = 2
+    p = oracle.params_for(ps, kernel=WENDLAND_C4)
+    ctx = Context(_gpu.params_for(ps, FP64, kernel=WENDLAND_C4))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    prev = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p)
+    out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam, stats=True)
+    torch.cuda.synchronize()
+    o = oracle.hkdk_step(ps.x, ps.v, ps.m, ps.u, ps.h, prev, lev, p, dt, lam,
+                         trace=_Progress())
+    st = _state_errors(x, v, u, out, o)
+    g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+    e = _gpu.errors(g, o, o["h"])
+    print({k: "%.2e" % val for k, val in st.items()},
+          {k: "%.2e" % val for k, val in e.items()}, flush=True)
+    for k, val in st.items():
+        assert val <= STATE_BOUND[FP64], (k, val)
+    for k, b in FP64_BOUNDS.items():
+        assert e[k] <= b, (k, e[k], b)
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
