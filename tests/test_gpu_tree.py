@@ -4,13 +4,13 @@ The tree path (Morton-ordered 64-particle leaves over a 1024^3 lattice) must
 give the same results as the cell-list path and the oracle: the same bounds
 as test_gpu_forward.py, forced on uniform inputs and chosen automatically on
 Plummer-clump inputs whose smoothing lengths span more than an order of
-magnitude.
+magnitude; with the cubic spline and with the Wendland C4 kernel.
 """
 import numpy as np
 import pytest
 
 import synth
-from paper_2511_21921_amd import FP32, FP64
+from paper_2511_21921_amd import FP32, FP64, WENDLAND_C4
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,23 @@ def test_clustered_switches_to_tree_and_matches_oracle(precision):
     print("h range %.1f, grid %d" % (hr, g["stats"]["grid"]))
     assert hr > 30
     assert g["stats"]["grid"] == 1024          # automatic choice of the tree path
+    assert g["stats"]["h_unconverged"] == 0
+    if precision == FP64:
+        assert g["stats"]["n_pairs_force"] == o["pairs_force"]
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_tree_with_the_wendland_c4_kernel(precision):
+    # the tree search's instances for the C4 kernel: forced on a random set
+    # at ~84 neighbours, and chosen automatically on Plummer clumps
+    from tests.test_gpu_c4 import C4_FP32_BOUNDS
+    bounds = FP64_BOUNDS if precision == FP64 else C4_FP32_BOUNDS
+    ps = synth.random_small(3001, 64, n_ngb=100.0, mass_spread=0.1)
+    g, _, _ = _compare(ps, precision, bounds, search=TREE, kernel=WENDLAND_C4)
+    assert g["stats"]["grid"] == 1024
+    ps = _clumps(20000, 8, 62)
+    g, o, _ = _compare(ps, precision, bounds, nbr=1, kernel=WENDLAND_C4)
+    assert g["stats"]["grid"] == 1024
     assert g["stats"]["h_unconverged"] == 0
     if precision == FP64:
         assert g["stats"]["n_pairs_force"] == o["pairs_force"]
