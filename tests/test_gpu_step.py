@@ -7,14 +7,15 @@ keeps v, u and h in the working precision and x in FP64, like the oracle.
 Bounds: FP64 1e-11 (relative, positions absolute in box units); FP32 the
 single-evaluation bounds of the forward parity tests, plus 2e-6 on the state
 (one FP32 rounding of v^1/2, u^1/2 and h per step, and the FP32 V and grad v
-that feed the smoothing-length rate).
+that feed the smoothing-length rate). The same in FP64 with the Wendland C4
+kernel.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from paper_2511_21921_amd import FP32, FP64, Context, CrkError
+from paper_2511_21921_amd import FP32, FP64, WENDLAND_C4, Context, CrkError
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +75,40 @@ def test_three_steps_match_the_oracle(precision):
             assert e[k] <= b, (it, k, e[k], b)
     # after the first step the geometry of the previous evaluation usually holds
     assert sum(spec) >= 1
+
+
+def test_steps_with_the_wendland_c4_kernel():
+    # the same three steps with the C4 kernel at ~84 neighbours (h solved
+    # with that kernel first), FP64
+    ps = synth.random_small(2000, 331, n_ngb=100.0, mass_spread=0.1)
+    p = oracle.params_for(ps, kernel=WENDLAND_C4)
+    ps.h = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p)["h"]
+    ps.h_mode = 0
+    print("case random2000 C4 FP64", flush=True)
+    dt, lam = 2e-4, 0.5
+    p = oracle.params_for(ps, kernel=WENDLAND_C4)
+    ctx = Context(_gpu.params_for(ps, FP64, kernel=WENDLAND_C4))
+    x, v, m, u, h = _gpu.to_dev(ps, FP64)
+    out = ctx.forward(x, v, m, u, h)
+    ox, ov, ou, oh = ps.x.copy(), ps.v.copy(), ps.u.copy(), ps.h.copy()
+    prev = oracle.forward(ox, ov, ps.m, ou, oh, p)
+    for it in range(3):
+        out = ctx.kdk_step(x, v, m, u, out, dt, lam)
+        torch.cuda.synchronize()
+        o = oracle.kdk_step(ox, ov, ps.m, ou, oh, prev, p, dt, lam)
+        ox, ov, ou, oh, prev = o["x"], o["v"], o["u"], o["h"], o
+        dx = np.abs(_np(x) - ox)
+        dx = np.minimum(dx, 1.0 - dx)
+        st = {"x": dx.max(), "v": np.abs(_np(v) - ov).max() / np.abs(ov).max(),
+              "u": np.max(np.abs(_np(u) / ou - 1)), "h": np.max(np.abs(_np(out["h"]) / oh - 1))}
+        g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+        e = _gpu.errors(g, o, o["h"])
+        print("step", it, {k: "%.2e" % val for k, val in st.items()},
+              {k: "%.2e" % val for k, val in e.items()}, flush=True)
+        for k, val in st.items():
+            assert val <= STATE_BOUND[FP64], (it, k, val)
+        for k, b in FP64_BOUNDS.items():
+            assert e[k] <= b, (it, k, e[k], b)
 
 
 def test_steps_conserve_momentum_and_track_energy():
