@@ -141,6 +141,31 @@ def test_reproducing_conditions(oracle_lib, h_mode):
             assert np.abs(sxg + (1.0 if a == g else 0.0)).max() < 1e-11
 
 
+@pytest.mark.parametrize("h_mode", [0, 1])
+def test_density_off_lattice(oracle_lib, h_mode):
+    """Sec. 2.5.1 eq. (rhow): rho_i = sum_j m_j V_j W^R_ij / sum_j V_j^2 W^R_ij, self included,
+    evaluated here with the textbook kernel of _pins and the oracle's V, A, B (pinned by the
+    volume and reproducing-condition tests) on random, unequal-mass particles, where W in
+    place of W^R, or a dropped V_j, give visibly different densities."""
+    ps = synth.random_small(400, 7, mass_spread=0.3, h_mode=h_mode)
+    o = oracle_lib.forward(ps.x, ps.v, ps.m, ps.u, ps.h, oracle_lib.params_for(ps))
+    lists = oracle_lib.neighbours(ps.x, o["h"], kind=0, lists=True)
+    ii, jj, d = _pins.pair_table(ps.x, lists, 1.0)
+    r = np.sqrt((d ** 2).sum(0))
+    assert np.all(r[ii == jj] == 0) and np.sum(ii == jj) == ps.n  # self terms listed once
+    Wv = _pins.W(r, o["h"][ii])
+    WR = o["A"][ii] * (1 + (o["B"][:, ii] * d).sum(0)) * Wv
+    Vj, mj = o["V"][jj], ps.m[jj]
+    n = ps.n
+    rho = np.bincount(ii, mj * Vj * WR, n) / np.bincount(ii, Vj * Vj * WR, n)
+    assert np.abs(rho / o["rho"] - 1).max() < 1e-12
+    # the pin separates the readings a slip would give
+    rho_w = np.bincount(ii, mj * Vj * Wv, n) / np.bincount(ii, Vj * Vj * Wv, n)
+    rho_nov = np.bincount(ii, mj * WR, n) / np.bincount(ii, Vj * WR, n)
+    assert np.abs(rho_w / o["rho"] - 1).max() > 1e-2
+    assert np.abs(rho_nov / o["rho"] - 1).max() > 1e-2
+
+
 def test_velocity_gradient_exact_for_linear_field(oracle_lib):
     """grad v (App. A.1 eq. gradv) is exact for v = v0 + M x (linear reproduction, Sec. 2.1)."""
     ps = synth.sedov(12, k=9)
