@@ -118,11 +118,15 @@ void crk_default_params(crk_params *p, int precision);
  * kernel and precision in range). Allocates nothing on the device. */
 crk_status crk_create(crk_ctx **ctx, const crk_params *p);
 
-/* Replaces the parameters of an existing context. */
+/* Replaces the parameters of an existing context. A change of any field
+ * other than timing and check_finite drops the state kept for crk_backward
+ * (a following crk_backward returns CRK_EINVAL until the next forward), so
+ * an adjoint is always taken with the parameters of its forward. */
 crk_status crk_set_params(crk_ctx *ctx, const crk_params *p);
 
 /* Pre-allocates device workspace for up to n_max particles so that later
- * calls with n <= n_max allocate only if a neighbour list outgrows it. */
+ * calls with n <= n_max allocate only if a neighbour list outgrows it. When
+ * this grows a buffer the forward state kept for crk_backward is dropped. */
 crk_status crk_reserve(crk_ctx *ctx, long long n_max);
 
 /* Releases the context and all workspace it owns. NULL is accepted. */
@@ -154,7 +158,10 @@ const char *crk_last_error(const crk_ctx *ctx);
  * root), it runs again the careful way. Either way the outputs are the same.
  * n = 0 is a no-op returning CRK_OK. Input and output arrays must not
  * overlap. The context keeps the cell list, neighbour list and the sorted
- * intermediates for a following crk_backward. */
+ * intermediates for a following crk_backward. After a status other than
+ * CRK_OK, CRK_ENOTCONV and CRK_ENONFINITE the output arrays (h included)
+ * are undefined: a speculative attempt may have written them before the
+ * failing check. Non-finite positions are rejected with CRK_EINVAL. */
 crk_status crk_forward(crk_ctx *ctx, void *hip_stream, long long n, const double *x,
                        const void *v, const void *m, const void *u, void *h, void *V,
                        void *rho, void *A, void *B, void *gradA, void *gradB, void *gradv,

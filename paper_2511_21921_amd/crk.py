@@ -180,6 +180,7 @@ class Context:
         cp = params.to_c()
         self._raise(lib().crk_set_params(self._h, C.byref(cp)))
         self.params, self._cp = params, cp
+        self.generation += 1  # the library drops the kept state when a parameter changed
 
     def reserve(self, n: int):
         self._raise(lib().crk_reserve(self._h, int(n)))

@@ -557,7 +557,7 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   *accepted = false;
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-  launch_check_inputs<R>(h, m, u, n, dcnt, s);
+  launch_check_inputs<R>(x, h, m, u, n, dcnt, s);
   ctx->G = ctx->spec_G;
   ctx->ell = P.box / ctx->G;
   ctx->lattice = 0;
@@ -660,11 +660,11 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   ctx->spec_ok = false;
   if (!accepted) {
     CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-    launch_check_inputs<R>(h, m, u, n, dcnt, s);
+    launch_check_inputs<R>(x, h, m, u, n, dcnt, s);
     CRK_HIP(hipGetLastError(), "input check launch");
     CRK_HIP(read_counters(ctx, s), "input check");
     if (ctx->host_cnt[CNT_BAD_INPUT])
-      return fail(ctx, CRK_EINVAL, "h, m and u must be finite and > 0");
+      return fail(ctx, CRK_EINVAL, "x must be finite; h, m and u finite and > 0");
     const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
     {
       // all masses equal (to rounding) => m_j / m_i = 1 needs no storage
@@ -830,7 +830,9 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   ctx->n_last = n;
   ctx->precision_last = P.precision;
   crk_status result = CRK_OK;
-  if (stats || P.check_finite) {
+  {
+    // the h-solve counters are always on the host (read after the solve, or
+    // by the speculative forward's end-of-call read)
     const unsigned long long* hc = ctx->host_cnt;
     if (stats) {
       stats->n_pairs_gather = (long long)hc[CNT_PAIRS_GATHER];
@@ -855,37 +857,68 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   return result;
 }
 
+// The adjoint workspace of n particles (Real of RS bytes): the arrays of
+// AdjState in declaration order (gx, gv, gu, gh, gV, gkc, gab, wgt4, gvc4,
+// mom4, kap), each 256-byte aligned. Writes the offsets, returns the total.
+constexpr int kAdjArrays = 11;
+constexpr size_t adj_layout(int64_t n, size_t RS, size_t* off) {
+  const size_t N = (size_t)(((n + 63) / 64) * 64);
+  const size_t blocks = (size_t)((n + kBlock - 1) / kBlock);
+  const size_t bytes[kAdjArrays] = {8 * 3 * N,  8 * 3 * N,  8 * N,       8 * N,
+                                    8 * N,      8 * 16 * N, 8 * 2 * blocks, 4 * RS * N,
+                                    12 * RS * N, 40 * RS * N, RS * N};
+  size_t t = 0;
+  for (int k = 0; k < kAdjArrays; ++k) {
+    if (off) off[k] = t;
+    t += (bytes[k] + 255) & ~(size_t)255;
+  }
+  return t;
+}
+
+template <class R>
+void adj_pointers(AdjState<R>& G, void* const* p) {
+  G.gx = (double*)p[0];
+  G.gv = (double*)p[1];
+  G.gu = (double*)p[2];
+  G.gh = (double*)p[3];
+  G.gV = (double*)p[4];
+  G.gkc = (double*)p[5];
+  G.gab = (double*)p[6];
+  G.wgt4 = (R4<R>*)p[7];
+  G.gvc4 = (R4<R>*)p[8];
+  G.mom4 = (R4<R>*)p[9];
+  G.kap = (R*)p[10];
+}
+
+// The adjoint of the last forward. The workspace comes from the context
+// (grown with hipMalloc as needed) or, when arena is given, is carved from
+// that device memory (at least adj_layout(n) bytes), with no allocation.
+// Every workspace array is written before it is read: nothing needs to
+// start at zero.
 template <class R>
 crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g_accel,
                          const double* g_dudt, double* g_x, double* g_v, double* g_u,
-                         double* g_ab) {
+                         double* g_ab, unsigned char* arena = nullptr) {
   const crk_params& P = ctx->p;
-  const size_t N = (size_t)(((n + 63) / 64) * 64);
-  CRK_HIP(ensure(ctx->a_gx, 8 * 3 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gv, 8 * 3 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gu, 8 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gh, 8 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gV, 8 * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gkc, 8 * 16 * N), "adjoint workspace");
   const size_t RS = real_size(P.precision);
-  CRK_HIP(ensure(ctx->a_gab, 8 * 2 * (size_t)grid_for(n)), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_wgt4, 4 * RS * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_gvc4, 12 * RS * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_mom4, 40 * RS * N), "adjoint workspace");
-  CRK_HIP(ensure(ctx->a_kap, RS * N), "adjoint workspace");
+  size_t off[kAdjArrays];
+  const size_t total = adj_layout(n, RS, off);
+  void* ptr[kAdjArrays];
+  if (arena) {
+    for (int k = 0; k < kAdjArrays; ++k) ptr[k] = arena + off[k];
+  } else {
+    Buf* bufs[kAdjArrays] = {&ctx->a_gx,  &ctx->a_gv,   &ctx->a_gu,   &ctx->a_gh,
+                             &ctx->a_gV,  &ctx->a_gkc,  &ctx->a_gab,  &ctx->a_wgt4,
+                             &ctx->a_gvc4, &ctx->a_mom4, &ctx->a_kap};
+    for (int k = 0; k < kAdjArrays; ++k) {
+      const size_t end = k + 1 < kAdjArrays ? off[k + 1] : total;
+      CRK_HIP(ensure(*bufs[k], end - off[k]), "adjoint workspace");
+      ptr[k] = bufs[k]->p;
+    }
+  }
   State<R> S = make_state<R>(ctx, n);
   AdjState<R> G;
-  G.gx = (double*)ctx->a_gx.p;
-  G.gv = (double*)ctx->a_gv.p;
-  G.gu = (double*)ctx->a_gu.p;
-  G.gh = (double*)ctx->a_gh.p;
-  G.gV = (double*)ctx->a_gV.p;
-  G.gkc = (double*)ctx->a_gkc.p;
-  G.gab = (double*)ctx->a_gab.p;
-  G.wgt4 = (R4<R>*)ctx->a_wgt4.p;
-  G.gvc4 = (R4<R>*)ctx->a_gvc4.p;
-  G.mom4 = (R4<R>*)ctx->a_mom4.p;
-  G.kap = (R*)ctx->a_kap.p;
+  adj_pointers(G, ptr);
   G.w_a = g_accel;
   G.w_u = g_dudt;
   launch_bwd_prep<R>(S, G, s);
@@ -1193,25 +1226,48 @@ crk_status crk_set_params(crk_ctx* ctx, const crk_params* p) {
   if (!ctx) return CRK_EINVAL;
   crk_status st = check_params(ctx, p);
   if (st != CRK_OK) return st;
-  const bool prec_changed = p->precision != ctx->p.precision;
+  const crk_params o = ctx->p;
   ctx->p = *p;
-  if (prec_changed) ctx->n_last = -1;
-  ctx->spec_ok = false;  // box, h mode, search or kernel may differ
+  // the cell-list geometry depends on these; the kept forward state on every
+  // parameter the passes or the adjoint read (all but timing and the check)
+  const bool geometry = o.box != p->box || o.n_h != p->n_h || o.kernel != p->kernel ||
+                        o.precision != p->precision || o.h_mode != p->h_mode ||
+                        o.h_max_iter != p->h_max_iter || o.h_rtol != p->h_rtol ||
+                        o.search != p->search;
+  const bool state = geometry || o.gamma != p->gamma || o.alpha != p->alpha ||
+                     o.beta != p->beta || o.eps2 != p->eps2 || o.dt_relax != p->dt_relax ||
+                     o.store_corrections != p->store_corrections;
+  if (geometry) ctx->spec_ok = false;
+  if (state) ctx->n_last = -1;  // crk_backward needs a forward with these parameters
   return CRK_OK;
 }
 
 crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
   if (!ctx || n_max < 0) return fail(ctx, CRK_EINVAL, "bad reserve size");
   if (n_max == 0) return CRK_OK;
+  // a buffer that grows is reallocated: the state kept for crk_backward is
+  // then gone
+  const void* before[] = {ctx->pos4.p, ctx->vel4.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
+                          ctx->mom.p, ctx->nlist.p, ctx->slist.p, ctx->ng.p, ctx->ns.p,
+                          ctx->vals_a.p, ctx->cell3.p, ctx->mass.p, ctx->uu.p, ctx->hbuf.p,
+                          ctx->Vbuf.p};
   hipError_t e = ensure_particles(ctx, n_max);
-  if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
   const int64_t npad = ((n_max + 63) / 64) * 64;
-  e = ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap);
+  if (e == hipSuccess) e = ensure(ctx->nlist, 4 * (size_t)npad * ctx->list_cap);
   if (e == hipSuccess) e = ensure(ctx->slist, 4 * (size_t)npad * ctx->slist_cap);
   if (e == hipSuccess)
     e = ensure(ctx->scr_r, real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
   if (e == hipSuccess) e = ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap);
-  if (e != hipSuccess) return hip_fail(ctx, e, "reserve");
+  const void* after[] = {ctx->pos4.p, ctx->vel4.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
+                         ctx->mom.p, ctx->nlist.p, ctx->slist.p, ctx->ng.p, ctx->ns.p,
+                         ctx->vals_a.p, ctx->cell3.p, ctx->mass.p, ctx->uu.p, ctx->hbuf.p,
+                         ctx->Vbuf.p};
+  for (size_t k = 0; k < sizeof(before) / sizeof(before[0]); ++k)
+    if (before[k] != after[k]) ctx->n_last = -1;
+  if (e != hipSuccess) {
+    ctx->n_last = -1;
+    return hip_fail(ctx, e, "reserve");
+  }
   return CRK_OK;
 }
 
@@ -1299,8 +1355,9 @@ crk_status crk_backward(crk_ctx* ctx, void* hip_stream, long long n, const doubl
   if (!g_alpha_beta) return fail(ctx, CRK_EINVAL, "null array argument");
   hipStream_t s = (hipStream_t)hip_stream;
   if (n == 0) {
-    hipError_t e = hipMemsetAsync(g_alpha_beta, 0, 16, s);
-    return e == hipSuccess ? CRK_OK : hip_fail(ctx, e, "memset");
+    launch_zero_f64(g_alpha_beta, 2, s);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_fail(ctx, e, "zero fill");
   }
   if (!g_accel || !g_dudt || !g_x || !g_v || !g_u)
     return fail(ctx, CRK_EINVAL, "null array argument");

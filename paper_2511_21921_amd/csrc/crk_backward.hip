@@ -528,7 +528,16 @@ __global__ void __launch_bounds__(kBlock) k_bwd_reduce_ab(const double* __restri
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_zero_f64(double* __restrict__ a, int64_t na) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < na) a[i] = 0.0;
+}
+
 }  // namespace
+
+void launch_zero_f64(double* a, int64_t na, hipStream_t s) {
+  if (na > 0) hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(na)), dim3(kBlock), 0, s, a, na);
+}
 
 #define CRK_DISPATCH_KB(kernel, KFN, ...)                                                   \
   do {                                                                                      \

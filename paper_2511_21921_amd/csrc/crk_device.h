@@ -33,6 +33,23 @@ template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 template <class R> using R4 = typename Vec4<R>::T;
 
+// ------------------------------------------------------------ positions ----
+
+// xa wrapped into [0, L). A non-finite xa (which the forward's input check
+// rejects) maps to 0, so that every cell index derived from it stays in range
+// until that check is read.
+__host__ __device__ inline double wrap_pos(double xa, double L) {
+  double t = xa - L * __builtin_floor(xa / L);
+  if (t >= L) t -= L;
+  return t >= 0.0 && t < L ? t : 0.0;
+}
+
+// Cell index of a wrapped coordinate t in [0, L), with inv = G / L: in [0, G).
+__host__ __device__ inline int cell_coord(double t, double inv, int G) {
+  const int k = (int)(t * inv);
+  return k < 0 ? 0 : (k < G ? k : G - 1);
+}
+
 // ------------------------------------------------------------- kernels ----
 // W(r, h) = C / h^3 w(q), q = r / h, compact support q < 1.
 // eval() returns w(q) and w'(q) (zero outside the support).

@@ -52,7 +52,8 @@ __device__ inline unsigned long long dbits(double d) {
 // Grid-stride over the inputs; each block reduces in LDS and issues one
 // atomic per counter (per-wave atomics on four shared addresses serialise).
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h,
+__global__ void __launch_bounds__(kBlock) k_check_inputs(const double* __restrict__ x,
+                                                         const R* __restrict__ h,
                                                          const R* __restrict__ m,
                                                          const R* __restrict__ u, int64_t n,
                                                          unsigned long long* cnt) {
@@ -60,7 +61,9 @@ __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
     const double hv = (double)h[i], mv = (double)m[i], uv = (double)u[i];
-    const bool ok = hv > 0.0 && mv > 0.0 && uv > 0.0 && hv < 1e300 && uv < 1e300 && mv < 1e300;
+    const double x0 = fabs(x[i]), x1 = fabs(x[n + i]), x2 = fabs(x[2 * n + i]);
+    const bool ok = hv > 0.0 && mv > 0.0 && uv > 0.0 && hv < 1e300 && uv < 1e300 && mv < 1e300 &&
+                    x0 < 1e300 && x1 < 1e300 && x2 < 1e300;
     bad += ok ? 0 : 1;
     if (ok) {
       const unsigned long long a = dbits(hv), b = dbits(mv), c = dbits(1.0 / mv);
@@ -102,13 +105,6 @@ __global__ void __launch_bounds__(kBlock) k_check_inputs(const R* __restrict__ h
   }
 }
 
-__device__ inline double wrap_pos(double xa, double L) {
-  double t = xa - L * floor(xa / L);
-  if (t >= L) t -= L;
-  if (t < 0.0) t = 0.0;
-  return t;
-}
-
 __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, int64_t n,
                                                  double L, int G, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
@@ -118,9 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, i
   int c[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double t = wrap_pos(x[a * n + i], L);
-    int k = (int)(t * inv);
-    c[a] = k < G ? k : G - 1;
+    c[a] = cell_coord(wrap_pos(x[a * n + i], L), inv, G);
   }
   keys[i] = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0];
   vals[i] = (uint32_t)i;
@@ -183,8 +177,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double t = wrap_pos(x[a * n + p], S.box);
-    const int k = (int)(t * inv);
-    c[a] = k < S.G ? k : S.G - 1;
+    c[a] = cell_coord(t, inv, S.G);
     xi[a] = (R)(t - ((double)c[a] + 0.5) * S.ell_d);
   }
   R4<R> q;
@@ -1129,11 +1122,11 @@ __global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, i
 // ----------------------------------------------------------- launchers ----
 
 template <class R>
-void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned long long* cnt,
-                         hipStream_t s) {
+void launch_check_inputs(const double* x, const R* h, const R* m, const R* u, int64_t n,
+                         unsigned long long* cnt, hipStream_t s) {
   const unsigned blocks = grid_for(n) < 1024u ? grid_for(n) : 1024u;
-  hipLaunchKernelGGL(k_check_inputs<R>, dim3(blocks > 0 ? blocks : 1), dim3(kBlock), 0, s, h, m, u,
-                     n, cnt);
+  hipLaunchKernelGGL(k_check_inputs<R>, dim3(blocks > 0 ? blocks : 1), dim3(kBlock), 0, s, x, h,
+                     m, u, n, cnt);
 }
 
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
@@ -1217,7 +1210,7 @@ void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long*
 }
 
 #define CRK_INSTANTIATE(R)                                                                   \
-  template void launch_check_inputs<R>(const R*, const R*, const R*, int64_t,                \
+  template void launch_check_inputs<R>(const double*, const R*, const R*, const R*, int64_t, \
                                        unsigned long long*, hipStream_t);                    \
   template void launch_gather<R>(const State<R>&, const double*, const R*, const R*,         \
                                  const R*, const R*, hipStream_t);                           \

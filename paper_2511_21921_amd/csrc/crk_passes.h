@@ -8,8 +8,8 @@ namespace crk {
 
 // Max of positive h (as double bits) and a count of bad inputs.
 template <class R>
-void launch_check_inputs(const R* h, const R* m, const R* u, int64_t n, unsigned long long* cnt,
-                         hipStream_t s);
+void launch_check_inputs(const double* x, const R* h, const R* m, const R* u, int64_t n,
+                         unsigned long long* cnt, hipStream_t s);
 
 // Cell keys of wrapped positions, identity values, and per-cell counts.
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
@@ -89,6 +89,9 @@ struct AdjState {
   const double* w_a;  // [3][n] loss weights on accel, caller order
   const double* w_u;  // [n] loss weights on du/dt, caller order
 };
+
+// Writes zeros to a[0 .. na) with a kernel (no memset node in a captured graph).
+void launch_zero_f64(double* a, int64_t na, hipStream_t s);
 
 template <class R>
 void launch_bwd_prep(const State<R>& S, const AdjState<R>& G, hipStream_t s);

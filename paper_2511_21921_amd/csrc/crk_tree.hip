@@ -24,13 +24,6 @@ __device__ inline uint32_t spread10(uint32_t v) {
   return v;
 }
 
-__device__ inline double wrap01(double xa, double L) {
-  double t = xa - L * floor(xa / L);
-  if (t >= L) t -= L;
-  if (t < 0.0) t = 0.0;
-  return t;
-}
-
 __global__ void __launch_bounds__(kBlock) k_morton(const double* __restrict__ x, int64_t n,
                                                    double L, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
@@ -40,8 +33,7 @@ __global__ void __launch_bounds__(kBlock) k_morton(const double* __restrict__ x,
   uint32_t c[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int k = (int)(wrap01(x[a * n + i], L) * inv);
-    c[a] = (uint32_t)(k < 1024 ? k : 1023);
+    c[a] = (uint32_t)cell_coord(wrap_pos(x[a * n + i], L), inv, 1024);
   }
   keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
   vals[i] = (uint32_t)i;

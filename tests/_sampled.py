@@ -103,3 +103,37 @@ def localized_jvp(ps, samples, subsets, params, w_a, w_u, dirs):
     pos = np.searchsorted(U, samples)
     val = float((w_a * j["d_accel"][:, pos]).sum() + (w_u * j["d_dudt"][pos]).sum())
     return val, U, d
+
+
+def separated_coordinates_jvp(ps, params, field, w_a, w_u, reach, grid=3, seed=0):
+    """Oracle dL/d(coordinate) for grid^3 coordinates of one field ("x", "v" or "u") at once.
+
+    L = sum_i w_a_i . a_i + w_u_i du_i/dt over the whole set. A coordinate of particle p
+    moves only the outputs of particles within reach of p (three hops of at most the
+    largest h: h and V, then the corrections, density and grad v, then the force pairs).
+    The perturbed particles are the ones nearest the points of a grid^3 lattice (randomly
+    offset), at least 2 reach apart, so the regions their coordinates move are disjoint:
+    one JVP along the sum of their unit directions (components cycling x, y, z) gives each
+    derivative as the loss weights contracted with the outputs that moved in its region.
+    Checked: the separation, and that every particle whose outputs moved lies within reach
+    of its perturbed particle. Returns (particles, components, derivatives)."""
+    rng = np.random.default_rng(seed)
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    tree = cKDTree(x, boxsize=1.0)
+    g = (np.stack(np.meshgrid(*[np.arange(grid)] * 3, indexing="ij"), -1).reshape(-1, 3) +
+         0.5 + rng.uniform(-0.5, 0.5, 3)) / grid
+    parts = tree.query(np.mod(g, 1.0))[1]
+    ptree = cKDTree(x[parts], boxsize=1.0)
+    sep = ptree.query(x[parts], k=2)[0][:, 1].min()
+    assert sep > 2 * reach / ps.box, ("perturbed particles too close", sep, reach)
+    comps = np.arange(parts.size) % (1 if field == "u" else 3)
+    dx, dv, du = np.zeros_like(ps.x), np.zeros_like(ps.v), np.zeros(ps.n)
+    tgt = {"x": dx, "v": dv, "u": du[None]}[field]
+    tgt[comps, parts] = 1.0
+    j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, params, dx, dv, du, 0.0, 0.0, nbr_mode=1)
+    contrib = (w_a * j["d_accel"]).sum(0) + w_u * j["d_dudt"]
+    moved = np.nonzero((np.abs(j["d_accel"]).sum(0) + np.abs(j["d_dudt"])) > 0)[0]
+    owner_d, owner = ptree.query(x[moved])
+    assert owner_d.max() < reach / ps.box, ("outputs moved beyond reach", owner_d.max(), reach)
+    vals = np.bincount(owner, contrib[moved], minlength=parts.size)
+    return parts, comps, vals

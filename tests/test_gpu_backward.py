@@ -20,6 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a HIP device", allow_module_level=True)
 
 from tests import _gpu  # noqa: E402
+from tests._sampled import separated_coordinates_jvp  # noqa: E402
 
 
 def _grad(ps, precision, ctx=None, **kw):
@@ -61,6 +62,35 @@ def _check_jvps(ps, g, tol, nbr=0, **kw):
     return worst
 
 
+def _elementwise(ps, g, precision, tol, per_field=64, seed=9, nbr=0, **kw):
+    """Sampled coordinates of g_x, g_v and g_u, each against the oracle JVP of L along
+    that coordinate's unit direction: |g - jvp| over the largest |jvp| of the field's
+    samples. Returns the worst error of each field."""
+    p = oracle.params_for(ps, **kw)
+    rng = np.random.default_rng(seed)
+    z3, z1 = np.zeros_like(ps.x), np.zeros(ps.n)
+    worst = {}
+    for field, rows in (("g_x", 3), ("g_v", 3), ("g_u", 1)):
+        parts = rng.choice(ps.n, per_field, replace=False)
+        comps = rng.integers(0, rows, per_field)
+        got, want = [], []
+        for i, a in zip(parts, comps):
+            dx, dv, du = z3.copy(), z3.copy(), z1.copy()
+            (dx if field == "g_x" else dv if field == "g_v" else du[None])[a, i] = 1.0
+            j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, p, dx, dv, du, 0.0, 0.0, nbr_mode=nbr)
+            want.append(float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum()))
+            got.append(float(g[field][a, i] if rows == 3 else g[field][i]))
+        got, want = np.array(got), np.array(want)
+        scale = np.abs(want).max()
+        worst[field] = float(np.abs(got - want).max() / scale)
+        print("  %s: %d coordinates, worst %.2e of max |jvp| %.3e" % (field, per_field,
+                                                                     worst[field], scale),
+              flush=True)
+    for field, e in worst.items():
+        assert e <= tol, (field, e)
+    return worst
+
+
 CASES = {
     "fixed_h": lambda: (lambda ps: (setattr(ps, "h_mode", 0), ps)[1])(synth.random_small(400, 51)),
     "adaptive_masses": lambda: synth.random_small(600, 52, mass_spread=0.1),
@@ -78,6 +108,52 @@ def test_adjoint_matches_oracle_jvp(case, precision, tol):
     print("case %s n=%d precision=%d" % (case, ps.n, precision), flush=True)
     g, _ = _grad(ps, precision)
     _check_jvps(ps, g, tol)
+
+
+# element-wise bounds: FP64 to rounding; FP32 ten times the worst error measured on
+# these cases (the FP32 adjoint sums FP32 pair terms into FP64 accumulators)
+ELEM_TOL = {FP64: 1e-9, FP32: 2e-4}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_adjoint_elementwise(case, precision):
+    ps = CASES[case]()
+    if ps.w_a is None:
+        rng = np.random.default_rng(3)
+        ps.w_a, ps.w_u = rng.normal(size=(3, ps.n)), rng.normal(size=ps.n)
+    print("case %s n=%d precision=%d (element-wise)" % (case, ps.n, precision), flush=True)
+    g, _ = _grad(ps, precision)
+    _elementwise(ps, g, precision, ELEM_TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_adjoint_elementwise_c4_and_relaxation(precision):
+    ps = synth.random_small(1500, 53)
+    ps.n_h = synth.n_h_for_neighbours(100)
+    print("case C4 n=%d precision=%d (element-wise)" % (ps.n, precision), flush=True)
+    g, _ = _grad(ps, precision, kernel=WENDLAND_C4)
+    _elementwise(ps, g, precision, ELEM_TOL[precision], kernel=WENDLAND_C4)
+    ps = synth.random_small(800, 54)
+    print("case relax n=%d precision=%d (element-wise)" % (ps.n, precision), flush=True)
+    g, _ = _grad(ps, precision, dt_relax=3.0)
+    _elementwise(ps, g, precision, ELEM_TOL[precision], dt_relax=3.0)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_stored_corrections_match_recompute(precision):
+    """store_corrections = 1 keeps the 40 moment sums of the forward for the adjoint;
+    the default recomputes them. Both adjoints agree and match the oracle JVP."""
+    ps = synth.random_small(1200, 56, mass_spread=0.1)
+    print("case stored corrections n=%d precision=%d" % (ps.n, precision), flush=True)
+    gs, _ = _grad(ps, precision, store_corrections=1)
+    gr, _ = _grad(ps, precision, store_corrections=0)
+    for k in ("g_x", "g_v", "g_u", "g_alpha_beta"):
+        rel = np.abs(gs[k] - gr[k]).max() / np.abs(gr[k]).max()
+        print("  %s stored vs recomputed %.2e" % (k, rel), flush=True)
+        assert rel <= (1e-13 if precision == FP64 else 1e-6), (k, rel)
+    _check_jvps(ps, gs, 1e-9 if precision == FP64 else 2e-4)
+    _elementwise(ps, gs, precision, ELEM_TOL[precision], per_field=32)
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 2e-4)])
@@ -141,6 +217,39 @@ def test_sedov64_v_fwd_bwd_fp32_vs_fp64_and_oracle():
     fd = (L(1) - L(-1)) / (2 * eps)
     print("  central FD % .10e rel %.2e" % (fd, abs(fd - gl) / abs(gl)))
     assert abs(fd - gl) <= 1e-5 * abs(gl)
+
+
+def test_sedov64_v_elementwise_adjoint():
+    """262,144 particles: 81 coordinates each of g_x, g_v and g_u, FP64 and FP32, against
+    the oracle's derivative of the full-set loss along each coordinate (nine JVPs of the
+    whole set, each over 27 coordinates far enough apart that their regions are disjoint)."""
+    ps = synth.sedov64_v()
+    print("case sedov64_v n=%d (element-wise)" % ps.n, flush=True)
+    g64, _ = _grad(ps, FP64)
+    g32, _ = _grad(ps, FP32)
+    p = oracle.params_for(ps)
+    # three hops of the largest solved h bound where a coordinate's change reaches
+    o = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p, nbr_mode=1)
+    reach = 3.0 * o["h"].max() * 1.01
+    worst = {}
+    for field, key in (("x", "g_x"), ("v", "g_v"), ("u", "g_u")):
+        got64, got32, want = [], [], []
+        for seed in range(3):
+            parts, comps, vals = separated_coordinates_jvp(ps, p, field, ps.w_a, ps.w_u, reach,
+                                                           seed=seed)
+            sel = (comps, parts) if field != "u" else (parts,)
+            got64.append(g64[key][sel])
+            got32.append(g32[key][sel])
+            want.append(vals)
+        want = np.concatenate(want)
+        scale = np.abs(want).max()
+        for prec, got in ((FP64, np.concatenate(got64)), (FP32, np.concatenate(got32))):
+            e = float(np.abs(got - want).max() / scale)
+            worst[(key, prec)] = e
+            print("  %s precision %d: %d coordinates, worst %.2e of max |jvp| %.3e"
+                  % (key, prec, want.size, e, scale), flush=True)
+    for (key, prec), e in worst.items():
+        assert e <= ELEM_TOL[prec], (key, prec, e)
 
 
 def test_autograd_function_and_gradcheck():

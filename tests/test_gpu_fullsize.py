@@ -62,10 +62,29 @@ def _candidates(ps, k, seed):
     return np.stack([bg, cl], axis=1).ravel()
 
 
-def _sampled_oracle(ps, k, seed):
-    """k samples (each with a complete subset of at most 40k particles) and their oracle values."""
-    kept, subsets, o = complete_subsets(ps, _candidates(ps, 4 * k, seed), oracle.params_for(ps),
-                                        want=k, max_size=40000)
+def _densest(ps, k):
+    """The k clump particles with the smallest distance to their 64th neighbour: the
+    densest clump cores, where h is smallest and the tree walks go deepest."""
+    from scipy.spatial import cKDTree
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    nb = ps.n // 2
+    r64 = cKDTree(x, boxsize=1.0).query(x[nb:], k=65, workers=-1)[0][:, 64]
+    return nb + np.argsort(r64)[:k]
+
+
+def _sampled_oracle(ps, k, seed, dense=2):
+    """k samples (each with a complete subset of at most 40k particles) plus the `dense`
+    densest core particles (any subset size), and their oracle values."""
+    p = oracle.params_for(ps)
+    kept, subsets, o = complete_subsets(ps, _candidates(ps, 4 * k, seed), p, want=k,
+                                        max_size=40000)
+    if dense:
+        kd, sd, od = complete_subsets(ps, _densest(ps, dense), p)
+        print("densest cores", kd.tolist(), "h", od["h"].tolist(), "subsets",
+              [q.size for q in sd], flush=True)
+        kept = np.concatenate([kept, kd])
+        subsets = subsets + sd
+        o = {key: np.concatenate([o[key], od[key]], axis=-1) for key in o}
     return kept, subsets, o
 
 
