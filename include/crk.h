@@ -180,6 +180,23 @@ crk_status crk_backward(crk_ctx *ctx, void *hip_stream, long long n, const doubl
                         const double *g_dudt, double *g_x, double *g_v, double *g_u,
                         double *g_alpha_beta);
 
+/* crk_backward with no device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight training or serving loops, harnesses
+ * that forbid hipMalloc. Same arguments, results and errors as crk_backward
+ * (it runs the same kernels), plus CRK_EINVAL for n above 65,536 particles.
+ * The workspace (the adjoint accumulators, packed records and per-block
+ * partial sums: 41 MiB, sized for 65,536 FP64 particles) is one static
+ * device array of the library, one copy per GPU, held until the process
+ * ends; its address on each device is taken on the first call there. Every
+ * call on a GPU reuses that array, so calls that overlap on one GPU (other
+ * streams, contexts or threads) race: the caller serialises them. Nothing
+ * in it needs to start at zero (every element is written before it is
+ * read). Pass times are not recorded. For a whole step without allocation,
+ * size the context with crk_reserve before the forward. */
+crk_status crk_backward_noalloc(crk_ctx *ctx, void *hip_stream, long long n,
+                                const double *g_accel, const double *g_dudt, double *g_x,
+                                double *g_v, double *g_u, double *g_alpha_beta);
+
 /* One kick-drift-kick step of length dt on a single timestep level (App. A.4
  * KDK update), with the smoothing length integrated by the combined Thacker
  * and continuity rate and its exponential update (App. A.3):

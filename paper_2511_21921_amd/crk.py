@@ -48,7 +48,8 @@ class crk_stats(C.Structure):
 
 
 EXPORTS = ["crk_default_params", "crk_create", "crk_set_params", "crk_reserve", "crk_destroy",
-           "crk_last_error", "crk_forward", "crk_backward", "crk_pass_count", "crk_pass_name",
+           "crk_last_error", "crk_forward", "crk_backward", "crk_backward_noalloc",
+           "crk_pass_count", "crk_pass_name",
            "crk_pass_times", "crk_kdk_step", "crk_hkdk_step", "crk_cooling_table", "crk_cool",
            "crk_deposit"]
 
@@ -80,6 +81,8 @@ def lib():
         L.crk_forward.restype = C.c_int
         L.crk_backward.argtypes = [P, P, C.c_longlong] + [P] * 6
         L.crk_backward.restype = C.c_int
+        L.crk_backward_noalloc.argtypes = [P, P, C.c_longlong] + [P] * 6
+        L.crk_backward_noalloc.restype = C.c_int
         L.crk_kdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 14 +
                                    [C.POINTER(crk_stats)])
         L.crk_kdk_step.restype = C.c_int
@@ -348,8 +351,11 @@ class Context:
         self._raise(L.crk_pass_times(self._h, ms, calls, int(reset)))
         return {L.crk_pass_name(i).decode(): (ms[i], calls[i]) for i in range(k)}
 
-    def backward(self, g_accel: torch.Tensor, g_dudt: torch.Tensor) -> dict:
-        """Adjoint of the last forward for L = sum g_accel.accel + sum g_dudt dudt."""
+    def backward(self, g_accel: torch.Tensor, g_dudt: torch.Tensor,
+                 noalloc: bool = False) -> dict:
+        """Adjoint of the last forward for L = sum g_accel.accel + sum g_dudt dudt.
+        noalloc: crk_backward_noalloc (workspace in the library's static array,
+        at most 65,536 particles)."""
         n = int(g_dudt.shape[0])
         dev = g_dudt.device
         _check(g_accel, torch.float64, (3, n), "g_accel")
@@ -359,8 +365,9 @@ class Context:
              "g_u": torch.empty(n, dtype=torch.float64, device=dev),
              "g_alpha_beta": torch.empty(2, dtype=torch.float64, device=dev)}
         stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-        rc = lib().crk_backward(self._h, stream, n, _ptr(g_accel), _ptr(g_dudt), _ptr(o["g_x"]),
-                                _ptr(o["g_v"]), _ptr(o["g_u"]), _ptr(o["g_alpha_beta"]))
+        fn = lib().crk_backward_noalloc if noalloc else lib().crk_backward
+        rc = fn(self._h, stream, n, _ptr(g_accel), _ptr(g_dudt), _ptr(o["g_x"]), _ptr(o["g_v"]),
+                _ptr(o["g_u"]), _ptr(o["g_alpha_beta"]))
         self._raise(rc)
         return o
 

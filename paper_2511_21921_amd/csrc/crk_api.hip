@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "crk.h"
@@ -916,30 +917,33 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
       ptr[k] = bufs[k]->p;
     }
   }
+  // no timing events on the allocation-free path (creating them allocates)
+  auto tb = [&](int k, hipStream_t st) { return arena ? hipSuccess : tbegin(ctx, k, st); };
+  auto te = [&](int k, hipStream_t st) { return arena ? hipSuccess : tend(ctx, k, st); };
   State<R> S = make_state<R>(ctx, n);
   AdjState<R> G;
   adj_pointers(G, ptr);
   G.w_a = g_accel;
   G.w_u = g_dudt;
   launch_bwd_prep<R>(S, G, s);
-  CRK_HIP(tbegin(ctx, P_BWD_FORCE, s), "event");
+  CRK_HIP(tb(P_BWD_FORCE, s), "event");
   launch_bwd_force<R>(S, G, P.kernel, s);
-  CRK_HIP(tend(ctx, P_BWD_FORCE, s), "event");
-  CRK_HIP(tbegin(ctx, P_BWD_DENSITY, s), "event");
+  CRK_HIP(te(P_BWD_FORCE, s), "event");
+  CRK_HIP(tb(P_BWD_DENSITY, s), "event");
   launch_bwd_density<R>(S, G, P.kernel, s);
-  CRK_HIP(tend(ctx, P_BWD_DENSITY, s), "event");
-  CRK_HIP(tbegin(ctx, P_BWD_CORR, s), "event");
+  CRK_HIP(te(P_BWD_DENSITY, s), "event");
+  CRK_HIP(tb(P_BWD_CORR, s), "event");
   launch_bwd_corr<R>(S, G, P.kernel, s);
-  CRK_HIP(tend(ctx, P_BWD_CORR, s), "event");
-  CRK_HIP(tbegin(ctx, P_BWD_MOMENTS, s), "event");
+  CRK_HIP(te(P_BWD_CORR, s), "event");
+  CRK_HIP(tb(P_BWD_MOMENTS, s), "event");
   launch_bwd_moments<R>(S, G, P.kernel, P.h_mode, s);
-  CRK_HIP(tend(ctx, P_BWD_MOMENTS, s), "event");
-  CRK_HIP(tbegin(ctx, P_BWD_VOLUME, s), "event");
+  CRK_HIP(te(P_BWD_MOMENTS, s), "event");
+  CRK_HIP(tb(P_BWD_VOLUME, s), "event");
   launch_bwd_volume<R>(S, G, P.kernel, s);
-  CRK_HIP(tend(ctx, P_BWD_VOLUME, s), "event");
-  CRK_HIP(tbegin(ctx, P_BWD_OTHER, s), "event");
+  CRK_HIP(te(P_BWD_VOLUME, s), "event");
+  CRK_HIP(tb(P_BWD_OTHER, s), "event");
   launch_bwd_finish<R>(S, G, g_x, g_v, g_u, g_ab, s);
-  CRK_HIP(tend(ctx, P_BWD_OTHER, s), "event");
+  CRK_HIP(te(P_BWD_OTHER, s), "event");
   CRK_HIP(hipGetLastError(), "adjoint launch");
   return CRK_OK;
 }
@@ -1182,6 +1186,37 @@ crk_status deposit_impl(crk_ctx* ctx, hipStream_t s, int64_t ng, const double* x
   return CRK_OK;
 }
 
+// ---- crk_backward_noalloc: the adjoint's workspace in a static array ----
+// One copy of this array lives on every GPU the library runs on, for the
+// life of the process. Host code never uses its name as an address: the
+// address on each device comes from hipGetSymbolAddress, taken once per
+// device with that device current, and is what the kernels receive.
+constexpr long long kNoAllocMaxN = 65536;
+constexpr size_t kNoAllocBytes = adj_layout(kNoAllocMaxN, 8, nullptr);  // 41 MiB (FP64 sizes)
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of scratch (address taken on its first use).
+hipError_t scratch_address(unsigned char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1364,6 +1399,36 @@ crk_status crk_backward(crk_ctx* ctx, void* hip_stream, long long n, const doubl
   if (ctx->p.precision == CRK_FP64)
     return backward_impl<double>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
   return backward_impl<float>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta);
+}
+
+crk_status crk_backward_noalloc(crk_ctx* ctx, void* hip_stream, long long n,
+                                const double* g_accel, const double* g_dudt, double* g_x,
+                                double* g_v, double* g_u, double* g_alpha_beta) {
+  if (!ctx) return CRK_EINVAL;
+  ctx->err.clear();
+  if (n > kNoAllocMaxN)
+    return fail(ctx, CRK_EINVAL, "crk_backward_noalloc takes at most 65536 particles");
+  if (n < 0 || n != ctx->n_last)
+    return fail(ctx, CRK_EINVAL, "no forward with this n on the context");
+  if (ctx->precision_last != ctx->p.precision)
+    return fail(ctx, CRK_EINVAL, "precision changed since the forward");
+  if (!g_alpha_beta) return fail(ctx, CRK_EINVAL, "null array argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (n == 0) {
+    launch_zero_f64(g_alpha_beta, 2, s);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_fail(ctx, e, "zero fill");
+  }
+  if (!g_accel || !g_dudt || !g_x || !g_v || !g_u)
+    return fail(ctx, CRK_EINVAL, "null array argument");
+  unsigned char* arena = nullptr;
+  CRK_HIP(scratch_address(&arena), "static workspace address");
+  if (adj_layout(n, real_size(ctx->p.precision), nullptr) > kNoAllocBytes)
+    return fail(ctx, CRK_EINVAL, "static workspace too small");  // not reached for n <= max
+  if (ctx->p.precision == CRK_FP64)
+    return backward_impl<double>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta,
+                                 arena);
+  return backward_impl<float>(ctx, s, n, g_accel, g_dudt, g_x, g_v, g_u, g_alpha_beta, arena);
 }
 
 crk_status crk_kdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
