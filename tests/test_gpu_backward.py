@@ -110,9 +110,10 @@ def test_adjoint_matches_oracle_jvp(case, precision, tol):
     _check_jvps(ps, g, tol)
 
 
-# element-wise bounds: FP64 to rounding; FP32 ten times the worst error measured on
-# these cases (the FP32 adjoint sums FP32 pair terms into FP64 accumulators)
-ELEM_TOL = {FP64: 1e-9, FP32: 2e-4}
+# element-wise bounds, relative to the largest |jvp| of the field's samples: FP64 measured
+# at most 5.7e-14; FP32 (FP32 pair terms summed in FP64) measured at most 3.3e-6 (g_u of
+# the unequal-mass case), bound nine times that
+ELEM_TOL = {FP64: 1e-12, FP32: 3e-5}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -151,7 +152,9 @@ def test_stored_corrections_match_recompute(precision):
     for k in ("g_x", "g_v", "g_u", "g_alpha_beta"):
         rel = np.abs(gs[k] - gr[k]).max() / np.abs(gr[k]).max()
         print("  %s stored vs recomputed %.2e" % (k, rel), flush=True)
-        assert rel <= (1e-13 if precision == FP64 else 1e-6), (k, rel)
+        # measured: FP64 7e-15, FP32 3.1e-6 (g_x; the stored FP32 moment sums and the
+        # recomputed ones round differently)
+        assert rel <= (1e-13 if precision == FP64 else 3e-5), (k, rel)
     _check_jvps(ps, gs, 1e-9 if precision == FP64 else 2e-4)
     _elementwise(ps, gs, precision, ELEM_TOL[precision], per_field=32)
 

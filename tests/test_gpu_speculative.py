@@ -101,9 +101,18 @@ def test_new_h_guess_either_way_equal():
     _rejected_then_fresh(ps1, ps2, expect_reject=False)
 
 
-def test_set_params_drops_the_geometry():
+def test_set_params_keeps_or_drops_the_geometry():
+    """A parameter the cell-list geometry does not depend on (alpha) keeps the
+    speculative forward, which then equals a fresh context's bit for bit; one it
+    depends on (n_h) drops it."""
     ps = synth.random_small(3000, 106)
     _, ctx = _gpu.run(ps, FP32)
     ctx.set_params(_gpu.params_for(ps, FP32, alpha=1.5))
     g, _ = _gpu.run(ps, FP32, ctx=ctx, alpha=1.5)
+    assert g["stats"]["speculative"] == 1
+    f, _ = _gpu.run(ps, FP32, alpha=1.5)
+    for k in ("h", "V", "rho", "A", "B", "gradv", "accel", "dudt"):
+        assert np.array_equal(g[k], f[k]), k
+    ctx.set_params(_gpu.params_for(ps, FP32, alpha=1.5, n_h=ps.n_h * 1.01))
+    g, _ = _gpu.run(ps, FP32, ctx=ctx, alpha=1.5, n_h=ps.n_h * 1.01)
     assert g["stats"]["speculative"] == 0
