@@ -55,9 +55,9 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos;
   uint32_t host_rows[2] = {};
-  int lvl_off[40] = {}, lvl_cnt[40] = {};
+  int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
   int lattice = 0;
   // adjoint workspace
@@ -149,6 +149,27 @@ void release(Buf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+}
+
+// Grows b to at least bytes, keeping its first keep bytes: copied on stream
+// s, which is synchronised before the old block is freed.
+hipError_t ensure_keep(Buf& b, size_t bytes, size_t keep, hipStream_t s) {
+  if (b.bytes >= bytes) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return e;
+  if (b.p && keep) {
+    e = hipMemcpyAsync(p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return e;
+    }
+  }
+  release(b);
+  b.p = p;
+  b.bytes = bytes;
+  return hipSuccess;
 }
 
 crk_status check_params(crk_ctx* ctx, const crk_params* p) {
@@ -247,13 +268,13 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.cslot = c->lattice ? (const uint32_t*)c->tslot.p : nullptr;
   S.vrow = c->lattice ? (const uint32_t*)c->wrow.p + ((n + 63) / 64) + 1 : nullptr;
   S.shrink = c->p.h_mode == 1 ? 1 : 0;
-  S.nlo = (float4*)c->nlo.p;
-  S.nhi = (float4*)c->nhi.p;
+  S.ncen = (float4*)c->nlo.p;
+  S.nhw = (float4*)c->nhi.p;
   S.grow = c->lattice ? (const uint32_t*)c->lrow.p : nullptr;
   S.srow = c->lattice ? (const uint32_t*)c->lrow.p + (n + 63) / 64 + 1 : nullptr;
   S.lvl_off = (const int*)c->lvl.p;
-  S.lvl_cnt = c->lvl.p ? (const int*)c->lvl.p + 40 : nullptr;
   S.nlevels = c->nlevels;
+  S.cpos = c->lattice ? (uint32_t*)c->cpos.p : nullptr;
   S.rcap = (R)c->rcap;
   S.cnt = (unsigned long long*)c->cnt.p;
   S.n_h3 = c->p.n_h * c->p.n_h * c->p.n_h;
@@ -368,9 +389,10 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   return CRK_OK;
 }
 
-// Tree path: Morton order over the 1024^3 lattice, leaves = waves, per-particle
-// candidate radii adapted until every h is bracketed; then the tree is rebuilt
-// with the solved h for the symmetric neighbour list.
+// Tree path: Morton order over the 1024^3 lattice, search leaves of kLeaf
+// particles, per-particle candidate radii adapted until every h is bracketed;
+// the candidates of every particle are kept (rounds append to the scratch)
+// and its gather list is filtered from them.
 template <class R>
 crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
                       const R* m, const R* u, const R* h) {
@@ -387,10 +409,12 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     if (ctx->scr_cap < want) ctx->scr_cap = want;
   }
   // levels of the implicit tree over the leaves
-  const int nleaf = (int)((n + 63) / 64);
+  const int nleaf = (int)((n + kLeaf - 1) / kLeaf);
   ctx->nlevels = 0;
   int off = 0;
-  for (int c = nleaf;; c = (c + 1) / 2) {
+  for (int c = nleaf;; c = (c + kFan - 1) / kFan) {
+    // the walk keeps 8 bits per level below the top in 64 bits
+    if (ctx->nlevels == 8) return fail(ctx, CRK_EINVAL, "tree too deep");
     ctx->lvl_off[ctx->nlevels] = off;
     ctx->lvl_cnt[ctx->nlevels] = c;
     off += c;
@@ -399,17 +423,18 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   }
   CRK_HIP(ensure(ctx->nlo, 16 * (size_t)off), "alloc tree");
   CRK_HIP(ensure(ctx->nhi, 16 * (size_t)off), "alloc tree");
-  CRK_HIP(ensure(ctx->lvl, 4 * 80), "alloc tree");
+  CRK_HIP(ensure(ctx->lvl, 4 * 2 * kMaxLevels), "alloc tree");
   CRK_HIP(ensure(ctx->rad, real_size(P.precision) * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->todo, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->tslot, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->need, 4 * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->cpos, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(npad / 64 + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
-  int lv[80];
-  for (int t = 0; t < 40; ++t) {
+  int lv[2 * kMaxLevels];
+  for (int t = 0; t < kMaxLevels; ++t) {
     lv[t] = ctx->lvl_off[t];
-    lv[40 + t] = ctx->lvl_cnt[t];
+    lv[kMaxLevels + t] = ctx->lvl_cnt[t];
   }
   CRK_HIP(hipMemcpyAsync(ctx->lvl.p, lv, sizeof(lv), hipMemcpyHostToDevice, s), "tree levels");
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
@@ -428,14 +453,18 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(tend(ctx, P_CELLS, s), "event");
   // Rounds over the particles still unsolved. Each round ranks them (scan of
   // the todo flags, todo[n] = 0), sizes every group of 64 ranks to the
-  // largest capacity request in it, runs the candidate walk and the h solve
-  // (or the volume for fixed h) on them, and stops when none is left.
+  // largest capacity request in it, places the round's rows after those of
+  // the earlier rounds (whose solved particles keep their candidates there),
+  // runs the candidate walk and the h solve (or the volume for fixed h) on
+  // them, and stops when none is left.
   int* todo = (int*)ctx->todo.p;
   uint32_t* slot = (uint32_t*)ctx->tslot.p;
   const int64_t ngrp = npad / 64;
   uint32_t* grows = (uint32_t*)ctx->wrow.p;  // per-group rows, then their offsets
   uint32_t* goff = grows + ngrp + 1;
   CRK_HIP(hipMemsetAsync(todo + n, 0, 4, s), "memset");
+  const size_t RS = real_size(P.precision);
+  uint32_t row_base = 0;  // rows taken by the earlier rounds
   bool solved = false;
   for (int round = 0; round < 40; ++round) {
     CRK_HIP(exclusive_scan_u32((const uint32_t*)todo, slot, n + 1, (uint32_t*)ctx->scan_tmp.p,
@@ -448,16 +477,22 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       launch_slot_rows<R>(S, grows, s);
     }
     CRK_HIP(exclusive_scan_u32(grows, goff, ngrp + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
+    launch_add_u32(goff, ngrp + 1, row_base, s);
     CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], goff + ngrp, 4, hipMemcpyDeviceToHost, s), "rows");
     CRK_HIP(hipStreamSynchronize(s), "scan");
     if (ctx->host_rows[0] == 0) {
       solved = true;
       break;
     }
-    const size_t words = 1024 * (size_t)ctx->host_rows[1];  // a row: 16 entries of 64 slots
-    CRK_HIP(ensure(ctx->scr_r, real_size(P.precision) * words), "alloc candidates");
+    const uint32_t rows_end = ctx->host_rows[1];  // a row: 16 entries of 64 slots
+    if (rows_end >= (1u << 26)) return fail(ctx, CRK_ENOMEM, "candidate scratch beyond 2^26 rows");
+    // the first round leaves a quarter more room for the later ones
+    const size_t want = 1024 * (size_t)(round == 0 ? rows_end + rows_end / 4 : rows_end);
+    const size_t keep = 1024 * (size_t)row_base;
+    CRK_HIP(ensure_keep(ctx->scr_r, RS * want, RS * keep, s), "alloc candidates");
+    CRK_HIP(ensure_keep(ctx->cand, 4 * want, 4 * keep, s), "alloc candidates");
     if (!ctx->equal_mass)
-      CRK_HIP(ensure(ctx->scr_m, real_size(P.precision) * words), "alloc candidates");
+      CRK_HIP(ensure_keep(ctx->scr_m, RS * want, RS * keep, s), "alloc candidates");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);
@@ -471,17 +506,16 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       launch_hsolve<R>(S, P.kernel, s);
     CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
+    row_base = rows_end;
   }
   CRK_HIP(read_counters(ctx, s), "h solve");
   if (!solved) return fail(ctx, CRK_EHIP, "tree h solve did not settle");
   return CRK_OK;
 }
 
-// Tree path neighbour lists with per-wave capacities. Gather lists by one
-// walk, each wave sized from the candidate counts of the h solve (they hold
-// every r < h_i; 4 entries of room for rounding), rerun with the exact
-// counts if that falls short. Scatter-only lists by transposing the gather
-// lists: count, per-wave offsets, fill, sort.
+// Tree path neighbour lists with per-wave capacities. Gather lists filtered
+// from the kept candidates (lengths, per-wave offsets, entries); scatter-only
+// lists by transposing the gather lists: count, per-wave offsets, fill, sort.
 template <class R>
 crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
@@ -509,21 +543,18 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
     return hipStreamSynchronize(s);
   };
   CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
-  CRK_HIP(offsets((const int*)ctx->ccnt.p, 4, wg, lg, &ctx->host_rows[0]), "list rows");
-  for (int attempt = 0;; ++attempt) {
-    CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
-    CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW * kCntSpread, 0, 8 * kCntSpread, s), "memset");
-    {
-      State<R> S = make_state<R>(ctx, n);
-      launch_gather_tree<R>(S, s);
-    }
-    CRK_HIP(hipGetLastError(), "neighbour list launch");
-    CRK_HIP(read_counters(ctx, s), "neighbour list");
-    if (!ctx->host_cnt[CNT_LIST_OVERFLOW]) break;
-    if (attempt == 1) return fail(ctx, CRK_EHIP, "neighbour list did not fit");
-    CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");  // exact counts
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_filter_tree<R>(S, false, s);
   }
+  CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");
+  CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
+  CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
+  {
+    State<R> S = make_state<R>(ctx, n);
+    launch_filter_tree<R>(S, true, s);
+  }
+  CRK_HIP(hipGetLastError(), "neighbour list launch");
   CRK_HIP(hipMemsetAsync(ns, 0, 4 * (size_t)nw * 64, s), "memset");
   {
     State<R> S = make_state<R>(ctx, n);
@@ -777,8 +808,6 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
     {
       State<R> S = make_state<R>(ctx, n);
       launch_pack<R>(S, h, V, s);
-      if (ctx->lattice)  // node boxes with the solved h for the symmetric search
-        launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
     }
     if (ctx->lattice) {
       crk_status st = tree_lists<R>(ctx, s, n);
@@ -1319,7 +1348,8 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
                 &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
-                &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow};
+                &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow,
+                &c->cpos};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)

@@ -482,7 +482,10 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
       S.hbuf[s] = hn;
       S.Vbuf[s] = hn * hn * hn / (C * sum_f);
       hbits = dbits((double)hn);
-      if (S.todo) S.todo[s] = 0;
+      if (S.todo) {
+        S.todo[s] = 0;
+        S.cpos[s] = scratch_pos(S, s);
+      }
     }
   }
   wave_max_u64(cnt_at(S.cnt, CNT_H_ITER_MAX), iters);
@@ -497,17 +500,17 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
   if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
-  if (is_passive(S, s)) {  // V comes from the stored state (k_pack)
-    if (S.todo) S.todo[s] = 0;
-    return;
+  if (S.todo) {
+    S.todo[s] = 0;
+    S.cpos[s] = scratch_pos(S, s);
   }
+  if (is_passive(S, s)) return;  // V comes from the stored state (k_pack)
   const R h = S.hbuf[s];
   int scap;
   const int64_t base = scratch_base(S, s, scap);
   R dsum;
   const R sum = candidate_sum<R, K>(S, base, S.ccnt[s] < scap ? S.ccnt[s] : scap, h, dsum);
   S.Vbuf[s] = h * h * h / (R(Shape<K>::C) * sum);
-  if (S.todo) S.todo[s] = 0;
 }
 
 template <class R>

@@ -30,8 +30,11 @@ template <class R>
 void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s);
 template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
+// a[0 .. na) += v
+void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s);
+// Gather lists from the kept candidates: lengths (write = false), then entries.
 template <class R>
-void launch_gather_tree(const State<R>& S, hipStream_t s);
+void launch_filter_tree(const State<R>& S, bool write, hipStream_t s);
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s);
 template <class R>
 void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s);

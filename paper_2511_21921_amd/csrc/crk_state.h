@@ -6,6 +6,10 @@
 
 namespace crk {
 
+constexpr int kLeaf = 16;        // tree path: particles per search leaf (a Morton run)
+constexpr int kFan = 8;          // tree path: children per tree node
+constexpr int kMaxLevels = 40;   // tree path: largest number of tree levels
+
 // Counters of one evaluation (unsigned long long, kCntSpread slots each).
 enum Counter {
   CNT_HMAX_BITS = 0,   // max input h as double bits
@@ -95,13 +99,17 @@ struct State {
   const uint32_t* cslot;
   const uint32_t* vrow;
   int shrink;         // tree path: adapt the radius of an overflowing particle
-  // tree over waves of 64 Morton-sorted particles (tree path): node boxes
-  // (x, y, z, h_max) low corner and (x, y, z, -) high corner per level
-  float4* nlo;
-  float4* nhi;
-  const int* lvl_off;  // node offset of each level (level 0 = leaves)
-  const int* lvl_cnt;  // node count of each level
+  // tree over leaves of kLeaf Morton-sorted particles (tree path): node boxes,
+  // built as (x, y, z, h_max) low and (x, y, z, -) high corners, then kept as
+  // (centre, h_max) in ncen and (half-widths, -) in nhw
+  float4* ncen;
+  float4* nhw;
+  const int* lvl_off;  // [2 kMaxLevels]: node offset of each level (level 0 =
+                       // leaves), then the node count of each level
   int nlevels;
+  // tree path: where each solved particle's candidates are kept, (row << 6) |
+  // lane for group_base (rows of all rounds are disjoint)
+  uint32_t* cpos;
   unsigned long long* cnt;
   // parameters
   double n_h3, gamma, alpha, beta, eps2, dt_relax, rtol;
@@ -212,6 +220,14 @@ __device__ inline int64_t scratch_base(const State<R>& S, int64_t s, int& cap) {
   const int64_t q = S.cslot[s], w = q >> 6;
   cap = (int)(S.vrow[w + 1] - S.vrow[w]) * 16;
   return group_base(S.vrow[w], q);
+}
+
+// Tree path: the packed position (row << 6) | lane of particle s's scratch
+// slot in this round, kept in cpos once its h is solved.
+template <class R>
+__device__ inline uint32_t scratch_pos(const State<R>& S, int64_t s) {
+  const uint32_t q = S.cslot[s];
+  return (S.vrow[q >> 6] << 6) | (q & 63u);
 }
 
 // Where particle s's symmetric neighbour list lives: the gather part

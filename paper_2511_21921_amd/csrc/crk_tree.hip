@@ -4,16 +4,25 @@
 // cosmological volume), a cell list sized to the largest h puts whole clumps
 // into single cells. This path instead sorts the particles along a Morton
 // curve over a 1024^3 lattice (positions are kept as lattice coordinates
-// plus FP32/FP64 offsets from the lattice-cell centre), takes every wave of 64
-// consecutive particles as a leaf, and builds an implicit binary tree of leaf
-// boxes with the largest h below each node. A wave walks the tree without a
-// stack (wave-uniform control flow) and reads each overlapping leaf as one
-// coalesced 64-particle tile that is broadcast to its lanes, exactly as the
-// cell-list path reads its row segments.
+// plus FP32/FP64 offsets from the lattice-cell centre), takes every run of
+// kLeaf = 16 consecutive particles as a search leaf, and builds an implicit
+// tree of leaf boxes with kFan = 8 children per node (a node is named by its
+// level and index; its children are the kFan nodes that follow kFan times
+// its index one level down). The 16 particles of a leaf sit on the 16 lanes
+// of one DPP row and walk the tree together for the union of their spheres:
+// a step tests the children of one node against every lane's sphere and
+// keeps, as bits of one 64-bit word, the children still to visit at each
+// level, so the walk needs no stack and a row takes a few tens of dependent
+// steps. The particles of a reached leaf are loaded once (one per lane) and
+// broadcast across the row, and every lane tests each of them. Candidates
+// within a particle's radius are kept with their index and distance: the h
+// solve reads the distances, and the gather list is the candidates within
+// the solved h.
 #include "crk_passes.h"
 
 namespace crk {
 namespace {
+
 
 __device__ inline uint32_t spread10(uint32_t v) {
   v &= 1023u;
@@ -32,50 +41,9 @@ __global__ void __launch_bounds__(kBlock) k_morton(const double* __restrict__ x,
   const double inv = 1024.0 / L;
   uint32_t c[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    c[a] = (uint32_t)cell_coord(wrap_pos(x[a * n + i], L), inv, 1024);
-  }
+  for (int a = 0; a < 3; ++a) c[a] = (uint32_t)cell_coord(wrap_pos(x[a * n + i], L), inv, 1024);
   keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
   vals[i] = (uint32_t)i;
-}
-
-// Leaf boxes (absolute positions, FP32) and the largest h of each leaf.
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __restrict__ h) {
-  const int64_t leaf = particle_id();
-  const int nleaf = S.lvl_cnt[0];
-  if (leaf >= nleaf) return;
-  const int64_t b = leaf * 64, e = (b + 64 < S.n) ? b + 64 : S.n;
-  float lo[3] = {3e30f, 3e30f, 3e30f}, hi[3] = {-3e30f, -3e30f, -3e30f}, hm = 0.f;
-  for (int64_t s = b; s < e; ++s) {
-    const uint32_t c3 = S.cell3[s];
-    const R4<R> p = S.pos4[s];
-    const float c[3] = {(float)(c3 & 1023u), (float)((c3 >> 10) & 1023u), (float)(c3 >> 20)};
-    const float xi[3] = {(float)p.x, (float)p.y, (float)p.z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float v = (c[a] + 0.5f) * (float)S.ell + xi[a];
-      lo[a] = fminf(lo[a], v);
-      hi[a] = fmaxf(hi[a], v);
-    }
-    hm = fmaxf(hm, (float)h[s]);
-  }
-  S.nlo[leaf] = make_float4(lo[0], lo[1], lo[2], hm);
-  S.nhi[leaf] = make_float4(hi[0], hi[1], hi[2], 0.f);
-}
-
-__global__ void __launch_bounds__(kBlock) k_tree_up(float4* nlo, float4* nhi, int off_c,
-                                                    int cnt_c, int off_p, int cnt_p) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= cnt_p) return;
-  float4 lo = nlo[off_c + 2 * k], hi = nhi[off_c + 2 * k];
-  if (2 * k + 1 < cnt_c) {
-    const float4 l2 = nlo[off_c + 2 * k + 1], h2 = nhi[off_c + 2 * k + 1];
-    lo = make_float4(fminf(lo.x, l2.x), fminf(lo.y, l2.y), fminf(lo.z, l2.z), fmaxf(lo.w, l2.w));
-    hi = make_float4(fmaxf(hi.x, h2.x), fmaxf(hi.y, h2.y), fmaxf(hi.z, h2.z), 0.f);
-  }
-  nlo[off_p + k] = lo;
-  nhi[off_p + k] = hi;
 }
 
 // Absolute position of a sorted particle (FP32, the rounding of the node
@@ -88,17 +56,64 @@ __device__ inline void abs_pos(const State<R>& S, uint32_t c3, const R4<R>& p, f
   a[2] = ((float)(c3 >> 20) + 0.5f) * ell + (float)p.z;
 }
 
-// Squared periodic distance from point a to the box [lo, hi] (both in the
-// unit cell [0, L] up to rounding).
-__device__ inline float point_gap2(const float a[3], float4 lo, float4 hi, float L) {
-  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+// Leaf boxes (absolute positions, FP32) and the largest h of each leaf.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __restrict__ h) {
+  const int64_t leaf = particle_id();
+  const int nleaf = S.lvl_off[kMaxLevels];  // level 0 count
+  if (leaf >= nleaf) return;
+  const int64_t b = leaf * kLeaf, e = (b + kLeaf < S.n) ? b + kLeaf : S.n;
+  float lo[3] = {3e30f, 3e30f, 3e30f}, hi[3] = {-3e30f, -3e30f, -3e30f}, hm = 0.f;
+  for (int64_t s = b; s < e; ++s) {
+    float v[3];
+    abs_pos(S, S.cell3[s], S.pos4[s], v);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], v[a]);
+      hi[a] = fmaxf(hi[a], v[a]);
+    }
+    hm = fmaxf(hm, (float)h[s]);
+  }
+  S.ncen[leaf] = make_float4(lo[0], lo[1], lo[2], hm);  // corners until k_box_centres
+  S.nhw[leaf] = make_float4(hi[0], hi[1], hi[2], 0.f);
+}
+
+// Node k of a level from its (up to kFan) children k kFan + c one level down.
+__global__ void __launch_bounds__(kBlock) k_tree_up(float4* nlo, float4* nhi, int off_c,
+                                                    int cnt_c, int off_p, int cnt_p) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= cnt_p) return;
+  float4 lo = nlo[off_c + kFan * k], hi = nhi[off_c + kFan * k];
+  for (int c = 1; c < kFan && kFan * k + c < cnt_c; ++c) {
+    const float4 l2 = nlo[off_c + kFan * k + c], h2 = nhi[off_c + kFan * k + c];
+    lo = make_float4(fminf(lo.x, l2.x), fminf(lo.y, l2.y), fminf(lo.z, l2.z), fmaxf(lo.w, l2.w));
+    hi = make_float4(fmaxf(hi.x, h2.x), fmaxf(hi.y, h2.y), fmaxf(hi.z, h2.z), 0.f);
+  }
+  nlo[off_p + k] = lo;
+  nhi[off_p + k] = hi;
+}
+
+// Every node box from its corners to (centre, h_max) and (half-widths, 0).
+__global__ void __launch_bounds__(kBlock) k_box_centres(float4* __restrict__ lo_c,
+                                                        float4* __restrict__ hi_w, int nnode) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nnode) return;
+  const float4 lo = lo_c[k], hi = hi_w[k];
+  lo_c[k] = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z), lo.w);
+  hi_w[k] = make_float4(0.5f * (hi.x - lo.x), 0.5f * (hi.y - lo.y), 0.5f * (hi.z - lo.z), 0.f);
+}
+
+// Squared periodic distance from point a to the box of centre c and
+// half-widths w: the distance to the box grows with that to its centre, so
+// the centre's nearest image gives the nearest image of the box.
+__device__ inline float box_gap2(const float a[3], float4 c, float4 w, float L, float inv_L) {
+  const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
   float g2 = 0.f;
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
-    const float d1 = l[t] - a[t], d2 = a[t] - h[t];
-    float g = 0.f;
-    if (d1 > 0.f) g = fminf(d1, a[t] + L - h[t]);       // left of the box, or its image
-    else if (d2 > 0.f) g = fminf(d2, l[t] + L - a[t]);  // right of the box, or its image
+    float d = cc[t] - a[t];
+    d -= L * rintf(d * inv_L);
+    const float g = fmaxf(fabsf(d) - ww[t], 0.f);
     g2 += g * g;
   }
   return g2;
@@ -106,35 +121,6 @@ __device__ inline float point_gap2(const float a[3], float4 lo, float4 hi, float
 
 // Radius widened against the FP32 rounding of positions and node boxes.
 __device__ inline float pad_radius(float r, float L) { return r * 1.00001f + 4e-6f * L; }
-
-// Stackless walk of the implicit binary tree. A node is entered when
-// need(lo, hi) holds for any lane of the wave (each lane tests its own
-// sphere against the node box); f(leaf) is called for every leaf reached.
-// All control flow is wave-uniform.
-template <class R, class N, class F>
-__device__ inline void tree_walk(const State<R>& S, N&& need, F&& f) {
-  const int top = S.nlevels - 1;
-  int level = top, k = 0;
-  while (true) {
-    bool visit = false;
-    if (k < S.lvl_cnt[level]) {
-      const int64_t node = S.lvl_off[level] + k;
-      visit = __ballot(need(S.nlo[node], S.nhi[node])) != 0ull;
-    }
-    if (visit && level > 0) {
-      --level;
-      k = 2 * k;
-      continue;
-    }
-    if (visit) f(k);
-    while (level < top && (k & 1)) {
-      k >>= 1;
-      ++level;
-    }
-    if (level == top) break;
-    ++k;
-  }
-}
 
 // Lattice separation x_ij from the lane's (pi, ci) and a candidate (pj, cj).
 template <class R>
@@ -151,72 +137,107 @@ __device__ inline void lattice_sep(const State<R>& S, const R4<R>& pi, uint32_t 
   x[2] = (pi.z - pj.z) + R(d[2]) * S.ell;
 }
 
-// Calls f(j, pj, mj, cj) for every particle of leaf k, broadcast to the wave.
-template <class R, class F>
-__device__ inline void leaf_tile(const State<R>& S, int64_t leaf, F&& f) {
-  const int lane = threadIdx.x & 63;
-  const int64_t b = leaf * 64;
-  const int cnt = (int)((b + 64 < S.n ? b + 64 : S.n) - b);
-  const int64_t jl = b + (lane < cnt ? lane : 0);
-  const R4<R> pl = S.pos4[jl];
-  const R ml = S.mass[jl];
-  const int cl = (int)S.cell3[jl];
-  for (int t = 0; t < cnt; ++t) {
-    R4<R> pj;
-    pj.x = bcast(pl.x, t);
-    pj.y = bcast(pl.y, t);
-    pj.z = bcast(pl.z, t);
-    pj.w = bcast(pl.w, t);
-    f((uint32_t)(b + t), pj, bcast(ml, t), (uint32_t)bcast(cl, t));
+// The level offsets and counts of the implicit tree, copied to LDS (a row's
+// walk indexes them by its own level).
+struct Levels {
+  int off[kMaxLevels], cnt[kMaxLevels];
+};
+
+// Broadcast of lane u of every 16-lane row to the whole row (DPP row_newbcast).
+template <int U>
+__device__ inline int row_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, false);
+}
+template <int U>
+__device__ inline uint32_t row_bcast(uint32_t v) {
+  return (uint32_t)row_bcast<U>((int)v);
+}
+template <int U>
+__device__ inline float row_bcast(float v) {
+  return __int_as_float(row_bcast<U>(__float_as_int(v)));
+}
+template <int U>
+__device__ inline double row_bcast(double v) {
+  return __hiloint2double(row_bcast<U>(__double2hiint(v)), row_bcast<U>(__double2loint(v)));
+}
+
+template <int U, class F>
+__device__ inline void unroll16(F&& f) {
+  if constexpr (U < 16) {
+    f(std::integral_constant<int, U>());
+    unroll16<U + 1>(f);
   }
 }
 
 // First candidate radius of every particle, kept small so that the first
 // walk stays cheap (particles whose h root lies beyond it grow it in later
 // rounds): the least of the h that the target count would need at the
-// density of the particle's 8 nearest leaf-mates, n_h r_8 (4 pi / 24)^(1/3),
-// at the density of its leaf box, and 1.5x that of the mean density. The
-// caller's h is kept instead (x1.05) when it lies within a factor 2 of that
-// estimate (a previous step's h). With fixed h the radius is h.
+// density of the particle's 8 nearest wave-mates (the 64 particles of its
+// wave), n_h r_8 (4 pi / 24)^(1/3), at the density of the wave's box, and
+// 1.5x that of the mean density (the estimate lies a fifth above the root
+// for the median particle and below it for a few percent). When the caller's
+// h lies within [0.75, 1.33] of the estimate (a previous step's h), 1.05 h is
+// taken where it is larger. With fixed h the radius is h.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) {
   const int64_t s = particle_id();
   if ((s & ~(int64_t)63) >= S.n) return;
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
-  const int64_t leaf = sc >> 6;
+  const int64_t wave = sc >> 6;
   R r = S.hbuf[sc];
   if (h_mode != 0) {
+    const int lane = threadIdx.x & 63;
     const R4<R> pi = S.pos4[sc];
     const uint32_t ci = S.cell3[sc];
+    const int64_t b = wave * 64;
+    const int cnt = (int)((b + 64 < S.n ? b + 64 : S.n) - b);
+    // the wave's particles, broadcast to its lanes one at a time
+    const int64_t jl = b + (lane < cnt ? lane : 0);
+    const R4<R> pl = S.pos4[jl];
+    const int cl = (int)S.cell3[jl];
     float d[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) d[t] = 3e30f;
-    leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
-      (void)mj;
-      if (j == (uint32_t)sc) return;
+    for (int t = 0; t < cnt; ++t) {
+      R4<R> pj;
+      pj.x = bcast(pl.x, t);
+      pj.y = bcast(pl.y, t);
+      pj.z = bcast(pl.z, t);
+      pj.w = R(0);
+      const uint32_t cj = (uint32_t)bcast(cl, t);
+      if (b + t == sc) continue;
       R x[3];
       lattice_sep(S, pi, ci, pj, cj, x);
       float v = (float)(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {  // keep the 8 smallest, sorted
-        const float lo = fminf(d[t], v);
-        v = fmaxf(d[t], v);
-        d[t] = lo;
+      for (int q = 0; q < 8; ++q) {  // keep the 8 smallest, sorted
+        const float lo = fminf(d[q], v);
+        v = fmaxf(d[q], v);
+        d[q] = lo;
       }
-    });
-    const int64_t b = leaf * 64;
-    const int64_t cnt = (b + 64 < S.n ? b + 64 : S.n) - b;
-    const float4 lo = S.nlo[leaf], hi = S.nhi[leaf];
+    }
+    // the wave's box: the union of its (up to four) leaves
+    const int nleaf = S.lvl_off[kMaxLevels];
+    float lo[3] = {3e30f, 3e30f, 3e30f}, hi[3] = {-3e30f, -3e30f, -3e30f};
+    for (int q = 0; q < 4 && wave * 4 + q < nleaf; ++q) {
+      const float4 c = S.ncen[wave * 4 + q], w = S.nhw[wave * 4 + q];
+      const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], cc[a] - ww[a]);
+        hi[a] = fmaxf(hi[a], cc[a] + ww[a]);
+      }
+    }
     const double pad = 0.5 * S.ell_d;  // coincident lattice cells have no volume
-    const double vol = ((double)(hi.x - lo.x) + pad) * ((double)(hi.y - lo.y) + pad) *
-                       ((double)(hi.z - lo.z) + pad);
+    const double vol = ((double)(hi[0] - lo[0]) + pad) * ((double)(hi[1] - lo[1]) + pad) *
+                       ((double)(hi[2] - lo[2]) + pad);
     double est = cbrt(S.n_h3 * vol / (double)cnt);
     if (cnt >= 9)  // (4 pi / 24)^(1/3)
       est = fmin(est, cbrt(S.n_h3) * sqrt((double)d[7]) * 0.80599597700823482);
     est = fmin(est, 1.5 * cbrt(S.n_h3 / (double)S.n) * S.box);
     const double g = (double)r;
-    const double h0 = (g > 0.5 * est && g < 2.0 * est) ? 1.05 * g : est;
+    const double h0 = (g > 0.75 * est && g < 1.33 * est) ? fmax(1.05 * g, est) : est;
     r = (R)fmin(h0, 0.45 * S.box);
   }
   if (active) {
@@ -227,130 +248,247 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 }
 
 // Candidates of every unsolved particle within its own radius ri, written to
-// its scratch slot. A particle whose candidates overflow its capacity also
-// gets, from the same walk, the counts and the h-root test
-// f(r) = C (w(0) + sum_j (m_j/m_i) w(r_ij / r)) - n_h^3 > 0 at ri and at four
-// smaller radii ri 0.75^k: the next round uses the smallest of these radii
-// that holds the root, with exactly the capacity its count needs, or, when
-// none does, a radius grown from the count. With fixed h only the capacity
-// is raised. Sums over the candidates that did fit are taken afterwards from
-// the scratch, so particles that fit pay only for the counts.
-template <class R, int K>
+// its scratch slot (list entry and distance; the mass ratio when masses
+// differ), in ascending j. Two phases:
+//  1. The 16 lanes of a DPP row (the particles of one leaf) walk the tree
+//     together: a step tests the children of the current node against every
+//     lane's sphere (a child is entered when some lane of the row reaches
+//     it), records the reached children as bits of pend (8 bits per level)
+//     and moves to the deepest pending one. The reached leaves are buffered
+//     per row in LDS; a batch of them is then taken by all rows in step: a
+//     leaf's particles are loaded one per lane, broadcast across the row as
+//     absolute FP32 positions and tested against the lane's sphere padded
+//     beyond their rounding. The indices that pass are written to the
+//     particle's slot.
+//  2. Each lane takes its passed indices in order, computes the separation
+//     exactly (lattice offsets, as every later pass does) and keeps those
+//     within ri, compacting them in place with their distance.
+// A particle whose passed indices overflow its capacity is counted, with the
+// counts within ri 0.75^k, k = 1 .. 4 (from the padded test): the next round
+// uses the smallest of those radii holding 1.3 (4 pi / 3) n_h^3 candidates,
+// with capacity for its count (or, if none does, ri with the whole count);
+// a radius that then falls short of the h root is grown by the h solve. With
+// fixed h the capacity is raised.
+template <class R, int K, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
   constexpr int kBins = 4;
+  constexpr int kRowBuf = 32;  // leaves a row buffers between batches
+  __shared__ Levels lv;
+  __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
+  for (int t = threadIdx.x; t < S.nlevels; t += kBlock) {
+    lv.off[t] = S.lvl_off[t];
+    lv.cnt[t] = S.lvl_off[kMaxLevels + t];
+  }
+  __syncthreads();
   const int64_t s = particle_id();
+  if ((s & ~(int64_t)63) >= S.n) return;  // whole wave past the end
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];
   const R ri = mine ? S.rad[sc] : R(0);
   unsigned long long retry = 0;
+  const int rowid = (threadIdx.x & 63) >> 4;
+  const uint64_t rowbits = 0xFFFFull << (16 * rowid);
+  const int sub = threadIdx.x & 15;
+  uint32_t* rbuf = lbuf[threadIdx.x >> 4];
   if (__ballot(mine) != 0ull) {
     const R4<R> pi = S.pos4[sc];
     const uint32_t ci = S.cell3[sc];
-    const R mi_inv = R(1) / S.mass[sc];
-    const R r2cap = ri * ri;
     int cap = 0;
     int64_t base = 0;
     if (mine) base = scratch_base(S, sc, cap);
-    R rk[kBins], t2[kBins], ik[kBins], fk[kBins];
-    int hk[kBins];
-    {
-      R r = ri;
-#pragma unroll
-      for (int k = 0; k < kBins; ++k) {
-        r *= R(0.75);
-        rk[k] = r;
-        t2[k] = r * r;
-        ik[k] = R(1) / r;
-        fk[k] = R(Shape<K>::w0);
-        hk[k] = 0;
-      }
-    }
-    const R iri = mine ? R(1) / ri : R(0);
-    R fi = R(Shape<K>::w0);
-    // adds the f sums of one candidate at ri and at the smaller radii
-    auto add_sums = [&](R r, R mr) {
-      R w, dw;
-      Shape<K>::eval(r * iri, w, dw);
-      fi += mr * w;
-#pragma unroll
-      for (int k = 0; k < kBins; ++k) {
-        Shape<K>::eval(r * ik[k], w, dw);
-        fk[k] += mr * w;
-      }
-    };
-    int cnt = 0;
-    Stage4<R> sr, sm;
     float P[3];
     abs_pos(S, ci, pi, P);
     const float L = (float)S.box;
+    const float inv_L = 1.0f / L;
     const float rp = mine ? pad_radius((float)ri, L) : -1.f;
-    const float rp2 = rp * rp;
-    auto need = [&](float4 lo, float4 hi) { return mine && point_gap2(P, lo, hi, L) < rp2; };
-    tree_walk(S, need, [&](int64_t leaf) {
-      leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
-        if (!mine || j == (uint32_t)s) return;
-        R x[3];
-        lattice_sep(S, pi, ci, pj, cj, x);
-        const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        if (r2 < r2cap) {
-          const R r = Sc<R>::sqrt(r2);
-          const R mr = mj * mi_inv;
-          if (cnt < cap) {
+    const float rp2 = mine ? rp * rp : -1.f;  // no box is nearer than -1
+    float t2[kBins];
+    int hk[kBins];
+    {
+      float r = rp;
+#pragma unroll
+      for (int k = 0; k < kBins; ++k) {
+        r *= 0.75f;
+        t2[k] = r * r;
+        hk[k] = 0;
+      }
+    }
+    // ---- phase 1: walk, padded test, passed indices to the slot ----
+    int np = 0;  // indices that passed
+    Stage4<uint32_t> sj;
+    auto pass = [&](uint32_t j, float d2) {
+      if (np < cap) {
+        sj.put(np & 3, j);
+        if ((np & 3) == 3) sj.flush_group(S.cand, base, np);
+      }
+      ++np;
+#pragma unroll
+      for (int k = 0; k < kBins; ++k) hk[k] += d2 < t2[k] ? 1 : 0;
+    };
+    // the buffered leaves of every row, all rows in step
+    int nbuf = 0;  // row-uniform
+    auto batch = [&]() {
+      // the leaves lane 0 of each row wrote are read by the whole row: keep
+      // the wave's LDS accesses in program order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int q = 0; __ballot(q < nbuf) != 0ull; ++q) {
+        const bool has = q < nbuf;
+        const int64_t leaf = has ? rbuf[q] : 0;
+        const int64_t j0 = leaf * kLeaf;
+        const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
+        const int64_t jl = j0 + (sub < m ? sub : m - 1);
+        float A[3];
+        abs_pos(S, S.cell3[jl], S.pos4[jl], A);
+        // the image of the lane's particle nearest the leaf's centre serves
+        // every particle of the leaf within the sphere when the leaf's
+        // half-widths stay below L/2 - rp (always, but in tiny boxes of few
+        // particles); otherwise each particle takes its own nearest image
+        const float4 lc = S.ncen[leaf], lw = S.nhw[leaf];
+        const float half = 0.5f * L - rp;
+        const bool wide = lw.x > half || lw.y > half || lw.z > half;
+        float Q[3] = {P[0], P[1], P[2]};
+        {
+          const float cc[3] = {lc.x, lc.y, lc.z};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) Q[a] += L * rintf((cc[a] - P[a]) * inv_L);
+        }
+        if (__ballot(wide) == 0ull) {
+          unroll16<0>([&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            const float dx = Q[0] - row_bcast<U>(A[0]);
+            const float dy = Q[1] - row_bcast<U>(A[1]);
+            const float dz = Q[2] - row_bcast<U>(A[2]);
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U), d2);
+          });
+        } else {
+          unroll16<0>([&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            float d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {  // nearest periodic image
+              d[a] = P[a] - row_bcast<U>(A[a]);
+              d[a] -= L * rintf(d[a] * inv_L);
+            }
+            const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U), d2);
+          });
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
+      nbuf = 0;
+    };
+    // the row's walk (identical in its 16 lanes)
+    const int top = S.nlevels - 1;
+    const bool row_work = (__ballot(mine) & rowbits) != 0ull;
+    int cur = 0, cur_level = top;  // the node whose children are tested next
+    uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
+    bool walking = row_work && top > 0;
+    if (row_work && top == 0) {  // a one-leaf tree: the root
+      if (sub == 0) rbuf[0] = 0;
+      nbuf = 1;
+    }
+    while (__ballot(walking) != 0ull) {
+      if (walking) {
+        const int cl = cur_level - 1;
+        const int c0 = cur * kFan;
+        const int m = min(kFan, lv.cnt[cl] - c0);
+        const int nb = lv.off[cl] + c0;
+        bool h[kFan];
+#pragma unroll
+        for (int c = 0; c < kFan; ++c) {  // missing children repeat the last one, unused
+          const int node = nb + (c < m ? c : m - 1);
+          h[c] = c < m && box_gap2(P, S.ncen[node], S.nhw[node], L, inv_L) < rp2;
+        }
+        uint32_t mask = 0;
+#pragma unroll
+        for (int c = 0; c < kFan; ++c)
+          if ((__ballot(h[c]) & rowbits) != 0ull) mask |= 1u << c;
+        if (cl == 0) {
+          for (; mask; mask &= mask - 1u) {  // the reached leaves, to the row's buffer
+            if (sub == 0) rbuf[nbuf] = (uint32_t)(c0 + __builtin_ctz(mask));
+            ++nbuf;
+          }
+        } else {
+          pend |= (uint64_t)mask << (8 * cl);
+        }
+        if (pend == 0ull) {
+          walking = false;
+        } else {  // the deepest pending child; its parent is an ancestor of cur
+          const int b = __builtin_ctzll(pend);
+          pend &= pend - 1;
+          const int lvl = b >> 3;
+          cur = ((cur >> (3 * (lvl + 1 - cur_level))) << 3) + (b & 7);
+          cur_level = lvl;
+        }
+      }
+      if (__ballot(nbuf > kRowBuf - kFan) != 0ull) batch();  // a buffer that could overflow
+    }
+    batch();
+    // ---- phase 2: exact separations of the passed indices, in place ----
+    int cnt = 0;
+    if (np <= cap) {
+      Stage4<R> sr, sm;
+      Stage4<uint32_t> sk;
+      const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
+      const R r2cap = ri * ri;
+      if (np & 3) sj.flush_group(S.cand, base, np - 1);  // the last partial chunk
+      for (int k = 0; k < np; k += 16) {
+        uint32_t jj[16];
+        load_group(S.cand + group_at(base, k), jj);  // read before this group is rewritten
+        for (int t = 0; t < 16 && k + t < np; ++t) {
+          const uint32_t j = jj[t];
+          R x[3];
+          lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+          const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+          if (r2 < r2cap && j != (uint32_t)s) {
             const int slot = cnt & 3;
-            sr.put(slot, r);
-            sm.put(slot, mr);
+            sr.put(slot, Sc<R>::sqrt(r2));
+            sk.put(slot, j << kCodeBits);
+            if (!EM) sm.put(slot, S.mass[j] * mi_inv);
             if (slot == 3) {
               sr.flush_group(S.scr_r, base, cnt);
-              if (!S.equal_mass) sm.flush_group(S.scr_m, base, cnt);
+              sk.flush_group(S.cand, base, cnt);
+              if (!EM) sm.flush_group(S.scr_m, base, cnt);
             }
-          } else if (S.shrink) {
-            add_sums(r, mr);
+            ++cnt;
           }
-          ++cnt;
-#pragma unroll
-          for (int k = 0; k < kBins; ++k) hk[k] += r2 < t2[k] ? 1 : 0;
         }
-      });
-    });
+      }
+      if (cnt & 3) {
+        sr.flush_group(S.scr_r, base, cnt - 1);
+        sk.flush_group(S.cand, base, cnt - 1);
+        if (!EM) sm.flush_group(S.scr_m, base, cnt - 1);
+      }
+    }
     if (mine) {
-      if (cnt > cap && S.shrink) {
-        for (int k = 0; k < cap; ++k) {  // the candidates that fitted
-          const int64_t e = group_at(base, k);
-          add_sums(S.scr_r[e], S.equal_mass ? R(1) : S.scr_m[e]);
-        }
-        const R C = R(Shape<K>::C), n_h3 = R(S.n_h3);
-        R rs = R(0);
-        int ns = 0;
-        if (C * fi - n_h3 > R(0)) {
-          rs = ri;
-          ns = cnt;
-        }
+      if (np > cap && S.shrink) {
+        // the smallest radius holding 1.3 times the target count, with room
+        // for what the padded test counted there
+        const double want = 1.3 * 4.18879020478639098 * S.n_h3;
+        double rs = (double)ri;
+        int ns = np;
+        double r = (double)ri;
 #pragma unroll
-        for (int k = 0; k < kBins; ++k)  // radii fall with k: keep the last one holding the root
-          if (C * fk[k] - n_h3 > R(0)) {
-            rs = rk[k];
-            ns = hk[k];
+        for (int q = 0; q < kBins; ++q) {
+          r *= 0.75;
+          if ((double)hk[q] >= want) {
+            rs = r;
+            ns = hk[q];
           }
-        if (rs > R(0)) {
-          S.rad[s] = rs;
-          S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
-        } else {  // the root lies beyond ri
-          const double g = grow_factor(S.n_h3, cnt);
-          S.rad[s] = (R)((double)ri * g);
-          S.need[s] = need_after_growth(cnt, g);
         }
+        S.rad[s] = (R)rs;
+        S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
         S.ccnt[s] = -1;
         retry = 1;
-      } else if (cnt > cap) {
-        S.need[s] = (cnt + 3) & ~3;  // fixed h: exactly the capacity it needs
+      } else if (np > cap) {
+        S.need[s] = (np + 3) & ~3;  // fixed h: the capacity it needs
         S.ccnt[s] = -1;
         retry = 1;
       } else {
-        if (cnt & 3) {
-          sr.flush_group(S.scr_r, base, cnt - 1);
-          if (!S.equal_mass) sm.flush_group(S.scr_m, base, cnt - 1);
-        }
         S.ccnt[s] = cnt;
       }
     }
@@ -370,63 +508,61 @@ __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __re
   atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 15) >> 4));
 }
 
-// Gather lists r_ij < h_i by a walk with each lane's own h. Every wave's
-// capacity (S.grow) comes from an upper bound of its counts; the counts are
-// stored in full, so an overflow (the host checks the largest) can be
-// rerun with exact capacities. Entries come in ascending j.
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_gather_tree(State<R> S) {
+// a[0 .. na) += v (the row offsets of a round, moved past the earlier rounds)
+__global__ void __launch_bounds__(kBlock) k_add_u32(uint32_t* __restrict__ a, int64_t na,
+                                                    uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < na) a[i] += v;
+}
+
+// Gather lists r_ij < h_i from the stored candidates of every particle (the
+// candidates hold every j with r_ij below the particle's radius, which is at
+// least its solved h). COUNT stores the lengths; WRITE (with per-wave
+// capacities from those lengths) writes the entries, in candidate order,
+// which is ascending j.
+template <class R, bool WRITE>
+__global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S) {
   const int64_t s = particle_id();
-  if ((s & ~(int64_t)63) >= S.n) return;  // whole wave past the end: it has no leaf
+  if ((s & ~(int64_t)63) >= S.n) return;
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
-  const R4<R> pi = S.pos4[sc];
-  const uint32_t ci = S.cell3[sc];
-  const R hi2 = pi.w * pi.w;
-  const int64_t wave = sc >> 6;
-  const int cap = (int)(S.grow[wave + 1] - S.grow[wave]) * 4;
-  const int64_t gb = slot_base(S.grow[wave], sc);
-  int ng = 0;
+  const int cnt = active ? S.ccnt[sc] : 0;
+  const uint32_t cp = S.cpos[sc];
+  const int64_t base = group_base((int64_t)(cp >> 6), (int64_t)(cp & 63u));
+  const R h = S.hbuf[sc];
+  int64_t gb = 0;
+  if (WRITE) gb = slot_base(S.grow[sc >> 6], sc);
   Stage4<uint32_t> sg;
-  float P[3];
-  abs_pos(S, ci, pi, P);
-  const float L = (float)S.box;
-  const float rp = active ? pad_radius((float)(R(1) / pi.w), L) : -1.f;
-  const float rp2 = rp * rp;
-  auto need = [&](float4 lo, float4 hi) { return active && point_gap2(P, lo, hi, L) < rp2; };
-  tree_walk(S, need, [&](int64_t leaf) {
-    leaf_tile(S, leaf, [&](uint32_t j, const R4<R>& pj, R mj, uint32_t cj) {
-      (void)mj;
-      if (!active || j == (uint32_t)s) return;
-      R x[3];
-      lattice_sep(S, pi, ci, pj, cj, x);
-      const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-      if (r2 * hi2 < R(1)) {
-        if (ng < cap) {
-          sg.put(ng & 3, j << kCodeBits);
+  int ng = 0;
+  for (int k = 0; k < cnt; k += 16) {
+    R rr[16];
+    uint32_t ee[16];
+    load_group(S.scr_r + group_at(base, k), rr);
+    if (WRITE) load_group(S.cand + group_at(base, k), ee);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (k + t < cnt && rr[t] < h) {
+        if (WRITE) {
+          sg.put(ng & 3, ee[t]);
           if ((ng & 3) == 3) sg.flush_at(S.nlist, gb, ng);
         }
         ++ng;
       }
-    });
-  });
-  unsigned long long g = 0, ovf = 0;
+    }
+  }
+  unsigned long long g = 0;
   if (active) {
-    const int st = ng < cap ? ng : cap;
-    if (st & 3) sg.flush_at(S.nlist, gb, st - 1);
-    S.ng[s] = ng;
-    g = (unsigned long long)ng;
-    if (ng > cap) ovf = (unsigned long long)ng;
+    if (WRITE) {
+      if (ng & 3) sg.flush_at(S.nlist, gb, ng - 1);
+      g = (unsigned long long)ng;
+    } else {
+      S.ng[s] = ng;
+    }
   }
+  if (WRITE) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    g += __shfl_xor(g, o, 64);
-    const unsigned long long a = __shfl_xor(ovf, o, 64);
-    ovf = a > ovf ? a : ovf;
-  }
-  if ((threadIdx.x & 63) == 0) {
-    if (g) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
-    if (ovf) atomicMax(cnt_at(S.cnt, CNT_LIST_OVERFLOW), ovf);
+    for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
+    if ((threadIdx.x & 63) == 0 && g) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
   }
 }
 
@@ -445,10 +581,10 @@ __global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cn
 
 // Scatter-only part of the symmetric list by transposing the gather lists:
 // j belongs to i's scatter-only list when i is in j's gather list
-// (r_ij < h_j) but j is not in i's (r_ij >= h_i). The separation is the same
-// expression with both signs flipped, so r_ij^2 is bit-identical from both
-// sides. COUNT adds to ns[i]; FILL appends j at fillc[i] (unordered, sorted
-// afterwards).
+// (r_ij < h_j) but j is not in i's (r_ij >= h_i). The separation is computed
+// as i's candidate walk computed it (x_ij from i's side) and r is its square
+// root, so the test here and i's gather filter decide alike. COUNT adds to
+// ns[i]; FILL appends j at fillc[i] (unordered, sorted afterwards).
 template <class R, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __restrict__ fillc) {
   const int64_t s = particle_id();
@@ -463,8 +599,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __rest
     const R4<R> pi = S.pos4[i];
     R x[3];
     lattice_sep(S, pi, S.cell3[i], pj, cj, x);
-    const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-    if (!(r2 * (pi.w * pi.w) < R(1))) {
+    const R r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    if (!(r < S.hbuf[i])) {
       if (FILL) {
         const int t = atomicAdd(&fillc[i], 1);
         const int64_t wi = (int64_t)(i >> 6);
@@ -517,8 +653,11 @@ void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const
                        hipStream_t s) {
   hipLaunchKernelGGL(k_leaf_boxes<R>, dim3(grid_for(host_cnt[0])), dim3(kBlock), 0, s, S, h);
   for (int l = 0; l + 1 < S.nlevels; ++l)
-    hipLaunchKernelGGL(k_tree_up, dim3(grid_for(host_cnt[l + 1])), dim3(kBlock), 0, s, S.nlo,
-                       S.nhi, host_off[l], host_cnt[l], host_off[l + 1], host_cnt[l + 1]);
+    hipLaunchKernelGGL(k_tree_up, dim3(grid_for(host_cnt[l + 1])), dim3(kBlock), 0, s, S.ncen,
+                       S.nhw, host_off[l], host_cnt[l], host_off[l + 1], host_cnt[l + 1]);
+  const int nnode = host_off[S.nlevels - 1] + host_cnt[S.nlevels - 1];
+  hipLaunchKernelGGL(k_box_centres, dim3(grid_for(nnode)), dim3(kBlock), 0, s, S.ncen, S.nhw,
+                     nnode);
 }
 
 template <class R>
@@ -528,10 +667,14 @@ void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s) {
 
 template <class R>
 void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s) {
-  if (kernel == 0)
-    hipLaunchKernelGGL((k_candidates_tree<R, 0>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
-  else
-    hipLaunchKernelGGL((k_candidates_tree<R, 1>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  const dim3 g(grid_for(S.n)), b(kBlock);
+  if (S.equal_mass) {
+    if (kernel == 0) hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S);
+    else hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S);
+  } else {
+    if (kernel == 0) hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S);
+    else hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S);
+  }
 }
 
 template <class R>
@@ -539,9 +682,17 @@ void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s) {
   hipLaunchKernelGGL(k_slot_rows<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, rows);
 }
 
+void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s) {
+  if (na > 0 && v)
+    hipLaunchKernelGGL(k_add_u32, dim3(grid_for(na)), dim3(kBlock), 0, s, a, na, v);
+}
+
 template <class R>
-void launch_gather_tree(const State<R>& S, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_tree<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+void launch_filter_tree(const State<R>& S, bool write, hipStream_t s) {
+  if (write)
+    hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  else
+    hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
 }
 
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s) {
@@ -566,7 +717,7 @@ void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
   template void launch_candidates_tree<R>(const State<R>&, int, hipStream_t);                \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
-  template void launch_gather_tree<R>(const State<R>&, hipStream_t);                         \
+  template void launch_filter_tree<R>(const State<R>&, bool, hipStream_t);                   \
   template void launch_scatter_tree<R>(const State<R>&, bool, int*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
