@@ -424,7 +424,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(ensure(ctx->nlo, 16 * (size_t)off), "alloc tree");
   CRK_HIP(ensure(ctx->nhi, 16 * (size_t)off), "alloc tree");
   CRK_HIP(ensure(ctx->lvl, 4 * 2 * kMaxLevels), "alloc tree");
-  CRK_HIP(ensure(ctx->rad, real_size(P.precision) * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->rad, real_size(P.precision) * 2 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->todo, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->tslot, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->need, 4 * (size_t)npad), "alloc tree");

@@ -440,8 +440,10 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
     if (cap_hit) {
       capped = 1;  // the root lies beyond the candidate radius
       if (S.rad) {
-        // tree path: grow the radius by what the candidate count suggests
+        // tree path: the root lies beyond this radius; grow it by what the
+        // candidate count suggests
         const double g = grow_factor(S.n_h3, cnt);
+        S.rad[S.n + s] = Rcap;
         S.rad[s] = (R)((double)Rcap * g);
         S.need[s] = max(S.need[s], need_after_growth(cnt, g));
       }

@@ -90,7 +90,8 @@ struct State {
   int scr_cap;
   int equal_mass;
   R rcap;
-  R* rad;             // per-particle candidate radius (tree path) or null
+  R* rad;             // per-particle candidate radius (tree path) or null; followed
+                      // (at rad + n) by the largest radius known to lie below the root
   int* need;          // per-particle candidate capacity request (tree path) or null
   int* todo;          // per-particle "h not solved yet" flag (tree path) or null
   // tree path: rank of each particle among the unsolved ones (its scratch

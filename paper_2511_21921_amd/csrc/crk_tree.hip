@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
   }
   if (active) {
     S.rad[s] = r;
+    S.rad[S.n + s] = R(0);  // no radius known below the root yet
     S.need[s] = S.scr_cap;
     S.todo[s] = 1;
   }
@@ -263,15 +264,15 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 //  2. Each lane takes its passed indices in order, computes the separation
 //     exactly (lattice offsets, as every later pass does) and keeps those
 //     within ri, compacting them in place with their distance.
-// A particle whose passed indices overflow its capacity is counted, with the
-// counts within ri 0.75^k, k = 1 .. 4 (from the padded test): the next round
-// uses the smallest of those radii holding 1.3 (4 pi / 3) n_h^3 candidates,
-// with capacity for its count (or, if none does, ri with the whole count);
-// a radius that then falls short of the h root is grown by the h solve. With
-// fixed h the capacity is raised.
+// A particle whose passed indices overflow its capacity is counted: the next
+// round takes the radius that would hold 1.3 (4 pi / 3) n_h^3 of them at the
+// density seen (at least half of ri), with capacity for 1.3 times what that
+// density gives there; a radius that then falls short of the h root is grown
+// by the h solve, and once that has happened radii only grow (an overflow
+// keeps the radius and raises the capacity), so the rounds end. With fixed h
+// the capacity is raised.
 template <class R, int K, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
-  constexpr int kBins = 4;
   constexpr int kRowBuf = 32;  // leaves a row buffers between batches
   __shared__ Levels lv;
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
@@ -303,28 +304,15 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
     const float inv_L = 1.0f / L;
     const float rp = mine ? pad_radius((float)ri, L) : -1.f;
     const float rp2 = mine ? rp * rp : -1.f;  // no box is nearer than -1
-    float t2[kBins];
-    int hk[kBins];
-    {
-      float r = rp;
-#pragma unroll
-      for (int k = 0; k < kBins; ++k) {
-        r *= 0.75f;
-        t2[k] = r * r;
-        hk[k] = 0;
-      }
-    }
     // ---- phase 1: walk, padded test, passed indices to the slot ----
     int np = 0;  // indices that passed
     Stage4<uint32_t> sj;
-    auto pass = [&](uint32_t j, float d2) {
+    auto pass = [&](uint32_t j) {
       if (np < cap) {
         sj.put(np & 3, j);
         if ((np & 3) == 3) sj.flush_group(S.cand, base, np);
       }
       ++np;
-#pragma unroll
-      for (int k = 0; k < kBins; ++k) hk[k] += d2 < t2[k] ? 1 : 0;
     };
     // the buffered leaves of every row, all rows in step
     int nbuf = 0;  // row-uniform
@@ -362,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
             const float dy = Q[1] - row_bcast<U>(A[1]);
             const float dz = Q[2] - row_bcast<U>(A[2]);
             const float d2 = dx * dx + dy * dy + dz * dz;
-            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U), d2);
+            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U));
           });
         } else {
           unroll16<0>([&](auto uc) {
@@ -374,7 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
               d[a] -= L * rintf(d[a] * inv_L);
             }
             const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U), d2);
+            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U));
           });
         }
       }
@@ -465,27 +453,22 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
       }
     }
     if (mine) {
-      if (np > cap && S.shrink) {
-        // the smallest radius holding 1.3 times the target count, with room
-        // for what the padded test counted there
+      if (np > cap && S.shrink && S.rad[S.n + s] == R(0)) {
+        // a radius holding about 1.3 times the target count at the density
+        // seen within ri (at least half of ri), with room for 1.3 times what
+        // that density gives there
         const double want = 1.3 * 4.18879020478639098 * S.n_h3;
-        double rs = (double)ri;
-        int ns = np;
-        double r = (double)ri;
-#pragma unroll
-        for (int q = 0; q < kBins; ++q) {
-          r *= 0.75;
-          if ((double)hk[q] >= want) {
-            rs = r;
-            ns = hk[q];
-          }
-        }
-        S.rad[s] = (R)rs;
+        const double f = fmax(cbrt(want / (double)np), 0.5);
+        S.rad[s] = (R)((double)ri * f);
+        const int ns = (int)(1.3 * (double)np * f * f * f) + 1;
         S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
         S.ccnt[s] = -1;
         retry = 1;
       } else if (np > cap) {
-        S.need[s] = (np + 3) & ~3;  // fixed h: the capacity it needs
+        // fixed h, or a radius that has already fallen short of the root
+        // once (from then on radii only grow): the same radius, with the
+        // capacity it needs
+        S.need[s] = (np + 3) & ~3;
         S.ccnt[s] = -1;
         retry = 1;
       } else {
