@@ -55,7 +55,7 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder;
   uint32_t host_rows[2] = {};
   int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
@@ -429,6 +429,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(ensure(ctx->tslot, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->need, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->cpos, 4 * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->torder, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(npad / 64 + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
   int lv[2 * kMaxLevels];
@@ -496,14 +497,22 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);
+    // the first round takes every particle in place; later ones only the
+    // unsolved, packed in rank order
+    const int64_t nt = ctx->host_rows[0];
+    const uint32_t* order = nullptr;
+    if (nt < n) {
+      launch_rank_order<R>(S, (uint32_t*)ctx->torder.p, s);
+      order = (const uint32_t*)ctx->torder.p;
+    }
     CRK_HIP(tbegin(ctx, P_CAND, s), "event");
-    launch_candidates_tree<R>(S, P.kernel, s);
+    launch_candidates_tree<R>(S, P.kernel, order, nt, s);
     CRK_HIP(tend(ctx, P_CAND, s), "event");
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     if (P.h_mode == 0)
-      launch_volume<R>(S, P.kernel, s);
+      launch_volume<R>(S, P.kernel, s, order, nt);
     else
-      launch_hsolve<R>(S, P.kernel, s);
+      launch_hsolve<R>(S, P.kernel, s, order, nt);
     CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
     row_base = rows_end;
@@ -1349,7 +1358,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
                 &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow,
-                &c->cpos};
+                &c->cpos, &c->torder};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)

@@ -412,9 +412,13 @@ __device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h,
 // f is non-decreasing in h; safeguarded Newton inside a bisection bracket,
 // stopping when a Newton step falls below the tolerance.
 
+// order (tree path retry rounds): thread t solves particle order[t], t < nt;
+// null: thread t solves particle t.
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
-  const int64_t s = particle_id();
+__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S, const uint32_t* __restrict__ order,
+                                                   int64_t nt) {
+  const int64_t t = particle_id();
+  const int64_t s = t < nt ? (order ? (int64_t)order[t] : t) : S.n;
   unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
   // tree path: only particles still to solve, whose candidate pass fitted
   const bool work = s < S.n && (!S.todo || (S.todo[s] && S.ccnt[s] >= 0));
@@ -498,8 +502,10 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
 
 // Fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included.
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
-  const int64_t s = particle_id();
+__global__ void __launch_bounds__(kBlock) k_volume(State<R> S, const uint32_t* __restrict__ order,
+                                                   int64_t nt) {
+  const int64_t t = particle_id();
+  const int64_t s = t < nt ? (order ? (int64_t)order[t] : t) : S.n;
   if (s >= S.n) return;
   if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
   if (S.todo) {
@@ -1167,12 +1173,22 @@ void launch_candidates(const State<R>& S, hipStream_t s) {
     hipLaunchKernelGGL((k_candidates<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
 }
 template <class R>
-void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {
-  CRK_DISPATCH_K(kernel, k_hsolve, S);
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s, const uint32_t* order,
+                   int64_t nt) {
+  if (nt < 0) nt = S.n;
+  if (nt == 0) return;
+  const dim3 g(grid_for(nt)), b(kBlock);
+  if (kernel == 0) hipLaunchKernelGGL((k_hsolve<R, 0>), g, b, 0, s, S, order, nt);
+  else hipLaunchKernelGGL((k_hsolve<R, 1>), g, b, 0, s, S, order, nt);
 }
 template <class R>
-void launch_volume(const State<R>& S, int kernel, hipStream_t s) {
-  CRK_DISPATCH_K(kernel, k_volume, S);
+void launch_volume(const State<R>& S, int kernel, hipStream_t s, const uint32_t* order,
+                   int64_t nt) {
+  if (nt < 0) nt = S.n;
+  if (nt == 0) return;
+  const dim3 g(grid_for(nt)), b(kBlock);
+  if (kernel == 0) hipLaunchKernelGGL((k_volume<R, 0>), g, b, 0, s, S, order, nt);
+  else hipLaunchKernelGGL((k_volume<R, 1>), g, b, 0, s, S, order, nt);
 }
 template <class R>
 void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s) {
@@ -1220,8 +1236,8 @@ void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long*
   template void launch_gather<R>(const State<R>&, const double*, const R*, const R*,         \
                                  const R*, const R*, hipStream_t);                           \
   template void launch_candidates<R>(const State<R>&, hipStream_t);                          \
-  template void launch_hsolve<R>(const State<R>&, int, hipStream_t);                         \
-  template void launch_volume<R>(const State<R>&, int, hipStream_t);                         \
+  template void launch_hsolve<R>(const State<R>&, int, hipStream_t, const uint32_t*, int64_t); \
+  template void launch_volume<R>(const State<R>&, int, hipStream_t, const uint32_t*, int64_t); \
   template void launch_pack<R>(const State<R>&, R*, R*, hipStream_t);                        \
   template void launch_nlist<R>(const State<R>&, hipStream_t);                               \
   template void launch_moments<R>(const State<R>&, int, CorrOut, hipStream_t);               \

@@ -26,8 +26,14 @@ void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const
                        hipStream_t s);
 template <class R>
 void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
+// The particles still to solve in rank order: order[cslot[s]] = s.
 template <class R>
-void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s);
+void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s);
+// Candidates of the unsolved particles; order null: thread t takes particle
+// t (all particles), else order[t] for t < nt.
+template <class R>
+void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
+                            hipStream_t s);
 template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 // a[0 .. na) += v
@@ -48,9 +54,11 @@ void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, c
 template <class R>
 void launch_candidates(const State<R>& S, hipStream_t s);
 template <class R>
-void launch_hsolve(const State<R>& S, int kernel, hipStream_t s);
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s,
+                   const uint32_t* order = nullptr, int64_t nt = -1);
 template <class R>
-void launch_volume(const State<R>& S, int kernel, hipStream_t s);
+void launch_volume(const State<R>& S, int kernel, hipStream_t s,
+                   const uint32_t* order = nullptr, int64_t nt = -1);
 // Stores 1/h and V into the packed records and writes h, V in caller order.
 template <class R>
 void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s);

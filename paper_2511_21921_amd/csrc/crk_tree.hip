@@ -272,7 +272,9 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 // keeps the radius and raises the capacity), so the rounds end. With fixed h
 // the capacity is raised.
 template <class R, int K, bool EM>
-__global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
+__global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
+                                                            const uint32_t* __restrict__ order,
+                                                            int64_t nt) {
   constexpr int kRowBuf = 32;  // leaves a row buffers between batches
   __shared__ Levels lv;
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
@@ -281,9 +283,12 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S) {
     lv.cnt[t] = S.lvl_off[kMaxLevels + t];
   }
   __syncthreads();
-  const int64_t s = particle_id();
-  if ((s & ~(int64_t)63) >= S.n) return;  // whole wave past the end
-  const bool active = s < S.n;
+  const int64_t t = particle_id();
+  if ((t & ~(int64_t)63) >= nt) return;  // whole wave past the end
+  const bool active = t < nt;
+  // this lane's particle: t itself, or the t-th still unsolved (retry
+  // rounds, so that a row holds 16 of them, close in the Morton order)
+  const int64_t s = active ? (order ? (int64_t)order[t] : t) : S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];
   const R ri = mine ? S.rad[sc] : R(0);
@@ -491,6 +496,13 @@ __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __re
   atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 15) >> 4));
 }
 
+// The unsolved particles in rank order.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_rank_order(State<R> S, uint32_t* __restrict__ order) {
+  const int64_t s = particle_id();
+  if (s < S.n && S.todo[s]) order[S.cslot[s]] = (uint32_t)s;
+}
+
 // a[0 .. na) += v (the row offsets of a round, moved past the earlier rounds)
 __global__ void __launch_bounds__(kBlock) k_add_u32(uint32_t* __restrict__ a, int64_t na,
                                                     uint32_t v) {
@@ -649,14 +661,25 @@ void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s) {
 }
 
 template <class R>
-void launch_candidates_tree(const State<R>& S, int kernel, hipStream_t s) {
-  const dim3 g(grid_for(S.n)), b(kBlock);
+void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s) {
+  hipLaunchKernelGGL(k_rank_order<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, order);
+}
+
+template <class R>
+void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
+                            hipStream_t s) {
+  if (nt <= 0) return;
+  const dim3 g(grid_for(nt)), b(kBlock);
   if (S.equal_mass) {
-    if (kernel == 0) hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S);
-    else hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S);
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, order, nt);
+    else
+      hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S, order, nt);
   } else {
-    if (kernel == 0) hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S);
-    else hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S);
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S, order, nt);
+    else
+      hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S, order, nt);
   }
 }
 
@@ -698,7 +721,9 @@ void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s
   template void launch_tree_build<R>(const State<R>&, const R*, const int*, const int*,      \
                                      hipStream_t);                                           \
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
-  template void launch_candidates_tree<R>(const State<R>&, int, hipStream_t);                \
+  template void launch_rank_order<R>(const State<R>&, uint32_t*, hipStream_t);              \
+  template void launch_candidates_tree<R>(const State<R>&, int, const uint32_t*, int64_t,    \
+                                          hipStream_t);                                      \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
   template void launch_filter_tree<R>(const State<R>&, bool, hipStream_t);                   \
   template void launch_scatter_tree<R>(const State<R>&, bool, int*, hipStream_t);
