@@ -109,6 +109,9 @@ typedef struct {
   int grid;                 /* cells per box side used by the cell list */
   int speculative;          /* 1: this forward ran on the previous one's cell-list geometry
                                and was accepted by its single end-of-call check */
+  long long n_candidates;   /* candidate pairs the neighbour search kept: the cell list's
+                               pairs within the cut of the solved h; the tree's pairs
+                               within each search radius, summed over its retry rounds */
 } crk_stats;
 
 /* Fills *p with the defaults for the given precision. */

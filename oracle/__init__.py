@@ -42,6 +42,8 @@ def lib():
         I64 = C.POINTER(C.c_int64)
         _lib.oracle_num_threads.argtypes = []
         _lib.oracle_num_threads.restype = C.c_int
+        _lib.oracle_set_threads.argtypes = [C.c_int]
+        _lib.oracle_set_threads.restype = None
         _lib.oracle_kernel_eval.argtypes = [C.c_int, C.c_int64, D, D, D, D]
         _lib.oracle_neighbours.argtypes = [C.c_int64, D, D, C.c_double, C.c_int, C.c_int, I64, I64]
         _lib.oracle_neighbours.restype = C.c_int
@@ -91,6 +93,11 @@ class Params:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (the benchmark's one-core timing)."""
+    lib().oracle_set_threads(int(n))
 
 
 def kernel_eval(kernel: int, q):

@@ -783,6 +783,16 @@ int forward_impl(int64_t n, const double* x, const double* v, const double* m, c
 
 extern "C" {
 
+// Threads of the OpenMP loops that follow (n >= 1); the benchmark times the
+// oracle on all host cores and on one.
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 // Threads the OpenMP loops use.
 int oracle_num_threads(void) {
 #ifdef _OPENMP

@@ -1,5 +1,8 @@
 """Oracle values of sampled particles of a large set, computed one by one.
 
+TEST INFRASTRUCTURE ONLY (tests/ and the benchmark's CPU-baseline leg), like the
+oracle itself.
+
 The forward outputs of particle i depend only on particles within a few
 smoothing lengths: its force neighbours j (r_ij < max(h_i, h_j)), their and
 its own gather neighbours k (r < h), and the gather neighbourhoods that fix
@@ -137,3 +140,35 @@ def separated_coordinates_jvp(ps, params, field, w_a, w_u, reach, grid=3, seed=0
     assert owner_d.max() < reach / ps.box, ("outputs moved beyond reach", owner_d.max(), reach)
     vals = np.bincount(owner, contrib[moved], minlength=parts.size)
     return parts, comps, vals
+
+
+def sample_candidates(ps, k, seed):
+    """2k candidate samples alternating uniform background and clump particles (the
+    clump generator puts the background first)."""
+    rng = np.random.default_rng(seed)
+    nb = ps.n // 2
+    bg = rng.choice(nb, k, replace=False)
+    cl = nb + rng.choice(ps.n - nb, k, replace=False)
+    return np.stack([bg, cl], axis=1).ravel()
+
+
+def densest(ps, k):
+    """The k clump particles with the smallest distance to their 64th neighbour: the
+    densest clump cores, where h is smallest and the tree walks go deepest."""
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    nb = ps.n // 2
+    r64 = cKDTree(x, boxsize=1.0).query(x[nb:], k=65, workers=-1)[0][:, 64]
+    return nb + np.argsort(r64)[:k]
+
+
+def sampled_oracle(ps, params, k, seed, dense=2, max_size=40000):
+    """k samples (each with a complete subset of at most max_size particles) plus the
+    `dense` densest core particles (any subset size), their subsets and oracle values."""
+    kept, subsets, o = complete_subsets(ps, sample_candidates(ps, 4 * k, seed), params,
+                                        want=k, max_size=max_size)
+    if dense:
+        kd, sd, od = complete_subsets(ps, densest(ps, dense), params)
+        kept = np.concatenate([kept, kd])
+        subsets = subsets + sd
+        o = {key: np.concatenate([o[key], od[key]], axis=-1) for key in o}
+    return kept, subsets, o

@@ -829,6 +829,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       State<R> S = make_state<R>(ctx, n);
       CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
       CRK_HIP(hipMemsetAsync(dcnt + CNT_LIST_OVERFLOW * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_CANDIDATES * kCntSpread, 0, 8 * kCntSpread, s), "memset");
       CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
       launch_nlist<R>(S, s);
       CRK_HIP(tend(ctx, P_NLIST, s), "event");
@@ -883,6 +884,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       stats->nonfinite = (int)hc[CNT_NONFINITE];
       stats->grid = ctx->G;
       stats->speculative = accepted ? 1 : 0;
+      stats->n_candidates = (long long)hc[CNT_CANDIDATES];
     }
     if (hc[CNT_H_UNCONV]) {
       result = CRK_ENOTCONV;

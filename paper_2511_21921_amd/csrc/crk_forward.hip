@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
   const int64_t s = particle_id();
-  unsigned long long g = 0, f = 0, ovf = 0, sovf = 0;
+  unsigned long long g = 0, f = 0, ovf = 0, sovf = 0, cands = 0;
   if (s < S.n) {
     // Classified by the stored candidate distance r: it is the same value
     // from both sides of a pair (the separation is computed with both signs
@@ -555,6 +555,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
     const int64_t base = scratch_base(S, s, ccap);
     // passive particles keep no lists (their force is not summed)
     const int cc = is_passive(S, s) ? 0 : (S.ccnt[s] < ccap ? S.ccnt[s] : ccap);
+    cands = (unsigned long long)cc;
     for (int k = 0; k < cc; k += 16) {
       const int64_t c = group_at(base, k);
       uint32_t ee[16];
@@ -598,6 +599,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
   }
   wave_add_u64(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
   wave_add_u64(cnt_at(S.cnt, CNT_PAIRS_FORCE), f);
+  wave_add_u64(cnt_at(S.cnt, CNT_CANDIDATES), cands);
   wave_max_u64(cnt_at(S.cnt, CNT_LIST_OVERFLOW), ovf);
   wave_max_u64(cnt_at(S.cnt, CNT_SLIST_OVERFLOW), sovf);
 }

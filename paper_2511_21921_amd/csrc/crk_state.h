@@ -31,6 +31,7 @@ enum Counter {
   CNT_HMAX_OUT_BITS,   // max solved h as double bits
   CNT_CELL_MAX,        // largest cell occupancy of the cell list
   CNT_TOO_DENSE,       // a cell beyond the occupancy limit of a speculative cell list
+  CNT_CANDIDATES,      // candidates kept by the neighbour search (all its passes)
   CNT_COUNT
 };
 

@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];
   const R ri = mine ? S.rad[sc] : R(0);
-  unsigned long long retry = 0;
+  unsigned long long retry = 0, kept = 0;
   const int rowid = (threadIdx.x & 63) >> 4;
   const uint64_t rowbits = 0xFFFFull << (16 * rowid);
   const int sub = threadIdx.x & 15;
@@ -478,12 +478,17 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         retry = 1;
       } else {
         S.ccnt[s] = cnt;
+        kept = (unsigned long long)cnt;
       }
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) retry += __shfl_xor(retry, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    retry += __shfl_xor(retry, o, 64);
+    kept += __shfl_xor(kept, o, 64);
+  }
   if ((threadIdx.x & 63) == 0 && retry) atomicAdd(cnt_at(S.cnt, CNT_RETRY), retry);
+  if ((threadIdx.x & 63) == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
 }
 
 // Capacity of every group of 64 scratch slots, in rows of 16-entry groups:

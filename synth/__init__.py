@@ -175,6 +175,9 @@ def plummer_clumps(n: int, n_clumps: int, k: int, box: float = 1.0) -> ParticleS
     h = np.full(n, n_h * (box ** 3 / n) ** (1.0 / 3.0))
     ps = ParticleSet("clumps%d" % round(n ** (1 / 3)), x, v, np.full(n, 1.0 / n), u, h, n_h, 1)
     ps.meta.update(n_clumps=n_clumps, clump_counts=counts, clump_a=a, clump_centres=centres)
+    # loss weights N(0, 1) from the fourth generator (the other draws are unaffected)
+    ps.w_a = rw.normal(size=(3, n))
+    ps.w_u = rw.normal(size=n)
     return ps
 
 

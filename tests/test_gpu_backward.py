@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a HIP device", allow_module_level=True)
 
 from tests import _gpu  # noqa: E402
-from tests._sampled import separated_coordinates_jvp  # noqa: E402
+from oracle.sampled import separated_coordinates_jvp  # noqa: E402
 
 
 def _grad(ps, precision, ctx=None, **kw):

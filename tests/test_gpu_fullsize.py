@@ -4,7 +4,7 @@ The 2.1M-particle clump set (FP32 forward) and the 16.8M-particle clump set
 (FP32 forward and adjoint with the corrections recomputed, one GPU's share of
 a large volume) are far beyond what the oracle runs whole. They are checked
 by (1) oracle values at sampled particles, computed on subsets that hold each
-sample's whole dependency chain (tests/_sampled.py); (2) oracle JVPs of a
+sample's whole dependency chain (oracle/sampled.py); (2) oracle JVPs of a
 loss whose weights sit on sampled particles only, which is then exact on the
 union of their subsets; (3) identities that hold at any size: momentum and
 energy conservation, the affine dependence of a and du/dt on (alpha, beta),
@@ -30,7 +30,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a HIP device", allow_module_level=True)
 
 from tests import _gpu  # noqa: E402
-from tests._sampled import complete_subsets, localized_jvp  # noqa: E402
+from oracle.sampled import localized_jvp, sampled_oracle  # noqa: E402
 
 SAMPLE_BOUNDS = {"h": 1e-5, "V": 2e-5, "rho": 2e-5, "A": 2e-5, "B/max": 2e-5, "gradA/max": 2e-5,
                  "gradB/max": 2e-5, "gradv/max": 2e-5, "accel_scaled_max": 5e-5,
@@ -53,38 +53,11 @@ def _conservation(ps, g):
     return mom, abs(e) / escale
 
 
-def _candidates(ps, k, seed):
-    """Candidate samples alternating uniform background and clump particles."""
-    rng = np.random.default_rng(seed)
-    nb = ps.n // 2  # the generator puts the background first
-    bg = rng.choice(nb, k, replace=False)
-    cl = nb + rng.choice(ps.n - nb, k, replace=False)
-    return np.stack([bg, cl], axis=1).ravel()
-
-
-def _densest(ps, k):
-    """The k clump particles with the smallest distance to their 64th neighbour: the
-    densest clump cores, where h is smallest and the tree walks go deepest."""
-    from scipy.spatial import cKDTree
-    x = np.mod(ps.x.T, ps.box) / ps.box
-    nb = ps.n // 2
-    r64 = cKDTree(x, boxsize=1.0).query(x[nb:], k=65, workers=-1)[0][:, 64]
-    return nb + np.argsort(r64)[:k]
-
-
 def _sampled_oracle(ps, k, seed, dense=2):
     """k samples (each with a complete subset of at most 40k particles) plus the `dense`
     densest core particles (any subset size), and their oracle values."""
-    p = oracle.params_for(ps)
-    kept, subsets, o = complete_subsets(ps, _candidates(ps, 4 * k, seed), p, want=k,
-                                        max_size=40000)
-    if dense:
-        kd, sd, od = complete_subsets(ps, _densest(ps, dense), p)
-        print("densest cores", kd.tolist(), "h", od["h"].tolist(), "subsets",
-              [q.size for q in sd], flush=True)
-        kept = np.concatenate([kept, kd])
-        subsets = subsets + sd
-        o = {key: np.concatenate([o[key], od[key]], axis=-1) for key in o}
+    kept, subsets, o = sampled_oracle(ps, oracle.params_for(ps), k, seed, dense=dense)
+    print("samples", kept.tolist(), "h", o["h"].tolist(), flush=True)
     return kept, subsets, o
 
 
