@@ -3,22 +3,30 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: the 64^3 = 262,144-particle Sedov-like jittered lattice (periodic
-unit box, u = 1e4 on the 27 sites nearest the centre, 1e-2 elsewhere,
-adaptive h for 64 neighbours, cubic spline) with N(0, 0.1) velocities and
-N(0, 1) loss weights, inputs resident in HBM. One step = one pass of the
-whole hot path: the forward (cell list, h solve and volume, neighbour list,
+Workload: clumps256, 256^3 = 16,777,216 gas particles in the periodic unit
+box, half uniform and half in 4096 Plummer clumps (log-normal clump masses,
+sigma 1 dex; scale radii uniform in 0.002-0.02), N(0, 0.05) velocities,
+log-normal u (sigma 0.5 dex), adaptive h for 64 neighbours (cubic spline;
+h spans ~30x), N(0, 1) loss weights: one GPU's share of a large-volume step,
+inputs resident in HBM. One step = one pass of the whole hot path: the
+forward (tree neighbour search with the h solve and volume, neighbour lists,
 moments + FP64 corrections, density / grad v / EOS, force and du/dt) and the
-adjoint of L = sum w_a . a + sum w_u du/dt (force, density, correction,
-moment and volume adjoints). value = ordered force pairs (j != i,
-r_ij < max(h_i, h_j)) per second of step wall time, FP32 pairs with FP64
-solve and accumulators. The same run reports the forward alone on the
-zero-velocity Sedov set, the same particles at the paper's gas resolution
-(Wendland C4, n_h = 4, ~268 neighbours), the plain FP64 GPU form, the error of the
-timed outputs against the FP64 oracle (values and one directional
-derivative), the roofline of the dominant kernel (from the library's
-HIP-event pass timers on the launch stream) and the oracle timed on the host
-cores. Prints exactly one JSON line on stdout.
+adjoint of L = sum w_a . a + sum w_u du/dt with the correction pass
+recomputed (store_corrections = 0). value = ordered force pairs (j != i,
+r_ij < max(h_i, h_j)) per second of step wall time; FP32 pairs with FP64
+correction solve and accumulators.
+
+The same run reports: the forward alone; the plain FP64 GPU form with its
+device memory; the errors of the timed outputs against the FP64 oracle at
+sampled particles (each computed on a subset that holds its whole
+dependency chain, so the oracle value is that of the full set) and of the
+gradient along a random direction (a loss localised on the samples); the
+roofline of the dominant kernel from the library's HIP-event pass timers on
+the launch stream; the oracle timed on the host cores on those subsets (all
+threads and one); and, as extra fields, the 64^3 Sedov-like lattice figures
+(forward + adjoint, forward, Wendland C4 at the paper's resolution, FP64),
+the time-step, hierarchy, cooling and deposition kernels. Prints exactly one
+JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -33,16 +41,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CRKSPH pair interactions/s (fwd, fwd+bwd) FP32 vs FP64 at rel err ≤1e-5"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
 
 # Algorithmic flops per unit of each pair pass (FMA = 2, add/mul/div/sqrt/
 # rsqrt = 1, one branch of the piecewise kernel): (flops, unit).
 FLOPS_PER_PAIR = {"force": (216, "pairs_force"), "bwd_force": (680, "pairs_force"),
-                  "moments": (109, "pairs_gather"), "density": (94, "pairs_gather")}
+                  "moments": (109, "pairs_gather"), "density": (94, "pairs_gather"),
+                  "bwd_density": (473, "pairs_gather"), "bwd_moments": (527, "pairs_gather")}
+# Algorithmic HBM bytes of the neighbour search: per particle a search takes,
+# its position record (16), lattice cell (4) and radius (4) read and its
+# candidate count (4) written; per candidate kept, its index and distance
+# (and the mass ratio where masses differ) written.
+SEARCH_BYTES_PER_PARTICLE = 28
+SEARCH_BYTES_PER_CANDIDATE = 8
+SEARCH_BYTES_PER_CANDIDATE_MASS = 4
 # Passes timed around exactly one kernel (the others group several).
-SINGLE_KERNEL = ("candidates", "hsolve", "nlist", "moments", "density", "force", "bwd_force",
+SINGLE_KERNEL = ("candidates", "hsolve", "moments", "density", "force", "bwd_force",
                  "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sedov64_v_fp32_traffic.md")
+PASS_NAMES = ("cells", "candidates", "hsolve", "nlist", "moments", "density", "force",
+              "bwd_force", "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume", "bwd_other")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "clumps256_fp32_traffic.md")
 
 
 def kernel_source_hash() -> str:
@@ -76,14 +94,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(ps, precision, steps, warmup, backward, kernel=0):
+def device_used() -> int:
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    return total - free
+
+
+def pass_ms(passes, name):
+    tot, calls = passes[name]
+    return tot / calls if calls else float("nan")
+
+
+def step_ms(passes, name, steps):
+    """Time of a pass per step (all its launches)."""
+    return passes[name][0] / steps
+
+
+def run_gpu(ps, precision, steps, warmup, backward, kernel=0, samples=None, grad_at=None):
+    """Times `steps` steps (forward, and the adjoint if backward) after `warmup`.
+
+    samples: particle indices whose forward outputs are returned (all when None).
+    grad_at: (U, w_a, w_u) - after timing, one more adjoint with loss weights w_a,
+    w_u (on the sampled particles only) whose gradients at the indices U are returned.
+    Returns ms per step, stats, pass times, outputs, device bytes the run added."""
     import numpy as np
     import torch
 
     from paper_2511_21921_amd import Context, Params
     dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    used0 = device_used()
     p = Params(box=ps.box, n_h=ps.n_h, h_mode=ps.h_mode, precision=precision, timing=1,
-               kernel=kernel)
+               kernel=kernel, store_corrections=0)
     ctx = Context(p)
     R = p.real
     t = lambda a, dt=R: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -108,14 +151,109 @@ def run_gpu(ps, precision, steps, warmup, backward, kernel=0):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     passes = ctx.pass_times(reset=True)
-    res = {k: val.cpu().numpy().astype(np.float64) for k, val in out.items()
+    dev_bytes = device_used() - used0
+    idx = None if samples is None else torch.as_tensor(samples, device=dev)
+    pick = (lambda a: a) if idx is None else (lambda a: a[..., idx])
+    res = {k: pick(val).cpu().numpy().astype(np.float64) for k, val in out.items()
            if isinstance(val, torch.Tensor)}
-    if backward:
+    if backward and samples is None:
         res.update({k: val.cpu().numpy() for k, val in g.items()})
+    if grad_at is not None:
+        U, gwa, gwu = grad_at
+        ui = torch.as_tensor(U, device=dev)
+        gl = ctx.backward(t(gwa, torch.float64), t(gwu, torch.float64))
+        res["grad_U"] = {k: (val[..., ui] if val.dim() and val.shape[-1] == ps.n else val)
+                         .cpu().numpy() for k, val in gl.items()}
+    del out, x, v, m, u, h, wa, wu
     ctx.close()
+    torch.cuda.synchronize()
     ms = (t1 - t0) * 1e3 / steps
-    return ms, stats, passes, res
+    return ms, stats, passes, res, dev_bytes
 
+
+def errors(g, o, h):
+    """Error of the GPU outputs g against oracle values o (same particles), scaled where a
+    value can vanish: relative for h, V, rho, A; against the largest oracle value (or 1/h,
+    1/h^2) for B, grad A, grad B, grad v; a and du/dt against the sum of the magnitudes of
+    their pair terms (the oracle's scale_a, scale_u) and as relative L2 norms."""
+    import numpy as np
+    rel_max = lambda a, b: float(np.max(np.abs(a / b - 1)))
+    rel_l2 = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    e = {k: rel_max(g[k], o[k]) for k in ("h", "V", "rho", "A")}
+    hmin = float(np.min(h))
+    for k, floor in (("B", 1 / hmin), ("gradA", 1 / hmin), ("gradB", 1 / hmin ** 2),
+                     ("gradv", 0.0)):
+        sc = max(float(np.abs(o[k]).max()), floor, 1e-300)
+        e[k + "/max"] = float(np.max(np.abs(g[k] - o[k])) / sc)
+    e["accel_relL2"] = rel_l2(g["accel"], o["accel"])
+    e["dudt_relL2"] = rel_l2(g["dudt"], o["dudt"])
+    e["accel_scaled_max"] = float(np.max(np.abs(g["accel"] - o["accel"]).max(0) /
+                                         np.maximum(o["scale_a"], 1e-300)))
+    e["dudt_scaled_max"] = float(np.max(np.abs(g["dudt"] - o["dudt"]) /
+                                        np.maximum(o["scale_u"], 1e-300)))
+    return {k: float("%.3e" % v) for k, v in e.items()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def roofline(ps, st, passes, steps):
+    """Roofline of the step's dominant kernel: the single-kernel pass with the largest
+    time per step, priced by its algorithmic model (bytes for the search, flops for the
+    pair passes); passes without a model fall back to the largest modelled one."""
+    import numpy as np
+    per_step = {k: step_ms(passes, k, steps) for k in SINGLE_KERNEL if passes[k][1]}
+    largest = max(per_step, key=per_step.get)
+    equal_mass = bool(np.all(ps.m == ps.m[0]))
+    cand_b = SEARCH_BYTES_PER_CANDIDATE + (0 if equal_mass else SEARCH_BYTES_PER_CANDIDATE_MASS)
+    models = {"candidates": ("hbm", SEARCH_BYTES_PER_PARTICLE * st["n_searched"] +
+                             cand_b * st["n_candidates"])}
+    for k, (f, unit) in FLOPS_PER_PAIR.items():
+        models[k] = ("alu", f * st["n_" + unit])
+    rk = largest if largest in models else max((k for k in models if k in per_step),
+                                               key=per_step.get)
+    bound, work = models[rk]
+    tot_ms, calls = passes[rk]
+    launches = calls // steps
+    sec = step_ms(passes, rk, steps) * 1e-3
+    tree = st["grid"] == 1024 and rk == "candidates"
+    kname = {"candidates": "k_candidates_tree" if tree else "k_candidates"}.get(rk, "k_" + rk)
+    traffic = traffic_bytes(kname)
+    if bound == "hbm":
+        achieved, peak, unit = work / sec / 1e9, PEAK_HBM_GBS, "GB/s"
+        model = ("%d B per particle searched (%d searched) + %d B per candidate kept (%d kept)"
+                 % (SEARCH_BYTES_PER_PARTICLE, st["n_searched"], cand_b, st["n_candidates"]))
+    else:
+        achieved, peak, unit = work / sec / 1e12, PEAK_FP32_TFLOPS, "TFLOP/s"
+        f, u = FLOPS_PER_PAIR[rk]
+        model = "%d flop per %s (%d)" % (f, u[:-1].replace("_", " "), st["n_" + u])
+    return {"bound": "alu" if bound == "alu" else "hbm", "kernel": kname,
+            "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "algorithmic_per_launch": round(work / launches),
+            "launches_per_step": launches, "kernel_ms_per_step": round(sec * 1e3, 3),
+            "model": model, "largest_pass": largest}
+
+
+def pass_table(passes, steps):
+    return {k: round(step_ms(passes, k, steps), 3) for k in PASS_NAMES if passes[k][1]}
+
+
+def pass_tflops(st, passes, steps):
+    return {k: round(f * st["n_" + u] / (step_ms(passes, k, steps) * 1e-3) / 1e12, 3)
+            for k, (f, u) in FLOPS_PER_PAIR.items() if passes[k][1]}
+
+
+# ---------------------------------------------------------------- extras ---
 
 # algorithmic HBM bytes per particle of the step's two elementwise kernels
 # (FP32 state, FP64 positions and forces): first kick + drift + h update reads
@@ -283,23 +421,188 @@ def run_deposit(ng, ns, steps, warmup, seed=12):
     return wall, dev_us
 
 
-def pass_ms(passes, name):
-    tot, calls = passes[name]
-    return tot / calls if calls else float("nan")
+def small_fields(args, cpu):
+    """The 64^3 Sedov-like lattice (262,144 particles): forward + adjoint, forward alone,
+    Wendland C4 at n_h = 4, FP64; errors against the oracle on the whole set when cpu."""
+    import numpy as np
+
+    import synth
+    from paper_2511_21921_amd import FP32, FP64
+    ps, ps0 = synth.sedov64_v(), synth.sedov64()
+    k = max(3, args.steps)
+    ms, st, passes, out, _ = run_gpu(ps, FP32, k, args.warmup, True)
+    msf, stf, passesf, outf, _ = run_gpu(ps0, FP32, k, args.warmup, False)
+    log("sedov64_v fp32 fwd+bwd %.3f ms, fwd %.3f ms" % (ms, msf))
+    r = {"workload": "sedov64_v: 64^3 = 262,144-particle jittered lattice, Sedov spike, "
+                     "N(0, 0.1) velocities, adaptive h (64 neighbours), cubic spline; forward "
+                     "+ adjoint (fwd: the same lattice at zero velocity, forward only)",
+         "value": st["n_pairs_force"] / (ms * 1e-3), "ms_per_step": round(ms, 4),
+         "pairs_force": st["n_pairs_force"], "pass_ms": pass_table(passes, k),
+         "pass_tflops": pass_tflops(st, passes, k),
+         "fwd_value": stf["n_pairs_force"] / (msf * 1e-3), "fwd_ms_per_step": round(msf, 4)}
+    psc = None
+    if not args.no_c4:
+        psc = synth.at_resolution(ps, 4.0)
+        kc = max(3, args.steps // 2)
+        msc, stc, passesc, outc, _ = run_gpu(psc, FP32, kc, args.warmup, True, kernel=1)
+        log("sedov64_v C4 n_h=4 fwd+bwd %.3f ms" % msc)
+        r["c4_268"] = {"value": stc["n_pairs_force"] / (msc * 1e-3), "ms_per_step": round(msc, 4),
+                       "workload": "sedov64_v particles with the Wendland C4 kernel at n_h = 4 "
+                                   "(~268 neighbours, the paper's gas resolution), forward + "
+                                   "adjoint", "pairs_force": stc["n_pairs_force"],
+                       "pass_ms": pass_table(passesc, kc)}
+    if not args.no_fp64:
+        k64 = max(3, args.steps // 2)
+        ms64, st64, _, _, _ = run_gpu(ps, FP64, k64, 1, True)
+        ms64f, _, _, _, _ = run_gpu(ps0, FP64, k64, 1, False)
+        log("sedov64_v fp64 fwd+bwd %.3f ms, fwd %.3f ms" % (ms64, ms64f))
+        r["fp64"] = {"value": st64["n_pairs_force"] / (ms64 * 1e-3), "ms_per_step": round(ms64, 4),
+                     "fp32_speedup": round(ms64 / ms, 3), "fwd_ms_per_step": round(ms64f, 4),
+                     "fwd_fp32_speedup": round(ms64f / msf, 3)}
+    if cpu:
+        import oracle
+        p = oracle.params_for(ps)
+        ref = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, p, nbr_mode=1)
+        ref0 = oracle.forward(ps0.x, ps0.v, ps0.m, ps0.u, ps0.h, oracle.params_for(ps0),
+                              nbr_mode=1)
+        rng = np.random.default_rng(11)
+        dx, dv = rng.normal(size=ps.x.shape), rng.normal(size=ps.x.shape)
+        du = rng.normal(size=ps.n) * ps.u
+        j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, p, dx, dv, du, 0.0, 0.0, nbr_mode=1)
+        jl = float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum())
+        gl = float((out["g_x"] * dx).sum() + (out["g_v"] * dv).sum() + (out["g_u"] * du).sum())
+        r["errors"] = errors(out, ref, ref["h"])
+        r["errors"]["grad_jvp_rel"] = float("%.3e" % (abs(gl - jl) / abs(jl)))
+        r["errors"]["fwd_accel_relL2"] = float("%.3e" % errors(outf, ref0, ref0["h"])[
+            "accel_relL2"])
+        if psc is not None:
+            refc = oracle.forward(psc.x, psc.v, psc.m, psc.u, psc.h,
+                                  oracle.params_for(psc, kernel=1), nbr_mode=1)
+            r["c4_268"]["errors"] = {k_: v_ for k_, v_ in errors(outc, refc, refc["h"]).items()
+                                     if k_ in ("accel_relL2", "dudt_relL2", "accel_scaled_max",
+                                               "dudt_scaled_max")}
+        log("sedov64_v errors", r["errors"])
+    return r, ps
+
+
+def extras(args, ps):
+    """Time integration, hierarchy, cooling and deposition around the passes."""
+    # kick-drift-kick steps at fixed h (the Thacker/continuity rate); dt is small
+    # enough that the ambient gas next to the Sedov spike (u = 1e-2, du/dt up to
+    # ~1e4 from its half of the pair work) stays positive over the timed steps
+    msk, stk, passesk = run_kdk(ps, args.steps, args.warmup, 1e-9)
+    step_us = pass_ms(passesk, "step") * 1e3  # two update launches per step
+    kdk = {"ms_per_step": round(msk, 4), "value": stk["n_pairs_force"] / (msk * 1e-3),
+           "unit": "interactions/s",
+           "workload": "sedov64_v, kick-drift-kick steps (dt = 1e-9, lambda = 0.5) with h "
+                       "integrated by the Thacker/continuity rate from the solved h",
+           "speculative_forwards": stk["speculative"],
+           "update_kernels": {"us_per_step": round(2 * step_us, 2),
+                              "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
+                              "GBps": round(STEP_BYTES_PER_PARTICLE * ps.n /
+                                            (2 * step_us * 1e-6) / 1e9, 1)}}
+    log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
+    hk = max(2, args.steps // 4)
+    msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
+    hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
+            "levels_0_1_2_3": hcount,
+            "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(s / "
+                        "median s)), 0, 3), s = c + |v| (eight substeps; passive "
+                        "particles skip the pair sums), against eight single-level "
+                        "steps of dt / 8"}
+    log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
+        % (msh, ms8, hcount))
+    ncool = 1 << 24
+    cus, ck = run_cool(ncool, args.steps, args.warmup)
+    cool_bps = COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6)
+    cool = {"us_per_launch": round(cus, 2), "value": ncool / (cus * 1e-6),
+            "unit": "particles/s",
+            "workload": "2^24 FP32 particles, u log-uniform over 7 decades, rho over 2; "
+                        "table of %d nodes at 0.004 dex, a broken power law with a stable "
+                        "zero" % ck,
+            "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
+                    "GBps": round(cool_bps / 1e9, 1),
+                    "frac_of_8TBps": round(cool_bps / 8e12, 3)}}
+    log("cooling: %.1f us for %d particles" % (cus, ncool))
+    ngas, nsrc = 1 << 21, 1 << 16
+    dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
+    dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
+           "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
+           "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 "
+                       "uniform sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair "
+                       "sort, two host reads"}
+    log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
+    return {"kdk_step": kdk, "hkdk_step": hkdk, "cooling": cool, "deposit": dep}
+
+
+def sampled_reference(ps, k, seed):
+    """Oracle values at k sampled particles of ps (plus the two densest clump cores), each
+    on a subset holding its whole dependency chain; the time it took."""
+    import oracle
+    from oracle.sampled import sampled_oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    kept, subsets, o = sampled_oracle(ps, oracle.params_for(ps), k, seed)
+    log("sampled oracle: %d samples, subsets %s, %.1f s"
+        % (kept.size, [s.size for s in subsets], time.perf_counter() - t0))
+    return kept, subsets, o
+
+
+def cpu_baseline(ps, subsets, budget_s=10.0):
+    """The oracle's forward on the complete sampled subsets, repeated until budget_s
+    (all threads), then on one thread until budget_s; ordered force pairs per second."""
+    import oracle
+    p = oracle.params_for(ps)
+
+    def run(budget):
+        pairs, spent, calls = 0, 0.0, 0
+        while spent < budget:
+            for s in subsets:
+                t0 = time.perf_counter()
+                r = oracle.forward(ps.x[:, s], ps.v[:, s], ps.m[s], ps.u[s], ps.h[s], p,
+                                   nbr_mode=1)
+                spent += time.perf_counter() - t0
+                pairs += r["pairs_force"]
+                calls += 1
+                if spent >= budget:
+                    break
+        return pairs / spent, spent, calls, pairs
+
+    threads = oracle.num_threads()
+    v_all, t_all, c_all, p_all = run(budget_s)
+    oracle.set_threads(1)
+    try:
+        v_one, t_one, c_one, p_one = run(budget_s)
+    finally:
+        oracle.set_threads(threads)
+    sizes = [s.size for s in subsets]
+    log("cpu oracle: %.3g pairs/s on %d threads, %.3g on one" % (v_all, threads, v_one))
+    return {"value": v_all, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": "clumps256, the FP64 forward of the oracle on the %d complete sampled "
+                      "subsets (%d-%d particles, each holding a sample's whole dependency "
+                      "chain, the two densest clump cores among them), %d subset calls, "
+                      "%d force pairs, %.1f s; forward only (the oracle's derivative is a "
+                      "forward-mode JVP)" % (len(sizes), min(sizes), max(sizes), c_all,
+                                             p_all, t_all),
+            "one_core": {"value": v_one, "cores": 1, "seconds": round(t_one, 2),
+                         "subset_calls": c_one},
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model()}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle: errors, gradient check and CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU forms")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 64^3 lattice fields and the extras (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the time-step, hierarchy, cooling and deposition fields "
-                         "(profiling runs of the forward + adjoint)")
-    ap.add_argument("--no-c4", action="store_true",
-                    help="skip the Wendland C4 n_h = 4 field (profiling runs of one workload)")
+                    help="skip the time-step, hierarchy, cooling and deposition fields")
+    ap.add_argument("--no-c4", action="store_true", help="skip the Wendland C4 n_h = 4 field")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with two plain 256 MiB device copies (untimed), the reference "
                          "for scaling the HBM byte counters of a profiling run")
@@ -316,176 +619,99 @@ def main():
     import synth
     from paper_2511_21921_amd import FP32, FP64
 
-    ps = synth.sedov64_v()
-    ps0 = synth.sedov64()
-    log("workload %s n=%d" % (ps.name, ps.n))
-    ms32, st32, passes32, out32 = run_gpu(ps, FP32, args.steps, args.warmup, True)
+    t0 = time.perf_counter()
+    ps = synth.clumps256()
+    log("workload %s n=%d (%.1f s)" % (ps.name, ps.n, time.perf_counter() - t0))
+    cpu = not args.no_cpu
+    kept = subsets = ref = None
+    grad_at = None
+    if cpu:
+        kept, subsets, ref = sampled_reference(ps, 8, 72)
+        U = np.unique(np.concatenate(subsets))
+        w_a = np.zeros((3, ps.n))
+        w_u = np.zeros(ps.n)
+        w_a[:, kept] = ps.w_a[:, kept]
+        w_u[kept] = ps.w_u[kept]
+        grad_at = (U, w_a, w_u)
+
+    ms32, st32, passes32, out32, mem32 = run_gpu(ps, FP32, args.steps, args.warmup, True,
+                                                 samples=kept, grad_at=grad_at)
     pairs = st32["n_pairs_force"]
-    log("fp32 fwd+bwd: %.3f ms/step, pairs %d, passes %s" % (ms32, pairs, passes32))
     value = pairs / (ms32 * 1e-3)
-    msf, stf, passesf, outf = run_gpu(ps0, FP32, args.steps, args.warmup, False)
-    log("fp32 fwd (v = 0): %.3f ms/step" % msf)
-    names = ("cells", "candidates", "hsolve", "nlist", "moments", "density", "force",
-             "bwd_force", "bwd_density", "bwd_corr", "bwd_moments", "bwd_volume", "bwd_other")
-    breakdown = {k: round(pass_ms(passes32, k), 4) for k in names}
-    flops = {k: f * st32["n_" + unit] for k, (f, unit) in FLOPS_PER_PAIR.items()}
-    pass_tflops = {k: round(f / (pass_ms(passes32, k) * 1e-3) / 1e12, 3) for k, f in flops.items()}
-    # dominant kernel: the longest single-kernel pass of the step
-    largest = max(SINGLE_KERNEL, key=lambda k: breakdown[k] if breakdown[k] == breakdown[k] else -1)
-    rk = largest if largest in flops else max(flops, key=lambda k: breakdown[k])
-    r_ms = pass_ms(passes32, rk)
-    achieved = flops[rk] / (r_ms * 1e-3) / 1e12
-    kname = "k_" + rk
-    traffic = traffic_bytes(kname)
-
-    # the paper's production resolution: Wendland C4, n_h = 4 (~268 neighbours)
-    c4 = None
-    if not args.no_c4:
-        psc = synth.at_resolution(ps, 4.0)
-        msc, stc, passesc, outc = run_gpu(psc, FP32, max(3, args.steps // 2), args.warmup, True,
-                                          kernel=1)
-        log("fp32 C4 n_h=4 fwd+bwd: %.3f ms/step" % msc)
-        c4 = {"value": stc["n_pairs_force"] / (msc * 1e-3), "ms_per_step": round(msc, 4),
-              "workload": "sedov64_v particles with the Wendland C4 kernel at n_h = 4 (~268 "
-                          "neighbours, the paper's gas resolution), forward + adjoint",
-              "pairs_force": stc["n_pairs_force"],
-              "pass_ms": {k: round(pass_ms(passesc, k), 4) for k in names}}
-
-    kdk = hkdk = cool = dep = None
-    if not args.no_extras:
-        # time integration around the passes: kick-drift-kick steps at fixed h
-        # (the Thacker/continuity rate); dt is small enough that the ambient gas next
-        # to the Sedov spike (u = 1e-2, du/dt up to ~1e4 from its half of the
-        # pair work) stays positive over the timed steps
-        msk, stk, passesk = run_kdk(ps, args.steps, args.warmup, 1e-9)
-        step_us = pass_ms(passesk, "step") * 1e3  # two update launches per step
-        kdk = {"ms_per_step": round(msk, 4), "value": stk["n_pairs_force"] / (msk * 1e-3),
-               "unit": "interactions/s",
-               "workload": "sedov64_v, kick-drift-kick steps (dt = 1e-9, lambda = 0.5) with h "
-                           "integrated by the Thacker/continuity rate from the solved h",
-               "speculative_forwards": stk["speculative"],
-               "update_kernels": {"us_per_step": round(2 * step_us, 2),
-                                  "bytes_per_particle": STEP_BYTES_PER_PARTICLE,
-                                  "GBps": round(STEP_BYTES_PER_PARTICLE * ps.n /
-                                                (2 * step_us * 1e-6) / 1e9, 1)}}
-        log("kdk step: %.3f ms, update kernels %.1f us" % (msk, 2 * step_us))
-
-        # timestep hierarchy (App. A.4): one big step on levels 0-3
-        hk = max(2, args.steps // 4)
-        msh, ms8, hcount = run_hkdk(ps, hk, 1, 8e-9)
-        hkdk = {"ms_per_big_step": round(msh, 4), "ms_per_8_single_level_steps": round(ms8, 4),
-                "levels_0_1_2_3": hcount,
-                "workload": "sedov64_v, one big step dt = 8e-9 on levels clip(ceil(log2(s / "
-                            "median s)), 0, 3), s = c + |v| (eight substeps; passive "
-                            "particles skip the pair sums), against eight single-level "
-                            "steps of dt / 8"}
-        log("hkdk step: %.3f ms per big step vs %.3f ms for 8 single-level steps, levels %s"
-            % (msh, ms8, hcount))
-
-        # exact-integration cooling (Sec. 2.2), 2^24 particles
-        ncool = 1 << 24
-        cus, ck = run_cool(ncool, args.steps, args.warmup)
-        cool_bps = COOL_BYTES_PER_PARTICLE * ncool / (cus * 1e-6)
-        cool = {"us_per_launch": round(cus, 2), "value": ncool / (cus * 1e-6),
-                "unit": "particles/s",
-                "workload": "2^24 FP32 particles, u log-uniform over 7 decades, rho over 2; "
-                            "table of %d nodes at 0.004 dex, a broken power law with a stable "
-                            "zero" % ck,
-                "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
-                        "GBps": round(cool_bps / 1e9, 1),
-                        "frac_of_8TBps": round(cool_bps / 8e12, 3)}}
-        log("cooling: %.1f us for %d particles" % (cus, ncool))
-
-        # subgrid deposition (App. A.2 eq. (Vsg), eq. (Anorm)): 2^21 gas, 2^16 sources
-        ngas, nsrc = 1 << 21, 1 << 16
-        dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
-        dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
-               "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
-               "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 "
-                           "uniform sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair "
-                           "sort, two host reads"}
-        log("deposit: %.1f us per call (device %.1f us)" % (dwall, ddev))
+    log("fp32 fwd+bwd: %.3f ms/step, %.4g pairs/s, %.1f GB, stats %s"
+        % (ms32, value, mem32 / 1e9, st32))
+    msf, stf, passesf, _, _ = run_gpu(ps, FP32, args.steps, args.warmup, False, samples=kept)
+    log("fp32 fwd: %.3f ms/step" % msf)
+    roof = roofline(ps, st32, passes32, args.steps)
+    log("roofline", roof)
 
     fp64 = None
     if not args.no_fp64:
-        k64 = max(3, args.steps // 2)
-        ms64, st64, passes64, _ = run_gpu(ps, FP64, k64, 1, True)
-        ms64f, _, _, _ = run_gpu(ps0, FP64, k64, 1, False)
-        log("fp64: fwd+bwd %.3f ms/step, fwd %.3f ms/step" % (ms64, ms64f))
+        k64 = max(2, args.steps // 4)
+        ms64, st64, passes64, out64, mem64 = run_gpu(ps, FP64, k64, 1, True, samples=kept)
+        log("fp64 fwd+bwd: %.3f ms/step, %.1f GB" % (ms64, mem64 / 1e9))
         fp64 = {"value": st64["n_pairs_force"] / (ms64 * 1e-3), "ms_per_step": round(ms64, 4),
-                "fp32_speedup": round(ms64 / ms32, 3),
-                "fwd_value": stf["n_pairs_force"] / (ms64f * 1e-3),
-                "fwd_ms_per_step": round(ms64f, 4), "fwd_fp32_speedup": round(ms64f / msf, 3),
-                "pass_ms": {k: round(pass_ms(passes64, k), 4) for k in names}}
+                "fp32_speedup": round(ms64 / ms32, 3), "device_GB": round(mem64 / 1e9, 2),
+                "steps": k64, "pass_ms": pass_table(passes64, k64)}
+        if cpu:
+            fp64["errors"] = errors(out64, ref, ref["h"])
 
-    cpu = None
     errs = None
-    if not args.no_cpu:
+    cpu_line = None
+    if cpu:
         import oracle
-        oracle.build(force=False)
-        # repeat the whole-workload forward until about 10 s of CPU work (at most 10 times)
-        reps, tc = 0, 0.0
-        while reps < 10 and (reps == 0 or tc < 10.0):
-            t0 = time.perf_counter()
-            ref = oracle.forward(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), nbr_mode=1)
-            tc += time.perf_counter() - t0
-            reps += 1
-        cpu = {"value": reps * ref["pairs_force"] / tc, "unit": "interactions/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "the whole workload, %d times: FP64 forward of all 262144 particles "
-                         "(%d force pairs, grid neighbour search), %.1f s in all; the oracle has "
-                         "no reverse mode, so this is a forward-only rate"
-                         % (reps, ref["pairs_force"], tc)}
-        ref0 = oracle.forward(ps0.x, ps0.v, ps0.m, ps0.u, ps0.h, oracle.params_for(ps0),
-                              nbr_mode=1)
-        rng = np.random.default_rng(11)
-        dx, dv = rng.normal(size=ps.x.shape), rng.normal(size=ps.x.shape)
-        du = rng.normal(size=ps.n) * ps.u
-        j = oracle.jvp(ps.x, ps.v, ps.m, ps.u, ps.h, oracle.params_for(ps), dx, dv, du, 0.0,
-                       0.0, nbr_mode=1)
-        jl = float((ps.w_a * j["d_accel"]).sum() + (ps.w_u * j["d_dudt"]).sum())
-        gl = float((out32["g_x"] * dx).sum() + (out32["g_v"] * dv).sum() +
-                   (out32["g_u"] * du).sum())
-        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-        errs = {"accel_relL2": rel(out32["accel"], ref["accel"]),
-                "dudt_relL2": rel(out32["dudt"], ref["dudt"]),
-                "grad_jvp_rel": abs(gl - jl) / abs(jl),
-                "fwd_accel_relL2": rel(outf["accel"], ref0["accel"]),
-                "h_relmax": float(np.max(np.abs(out32["h"] / ref["h"] - 1))),
-                "rho_relmax": float(np.max(np.abs(out32["rho"] / ref["rho"] - 1))),
-                "pairs_oracle": ref["pairs_force"]}
+        from oracle.sampled import localized_jvp
+        errs = errors(out32, ref, ref["h"])
+        U, w_a, w_u = grad_at
+        rng = np.random.default_rng(74)
+
+        def dirs(Us):
+            dx = rng.normal(size=(3, Us.size)) * 1e-3
+            dv = rng.normal(size=(3, Us.size))
+            du = rng.normal(size=Us.size) * ps.u[Us]
+            return dx, dv, du, 0.0, 0.0
+        t0 = time.perf_counter()
+        jl, Uj, (dx, dv, du, _, _) = localized_jvp(ps, kept, subsets, oracle.params_for(ps),
+                                                  w_a[:, kept], w_u[kept], dirs)
+        tj = time.perf_counter() - t0
+        g = out32["grad_U"]
+        gl = float((g["g_x"] * dx).sum() + (g["g_v"] * dv).sum() + (g["g_u"] * du).sum())
+        errs["grad_jvp_rel"] = float("%.3e" % (abs(gl - jl) / abs(jl)))
+        errs["samples"] = int(kept.size)
+        errs["jvp_particles"] = int(Uj.size)
+        errs["jvp_seconds"] = round(tj, 2)
         log("errors", errs)
-        if c4 is not None:
-            refc = oracle.forward(psc.x, psc.v, psc.m, psc.u, psc.h,
-                                  oracle.params_for(psc, kernel=1), nbr_mode=1)
-            c4["errors"] = {"accel_relL2": rel(outc["accel"], refc["accel"]),
-                            "dudt_relL2": rel(outc["dudt"], refc["dudt"]),
-                            "pairs_oracle": refc["pairs_force"]}
-            log("C4 errors", c4["errors"])
+        cpu_line = cpu_baseline(ps, subsets)
+
+    small = more = None
+    if not args.no_small:
+        small, ps64 = small_fields(args, cpu)
+        if not args.no_extras:
+            more = extras(args, ps64)
 
     line = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sedov64_v: 64^3=262144-particle jittered lattice, Sedov spike, "
-                               "N(0,0.1) velocities, adaptive h (64 neighbours), cubic spline; "
-                               "forward + adjoint of sum w_a.a + sum w_u.du/dt",
+        "config": {"workload": "clumps256: 256^3 = 16,777,216 particles, half uniform and half "
+                               "in 4096 Plummer clumps, N(0, 0.05) velocities, log-normal u, "
+                               "adaptive h (64 neighbours, ~30x range), cubic spline; forward "
+                               "+ adjoint of sum w_a.a + sum w_u.du/dt, corrections recomputed "
+                               "in the adjoint",
                    "n": ps.n, "pairs_force": pairs, "pairs_gather": st32["n_pairs_gather"],
-                   "step": "forward+backward"},
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None if traffic is None else round(traffic),
-                     "flops_per_unit": FLOPS_PER_PAIR[rk][0], "unit_count": FLOPS_PER_PAIR[rk][1],
-                     "kernel_ms": round(r_ms, 4), "largest_pass": largest},
+                   "step": "forward+backward", "search": "tree" if st32["grid"] == 1024
+                   else "cell list", "device_GB": round(mem32 / 1e9, 2)},
+        "roofline": roof,
+        "pass_ms": pass_table(passes32, args.steps),
+        "pass_tflops": pass_tflops(st32, passes32, args.steps),
         "fwd": {"value": stf["n_pairs_force"] / (msf * 1e-3), "ms_per_step": round(msf, 4),
-                "workload": "sedov64 (same particles, zero velocity), forward only",
-                "pass_ms": {k: round(pass_ms(passesf, k), 4) for k in names[:7]}},
-        "pass_ms": breakdown, "pass_tflops": pass_tflops,
-        "c4_268": c4, "kdk_step": kdk, "hkdk_step": hkdk, "cooling": cool, "deposit": dep,
-        "fp64": fp64, "errors": errs, "cpu_baseline": cpu,
+                "pass_ms": pass_table(passesf, args.steps)},
+        "fp64": fp64, "errors": errs, "cpu_baseline": cpu_line,
+        "sedov64": small,
     }
+    if more:
+        line.update(more)
     print(json.dumps(line), flush=True)
     if args.calibration_copy:
         import torch

@@ -112,6 +112,8 @@ typedef struct {
   long long n_candidates;   /* candidate pairs the neighbour search kept: the cell list's
                                pairs within the cut of the solved h; the tree's pairs
                                within each search radius, summed over its retry rounds */
+  long long n_searched;     /* particles the neighbour search launches took (n per cell-list
+                               search; the particles of every tree round) */
 } crk_stats;
 
 /* Fills *p with the defaults for the given precision. */

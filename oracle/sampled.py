@@ -34,18 +34,24 @@ def _dependency_set(tree_sub, xs, h, i):
     return np.fromiter(dep, dtype=np.int64)
 
 
+def unit_tree(ps):
+    """Positions mapped to the unit periodic box and their k-d tree."""
+    x = np.mod(ps.x.T, ps.box) / ps.box
+    return x, cKDTree(x, boxsize=1.0)
+
+
 def complete_subsets(ps, samples, params, grow=1.5, max_rounds=6, start=4.0, want=None,
-                     max_size=None):
+                     max_size=None, tree=None):
     """For sampled indices, balls of the full set on which the oracle's outputs
     at the sample are exact, and those outputs.
 
     samples are tried in order; with want, the first `want` that complete
     within max_size particles are kept (a candidate deep in a very massive
     clump would need a subset the oracle takes minutes on).
+    tree: unit_tree(ps), when the caller has it already.
     Returns (kept samples, list of subset index arrays, dict of sample outputs
     with the samples on the last axis)."""
-    x = np.mod(ps.x.T, ps.box) / ps.box
-    tree = cKDTree(x, boxsize=1.0)
+    x, tree = unit_tree(ps) if tree is None else tree
     k = min(65, ps.n)
     r64 = tree.query(x[samples], k=k)[0][:, k - 1]
     kept, subsets, per = [], [], []
@@ -152,22 +158,37 @@ def sample_candidates(ps, k, seed):
     return np.stack([bg, cl], axis=1).ravel()
 
 
-def densest(ps, k):
+def densest(ps, k, tree=None):
     """The k clump particles with the smallest distance to their 64th neighbour: the
-    densest clump cores, where h is smallest and the tree walks go deepest."""
-    x = np.mod(ps.x.T, ps.box) / ps.box
+    densest clump cores, where h is smallest and the tree walks go deepest.
+
+    A Plummer sphere's central density is proportional to N / a^3, so with the
+    generator's clump table only the 256 particles nearest the centres of the 16
+    clumps highest in N / a^3 are ranked; without it every clump particle is."""
+    x, tree = unit_tree(ps) if tree is None else tree
     nb = ps.n // 2
-    r64 = cKDTree(x, boxsize=1.0).query(x[nb:], k=65, workers=-1)[0][:, 64]
-    return nb + np.argsort(r64)[:k]
+    meta = getattr(ps, "meta", {})
+    if "clump_centres" in meta:
+        cen = np.asarray(meta["clump_centres"], dtype=np.float64)
+        cen = np.mod(cen.reshape(-1, 3) if cen.shape[-1] == 3 else cen.T, ps.box) / ps.box
+        rank = np.asarray(meta["clump_counts"]) / np.asarray(meta["clump_a"]) ** 3
+        top = np.argsort(rank)[::-1][:16]
+        near = np.unique(tree.query(cen[top], k=256)[1].ravel())
+        cand = near[near >= nb]
+    else:
+        cand = np.arange(nb, ps.n)
+    r64 = tree.query(x[cand], k=65, workers=-1)[0][:, 64]
+    return cand[np.argsort(r64)[:k]]
 
 
 def sampled_oracle(ps, params, k, seed, dense=2, max_size=40000):
     """k samples (each with a complete subset of at most max_size particles) plus the
     `dense` densest core particles (any subset size), their subsets and oracle values."""
+    tree = unit_tree(ps)
     kept, subsets, o = complete_subsets(ps, sample_candidates(ps, 4 * k, seed), params,
-                                        want=k, max_size=max_size)
+                                        want=k, max_size=max_size, tree=tree)
     if dense:
-        kd, sd, od = complete_subsets(ps, densest(ps, dense), params)
+        kd, sd, od = complete_subsets(ps, densest(ps, dense, tree), params, tree=tree)
         kept = np.concatenate([kept, kd])
         subsets = subsets + sd
         o = {key: np.concatenate([o[key], od[key]], axis=-1) for key in o}

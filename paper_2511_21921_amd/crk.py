@@ -42,7 +42,7 @@ class crk_stats(C.Structure):
                 ("h_iter_max", C.c_int), ("h_unconverged", C.c_int), ("m2_singular", C.c_int),
                 ("relaxed", C.c_int), ("nonfinite", C.c_int), ("grid", C.c_int),
                 ("speculative", C.c_int),
-                ("n_candidates", C.c_longlong)]
+                ("n_candidates", C.c_longlong), ("n_searched", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

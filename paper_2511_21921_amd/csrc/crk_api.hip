@@ -91,6 +91,7 @@ struct crk_ctx {
   int equal_mass = 0;
   // state of the last forward
   long long n_last = -1;
+  long long searched = 0;  // particles the last forward's neighbour searches took
   int G = 0;
   double ell = 0.0;
   double rcap = 0.0;
@@ -508,6 +509,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(tbegin(ctx, P_CAND, s), "event");
     launch_candidates_tree<R>(S, P.kernel, order, nt, s);
     CRK_HIP(tend(ctx, P_CAND, s), "event");
+    ctx->searched += nt;
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     if (P.h_mode == 0)
       launch_volume<R>(S, P.kernel, s, order, nt);
@@ -628,6 +630,7 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   CRK_HIP(tbegin(ctx, P_CAND, s), "event");
   launch_candidates<R>(S, s);
   CRK_HIP(tend(ctx, P_CAND, s), "event");
+  ctx->searched += n;
   CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
   if (P.h_mode == 0)
     launch_volume<R>(S, P.kernel, s);
@@ -690,6 +693,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
                         crk_stats* stats) {
   const crk_params& P = ctx->p;
   ctx->n_last = -1;
+  ctx->searched = 0;
   CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   bool accepted = false;
@@ -761,6 +765,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       CRK_HIP(tbegin(ctx, P_CAND, s), "event");
       launch_candidates<R>(S, s);
       CRK_HIP(tend(ctx, P_CAND, s), "event");
+      ctx->searched += n;
       CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
       if (P.h_mode == 0)
         launch_volume<R>(S, P.kernel, s);
@@ -885,6 +890,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       stats->grid = ctx->G;
       stats->speculative = accepted ? 1 : 0;
       stats->n_candidates = (long long)hc[CNT_CANDIDATES];
+      stats->n_searched = ctx->searched;
     }
     if (hc[CNT_H_UNCONV]) {
       result = CRK_ENOTCONV;

@@ -46,10 +46,10 @@ def test_struct_layouts_match_header(crk, tmp_path):
 #include <stddef.h>
 #include "crk.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(crk_params), offsetof(crk_params, h_rtol),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(crk_params), offsetof(crk_params, h_rtol),
          offsetof(crk_params, check_finite), offsetof(crk_params, search), sizeof(crk_stats),
          offsetof(crk_stats, grid), offsetof(crk_stats, speculative),
-         offsetof(crk_stats, n_candidates));
+         offsetof(crk_stats, n_candidates), offsetof(crk_stats, n_searched));
   return 0;
 }
 """)
@@ -59,7 +59,7 @@ int main(void) {
     want = [C.sizeof(crk.crk_params), crk.crk_params.h_rtol.offset,
             crk.crk_params.check_finite.offset, crk.crk_params.search.offset,
             C.sizeof(crk.crk_stats), crk.crk_stats.grid.offset, crk.crk_stats.speculative.offset,
-            crk.crk_stats.n_candidates.offset]
+            crk.crk_stats.n_candidates.offset, crk.crk_stats.n_searched.offset]
     assert got == want
 
 

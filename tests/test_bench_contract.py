@@ -31,10 +31,11 @@ def test_traffic_figure_follows_the_source_hash(monkeypatch):
         line = next(l for l in fh if l.startswith("traffic-json:"))
     t = json.loads(line.split(":", 1)[1])
     assert {"source_sha256", "fetch_factor", "write_factor", "kernels"} <= set(t)
-    k = t["kernels"]["k_bwd_force"]
+    name = sorted(t["kernels"])[0]
+    k = t["kernels"][name]
     want = 1024.0 * (k["fetch_kib"] * t["fetch_factor"] + k["write_kib"] * t["write_factor"])
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: t["source_sha256"])
-    assert bench.traffic_bytes("k_bwd_force") == pytest.approx(want)
+    assert bench.traffic_bytes(name) == pytest.approx(want)
     assert bench.traffic_bytes("no_such_kernel") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
-    assert bench.traffic_bytes("k_bwd_force") is None
+    assert bench.traffic_bytes(name) is None
