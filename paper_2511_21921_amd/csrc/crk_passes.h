@@ -30,7 +30,8 @@ void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
 template <class R>
 void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s);
 // Candidates of the unsolved particles; order null: thread t takes particle
-// t (all particles), else order[t] for t < nt.
+// t (all particles, 16 neighbouring particles per row sharing a walk), else
+// the 16-lane row t takes particle order[t] for t < nt.
 template <class R>
 void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
                             hipStream_t s);

@@ -491,6 +491,153 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   if ((threadIdx.x & 63) == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
 }
 
+// The same candidates for particles taken one per 16-lane row: the retry
+// rounds, whose unsolved particles lie too far apart for 16 of them to share
+// a walk (a row of scattered particles would test every lane against the
+// union of 16 disjoint neighbourhoods). The row walks the tree for the one
+// sphere with a node's children tested one per lane, tests a reached leaf's
+// particles one per lane, and appends the passed indices in order (a prefix
+// count over the row's ballot); phase 2 takes 16 passed indices at a time
+// across the row and compacts the kept ones in place. The capacity and the
+// overflow rules are those of k_candidates_tree.
+template <class R, int K, bool EM>
+__global__ void __launch_bounds__(kBlock) k_candidates_coop(State<R> S,
+                                                            const uint32_t* __restrict__ order,
+                                                            int64_t nt) {
+  __shared__ Levels lv;
+  for (int t = threadIdx.x; t < S.nlevels; t += kBlock) {
+    lv.off[t] = S.lvl_off[t];
+    lv.cnt[t] = S.lvl_off[kMaxLevels + t];
+  }
+  __syncthreads();
+  const int64_t tid = particle_id();
+  if (((tid & ~(int64_t)63) >> 4) >= nt) return;  // the wave's four rows past the end
+  const int64_t t = tid >> 4;                      // this row's rank in the round
+  const int lane = threadIdx.x & 63, sub = lane & 15, rowid = lane >> 4;
+  const uint64_t rowbits = 0xFFFFull << (16 * rowid);
+  const uint64_t below = rowbits & ((1ull << lane) - 1ull);  // row lanes before this one
+  const bool active = t < nt;
+  const int64_t s = active ? (int64_t)order[t] : S.n;
+  const int64_t sc = active ? s : 0;
+  const bool mine = active && S.todo[sc];  // uniform over the row
+  unsigned long long retry = 0, kept = 0;
+  if (__ballot(mine) != 0ull) {
+    const R ri = mine ? S.rad[sc] : R(0);
+    const R4<R> pi = S.pos4[sc];
+    const uint32_t ci = S.cell3[sc];
+    int cap = 0;
+    int64_t base = 0;
+    if (mine) base = scratch_base(S, sc, cap);
+    float P[3];
+    abs_pos(S, ci, pi, P);
+    const float L = (float)S.box;
+    const float inv_L = 1.0f / L;
+    const float rp = mine ? pad_radius((float)ri, L) : -1.f;
+    const float rp2 = mine ? rp * rp : -1.f;
+    // ---- phase 1: walk, padded tests, passed indices in order ----
+    int np = 0;  // uniform over the row
+    auto test_leaf = [&](int64_t leaf) {
+      const int64_t j0 = leaf * kLeaf;
+      const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
+      const bool valid = sub < m;
+      const int64_t j = j0 + (valid ? sub : 0);
+      float A[3];
+      abs_pos(S, S.cell3[j], S.pos4[j], A);
+      float d2 = 0.f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {  // nearest periodic image
+        float d = P[a] - A[a];
+        d -= L * rintf(d * inv_L);
+        d2 += d * d;
+      }
+      const bool pass = valid && d2 < rp2;
+      const uint64_t b = __ballot(pass) & rowbits;
+      const int at = np + __popcll(b & below);
+      if (pass && at < cap) S.cand[group_at(base, at)] = (uint32_t)j;
+      np += __popcll(b);
+    };
+    const int top = S.nlevels - 1;
+    int cur = 0, cur_level = top;  // the node whose children are tested next
+    uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
+    bool walking = mine && top > 0;
+    if (mine && top == 0) test_leaf(0);
+    while (__ballot(walking) != 0ull) {
+      if (walking) {
+        const int cl = cur_level - 1;
+        const int c0 = cur * kFan;
+        const int m = min(kFan, lv.cnt[cl] - c0);
+        const int node = lv.off[cl] + c0 + (sub < m ? sub : m - 1);
+        const bool h = sub < m && box_gap2(P, S.ncen[node], S.nhw[node], L, inv_L) < rp2;
+        const uint32_t mask = (uint32_t)((__ballot(h) & rowbits) >> (16 * rowid));
+        if (cl == 0) {
+          for (uint32_t mm = mask; mm; mm &= mm - 1u) test_leaf(c0 + __builtin_ctz(mm));
+        } else {
+          pend |= (uint64_t)mask << (8 * cl);
+        }
+        if (pend == 0ull) {
+          walking = false;
+        } else {  // the deepest pending child; its parent is an ancestor of cur
+          const int b = __builtin_ctzll(pend);
+          pend &= pend - 1;
+          const int lvl = b >> 3;
+          cur = ((cur >> (3 * (lvl + 1 - cur_level))) << 3) + (b & 7);
+          cur_level = lvl;
+        }
+      }
+    }
+    // ---- phase 2: exact separations, 16 passed indices at a time ----
+    int cnt = 0;  // uniform over the row
+    if (mine && np <= cap) {
+      const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
+      const R r2cap = ri * ri;
+      for (int k = 0; k < np; k += 16) {
+        const int e = k + sub;
+        const bool in = e < np;
+        const uint32_t j = in ? S.cand[group_at(base, e)] : (uint32_t)sc;
+        R x[3];
+        lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+        const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const bool keep = in && r2 < r2cap && j != (uint32_t)s;
+        // every lane of the row has read its entry (the ballot waits on
+        // it); a kept entry moves to a position at or before its own
+        const uint64_t b = __ballot(keep) & rowbits;
+        if (keep) {
+          const int64_t at = group_at(base, cnt + __popcll(b & below));
+          S.scr_r[at] = Sc<R>::sqrt(r2);
+          S.cand[at] = j << kCodeBits;
+          if (!EM) S.scr_m[at] = S.mass[j] * mi_inv;
+        }
+        cnt += __popcll(b);
+      }
+    }
+    if (mine && sub == 0) {
+      if (np > cap && S.shrink && S.rad[S.n + s] == R(0)) {
+        const double want = 1.3 * 4.18879020478639098 * S.n_h3;
+        const double f = fmax(cbrt(want / (double)np), 0.5);
+        S.rad[s] = (R)((double)ri * f);
+        const int ns = (int)(1.3 * (double)np * f * f * f) + 1;
+        S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
+        S.ccnt[s] = -1;
+        retry = 1;
+      } else if (np > cap) {
+        S.need[s] = (np + 3) & ~3;
+        S.ccnt[s] = -1;
+        retry = 1;
+      } else {
+        S.ccnt[s] = cnt;
+        kept = (unsigned long long)cnt;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    retry += __shfl_xor(retry, o, 64);
+    kept += __shfl_xor(kept, o, 64);
+  }
+  if (lane == 0 && retry) atomicAdd(cnt_at(S.cnt, CNT_RETRY), retry);
+  if (lane == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
+}
+
 // Capacity of every group of 64 scratch slots, in rows of 16-entry groups:
 // the largest request of the unsolved particles ranked into it (rows zeroed
 // beforehand).
@@ -674,7 +821,23 @@ template <class R>
 void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
                             hipStream_t s) {
   if (nt <= 0) return;
-  const dim3 g(grid_for(nt)), b(kBlock);
+  const dim3 b(kBlock);
+  if (order) {  // a row per particle
+    const dim3 g(grid_for(16 * nt));
+    if (S.equal_mass) {
+      if (kernel == 0)
+        hipLaunchKernelGGL((k_candidates_coop<R, 0, true>), g, b, 0, s, S, order, nt);
+      else
+        hipLaunchKernelGGL((k_candidates_coop<R, 1, true>), g, b, 0, s, S, order, nt);
+    } else {
+      if (kernel == 0)
+        hipLaunchKernelGGL((k_candidates_coop<R, 0, false>), g, b, 0, s, S, order, nt);
+      else
+        hipLaunchKernelGGL((k_candidates_coop<R, 1, false>), g, b, 0, s, S, order, nt);
+    }
+    return;
+  }
+  const dim3 g(grid_for(nt));
   if (S.equal_mass) {
     if (kernel == 0)
       hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, order, nt);
