@@ -8,16 +8,13 @@
 // kLeaf = 16 consecutive particles as a search leaf, and builds an implicit
 // tree of leaf boxes with kFan = 8 children per node (a node is named by its
 // level and index; its children are the kFan nodes that follow kFan times
-// its index one level down). The 16 particles of a leaf sit on the 16 lanes
-// of one DPP row and walk the tree together for the union of their spheres:
-// a step tests the children of one node against every lane's sphere and
-// keeps, as bits of one 64-bit word, the children still to visit at each
-// level, so the walk needs no stack and a row takes a few tens of dependent
-// steps. The particles of a reached leaf are loaded once (one per lane) and
-// broadcast across the row, and every lane tests each of them. Candidates
-// within a particle's radius are kept with their index and distance: the h
-// solve reads the distances, and the gather list is the candidates within
-// the solved h.
+// its index one level down). A particle's 16-lane row walks the tree for its
+// sphere: a step tests the children of one node (one per lane) and keeps, as
+// bits of one 64-bit word, the children still to visit at each level, so the
+// walk needs no stack. The particles of a reached leaf are tested one per
+// lane. Candidates within a particle's radius are kept with their index and
+// distance: the h solve reads the distances, and the gather list is the
+// candidates within the solved h.
 #include "crk_passes.h"
 
 namespace crk {
@@ -143,32 +140,6 @@ struct Levels {
   int off[kMaxLevels], cnt[kMaxLevels];
 };
 
-// Broadcast of lane u of every 16-lane row to the whole row (DPP row_newbcast).
-template <int U>
-__device__ inline int row_bcast(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, false);
-}
-template <int U>
-__device__ inline uint32_t row_bcast(uint32_t v) {
-  return (uint32_t)row_bcast<U>((int)v);
-}
-template <int U>
-__device__ inline float row_bcast(float v) {
-  return __int_as_float(row_bcast<U>(__float_as_int(v)));
-}
-template <int U>
-__device__ inline double row_bcast(double v) {
-  return __hiloint2double(row_bcast<U>(__double2hiint(v)), row_bcast<U>(__double2loint(v)));
-}
-
-template <int U, class F>
-__device__ inline void unroll16(F&& f) {
-  if constexpr (U < 16) {
-    f(std::integral_constant<int, U>());
-    unroll16<U + 1>(f);
-  }
-}
-
 // First candidate radius of every particle, kept small so that the first
 // walk stays cheap (particles whose h root lies beyond it grow it in later
 // rounds): the least of the h that the target count would need at the
@@ -250,20 +221,24 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 
 // Candidates of every unsolved particle within its own radius ri, written to
 // its scratch slot (list entry and distance; the mass ratio when masses
-// differ), in ascending j. Two phases:
-//  1. The 16 lanes of a DPP row (the particles of one leaf) walk the tree
-//     together: a step tests the children of the current node against every
-//     lane's sphere (a child is entered when some lane of the row reaches
-//     it), records the reached children as bits of pend (8 bits per level)
-//     and moves to the deepest pending one. The reached leaves are buffered
-//     per row in LDS; a batch of them is then taken by all rows in step: a
-//     leaf's particles are loaded one per lane, broadcast across the row as
-//     absolute FP32 positions and tested against the lane's sphere padded
-//     beyond their rounding. The indices that pass are written to the
-//     particle's slot.
-//  2. Each lane takes its passed indices in order, computes the separation
-//     exactly (lattice offsets, as every later pass does) and keeps those
-//     within ri, compacting them in place with their distance.
+// differ), in ascending j. A 16-lane row takes one particle (order null: row
+// t takes particle t; else order[t], the unsolved particles of a retry round
+// in rank order). Two phases:
+//  1. The row walks the tree for the particle's sphere: a step tests the
+//     kFan children of the current node one per lane (a child is entered
+//     when the sphere, padded beyond the FP32 rounding, reaches its box),
+//     records the reached children as bits of pend (8 bits per level) and
+//     moves to the deepest pending one, so the walk needs no stack. Reached
+//     leaves are queued per row in LDS and tested by all rows of the wave in
+//     step (a row's q-th queued leaf at step q), so that the wave's leaf
+//     tests take as many steps as its longest queue rather than, step by
+//     step of the walk, the most leaves any row reached. A leaf's 16
+//     particles are tested one per lane against the padded sphere as
+//     absolute FP32 positions; the passed indices are appended to the slot
+//     in order (prefix counts over the row's ballot).
+//  2. The row takes 16 passed indices at a time, one per lane, computes the
+//     separation exactly (lattice offsets, as every later pass does) and
+//     compacts those within ri in place with their distance.
 // A particle whose passed indices overflow its capacity is counted: the next
 // round takes the radius that would hold 1.3 (4 pi / 3) n_h^3 of them at the
 // density seen (at least half of ri), with capacity for 1.3 times what that
@@ -271,253 +246,32 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 // by the h solve, and once that has happened radii only grow (an overflow
 // keeps the radius and raises the capacity), so the rounds end. With fixed h
 // the capacity is raised.
+// A row per particle rather than 16 particles sharing a walk: rows of
+// neighbouring particles test every lane against the union of 16 spheres
+// (about eight times the particles of one sphere, most of them rejected),
+// and the retry rounds' rows of scattered particles the union of 16
+// disjoint neighbourhoods.
 template <class R, int K, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
                                                             const uint32_t* __restrict__ order,
                                                             int64_t nt) {
-  constexpr int kRowBuf = 32;  // leaves a row buffers between batches
   __shared__ Levels lv;
+  for (int t = threadIdx.x; t < S.nlevels; t += kBlock) {
+    lv.off[t] = S.lvl_off[t];
+    lv.cnt[t] = S.lvl_off[kMaxLevels + t];
+  }
+  __syncthreads();
+  constexpr int kRowBuf = 32;  // leaves a row queues between drains
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
-  for (int t = threadIdx.x; t < S.nlevels; t += kBlock) {
-    lv.off[t] = S.lvl_off[t];
-    lv.cnt[t] = S.lvl_off[kMaxLevels + t];
-  }
-  __syncthreads();
-  const int64_t t = particle_id();
-  if ((t & ~(int64_t)63) >= nt) return;  // whole wave past the end
-  const bool active = t < nt;
-  // this lane's particle: t itself, or the t-th still unsolved (retry
-  // rounds, so that a row holds 16 of them, close in the Morton order)
-  const int64_t s = active ? (order ? (int64_t)order[t] : t) : S.n;
-  const int64_t sc = active ? s : 0;
-  const bool mine = active && S.todo[sc];
-  const R ri = mine ? S.rad[sc] : R(0);
-  unsigned long long retry = 0, kept = 0;
-  const int rowid = (threadIdx.x & 63) >> 4;
-  const uint64_t rowbits = 0xFFFFull << (16 * rowid);
-  const int sub = threadIdx.x & 15;
-  uint32_t* rbuf = lbuf[threadIdx.x >> 4];
-  if (__ballot(mine) != 0ull) {
-    const R4<R> pi = S.pos4[sc];
-    const uint32_t ci = S.cell3[sc];
-    int cap = 0;
-    int64_t base = 0;
-    if (mine) base = scratch_base(S, sc, cap);
-    float P[3];
-    abs_pos(S, ci, pi, P);
-    const float L = (float)S.box;
-    const float inv_L = 1.0f / L;
-    const float rp = mine ? pad_radius((float)ri, L) : -1.f;
-    const float rp2 = mine ? rp * rp : -1.f;  // no box is nearer than -1
-    // ---- phase 1: walk, padded test, passed indices to the slot ----
-    int np = 0;  // indices that passed
-    Stage4<uint32_t> sj;
-    auto pass = [&](uint32_t j) {
-      if (np < cap) {
-        sj.put(np & 3, j);
-        if ((np & 3) == 3) sj.flush_group(S.cand, base, np);
-      }
-      ++np;
-    };
-    // the buffered leaves of every row, all rows in step
-    int nbuf = 0;  // row-uniform
-    auto batch = [&]() {
-      // the leaves lane 0 of each row wrote are read by the whole row: keep
-      // the wave's LDS accesses in program order
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int q = 0; __ballot(q < nbuf) != 0ull; ++q) {
-        const bool has = q < nbuf;
-        const int64_t leaf = has ? rbuf[q] : 0;
-        const int64_t j0 = leaf * kLeaf;
-        const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
-        const int64_t jl = j0 + (sub < m ? sub : m - 1);
-        float A[3];
-        abs_pos(S, S.cell3[jl], S.pos4[jl], A);
-        // the image of the lane's particle nearest the leaf's centre serves
-        // every particle of the leaf within the sphere when the leaf's
-        // half-widths stay below L/2 - rp (always, but in tiny boxes of few
-        // particles); otherwise each particle takes its own nearest image
-        const float4 lc = S.ncen[leaf], lw = S.nhw[leaf];
-        const float half = 0.5f * L - rp;
-        const bool wide = lw.x > half || lw.y > half || lw.z > half;
-        float Q[3] = {P[0], P[1], P[2]};
-        {
-          const float cc[3] = {lc.x, lc.y, lc.z};
-#pragma unroll
-          for (int a = 0; a < 3; ++a) Q[a] += L * rintf((cc[a] - P[a]) * inv_L);
-        }
-        if (__ballot(wide) == 0ull) {
-          unroll16<0>([&](auto uc) {
-            constexpr int U = decltype(uc)::value;
-            const float dx = Q[0] - row_bcast<U>(A[0]);
-            const float dy = Q[1] - row_bcast<U>(A[1]);
-            const float dz = Q[2] - row_bcast<U>(A[2]);
-            const float d2 = dx * dx + dy * dy + dz * dz;
-            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U));
-          });
-        } else {
-          unroll16<0>([&](auto uc) {
-            constexpr int U = decltype(uc)::value;
-            float d[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {  // nearest periodic image
-              d[a] = P[a] - row_bcast<U>(A[a]);
-              d[a] -= L * rintf(d[a] * inv_L);
-            }
-            const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (has && U < m && d2 < rp2) pass((uint32_t)(j0 + U));
-          });
-        }
-      }
-      __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
-      nbuf = 0;
-    };
-    // the row's walk (identical in its 16 lanes)
-    const int top = S.nlevels - 1;
-    const bool row_work = (__ballot(mine) & rowbits) != 0ull;
-    int cur = 0, cur_level = top;  // the node whose children are tested next
-    uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
-    bool walking = row_work && top > 0;
-    if (row_work && top == 0) {  // a one-leaf tree: the root
-      if (sub == 0) rbuf[0] = 0;
-      nbuf = 1;
-    }
-    while (__ballot(walking) != 0ull) {
-      if (walking) {
-        const int cl = cur_level - 1;
-        const int c0 = cur * kFan;
-        const int m = min(kFan, lv.cnt[cl] - c0);
-        const int nb = lv.off[cl] + c0;
-        bool h[kFan];
-#pragma unroll
-        for (int c = 0; c < kFan; ++c) {  // missing children repeat the last one, unused
-          const int node = nb + (c < m ? c : m - 1);
-          h[c] = c < m && box_gap2(P, S.ncen[node], S.nhw[node], L, inv_L) < rp2;
-        }
-        uint32_t mask = 0;
-#pragma unroll
-        for (int c = 0; c < kFan; ++c)
-          if ((__ballot(h[c]) & rowbits) != 0ull) mask |= 1u << c;
-        if (cl == 0) {
-          for (; mask; mask &= mask - 1u) {  // the reached leaves, to the row's buffer
-            if (sub == 0) rbuf[nbuf] = (uint32_t)(c0 + __builtin_ctz(mask));
-            ++nbuf;
-          }
-        } else {
-          pend |= (uint64_t)mask << (8 * cl);
-        }
-        if (pend == 0ull) {
-          walking = false;
-        } else {  // the deepest pending child; its parent is an ancestor of cur
-          const int b = __builtin_ctzll(pend);
-          pend &= pend - 1;
-          const int lvl = b >> 3;
-          cur = ((cur >> (3 * (lvl + 1 - cur_level))) << 3) + (b & 7);
-          cur_level = lvl;
-        }
-      }
-      if (__ballot(nbuf > kRowBuf - kFan) != 0ull) batch();  // a buffer that could overflow
-    }
-    batch();
-    // ---- phase 2: exact separations of the passed indices, in place ----
-    int cnt = 0;
-    if (np <= cap) {
-      Stage4<R> sr, sm;
-      Stage4<uint32_t> sk;
-      const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
-      const R r2cap = ri * ri;
-      if (np & 3) sj.flush_group(S.cand, base, np - 1);  // the last partial chunk
-      for (int k = 0; k < np; k += 16) {
-        uint32_t jj[16];
-        load_group(S.cand + group_at(base, k), jj);  // read before this group is rewritten
-        for (int t = 0; t < 16 && k + t < np; ++t) {
-          const uint32_t j = jj[t];
-          R x[3];
-          lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
-          const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-          if (r2 < r2cap && j != (uint32_t)s) {
-            const int slot = cnt & 3;
-            sr.put(slot, Sc<R>::sqrt(r2));
-            sk.put(slot, j << kCodeBits);
-            if (!EM) sm.put(slot, S.mass[j] * mi_inv);
-            if (slot == 3) {
-              sr.flush_group(S.scr_r, base, cnt);
-              sk.flush_group(S.cand, base, cnt);
-              if (!EM) sm.flush_group(S.scr_m, base, cnt);
-            }
-            ++cnt;
-          }
-        }
-      }
-      if (cnt & 3) {
-        sr.flush_group(S.scr_r, base, cnt - 1);
-        sk.flush_group(S.cand, base, cnt - 1);
-        if (!EM) sm.flush_group(S.scr_m, base, cnt - 1);
-      }
-    }
-    if (mine) {
-      if (np > cap && S.shrink && S.rad[S.n + s] == R(0)) {
-        // a radius holding about 1.3 times the target count at the density
-        // seen within ri (at least half of ri), with room for 1.3 times what
-        // that density gives there
-        const double want = 1.3 * 4.18879020478639098 * S.n_h3;
-        const double f = fmax(cbrt(want / (double)np), 0.5);
-        S.rad[s] = (R)((double)ri * f);
-        const int ns = (int)(1.3 * (double)np * f * f * f) + 1;
-        S.need[s] = ((ns > 4 ? ns : 4) + 3) & ~3;
-        S.ccnt[s] = -1;
-        retry = 1;
-      } else if (np > cap) {
-        // fixed h, or a radius that has already fallen short of the root
-        // once (from then on radii only grow): the same radius, with the
-        // capacity it needs
-        S.need[s] = (np + 3) & ~3;
-        S.ccnt[s] = -1;
-        retry = 1;
-      } else {
-        S.ccnt[s] = cnt;
-        kept = (unsigned long long)cnt;
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    retry += __shfl_xor(retry, o, 64);
-    kept += __shfl_xor(kept, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0 && retry) atomicAdd(cnt_at(S.cnt, CNT_RETRY), retry);
-  if ((threadIdx.x & 63) == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
-}
-
-// The same candidates for particles taken one per 16-lane row: the retry
-// rounds, whose unsolved particles lie too far apart for 16 of them to share
-// a walk (a row of scattered particles would test every lane against the
-// union of 16 disjoint neighbourhoods). The row walks the tree for the one
-// sphere with a node's children tested one per lane, tests a reached leaf's
-// particles one per lane, and appends the passed indices in order (a prefix
-// count over the row's ballot); phase 2 takes 16 passed indices at a time
-// across the row and compacts the kept ones in place. The capacity and the
-// overflow rules are those of k_candidates_tree.
-template <class R, int K, bool EM>
-__global__ void __launch_bounds__(kBlock) k_candidates_coop(State<R> S,
-                                                            const uint32_t* __restrict__ order,
-                                                            int64_t nt) {
-  __shared__ Levels lv;
-  for (int t = threadIdx.x; t < S.nlevels; t += kBlock) {
-    lv.off[t] = S.lvl_off[t];
-    lv.cnt[t] = S.lvl_off[kMaxLevels + t];
-  }
-  __syncthreads();
   const int64_t tid = particle_id();
   if (((tid & ~(int64_t)63) >> 4) >= nt) return;  // the wave's four rows past the end
   const int64_t t = tid >> 4;                      // this row's rank in the round
   const int lane = threadIdx.x & 63, sub = lane & 15, rowid = lane >> 4;
   const uint64_t rowbits = 0xFFFFull << (16 * rowid);
   const uint64_t below = rowbits & ((1ull << lane) - 1ull);  // row lanes before this one
+  uint32_t* rbuf = lbuf[threadIdx.x >> 4];
   const bool active = t < nt;
-  const int64_t s = active ? (int64_t)order[t] : S.n;
+  const int64_t s = active ? (order ? (int64_t)order[t] : t) : S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];  // uniform over the row
   unsigned long long retry = 0, kept = 0;
@@ -556,11 +310,30 @@ __global__ void __launch_bounds__(kBlock) k_candidates_coop(State<R> S,
       if (pass && at < cap) S.cand[group_at(base, at)] = (uint32_t)j;
       np += __popcll(b);
     };
+    // Reached leaves are queued per row in LDS and tested by all rows in
+    // step (a row's q-th queued leaf at step q), so that a wave's leaf tests
+    // take as many steps as its longest queue rather than, step by step of
+    // the walk, the most leaves any row reached.
+    int nbuf = 0;  // uniform over the row
+    auto drain = [&]() {
+      // the entries the row's lanes wrote are read by the whole row: keep
+      // the wave's LDS accesses in program order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int q = 0; __ballot(q < nbuf) != 0ull; ++q)
+        if (q < nbuf) test_leaf(rbuf[q]);
+      __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
+      nbuf = 0;
+    };
     const int top = S.nlevels - 1;
     int cur = 0, cur_level = top;  // the node whose children are tested next
     uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
     bool walking = mine && top > 0;
-    if (mine && top == 0) test_leaf(0);
+    if (mine && top == 0) {
+      if (sub == 0) rbuf[0] = 0;
+      nbuf = 1;
+    }
     while (__ballot(walking) != 0ull) {
       if (walking) {
         const int cl = cur_level - 1;
@@ -568,9 +341,11 @@ __global__ void __launch_bounds__(kBlock) k_candidates_coop(State<R> S,
         const int m = min(kFan, lv.cnt[cl] - c0);
         const int node = lv.off[cl] + c0 + (sub < m ? sub : m - 1);
         const bool h = sub < m && box_gap2(P, S.ncen[node], S.nhw[node], L, inv_L) < rp2;
-        const uint32_t mask = (uint32_t)((__ballot(h) & rowbits) >> (16 * rowid));
-        if (cl == 0) {
-          for (uint32_t mm = mask; mm; mm &= mm - 1u) test_leaf(c0 + __builtin_ctz(mm));
+        const uint64_t hb = __ballot(h) & rowbits;
+        const uint32_t mask = (uint32_t)(hb >> (16 * rowid));
+        if (cl == 0) {  // the reached leaves, in order, to the row's queue
+          if (h) rbuf[nbuf + __popcll(hb & below)] = (uint32_t)(c0 + sub);
+          nbuf += __popc(mask);
         } else {
           pend |= (uint64_t)mask << (8 * cl);
         }
@@ -584,7 +359,9 @@ __global__ void __launch_bounds__(kBlock) k_candidates_coop(State<R> S,
           cur_level = lvl;
         }
       }
+      if (__ballot(nbuf > kRowBuf - kFan) != 0ull) drain();  // a queue that could overflow
     }
+    drain();
     // ---- phase 2: exact separations, 16 passed indices at a time ----
     int cnt = 0;  // uniform over the row
     if (mine && np <= cap) {
@@ -821,23 +598,7 @@ template <class R>
 void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
                             hipStream_t s) {
   if (nt <= 0) return;
-  const dim3 b(kBlock);
-  if (order) {  // a row per particle
-    const dim3 g(grid_for(16 * nt));
-    if (S.equal_mass) {
-      if (kernel == 0)
-        hipLaunchKernelGGL((k_candidates_coop<R, 0, true>), g, b, 0, s, S, order, nt);
-      else
-        hipLaunchKernelGGL((k_candidates_coop<R, 1, true>), g, b, 0, s, S, order, nt);
-    } else {
-      if (kernel == 0)
-        hipLaunchKernelGGL((k_candidates_coop<R, 0, false>), g, b, 0, s, S, order, nt);
-      else
-        hipLaunchKernelGGL((k_candidates_coop<R, 1, false>), g, b, 0, s, S, order, nt);
-    }
-    return;
-  }
-  const dim3 g(grid_for(nt));
+  const dim3 g(grid_for(16 * nt)), b(kBlock);  // a 16-lane row per particle
   if (S.equal_mass) {
     if (kernel == 0)
       hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, order, nt);
