@@ -55,7 +55,7 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder, absp;
   uint32_t host_rows[2] = {};
   int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
@@ -431,6 +431,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(ensure(ctx->need, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->cpos, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->torder, 4 * (size_t)npad), "alloc tree");
+  CRK_HIP(ensure(ctx->absp, 16 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(npad / 64 + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
   int lv[2 * kMaxLevels];
@@ -449,7 +450,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   {
     State<R> S = make_state<R>(ctx, n);
     launch_gather<R>(S, x, v, m, u, h, s);
-    launch_tree_build<R>(S, S.hbuf, ctx->lvl_off, ctx->lvl_cnt, s);
+    launch_tree_build<R>(S, S.hbuf, (float4*)ctx->absp.p, ctx->lvl_off, ctx->lvl_cnt, s);
     launch_init_radius<R>(S, P.h_mode, s);
   }
   CRK_HIP(tend(ctx, P_CELLS, s), "event");
@@ -507,7 +508,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       order = (const uint32_t*)ctx->torder.p;
     }
     CRK_HIP(tbegin(ctx, P_CAND, s), "event");
-    launch_candidates_tree<R>(S, P.kernel, order, nt, s);
+    launch_candidates_tree<R>(S, (const float4*)ctx->absp.p, P.kernel, order, nt, s);
     CRK_HIP(tend(ctx, P_CAND, s), "event");
     ctx->searched += nt;
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
@@ -1366,7 +1367,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
                 &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow,
-                &c->cpos, &c->torder};
+                &c->cpos, &c->torder, &c->absp};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)

@@ -22,8 +22,8 @@ void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint3
                    hipStream_t s);
 // Leaf boxes (with the largest h of each leaf, from h) and the node levels.
 template <class R>
-void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const int* host_cnt,
-                       hipStream_t s);
+void launch_tree_build(const State<R>& S, const R* h, float4* absp, const int* host_off,
+                       const int* host_cnt, hipStream_t s);
 template <class R>
 void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
 // The particles still to solve in rank order: order[cslot[s]] = s.
@@ -33,8 +33,8 @@ void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s);
 // t (all particles, 16 neighbouring particles per row sharing a walk), else
 // the 16-lane row t takes particle order[t] for t < nt.
 template <class R>
-void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
-                            hipStream_t s);
+void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
+                            const uint32_t* order, int64_t nt, hipStream_t s);
 template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 // a[0 .. na) += v

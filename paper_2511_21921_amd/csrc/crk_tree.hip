@@ -53,9 +53,11 @@ __device__ inline void abs_pos(const State<R>& S, uint32_t c3, const R4<R>& p, f
   a[2] = ((float)(c3 >> 20) + 0.5f) * ell + (float)p.z;
 }
 
-// Leaf boxes (absolute positions, FP32) and the largest h of each leaf.
+// Leaf boxes (absolute positions, FP32) and the largest h of each leaf; the
+// absolute positions themselves go to absp (the search's leaf tests).
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __restrict__ h) {
+__global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __restrict__ h,
+                                                       float4* __restrict__ absp) {
   const int64_t leaf = particle_id();
   const int nleaf = S.lvl_off[kMaxLevels];  // level 0 count
   if (leaf >= nleaf) return;
@@ -64,6 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __re
   for (int64_t s = b; s < e; ++s) {
     float v[3];
     abs_pos(S, S.cell3[s], S.pos4[s], v);
+    absp[s] = make_float4(v[0], v[1], v[2], 0.f);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       lo[a] = fminf(lo[a], v[a]);
@@ -98,22 +101,6 @@ __global__ void __launch_bounds__(kBlock) k_box_centres(float4* __restrict__ lo_
   const float4 lo = lo_c[k], hi = hi_w[k];
   lo_c[k] = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z), lo.w);
   hi_w[k] = make_float4(0.5f * (hi.x - lo.x), 0.5f * (hi.y - lo.y), 0.5f * (hi.z - lo.z), 0.f);
-}
-
-// Squared periodic distance from point a to the box of centre c and
-// half-widths w: the distance to the box grows with that to its centre, so
-// the centre's nearest image gives the nearest image of the box.
-__device__ inline float box_gap2(const float a[3], float4 c, float4 w, float L, float inv_L) {
-  const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
-  float g2 = 0.f;
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    float d = cc[t] - a[t];
-    d -= L * rintf(d * inv_L);
-    const float g = fmaxf(fabsf(d) - ww[t], 0.f);
-    g2 += g * g;
-  }
-  return g2;
 }
 
 // Radius widened against the FP32 rounding of positions and node boxes.
@@ -253,6 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 // disjoint neighbourhoods.
 template <class R, int K, bool EM>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
+                                                            const float4* __restrict__ absp,
                                                             const uint32_t* __restrict__ order,
                                                             int64_t nt) {
   __shared__ Levels lv;
@@ -290,78 +278,106 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     const float rp2 = mine ? rp * rp : -1.f;
     // ---- phase 1: walk, padded tests, passed indices in order ----
     int np = 0;  // uniform over the row
-    auto test_leaf = [&](int64_t leaf) {
-      const int64_t j0 = leaf * kLeaf;
-      const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
-      const bool valid = sub < m;
-      const int64_t j = j0 + (valid ? sub : 0);
-      float A[3];
-      abs_pos(S, S.cell3[j], S.pos4[j], A);
-      float d2 = 0.f;
+    // A sphere that stays a padded radius away from every face of the box
+    // reaches no periodic image (box centres and positions lie in the box),
+    // so its tests need no nearest-image shift; rows whose sphere crosses a
+    // face take it (wave-uniform choice).
+    bool inside = true;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {  // nearest periodic image
-        float d = P[a] - A[a];
-        d -= L * rintf(d * inv_L);
-        d2 += d * d;
-      }
-      const bool pass = valid && d2 < rp2;
-      const uint64_t b = __ballot(pass) & rowbits;
-      const int at = np + __popcll(b & below);
-      if (pass && at < cap) S.cand[group_at(base, at)] = (uint32_t)j;
-      np += __popcll(b);
-    };
-    // Reached leaves are queued per row in LDS and tested by all rows in
-    // step (a row's q-th queued leaf at step q), so that a wave's leaf tests
-    // take as many steps as its longest queue rather than, step by step of
-    // the walk, the most leaves any row reached.
-    int nbuf = 0;  // uniform over the row
-    auto drain = [&]() {
-      // the entries the row's lanes wrote are read by the whole row: keep
-      // the wave's LDS accesses in program order
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int q = 0; __ballot(q < nbuf) != 0ull; ++q)
-        if (q < nbuf) test_leaf(rbuf[q]);
-      __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
-      nbuf = 0;
-    };
-    const int top = S.nlevels - 1;
-    int cur = 0, cur_level = top;  // the node whose children are tested next
-    uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
-    bool walking = mine && top > 0;
-    if (mine && top == 0) {
-      if (sub == 0) rbuf[0] = 0;
-      nbuf = 1;
-    }
-    while (__ballot(walking) != 0ull) {
-      if (walking) {
-        const int cl = cur_level - 1;
-        const int c0 = cur * kFan;
-        const int m = min(kFan, lv.cnt[cl] - c0);
-        const int node = lv.off[cl] + c0 + (sub < m ? sub : m - 1);
-        const bool h = sub < m && box_gap2(P, S.ncen[node], S.nhw[node], L, inv_L) < rp2;
-        const uint64_t hb = __ballot(h) & rowbits;
-        const uint32_t mask = (uint32_t)(hb >> (16 * rowid));
-        if (cl == 0) {  // the reached leaves, in order, to the row's queue
-          if (h) rbuf[nbuf + __popcll(hb & below)] = (uint32_t)(c0 + sub);
-          nbuf += __popc(mask);
-        } else {
-          pend |= (uint64_t)mask << (8 * cl);
+    for (int a = 0; a < 3; ++a) inside = inside && P[a] > rp + 1e-5f * L && P[a] < L - rp - 1e-5f * L;
+    auto phase1 = [&](auto wrap_t) {
+      constexpr bool WRAP = decltype(wrap_t)::value;
+      auto box2 = [&](float4 c, float4 w) {  // squared gap to the box of centre c
+        const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
+        float g2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float d = cc[a] - P[a];
+          if constexpr (WRAP) d -= L * rintf(d * inv_L);
+          const float g = fmaxf(fabsf(d) - ww[a], 0.f);
+          g2 += g * g;
         }
-        if (pend == 0ull) {
-          walking = false;
-        } else {  // the deepest pending child; its parent is an ancestor of cur
-          const int b = __builtin_ctzll(pend);
-          pend &= pend - 1;
-          const int lvl = b >> 3;
-          cur = ((cur >> (3 * (lvl + 1 - cur_level))) << 3) + (b & 7);
-          cur_level = lvl;
+        return g2;
+      };
+      auto point2 = [&](float4 c) {  // squared distance to point c
+        const float cc[3] = {c.x, c.y, c.z};
+        float d2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float d = cc[a] - P[a];
+          if constexpr (WRAP) d -= L * rintf(d * inv_L);
+          d2 += d * d;
         }
+        return d2;
+      };
+      auto test_leaf = [&](int64_t leaf) {
+        const int64_t j0 = leaf * kLeaf;
+        const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
+        const bool valid = sub < m;
+        const int64_t j = j0 + (valid ? sub : 0);
+        const bool pass = valid && point2(absp[j]) < rp2;
+        const uint64_t b = __ballot(pass) & rowbits;
+        const int at = np + __popcll(b & below);
+        if (pass && at < cap) S.cand[group_at(base, at)] = (uint32_t)j;
+        np += __popcll(b);
+      };
+      // Reached leaves are queued per row in LDS and tested by all rows in
+      // step (a row's q-th queued leaf at step q), so that a wave's leaf tests
+      // take as many steps as its longest queue rather than, step by step of
+      // the walk, the most leaves any row reached.
+      int nbuf = 0;  // uniform over the row
+      auto drain = [&]() {
+        // the entries the row's lanes wrote are read by the whole row: keep
+        // the wave's LDS accesses in program order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = 0; __ballot(q < nbuf) != 0ull; ++q)
+          if (q < nbuf) test_leaf(rbuf[q]);
+        __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
+        nbuf = 0;
+      };
+      const int top = S.nlevels - 1;
+      int cur = 0, cur_level = top;  // the node whose children are tested next
+      uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
+      bool walking = mine && top > 0;
+      if (mine && top == 0) {
+        if (sub == 0) rbuf[0] = 0;
+        nbuf = 1;
       }
-      if (__ballot(nbuf > kRowBuf - kFan) != 0ull) drain();  // a queue that could overflow
-    }
-    drain();
+      while (__ballot(walking) != 0ull) {
+        if (walking) {
+          const int cl = cur_level - 1;
+          const int c0 = cur * kFan;
+          const int m = min(kFan, lv.cnt[cl] - c0);
+          const int node = lv.off[cl] + c0 + (sub < m ? sub : m - 1);
+          const bool h = sub < m && box2(S.ncen[node], S.nhw[node]) < rp2;
+          const uint64_t hb = __ballot(h) & rowbits;
+          const uint32_t mask = (uint32_t)(hb >> (16 * rowid));
+          if (cl == 0) {  // the reached leaves, in order, to the row's queue
+            if (h) rbuf[nbuf + __popcll(hb & below)] = (uint32_t)(c0 + sub);
+            nbuf += __popc(mask);
+          } else {
+            pend |= (uint64_t)mask << (8 * cl);
+          }
+          if (pend == 0ull) {
+            walking = false;
+          } else {  // the deepest pending child; its parent is an ancestor of cur
+            const int b = __builtin_ctzll(pend);
+            pend &= pend - 1;
+            const int lvl = b >> 3;
+            cur = ((cur >> (3 * (lvl + 1 - cur_level))) << 3) + (b & 7);
+            cur_level = lvl;
+          }
+        }
+        if (__ballot(nbuf > kRowBuf - kFan) != 0ull) drain();  // a queue that could overflow
+      }
+      drain();
+    };
+    if (__ballot(!inside) == 0ull)
+      phase1(std::false_type());
+    else
+      phase1(std::true_type());
     // ---- phase 2: exact separations, 16 passed indices at a time ----
     int cnt = 0;  // uniform over the row
     if (mine && np <= cap) {
@@ -573,9 +589,10 @@ void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint3
 }
 
 template <class R>
-void launch_tree_build(const State<R>& S, const R* h, const int* host_off, const int* host_cnt,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_leaf_boxes<R>, dim3(grid_for(host_cnt[0])), dim3(kBlock), 0, s, S, h);
+void launch_tree_build(const State<R>& S, const R* h, float4* absp, const int* host_off,
+                       const int* host_cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_leaf_boxes<R>, dim3(grid_for(host_cnt[0])), dim3(kBlock), 0, s, S, h,
+                     absp);
   for (int l = 0; l + 1 < S.nlevels; ++l)
     hipLaunchKernelGGL(k_tree_up, dim3(grid_for(host_cnt[l + 1])), dim3(kBlock), 0, s, S.ncen,
                        S.nhw, host_off[l], host_cnt[l], host_off[l + 1], host_cnt[l + 1]);
@@ -595,20 +612,20 @@ void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s) {
 }
 
 template <class R>
-void launch_candidates_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
-                            hipStream_t s) {
+void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
+                            const uint32_t* order, int64_t nt, hipStream_t s) {
   if (nt <= 0) return;
   const dim3 g(grid_for(16 * nt)), b(kBlock);  // a 16-lane row per particle
   if (S.equal_mass) {
     if (kernel == 0)
-      hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, order, nt);
+      hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, absp, order, nt);
     else
-      hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S, order, nt);
+      hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S, absp, order, nt);
   } else {
     if (kernel == 0)
-      hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S, order, nt);
+      hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S, absp, order, nt);
     else
-      hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S, order, nt);
+      hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S, absp, order, nt);
   }
 }
 
@@ -647,12 +664,12 @@ void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s
 }
 
 #define CRK_INSTANTIATE_TREE(R)                                                               \
-  template void launch_tree_build<R>(const State<R>&, const R*, const int*, const int*,      \
+  template void launch_tree_build<R>(const State<R>&, const R*, float4*, const int*, const int*,      \
                                      hipStream_t);                                           \
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
   template void launch_rank_order<R>(const State<R>&, uint32_t*, hipStream_t);              \
-  template void launch_candidates_tree<R>(const State<R>&, int, const uint32_t*, int64_t,    \
-                                          hipStream_t);                                      \
+  template void launch_candidates_tree<R>(const State<R>&, const float4*, int,               \
+                                          const uint32_t*, int64_t, hipStream_t);            \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
   template void launch_filter_tree<R>(const State<R>&, bool, hipStream_t);                   \
   template void launch_scatter_tree<R>(const State<R>&, bool, int*, hipStream_t);
