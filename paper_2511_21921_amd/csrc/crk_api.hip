@@ -555,29 +555,20 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
     return hipStreamSynchronize(s);
   };
   CRK_HIP(tbegin(ctx, P_NLIST, s), "event");
-  {
-    State<R> S = make_state<R>(ctx, n);
-    launch_filter_tree<R>(S, false, s);
-  }
-  CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");
-  CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
-  CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
-  {
-    State<R> S = make_state<R>(ctx, n);
-    launch_filter_tree<R>(S, true, s);
-  }
-  CRK_HIP(hipGetLastError(), "neighbour list launch");
   CRK_HIP(hipMemsetAsync(ns, 0, 4 * (size_t)nw * 64, s), "memset");
   {
     State<R> S = make_state<R>(ctx, n);
-    launch_scatter_tree<R>(S, false, fillc, s);
+    launch_filter_tree<R>(S, false, fillc, s);
   }
+  CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");
   CRK_HIP(offsets(ns, 0, ws, ls, &ctx->host_rows[1]), "list rows");
+  CRK_HIP(ensure(ctx->nlist, 4 * 256 * (size_t)ctx->host_rows[0]), "alloc neighbour list");
   CRK_HIP(ensure(ctx->slist, 4 * 256 * (size_t)ctx->host_rows[1]), "alloc neighbour list");
+  CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
   CRK_HIP(hipMemsetAsync(fillc, 0, 4 * (size_t)nw * 64, s), "memset");
   {
     State<R> S = make_state<R>(ctx, n);
-    launch_scatter_tree<R>(S, true, fillc, s);
+    launch_filter_tree<R>(S, true, fillc, s);
   }
   CRK_HIP(tend(ctx, P_NLIST, s), "event");
   CRK_HIP(hipGetLastError(), "neighbour list launch");

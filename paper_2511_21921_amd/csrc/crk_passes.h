@@ -39,12 +39,12 @@ template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 // a[0 .. na) += v
 void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s);
-// Gather lists from the kept candidates: lengths (write = false), then entries.
+// Gather lists and the scatter-only lists (their transpose) from the kept
+// candidates: lengths and scatter-only counts (write = false), then entries,
+// the scatter-only ones appended at fillc and then sorted.
 template <class R>
-void launch_filter_tree(const State<R>& S, bool write, hipStream_t s);
+void launch_filter_tree(const State<R>& S, bool write, int* fillc, hipStream_t s);
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s);
-template <class R>
-void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s);
 
 // Gather caller arrays into cell-sorted SoA with cell-centre offsets.
 template <class R>

@@ -455,13 +455,20 @@ __global__ void __launch_bounds__(kBlock) k_add_u32(uint32_t* __restrict__ a, in
   if (i < na) a[i] += v;
 }
 
-// Gather lists r_ij < h_i from the stored candidates of every particle (the
+// Neighbour lists from the stored candidates of every particle (the
 // candidates hold every j with r_ij below the particle's radius, which is at
-// least its solved h). COUNT stores the lengths; WRITE (with per-wave
-// capacities from those lengths) writes the entries, in candidate order,
-// which is ascending j.
+// least its solved h): the gather list (r_ij < h_i, in candidate order, which
+// is ascending j) and the particle's share in the scatter-only lists, the
+// transpose: i belongs to j's scatter-only list when i gathers j
+// (r_ij < h_i) but j does not gather i (r_ij >= h_j). The
+// separation is the candidate walk's, computed from i's side; the walk of j
+// computes it from j's side as the exact negation (lattice offsets and
+// differences negate exactly), so j's own gather filter and this test decide
+// alike. COUNT stores the gather lengths and adds to the scatter-only counts
+// ns[j]; WRITE (with per-wave capacities from those counts) writes the gather
+// entries and appends i at fillc[j] (unordered; sorted afterwards).
 template <class R, bool WRITE>
-__global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S) {
+__global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restrict__ fillc) {
   const int64_t s = particle_id();
   if ((s & ~(int64_t)63) >= S.n) return;
   const bool active = s < S.n;
@@ -478,15 +485,26 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S) {
     R rr[16];
     uint32_t ee[16];
     load_group(S.scr_r + group_at(base, k), rr);
-    if (WRITE) load_group(S.cand + group_at(base, k), ee);
+    load_group(S.cand + group_at(base, k), ee);
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       if (k + t < cnt && rr[t] < h) {
+        const uint32_t j = ee[t] >> kCodeBits;
         if (WRITE) {
           sg.put(ng & 3, ee[t]);
           if ((ng & 3) == 3) sg.flush_at(S.nlist, gb, ng);
         }
         ++ng;
+        if (!(rr[t] < S.hbuf[j])) {  // this particle is in j's scatter-only list
+          if (WRITE) {
+            const int u = atomicAdd(&fillc[j], 1);
+            const int64_t wj = (int64_t)(j >> 6);
+            const int scap = (int)(S.srow[wj + 1] - S.srow[wj]) * 4;
+            if (u < scap) S.slist[slot_at(slot_base(S.srow[wj], j), u)] = (uint32_t)s << kCodeBits;
+          } else {
+            atomicAdd(&S.ns[j], 1);
+          }
+        }
       }
     }
   }
@@ -517,40 +535,6 @@ __global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cn
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_xor(c, o, 64));
   if ((threadIdx.x & 63) == 0) rows[s >> 6] = (uint32_t)((c + 3) >> 2);
-}
-
-// Scatter-only part of the symmetric list by transposing the gather lists:
-// j belongs to i's scatter-only list when i is in j's gather list
-// (r_ij < h_j) but j is not in i's (r_ij >= h_i). The separation is computed
-// as i's candidate walk computed it (x_ij from i's side) and r is its square
-// root, so the test here and i's gather filter decide alike. COUNT adds to
-// ns[i]; FILL appends j at fillc[i] (unordered, sorted afterwards).
-template <class R, bool FILL>
-__global__ void __launch_bounds__(kBlock) k_scatter_tree(State<R> S, int* __restrict__ fillc) {
-  const int64_t s = particle_id();
-  if (s >= S.n) return;
-  const R4<R> pj = S.pos4[s];
-  const uint32_t cj = S.cell3[s];
-  const int64_t w = s >> 6;
-  const int ng = S.ng[s];
-  const int64_t gb = slot_base(S.grow[w], s);
-  for (int k = 0; k < ng; ++k) {
-    const uint32_t i = S.nlist[slot_at(gb, k)] >> kCodeBits;
-    const R4<R> pi = S.pos4[i];
-    R x[3];
-    lattice_sep(S, pi, S.cell3[i], pj, cj, x);
-    const R r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    if (!(r < S.hbuf[i])) {
-      if (FILL) {
-        const int t = atomicAdd(&fillc[i], 1);
-        const int64_t wi = (int64_t)(i >> 6);
-        const int scap = (int)(S.srow[wi + 1] - S.srow[wi]) * 4;
-        if (t < scap) S.slist[slot_at(slot_base(S.srow[wi], i), t)] = (uint32_t)s << kCodeBits;
-      } else {
-        atomicAdd(&S.ns[i], 1);
-      }
-    }
-  }
 }
 
 // Sorts every scatter-only list by j (insertion sort; the lists are short),
@@ -640,27 +624,19 @@ void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s) {
 }
 
 template <class R>
-void launch_filter_tree(const State<R>& S, bool write, hipStream_t s) {
-  if (write)
-    hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
-  else
-    hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+void launch_filter_tree(const State<R>& S, bool write, int* fillc, hipStream_t s) {
+  if (write) {
+    hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
+                       fillc);
+    hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  } else {
+    hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
+                       fillc);
+  }
 }
 
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s) {
   hipLaunchKernelGGL(k_wave_rows, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, extra, rows);
-}
-
-template <class R>
-void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s) {
-  if (fill) {
-    hipLaunchKernelGGL((k_scatter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
-                       fillc);
-    hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
-  } else {
-    hipLaunchKernelGGL((k_scatter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
-                       fillc);
-  }
 }
 
 #define CRK_INSTANTIATE_TREE(R)                                                               \
@@ -671,8 +647,7 @@ void launch_scatter_tree(const State<R>& S, bool fill, int* fillc, hipStream_t s
   template void launch_candidates_tree<R>(const State<R>&, const float4*, int,               \
                                           const uint32_t*, int64_t, hipStream_t);            \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
-  template void launch_filter_tree<R>(const State<R>&, bool, hipStream_t);                   \
-  template void launch_scatter_tree<R>(const State<R>&, bool, int*, hipStream_t);
+  template void launch_filter_tree<R>(const State<R>&, bool, int*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
 CRK_INSTANTIATE_TREE(double)
