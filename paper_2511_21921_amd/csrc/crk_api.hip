@@ -512,10 +512,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(tend(ctx, P_CAND, s), "event");
     ctx->searched += nt;
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
-    if (P.h_mode == 0)
-      launch_volume<R>(S, P.kernel, s, order, nt);
-    else
-      launch_hsolve<R>(S, P.kernel, s, order, nt);
+    launch_hsolve_tree<R>(S, P.kernel, order, nt, s);
     CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
     row_base = rows_end;

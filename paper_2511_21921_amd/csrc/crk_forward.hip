@@ -28,25 +28,6 @@ __device__ inline R dot3(const R a[3], const R b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-__device__ inline void wave_add_u64(unsigned long long* dst, unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
-}
-
-__device__ inline void wave_max_u64(unsigned long long* dst, unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long t = __shfl_xor(v, o, 64);
-    v = t > v ? t : v;
-  }
-  if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
-}
-
-__device__ inline unsigned long long dbits(double d) {
-  return (unsigned long long)__double_as_longlong(d);
-}
-
 // ------------------------------------------------------------- inputs ----
 
 // Grid-stride over the inputs; each block reduces in LDS and issues one
@@ -412,26 +393,20 @@ __device__ inline R candidate_sum(const State<R>& S, int64_t base, int cnt, R h,
 // f is non-decreasing in h; safeguarded Newton inside a bisection bracket,
 // stopping when a Newton step falls below the tolerance.
 
-// order (tree path retry rounds): thread t solves particle order[t], t < nt;
-// null: thread t solves particle t.
+// Cell path: a thread per particle (the tree path solves with k_hsolve_rows).
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S, const uint32_t* __restrict__ order,
-                                                   int64_t nt) {
-  const int64_t t = particle_id();
-  const int64_t s = t < nt ? (order ? (int64_t)order[t] : t) : S.n;
+__global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S) {
+  const int64_t s = particle_id();
   unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
-  // tree path: only particles still to solve, whose candidate pass fitted
-  const bool work = s < S.n && (!S.todo || (S.todo[s] && S.ccnt[s] >= 0));
-  if (work) {
+  if (s < S.n) {
     int scap;
     const int64_t q = scratch_base(S, s, scap);
     const int cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
     const R C = R(Shape<K>::C);
     const R n_h3 = R(S.n_h3);
-    const R Rcap = S.rad ? S.rad[s] : S.rcap;
+    const R Rcap = S.rcap;
     const R rtol = R(S.rtol);
-    R h = S.hbuf[s];
-    if (!(h > R(0) && h < Rcap)) h = R(0.5) * Rcap;
+    R h = first_h(S.hbuf[s], Rcap, cnt, S.n_h3);
     R dsum, sum = candidate_sum<R, K>(S, q, cnt, h, dsum);
     R f = C * sum - n_h3;
     // the bracket [0, Rcap] holds the root only if f(Rcap) > 0; that needs
@@ -443,14 +418,6 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S, const uint32_t* _
     }
     if (cap_hit) {
       capped = 1;  // the root lies beyond the candidate radius
-      if (S.rad) {
-        // tree path: the root lies beyond this radius; grow it by what the
-        // candidate count suggests
-        const double g = grow_factor(S.n_h3, cnt);
-        S.rad[S.n + s] = Rcap;
-        S.rad[s] = (R)((double)Rcap * g);
-        S.need[s] = max(S.need[s], need_after_growth(cnt, g));
-      }
     } else {
       R lo = R(0), hi = Rcap;
       bool conv = false;
@@ -488,10 +455,6 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S, const uint32_t* _
       S.hbuf[s] = hn;
       S.Vbuf[s] = hn * hn * hn / (C * sum_f);
       hbits = dbits((double)hn);
-      if (S.todo) {
-        S.todo[s] = 0;
-        S.cpos[s] = scratch_pos(S, s);
-      }
     }
   }
   wave_max_u64(cnt_at(S.cnt, CNT_H_ITER_MAX), iters);
@@ -502,16 +465,9 @@ __global__ void __launch_bounds__(kBlock) k_hsolve(State<R> S, const uint32_t* _
 
 // Fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included.
 template <class R, int K>
-__global__ void __launch_bounds__(kBlock) k_volume(State<R> S, const uint32_t* __restrict__ order,
-                                                   int64_t nt) {
-  const int64_t t = particle_id();
-  const int64_t s = t < nt ? (order ? (int64_t)order[t] : t) : S.n;
+__global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
+  const int64_t s = particle_id();
   if (s >= S.n) return;
-  if (S.todo && !(S.todo[s] && S.ccnt[s] >= 0)) return;  // tree path: solved or retrying
-  if (S.todo) {
-    S.todo[s] = 0;
-    S.cpos[s] = scratch_pos(S, s);
-  }
   if (is_passive(S, s)) return;  // V comes from the stored state (k_pack)
   const R h = S.hbuf[s];
   int scap;
@@ -1175,22 +1131,18 @@ void launch_candidates(const State<R>& S, hipStream_t s) {
     hipLaunchKernelGGL((k_candidates<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
 }
 template <class R>
-void launch_hsolve(const State<R>& S, int kernel, hipStream_t s, const uint32_t* order,
-                   int64_t nt) {
-  if (nt < 0) nt = S.n;
-  if (nt == 0) return;
-  const dim3 g(grid_for(nt)), b(kBlock);
-  if (kernel == 0) hipLaunchKernelGGL((k_hsolve<R, 0>), g, b, 0, s, S, order, nt);
-  else hipLaunchKernelGGL((k_hsolve<R, 1>), g, b, 0, s, S, order, nt);
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {
+  if (S.n == 0) return;
+  const dim3 g(grid_for(S.n)), b(kBlock);
+  if (kernel == 0) hipLaunchKernelGGL((k_hsolve<R, 0>), g, b, 0, s, S);
+  else hipLaunchKernelGGL((k_hsolve<R, 1>), g, b, 0, s, S);
 }
 template <class R>
-void launch_volume(const State<R>& S, int kernel, hipStream_t s, const uint32_t* order,
-                   int64_t nt) {
-  if (nt < 0) nt = S.n;
-  if (nt == 0) return;
-  const dim3 g(grid_for(nt)), b(kBlock);
-  if (kernel == 0) hipLaunchKernelGGL((k_volume<R, 0>), g, b, 0, s, S, order, nt);
-  else hipLaunchKernelGGL((k_volume<R, 1>), g, b, 0, s, S, order, nt);
+void launch_volume(const State<R>& S, int kernel, hipStream_t s) {
+  if (S.n == 0) return;
+  const dim3 g(grid_for(S.n)), b(kBlock);
+  if (kernel == 0) hipLaunchKernelGGL((k_volume<R, 0>), g, b, 0, s, S);
+  else hipLaunchKernelGGL((k_volume<R, 1>), g, b, 0, s, S);
 }
 template <class R>
 void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s) {
@@ -1238,8 +1190,8 @@ void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long*
   template void launch_gather<R>(const State<R>&, const double*, const R*, const R*,         \
                                  const R*, const R*, hipStream_t);                           \
   template void launch_candidates<R>(const State<R>&, hipStream_t);                          \
-  template void launch_hsolve<R>(const State<R>&, int, hipStream_t, const uint32_t*, int64_t); \
-  template void launch_volume<R>(const State<R>&, int, hipStream_t, const uint32_t*, int64_t); \
+  template void launch_hsolve<R>(const State<R>&, int, hipStream_t); \
+  template void launch_volume<R>(const State<R>&, int, hipStream_t); \
   template void launch_pack<R>(const State<R>&, R*, R*, hipStream_t);                        \
   template void launch_nlist<R>(const State<R>&, hipStream_t);                               \
   template void launch_moments<R>(const State<R>&, int, CorrOut, hipStream_t);               \

@@ -35,6 +35,11 @@ void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s);
 template <class R>
 void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
                             const uint32_t* order, int64_t nt, hipStream_t s);
+// The h solve (solved h) or the volume (fixed h) of the particles whose
+// candidates the round kept, a 16-lane row per particle (order as above).
+template <class R>
+void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
+                        hipStream_t s);
 template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 // a[0 .. na) += v
@@ -55,11 +60,9 @@ void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, c
 template <class R>
 void launch_candidates(const State<R>& S, hipStream_t s);
 template <class R>
-void launch_hsolve(const State<R>& S, int kernel, hipStream_t s,
-                   const uint32_t* order = nullptr, int64_t nt = -1);
+void launch_hsolve(const State<R>& S, int kernel, hipStream_t s);
 template <class R>
-void launch_volume(const State<R>& S, int kernel, hipStream_t s,
-                   const uint32_t* order = nullptr, int64_t nt = -1);
+void launch_volume(const State<R>& S, int kernel, hipStream_t s);
 // Stores 1/h and V into the packed records and writes h, V in caller order.
 template <class R>
 void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s);

@@ -45,6 +45,26 @@ __device__ inline unsigned long long* cnt_at(unsigned long long* cnt, int c) {
   return cnt + c * kCntSpread + (blockIdx.x & (kCntSpread - 1));
 }
 
+// A wave's sum (or maximum) of v, added (or maxed) into *dst by its lane 0.
+__device__ inline void wave_add_u64(unsigned long long* dst, unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+__device__ inline void wave_max_u64(unsigned long long* dst, unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = __shfl_xor(v, o, 64);
+    v = t > v ? t : v;
+  }
+  if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
+}
+
+// Bits of a non-negative double, ordered as the value (counter maxima).
+__device__ inline unsigned long long dbits(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
 template <class R>
 struct State {
   int64_t n;
@@ -200,6 +220,19 @@ __device__ inline int64_t particle_id() {
 __device__ inline double grow_factor(double n_h3, int cnt) {
   const double g = 1.1 * cbrt(4.18879020478639098 * n_h3 / (double)(cnt > 1 ? cnt : 1));
   return g < 1.25 ? 1.25 : (g > 4.0 ? 4.0 : g);
+}
+
+// First h of the solve: the h at which cnt candidates within Rcap would be
+// (4 pi / 3) n_h^3 at uniform density, Rcap (target / cnt)^(1/3), unless the
+// caller's h lies within a factor 1.5 of it (a previous step's h); always
+// inside (0, Rcap). The root does not depend on it, only the iterations do.
+template <class R>
+__device__ inline R first_h(R h_in, R Rcap, int cnt, double n_h3) {
+  const double est = (double)Rcap * cbrt(4.18879020478639098 * n_h3 / (double)(cnt > 1 ? cnt : 1));
+  double h = (double)h_in;
+  if (!(h > est / 1.5 && h < est * 1.5)) h = est;
+  if (!(h > 0.0 && h < (double)Rcap)) h = 0.5 * (double)Rcap;
+  return (R)h;
 }
 
 // Capacity to request for the grown radius: the count scaled by the volume,

@@ -206,6 +206,157 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
   }
 }
 
+// The h solve of k_hsolve (or the volume of k_volume for fixed h) with a
+// 16-lane row per particle: lane sub takes the kept candidates 16 it + sub,
+// holding the first kRegGroups groups in registers (read once) and reading
+// any further ones at every evaluation. The sums over the row are butterfly
+// reductions, which leave the same value in every lane, so the solve is
+// uniform over the row and its lane 0 writes the results. The spread over
+// the row keeps a particle with thousands of candidates (a sphere that
+// takes in a dense clump core) from holding a wave for thousands of serial
+// steps per evaluation. order null: row t takes particle t; else order[t].
+constexpr int kRegGroups = 8;
+template <class R, int K, bool EM>
+__global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
+                                                        const uint32_t* __restrict__ order,
+                                                        int64_t nt) {
+  const int64_t tid = particle_id();
+  if (((tid & ~(int64_t)63) >> 4) >= nt) return;  // the wave's four rows past the end
+  const int64_t t = tid >> 4;
+  const int sub = threadIdx.x & 15;
+  const int64_t s = t < nt ? (order ? (int64_t)order[t] : t) : S.n;
+  // particles still to solve whose candidate pass fitted (uniform over the row)
+  const bool work = s < S.n && S.todo[s] && S.ccnt[s] >= 0;
+  unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
+  if (__ballot(work) != 0ull) {
+    int scap = 0, cnt = 0;
+    int64_t base = 0;
+    if (work) {
+      base = scratch_base(S, s, scap);
+      cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
+    }
+    const int ngroups = (cnt + 15) >> 4;
+    R rk[kRegGroups], mk[kRegGroups];
+#pragma unroll
+    for (int it = 0; it < kRegGroups; ++it) {
+      const int e = 16 * it + sub;
+      rk[it] = e < cnt ? S.scr_r[group_at(base, e)] : R(0);
+      mk[it] = (!EM && e < cnt) ? S.scr_m[group_at(base, e)] : R(0);
+    }
+    auto sums = [&](R h, R& dsum) {
+      const R hinv = R(1) / h;
+      R sum = R(0), ds = R(0);
+      auto add = [&](int e, R r, R mr) {
+        // entries past the count are moved outside the support (w = w' = 0)
+        const bool in = e < cnt;
+        const R q = in ? r * hinv : R(2);
+        R w, dw;
+        Shape<K>::eval(q, w, dw);
+        const R mt = EM ? R(1) : (in ? mr : R(0));
+        sum += mt * w;
+        ds += mt * dw * q;
+      };
+#pragma unroll
+      for (int it = 0; it < kRegGroups; ++it)
+        if (it < ngroups) add(16 * it + sub, rk[it], mk[it]);
+      for (int it = kRegGroups; it < ngroups; ++it) {
+        const int e = 16 * it + sub;
+        const int64_t at = group_at(base, e < cnt ? e : 0);
+        add(e, S.scr_r[at], EM ? R(1) : S.scr_m[at]);
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 16);
+        ds += __shfl_xor(ds, o, 16);
+      }
+      dsum = ds;
+      return sum + R(Shape<K>::w0);
+    };
+    const R C = R(Shape<K>::C);
+    if (work && !S.shrink) {
+      // fixed h: V_i = m_i / sum_j m_j W(r_ij, h_i), self term included
+      const R h = S.hbuf[s];
+      R dsum;
+      const R sum = sums(h, dsum);
+      if (sub == 0) {
+        S.todo[s] = 0;
+        S.cpos[s] = scratch_pos(S, s);
+        if (!is_passive(S, s)) S.Vbuf[s] = h * h * h / (C * sum);
+      }
+    } else if (work) {
+      // f(h) = C (w(0) + sum_j (m_j/m_i) w(r_ij / h)) - n_h^3, non-decreasing
+      // in h: safeguarded Newton inside a bisection bracket, as k_hsolve
+      const R Rcap = S.rad[s];
+      const R n_h3 = R(S.n_h3);
+      const R rtol = R(S.rtol);
+      R h = first_h(S.hbuf[s], Rcap, cnt, S.n_h3);
+      R dsum, sum = sums(h, dsum);
+      R f = C * sum - n_h3;
+      // the bracket [0, Rcap] holds the root only if f(Rcap) > 0
+      bool cap_hit = false;
+      if (!(f > R(0))) {
+        R ds2;
+        cap_hit = !(C * sums(Rcap, ds2) - n_h3 > R(0));
+      }
+      if (cap_hit) {
+        // the root lies beyond the radius: grow it by what the candidate
+        // count suggests; the particle is taken again in the next round
+        if (sub == 0) {
+          capped = 1;
+          const double g = grow_factor(S.n_h3, cnt);
+          S.rad[S.n + s] = Rcap;
+          S.rad[s] = (R)((double)Rcap * g);
+          S.need[s] = max(S.need[s], need_after_growth(cnt, g));
+        }
+      } else {
+        R lo = R(0), hi = Rcap;
+        bool conv = false;
+        int it = 0;
+        R hn = h;
+        for (;;) {
+          const R fp = -C * dsum / h;
+          if (f > R(0)) hi = h; else lo = h;
+          hn = R(0.5) * (lo + hi);
+          if (fp > R(0)) {
+            const R nt_ = h - f / fp;
+            const R step = nt_ > h ? nt_ - h : h - nt_;
+            if (step <= rtol * h) {
+              hn = nt_ < lo ? lo : (nt_ > hi ? hi : nt_);
+              conv = true;
+              break;
+            }
+            if (nt_ > lo && nt_ < hi) hn = nt_;
+          }
+          if (hi - lo <= rtol * hn) {
+            conv = true;
+            break;
+          }
+          if (++it >= S.max_iter) break;
+          h = hn;
+          sum = sums(h, dsum);
+          f = C * sum - n_h3;
+        }
+        // V at the final h from the last sums (first order in the step, which
+        // is below the tolerance; an unconverged h gets its own pass)
+        const R sum_f = conv ? sum - dsum / h * (hn - h) : sums(hn, dsum);
+        if (sub == 0) {
+          iters = (unsigned long long)(it + 1);
+          unconv = conv ? 0 : 1;
+          S.hbuf[s] = hn;
+          S.Vbuf[s] = hn * hn * hn / (C * sum_f);
+          hbits = dbits((double)hn);
+          S.todo[s] = 0;
+          S.cpos[s] = scratch_pos(S, s);
+        }
+      }
+    }
+  }
+  wave_max_u64(cnt_at(S.cnt, CNT_H_ITER_MAX), iters);
+  wave_add_u64(cnt_at(S.cnt, CNT_H_UNCONV), unconv);
+  wave_add_u64(cnt_at(S.cnt, CNT_H_CAPPED), capped);
+  wave_max_u64(cnt_at(S.cnt, CNT_HMAX_OUT_BITS), hbits);
+}
+
 // Candidates of every unsolved particle within its own radius ri, written to
 // its scratch slot (list entry and distance; the mass ratio when masses
 // differ), in ascending j. A 16-lane row takes one particle (order null: row
@@ -614,6 +765,24 @@ void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
 }
 
 template <class R>
+void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
+                        hipStream_t s) {
+  if (nt <= 0) return;
+  const dim3 g(grid_for(16 * nt)), b(kBlock);  // a 16-lane row per particle
+  if (S.equal_mass) {
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_hsolve_rows<R, 0, true>), g, b, 0, s, S, order, nt);
+    else
+      hipLaunchKernelGGL((k_hsolve_rows<R, 1, true>), g, b, 0, s, S, order, nt);
+  } else {
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_hsolve_rows<R, 0, false>), g, b, 0, s, S, order, nt);
+    else
+      hipLaunchKernelGGL((k_hsolve_rows<R, 1, false>), g, b, 0, s, S, order, nt);
+  }
+}
+
+template <class R>
 void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s) {
   hipLaunchKernelGGL(k_slot_rows<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, rows);
 }
@@ -646,6 +815,8 @@ void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipS
   template void launch_rank_order<R>(const State<R>&, uint32_t*, hipStream_t);              \
   template void launch_candidates_tree<R>(const State<R>&, const float4*, int,               \
                                           const uint32_t*, int64_t, hipStream_t);            \
+  template void launch_hsolve_tree<R>(const State<R>&, int, const uint32_t*, int64_t,       \
+                                      hipStream_t);                                          \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
   template void launch_filter_tree<R>(const State<R>&, bool, int*, hipStream_t);
 
