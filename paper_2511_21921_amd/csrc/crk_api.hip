@@ -466,7 +466,6 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   uint32_t* grows = (uint32_t*)ctx->wrow.p;  // per-group rows, then their offsets
   uint32_t* goff = grows + ngrp + 1;
   CRK_HIP(hipMemsetAsync(todo + n, 0, 4, s), "memset");
-  const size_t RS = real_size(P.precision);
   uint32_t row_base = 0;  // rows taken by the earlier rounds
   bool solved = false;
   for (int round = 0; round < 40; ++round) {
@@ -489,13 +488,12 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     }
     const uint32_t rows_end = ctx->host_rows[1];  // a row: 16 entries of 64 slots
     if (rows_end >= (1u << 26)) return fail(ctx, CRK_ENOMEM, "candidate scratch beyond 2^26 rows");
-    // the first round leaves a quarter more room for the later ones
-    const size_t want = 1024 * (size_t)(round == 0 ? rows_end + rows_end / 4 : rows_end);
+    // the first round leaves an eighth more room for the later ones (the
+    // candidates are kept as indices only: the h solve and the list filter
+    // recompute the distances)
+    const size_t want = 1024 * (size_t)(round == 0 ? rows_end + rows_end / 8 : rows_end);
     const size_t keep = 1024 * (size_t)row_base;
-    CRK_HIP(ensure_keep(ctx->scr_r, RS * want, RS * keep, s), "alloc candidates");
     CRK_HIP(ensure_keep(ctx->cand, 4 * want, 4 * keep, s), "alloc candidates");
-    if (!ctx->equal_mass)
-      CRK_HIP(ensure_keep(ctx->scr_m, RS * want, RS * keep, s), "alloc candidates");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);

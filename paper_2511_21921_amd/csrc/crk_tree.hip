@@ -208,14 +208,15 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
 
 // The h solve of k_hsolve (or the volume of k_volume for fixed h) with a
 // 16-lane row per particle: lane sub takes the kept candidates 16 it + sub,
-// holding the first kRegGroups groups in registers (read once) and reading
-// any further ones at every evaluation. The sums over the row are butterfly
+// recomputing their distances from the positions (the candidate pass keeps
+// only the indices), holding those of the first kRegGroups groups in
+// registers and recomputing any further ones at every evaluation. The sums over the row are butterfly
 // reductions, which leave the same value in every lane, so the solve is
 // uniform over the row and its lane 0 writes the results. The spread over
 // the row keeps a particle with thousands of candidates (a sphere that
 // takes in a dense clump core) from holding a wave for thousands of serial
 // steps per evaluation. order null: row t takes particle t; else order[t].
-constexpr int kRegGroups = 8;
+constexpr int kRegGroups = 16;
 template <class R, int K, bool EM>
 __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
                                                         const uint32_t* __restrict__ order,
@@ -236,13 +237,24 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
       cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
     }
     const int ngroups = (cnt + 15) >> 4;
+    // the distance and mass ratio of kept entry e, as the candidate pass
+    // computed them (the same separation arithmetic, so the same bits)
+    const int64_t sc = s < S.n ? s : 0;
+    const R4<R> pi = S.pos4[sc];
+    const uint32_t ci = S.cell3[sc];
+    const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
+    auto entry = [&](int e, R& r, R& mr) {
+      const uint32_t j = S.cand[group_at(base, e < cnt ? e : 0)] >> kCodeBits;
+      R x[3];
+      lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+      r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      mr = EM ? R(1) : S.mass[j] * mi_inv;
+    };
     R rk[kRegGroups], mk[kRegGroups];
+    // all slots at once, without branches, so that their loads are in
+    // flight together (slots past the count read entry 0 and stay unused)
 #pragma unroll
-    for (int it = 0; it < kRegGroups; ++it) {
-      const int e = 16 * it + sub;
-      rk[it] = e < cnt ? S.scr_r[group_at(base, e)] : R(0);
-      mk[it] = (!EM && e < cnt) ? S.scr_m[group_at(base, e)] : R(0);
-    }
+    for (int it = 0; it < kRegGroups; ++it) entry(16 * it + sub, rk[it], mk[it]);
     auto sums = [&](R h, R& dsum) {
       const R hinv = R(1) / h;
       R sum = R(0), ds = R(0);
@@ -260,9 +272,9 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
       for (int it = 0; it < kRegGroups; ++it)
         if (it < ngroups) add(16 * it + sub, rk[it], mk[it]);
       for (int it = kRegGroups; it < ngroups; ++it) {
-        const int e = 16 * it + sub;
-        const int64_t at = group_at(base, e < cnt ? e : 0);
-        add(e, S.scr_r[at], EM ? R(1) : S.scr_m[at]);
+        R r, mr;
+        entry(16 * it + sub, r, mr);
+        add(16 * it + sub, r, mr);
       }
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) {
@@ -532,7 +544,6 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     // ---- phase 2: exact separations, 16 passed indices at a time ----
     int cnt = 0;  // uniform over the row
     if (mine && np <= cap) {
-      const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
       const R r2cap = ri * ri;
       for (int k = 0; k < np; k += 16) {
         const int e = k + sub;
@@ -545,12 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         // every lane of the row has read its entry (the ballot waits on
         // it); a kept entry moves to a position at or before its own
         const uint64_t b = __ballot(keep) & rowbits;
-        if (keep) {
-          const int64_t at = group_at(base, cnt + __popcll(b & below));
-          S.scr_r[at] = Sc<R>::sqrt(r2);
-          S.cand[at] = j << kCodeBits;
-          if (!EM) S.scr_m[at] = S.mass[j] * mi_inv;
-        }
+        if (keep) S.cand[group_at(base, cnt + __popcll(b & below))] = j << kCodeBits;
         cnt += __popcll(b);
       }
     }
@@ -611,68 +617,66 @@ __global__ void __launch_bounds__(kBlock) k_add_u32(uint32_t* __restrict__ a, in
 // least its solved h): the gather list (r_ij < h_i, in candidate order, which
 // is ascending j) and the particle's share in the scatter-only lists, the
 // transpose: i belongs to j's scatter-only list when i gathers j
-// (r_ij < h_i) but j does not gather i (r_ij >= h_j). The
-// separation is the candidate walk's, computed from i's side; the walk of j
-// computes it from j's side as the exact negation (lattice offsets and
-// differences negate exactly), so j's own gather filter and this test decide
-// alike. COUNT stores the gather lengths and adds to the scatter-only counts
+// (r_ij < h_i) but j does not gather i (r_ij >= h_j). The separation is
+// recomputed as the candidate walk computed it, from i's side; from j's side
+// it is the exact negation (lattice offsets and differences negate exactly),
+// so j's own gather filter and this test decide alike. COUNT stores the gather lengths and adds to the scatter-only counts
 // ns[j]; WRITE (with per-wave capacities from those counts) writes the gather
 // entries and appends i at fillc[j] (unordered; sorted afterwards).
+// A 16-lane row per particle: the row takes 16 candidates at a time, one per
+// lane, and appends the gather entries in order (prefix counts over the
+// row's ballot), so that a particle's hundreds of recomputed separations are
+// in flight together rather than one after another.
 template <class R, bool WRITE>
 __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restrict__ fillc) {
-  const int64_t s = particle_id();
-  if ((s & ~(int64_t)63) >= S.n) return;
+  const int64_t tid = particle_id();
+  if (((tid & ~(int64_t)63) >> 4) >= S.n) return;  // the wave's four rows past the end
+  const int64_t s = tid >> 4;
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const uint64_t rowbits = 0xFFFFull << (lane & 48);
+  const uint64_t below = rowbits & ((1ull << lane) - 1ull);
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
-  const int cnt = active ? S.ccnt[sc] : 0;
+  const int cnt = active ? S.ccnt[sc] : 0;  // uniform over the row
   const uint32_t cp = S.cpos[sc];
   const int64_t base = group_base((int64_t)(cp >> 6), (int64_t)(cp & 63u));
   const R h = S.hbuf[sc];
+  const R4<R> pi = S.pos4[sc];
+  const uint32_t ci = S.cell3[sc];
   int64_t gb = 0;
   if (WRITE) gb = slot_base(S.grow[sc >> 6], sc);
-  Stage4<uint32_t> sg;
-  int ng = 0;
+  int ng = 0;  // uniform over the row
   for (int k = 0; k < cnt; k += 16) {
-    R rr[16];
-    uint32_t ee[16];
-    load_group(S.scr_r + group_at(base, k), rr);
-    load_group(S.cand + group_at(base, k), ee);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (k + t < cnt && rr[t] < h) {
-        const uint32_t j = ee[t] >> kCodeBits;
-        if (WRITE) {
-          sg.put(ng & 3, ee[t]);
-          if ((ng & 3) == 3) sg.flush_at(S.nlist, gb, ng);
-        }
-        ++ng;
-        if (!(rr[t] < S.hbuf[j])) {  // this particle is in j's scatter-only list
-          if (WRITE) {
-            const int u = atomicAdd(&fillc[j], 1);
-            const int64_t wj = (int64_t)(j >> 6);
-            const int scap = (int)(S.srow[wj + 1] - S.srow[wj]) * 4;
-            if (u < scap) S.slist[slot_at(slot_base(S.srow[wj], j), u)] = (uint32_t)s << kCodeBits;
-          } else {
-            atomicAdd(&S.ns[j], 1);
-          }
-        }
+    const int e = k + sub;
+    const bool in = e < cnt;
+    const uint32_t ent = S.cand[group_at(base, in ? e : 0)];
+    const uint32_t j = in ? ent >> kCodeBits : (uint32_t)sc;
+    R x[3];
+    lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+    const R r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const bool g = in && r < h;
+    const uint64_t b = __ballot(g) & rowbits;
+    if (WRITE && g) S.nlist[slot_at(gb, ng + __popcll(b & below))] = ent;
+    ng += __popcll(b);
+    if (g && !(r < S.hbuf[j])) {  // this particle is in j's scatter-only list
+      if (WRITE) {
+        const int u = atomicAdd(&fillc[j], 1);
+        const int64_t wj = (int64_t)(j >> 6);
+        const int scap = (int)(S.srow[wj + 1] - S.srow[wj]) * 4;
+        if (u < scap) S.slist[slot_at(slot_base(S.srow[wj], j), u)] = (uint32_t)s << kCodeBits;
+      } else {
+        atomicAdd(&S.ns[j], 1);
       }
     }
   }
-  unsigned long long g = 0;
-  if (active) {
-    if (WRITE) {
-      if (ng & 3) sg.flush_at(S.nlist, gb, ng - 1);
-      g = (unsigned long long)ng;
-    } else {
+  unsigned long long gsum = 0;
+  if (active && sub == 0) {
+    if (WRITE)
+      gsum = (unsigned long long)ng;
+    else
       S.ng[s] = ng;
-    }
   }
-  if (WRITE) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
-    if ((threadIdx.x & 63) == 0 && g) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_GATHER), g);
-  }
+  if (WRITE) wave_add_u64(cnt_at(S.cnt, CNT_PAIRS_GATHER), gsum);
 }
 
 // Per-wave capacity in chunk rows from per-particle counts: the largest of
@@ -795,12 +799,12 @@ void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s) {
 template <class R>
 void launch_filter_tree(const State<R>& S, bool write, int* fillc, hipStream_t s) {
   if (write) {
-    hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
-                       fillc);
+    hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(16 * S.n)), dim3(kBlock), 0, s,
+                       S, fillc);
     hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
   } else {
-    hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S,
-                       fillc);
+    hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(16 * S.n)), dim3(kBlock), 0, s,
+                       S, fillc);
   }
 }
 
