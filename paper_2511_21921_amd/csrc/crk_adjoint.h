@@ -378,9 +378,10 @@ __host__ __device__ inline void mom_expand(const double raw[40], MomFull& D) {
     }
 }
 
-// Returns false (and zero adjoints) for a singular second moment.
+// Returns false (and zero adjoints) for a singular second moment (tol as the
+// forward's, SingularTol of the working precision).
 __host__ __device__ inline bool corr_solve_adj(const double raw[40], const double kcbar[16],
-                                               double out[40]) {
+                                               double out[40], double tol) {
   for (int t = 0; t < 40; ++t) out[t] = 0.0;
   MomFull D;
   mom_expand(raw, D);
@@ -397,7 +398,7 @@ __host__ __device__ inline bool corr_solve_adj(const double raw[40], const doubl
   cof[8] = m2[0] * m2[4] - m2[1] * m2[3];
   const double det = m2[0] * cof[0] + m2[1] * cof[3] + m2[2] * cof[6];
   const double tr = fabs(m2[0]) + fabs(m2[4]) + fabs(m2[8]);
-  if (!(fabs(det) > 1e-12 * tr * tr * tr)) return false;
+  if (!(fabs(det) > tol * tr * tr * tr)) return false;
   double inv[9];
   for (int t = 0; t < 9; ++t) inv[t] = cof[t] / det;
   // forward

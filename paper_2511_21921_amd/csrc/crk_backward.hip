@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_corr(State<R> S, AdjState<R> G) 
   double kcb[16];
   for (int t = 0; t < 16; ++t) kcb[t] = G.gkc[t * n + s];
   double out[40];
-  corr_solve_adj(raw, kcb, out);
+  corr_solve_adj(raw, kcb, out, SingularTol<R>::v);
 #pragma unroll
   for (int t = 0; t < 10; ++t) {
     R4<R> q;

@@ -141,6 +141,17 @@ __host__ __device__ inline void kc_apply(const KC<R>& k, const R x[3], R W, cons
 // the stencil code 25*(dz+2) + 5*(dy+2) + (dx+2) (low 7 bits).
 
 constexpr int kCodeBits = 7;
+
+// A second moment m2 counts as singular (the particle keeps the uncorrected
+// kernel: fewer than three non-coplanar neighbours) when |det m2| <= tol tr^3,
+// tr = |m2_00| + |m2_11| + |m2_22|. In FP64 tol = 1e-12. FP32 pair arithmetic
+// rounds every product x_a x_b to ~6e-8, which alone leaves the sum over a
+// rank-deficient neighbourhood with |det| ~ 1e-8 tr^3, so the FP32 passes take
+// tol = 1e-6: an inverse that amplifies their rounding by 10^5 or more carries
+// no FP32 digit, and would turn a degenerate neighbourhood into arbitrarily
+// large corrections.
+template <class R> struct SingularTol { static constexpr double v = 1e-12; };
+template <> struct SingularTol<float> { static constexpr double v = 1e-6; };
 constexpr uint32_t kCodeMask = 127u;
 constexpr int kSelfCode = 62;  // d = (0, 0, 0)
 

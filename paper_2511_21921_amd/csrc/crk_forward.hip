@@ -664,6 +664,7 @@ struct Corr64 {
   bool singular;
 };
 
+template <class R>
 __device__ inline void solve_corrections(const Mom64& D, Corr64& o) {
   const double* m2 = D.m2;
   double cof[9];
@@ -678,7 +679,7 @@ __device__ inline void solve_corrections(const Mom64& D, Corr64& o) {
   cof[8] = m2[0] * m2[4] - m2[1] * m2[3];
   const double det = m2[0] * cof[0] + m2[1] * cof[3] + m2[2] * cof[6];
   const double tr = fabs(m2[0]) + fabs(m2[4]) + fabs(m2[8]);
-  o.singular = !(fabs(det) > 1e-12 * tr * tr * tr);
+  o.singular = !(fabs(det) > SingularTol<R>::v * tr * tr * tr);
   if (o.singular) {
     o.A = 1.0;
 #pragma unroll
@@ -781,7 +782,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
       for (int t = 0; t < 18; ++t) S.mom[(22 + t) * n + s] = M.X2[t];
     }
     Corr64 c;
-    solve_corrections(D, c);
+    solve_corrections<R>(D, c);
     sing = c.singular ? 1 : 0;
     store_kc(S, s, c);
     const int64_t n = S.n;

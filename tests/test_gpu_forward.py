@@ -149,3 +149,42 @@ def test_empty_and_error_paths():
         ctx.forward(x, v, m, torch.zeros_like(u), h)
     assert ei.value.status == -1
     del e
+
+
+def _planar_cluster():
+    """A jittered 8^3 lattice in one corner of the box, and far from it four
+    particles in the plane z = 0.75 that see only one another: their second
+    moments have rank two (singular), and their fixed h reaches no lattice
+    particle. FP32 products leave such a sum with |det| ~ 1e-8 tr^3."""
+    rng = np.random.default_rng(41)
+    g = (np.arange(8) + 0.5) * 0.04
+    x = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    x = x + rng.uniform(-0.004, 0.004, x.shape)
+    c = np.array([[0.75, 0.75, 0.75], [0.77, 0.752, 0.75], [0.749, 0.771, 0.75],
+                  [0.728, 0.741, 0.75]]).T
+    x = np.concatenate([x, c], axis=1)
+    n = x.shape[1]
+    h = np.full(n, 0.085)
+    h[-4:] = 0.05
+    ps = synth.ParticleSet("planar4", x, rng.normal(0, 0.1, (3, n)), np.full(n, 1.0 / n),
+                           10 ** rng.normal(0, 0.2, n), h, synth.n_h_for_neighbours(32), 0)
+    return ps
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_singular_second_moments_keep_the_uncorrected_kernel(precision):
+    ps = _planar_cluster()
+    print("case planar4 n=%d precision=%d" % (ps.n, precision), flush=True)
+    g, _ = _gpu.run(ps, precision)
+    o = _oracle(ps)
+    print(g["stats"], "oracle singular", o["m2_singular"], flush=True)
+    assert o["m2_singular"] == 4 and g["stats"]["m2_singular"] == 4
+    np.testing.assert_array_equal(g["A"][-4:], 1.0)
+    np.testing.assert_array_equal(g["B"][:, -4:], 0.0)
+    e = _gpu.errors({k: v[..., -4:] for k, v in g.items() if isinstance(v, np.ndarray)},
+                    {k: v[..., -4:] for k, v in o.items() if isinstance(v, np.ndarray)},
+                    o["h"][-4:])
+    bounds = FP64_BOUNDS if precision == FP64 else FP32_BOUNDS
+    print({k: "%.2e" % v for k, v in e.items()}, flush=True)
+    for k in ("accel_relL2", "dudt_relL2", "rho"):
+        assert e[k] <= bounds[k], (k, e[k])
