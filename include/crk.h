@@ -251,23 +251,36 @@ crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
  *   close (interval end): v = v^1/2 + a^1 dt_a/2, u = u^1/2 + (du/dt)^1 dt_a/2,
  *          and the particle's evaluation (accel, dudt, V, rho, A, B, gradA,
  *          gradB, gradv) is stored in the arrays.
- * Levels stay fixed during the call; every interval ends at dt, so the state
- * returned is synchronised. Arrays as in crk_kdk_step, all in/out: on entry
+ * Timestep refinement (App. A.5; refine_at null: none): refine_at [n] and
+ * refine_level [n] (int, device) move particle i with refine_at[i] >= 0 to
+ * the finer level refine_level[i] at the start of substep j_r = refine_at[i]
+ * (time j_r dt_min; Lmax counts the refinement levels). Its interval opened
+ * e before; v and u advance under the constant a^0, du^0 to that time
+ * (v <- v + a^0 e) and an interval of the new level opens there as above,
+ * so the cycle ends with v^1 = v^0 + a^0 e + (a^0 + a^1) dt_c / 2 (the
+ * corrected half kick for e = 0, the piecewise-constant final kick
+ * otherwise); the particle keeps the new level to the end of the big step.
+ * j_r must lie in [0, 2^Lmax) on the new level's grid (a multiple of
+ * 2^(Lmax - refine_level[i])), refine_level[i] in (levels[i], 30].
+ * Otherwise levels stay fixed during the call; every interval ends at dt, so
+ * the state returned is synchronised. Arrays as in crk_kdk_step, all in/out: on entry
  * the evaluation at the current state (every particle), on return each
  * particle's latest evaluation (all at the new state). With every level 0
- * this is crk_kdk_step up to rounding. The context needs h_mode 0; its
+ * and no refinement this is crk_kdk_step up to rounding. The context needs h_mode 0; its
  * workspace holds the half-kicked state and hdot. After a call with Lmax > 0
  * crk_backward is not available (the last evaluation had passive
  * particles). Errors: CRK_EINVAL for h_mode != 0, a bad dt or lambda, levels
- * outside [0, 30], null arrays or n above 2^25 - 1; otherwise those of
+ * outside [0, 30], a refinement that breaks the rules above, null arrays
+ * (refine_level null with refine_at given) or n above 2^25 - 1; otherwise those of
  * crk_forward, from any substep (after such an error the arrays may hold a
  * partly advanced state). The call reads the device a few times per substep
- * (the level range once, then the forward's checks). n = 0 is a no-op. */
+ * (the level range once, the refinements once, then the forward's checks).
+ * n = 0 is a no-op. */
 crk_status crk_hkdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
-                         double thacker_lambda, const int *levels, double *x, void *v,
-                         const void *m, void *u, void *h, void *V, void *rho, void *A, void *B,
-                         void *gradA, void *gradB, void *gradv, double *accel, double *dudt,
-                         crk_stats *stats);
+                         double thacker_lambda, const int *levels, const int *refine_at,
+                         const int *refine_level, double *x, void *v, const void *m, void *u,
+                         void *h, void *V, void *rho, void *A, void *B, void *gradA, void *gradB,
+                         void *gradv, double *accel, double *dudt, crk_stats *stats);
 
 /* Tabulated source function of the exact-integration cooling (Sec. 2.2,
  * exact integration): lam[k] at u_k = 10^(log10_u0 + k dex), k = 0 .. K-1,

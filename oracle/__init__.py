@@ -250,72 +250,123 @@ def kdk_step(x, v, m, u, h, prev: dict, params: Params, dt: float, lam: float,
 # step is over, open their next interval. The evaluation takes each
 # particle's velocity and energy at that time under its constant a^0 and
 # du^0 (the predicted values of the single-level step, R14, for the active
-# ones). Levels stay fixed over the big step (the limiter that refines them
-# mid-step is not part of this).
+# ones).
+#
+# Timestep refinement, App. A.5: a particle may be moved to a finer level L'
+# at the start of substep j_r (a limiter's decision, given by the caller).
+# Its interval opened at t_0 with its level L; at t_r = j_r dt_min, e = t_r
+# - t_0 into it, the half-kicked state is re-synchronised: the velocity and
+# energy advance under the constant a^0, du^0 to t_r (v <- v^0 + a^0 e), and
+# a new interval of dt_c = dt / 2^L' opens there as any interval opens. The
+# cycle then ends with v^1 = v^0 + a^0 e + (a^0 + a^1) dt_c / 2, which is
+# App. A.5's piecewise-constant final kick with dt_b = e + dt_c (for e = 0
+# its corrected half kick, v^1/2 = v^0 + a^0 dt_b / 2); the drift keeps the
+# parabola of a^0, and the particle stays on level L' to the end of the big
+# step. j_r must lie on the grid of L' (a multiple of 2^(Lmax - L')) so that
+# the refined intervals end on it; at an interval start of L (e = 0) the
+# refinement is the same as having level L' from there on.
 
 def hkdk_step(x, v, m, u, h, prev: dict, levels, params: Params, dt: float, lam: float,
-              nbr_mode: int = 0, trace: list = None) -> dict:
+              nbr_mode: int = 0, trace: list = None, refine=None, evaluate=None) -> dict:
     """One big step of the hierarchy from the synchronised state (x, v, u, h).
 
     prev holds the evaluation at that state with h fixed (accel, dudt, V,
     rho, A, B, gradA, gradB, gradv). levels: int per particle, >= 0.
+    refine: None, or (refine_at, refine_level) per particle: refine_at = -1
+    for none, else the substep j_r at whose start the particle moves to the
+    finer level refine_level (Lmax counts these levels too).
+    evaluate: None (the CRKSPH forward), or a function (x, v, u, h, passive)
+    returning at least accel and dudt (the integrator's own tests).
     Returns the synchronised x, v, u, h and each particle's latest
     evaluation (the prev of the next big step). trace, when given, collects
     per substep the passive mask and the x, h, V, rho the evaluation used.
     """
     if params.h_mode != 0:
         raise ValueError("the time-integrated smoothing length needs h_mode = 0")
-    levels = np.asarray(levels, dtype=np.int64)
+    levels = np.asarray(levels, dtype=np.int64).copy()
     if levels.min() < 0:
         raise ValueError("levels must be >= 0")
     x, v, m, u, h = _c(x).copy(), _c(v).copy(), _c(m), _c(u).copy(), _c(h).copy()
-    lmax = int(levels.max())
+    r_at = np.full(m.size, -1, dtype=np.int64)
+    r_lev = levels.copy()
+    if refine is not None:
+        r_at = np.asarray(refine[0], dtype=np.int64)
+        r_lev = np.asarray(refine[1], dtype=np.int64)
+    ref = r_at >= 0
+    lmax = int(max(levels.max(), r_lev[ref].max() if ref.any() else 0))
     nsub = 1 << lmax
+    if ref.any():
+        if np.any(r_lev[ref] <= levels[ref]):
+            raise ValueError("a refinement moves a particle to a finer level")
+        if np.any(r_at[ref] >= nsub) or np.any(r_at[ref] % (1 << (lmax - r_lev[ref])) != 0):
+            raise ValueError("a refinement starts on the grid of its new level")
     dt_min = dt / nsub
-    per = np.left_shift(1, lmax - levels)  # substeps per active interval
-    dta = per * dt_min
-    st = {k: _c(prev[k]).copy() for k in ("accel", "dudt") + PASSIVE_KEYS}
+    if evaluate is None:
+        def evaluate(x_, v_, u_, h_, passive):
+            return forward(x_, v_, m, u_, h_, params, nbr_mode=nbr_mode, passive=passive)
+    keys = ("accel", "dudt") + tuple(k for k in PASSIVE_KEYS if k in prev)
+    st = {k: _c(prev[k]).copy() for k in keys}
     vh = np.empty_like(v)
     uh = np.empty_like(u)
     hdot = np.empty_like(h)
+    per = np.left_shift(1, lmax - levels)  # substeps per active interval
+    dta = per * dt_min
+    start = np.zeros(m.size, dtype=np.int64)  # substep that opened each interval
 
     def open_interval(sel):
         vh[:, sel] = v[:, sel] + 0.5 * dta[sel] * st["accel"][:, sel]
         uh[sel] = u[sel] + 0.5 * dta[sel] * st["dudt"][sel]
-        g = st["gradv"]
-        div_v = g[0, sel] + g[4, sel] + g[8, sel]
-        delta_n = params.n_h * np.cbrt(st["V"][sel]) / h[sel]
-        h_thacker = h[sel] * (1.0 - lam + lam * delta_n)
-        hdot[sel] = (h_thacker - h[sel]) / dta[sel] + h[sel] * div_v / 3.0
+        if "gradv" in st:
+            g = st["gradv"]
+            div_v = g[0, sel] + g[4, sel] + g[8, sel]
+            delta_n = params.n_h * np.cbrt(st["V"][sel]) / h[sel]
+            h_thacker = h[sel] * (1.0 - lam + lam * delta_n)
+            hdot[sel] = (h_thacker - h[sel]) / dta[sel] + h[sel] * div_v / 3.0
+        else:
+            hdot[sel] = 0.0
 
     open_interval(np.ones(m.size, dtype=bool))
     for j in range(nsub):
-        start = (j // per) * per  # substep that opened each particle's interval
+        sel = r_at == j
+        if sel.any():
+            # re-synchronise at t_r under the constant a^0, du^0 and open the
+            # refined interval there
+            e = (j - start[sel]) * dt_min
+            v[:, sel] = v[:, sel] + st["accel"][:, sel] * e
+            u[sel] = u[sel] + st["dudt"][sel] * e
+            levels[sel] = r_lev[sel]
+            per[sel] = 1 << (lmax - levels[sel])
+            dta[sel] = per[sel] * dt_min
+            start[sel] = j
+            open_interval(sel)
         elapsed = (j - start) * dt_min
         # drift
         v_j = vh + st["accel"] * (elapsed + 0.5 * (dt_min - dta))
         x = np.mod(x + v_j * dt_min, params.box)
         h = h * np.exp(hdot * dt_min / h)
-        g = st["gradv"]
-        st["V"] = (h / params.n_h) ** 3
-        st["rho"] = st["rho"] * np.exp(-(g[0] + g[4] + g[8]) * dt_min)
+        if "gradv" in st:
+            g = st["gradv"]
+            st["V"] = (h / params.n_h) ** 3
+            st["rho"] = st["rho"] * np.exp(-(g[0] + g[4] + g[8]) * dt_min)
         # evaluation for the particles whose interval ends now
         j_end = j + 1
-        active = (j_end % per) == 0
+        active = (j_end - start) == per
         t_rel = (j_end - start) * dt_min - 0.5 * dta  # time since the half kick's centre
         v_p = vh + st["accel"] * t_rel
         u_p = uh + st["dudt"] * t_rel
-        pas = dict({k: st[k] for k in PASSIVE_KEYS}, mask=~active)
+        pas = dict({k: st[k] for k in PASSIVE_KEYS if k in st}, mask=~active)
         if trace is not None:
             trace.append({"passive": ~active, "x": x.copy(), "h": h.copy(),
-                          "V": st["V"].copy(), "rho": st["rho"].copy()})
-        o = forward(x, v_p, m, u_p, h, params, nbr_mode=nbr_mode, passive=pas)
+                          "V": st["V"].copy() if "V" in st else None,
+                          "rho": st["rho"].copy() if "rho" in st else None})
+        o = evaluate(x, v_p, u_p, h, pas)
         # second kick of the active particles; their evaluation is stored
         v[:, active] = vh[:, active] + 0.5 * dta[active] * o["accel"][:, active]
         u[active] = uh[active] + 0.5 * dta[active] * o["dudt"][active]
-        for k in ("accel", "dudt") + PASSIVE_KEYS:
+        for k in keys:
             st[k][..., active] = o[k][..., active]
         if j_end < nsub:
+            start[active] = j_end
             open_interval(active)
     # every interval ends at dt: the last evaluation had every particle active
     out = dict(o)

@@ -87,7 +87,7 @@ def lib():
         L.crk_kdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 14 +
                                    [C.POINTER(crk_stats)])
         L.crk_kdk_step.restype = C.c_int
-        L.crk_hkdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 15 +
+        L.crk_hkdk_step.argtypes = ([P, P, C.c_longlong, C.c_double, C.c_double] + [P] * 17 +
                                     [C.POINTER(crk_stats)])
         L.crk_hkdk_step.restype = C.c_int
         L.crk_cooling_table.argtypes = [P, P, C.c_int, C.c_double, C.c_double,
@@ -267,15 +267,22 @@ class Context:
 
     def hkdk_step(self, x: torch.Tensor, v: torch.Tensor, m: torch.Tensor, u: torch.Tensor,
                   out: dict, levels: torch.Tensor, dt: float, lam: float = 0.5,
-                  stats: bool = False) -> dict:
+                  stats: bool = False, refine=None) -> dict:
         """One big step of the power-of-two timestep hierarchy (crk_hkdk_step):
         levels is an int32 device tensor [n]; x, v, u and out are advanced in
-        place as in kdk_step, out holding each particle's latest evaluation."""
+        place as in kdk_step, out holding each particle's latest evaluation.
+        refine: None, or (refine_at, refine_level) int32 device tensors [n]
+        (refine_at -1: no refinement), the timestep refinement of the step."""
         n = int(m.shape[0])
         R = self.params.real
         _check(x, torch.float64, (3, n), "x")
         _check(v, R, (3, n), "v")
         _check(levels, torch.int32, (n,), "levels")
+        r_at = r_lev = None
+        if refine is not None:
+            r_at, r_lev = refine
+            _check(r_at, torch.int32, (n,), "refine_at")
+            _check(r_lev, torch.int32, (n,), "refine_level")
         for t, name in [(m, "m"), (u, "u"), (out["h"], "h"), (out["V"], "V"),
                         (out["rho"], "rho"), (out["A"], "A")]:
             _check(t, R, (n,), name)
@@ -286,7 +293,8 @@ class Context:
         st = crk_stats()
         stream = C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
         self.generation += 1
-        rc = lib().crk_hkdk_step(self._h, stream, n, float(dt), float(lam), _ptr(levels), _ptr(x),
+        rc = lib().crk_hkdk_step(self._h, stream, n, float(dt), float(lam), _ptr(levels),
+                                 _ptr(r_at), _ptr(r_lev), _ptr(x),
                                  _ptr(v), _ptr(m), _ptr(u), _ptr(out["h"]), _ptr(out["V"]),
                                  _ptr(out["rho"]), _ptr(out["A"]), _ptr(out["B"]),
                                  _ptr(out["gradA"]), _ptr(out["gradB"]), _ptr(out["gradv"]),

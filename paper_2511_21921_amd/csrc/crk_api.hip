@@ -55,7 +55,7 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder, absp;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder, absp, hl_lvl;
   uint32_t host_rows[2] = {};
   int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
@@ -1015,21 +1015,37 @@ crk_status step_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double l
 // the active ones and open their next interval.
 template <class R>
 crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double lam,
-                      const int* levels, double* x, R* v, const R* m, R* u, R* h, R* V, R* rho,
-                      void* A, void* B, void* gradA, void* gradB, R* gradv, double* accel,
-                      double* dudt, crk_stats* stats) {
+                      const int* levels, const int* refine_at, const int* refine_level,
+                      double* x, R* v, const R* m, R* u, R* h, R* V, R* rho, void* A, void* B,
+                      void* gradA, void* gradB, R* gradv, double* accel, double* dudt,
+                      crk_stats* stats) {
   const crk_params& P = ctx->p;
   const size_t N = (size_t)n;
   CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-  launch_level_range(levels, n, dcnt, s);
+  launch_level_range(levels, refine_at, refine_level, n, dcnt, s);
   CRK_HIP(hipGetLastError(), "level launch");
   CRK_HIP(read_counters(ctx, s), "levels");
-  if (ctx->host_cnt[CNT_BAD_INPUT]) return fail(ctx, CRK_EINVAL, "levels must lie in [0, 30]");
+  if (ctx->host_cnt[CNT_BAD_INPUT])
+    return fail(ctx, CRK_EINVAL,
+                "levels must lie in [0, 30], refinements on a finer level in [1, 30]");
   const int lmax = (int)ctx->host_cnt[CNT_H_ITER_MAX];
+  if (refine_at) {
+    CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
+    launch_refine_grid(refine_at, refine_level, n, lmax, dcnt, s);
+    CRK_HIP(hipGetLastError(), "level launch");
+    CRK_HIP(read_counters(ctx, s), "refinements");
+    if (ctx->host_cnt[CNT_BAD_INPUT])
+      return fail(ctx, CRK_EINVAL,
+                  "a refinement starts before the last substep, on the grid of its new level");
+  }
   const int64_t nsub = (int64_t)1 << lmax;
   const double dt_min = dt / (double)nsub;
+  // the current level of every particle (refinements change it)
+  CRK_HIP(ensure(ctx->hl_lvl, 4 * N), "step workspace");
+  int* lvl = (int*)ctx->hl_lvl.p;
+  CRK_HIP(hipMemcpyAsync(lvl, levels, 4 * N, hipMemcpyDeviceToDevice, s), "levels");
   CRK_HIP(ensure(ctx->vpred, sizeof(R) * 3 * N), "step workspace");
   CRK_HIP(ensure(ctx->upred, sizeof(R) * N), "step workspace");
   CRK_HIP(ensure(ctx->hl_vh, sizeof(R) * 3 * N), "step workspace");
@@ -1046,22 +1062,25 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
   double* acc1 = (double*)ctx->hl_acc.p;
   double* du1 = (double*)ctx->hl_du.p;
   CRK_HIP(tbegin(ctx, P_STEP, s), "event");
-  launch_hier_open<R>(n, levels, lmax, 0, dt_min, lam, P.n_h, v, u, h, V, gradv, accel, dudt,
-                      vh, uh, hdot, s);
+  launch_hier_open<R>(n, lvl, lmax, 0, dt_min, lam, P.n_h, v, u, h, V, gradv, accel, dudt, vh,
+                      uh, hdot, s);
   CRK_HIP(tend(ctx, P_STEP, s), "event");
   crk_status result = CRK_OK;
   for (int64_t j = 0; j < nsub; ++j) {
     const int64_t jend = j + 1;
     CRK_HIP(tbegin(ctx, P_STEP, s), "event");
-    launch_hier_drift<R>(n, levels, lmax, j, dt_min, P.n_h, P.box, x, vh, accel, h, hdot, V, rho,
+    if (refine_at)
+      launch_hier_refine<R>(n, j, refine_at, refine_level, lvl, lmax, dt_min, lam, P.n_h, v, u,
+                            h, V, gradv, accel, dudt, vh, uh, hdot, s);
+    launch_hier_drift<R>(n, lvl, lmax, j, dt_min, P.n_h, P.box, x, vh, accel, h, hdot, V, rho,
                          gradv, s);
-    launch_hier_predict<R>(n, levels, lmax, jend, dt_min, vh, uh, accel, dudt, vp, up, s);
+    launch_hier_predict<R>(n, lvl, lmax, jend, dt_min, vh, uh, accel, dudt, vp, up, s);
     CRK_HIP(tend(ctx, P_STEP, s), "event");
     CRK_HIP(hipGetLastError(), "hierarchy launch");
     // the neighbour-list pass marks the passive partners of active particles
     CRK_HIP(hipMemsetAsync(ctx->hl_need.p, 0, N, s), "memset");
     // the passes see the levels and the stored state during this forward only
-    ctx->hl_levels = levels;
+    ctx->hl_levels = lvl;
     ctx->hl_lmax = lmax;
     ctx->hl_jend = jend;
     ctx->hl_V = V;
@@ -1077,10 +1096,10 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
     if (st != CRK_OK && st != CRK_ENOTCONV && st != CRK_ENONFINITE) return st;
     if (st != CRK_OK) result = st;
     CRK_HIP(tbegin(ctx, P_STEP, s), "event");
-    launch_hier_close<R>(n, levels, lmax, jend, dt_min, v, u, vh, uh, acc1, du1, accel, dudt, s);
+    launch_hier_close<R>(n, lvl, lmax, jend, dt_min, v, u, vh, uh, acc1, du1, accel, dudt, s);
     if (jend < nsub)
-      launch_hier_open<R>(n, levels, lmax, jend, dt_min, lam, P.n_h, v, u, h, V, gradv, accel,
-                          dudt, vh, uh, hdot, s);
+      launch_hier_open<R>(n, lvl, lmax, jend, dt_min, lam, P.n_h, v, u, h, V, gradv, accel, dudt,
+                          vh, uh, hdot, s);
     CRK_HIP(tend(ctx, P_STEP, s), "event");
     CRK_HIP(hipGetLastError(), "hierarchy launch");
   }
@@ -1353,7 +1372,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
                 &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow,
-                &c->cpos, &c->torder, &c->absp};
+                &c->cpos, &c->torder, &c->absp, &c->hl_lvl};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)
@@ -1497,10 +1516,10 @@ crk_status crk_kdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
 }
 
 crk_status crk_hkdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
-                         double thacker_lambda, const int* levels, double* x, void* v,
-                         const void* m, void* u, void* h, void* V, void* rho, void* A, void* B,
-                         void* gradA, void* gradB, void* gradv, double* accel, double* dudt,
-                         crk_stats* stats) {
+                         double thacker_lambda, const int* levels, const int* refine_at,
+                         const int* refine_level, double* x, void* v, const void* m, void* u,
+                         void* h, void* V, void* rho, void* A, void* B, void* gradA, void* gradB,
+                         void* gradv, double* accel, double* dudt, crk_stats* stats) {
   if (!ctx) return CRK_EINVAL;
   ctx->err.clear();
   if (ctx->p.h_mode != 0)
@@ -1516,16 +1535,17 @@ crk_status crk_hkdk_step(crk_ctx* ctx, void* hip_stream, long long n, double dt,
   }
   if (n > (1ll << 25) - 1) return fail(ctx, CRK_EINVAL, "n exceeds 2^25 - 1 particles");
   if (!levels || !x || !v || !m || !u || !h || !V || !rho || !A || !B || !gradA || !gradB ||
-      !gradv || !accel || !dudt)
+      !gradv || !accel || !dudt || (refine_at && !refine_level))
     return fail(ctx, CRK_EINVAL, "null array argument");
   hipStream_t s = (hipStream_t)hip_stream;
   if (ctx->p.precision == CRK_FP64)
-    return hstep_impl<double>(ctx, s, n, dt, thacker_lambda, levels, x, (double*)v,
-                              (const double*)m, (double*)u, (double*)h, (double*)V, (double*)rho,
-                              A, B, gradA, gradB, (double*)gradv, accel, dudt, stats);
-  return hstep_impl<float>(ctx, s, n, dt, thacker_lambda, levels, x, (float*)v, (const float*)m,
-                           (float*)u, (float*)h, (float*)V, (float*)rho, A, B, gradA, gradB,
-                           (float*)gradv, accel, dudt, stats);
+    return hstep_impl<double>(ctx, s, n, dt, thacker_lambda, levels, refine_at, refine_level, x,
+                              (double*)v, (const double*)m, (double*)u, (double*)h, (double*)V,
+                              (double*)rho, A, B, gradA, gradB, (double*)gradv, accel, dudt,
+                              stats);
+  return hstep_impl<float>(ctx, s, n, dt, thacker_lambda, levels, refine_at, refine_level, x,
+                           (float*)v, (const float*)m, (float*)u, (float*)h, (float*)V,
+                           (float*)rho, A, B, gradA, gradB, (float*)gradv, accel, dudt, stats);
 }
 
 crk_status crk_cooling_table(crk_ctx* ctx, void* hip_stream, int K, double log10_u0, double dex,

@@ -152,7 +152,19 @@ template <class R>
 void launch_hier_close(int64_t n, const int* levels, int lmax, int64_t jend, double dt_min, R* v,
                        R* u, const R* vh, const R* uh, const double* acc1, const double* du1,
                        double* accel, double* dudt, hipStream_t s);
-void launch_level_range(const int* levels, int64_t n, unsigned long long* cnt, hipStream_t s);
+// timestep refinement (App. A.5): re-synchronise and reopen the particles
+// refined at substep j on their finer level (lvl: the current levels)
+template <class R>
+void launch_hier_refine(int64_t n, int64_t j, const int* refine_at, const int* refine_level,
+                        int* lvl, int lmax, double dt_min, double lam, double n_h, R* v, R* u,
+                        const R* h, const R* V, const R* gradv, const double* accel,
+                        const double* dudt, R* vh, R* uh, double* hdot, hipStream_t s);
+// largest level and bad levels or refinements (refine_at null: none), then
+// refinements off their level's grid for the largest level lmax
+void launch_level_range(const int* levels, const int* refine_at, const int* refine_level,
+                        int64_t n, unsigned long long* cnt, hipStream_t s);
+void launch_refine_grid(const int* refine_at, const int* refine_level, int64_t n, int lmax,
+                        unsigned long long* cnt, hipStream_t s);
 
 // subgrid deposition: the gas grid, the source passes, the pair list and
 // the per-gas sums (caller order)

@@ -105,6 +105,46 @@ __global__ void __launch_bounds__(kBlock) k_hier_open(
   hdot[i] = (h_thacker - hi) / dta + hi * div / 3.0;
 }
 
+// Timestep refinement at the start of substep j (App. A.5): a particle with
+// refine_at = j moves to the finer level refine_level. Its interval opened
+// at the last substep on the grid of its old level, e = (j - that) dt_min
+// before; its velocity and energy advance under the constant a^0, du^0 to
+// t_r = j dt_min (v <- v + a^0 e), and a new interval of the new level opens
+// there as k_hier_open opens one (half kick and hdot from the particle's
+// current h and stored V, grad v). j lies on the new level's grid (checked
+// by the caller), so the new interval ends on it; the cycle thus ends with
+// v^1 = v^0 + a^0 e + (a^0 + a^1) dt_c / 2, the piecewise-constant final
+// kick, and the particle keeps the new level to the end of the big step.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_hier_refine(
+    int64_t n, int64_t j, const int* __restrict__ refine_at, const int* __restrict__ refine_level,
+    int* __restrict__ lvl, int lmax, double dt_min, double lam, double n_h, R* __restrict__ v,
+    R* __restrict__ u, const R* __restrict__ h, const R* __restrict__ V,
+    const R* __restrict__ gradv, const double* __restrict__ accel,
+    const double* __restrict__ dudt, R* __restrict__ vh, R* __restrict__ uh,
+    double* __restrict__ hdot) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || refine_at[i] != j) return;
+  const int64_t per_old = level_span(lvl, lmax, i);
+  const double e = (double)(j & (per_old - 1)) * dt_min;
+  lvl[i] = refine_level[i];
+  const double dtc = (double)level_span(lvl, lmax, i) * dt_min;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double vr = (double)v[a * n + i] + accel[a * n + i] * e;
+    v[a * n + i] = (R)vr;
+    vh[a * n + i] = (R)((double)(R)vr + 0.5 * dtc * accel[a * n + i]);
+  }
+  const double ur = (double)u[i] + dudt[i] * e;
+  u[i] = (R)ur;
+  uh[i] = (R)((double)(R)ur + 0.5 * dtc * dudt[i]);
+  const double hi = (double)h[i];
+  const double div = (double)gradv[i] + (double)gradv[4 * n + i] + (double)gradv[8 * n + i];
+  const double delta_n = n_h * cbrt((double)V[i]) / hi;
+  const double h_thacker = hi * (1.0 - lam + lam * delta_n);
+  hdot[i] = (h_thacker - hi) / dtc + hi * div / 3.0;
+}
+
 // Drift of substep j for every particle: positions on the parabola of the
 // particle's constant a^0, v_j = v^1/2 + a^0 (t_elapsed + (dt_min - dt_a) / 2)
 // (FP64, wrapped into [0, box)); h <- h exp(hdot dt_min / h); the passive
@@ -180,14 +220,23 @@ __global__ void __launch_bounds__(kBlock) k_hier_close(
   dudt[i] = du1[i];
 }
 
-// Largest level (a max counter) and the count of levels outside [0, 30].
-__global__ void __launch_bounds__(kBlock) k_level_range(const int* __restrict__ levels, int64_t n,
+// Largest level (a max counter) over the levels and the refinement levels,
+// and the count of levels outside [0, 30] or refinements not to a finer
+// level (refine_at null: none).
+__global__ void __launch_bounds__(kBlock) k_level_range(const int* __restrict__ levels,
+                                                        const int* __restrict__ refine_at,
+                                                        const int* __restrict__ refine_level,
+                                                        int64_t n,
                                                         unsigned long long* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned long long top = 0, bad = 0;
   if (i < n) {
     const int L = levels[i];
     if (L < 0 || L > 30) bad = 1; else top = (unsigned long long)L;
+    if (refine_at && refine_at[i] >= 0) {
+      const int Lr = refine_level[i];
+      if (!(Lr > L && Lr <= 30)) bad = 1; else top = top > (unsigned long long)Lr ? top : Lr;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -199,6 +248,24 @@ __global__ void __launch_bounds__(kBlock) k_level_range(const int* __restrict__ 
     if (top) atomicMax(cnt_at(cnt, CNT_H_ITER_MAX), top);
     if (bad) atomicAdd(cnt_at(cnt, CNT_BAD_INPUT), bad);
   }
+}
+
+// Refinements off the grid of their new level (refine_at not a multiple of
+// 2^(lmax - refine_level)) or past the last substep, counted as bad input.
+__global__ void __launch_bounds__(kBlock) k_refine_grid(const int* __restrict__ refine_at,
+                                                        const int* __restrict__ refine_level,
+                                                        int64_t n, int lmax,
+                                                        unsigned long long* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long bad = 0;
+  if (i < n && refine_at[i] >= 0) {
+    const int64_t j = refine_at[i];
+    const int64_t per = (int64_t)1 << (lmax - refine_level[i]);
+    if (j >= ((int64_t)1 << lmax) || (j & (per - 1))) bad = 1;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(cnt_at(cnt, CNT_BAD_INPUT), bad);
 }
 
 }  // namespace
@@ -236,8 +303,26 @@ void launch_hier_close(int64_t n, const int* levels, int lmax, int64_t jend, dou
                      jend, dt_min, v, u, vh, uh, acc1, du1, accel, dudt);
 }
 
-void launch_level_range(const int* levels, int64_t n, unsigned long long* cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_level_range, dim3(grid_for(n)), dim3(kBlock), 0, s, levels, n, cnt);
+void launch_level_range(const int* levels, const int* refine_at, const int* refine_level,
+                        int64_t n, unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_range, dim3(grid_for(n)), dim3(kBlock), 0, s, levels, refine_at,
+                     refine_level, n, cnt);
+}
+
+void launch_refine_grid(const int* refine_at, const int* refine_level, int64_t n, int lmax,
+                        unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_grid, dim3(grid_for(n)), dim3(kBlock), 0, s, refine_at,
+                     refine_level, n, lmax, cnt);
+}
+
+template <class R>
+void launch_hier_refine(int64_t n, int64_t j, const int* refine_at, const int* refine_level,
+                        int* lvl, int lmax, double dt_min, double lam, double n_h, R* v, R* u,
+                        const R* h, const R* V, const R* gradv, const double* accel,
+                        const double* dudt, R* vh, R* uh, double* hdot, hipStream_t s) {
+  hipLaunchKernelGGL(k_hier_refine<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, j, refine_at,
+                     refine_level, lvl, lmax, dt_min, lam, n_h, v, u, h, V, gradv, accel, dudt,
+                     vh, uh, hdot);
 }
 
 template <class R>
@@ -272,7 +357,11 @@ void launch_kick_close(int64_t n, double dt, R* v, R* u, const double* accel, co
                                        hipStream_t);                                             \
   template void launch_hier_close<R>(int64_t, const int*, int, int64_t, double, R*, R*,         \
                                      const R*, const R*, const double*, const double*, double*, \
-                                     double*, hipStream_t);
+                                     double*, hipStream_t);                                      \
+  template void launch_hier_refine<R>(int64_t, int64_t, const int*, const int*, int*, int,      \
+                                      double, double, double, R*, R*, const R*, const R*,       \
+                                      const R*, const double*, const double*, R*, R*, double*,  \
+                                      hipStream_t);
 CRK_STEP_INSTANTIATE(float)
 CRK_STEP_INSTANTIATE(double)
 

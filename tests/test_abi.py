@@ -89,7 +89,7 @@ def test_null_context_is_rejected(crk):
     assert L.crk_forward(None, None, 0, *([None] * 14), None) == -1
     assert L.crk_backward(None, None, 0, *([None] * 6)) == -1
     assert L.crk_kdk_step(None, None, 0, 1e-3, 0.5, *([None] * 14), None) == -1
-    assert L.crk_hkdk_step(None, None, 0, 1e-3, 0.5, *([None] * 15), None) == -1
+    assert L.crk_hkdk_step(None, None, 0, 1e-3, 0.5, *([None] * 17), None) == -1
     assert L.crk_cooling_table(None, None, 2, 0.0, 0.1, None) == -1
     assert L.crk_cool(None, None, 0, 1.0, None, None) == -1
     assert L.crk_deposit(None, None, 0, *([None] * 7), 0, *([None] * 5), 2.0, 1.0, 1.0,

@@ -13,6 +13,12 @@ passive V and rho; measured <= 2.5e-6). A wrong passive state shows at
 all levels 0 is crk_kdk_step and one level L everywhere is 2^L single-level
 steps of dt / 2^L (up to the rounding of the two h-update forms), in FP64
 and FP32; one big step with the Wendland C4 kernel (FP64); the argument errors.
+Timestep refinement (App. A.5): two big steps on levels 0-2 with random
+refinements to finer levels (up to 3: eight substeps), at substeps on their
+new level's grid, midway through intervals and at their starts, against the
+oracle's refined step to the same bounds; no refinement (refine_at -1 for
+every particle) is the plain step bit for bit; refinements that break the
+rules are CRK_EINVAL.
 """
 import numpy as np
 import pytest
@@ -296,3 +302,95 @@ def test_big_step_with_relaxation():
         assert val <= STATE_BOUND[FP64], (k, val)
     for k, b in FP64_BOUNDS.items():
         assert e[k] <= b, (k, e[k], b)
+
+
+def _refine(n, rng, lev, lmax):
+    at = np.full(n, -1, dtype=np.int64)
+    to = lev.copy()
+    for i in np.nonzero(rng.uniform(size=n) < 0.3)[0]:
+        if lev[i] >= lmax:
+            continue
+        L = int(rng.integers(lev[i] + 1, lmax + 1))
+        at[i] = int(rng.integers(0, 1 << L)) << (lmax - L)
+        to[i] = L
+    return at, to
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_refined_big_steps_match_the_oracle(precision):
+    ps = _start(3000, 331)
+    print("case random3000 levels 0-2 refined to 3, precision=%d" % precision, flush=True)
+    dt, lam = 2e-4, 0.5
+    rng = np.random.default_rng(332)
+    lev = rng.integers(0, 3, ps.n)
+    lev[0] = 2
+    p = oracle.params_for(ps)
+    ctx = Context(_gpu.params_for(ps, precision))
+    x, v, m, u, h = _gpu.to_dev(ps, precision)
+    levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+    out = ctx.forward(x, v, m, u, h)
+    ox, ov, ou, oh = ps.x.copy(), ps.v.copy(), ps.u.copy(), ps.h.copy()
+    prev = oracle.forward(ox, ov, ps.m, ou, oh, p)
+    bounds = FP64_BOUNDS if precision == FP64 else FP32_BOUNDS
+    for it in range(2):
+        at, to = _refine(ps.n, rng, lev, 3)
+        print("big step", it, "refinements", int((at >= 0).sum()), "midway",
+              int(((at >= 0) & (at % (1 << (3 - lev)) != 0)).sum()), flush=True)
+        ref = (torch.tensor(at, dtype=torch.int32, device=x.device),
+               torch.tensor(to, dtype=torch.int32, device=x.device))
+        out = ctx.hkdk_step(x, v, m, u, out, levels, dt, lam, stats=True, refine=ref)
+        torch.cuda.synchronize()
+        o = oracle.hkdk_step(ox, ov, ps.m, ou, oh, prev, lev, p, dt, lam, refine=(at, to))
+        ox, ov, ou, oh, prev = o["x"], o["v"], o["u"], o["h"], o
+        st = _state_errors(x, v, u, out, o)
+        g = {k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}
+        e = _gpu.errors(g, o, o["h"])
+        print("big step", it, {k: "%.2e" % val for k, val in st.items()},
+              {k: "%.2e" % val for k, val in e.items()}, flush=True)
+        for k, val in st.items():
+            assert val <= STATE_BOUND[precision], (it, k, val)
+        for k, b in bounds.items():
+            assert e[k] <= b, (it, k, e[k], b)
+
+
+def test_empty_refinement_is_the_plain_step():
+    ps = _start(1500, 341)
+    print("case random1500 refine_at all -1", flush=True)
+    lev = np.random.default_rng(342).integers(0, 3, ps.n)
+    runs = []
+    for refine in (False, True):
+        ctx = Context(_gpu.params_for(ps, FP32))
+        x, v, m, u, h = _gpu.to_dev(ps, FP32)
+        levels = torch.tensor(lev, dtype=torch.int32, device=x.device)
+        out = ctx.forward(x, v, m, u, h)
+        ref = None
+        if refine:
+            ref = (torch.full((ps.n,), -1, dtype=torch.int32, device=x.device), levels.clone())
+        out = ctx.hkdk_step(x, v, m, u, out, levels, 2e-4, 0.5, refine=ref)
+        torch.cuda.synchronize()
+        runs.append({"x": _np(x), "v": _np(v), "u": _np(u),
+                     **{k: _np(t) for k, t in out.items() if isinstance(t, torch.Tensor)}})
+    for k in runs[0]:
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
+def test_refinement_errors():
+    ps = _start(300, 351)
+    print("case random300 bad refinements", flush=True)
+    ctx = Context(_gpu.params_for(ps, FP32))
+    x, v, m, u, h = _gpu.to_dev(ps, FP32)
+    out = ctx.forward(x, v, m, u, h)
+    lev = torch.ones(ps.n, dtype=torch.int32, device=x.device)
+    at = torch.full((ps.n,), -1, dtype=torch.int32, device=x.device)
+    at[5] = 0
+    with pytest.raises(CrkError):  # not a finer level
+        ctx.hkdk_step(x, v, m, u, out, lev, 1e-4, refine=(at, lev.clone()))
+    to = lev.clone()
+    to[5] = 2
+    to[6] = 3
+    at[6] = 0
+    at[5] = 1  # level 2 of lmax 3 starts on even substeps only
+    with pytest.raises(CrkError):
+        ctx.hkdk_step(x, v, m, u, out, lev, 1e-4, refine=(at, to))
+    at[5] = 2
+    ctx.hkdk_step(x, v, m, u, out, lev, 1e-4, refine=(at, to))
