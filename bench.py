@@ -133,8 +133,9 @@ def run_gpu(ps, precision, steps, warmup, backward, kernel=0, samples=None, grad
     x, v, m, u, h = t(ps.x, torch.float64), t(ps.v), t(ps.m), t(ps.u), t(ps.h)
     wa = t(ps.w_a, torch.float64) if backward else None
     wu = t(ps.w_u, torch.float64) if backward else None
-    ctx.reserve(ps.n)
-    out = ctx.forward(x, v, m, u, h, stats=True)   # sizes workspace and lists
+    # the first call sizes the workspace for this search (crk_reserve would also
+    # size the cell list's candidate scratch, which the tree search does not use)
+    out = ctx.forward(x, v, m, u, h, stats=True)
     stats = out["stats"]
 
     def step():
