@@ -354,6 +354,17 @@ def run_hkdk(ps, steps, warmup, dt):
 
 
 COOL_BYTES_PER_PARTICLE = 12  # FP32: read u and rho, write u
+# FP64 operations per particle on the common path (a run of same-sign bins):
+# rho dt 1, bin index 2, the in-bin log 4, the in-bin integral 2, the target 2,
+# its inverse 6 (difference, two divisions, node log 3), the final sum 1: 18,
+# and four transcendentals (log10, expm1, log1p, exp) counted as one each
+COOL_FP64_OPS_PER_PARTICLE = 22
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (published)
+# Algorithmic HBM bytes of a deposition call (FP32 state, FP64 positions):
+# per gas particle x 24, h, V, m, mZ, u 20, v 12 read and m, mZ, u, v 24
+# written; per source x 24, dM, dMZ, dE 12, v 12 read and V, h, A 12 written
+DEP_BYTES_PER_GAS = 80
+DEP_BYTES_PER_SOURCE = 60
 
 
 def run_cool(n, steps, warmup, seed=11):
@@ -523,12 +534,26 @@ def extras(args, ps):
                         "zero" % ck,
             "hbm": {"bytes_per_particle": COOL_BYTES_PER_PARTICLE,
                     "GBps": round(cool_bps / 1e9, 1),
-                    "frac_of_8TBps": round(cool_bps / 8e12, 3)}}
+                    "frac_of_8TBps": round(cool_bps / 8e12, 3)},
+            "fp64_alu": {"ops_per_particle": COOL_FP64_OPS_PER_PARTICLE,
+                         "model": "18 FP64 arithmetic operations and 4 transcendentals counted as "
+                                  "one each, per particle on the common path",
+                         "achieved_TFLOPs": round(COOL_FP64_OPS_PER_PARTICLE * ncool /
+                                                  (cus * 1e-6) / 1e12, 3),
+                         "peak": PEAK_FP64_TFLOPS,
+                         "frac": round(COOL_FP64_OPS_PER_PARTICLE * ncool / (cus * 1e-6) / 1e12 /
+                                       PEAK_FP64_TFLOPS, 4)}}
     log("cooling: %.1f us for %d particles" % (cus, ncool))
     ngas, nsrc = 1 << 21, 1 << 16
     dwall, ddev = run_deposit(ngas, nsrc, args.steps, args.warmup)
+    dep_bytes = DEP_BYTES_PER_GAS * ngas + DEP_BYTES_PER_SOURCE * nsrc
     dep = {"us_per_call": round(dwall, 2), "device_us_per_call": round(ddev, 2),
            "value": nsrc / (dwall * 1e-6), "unit": "sources/s",
+           "hbm": {"bytes_per_call": dep_bytes,
+                   "model": "%d B per gas particle and %d B per source read or written once"
+                            % (DEP_BYTES_PER_GAS, DEP_BYTES_PER_SOURCE),
+                   "GBps": round(dep_bytes / (ddev * 1e-6) / 1e9, 1),
+                   "frac_of_8TBps": round(dep_bytes / (ddev * 1e-6) / 8e12, 4)},
            "workload": "2^21 FP32 gas (uniform, ~32 neighbours, h spread 20%), 2^16 "
                        "uniform sources, Wendland C4, n_h,s = 2.25; one gas grid, one pair "
                        "sort, two host reads"}
@@ -604,6 +629,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-step, hierarchy, cooling and deposition fields")
     ap.add_argument("--no-c4", action="store_true", help="skip the Wendland C4 n_h = 4 field")
+    ap.add_argument("--only-small", action="store_true",
+                    help="only the 64^3 lattice fields, printed as the line (profiling runs of "
+                         "that workload; not the benchmark's measurement)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with two plain 256 MiB device copies (untimed), the reference "
                          "for scaling the HBM byte counters of a profiling run")
@@ -619,6 +647,13 @@ def main():
 
     import synth
     from paper_2511_21921_amd import FP32, FP64
+
+    if args.only_small:
+        small, _ = small_fields(args, not args.no_cpu)
+        print(json.dumps({"metric": METRIC, "profile_only": "sedov64", "sedov64": small}),
+              flush=True)
+        calibration_copy(args)
+        return
 
     t0 = time.perf_counter()
     ps = synth.clumps256()
@@ -714,6 +749,12 @@ def main():
     if more:
         line.update(more)
     print(json.dumps(line), flush=True)
+    calibration_copy(args)
+
+
+def calibration_copy(args):
+    """Two plain 256 MiB device copies (untimed): the reference that scales the HBM byte
+    counters of a profiling run."""
     if args.calibration_copy:
         import torch
         a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda:0")
