@@ -553,7 +553,7 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   CRK_HIP(hipMemsetAsync(ns, 0, 4 * (size_t)nw * 64, s), "memset");
   {
     State<R> S = make_state<R>(ctx, n);
-    launch_filter_tree<R>(S, false, fillc, s);
+    launch_filter_tree<R>(S, false, fillc, nullptr, s);
   }
   CRK_HIP(offsets(ng, 0, wg, lg, &ctx->host_rows[0]), "list rows");
   CRK_HIP(offsets(ns, 0, ws, ls, &ctx->host_rows[1]), "list rows");
@@ -561,9 +561,11 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
   CRK_HIP(ensure(ctx->slist, 4 * 256 * (size_t)ctx->host_rows[1]), "alloc neighbour list");
   CRK_HIP(hipMemsetAsync(dcnt + CNT_PAIRS_GATHER * kCntSpread, 0, 8 * 2 * kCntSpread, s), "memset");
   CRK_HIP(hipMemsetAsync(fillc, 0, 4 * (size_t)nw * 64, s), "memset");
+  CRK_HIP(hipMemsetAsync(dcnt + CNT_LONG_LISTS * kCntSpread, 0, 8 * kCntSpread, s), "memset");
   {
+    // the rank order of the search rounds is free: the queue of long lists
     State<R> S = make_state<R>(ctx, n);
-    launch_filter_tree<R>(S, true, fillc, s);
+    launch_filter_tree<R>(S, true, fillc, (uint32_t*)ctx->torder.p, s);
   }
   CRK_HIP(tend(ctx, P_NLIST, s), "event");
   CRK_HIP(hipGetLastError(), "neighbour list launch");
@@ -924,11 +926,14 @@ void adj_pointers(AdjState<R>& G, void* const* p) {
   G.kap = (R*)p[10];
 }
 
-// The adjoint of the last forward. The workspace comes from the context
-// (grown with hipMalloc as needed) or, when arena is given, is carved from
-// that device memory (at least adj_layout(n) bytes), with no allocation.
-// Every workspace array is written before it is read: nothing needs to
-// start at zero.
+// The adjoint of the last forward. The workspace comes from the context or,
+// when arena is given, is carved from that device memory (at least
+// adj_layout(n) bytes), with no allocation. From the context it is carved
+// from the candidate scratch when that is large enough (the scratch is dead
+// once the forward has built its neighbour lists, and the next forward
+// rebuilds it from nothing), else from arrays grown with hipMalloc. Every
+// workspace array is written before it is read: nothing needs to start at
+// zero.
 template <class R>
 crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g_accel,
                          const double* g_dudt, double* g_x, double* g_v, double* g_u,
@@ -938,8 +943,10 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   size_t off[kAdjArrays];
   const size_t total = adj_layout(n, RS, off);
   void* ptr[kAdjArrays];
-  if (arena) {
-    for (int k = 0; k < kAdjArrays; ++k) ptr[k] = arena + off[k];
+  unsigned char* base = arena;
+  if (!base && ctx->cand.bytes >= total) base = (unsigned char*)ctx->cand.p;
+  if (base) {
+    for (int k = 0; k < kAdjArrays; ++k) ptr[k] = base + off[k];
   } else {
     Buf* bufs[kAdjArrays] = {&ctx->a_gx,  &ctx->a_gv,   &ctx->a_gu,   &ctx->a_gh,
                              &ctx->a_gV,  &ctx->a_gkc,  &ctx->a_gab,  &ctx->a_wgt4,

@@ -46,9 +46,12 @@ void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
 void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s);
 // Gather lists and the scatter-only lists (their transpose) from the kept
 // candidates: lengths and scatter-only counts (write = false), then entries,
-// the scatter-only ones appended at fillc and then sorted.
+// the scatter-only ones appended at fillc and then sorted (queue: room for n
+// particle indices, the lists too long to sort in registers; the counter
+// CNT_LONG_LISTS must start at zero).
 template <class R>
-void launch_filter_tree(const State<R>& S, bool write, int* fillc, hipStream_t s);
+void launch_filter_tree(const State<R>& S, bool write, int* fillc, uint32_t* queue,
+                        hipStream_t s);
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s);
 
 // Gather caller arrays into cell-sorted SoA with cell-centre offsets.

@@ -32,6 +32,7 @@ enum Counter {
   CNT_CELL_MAX,        // largest cell occupancy of the cell list
   CNT_TOO_DENSE,       // a cell beyond the occupancy limit of a speculative cell list
   CNT_CANDIDATES,      // candidates kept by the neighbour search (all its passes)
+  CNT_LONG_LISTS,      // tree path: scatter-only lists queued for the wave sort (slot 0 only)
   CNT_COUNT
 };
 

@@ -594,8 +594,25 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __restrict__ rows) {
   const int64_t s = particle_id();
-  if (s >= S.n || !S.todo[s]) return;
-  atomicMax(&rows[S.cslot[s] >> 6], (uint32_t)((S.need[s] + 15) >> 4));
+  if ((s & ~(int64_t)63) >= S.n) return;
+  const bool t = s < S.n && S.todo[s];
+  const uint64_t any = __ballot(t);
+  if (any == 0ull) return;
+  // the unsolved particles of a wave hold consecutive ranks, so they fall in
+  // at most two consecutive groups of 64: one max and one atomic per group
+  const uint32_t key = t ? (S.cslot[s] >> 6) : 0u;
+  const uint32_t val = t ? (uint32_t)((S.need[s] + 15) >> 4) : 0u;
+  const uint32_t g0 = (uint32_t)__shfl((int)key, __ffsll((unsigned long long)any) - 1, 64);
+  uint32_t v0 = (t && key == g0) ? val : 0u, v1 = (t && key != g0) ? val : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 = max(v0, (uint32_t)__shfl_xor((int)v0, o, 64));
+    v1 = max(v1, (uint32_t)__shfl_xor((int)v1, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&rows[g0], v0);
+    if (v1) atomicMax(&rows[g0 + 1], v1);
+  }
 }
 
 // The unsolved particles in rank order.
@@ -692,32 +709,143 @@ __global__ void __launch_bounds__(kBlock) k_wave_rows(const int* __restrict__ cn
   if ((threadIdx.x & 63) == 0) rows[s >> 6] = (uint32_t)((c + 3) >> 2);
 }
 
-// Sorts every scatter-only list by j (insertion sort; the lists are short),
-// giving the order a walk would produce and making runs reproducible; counts
-// the force pairs.
+// Ascending bitonic sorting network over N values held in registers (every
+// index is a compile-time constant once the loops unroll).
+template <int N>
+__device__ inline void bitonic_sort(uint32_t (&a)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint32_t lo = min(a[i], a[l]), hi = max(a[i], a[l]);
+          a[i] = (i & k) == 0 ? lo : hi;
+          a[l] = (i & k) == 0 ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
+// One lane's list of ns <= N entries, read as 16-byte chunks, padded with
+// 0xffffffff, sorted in registers and written back chunk by chunk.
+template <int N>
+__device__ inline void sort_list_regs(uint32_t* __restrict__ list, int64_t sb, int ns) {
+  uint32_t a[N];
+#pragma unroll
+  for (int c = 0; c < N / 4; ++c) {
+    uint4 q = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+    if (4 * c < ns) q = *reinterpret_cast<const uint4*>(list + slot_at(sb, 4 * c));
+    a[4 * c] = 4 * c < ns ? q.x : 0xffffffffu;
+    a[4 * c + 1] = 4 * c + 1 < ns ? q.y : 0xffffffffu;
+    a[4 * c + 2] = 4 * c + 2 < ns ? q.z : 0xffffffffu;
+    a[4 * c + 3] = 4 * c + 3 < ns ? q.w : 0xffffffffu;
+  }
+  bitonic_sort<N>(a);
+#pragma unroll
+  for (int c = 0; c < N / 4; ++c)
+    if (4 * c < ns)
+      *reinterpret_cast<uint4*>(list + slot_at(sb, 4 * c)) =
+          make_uint4(a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]);
+}
+
+// Sorts every scatter-only list by j, giving the order a walk would produce
+// and making runs reproducible; counts the force pairs. Lists of at most 64
+// entries are sorted in their lane's registers (a network of the wave's size
+// class); longer ones are queued (queue[], their number in the slot 0 of
+// CNT_LONG_LISTS) for k_sort_long.
+constexpr int kShortList = 64;
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S) {
+__global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S, uint32_t* __restrict__ queue) {
   const int64_t s = particle_id();
+  if ((s & ~(int64_t)63) >= S.n) return;
   unsigned long long f = 0;
+  int ns = 0;
+  int64_t sb = 0;
   if (s < S.n) {
     const int64_t w = s >> 6;
     const int scap = (int)(S.srow[w + 1] - S.srow[w]) * 4;
-    const int ns = S.ns[s] < scap ? S.ns[s] : scap;
-    const int64_t sb = slot_base(S.srow[w], s);
-    for (int a = 1; a < ns; ++a) {
-      const uint32_t v = S.slist[slot_at(sb, a)];
-      int b = a - 1;
-      while (b >= 0 && S.slist[slot_at(sb, b)] > v) {
-        S.slist[slot_at(sb, b + 1)] = S.slist[slot_at(sb, b)];
-        --b;
-      }
-      S.slist[slot_at(sb, b + 1)] = v;
-    }
+    ns = S.ns[s] < scap ? S.ns[s] : scap;
+    sb = slot_base(S.srow[w], s);
     f = (unsigned long long)(S.ng[s] + S.ns[s]);
+  }
+  if (ns > kShortList) {
+    queue[atomicAdd(S.cnt + CNT_LONG_LISTS * kCntSpread, 1ull)] = (uint32_t)s;
+    ns = 0;
+  }
+  int big = ns;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) big = max(big, __shfl_xor(big, o, 64));
+  if (big > 32) {
+    sort_list_regs<64>(S.slist, sb, ns);
+  } else if (big > 16) {
+    sort_list_regs<32>(S.slist, sb, ns);
+  } else if (big > 8) {
+    sort_list_regs<16>(S.slist, sb, ns);
+  } else if (big > 1) {
+    sort_list_regs<8>(S.slist, sb, ns);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
   if ((threadIdx.x & 63) == 0 && f) atomicAdd(cnt_at(S.cnt, CNT_PAIRS_FORCE), f);
+}
+
+// The queued long scatter-only lists, one per single-wave block in turn: up
+// to kLongSort entries are padded to a power of two with 0xffffffff and
+// sorted by a bitonic network in LDS (each compare-exchange owned by the lane
+// of its lower index, a barrier between steps); a longer list takes an
+// insertion sort in memory by one lane.
+constexpr int kLongSort = 4096;
+template <class R>
+__global__ void __launch_bounds__(64) k_sort_long(State<R> S, const uint32_t* __restrict__ queue) {
+  __shared__ uint32_t buf[kLongSort];
+  const unsigned long long nq = S.cnt[CNT_LONG_LISTS * kCntSpread];
+  const int lane = threadIdx.x;
+  for (unsigned long long q = blockIdx.x; q < nq; q += gridDim.x) {
+    const int64_t s = queue[q];
+    const int64_t w = s >> 6;
+    const int scap = (int)(S.srow[w + 1] - S.srow[w]) * 4;
+    const int ns = S.ns[s] < scap ? S.ns[s] : scap;
+    const int64_t sb = slot_base(S.srow[w], s);
+    if (ns > kLongSort) {
+      if (lane == 0) {
+        for (int a = 1; a < ns; ++a) {
+          const uint32_t v = S.slist[slot_at(sb, a)];
+          int b = a - 1;
+          while (b >= 0 && S.slist[slot_at(sb, b)] > v) {
+            S.slist[slot_at(sb, b + 1)] = S.slist[slot_at(sb, b)];
+            --b;
+          }
+          S.slist[slot_at(sb, b + 1)] = v;
+        }
+      }
+      continue;
+    }
+    int P = 64;
+    while (P < ns) P <<= 1;
+    for (int k = lane; k < P; k += 64) buf[k] = k < ns ? S.slist[slot_at(sb, k)] : 0xffffffffu;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < P; i += 64) {
+          const int l = i ^ j;
+          if (l > i) {
+            const uint32_t a = buf[i], b = buf[l];
+            if ((a > b) == ((i & k) == 0)) {
+              buf[i] = b;
+              buf[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int k = lane; k < ns; k += 64) S.slist[slot_at(sb, k)] = buf[k];
+    __syncthreads();  // the reads above before the next list's writes
+  }
 }
 
 }  // namespace
@@ -797,11 +925,13 @@ void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s) {
 }
 
 template <class R>
-void launch_filter_tree(const State<R>& S, bool write, int* fillc, hipStream_t s) {
+void launch_filter_tree(const State<R>& S, bool write, int* fillc, uint32_t* queue,
+                        hipStream_t s) {
   if (write) {
     hipLaunchKernelGGL((k_filter_tree<R, true>), dim3(grid_for(16 * S.n)), dim3(kBlock), 0, s,
                        S, fillc);
-    hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+    hipLaunchKernelGGL(k_scatter_sort<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, queue);
+    hipLaunchKernelGGL(k_sort_long<R>, dim3(1024), dim3(64), 0, s, S, (const uint32_t*)queue);
   } else {
     hipLaunchKernelGGL((k_filter_tree<R, false>), dim3(grid_for(16 * S.n)), dim3(kBlock), 0, s,
                        S, fillc);
@@ -822,7 +952,7 @@ void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipS
   template void launch_hsolve_tree<R>(const State<R>&, int, const uint32_t*, int64_t,       \
                                       hipStream_t);                                          \
   template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
-  template void launch_filter_tree<R>(const State<R>&, bool, int*, hipStream_t);
+  template void launch_filter_tree<R>(const State<R>&, bool, int*, uint32_t*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
 CRK_INSTANTIATE_TREE(double)
