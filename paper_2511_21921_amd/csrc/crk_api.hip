@@ -55,13 +55,17 @@ struct crk_ctx {
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
-  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder, absp, hl_lvl;
+  Buf rad, need, todo, tslot, nlo, nhi, lvl, wrow, lrow, cpos, torder, absp, hl_lvl, need4, coff;
+  // tree path candidate pool: entries the last forward's rounds took, and the
+  // placement of the current round (see State::pool_base4)
+  size_t pool_hint = 0;
+  int64_t pool_base4 = 0;
+  int64_t pool_cap = 0;
   uint32_t host_rows[2] = {};
   int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
   int lattice = 0;
-  // adjoint workspace
-  Buf a_gx, a_gv, a_gu, a_gh, a_gV, a_gkc, a_gab, a_wgt4, a_gvc4, a_mom4, a_kap;
+  // (the adjoint workspace is carved from the candidate scratch)
   // time step: the velocity and energy predicted for the end-of-step evaluation
   Buf vpred, upred;
   // timestep hierarchy: half-kicked velocity and energy, hdot, and the
@@ -267,7 +271,9 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.need = c->lattice ? (int*)c->need.p : nullptr;
   S.todo = c->lattice ? (int*)c->todo.p : nullptr;
   S.cslot = c->lattice ? (const uint32_t*)c->tslot.p : nullptr;
-  S.vrow = c->lattice ? (const uint32_t*)c->wrow.p + ((n + 63) / 64) + 1 : nullptr;
+  S.coff4 = c->lattice ? (const uint32_t*)c->coff.p : nullptr;
+  S.pool_base4 = c->pool_base4;
+  S.pool_cap = c->pool_cap;
   S.shrink = c->p.h_mode == 1 ? 1 : 0;
   S.ncen = (float4*)c->nlo.p;
   S.nhw = (float4*)c->nhi.p;
@@ -404,10 +410,11 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   ctx->G = 1024;
   ctx->ell = P.box / 1024.0;
   {
-    // room for ~5x the expected neighbour count (4 pi / 3) n_h^3 before a radius shrinks
+    // room for ~5x the expected neighbour count (4 pi / 3) n_h^3 before a
+    // radius shrinks (the cell path's capacity is its own: it is set again
+    // there)
     const double expect = 4.18879 * P.n_h * P.n_h * P.n_h;
-    const int want = std::max(320, (int)((5.0 * expect + 31.0) / 32.0) * 32);
-    if (ctx->scr_cap < want) ctx->scr_cap = want;
+    ctx->scr_cap = std::max(320, (int)((5.0 * expect + 31.0) / 32.0) * 32);
   }
   // levels of the implicit tree over the leaves
   const int nleaf = (int)((n + kLeaf - 1) / kLeaf);
@@ -432,7 +439,8 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   CRK_HIP(ensure(ctx->cpos, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->torder, 4 * (size_t)npad), "alloc tree");
   CRK_HIP(ensure(ctx->absp, 16 * (size_t)npad), "alloc tree");
-  CRK_HIP(ensure(ctx->wrow, 4 * 2 * (size_t)(npad / 64 + 1)), "alloc tree");
+  CRK_HIP(ensure(ctx->need4, 4 * (size_t)(npad + 1)), "alloc tree");
+  CRK_HIP(ensure(ctx->coff, 4 * (size_t)(npad + 1)), "alloc tree");
   CRK_HIP(ensure(ctx->scan_tmp, 4 * (size_t)scan_tmp_words(n + 1)), "alloc scan");
   int lv[2 * kMaxLevels];
   for (int t = 0; t < kMaxLevels; ++t) {
@@ -455,45 +463,66 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   }
   CRK_HIP(tend(ctx, P_CELLS, s), "event");
   // Rounds over the particles still unsolved. Each round ranks them (scan of
-  // the todo flags, todo[n] = 0), sizes every group of 64 ranks to the
-  // largest capacity request in it, places the round's rows after those of
-  // the earlier rounds (whose solved particles keep their candidates there),
-  // runs the candidate walk and the h solve (or the volume for fixed h) on
-  // them, and stops when none is left.
+  // the todo flags, todo[n] = 0), runs the candidate walk and the h solve (or
+  // the volume for fixed h) on them, and stops when none is left. The first
+  // round stages every row in LDS when its capacity fits there, and the
+  // blocks append the kept candidates to the pool; the others give each
+  // particle the room it asks for after what the earlier rounds took (the
+  // solved particles keep their candidates where they are).
   int* todo = (int*)ctx->todo.p;
   uint32_t* slot = (uint32_t*)ctx->tslot.p;
-  const int64_t ngrp = npad / 64;
-  uint32_t* grows = (uint32_t*)ctx->wrow.p;  // per-group rows, then their offsets
-  uint32_t* goff = grows + ngrp + 1;
+  uint32_t* need4 = (uint32_t*)ctx->need4.p;
+  uint32_t* coff = (uint32_t*)ctx->coff.p;
   CRK_HIP(hipMemsetAsync(todo + n, 0, 4, s), "memset");
-  uint32_t row_base = 0;  // rows taken by the earlier rounds
+  const double expect = 4.18879 * P.n_h * P.n_h * P.n_h;
+  int64_t used4 = 0;  // pool entries the earlier rounds took, in 4-entry units
+  bool staged = false;
+  unsigned long long pool_taken = 0;
   bool solved = false;
   for (int round = 0; round < 40; ++round) {
+    const bool stage = round == 0 && stage_fits(ctx->scr_cap);
     CRK_HIP(exclusive_scan_u32((const uint32_t*)todo, slot, n + 1, (uint32_t*)ctx->scan_tmp.p,
                                s),
             "scan");
     CRK_HIP(hipMemcpyAsync(&ctx->host_rows[0], slot + n, 4, hipMemcpyDeviceToHost, s), "rows");
-    CRK_HIP(hipMemsetAsync(grows, 0, 4 * (size_t)(ngrp + 1), s), "memset");
-    {
+    if (!stage) {
       State<R> S = make_state<R>(ctx, n);
-      launch_slot_rows<R>(S, grows, s);
+      launch_need4<R>(S, need4, s);
+      CRK_HIP(exclusive_scan_u32(need4, coff, n + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
+      CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], coff + n, 4, hipMemcpyDeviceToHost, s), "rows");
     }
-    CRK_HIP(exclusive_scan_u32(grows, goff, ngrp + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
-    launch_add_u32(goff, ngrp + 1, row_base, s);
-    CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], goff + ngrp, 4, hipMemcpyDeviceToHost, s), "rows");
+    if (staged)
+      CRK_HIP(hipMemcpyAsync(&pool_taken, dcnt + CNT_POOL * kCntSpread, 8, hipMemcpyDeviceToHost,
+                             s),
+              "pool");
     CRK_HIP(hipStreamSynchronize(s), "scan");
+    if (staged) {
+      used4 = (int64_t)(std::min<unsigned long long>(pool_taken, (unsigned long long)ctx->pool_cap) / 4);
+      staged = false;
+    }
     if (ctx->host_rows[0] == 0) {
       solved = true;
       break;
     }
-    const uint32_t rows_end = ctx->host_rows[1];  // a row: 16 entries of 64 slots
-    if (rows_end >= (1u << 26)) return fail(ctx, CRK_ENOMEM, "candidate scratch beyond 2^26 rows");
-    // the first round leaves an eighth more room for the later ones (the
-    // candidates are kept as indices only: the h solve and the list filter
-    // recompute the distances)
-    const size_t want = 1024 * (size_t)(round == 0 ? rows_end + rows_end / 8 : rows_end);
-    const size_t keep = 1024 * (size_t)row_base;
-    CRK_HIP(ensure_keep(ctx->cand, 4 * want, 4 * keep, s), "alloc candidates");
+    if (stage) {
+      // room for every round, from what the last forward's rounds took (at
+      // first twice the expected neighbour count per particle)
+      const size_t want = std::max(ctx->pool_hint, (size_t)((double)n * 2.0 * expect) + 4096);
+      CRK_HIP(ensure(ctx->cand, 4 * want), "alloc candidates");
+      CRK_HIP(hipMemsetAsync(dcnt + CNT_POOL * kCntSpread, 0, 8 * kCntSpread, s), "memset");
+      ctx->pool_base4 = 0;
+      ctx->pool_cap = (int64_t)(ctx->cand.bytes / 4) & ~(int64_t)3;
+      staged = true;
+    } else {
+      const int64_t add4 = ctx->host_rows[1];
+      if (used4 + add4 >= ((int64_t)1 << 32))
+        return fail(ctx, CRK_ENOMEM, "candidate pool beyond 2^34 entries");
+      CRK_HIP(ensure_keep(ctx->cand, 16 * (size_t)(used4 + add4), 16 * (size_t)used4, s),
+              "alloc candidates");
+      ctx->pool_base4 = used4;
+      ctx->pool_cap = 0;
+      used4 += add4;
+    }
     CRK_HIP(hipMemsetAsync(dcnt + CNT_H_CAPPED * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);
@@ -506,15 +535,16 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       order = (const uint32_t*)ctx->torder.p;
     }
     CRK_HIP(tbegin(ctx, P_CAND, s), "event");
-    launch_candidates_tree<R>(S, (const float4*)ctx->absp.p, P.kernel, order, nt, s);
+    launch_candidates_tree<R>(S, (const float4*)ctx->absp.p, P.kernel, stage, order, nt, s);
     CRK_HIP(tend(ctx, P_CAND, s), "event");
     ctx->searched += nt;
     CRK_HIP(tbegin(ctx, P_HSOLVE, s), "event");
     launch_hsolve_tree<R>(S, P.kernel, order, nt, s);
     CRK_HIP(tend(ctx, P_HSOLVE, s), "event");
     CRK_HIP(hipGetLastError(), "h solve launch");
-    row_base = rows_end;
   }
+  // the next forward reserves what this one took, and a twentieth more
+  ctx->pool_hint = (size_t)(4.2 * (double)used4) + 4096;
   CRK_HIP(read_counters(ctx, s), "h solve");
   if (!solved) return fail(ctx, CRK_EHIP, "tree h solve did not settle");
   return CRK_OK;
@@ -926,14 +956,12 @@ void adj_pointers(AdjState<R>& G, void* const* p) {
   G.kap = (R*)p[10];
 }
 
-// The adjoint of the last forward. The workspace comes from the context or,
-// when arena is given, is carved from that device memory (at least
-// adj_layout(n) bytes), with no allocation. From the context it is carved
-// from the candidate scratch when that is large enough (the scratch is dead
-// once the forward has built its neighbour lists, and the next forward
-// rebuilds it from nothing), else from arrays grown with hipMalloc. Every
-// workspace array is written before it is read: nothing needs to start at
-// zero.
+// The adjoint of the last forward. The workspace is carved from arena when
+// given (at least adj_layout(n) bytes), with no allocation, else from the
+// candidate scratch, grown to that size if smaller: the scratch is dead once
+// the forward has built its neighbour lists, and the next forward rebuilds
+// it from nothing. Every workspace array is written before it is read:
+// nothing needs to start at zero.
 template <class R>
 crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g_accel,
                          const double* g_dudt, double* g_x, double* g_v, double* g_u,
@@ -944,19 +972,11 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   const size_t total = adj_layout(n, RS, off);
   void* ptr[kAdjArrays];
   unsigned char* base = arena;
-  if (!base && ctx->cand.bytes >= total) base = (unsigned char*)ctx->cand.p;
-  if (base) {
-    for (int k = 0; k < kAdjArrays; ++k) ptr[k] = base + off[k];
-  } else {
-    Buf* bufs[kAdjArrays] = {&ctx->a_gx,  &ctx->a_gv,   &ctx->a_gu,   &ctx->a_gh,
-                             &ctx->a_gV,  &ctx->a_gkc,  &ctx->a_gab,  &ctx->a_wgt4,
-                             &ctx->a_gvc4, &ctx->a_mom4, &ctx->a_kap};
-    for (int k = 0; k < kAdjArrays; ++k) {
-      const size_t end = k + 1 < kAdjArrays ? off[k + 1] : total;
-      CRK_HIP(ensure(*bufs[k], end - off[k]), "adjoint workspace");
-      ptr[k] = bufs[k]->p;
-    }
+  if (!base) {
+    CRK_HIP(ensure(ctx->cand, total), "adjoint workspace");
+    base = (unsigned char*)ctx->cand.p;
   }
+  for (int k = 0; k < kAdjArrays; ++k) ptr[k] = base + off[k];
   // no timing events on the allocation-free path (creating them allocates)
   auto tb = [&](int k, hipStream_t st) { return arena ? hipSuccess : tbegin(ctx, k, st); };
   auto te = [&](int k, hipStream_t st) { return arena ? hipSuccess : tend(ctx, k, st); };
@@ -1370,8 +1390,7 @@ crk_status crk_destroy(crk_ctx* c) {
   Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_start,
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
-                &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->a_gx, &c->a_gv, &c->a_gu, &c->a_gh, &c->a_gV, &c->a_gkc,
-                &c->a_gab, &c->a_wgt4, &c->a_gvc4, &c->a_mom4, &c->a_kap, &c->vpred, &c->upred,
+                &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->vpred, &c->upred,
                 &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need,
                 &c->cool_lam, &c->cool_oma, &c->cool_co, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
@@ -1379,7 +1398,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->dep_pj_a, &c->dep_pj_b, &c->dep_ps_a, &c->dep_ps_b, &c->dep_ptmp,
                 &c->dep_p4, &c->dep_pv, &c->dep_sp, &c->dep_slot,
                 &c->rad, &c->need, &c->todo, &c->tslot, &c->nlo, &c->nhi, &c->lvl, &c->wrow, &c->lrow,
-                &c->cpos, &c->torder, &c->absp, &c->hl_lvl};
+                &c->cpos, &c->torder, &c->absp, &c->hl_lvl, &c->need4, &c->coff};
   for (Buf* b : all) release(*b);
   if (c->host_raw) (void)hipHostFree(c->host_raw);
   if (c->events_ready)

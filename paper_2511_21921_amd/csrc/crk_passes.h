@@ -29,21 +29,24 @@ void launch_init_radius(const State<R>& S, int h_mode, hipStream_t s);
 // The particles still to solve in rank order: order[cslot[s]] = s.
 template <class R>
 void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s);
-// Candidates of the unsolved particles; order null: thread t takes particle
-// t (all particles, 16 neighbouring particles per row sharing a walk), else
-// the 16-lane row t takes particle order[t] for t < nt.
+// Candidates of the unsolved particles, a 16-lane row per particle: row t
+// takes particle t (order null) or order[t], for t < nt. stage: the rows
+// work in LDS (capacity scr_cap, at most what stage_fits allows) and the
+// blocks append to the pool at the CNT_POOL counter, below pool_cap; else
+// each particle works in its room of need[s] at pool_base4 + coff4[s].
 template <class R>
-void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
+void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel, bool stage,
                             const uint32_t* order, int64_t nt, hipStream_t s);
+bool stage_fits(int scr_cap);
 // The h solve (solved h) or the volume (fixed h) of the particles whose
 // candidates the round kept, a 16-lane row per particle (order as above).
 template <class R>
 void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
                         hipStream_t s);
+// need4[s]: the room unsolved particle s asks for, in 4-entry units (0 when
+// solved), and need4[n] = 0
 template <class R>
-void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s);
-// a[0 .. na) += v
-void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s);
+void launch_need4(const State<R>& S, uint32_t* need4, hipStream_t s);
 // Gather lists and the scatter-only lists (their transpose) from the kept
 // candidates: lengths and scatter-only counts (write = false), then entries,
 // the scatter-only ones appended at fillc and then sorted (queue: room for n

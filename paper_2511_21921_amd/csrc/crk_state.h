@@ -33,6 +33,7 @@ enum Counter {
   CNT_TOO_DENSE,       // a cell beyond the occupancy limit of a speculative cell list
   CNT_CANDIDATES,      // candidates kept by the neighbour search (all its passes)
   CNT_LONG_LISTS,      // tree path: scatter-only lists queued for the wave sort (slot 0 only)
+  CNT_POOL,            // tree path: candidate pool entries taken by staged blocks (slot 0 only)
   CNT_COUNT
 };
 
@@ -116,11 +117,18 @@ struct State {
                       // (at rad + n) by the largest radius known to lie below the root
   int* need;          // per-particle candidate capacity request (tree path) or null
   int* todo;          // per-particle "h not solved yet" flag (tree path) or null
-  // tree path: rank of each particle among the unsolved ones (its scratch
-  // slot), and the group-row offset of every group of 64 slots, whose
-  // capacity is the largest request in the group; null on the cell path
+  // tree path: rank of each particle among the unsolved ones; null on the
+  // cell path
   const uint32_t* cslot;
-  const uint32_t* vrow;
+  // tree path candidate pool (cand), every particle's candidates contiguous
+  // from entry 4 cpos[s]: a round that stages them in LDS (the first, when
+  // the capacity fits) appends each block's at a bump counter (the slot 0 of
+  // CNT_POOL) below pool_cap entries; the other rounds give particle s the
+  // room need[s] at 4 (pool_base4 + coff4[s]) (coff4: exclusive sums of the
+  // requests of the round, in 4-entry units)
+  const uint32_t* coff4;
+  int64_t pool_base4;
+  int64_t pool_cap;
   int shrink;         // tree path: adapt the radius of an overflowing particle
   // tree over leaves of kLeaf Morton-sorted particles (tree path): node boxes,
   // built as (x, y, z, h_max) low and (x, y, z, -) high corners, then kept as
@@ -130,8 +138,7 @@ struct State {
   const int* lvl_off;  // [2 kMaxLevels]: node offset of each level (level 0 =
                        // leaves), then the node count of each level
   int nlevels;
-  // tree path: where each solved particle's candidates are kept, (row << 6) |
-  // lane for group_base (rows of all rounds are disjoint)
+  // tree path: where each particle's candidates start, in 4-entry units
   uint32_t* cpos;
   unsigned long long* cnt;
   // parameters
@@ -244,26 +251,12 @@ __device__ inline int need_after_growth(int cnt, double g) {
   return (c + 3) & ~3;
 }
 
-// First word and capacity of particle s's candidate scratch: slot s with the
-// uniform capacity on the cell path; on the tree path its rank among the
-// particles still unsolved, with the capacity of its group of 64 ranks.
+// First word and capacity of particle s's candidate scratch on the cell
+// path: slot s with the uniform capacity.
 template <class R>
 __device__ inline int64_t scratch_base(const State<R>& S, int64_t s, int& cap) {
-  if (!S.cslot) {
-    cap = S.scr_cap;
-    return group_base((s >> 6) * (int64_t)(S.scr_cap >> 4), s);
-  }
-  const int64_t q = S.cslot[s], w = q >> 6;
-  cap = (int)(S.vrow[w + 1] - S.vrow[w]) * 16;
-  return group_base(S.vrow[w], q);
-}
-
-// Tree path: the packed position (row << 6) | lane of particle s's scratch
-// slot in this round, kept in cpos once its h is solved.
-template <class R>
-__device__ inline uint32_t scratch_pos(const State<R>& S, int64_t s) {
-  const uint32_t q = S.cslot[s];
-  return (S.vrow[q >> 6] << 6) | (q & 63u);
+  cap = S.scr_cap;
+  return group_base((s >> 6) * (int64_t)(S.scr_cap >> 4), s);
 }
 
 // Where particle s's symmetric neighbour list lives: the gather part

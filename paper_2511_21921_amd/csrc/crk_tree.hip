@@ -230,11 +230,11 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
   const bool work = s < S.n && S.todo[s] && S.ccnt[s] >= 0;
   unsigned long long iters = 0, unconv = 0, capped = 0, hbits = 0;
   if (__ballot(work) != 0ull) {
-    int scap = 0, cnt = 0;
+    int cnt = 0;
     int64_t base = 0;
     if (work) {
-      base = scratch_base(S, s, scap);
-      cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
+      base = 4 * (int64_t)S.cpos[s];
+      cnt = S.ccnt[s];
     }
     const int ngroups = (cnt + 15) >> 4;
     // the distance and mass ratio of kept entry e, as the candidate pass
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
     const uint32_t ci = S.cell3[sc];
     const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
     auto entry = [&](int e, R& r, R& mr) {
-      const uint32_t j = S.cand[group_at(base, e < cnt ? e : 0)] >> kCodeBits;
+      const uint32_t j = S.cand[base + (e < cnt ? e : 0)] >> kCodeBits;
       R x[3];
       lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
       r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -292,7 +292,6 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
       const R sum = sums(h, dsum);
       if (sub == 0) {
         S.todo[s] = 0;
-        S.cpos[s] = scratch_pos(S, s);
         if (!is_passive(S, s)) S.Vbuf[s] = h * h * h / (C * sum);
       }
     } else if (work) {
@@ -358,7 +357,6 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
           S.Vbuf[s] = hn * hn * hn / (C * sum_f);
           hbits = dbits((double)hn);
           S.todo[s] = 0;
-          S.cpos[s] = scratch_pos(S, s);
         }
       }
     }
@@ -369,11 +367,18 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
   wave_max_u64(cnt_at(S.cnt, CNT_HMAX_OUT_BITS), hbits);
 }
 
-// Candidates of every unsolved particle within its own radius ri, written to
-// its scratch slot (list entry and distance; the mass ratio when masses
-// differ), in ascending j. A 16-lane row takes one particle (order null: row
-// t takes particle t; else order[t], the unsolved particles of a retry round
-// in rank order). Two phases:
+constexpr int kStage = 320;  // LDS staging capacity of a row, in entries
+
+// Candidates of every unsolved particle within its own radius ri (their
+// indices, in ascending j), kept contiguous in the candidate pool from entry
+// 4 cpos[s]. A 16-lane row takes one particle (order null: row t takes
+// particle t; else order[t], the unsolved particles of a retry round in rank
+// order). Two phases, which work in the row's room of need[s] entries at
+// pool_base4 + coff4[s], or (STAGE) in the row's LDS stage of scr_cap
+// entries, after which every block takes the room its rows' kept candidates
+// need from the pool's bump counter and copies them there (a block that
+// finds the pool full leaves its particles to the next round, with room of
+// their own):
 //  1. The row walks the tree for the particle's sphere: a step tests the
 //     kFan children of the current node one per lane (a child is entered
 //     when the sphere, padded beyond the FP32 rounding, reaches its box),
@@ -384,11 +389,11 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
 //     tests take as many steps as its longest queue rather than, step by
 //     step of the walk, the most leaves any row reached. A leaf's 16
 //     particles are tested one per lane against the padded sphere as
-//     absolute FP32 positions; the passed indices are appended to the slot
-//     in order (prefix counts over the row's ballot).
+//     absolute FP32 positions; the passed indices are appended in order
+//     (prefix counts over the row's ballot).
 //  2. The row takes 16 passed indices at a time, one per lane, computes the
 //     separation exactly (lattice offsets, as every later pass does) and
-//     compacts those within ri in place with their distance.
+//     compacts those within ri in place.
 // A particle whose passed indices overflow its capacity is counted: the next
 // round takes the radius that would hold 1.3 (4 pi / 3) n_h^3 of them at the
 // density seen (at least half of ri), with capacity for 1.3 times what that
@@ -401,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
 // (about eight times the particles of one sphere, most of them rejected),
 // and the retry rounds' rows of scattered particles the union of 16
 // disjoint neighbourhoods.
-template <class R, int K, bool EM>
+template <class R, int K, bool EM, bool STAGE>
 __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
                                                             const float4* __restrict__ absp,
                                                             const uint32_t* __restrict__ order,
@@ -414,25 +419,53 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   __syncthreads();
   constexpr int kRowBuf = 32;  // leaves a row queues between drains
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
+  // STAGE: every row's passed indices, then its kept candidates, in LDS
+  __shared__ uint4 stage4[STAGE ? kBlock / 16 : 1][STAGE ? kStage / 4 : 1];
+  __shared__ uint32_t rcnt[kBlock / 16];
+  __shared__ unsigned long long rbase[kBlock / 16];
   const int64_t tid = particle_id();
-  if (((tid & ~(int64_t)63) >> 4) >= nt) return;  // the wave's four rows past the end
+  // a wave whose four rows are past the end leaves at once, unless the
+  // block's barriers below still need it
+  if (!STAGE && ((tid & ~(int64_t)63) >> 4) >= nt) return;
   const int64_t t = tid >> 4;                      // this row's rank in the round
   const int lane = threadIdx.x & 63, sub = lane & 15, rowid = lane >> 4;
   const uint64_t rowbits = 0xFFFFull << (16 * rowid);
   const uint64_t below = rowbits & ((1ull << lane) - 1ull);  // row lanes before this one
   uint32_t* rbuf = lbuf[threadIdx.x >> 4];
+  uint32_t* srow = reinterpret_cast<uint32_t*>(stage4[STAGE ? threadIdx.x >> 4 : 0]);
   const bool active = t < nt;
   const int64_t s = active ? (order ? (int64_t)order[t] : t) : S.n;
   const int64_t sc = active ? s : 0;
   const bool mine = active && S.todo[sc];  // uniform over the row
   unsigned long long retry = 0, kept = 0;
+  bool fits = false;  // uniform over the row: the passed indices fitted
+  int np = 0, cnt = 0;  // uniform over the row
   if (__ballot(mine) != 0ull) {
     const R ri = mine ? S.rad[sc] : R(0);
     const R4<R> pi = S.pos4[sc];
     const uint32_t ci = S.cell3[sc];
     int cap = 0;
     int64_t base = 0;
-    if (mine) base = scratch_base(S, sc, cap);
+    if (mine) {
+      if constexpr (STAGE) {
+        cap = S.scr_cap;  // at most kStage
+      } else {
+        cap = (S.need[sc] + 3) & ~3;
+        base = 4 * (S.pool_base4 + (int64_t)S.coff4[sc]);
+      }
+    }
+    auto put = [&](int at, uint32_t v) {
+      if constexpr (STAGE)
+        srow[at] = v;
+      else
+        S.cand[base + at] = v;
+    };
+    auto get = [&](int at) -> uint32_t {
+      if constexpr (STAGE)
+        return srow[at];
+      else
+        return S.cand[base + at];
+    };
     float P[3];
     abs_pos(S, ci, pi, P);
     const float L = (float)S.box;
@@ -440,7 +473,6 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     const float rp = mine ? pad_radius((float)ri, L) : -1.f;
     const float rp2 = mine ? rp * rp : -1.f;
     // ---- phase 1: walk, padded tests, passed indices in order ----
-    int np = 0;  // uniform over the row
     // A sphere that stays a padded radius away from every face of the box
     // reaches no periodic image (box centres and positions lie in the box),
     // so its tests need no nearest-image shift; rows whose sphere crosses a
@@ -481,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         const bool pass = valid && point2(absp[j]) < rp2;
         const uint64_t b = __ballot(pass) & rowbits;
         const int at = np + __popcll(b & below);
-        if (pass && at < cap) S.cand[group_at(base, at)] = (uint32_t)j;
+        if (pass && at < cap) put(at, (uint32_t)j);
         np += __popcll(b);
       };
       // Reached leaves are queued per row in LDS and tested by all rows in
@@ -542,13 +574,18 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     else
       phase1(std::true_type());
     // ---- phase 2: exact separations, 16 passed indices at a time ----
-    int cnt = 0;  // uniform over the row
-    if (mine && np <= cap) {
+    fits = mine && np <= cap;
+    if constexpr (STAGE) {  // the row's entries, written by its lanes, read by the row
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (fits) {
       const R r2cap = ri * ri;
       for (int k = 0; k < np; k += 16) {
         const int e = k + sub;
         const bool in = e < np;
-        const uint32_t j = in ? S.cand[group_at(base, e)] : (uint32_t)sc;
+        const uint32_t j = in ? get(e) : (uint32_t)sc;
         R x[3];
         lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
         const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
@@ -556,7 +593,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         // every lane of the row has read its entry (the ballot waits on
         // it); a kept entry moves to a position at or before its own
         const uint64_t b = __ballot(keep) & rowbits;
-        if (keep) S.cand[group_at(base, cnt + __popcll(b & below))] = j << kCodeBits;
+        if (keep) put(cnt + __popcll(b & below), j << kCodeBits);
         cnt += __popcll(b);
       }
     }
@@ -573,9 +610,45 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         S.need[s] = (np + 3) & ~3;
         S.ccnt[s] = -1;
         retry = 1;
-      } else {
+      } else if (!STAGE) {
         S.ccnt[s] = cnt;
+        S.cpos[s] = (uint32_t)(base >> 2);
         kept = (unsigned long long)cnt;
+      }
+    }
+  }
+  if constexpr (STAGE) {
+    // the block's kept candidates go to the pool in one piece: each row's
+    // count rounded up to 4 entries, their sum taken from the bump counter
+    const int row = threadIdx.x >> 4;
+    const int c4 = fits ? (cnt + 3) & ~3 : 0;
+    if (sub == 0) rcnt[row] = (uint32_t)c4;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (int q = 0; q < kBlock / 16; ++q) tot += rcnt[q];
+      unsigned long long b = tot ? atomicAdd(S.cnt + CNT_POOL * kCntSpread, tot) : 0ull;
+      for (int q = 0; q < kBlock / 16; ++q) {
+        rbase[q] = b;
+        b += rcnt[q];
+      }
+    }
+    __syncthreads();
+    if (fits) {
+      const unsigned long long b = rbase[row];
+      if (b + (unsigned long long)c4 <= (unsigned long long)S.pool_cap) {
+        for (int k = 4 * sub; k < c4; k += 64)
+          *reinterpret_cast<uint4*>(S.cand + b + k) = *reinterpret_cast<const uint4*>(srow + k);
+        if (sub == 0) {
+          S.ccnt[s] = cnt;
+          S.cpos[s] = (uint32_t)(b >> 2);
+          kept = (unsigned long long)cnt;
+        }
+      } else if (sub == 0) {
+        // the pool is full: the next round gives the particle room of its own
+        S.need[s] = (np + 3) & ~3;
+        S.ccnt[s] = -1;
+        retry = 1;
       }
     }
   }
@@ -588,31 +661,13 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   if (lane == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
 }
 
-// Capacity of every group of 64 scratch slots, in rows of 16-entry groups:
-// the largest request of the unsolved particles ranked into it (rows zeroed
-// beforehand).
+// The room every unsolved particle asks for, in 4-entry units (zero for the
+// solved ones; need4[n] = 0 closes the exclusive sums).
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_slot_rows(State<R> S, uint32_t* __restrict__ rows) {
+__global__ void __launch_bounds__(kBlock) k_need4(State<R> S, uint32_t* __restrict__ need4) {
   const int64_t s = particle_id();
-  if ((s & ~(int64_t)63) >= S.n) return;
-  const bool t = s < S.n && S.todo[s];
-  const uint64_t any = __ballot(t);
-  if (any == 0ull) return;
-  // the unsolved particles of a wave hold consecutive ranks, so they fall in
-  // at most two consecutive groups of 64: one max and one atomic per group
-  const uint32_t key = t ? (S.cslot[s] >> 6) : 0u;
-  const uint32_t val = t ? (uint32_t)((S.need[s] + 15) >> 4) : 0u;
-  const uint32_t g0 = (uint32_t)__shfl((int)key, __ffsll((unsigned long long)any) - 1, 64);
-  uint32_t v0 = (t && key == g0) ? val : 0u, v1 = (t && key != g0) ? val : 0u;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v0 = max(v0, (uint32_t)__shfl_xor((int)v0, o, 64));
-    v1 = max(v1, (uint32_t)__shfl_xor((int)v1, o, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&rows[g0], v0);
-    if (v1) atomicMax(&rows[g0 + 1], v1);
-  }
+  if (s < S.n) need4[s] = S.todo[s] ? (uint32_t)((S.need[s] + 3) >> 2) : 0u;
+  if (s == 0) need4[S.n] = 0u;
 }
 
 // The unsolved particles in rank order.
@@ -620,13 +675,6 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_rank_order(State<R> S, uint32_t* __restrict__ order) {
   const int64_t s = particle_id();
   if (s < S.n && S.todo[s]) order[S.cslot[s]] = (uint32_t)s;
-}
-
-// a[0 .. na) += v (the row offsets of a round, moved past the earlier rounds)
-__global__ void __launch_bounds__(kBlock) k_add_u32(uint32_t* __restrict__ a, int64_t na,
-                                                    uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < na) a[i] += v;
 }
 
 // Neighbour lists from the stored candidates of every particle (the
@@ -655,8 +703,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
   const bool active = s < S.n;
   const int64_t sc = active ? s : 0;
   const int cnt = active ? S.ccnt[sc] : 0;  // uniform over the row
-  const uint32_t cp = S.cpos[sc];
-  const int64_t base = group_base((int64_t)(cp >> 6), (int64_t)(cp & 63u));
+  const int64_t base = 4 * (int64_t)S.cpos[sc];
   const R h = S.hbuf[sc];
   const R4<R> pi = S.pos4[sc];
   const uint32_t ci = S.cell3[sc];
@@ -666,7 +713,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
   for (int k = 0; k < cnt; k += 16) {
     const int e = k + sub;
     const bool in = e < cnt;
-    const uint32_t ent = S.cand[group_at(base, in ? e : 0)];
+    const uint32_t ent = S.cand[base + (in ? e : 0)];
     const uint32_t j = in ? ent >> kCodeBits : (uint32_t)sc;
     R x[3];
     lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
@@ -753,11 +800,11 @@ __device__ inline void sort_list_regs(uint32_t* __restrict__ list, int64_t sb, i
 }
 
 // Sorts every scatter-only list by j, giving the order a walk would produce
-// and making runs reproducible; counts the force pairs. Lists of at most 64
+// and making runs reproducible; counts the force pairs. Lists of at most 32
 // entries are sorted in their lane's registers (a network of the wave's size
 // class); longer ones are queued (queue[], their number in the slot 0 of
 // CNT_LONG_LISTS) for k_sort_long.
-constexpr int kShortList = 64;
+constexpr int kShortList = 32;
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S, uint32_t* __restrict__ queue) {
   const int64_t s = particle_id();
@@ -779,9 +826,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter_sort(State<R> S, uint32_t* _
   int big = ns;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) big = max(big, __shfl_xor(big, o, 64));
-  if (big > 32) {
-    sort_list_regs<64>(S.slist, sb, ns);
-  } else if (big > 16) {
+  if (big > 16) {
     sort_list_regs<32>(S.slist, sb, ns);
   } else if (big > 8) {
     sort_list_regs<16>(S.slist, sb, ns);
@@ -879,22 +924,31 @@ void launch_rank_order(const State<R>& S, uint32_t* order, hipStream_t s) {
 }
 
 template <class R>
-void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel,
+void launch_candidates_tree(const State<R>& S, const float4* absp, int kernel, bool stage,
                             const uint32_t* order, int64_t nt, hipStream_t s) {
   if (nt <= 0) return;
   const dim3 g(grid_for(16 * nt)), b(kBlock);  // a 16-lane row per particle
+  auto go = [&](auto em, auto st) {
+    constexpr bool EM = decltype(em)::value, ST = decltype(st)::value;
+    if (kernel == 0)
+      hipLaunchKernelGGL((k_candidates_tree<R, 0, EM, ST>), g, b, 0, s, S, absp, order, nt);
+    else
+      hipLaunchKernelGGL((k_candidates_tree<R, 1, EM, ST>), g, b, 0, s, S, absp, order, nt);
+  };
   if (S.equal_mass) {
-    if (kernel == 0)
-      hipLaunchKernelGGL((k_candidates_tree<R, 0, true>), g, b, 0, s, S, absp, order, nt);
+    if (stage)
+      go(std::true_type(), std::true_type());
     else
-      hipLaunchKernelGGL((k_candidates_tree<R, 1, true>), g, b, 0, s, S, absp, order, nt);
+      go(std::true_type(), std::false_type());
   } else {
-    if (kernel == 0)
-      hipLaunchKernelGGL((k_candidates_tree<R, 0, false>), g, b, 0, s, S, absp, order, nt);
+    if (stage)
+      go(std::false_type(), std::true_type());
     else
-      hipLaunchKernelGGL((k_candidates_tree<R, 1, false>), g, b, 0, s, S, absp, order, nt);
+      go(std::false_type(), std::false_type());
   }
 }
+
+bool stage_fits(int scr_cap) { return scr_cap <= kStage; }
 
 template <class R>
 void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
@@ -915,13 +969,8 @@ void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, in
 }
 
 template <class R>
-void launch_slot_rows(const State<R>& S, uint32_t* rows, hipStream_t s) {
-  hipLaunchKernelGGL(k_slot_rows<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, rows);
-}
-
-void launch_add_u32(uint32_t* a, int64_t na, uint32_t v, hipStream_t s) {
-  if (na > 0 && v)
-    hipLaunchKernelGGL(k_add_u32, dim3(grid_for(na)), dim3(kBlock), 0, s, a, na, v);
+void launch_need4(const State<R>& S, uint32_t* need4, hipStream_t s) {
+  hipLaunchKernelGGL(k_need4<R>, dim3(grid_for(S.n + 1)), dim3(kBlock), 0, s, S, need4);
 }
 
 template <class R>
@@ -947,11 +996,11 @@ void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipS
                                      hipStream_t);                                           \
   template void launch_init_radius<R>(const State<R>&, int, hipStream_t);                    \
   template void launch_rank_order<R>(const State<R>&, uint32_t*, hipStream_t);              \
-  template void launch_candidates_tree<R>(const State<R>&, const float4*, int,               \
+  template void launch_candidates_tree<R>(const State<R>&, const float4*, int, bool,         \
                                           const uint32_t*, int64_t, hipStream_t);            \
   template void launch_hsolve_tree<R>(const State<R>&, int, const uint32_t*, int64_t,       \
                                       hipStream_t);                                          \
-  template void launch_slot_rows<R>(const State<R>&, uint32_t*, hipStream_t);               \
+  template void launch_need4<R>(const State<R>&, uint32_t*, hipStream_t);               \
   template void launch_filter_tree<R>(const State<R>&, bool, int*, uint32_t*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
