@@ -104,6 +104,10 @@ struct crk_ctx {
   // Cell-list geometry of the last forward that settled on its first
   // attempt; the next forward with the same n and precision launches every
   // pass with it and checks once at the end that it still holds.
+  // the sorted cell keys and permutation of the last cell-list build (grid
+  // cells_G, cells_n particles; cells_G = 0 once they are overwritten)
+  int cells_G = 0;
+  long long cells_n = -1;
   bool spec_ok = false;
   long long spec_n = -1;
   int spec_prec = -1;
@@ -206,6 +210,8 @@ hipError_t ensure_particles(crk_ctx* c, int64_t n) {
   const size_t R = real_size(c->p.precision);
   const int64_t npad = ((n + 63) / 64) * 64;
   hipError_t e;
+  // grown key or permutation buffers lose the kept cell list
+  if (c->keys_a.bytes < 4 * (size_t)npad || c->vals_a.bytes < 4 * (size_t)npad) c->cells_G = 0;
 #define ENS(b, bytes) \
   if ((e = ensure(c->b, (size_t)(bytes))) != hipSuccess) return e
   ENS(keys_a, 4 * npad);
@@ -393,6 +399,8 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   launch_cell_bounds((const uint32_t*)ctx->keys_a.p, n, ncell, (uint32_t*)ctx->cell_start.p,
                      occ_limit, (unsigned long long*)ctx->cnt.p, s);
   CRK_HIP(hipGetLastError(), "cell bounds launch");
+  ctx->cells_G = ctx->G;
+  ctx->cells_n = n;
   return CRK_OK;
 }
 
@@ -409,6 +417,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   ctx->lattice = 1;
   ctx->G = 1024;
   ctx->ell = P.box / 1024.0;
+  ctx->cells_G = 0;  // the Morton sort below takes the key buffers
   {
     // room for ~5x the expected neighbour count (4 pi / 3) n_h^3 before a
     // radius shrinks (the cell path's capacity is its own: it is set again
@@ -487,7 +496,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(hipMemcpyAsync(&ctx->host_rows[0], slot + n, 4, hipMemcpyDeviceToHost, s), "rows");
     if (!stage) {
       State<R> S = make_state<R>(ctx, n);
-      launch_need4<R>(S, need4, s);
+      launch_need4<R>(S, need4, round > 0, s);
       CRK_HIP(exclusive_scan_u32(need4, coff, n + 1, (uint32_t*)ctx->scan_tmp.p, s), "scan");
       CRK_HIP(hipMemcpyAsync(&ctx->host_rows[1], coff + n, 4, hipMemcpyDeviceToHost, s), "rows");
     }
@@ -527,10 +536,10 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     CRK_HIP(hipMemsetAsync(dcnt + CNT_RETRY * kCntSpread, 0, 8 * kCntSpread, s), "memset");
     State<R> S = make_state<R>(ctx, n);
     // the first round takes every particle in place; later ones only the
-    // unsolved, packed in rank order
+    // unsolved, packed in rank order (the walk knows a retry round by order)
     const int64_t nt = ctx->host_rows[0];
     const uint32_t* order = nullptr;
-    if (nt < n) {
+    if (round > 0) {
       launch_rank_order<R>(S, (uint32_t*)ctx->torder.p, s);
       order = (const uint32_t*)ctx->torder.p;
     }
@@ -609,7 +618,11 @@ crk_status tree_lists(crk_ctx* ctx, hipStream_t s, int64_t n) {
 // (same grid from this input's largest h, same mass form, no cell beyond
 // the clustering limit, no candidate or list overflow, no capped h root).
 // Then the results are the careful path's, bit for bit; otherwise
-// *accepted stays false and the caller runs the careful path.
+// *accepted stays false and the caller runs the careful path. When the last
+// cell-list build is still at hand (same grid and count), one read first
+// tells whether any particle has changed cell: if none has, the list is kept
+// (its sorted order and cell starts are those a new sort of these positions
+// gives), else it is built again.
 template <class R>
 crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
                         const R* m, const R* u, R* h, R* V, R* rho, void* A, void* B,
@@ -629,9 +642,19 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   const double ncell = (double)ctx->G * ctx->G * ctx->G;
   const double occ_rule = std::max(1024.0, 16.0 * (double)n / ncell);
   CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
-  crk_status st = build_cells<R>(ctx, s, n, x,
-                                 P.search == 0 ? (unsigned long long)occ_rule : ~0ull);
-  if (st != CRK_OK) return st;
+  bool keep_cells = ctx->cells_G == ctx->G && ctx->cells_n == n;
+  if (keep_cells) {
+    launch_keys_check(x, n, P.box, ctx->G, (const uint32_t*)ctx->keys_a.p,
+                      (const uint32_t*)ctx->vals_a.p, dcnt, s);
+    CRK_HIP(hipGetLastError(), "cell check launch");
+    CRK_HIP(read_counters(ctx, s), "cell check");
+    keep_cells = ctx->host_cnt[CNT_MOVED] == 0;
+  }
+  if (!keep_cells) {
+    crk_status st = build_cells<R>(ctx, s, n, x,
+                                   P.search == 0 ? (unsigned long long)occ_rule : ~0ull);
+    if (st != CRK_OK) return st;
+  }
   {
     State<R> S = make_state<R>(ctx, n);
     launch_gather<R>(S, x, v, m, u, h, s);

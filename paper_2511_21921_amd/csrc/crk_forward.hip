@@ -101,6 +101,32 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ x, i
   vals[i] = (uint32_t)i;
 }
 
+// The kept cell list against new positions: every sorted slot s recomputes
+// the cell of its particle perm[s] and counts it in CNT_MOVED when that
+// differs from keys[s] (the list then no longer sorts these positions).
+__global__ void __launch_bounds__(kBlock) k_keys_check(const double* __restrict__ x, int64_t n,
+                                                       double L, int G,
+                                                       const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ perm,
+                                                       unsigned long long* __restrict__ cnt) {
+  const int64_t s = particle_id();
+  if ((s & ~(int64_t)63) >= n) return;
+  unsigned long long moved = 0;
+  if (s < n) {
+    const double inv = (double)G / L;
+    const uint32_t p = perm[s];
+    if (p < (uint32_t)n) {
+      int c[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c[a] = cell_coord(wrap_pos(x[a * n + p], L), inv, G);
+      moved = ((uint32_t)c[2] * G + (uint32_t)c[1]) * G + (uint32_t)c[0] != keys[s] ? 1ull : 0ull;
+    } else {
+      moved = 1;  // not a permutation of these particles
+    }
+  }
+  wave_add_u64(cnt_at(cnt, CNT_MOVED), moved);
+}
+
 // cell_start[c] = first sorted position whose key is >= c, for c = 0..ncell
 // (a binary search of the sorted keys per cell; no atomics). The largest
 // occupancy start[c + 1] - start[c] is reduced per block into one atomic;
@@ -155,10 +181,17 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   int c[3];
   R xi[3];
   const double inv = (double)S.G / S.box;
+  // the cell list's own cell of the slot (on a kept list the particle may
+  // have left it: its offset from that cell's centre is then beyond half a
+  // side, but the walk stays consistent with the list)
+  const uint32_t key = S.lattice ? 0u : S.keys[s];
+  const uint32_t G = (uint32_t)S.G;
+  const uint32_t kz = key / (G * G);
+  const int kc[3] = {(int)(key % G), (int)((key / G) % G), (int)(kz < G ? kz : G - 1)};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double t = wrap_pos(x[a * n + p], S.box);
-    c[a] = cell_coord(t, inv, S.G);
+    c[a] = S.lattice ? cell_coord(t, inv, S.G) : kc[a];
     xi[a] = (R)(t - ((double)c[a] + 0.5) * S.ell_d);
   }
   R4<R> q;
@@ -1102,6 +1135,12 @@ void launch_check_inputs(const double* x, const R* h, const R* m, const R* u, in
 void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, uint32_t* vals,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys, vals);
+}
+
+void launch_keys_check(const double* x, int64_t n, double box, int G, const uint32_t* keys,
+                       const uint32_t* perm, unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys_check, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys,
+                     perm, cnt);
 }
 
 void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,

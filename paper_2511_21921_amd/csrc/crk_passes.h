@@ -16,6 +16,10 @@ void launch_keys(const double* x, int64_t n, double box, int G, uint32_t* keys, 
                  hipStream_t s);
 void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,
                         unsigned long long occ_limit, unsigned long long* cnt, hipStream_t s);
+// Counts in CNT_MOVED the sorted slots whose particle's cell (from x) is no
+// longer keys[s]: zero means the kept cell list still sorts x.
+void launch_keys_check(const double* x, int64_t n, double box, int G, const uint32_t* keys,
+                       const uint32_t* perm, unsigned long long* cnt, hipStream_t s);
 
 // Morton keys over the 1024^3 lattice (tree path) and identity values.
 void launch_morton(const double* x, int64_t n, double box, uint32_t* keys, uint32_t* vals,
@@ -43,10 +47,10 @@ bool stage_fits(int scr_cap);
 template <class R>
 void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, int64_t nt,
                         hipStream_t s);
-// need4[s]: the room unsolved particle s asks for, in 4-entry units (0 when
-// solved), and need4[n] = 0
+// need4[s]: the room unsolved particle s gets (room_for), in 4-entry units (0
+// when solved), and need4[n] = 0; retry: a round after the first
 template <class R>
-void launch_need4(const State<R>& S, uint32_t* need4, hipStream_t s);
+void launch_need4(const State<R>& S, uint32_t* need4, bool retry, hipStream_t s);
 // Gather lists and the scatter-only lists (their transpose) from the kept
 // candidates: lengths and scatter-only counts (write = false), then entries,
 // the scatter-only ones appended at fillc and then sorted (queue: room for n

@@ -34,6 +34,7 @@ enum Counter {
   CNT_CANDIDATES,      // candidates kept by the neighbour search (all its passes)
   CNT_LONG_LISTS,      // tree path: scatter-only lists queued for the wave sort (slot 0 only)
   CNT_POOL,            // tree path: candidate pool entries taken by staged blocks (slot 0 only)
+  CNT_MOVED,           // particles whose cell differs from the kept cell list's
   CNT_COUNT
 };
 
@@ -249,6 +250,14 @@ __device__ inline int need_after_growth(int cnt, double g) {
   const double v = 1.3 * (double)(cnt > 1 ? cnt : 1) * g * g * g;
   const int c = v < 1e8 ? (int)v : 100000000;
   return (c + 3) & ~3;
+}
+
+// Tree path: the room a round gives a particle that asks for need entries,
+// in whole 4-entry chunks: in a retry round half as much again (an overflow
+// of the estimate costs another round); in the first, where every particle
+// asks for the uniform capacity, just that.
+__device__ inline int room_for(int need, bool retry) {
+  return (need + (retry ? need >> 1 : 0) + 3) & ~3;
 }
 
 // First word and capacity of particle s's candidate scratch on the cell

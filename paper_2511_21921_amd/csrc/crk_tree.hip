@@ -373,8 +373,8 @@ constexpr int kStage = 320;  // LDS staging capacity of a row, in entries
 // indices, in ascending j), kept contiguous in the candidate pool from entry
 // 4 cpos[s]. A 16-lane row takes one particle (order null: row t takes
 // particle t; else order[t], the unsolved particles of a retry round in rank
-// order). Two phases, which work in the row's room of need[s] entries at
-// pool_base4 + coff4[s], or (STAGE) in the row's LDS stage of scr_cap
+// order). Two phases, which work in the row's room (room_for(need[s])
+// entries at pool_base4 + coff4[s]), or (STAGE) in the row's LDS stage of scr_cap
 // entries, after which every block takes the room its rows' kept candidates
 // need from the pool's bump counter and copies them there (a block that
 // finds the pool full leaves its particles to the next round, with room of
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
       if constexpr (STAGE) {
         cap = S.scr_cap;  // at most kStage
       } else {
-        cap = (S.need[sc] + 3) & ~3;
+        cap = room_for(S.need[sc], order != nullptr);  // order: a retry round
         base = 4 * (S.pool_base4 + (int64_t)S.coff4[sc]);
       }
     }
@@ -661,12 +661,13 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   if (lane == 0 && kept) atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), kept);
 }
 
-// The room every unsolved particle asks for, in 4-entry units (zero for the
-// solved ones; need4[n] = 0 closes the exclusive sums).
+// The room every unsolved particle gets in a retry round, in 4-entry units
+// (zero for the solved ones; need4[n] = 0 closes the exclusive sums).
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_need4(State<R> S, uint32_t* __restrict__ need4) {
+__global__ void __launch_bounds__(kBlock) k_need4(State<R> S, uint32_t* __restrict__ need4,
+                                                  bool retry) {
   const int64_t s = particle_id();
-  if (s < S.n) need4[s] = S.todo[s] ? (uint32_t)((S.need[s] + 3) >> 2) : 0u;
+  if (s < S.n) need4[s] = S.todo[s] ? (uint32_t)(room_for(S.need[s], retry) >> 2) : 0u;
   if (s == 0) need4[S.n] = 0u;
 }
 
@@ -969,8 +970,8 @@ void launch_hsolve_tree(const State<R>& S, int kernel, const uint32_t* order, in
 }
 
 template <class R>
-void launch_need4(const State<R>& S, uint32_t* need4, hipStream_t s) {
-  hipLaunchKernelGGL(k_need4<R>, dim3(grid_for(S.n + 1)), dim3(kBlock), 0, s, S, need4);
+void launch_need4(const State<R>& S, uint32_t* need4, bool retry, hipStream_t s) {
+  hipLaunchKernelGGL(k_need4<R>, dim3(grid_for(S.n + 1)), dim3(kBlock), 0, s, S, need4, retry);
 }
 
 template <class R>
@@ -1000,7 +1001,7 @@ void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipS
                                           const uint32_t*, int64_t, hipStream_t);            \
   template void launch_hsolve_tree<R>(const State<R>&, int, const uint32_t*, int64_t,       \
                                       hipStream_t);                                          \
-  template void launch_need4<R>(const State<R>&, uint32_t*, hipStream_t);               \
+  template void launch_need4<R>(const State<R>&, uint32_t*, bool, hipStream_t);               \
   template void launch_filter_tree<R>(const State<R>&, bool, int*, uint32_t*, hipStream_t);
 
 CRK_INSTANTIATE_TREE(float)
