@@ -70,7 +70,11 @@ struct crk_ctx {
   Buf vpred, upred;
   // timestep hierarchy: half-kicked velocity and energy, hdot, and the
   // evaluation of the substep (its accel and du/dt before the close)
-  Buf hl_vh, hl_uh, hl_hdot, hl_acc, hl_du, hl_need;
+  Buf hl_vh, hl_uh, hl_hdot, hl_acc, hl_du, hl_need, hl_act;
+  // a substep with few active particles lists them (hl_act) for the row
+  // passes: hl_rows, and their number
+  bool hl_rows = false;
+  long long hl_nact = 0;
   // levels and stored state seen by the passes during a hierarchical
   // substep (null levels: every particle active)
   const int* hl_levels = nullptr;
@@ -309,6 +313,9 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.pgA = (const R*)c->hl_gA;
   S.pgB = (const R*)c->hl_gB;
   S.needed = c->hl_levels && !c->lattice ? (uint8_t*)c->hl_need.p : nullptr;
+  const bool rows = c->hl_levels && c->hl_rows && !c->lattice;
+  S.act = rows ? (const uint32_t*)c->hl_act.p : nullptr;
+  S.nact = rows ? c->hl_nact : 0;
   return S;
 }
 
@@ -366,6 +373,18 @@ hipError_t read_counters(crk_ctx* c, hipStream_t s) {
     c->host_cnt[k] = v;
   }
   return hipSuccess;
+}
+
+// Hierarchy substeps with at most this many active particles (and not all)
+// give each a 16-lane row in the pair passes.
+constexpr long long kRowsMax = 32768;
+
+// From the counters just read: whether this substep lists its active
+// particles for the row passes.
+void set_rows(crk_ctx* ctx, int64_t n) {
+  const long long na = (long long)ctx->host_cnt[CNT_ACTIVE];
+  ctx->hl_nact = na;
+  ctx->hl_rows = ctx->hl_levels && na <= kRowsMax && na < n;
 }
 
 double bits_to_double(unsigned long long b) {
@@ -633,6 +652,8 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
   launch_check_inputs<R>(x, h, m, u, n, dcnt, s);
+  if (ctx->hl_levels)
+    launch_count_active(ctx->hl_levels, n, ctx->hl_lmax, ctx->hl_jend, dcnt, s);
   ctx->G = ctx->spec_G;
   ctx->ell = P.box / ctx->G;
   ctx->lattice = 0;
@@ -643,11 +664,13 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   const double occ_rule = std::max(1024.0, 16.0 * (double)n / ncell);
   CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
   bool keep_cells = ctx->cells_G == ctx->G && ctx->cells_n == n;
+  bool read = false;
   if (keep_cells) {
     launch_keys_check(x, n, P.box, ctx->G, (const uint32_t*)ctx->keys_a.p,
                       (const uint32_t*)ctx->vals_a.p, dcnt, s);
     CRK_HIP(hipGetLastError(), "cell check launch");
     CRK_HIP(read_counters(ctx, s), "cell check");
+    read = true;
     keep_cells = ctx->host_cnt[CNT_MOVED] == 0;
   }
   if (!keep_cells) {
@@ -655,9 +678,12 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
                                    P.search == 0 ? (unsigned long long)occ_rule : ~0ull);
     if (st != CRK_OK) return st;
   }
+  if (ctx->hl_levels && !read) CRK_HIP(read_counters(ctx, s), "active count");
+  set_rows(ctx, n);
   {
     State<R> S = make_state<R>(ctx, n);
     launch_gather<R>(S, x, v, m, u, h, s);
+    if (ctx->hl_rows) launch_active_list<R>(S, (uint32_t*)ctx->hl_act.p, s);
   }
   CRK_HIP(tend(ctx, P_CELLS, s), "event");
   CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
@@ -748,8 +774,11 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   if (!accepted) {
     CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
     launch_check_inputs<R>(x, h, m, u, n, dcnt, s);
+    if (ctx->hl_levels)
+      launch_count_active(ctx->hl_levels, n, ctx->hl_lmax, ctx->hl_jend, dcnt, s);
     CRK_HIP(hipGetLastError(), "input check launch");
     CRK_HIP(read_counters(ctx, s), "input check");
+    set_rows(ctx, n);
     if (ctx->host_cnt[CNT_BAD_INPUT])
       return fail(ctx, CRK_EINVAL, "x must be finite; h, m and u finite and > 0");
     const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
@@ -795,6 +824,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       {
         State<R> S = make_state<R>(ctx, n);
         launch_gather<R>(S, x, v, m, u, h, s);
+        if (ctx->hl_rows) launch_active_list<R>(S, (uint32_t*)ctx->hl_act.p, s);
       }
       CRK_HIP(tend(ctx, P_CELLS, s), "event");
       CRK_HIP(ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap), "alloc candidates");
@@ -1104,6 +1134,7 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
   CRK_HIP(ensure(ctx->hl_acc, 8 * 3 * N), "step workspace");
   CRK_HIP(ensure(ctx->hl_du, 8 * N), "step workspace");
   CRK_HIP(ensure(ctx->hl_need, N), "step workspace");
+  CRK_HIP(ensure(ctx->hl_act, 4 * N), "step workspace");
   R* vp = (R*)ctx->vpred.p;
   R* up = (R*)ctx->upred.p;
   R* vh = (R*)ctx->hl_vh.p;
@@ -1414,7 +1445,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->vpred, &c->upred,
-                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need,
+                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need, &c->hl_act,
                 &c->cool_lam, &c->cool_oma, &c->cool_co, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,

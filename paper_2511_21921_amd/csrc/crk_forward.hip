@@ -127,6 +127,35 @@ __global__ void __launch_bounds__(kBlock) k_keys_check(const double* __restrict_
   wave_add_u64(cnt_at(cnt, CNT_MOVED), moved);
 }
 
+// Hierarchy: the particles (caller order) active at the end of substep jend,
+// counted in CNT_ACTIVE.
+__global__ void __launch_bounds__(kBlock) k_count_active(const int* __restrict__ levels,
+                                                         int64_t n, int lmax, int64_t jend,
+                                                         unsigned long long* __restrict__ cnt) {
+  const int64_t p = particle_id();
+  if ((p & ~(int64_t)63) >= n) return;
+  unsigned long long a = 0;
+  if (p < n) a = (jend & ((1ll << (lmax - levels[p])) - 1)) == 0 ? 1ull : 0ull;
+  wave_add_u64(cnt_at(cnt, CNT_ACTIVE), a);
+}
+
+// The sorted slots of the active particles, appended to list (a wave's at
+// once; the order is not kept).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_active_list(State<R> S, uint32_t* __restrict__ list) {
+  const int64_t s = particle_id();
+  if ((s & ~(int64_t)63) >= S.n) return;
+  const bool a = s < S.n && !is_passive(S, s);
+  const uint64_t b = __ballot(a);
+  if (b == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == __ffsll((unsigned long long)b) - 1)
+    base = atomicAdd(S.cnt + CNT_ACTLIST * kCntSpread, (unsigned long long)__popcll(b));
+  base = __shfl(base, __ffsll((unsigned long long)b) - 1, 64);
+  if (a) list[base + __popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)s;
+}
+
 // cell_start[c] = first sorted position whose key is >= c, for c = 0..ncell
 // (a binary search of the sorted keys per cell; no atomics). The largest
 // occupancy start[c + 1] - start[c] is reduced per block into one atomic;
@@ -613,13 +642,13 @@ struct Moments {
   R m0, m1[3], m2[6], dm0[3], X1[9], X2[18];
 };
 
+// The sums start from the self term (m0 = V_i W(0)) or from zero.
 template <class R, int K>
-__device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<R>& M) {
-  const R4<R> pi = S.pos4[s];
-  const R hinv = pi.w;
+__device__ __forceinline__ void moments_start(const State<R>& S, int64_t s, bool self,
+                                              Moments<R>& M) {
+  const R hinv = S.pos4[s].w;
   const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
-  const R C4 = C3 * hinv;
-  M.m0 = S.vel4[s].w * C3 * R(Shape<K>::w0);
+  M.m0 = self ? S.vel4[s].w * C3 * R(Shape<K>::w0) : R(0);
 #pragma unroll
   for (int t = 0; t < 3; ++t) M.m1[t] = M.dm0[t] = R(0);
 #pragma unroll
@@ -628,39 +657,74 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
   for (int t = 0; t < 9; ++t) M.X1[t] = R(0);
 #pragma unroll
   for (int t = 0; t < 18; ++t) M.X2[t] = R(0);
+}
+
+// Adds neighbour entry e of particle s (position pi, 1/h hinv, C h^-3 and
+// C h^-4) to the sums.
+template <class R, int K>
+__device__ __forceinline__ void moment_term(const State<R>& S, int64_t s, const R4<R>& pi,
+                                            R hinv, R C3, R C4, uint32_t e, Moments<R>& M) {
+  const uint32_t j = e >> kCodeBits;
+  const R4<R> pj = S.pos4[j];
+  const R Vj = S.vel4[j].w;
+  R x[3];
+  pair_x(S, s, pi, pj, e, x);
+  const R r2 = dot3(x, x);
+  const R rinv = Sc<R>::rsqrt(r2);
+  const R q = r2 * rinv * hinv;
+  R w, dw;
+  Shape<K>::eval(q, w, dw);
+  const R VW = Vj * C3 * w;
+  const R fg = Vj * C4 * dw * rinv;
+  const R Vg[3] = {fg * x[0], fg * x[1], fg * x[2]};
+  const R p6[6] = {x[0] * x[0], x[0] * x[1], x[0] * x[2], x[1] * x[1], x[1] * x[2], x[2] * x[2]};
+  M.m0 += VW;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) M.m1[a] += x[a] * VW;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) M.m2[t] += p6[t] * VW;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    M.dm0[g] += Vg[g];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) M.X1[g * 3 + a] += x[a] * Vg[g];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) M.X2[g * 6 + t] += p6[t] * Vg[g];
+  }
+}
+
+template <class R, int K>
+__device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<R>& M) {
+  const R4<R> pi = S.pos4[s];
+  const R hinv = pi.w;
+  const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+  const R C4 = C3 * hinv;
+  moments_start<R, K>(S, s, true, M);
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;
   const int ng = nb.ng;
-  for (int k = 0; k < ng; ++k) {
-    const uint32_t e = gather_entry(S, nb, k, ebuf);
-    const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
-    const R Vj = S.vel4[j].w;
-    R x[3];
-    pair_x(S, s, pi, pj, e, x);
-    const R r2 = dot3(x, x);
-    const R rinv = Sc<R>::rsqrt(r2);
-    const R q = r2 * rinv * hinv;
-    R w, dw;
-    Shape<K>::eval(q, w, dw);
-    const R VW = Vj * C3 * w;
-    const R fg = Vj * C4 * dw * rinv;
-    const R Vg[3] = {fg * x[0], fg * x[1], fg * x[2]};
-    const R p6[6] = {x[0] * x[0], x[0] * x[1], x[0] * x[2], x[1] * x[1], x[1] * x[2], x[2] * x[2]};
-    M.m0 += VW;
+  for (int k = 0; k < ng; ++k)
+    moment_term<R, K>(S, s, pi, hinv, C3, C4, gather_entry(S, nb, k, ebuf), M);
+}
+
+// Sums of a 16-lane row, each lane taking the entries k = sub mod 16, then
+// summed over the row (every lane ends with the row's sums).
+template <class R, int K>
+__device__ inline void accumulate_moments_row(const State<R>& S, int64_t s, int sub,
+                                              Moments<R>& M) {
+  const R4<R> pi = S.pos4[s];
+  const R hinv = pi.w;
+  const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+  const R C4 = C3 * hinv;
+  moments_start<R, K>(S, s, sub == 0, M);
+  const NbrRef nb = nbr_ref(S, s);
+  for (int k = sub; k < nb.ng; k += 16)
+    moment_term<R, K>(S, s, pi, hinv, C3, C4, S.nlist[slot_at(nb.gb, k)], M);
+  R* v = reinterpret_cast<R*>(&M);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) M.m1[a] += x[a] * VW;
+  for (int t = 0; t < 40; ++t)
 #pragma unroll
-    for (int t = 0; t < 6; ++t) M.m2[t] += p6[t] * VW;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-      M.dm0[g] += Vg[g];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) M.X1[g * 3 + a] += x[a] * Vg[g];
-#pragma unroll
-      for (int t = 0; t < 6; ++t) M.X2[g * 6 + t] += p6[t] * Vg[g];
-    }
-  }
+    for (int o = 8; o > 0; o >>= 1) v[t] += __shfl_xor(v[t], o, 16);
 }
 
 // Full moment set (40 values, FP64) from the accumulated sums.
@@ -774,6 +838,48 @@ __device__ inline void store_kc(const State<R>& S, int64_t s, const Corr64& c) {
   }
 }
 
+// Corrections from the sums of particle s: stored (moments when kept,
+// packed corrections) and written in caller order; 1 when the second moment
+// was singular.
+template <class R>
+__device__ inline unsigned long long moments_finish(const State<R>& S, int64_t s,
+                                                    const Moments<R>& M, CorrOut o) {
+  Mom64 D;
+  expand_moments(M, D);
+  if (S.mom) {
+    const int64_t n = S.n;
+    S.mom[s] = (R)D.m0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) S.mom[(1 + t) * n + s] = M.m1[t];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) S.mom[(4 + t) * n + s] = M.m2[t];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) S.mom[(10 + t) * n + s] = M.dm0[t];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) S.mom[(13 + t) * n + s] = M.X1[t];
+#pragma unroll
+    for (int t = 0; t < 18; ++t) S.mom[(22 + t) * n + s] = M.X2[t];
+  }
+  Corr64 c;
+  solve_corrections<R>(D, c);
+  store_kc(S, s, c);
+  const int64_t n = S.n;
+  const uint32_t p = S.perm[s];
+  R* A = (R*)o.A;
+  R* B = (R*)o.B;
+  R* gA = (R*)o.gradA;
+  R* gB = (R*)o.gradB;
+  A[p] = (R)c.A;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    B[t * n + p] = (R)c.B[t];
+    gA[t * n + p] = (R)c.dA[t];
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) gB[t * n + p] = (R)c.dB[t];
+  return c.singular ? 1ull : 0ull;
+}
+
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
   const int64_t s = particle_id();
@@ -795,45 +901,28 @@ __global__ void __launch_bounds__(kBlock) k_moments(State<R> S, CorrOut o) {
       for (int t = 0; t < 9; ++t) c.dB[t] = (double)S.pgB[t * n + p];
       store_kc(S, s, c);
     }
-  } else if (s < S.n) {
+  } else if (s < S.n && !S.act) {  // (a list of active particles: k_moments_rows)
     Moments<R> M;
     accumulate_moments<R, K>(S, s, M);
-    Mom64 D;
-    expand_moments(M, D);
-    if (S.mom) {
-      const int64_t n = S.n;
-      S.mom[s] = (R)D.m0;
-#pragma unroll
-      for (int t = 0; t < 3; ++t) S.mom[(1 + t) * n + s] = M.m1[t];
-#pragma unroll
-      for (int t = 0; t < 6; ++t) S.mom[(4 + t) * n + s] = M.m2[t];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) S.mom[(10 + t) * n + s] = M.dm0[t];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) S.mom[(13 + t) * n + s] = M.X1[t];
-#pragma unroll
-      for (int t = 0; t < 18; ++t) S.mom[(22 + t) * n + s] = M.X2[t];
-    }
-    Corr64 c;
-    solve_corrections<R>(D, c);
-    sing = c.singular ? 1 : 0;
-    store_kc(S, s, c);
-    const int64_t n = S.n;
-    const uint32_t p = S.perm[s];
-    R* A = (R*)o.A;
-    R* B = (R*)o.B;
-    R* gA = (R*)o.gradA;
-    R* gB = (R*)o.gradB;
-    A[p] = (R)c.A;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      B[t * n + p] = (R)c.B[t];
-      gA[t * n + p] = (R)c.dA[t];
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) gB[t * n + p] = (R)c.dB[t];
+    sing = moments_finish<R>(S, s, M, o);
   }
   wave_add_u64(cnt_at(S.cnt, CNT_SINGULAR), sing);
+}
+
+// The active particles of a hierarchy substep listed in act (nact of them),
+// a 16-lane row each.
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_moments_rows(State<R> S, CorrOut o) {
+  const int64_t r = particle_id() >> 4;
+  const int sub = threadIdx.x & 15;
+  unsigned long long sing = 0;
+  if (r < S.nact) {
+    const int64_t s = S.act[r];
+    Moments<R> M;
+    accumulate_moments_row<R, K>(S, s, sub, M);
+    if (sub == 0) sing = moments_finish<R>(S, s, M, o);
+  }
+  if (sing) atomicAdd(cnt_at(S.cnt, CNT_SINGULAR), sing);
 }
 
 // ------------------------------------------------ density, grad v, EOS ----
@@ -875,6 +964,106 @@ __device__ inline void load_gv(const State<R>& S, int64_t j, R gv[9], R& relaxed
   relaxed = q2.y;
 }
 
+// The density sums of particle s over its gather entries k = k0, k0 + DK, ...
+// (the self term with k0 = 0): Num, Den and the nine grad v sums.
+template <class R, int K, int DK>
+__device__ inline void density_sums(const State<R>& S, int64_t s, int k0, R sums[11]) {
+  const R4<R> pi = S.pos4[s];
+  const R4<R> vi = S.vel4[s];
+  const R hinv = pi.w;
+  const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
+  const R C4 = C3 * hinv;
+  KC<R> ki;
+  load_kc(S, s, ki);
+  // self term: x = 0, W^R_ii = A_i W(0)
+  const R W0 = C3 * R(Shape<K>::w0);
+  R num = k0 == 0 ? S.mass[s] * vi.w * ki.a * W0 : R(0);
+  R den = k0 == 0 ? vi.w * vi.w * ki.a * W0 : R(0);
+  R gv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) gv[t] = R(0);
+  const NbrRef nb = nbr_ref(S, s);
+  uint4 ebuf;
+  const int ng = nb.ng;
+  for (int k = k0; k < ng; k += DK) {
+    const uint32_t e = DK == 1 ? gather_entry(S, nb, k, ebuf) : S.nlist[slot_at(nb.gb, k)];
+    const uint32_t j = e >> kCodeBits;
+    const R4<R> pj = S.pos4[j];
+    const R4<R> vj = S.vel4[j];
+    const R mj = S.mass[j];
+    R x[3];
+    pair_x(S, s, pi, pj, e, x);
+    const R r2 = dot3(x, x);
+    const R rinv = Sc<R>::rsqrt(r2);
+    R w, dw;
+    Shape<K>::eval(r2 * rinv * hinv, w, dw);
+    const R W = C3 * w;
+    const R fg = C4 * dw * rinv;
+    const R gW[3] = {fg * x[0], fg * x[1], fg * x[2]};
+    R WR, gWR[3];
+    kc_apply(ki, x, W, gW, WR, gWR);
+    num += mj * vj.w * WR;
+    den += vj.w * vj.w * WR;
+    const R dv[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int g = 0; g < 3; ++g) gv[a * 3 + g] -= vj.w * dv[a] * gWR[g];
+  }
+  sums[0] = num;
+  sums[1] = den;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) sums[2 + t] = gv[t];
+}
+
+// rho, P, c and the relaxation flag from the sums of particle s, stored and
+// written in caller order; 1 when relaxed.
+template <class R>
+__device__ inline unsigned long long density_finish(const State<R>& S, int64_t s,
+                                                    const R sums[11], R* rho_out,
+                                                    R* gradv_out) {
+  unsigned long long nrel = 0;
+  {
+    const R num = sums[0], den = sums[1];
+    R gv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gv[t] = sums[2 + t];
+    const R rho = num / den;
+    const R u = S.uu[s];
+    const R gam = R(S.gamma);
+    const R P = (gam - R(1)) * rho * u;
+    const R c = Sc<R>::sqrt(gam * (gam - R(1)) * u);
+    R relaxed = R(0);
+    if (S.dt_relax > 0.0) {
+      const double div = (double)gv[0] + (double)gv[4] + (double)gv[8];
+      // exp(|div v| dt) > 8  <=>  |div v| dt > ln 8
+      if (fabs(div) * S.dt_relax > 2.0794415416798357) {
+        relaxed = R(1);
+        nrel = 1;
+      }
+    }
+    R4<R> st;
+    st.x = rho;
+    st.y = P;
+    st.z = c;
+    st.w = den;
+    S.st4[s] = st;
+    R4<R> g0, g1, g2;
+    g0.x = gv[0]; g0.y = gv[1]; g0.z = gv[2]; g0.w = gv[3];
+    g1.x = gv[4]; g1.y = gv[5]; g1.z = gv[6]; g1.w = gv[7];
+    g2.x = gv[8]; g2.y = relaxed; g2.z = R(0); g2.w = R(0);
+    S.gv4[3 * s] = g0;
+    S.gv4[3 * s + 1] = g1;
+    S.gv4[3 * s + 2] = g2;
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    rho_out[p] = rho;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gradv_out[t * n + p] = gv[t];
+  }
+  return nrel;
+}
+
 template <class R, int K>
 __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ rho_out,
                                                     R* __restrict__ gradv_out) {
@@ -912,84 +1101,35 @@ __global__ void __launch_bounds__(kBlock) k_density(State<R> S, R* __restrict__ 
     S.gv4[3 * s] = g0;
     S.gv4[3 * s + 1] = g1;
     S.gv4[3 * s + 2] = g2;
-  } else if (s < S.n) {
-    const R4<R> pi = S.pos4[s];
-    const R4<R> vi = S.vel4[s];
-    const R hinv = pi.w;
-    const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
-    const R C4 = C3 * hinv;
-    KC<R> ki;
-    load_kc(S, s, ki);
-    // self term: x = 0, W^R_ii = A_i W(0)
-    const R W0 = C3 * R(Shape<K>::w0);
-    R num = S.mass[s] * vi.w * ki.a * W0;
-    R den = vi.w * vi.w * ki.a * W0;
-    R gv[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) gv[t] = R(0);
-    const NbrRef nb = nbr_ref(S, s);
-    uint4 ebuf;
-    const int ng = nb.ng;
-    for (int k = 0; k < ng; ++k) {
-      const uint32_t e = gather_entry(S, nb, k, ebuf);
-      const uint32_t j = e >> kCodeBits;
-      const R4<R> pj = S.pos4[j];
-      const R4<R> vj = S.vel4[j];
-      const R mj = S.mass[j];
-      R x[3];
-      pair_x(S, s, pi, pj, e, x);
-      const R r2 = dot3(x, x);
-      const R rinv = Sc<R>::rsqrt(r2);
-      R w, dw;
-      Shape<K>::eval(r2 * rinv * hinv, w, dw);
-      const R W = C3 * w;
-      const R fg = C4 * dw * rinv;
-      const R gW[3] = {fg * x[0], fg * x[1], fg * x[2]};
-      R WR, gWR[3];
-      kc_apply(ki, x, W, gW, WR, gWR);
-      num += mj * vj.w * WR;
-      den += vj.w * vj.w * WR;
-      const R dv[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int g = 0; g < 3; ++g) gv[a * 3 + g] -= vj.w * dv[a] * gWR[g];
-    }
-    const R rho = num / den;
-    const R u = S.uu[s];
-    const R gam = R(S.gamma);
-    const R P = (gam - R(1)) * rho * u;
-    const R c = Sc<R>::sqrt(gam * (gam - R(1)) * u);
-    R relaxed = R(0);
-    if (S.dt_relax > 0.0) {
-      const double div = (double)gv[0] + (double)gv[4] + (double)gv[8];
-      // exp(|div v| dt) > 8  <=>  |div v| dt > ln 8
-      if (fabs(div) * S.dt_relax > 2.0794415416798357) {
-        relaxed = R(1);
-        nrel = 1;
-      }
-    }
-    R4<R> st;
-    st.x = rho;
-    st.y = P;
-    st.z = c;
-    st.w = den;
-    S.st4[s] = st;
-    R4<R> g0, g1, g2;
-    g0.x = gv[0]; g0.y = gv[1]; g0.z = gv[2]; g0.w = gv[3];
-    g1.x = gv[4]; g1.y = gv[5]; g1.z = gv[6]; g1.w = gv[7];
-    g2.x = gv[8]; g2.y = relaxed; g2.z = R(0); g2.w = R(0);
-    S.gv4[3 * s] = g0;
-    S.gv4[3 * s + 1] = g1;
-    S.gv4[3 * s + 2] = g2;
-    const int64_t n = S.n;
-    const uint32_t p = S.perm[s];
-    rho_out[p] = rho;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) gradv_out[t * n + p] = gv[t];
+  } else if (s < S.n && !S.act) {  // (a list of active particles: k_density_rows)
+    R sums[11];
+    density_sums<R, K, 1>(S, s, 0, sums);
+    nrel = density_finish<R>(S, s, sums, rho_out, gradv_out);
   }
   wave_add_u64(cnt_at(S.cnt, CNT_RELAXED), nrel);
 }
+
+// The active particles of a hierarchy substep listed in act, a 16-lane row
+// each.
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_density_rows(State<R> S, R* __restrict__ rho_out,
+                                                         R* __restrict__ gradv_out) {
+  const int64_t r = particle_id() >> 4;
+  const int sub = threadIdx.x & 15;
+  unsigned long long nrel = 0;
+  if (r < S.nact) {
+    const int64_t s = S.act[r];
+    R sums[11];
+    density_sums<R, K, 16>(S, s, sub, sums);
+#pragma unroll
+    for (int t = 0; t < 11; ++t)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) sums[t] += __shfl_xor(sums[t], o, 16);
+    if (sub == 0) nrel = density_finish<R>(S, s, sums, rho_out, gradv_out);
+  }
+  if (nrel) atomicAdd(cnt_at(S.cnt, CNT_RELAXED), nrel);
+}
+
 
 // ------------------------------------------------------ force and du/dt ----
 // For j != i with r_ij < max(h_i, h_j):
@@ -1015,6 +1155,72 @@ __device__ inline void side_grad(const KC<R>& k, const R x[3], R r2, R rinv, R h
   kc_apply(k, x, W, gW, WR, out);
 }
 
+// Adds the force pair of particle s with neighbour entry e (i's position,
+// velocity, state, corrections, velocity gradient and relaxation flag, its
+// h, and the viscosity parameters) to acc and du.
+template <class R, int K>
+__device__ __forceinline__ void force_term(const State<R>& S, int64_t s, const R4<R>& pi,
+                                           const R4<R>& vi, const R4<R>& si, const KC<R>& ki,
+                                           const R gvi[9], R reli, R hi, bool relax_on,
+                                           R alpha, R beta, R eps2, uint32_t e, double acc[3],
+                                           double& du) {
+  const uint32_t j = e >> kCodeBits;
+  const R4<R> pj = S.pos4[j];
+  const R4<R> vj = S.vel4[j];
+  const R4<R> sj = S.st4[j];
+  KC<R> kj;
+  load_kc(S, j, kj);
+  R gvj[9], relj;
+  load_gv(S, j, gvj, relj);
+  R x[3];
+  pair_x(S, s, pi, pj, e, x);
+  const R r2 = dot3(x, x);
+  const R rinv = Sc<R>::rsqrt(r2);
+  KC<R> kiu = ki;
+  if (relax_on && (reli != R(0) || relj != R(0))) {
+    kc_plain(kiu);
+    kc_plain(kj);
+  }
+  R Gi[3], Gj[3];
+  side_grad<R, K>(kiu, x, r2, rinv, pi.w, Gi);
+  const R xm[3] = {-x[0], -x[1], -x[2]};
+  side_grad<R, K>(kj, xm, r2, rinv, pj.w, Gj);
+  R G[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
+  // limited artificial viscosity
+  R gix[3], gjx[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gix[a] = gvi[a * 3] * x[0] + gvi[a * 3 + 1] * x[1] + gvi[a * 3 + 2] * x[2];
+    gjx[a] = gvj[a * 3] * x[0] + gvj[a * 3 + 1] * x[1] + gvj[a * 3 + 2] * x[2];
+  }
+  const R nn = dot3(x, gix), dd = dot3(x, gjx);
+  const R sum = nn + dd;
+  const R s2 = sum * sum;
+  R phi = R(0);
+  if (s2 > R(0)) {
+    phi = Sc<R>::div(R(4) * nn * dd, s2);
+    phi = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+  }
+  const R hp = R(0.5) * phi;
+  const R vp[3] = {(vi.x - vj.x) - hp * (gix[0] + gjx[0]), (vi.y - vj.y) - hp * (gix[1] + gjx[1]),
+                   (vi.z - vj.z) - hp * (gix[2] + gjx[2])};
+  const R vpx = dot3(vp, x);
+  const R hj = Sc<R>::rcp(pj.w);
+  R mui = Sc<R>::div(vpx * hi, r2 + eps2 * hi * hi);
+  R muj = Sc<R>::div(vpx * hj, r2 + eps2 * hj * hj);
+  mui = mui < R(0) ? mui : R(0);
+  muj = muj < R(0) ? muj : R(0);
+  const R Qi = si.x * (-alpha * si.z * mui + beta * mui * mui);
+  const R Qj = sj.x * (-alpha * sj.z * muj + beta * muj * muj);
+  const R sfac = R(-0.5) * vi.w * vj.w * (si.y + sj.y + Qi + Qj);
+  const R F[3] = {sfac * G[0], sfac * G[1], sfac * G[2]};
+  const R work = (vi.x - vj.x) * F[0] + (vi.y - vj.y) * F[1] + (vi.z - vj.z) * F[2];
+  acc[0] += (double)F[0];
+  acc[1] += (double)F[1];
+  acc[2] += (double)F[2];
+  du += (double)work;
+}
+
 // HIER: a substep of the timestep hierarchy (the passive particles keep their
 // acceleration: nothing to sum or write); a separate instance, so that the
 // ordinary forward's code is not shaped by the extra branch
@@ -1023,7 +1229,7 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
                                                   double* __restrict__ dudt) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
-  if (HIER && is_passive(S, s)) return;
+  if (HIER && (is_passive(S, s) || S.act)) return;  // (a list of active: k_force_rows)
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
   const R4<R> si = S.st4[s];
@@ -1039,64 +1245,9 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   uint4 ebuf;  // at 3 waves per SIMD this beats 4 waves with the chunk in LDS
   const int ng = nb.ng, ns = nb.ns;
   const int total = ng + ns;
-  for (int t = 0; t < total; ++t) {
-    const uint32_t e = nbr_entry(S, nb, t, ebuf);
-    const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
-    const R4<R> vj = S.vel4[j];
-    const R4<R> sj = S.st4[j];
-    KC<R> kj;
-    load_kc(S, j, kj);
-    R gvj[9], relj;
-    load_gv(S, j, gvj, relj);
-    R x[3];
-    pair_x(S, s, pi, pj, e, x);
-    const R r2 = dot3(x, x);
-    const R rinv = Sc<R>::rsqrt(r2);
-    KC<R> kiu = ki;
-    if (relax_on && (reli != R(0) || relj != R(0))) {
-      kc_plain(kiu);
-      kc_plain(kj);
-    }
-    R Gi[3], Gj[3];
-    side_grad<R, K>(kiu, x, r2, rinv, pi.w, Gi);
-    const R xm[3] = {-x[0], -x[1], -x[2]};
-    side_grad<R, K>(kj, xm, r2, rinv, pj.w, Gj);
-    R G[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
-    // limited artificial viscosity
-    R gix[3], gjx[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gix[a] = gvi[a * 3] * x[0] + gvi[a * 3 + 1] * x[1] + gvi[a * 3 + 2] * x[2];
-      gjx[a] = gvj[a * 3] * x[0] + gvj[a * 3 + 1] * x[1] + gvj[a * 3 + 2] * x[2];
-    }
-    const R nn = dot3(x, gix), dd = dot3(x, gjx);
-    const R sum = nn + dd;
-    const R s2 = sum * sum;
-    R phi = R(0);
-    if (s2 > R(0)) {
-      phi = Sc<R>::div(R(4) * nn * dd, s2);
-      phi = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
-    }
-    const R hp = R(0.5) * phi;
-    const R vp[3] = {(vi.x - vj.x) - hp * (gix[0] + gjx[0]), (vi.y - vj.y) - hp * (gix[1] + gjx[1]),
-                     (vi.z - vj.z) - hp * (gix[2] + gjx[2])};
-    const R vpx = dot3(vp, x);
-    const R hj = Sc<R>::rcp(pj.w);
-    R mui = Sc<R>::div(vpx * hi, r2 + eps2 * hi * hi);
-    R muj = Sc<R>::div(vpx * hj, r2 + eps2 * hj * hj);
-    mui = mui < R(0) ? mui : R(0);
-    muj = muj < R(0) ? muj : R(0);
-    const R Qi = si.x * (-alpha * si.z * mui + beta * mui * mui);
-    const R Qj = sj.x * (-alpha * sj.z * muj + beta * muj * muj);
-    const R sfac = R(-0.5) * vi.w * vj.w * (si.y + sj.y + Qi + Qj);
-    const R F[3] = {sfac * G[0], sfac * G[1], sfac * G[2]};
-    const R work = (vi.x - vj.x) * F[0] + (vi.y - vj.y) * F[1] + (vi.z - vj.z) * F[2];
-    acc[0] += (double)F[0];
-    acc[1] += (double)F[1];
-    acc[2] += (double)F[2];
-    du += (double)work;
-  }
+  for (int t = 0; t < total; ++t)
+    force_term<R, K>(S, s, pi, vi, si, ki, gvi, reli, hi, relax_on, alpha, beta, eps2,
+                     nbr_entry(S, nb, t, ebuf), acc, du);
   const int64_t n = S.n;
   const uint32_t p = S.perm[s];
   const double minv = 1.0 / (double)S.mass[s];
@@ -1104,6 +1255,48 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   accel[n + p] = acc[1] * minv;
   accel[2 * n + p] = acc[2] * minv;
   dudt[p] = -0.5 * du * minv;
+}
+
+// The active particles of a hierarchy substep listed in act, a 16-lane row
+// each: lane sub takes the pairs t = sub mod 16, the row sums in FP64.
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_force_rows(State<R> S, double* __restrict__ accel,
+                                                       double* __restrict__ dudt) {
+  const int64_t r = particle_id() >> 4;
+  const int sub = threadIdx.x & 15;
+  if (r >= S.nact) return;  // the whole row
+  const int64_t s = S.act[r];
+  const R4<R> pi = S.pos4[s];
+  const R4<R> vi = S.vel4[s];
+  const R4<R> si = S.st4[s];
+  KC<R> ki;
+  load_kc(S, s, ki);
+  R gvi[9], reli;
+  load_gv(S, s, gvi, reli);
+  const bool relax_on = S.dt_relax > 0.0;
+  const R alpha = R(S.alpha), beta = R(S.beta), eps2 = R(S.eps2);
+  const R hi = R(1) / pi.w;
+  double acc[3] = {0.0, 0.0, 0.0}, du = 0.0;
+  const NbrRef nb = nbr_ref(S, s);
+  const int total = nb.ng + nb.ns;
+  for (int t = sub; t < total; t += 16)
+    force_term<R, K>(S, s, pi, vi, si, ki, gvi, reli, hi, relax_on, alpha, beta, eps2,
+                     nbr_entry1(S, nb, t), acc, du);
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a] += __shfl_xor(acc[a], o, 16);
+    du += __shfl_xor(du, o, 16);
+  }
+  if (sub == 0) {
+    const int64_t n = S.n;
+    const uint32_t p = S.perm[s];
+    const double minv = 1.0 / (double)S.mass[s];
+    accel[p] = acc[0] * minv;
+    accel[n + p] = acc[1] * minv;
+    accel[2 * n + p] = acc[2] * minv;
+    dudt[p] = -0.5 * du * minv;
+  }
 }
 
 // ------------------------------------------------------------ checks -----
@@ -1141,6 +1334,16 @@ void launch_keys_check(const double* x, int64_t n, double box, int G, const uint
                        const uint32_t* perm, unsigned long long* cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_keys_check, dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, box, G, keys,
                      perm, cnt);
+}
+
+void launch_count_active(const int* levels, int64_t n, int lmax, int64_t jend,
+                         unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_active, dim3(grid_for(n)), dim3(kBlock), 0, s, levels, n, lmax, jend,
+                     cnt);
+}
+template <class R>
+void launch_active_list(const State<R>& S, uint32_t* list, hipStream_t s) {
+  hipLaunchKernelGGL(k_active_list<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S, list);
 }
 
 void launch_cell_bounds(const uint32_t* keys, int64_t n, int64_t ncell, uint32_t* start,
@@ -1192,18 +1395,32 @@ template <class R>
 void launch_nlist(const State<R>& S, hipStream_t s) {
   hipLaunchKernelGGL(k_nlist<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
 }
+// a 16-lane row per listed active particle
+#define CRK_DISPATCH_ROWS(kernel, KFN, ...)                                                 \
+  do {                                                                                      \
+    const dim3 rg(grid_for(16 * S.nact));                                                   \
+    if ((kernel) == 0)                                                                      \
+      hipLaunchKernelGGL((KFN<R, 0>), rg, dim3(kBlock), 0, s, __VA_ARGS__);                 \
+    else                                                                                    \
+      hipLaunchKernelGGL((KFN<R, 1>), rg, dim3(kBlock), 0, s, __VA_ARGS__);                 \
+  } while (0)
+
 template <class R>
 void launch_moments(const State<R>& S, int kernel, CorrOut o, hipStream_t s) {
   CRK_DISPATCH_K(kernel, k_moments, S, o);
+  if (S.act && S.nact > 0) CRK_DISPATCH_ROWS(kernel, k_moments_rows, S, o);
 }
 template <class R>
 void launch_density(const State<R>& S, int kernel, R* rho_out, R* gradv_out, hipStream_t s) {
   CRK_DISPATCH_K(kernel, k_density, S, rho_out, gradv_out);
+  if (S.act && S.nact > 0) CRK_DISPATCH_ROWS(kernel, k_density_rows, S, rho_out, gradv_out);
 }
 template <class R>
 void launch_force(const State<R>& S, int kernel, double* accel, double* dudt, hipStream_t s) {
   const dim3 grid(grid_for(S.n)), block(kBlock);
-  if (S.levels) {
+  if (S.act) {  // the passive particles need nothing: only the rows
+    if (S.nact > 0) CRK_DISPATCH_ROWS(kernel, k_force_rows, S, accel, dudt);
+  } else if (S.levels) {
     if (kernel == 0)
       hipLaunchKernelGGL((k_force<R, 0, true>), grid, block, 0, s, S, accel, dudt);
     else
@@ -1237,6 +1454,7 @@ void launch_count_nonfinite_f64(const double* a, int64_t na, unsigned long long*
   template void launch_moments<R>(const State<R>&, int, CorrOut, hipStream_t);               \
   template void launch_density<R>(const State<R>&, int, R*, R*, hipStream_t);                \
   template void launch_force<R>(const State<R>&, int, double*, double*, hipStream_t);        \
+  template void launch_active_list<R>(const State<R>&, uint32_t*, hipStream_t);              \
   template void launch_count_nonfinite<R>(const R*, int64_t, unsigned long long*, hipStream_t);
 
 CRK_INSTANTIATE(float)

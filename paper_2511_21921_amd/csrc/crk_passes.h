@@ -61,6 +61,14 @@ void launch_filter_tree(const State<R>& S, bool write, int* fillc, uint32_t* que
                         hipStream_t s);
 void launch_wave_rows(const int* cnt, int64_t n, int extra, uint32_t* rows, hipStream_t s);
 
+// Hierarchy: CNT_ACTIVE counts the particles active at the end of substep
+// jend; the active sorted slots appended to list (CNT_ACTLIST, slot 0, must
+// start at zero).
+void launch_count_active(const int* levels, int64_t n, int lmax, int64_t jend,
+                         unsigned long long* cnt, hipStream_t s);
+template <class R>
+void launch_active_list(const State<R>& S, uint32_t* list, hipStream_t s);
+
 // Gather caller arrays into cell-sorted SoA with cell-centre offsets.
 template <class R>
 void launch_gather(const State<R>& S, const double* x, const R* v, const R* m, const R* u,

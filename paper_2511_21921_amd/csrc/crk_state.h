@@ -35,6 +35,8 @@ enum Counter {
   CNT_LONG_LISTS,      // tree path: scatter-only lists queued for the wave sort (slot 0 only)
   CNT_POOL,            // tree path: candidate pool entries taken by staged blocks (slot 0 only)
   CNT_MOVED,           // particles whose cell differs from the kept cell list's
+  CNT_ACTIVE,          // hierarchy: particles active at the substep's end
+  CNT_ACTLIST,         // hierarchy: length of the active list (slot 0 only)
   CNT_COUNT
 };
 
@@ -166,6 +168,11 @@ struct State {
   // particles and their list partners: the passive particles whose stored
   // state a force pair reads (null: every particle's state is packed)
   uint8_t* needed;
+  // a substep with few active particles: their sorted slots (nact of them,
+  // in no particular order); the pair passes then give each a 16-lane row
+  // (null: a thread per particle)
+  const uint32_t* act;
+  int64_t nact;
 };
 
 // whether sorted particle s is passive (reads nothing without a hierarchy)
