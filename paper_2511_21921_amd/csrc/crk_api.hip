@@ -75,6 +75,11 @@ struct crk_ctx {
   // passes: hl_rows, and their number
   bool hl_rows = false;
   long long hl_nact = 0;
+  // per big step: the particles per level and the refined ones (read once),
+  // and for the current substep a bound on its active particles from them
+  Buf hl_hist;
+  unsigned long long hl_hist_host[32] = {};
+  long long hl_bound = 0;
   // levels and stored state seen by the passes during a hierarchical
   // substep (null levels: every particle active)
   const int* hl_levels = nullptr;
@@ -112,6 +117,10 @@ struct crk_ctx {
   // cells_G, cells_n particles; cells_G = 0 once they are overwritten)
   int cells_G = 0;
   long long cells_n = -1;
+  // whether the last check of a kept cell list found no particle moved: the
+  // next speculative forward then keeps the list without reading the check
+  // first (a move found at the end rejects that forward)
+  bool cells_stable = false;
   bool spec_ok = false;
   long long spec_n = -1;
   int spec_prec = -1;
@@ -379,10 +388,10 @@ hipError_t read_counters(crk_ctx* c, hipStream_t s) {
 // give each a 16-lane row in the pair passes.
 constexpr long long kRowsMax = 32768;
 
-// From the counters just read: whether this substep lists its active
-// particles for the row passes.
-void set_rows(crk_ctx* ctx, int64_t n) {
-  const long long na = (long long)ctx->host_cnt[CNT_ACTIVE];
+// Whether this substep lists its active particles for the row passes, from
+// na, their number or a bound on it (the row grids are sized by it; the row
+// kernels take the list's own length).
+void set_rows(crk_ctx* ctx, int64_t n, long long na) {
   ctx->hl_nact = na;
   ctx->hl_rows = ctx->hl_levels && na <= kRowsMax && na < n;
 }
@@ -652,8 +661,6 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
   launch_check_inputs<R>(x, h, m, u, n, dcnt, s);
-  if (ctx->hl_levels)
-    launch_count_active(ctx->hl_levels, n, ctx->hl_lmax, ctx->hl_jend, dcnt, s);
   ctx->G = ctx->spec_G;
   ctx->ell = P.box / ctx->G;
   ctx->lattice = 0;
@@ -663,23 +670,20 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   const double ncell = (double)ctx->G * ctx->G * ctx->G;
   const double occ_rule = std::max(1024.0, 16.0 * (double)n / ncell);
   CRK_HIP(tbegin(ctx, P_CELLS, s), "event");
-  bool keep_cells = ctx->cells_G == ctx->G && ctx->cells_n == n;
-  bool read = false;
-  if (keep_cells) {
+  // the kept cell list: checked against these positions whenever it is at
+  // hand; kept without waiting for the check when the last check found it
+  // still sorted, else built again (the check then tells the next forward)
+  const bool at_hand = ctx->cells_G == ctx->G && ctx->cells_n == n;
+  if (at_hand)
     launch_keys_check(x, n, P.box, ctx->G, (const uint32_t*)ctx->keys_a.p,
                       (const uint32_t*)ctx->vals_a.p, dcnt, s);
-    CRK_HIP(hipGetLastError(), "cell check launch");
-    CRK_HIP(read_counters(ctx, s), "cell check");
-    read = true;
-    keep_cells = ctx->host_cnt[CNT_MOVED] == 0;
-  }
-  if (!keep_cells) {
+  const bool kept = at_hand && ctx->cells_stable;
+  if (!kept) {
     crk_status st = build_cells<R>(ctx, s, n, x,
                                    P.search == 0 ? (unsigned long long)occ_rule : ~0ull);
     if (st != CRK_OK) return st;
   }
-  if (ctx->hl_levels && !read) CRK_HIP(read_counters(ctx, s), "active count");
-  set_rows(ctx, n);
+  set_rows(ctx, n, ctx->hl_bound);
   {
     State<R> S = make_state<R>(ctx, n);
     launch_gather<R>(S, x, v, m, u, h, s);
@@ -730,6 +734,11 @@ crk_status forward_fast(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
   CRK_HIP(hipGetLastError(), "pass launch");
   CRK_HIP(read_counters(ctx, s), "speculative forward");
   const unsigned long long* hc = ctx->host_cnt;
+  if (at_hand) ctx->cells_stable = hc[CNT_MOVED] == 0;
+  if (kept && hc[CNT_MOVED]) {
+    ctx->cells_G = 0;  // a particle left its cell: the list no longer sorts x
+    return CRK_OK;
+  }
   if (hc[CNT_BAD_INPUT]) return CRK_OK;  // the careful path reports it
   const double h0max = bits_to_double(hc[CNT_HMAX_BITS]);
   if (!(h0max < 0.5 * P.box)) return CRK_OK;
@@ -778,7 +787,7 @@ crk_status forward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
       launch_count_active(ctx->hl_levels, n, ctx->hl_lmax, ctx->hl_jend, dcnt, s);
     CRK_HIP(hipGetLastError(), "input check launch");
     CRK_HIP(read_counters(ctx, s), "input check");
-    set_rows(ctx, n);
+    set_rows(ctx, n, (long long)ctx->host_cnt[CNT_ACTIVE]);
     if (ctx->host_cnt[CNT_BAD_INPUT])
       return fail(ctx, CRK_EINVAL, "x must be finite; h, m and u finite and > 0");
     const double h0max = bits_to_double(ctx->host_cnt[CNT_HMAX_BITS]);
@@ -1104,8 +1113,13 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
   CRK_HIP(ensure_particles(ctx, n), "workspace allocation");
   unsigned long long* dcnt = (unsigned long long*)ctx->cnt.p;
   CRK_HIP(hipMemsetAsync(dcnt, 0, 8 * CNT_COUNT * kCntSpread, s), "memset");
-  launch_level_range(levels, refine_at, refine_level, n, dcnt, s);
+  CRK_HIP(ensure(ctx->hl_hist, 8 * 32), "step workspace");
+  CRK_HIP(hipMemsetAsync(ctx->hl_hist.p, 0, 8 * 32, s), "memset");
+  launch_level_range(levels, refine_at, refine_level, n, dcnt,
+                     (unsigned long long*)ctx->hl_hist.p, s);
   CRK_HIP(hipGetLastError(), "level launch");
+  CRK_HIP(hipMemcpyAsync(ctx->hl_hist_host, ctx->hl_hist.p, 8 * 32, hipMemcpyDeviceToHost, s),
+          "levels");
   CRK_HIP(read_counters(ctx, s), "levels");
   if (ctx->host_cnt[CNT_BAD_INPUT])
     return fail(ctx, CRK_EINVAL,
@@ -1160,6 +1174,14 @@ crk_status hstep_impl(crk_ctx* ctx, hipStream_t s, int64_t n, double dt, double 
     CRK_HIP(hipGetLastError(), "hierarchy launch");
     // the neighbour-list pass marks the passive partners of active particles
     CRK_HIP(hipMemsetAsync(ctx->hl_need.p, 0, N, s), "memset");
+    // the particles of the levels whose interval ends here, and every refined
+    // one, bound those active at this substep's end
+    {
+      long long bound = (long long)ctx->hl_hist_host[31];
+      for (int L = 0; L <= lmax; ++L)
+        if ((jend & (((int64_t)1 << (lmax - L)) - 1)) == 0) bound += (long long)ctx->hl_hist_host[L];
+      ctx->hl_bound = std::min<long long>(bound, n);
+    }
     // the passes see the levels and the stored state during this forward only
     ctx->hl_levels = lvl;
     ctx->hl_lmax = lmax;
@@ -1445,7 +1467,7 @@ crk_status crk_destroy(crk_ctx* c) {
                 &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->vpred, &c->upred,
-                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need, &c->hl_act,
+                &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need, &c->hl_act, &c->hl_hist,
                 &c->cool_lam, &c->cool_oma, &c->cool_co, &c->cool_G, &c->cool_run, &c->cool_binint,
                 &c->dep_keys_a, &c->dep_keys_b, &c->dep_vals_a, &c->dep_vals_b, &c->dep_start,
                 &c->dep_tmp, &c->dep_cnt, &c->dep_npair, &c->dep_off, &c->dep_first,

@@ -259,6 +259,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
     S.ccnt[s] = 0;
     return;
   }
+  if (S.act) return;  // a listed active particle: k_candidates_rows
   const R4<R> pi = S.pos4[s];
   const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
   const R rc2 = S.rcap * S.rcap;
@@ -531,6 +532,7 @@ __global__ void __launch_bounds__(kBlock) k_volume(State<R> S) {
   const int64_t s = particle_id();
   if (s >= S.n) return;
   if (is_passive(S, s)) return;  // V comes from the stored state (k_pack)
+  if (S.act) return;             // a listed active particle: k_volume_rows
   const R h = S.hbuf[s];
   int scap;
   const int64_t base = scratch_base(S, s, scap);
@@ -560,7 +562,8 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_nlist(State<R> S) {
   const int64_t s = particle_id();
   unsigned long long g = 0, f = 0, ovf = 0, sovf = 0, cands = 0;
-  if (s < S.n) {
+  // (a listed active particle: k_nlist_rows)
+  if (s < S.n && !(S.act && !is_passive(S, s))) {
     // Classified by the stored candidate distance r: it is the same value
     // from both sides of a pair (the separation is computed with both signs
     // flipped), so j lands in i's scatter-only list exactly when i is in j's
@@ -916,7 +919,7 @@ __global__ void __launch_bounds__(kBlock) k_moments_rows(State<R> S, CorrOut o) 
   const int64_t r = particle_id() >> 4;
   const int sub = threadIdx.x & 15;
   unsigned long long sing = 0;
-  if (r < S.nact) {
+  if (r < (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) {
     const int64_t s = S.act[r];
     Moments<R> M;
     accumulate_moments_row<R, K>(S, s, sub, M);
@@ -1117,7 +1120,7 @@ __global__ void __launch_bounds__(kBlock) k_density_rows(State<R> S, R* __restri
   const int64_t r = particle_id() >> 4;
   const int sub = threadIdx.x & 15;
   unsigned long long nrel = 0;
-  if (r < S.nact) {
+  if (r < (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) {
     const int64_t s = S.act[r];
     R sums[11];
     density_sums<R, K, 16>(S, s, sub, sums);
@@ -1264,7 +1267,7 @@ __global__ void __launch_bounds__(kBlock) k_force_rows(State<R> S, double* __res
                                                        double* __restrict__ dudt) {
   const int64_t r = particle_id() >> 4;
   const int sub = threadIdx.x & 15;
-  if (r >= S.nact) return;  // the whole row
+  if (r >= (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) return;  // the whole row
   const int64_t s = S.act[r];
   const R4<R> pi = S.pos4[s];
   const R4<R> vi = S.vel4[s];
@@ -1313,6 +1316,171 @@ __global__ void __launch_bounds__(kBlock) k_nonfinite(const R* __restrict__ a, i
   wave_add_u64(cnt_at(cnt, CNT_NONFINITE), bad);
 }
 
+
+// ---------------------------------------------- rows for few active ones --
+// A hierarchy substep with few active particles (listed in act) gives each a
+// 16-lane row in the candidate, volume and neighbour-list passes as well;
+// the rows keep the entry order and values of the thread kernels.
+
+// The stencil walk of k_candidates by a row: its lanes test 16 consecutive
+// particles of a cell run at a time and append the accepted ones in order.
+template <class R, bool EM>
+__global__ void __launch_bounds__(kBlock) k_candidates_rows(State<R> S) {
+  if (__ballot(S.cnt[CNT_TOO_DENSE * kCntSpread + (threadIdx.x & 63)] != 0ull)) return;
+  const int64_t r = particle_id() >> 4;
+  if (r >= (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) return;  // the whole row
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const uint64_t rowbits = 0xFFFFull << (lane & 48);
+  const uint64_t below = rowbits & ((1ull << lane) - 1ull);
+  const int64_t s = S.act[r];
+  const R4<R> pi = S.pos4[s];
+  const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
+  const R rc2 = S.rcap * S.rcap;
+  int cap;
+  const int64_t base = scratch_base(S, s, cap);
+  int cnt = 0;  // uniform over the row
+  const uint32_t c3 = S.cell3[s];
+  const int G = S.G;
+  const int cx = (int)(c3 & 1023u), cy = (int)((c3 >> 10) & 1023u), cz = (int)(c3 >> 20);
+  const R ell = S.ell;
+  const uint32_t n = (uint32_t)S.n;
+  auto gap2 = [&](R xi, int d) {
+    const R lo = (R(d) - R(0.5)) * ell - xi, hi = xi - (R(d) + R(0.5)) * ell;
+    const R g = lo > hi ? lo : hi;
+    return g > R(0) ? g * g : R(0);
+  };
+  auto walk = [&](uint32_t c0, int x0, int d0, int d1, int dy, int dz, bool own_row) {
+    const uint32_t b = S.cell_start[c0];
+    uint32_t e = S.cell_start[c0 + (uint32_t)(d1 - d0 + 1)];
+    if (e > n) e = n;
+    const int xoff = d0 - x0;
+    const int code0 = (int)stencil_code(0, dy, dz);
+    const R oy = R(dy) * ell, oz = R(dz) * ell;
+    for (uint32_t j0 = b; j0 < e; j0 += 16) {
+      const uint32_t j = j0 + (uint32_t)sub;
+      const bool valid = j < e;
+      const R4<R> pj = S.pos4[valid ? j : e - 1];
+      const int dx = (int)pj.w + xoff;
+      R x[3];
+      x[0] = (pi.x - pj.x) - R(dx) * ell;
+      x[1] = (pi.y - pj.y) - oy;
+      x[2] = (pi.z - pj.z) - oz;
+      const R r2 = dot3(x, x);
+      bool ok = valid && r2 < rc2;
+      if (own_row) ok = ok && !(j == (uint32_t)s && dx == 0);
+      const uint64_t bm = __ballot(ok) & rowbits;
+      const int at = cnt + __popcll(bm & below);
+      if (ok && at < cap) {
+        const int64_t q = group_at(base, at);
+        S.cand[q] = (j << kCodeBits) | (uint32_t)(code0 + dx);
+        S.scr_r[q] = Sc<R>::sqrt(r2);
+        if (!EM) S.scr_m[q] = S.mass[j] * mi_inv;
+      }
+      cnt += __popcll(bm);
+    }
+  };
+  for (int dz = -2; dz <= 2; ++dz) {
+    const R gz = gap2(pi.z, dz);
+    if (!(gz < rc2)) continue;
+    const int z = wrap_cell(cz + dz, G);
+    for (int dy = -2; dy <= 2; ++dy) {
+      const R gyz = gz + gap2(pi.y, dy);
+      if (!(gyz < rc2)) continue;
+      const int y = wrap_cell(cy + dy, G);
+      const uint32_t rowbase = ((uint32_t)z * G + (uint32_t)y) * G;
+      int dlo = 3, dhi = -3;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx)
+        if (gyz + gap2(pi.x, dx) < rc2) {
+          dlo = dx < dlo ? dx : dlo;
+          dhi = dx;
+        }
+      const int a1 = min(dhi, -cx - 1);
+      const int b0 = max(dlo, -cx), b1 = min(dhi, G - 1 - cx);
+      const int c0 = max(dlo, G - cx);
+      const bool own = dy == 0 && dz == 0;
+      if (dlo <= a1) walk(rowbase + (uint32_t)(cx + dlo + G), cx + dlo + G, dlo, a1, dy, dz, own);
+      if (b0 <= b1) walk(rowbase + (uint32_t)(cx + b0), cx + b0, b0, b1, dy, dz, own);
+      if (c0 <= dhi) walk(rowbase + (uint32_t)(cx + c0 - G), cx + c0 - G, c0, dhi, dy, dz, own);
+    }
+  }
+  if (sub == 0) {
+    S.ccnt[s] = cnt < cap ? cnt : cap;
+    if (cnt > cap) atomicMax(cnt_at(S.cnt, CNT_SCR_OVERFLOW), (unsigned long long)cnt);
+  }
+}
+
+// The fixed-h volume of k_volume by a row (the self term in lane 0).
+template <class R, int K>
+__global__ void __launch_bounds__(kBlock) k_volume_rows(State<R> S) {
+  const int64_t r = particle_id() >> 4;
+  if (r >= (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) return;
+  const int sub = threadIdx.x & 15;
+  const int64_t s = S.act[r];
+  const R h = S.hbuf[s];
+  const R hinv = R(1) / h;
+  int scap;
+  const int64_t base = scratch_base(S, s, scap);
+  const int cnt = S.ccnt[s] < scap ? S.ccnt[s] : scap;
+  R sum = sub == 0 ? R(Shape<K>::w0) : R(0);
+  for (int k = sub; k < cnt; k += 16) {
+    const int64_t e = group_at(base, k);
+    R w, dw;
+    Shape<K>::eval(S.scr_r[e] * hinv, w, dw);
+    sum += (S.equal_mass ? R(1) : S.scr_m[e]) * w;
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
+  if (sub == 0) S.Vbuf[s] = h * h * h / (R(Shape<K>::C) * sum);
+}
+
+// The neighbour lists of k_nlist by a row: 16 candidates at a time, the
+// gather and scatter-only entries appended in candidate order.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_nlist_rows(State<R> S) {
+  const int64_t r = particle_id() >> 4;
+  if (r >= (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) return;
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const uint64_t rowbits = 0xFFFFull << (lane & 48);
+  const uint64_t below = rowbits & ((1ull << lane) - 1ull);
+  const int64_t s = S.act[r];
+  const R hi = S.hbuf[s];
+  int ccap;
+  const int64_t base = scratch_base(S, s, ccap);
+  const int cc = S.ccnt[s] < ccap ? S.ccnt[s] : ccap;
+  const int cap = S.list_cap, scap = S.slist_cap;
+  int ng = 0, ns = 0;  // uniform over the row
+  for (int k = 0; k < cc; k += 16) {
+    const int t = k + sub;
+    const bool in = t < cc;
+    const int64_t c = group_at(base, in ? t : 0);
+    const uint32_t e = S.cand[c];
+    const R rr = S.scr_r[c];
+    const bool g = in && rr < hi;
+    const bool sc = in && !g && rr < S.hbuf[e >> kCodeBits];
+    const uint64_t gm = __ballot(g) & rowbits, sm = __ballot(sc) & rowbits;
+    if (g) {
+      const int at = ng + __popcll(gm & below);
+      if (at < cap) S.nlist[list_index(s, cap, at)] = e;
+    }
+    if (sc) {
+      const int at = ns + __popcll(sm & below);
+      if (at < scap) S.slist[list_index(s, scap, at)] = e;
+    }
+    if (S.needed && (g || sc)) S.needed[e >> kCodeBits] = 1;
+    ng += __popcll(gm);
+    ns += __popcll(sm);
+  }
+  if (sub == 0) {
+    S.ng[s] = ng;
+    S.ns[s] = ns;
+    atomicAdd(cnt_at(S.cnt, CNT_PAIRS_GATHER), (unsigned long long)ng);
+    atomicAdd(cnt_at(S.cnt, CNT_PAIRS_FORCE), (unsigned long long)(ng + ns));
+    atomicAdd(cnt_at(S.cnt, CNT_CANDIDATES), (unsigned long long)cc);
+    if (ng > cap) atomicMax(cnt_at(S.cnt, CNT_LIST_OVERFLOW), (unsigned long long)ng);
+    if (ns > scap) atomicMax(cnt_at(S.cnt, CNT_SLIST_OVERFLOW), (unsigned long long)ns);
+  }
+}
 }  // namespace
 
 // ----------------------------------------------------------- launchers ----
@@ -1372,6 +1540,13 @@ void launch_candidates(const State<R>& S, hipStream_t s) {
     hipLaunchKernelGGL((k_candidates<R, true>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
   else
     hipLaunchKernelGGL((k_candidates<R, false>), dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  if (S.act && S.nact > 0) {
+    const dim3 rg(grid_for(16 * S.nact));
+    if (S.equal_mass)
+      hipLaunchKernelGGL((k_candidates_rows<R, true>), rg, dim3(kBlock), 0, s, S);
+    else
+      hipLaunchKernelGGL((k_candidates_rows<R, false>), rg, dim3(kBlock), 0, s, S);
+  }
 }
 template <class R>
 void launch_hsolve(const State<R>& S, int kernel, hipStream_t s) {
@@ -1386,6 +1561,11 @@ void launch_volume(const State<R>& S, int kernel, hipStream_t s) {
   const dim3 g(grid_for(S.n)), b(kBlock);
   if (kernel == 0) hipLaunchKernelGGL((k_volume<R, 0>), g, b, 0, s, S);
   else hipLaunchKernelGGL((k_volume<R, 1>), g, b, 0, s, S);
+  if (S.act && S.nact > 0) {
+    const dim3 rg(grid_for(16 * S.nact));
+    if (kernel == 0) hipLaunchKernelGGL((k_volume_rows<R, 0>), rg, b, 0, s, S);
+    else hipLaunchKernelGGL((k_volume_rows<R, 1>), rg, b, 0, s, S);
+  }
 }
 template <class R>
 void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s) {
@@ -1394,6 +1574,8 @@ void launch_pack(const State<R>& S, R* h_out, R* V_out, hipStream_t s) {
 template <class R>
 void launch_nlist(const State<R>& S, hipStream_t s) {
   hipLaunchKernelGGL(k_nlist<R>, dim3(grid_for(S.n)), dim3(kBlock), 0, s, S);
+  if (S.act && S.nact > 0)
+    hipLaunchKernelGGL(k_nlist_rows<R>, dim3(grid_for(16 * S.nact)), dim3(kBlock), 0, s, S);
 }
 // a 16-lane row per listed active particle
 #define CRK_DISPATCH_ROWS(kernel, KFN, ...)                                                 \

@@ -177,10 +177,13 @@ void launch_hier_refine(int64_t n, int64_t j, const int* refine_at, const int* r
                         int* lvl, int lmax, double dt_min, double lam, double n_h, R* v, R* u,
                         const R* h, const R* V, const R* gradv, const double* accel,
                         const double* dudt, R* vh, R* uh, double* hdot, hipStream_t s);
-// largest level and bad levels or refinements (refine_at null: none), then
-// refinements off their level's grid for the largest level lmax
+// largest level and bad levels or refinements (refine_at null: none), the
+// particles per level (hist[L], L <= 30) and the refined ones (hist[31]; hist
+// must start at zero), then refinements off their level's grid for the
+// largest level lmax
 void launch_level_range(const int* levels, const int* refine_at, const int* refine_level,
-                        int64_t n, unsigned long long* cnt, hipStream_t s);
+                        int64_t n, unsigned long long* cnt, unsigned long long* hist,
+                        hipStream_t s);
 void launch_refine_grid(const int* refine_at, const int* refine_level, int64_t n, int lmax,
                         unsigned long long* cnt, hipStream_t s);
 

@@ -168,9 +168,10 @@ struct State {
   // particles and their list partners: the passive particles whose stored
   // state a force pair reads (null: every particle's state is packed)
   uint8_t* needed;
-  // a substep with few active particles: their sorted slots (nact of them,
-  // in no particular order); the pair passes then give each a 16-lane row
-  // (null: a thread per particle)
+  // a substep with few active particles: their sorted slots (as many as the
+  // slot 0 of CNT_ACTLIST counts, in no particular order); the pair passes
+  // then give each a 16-lane row, in grids of nact rows, a bound on that
+  // number (act null: a thread per particle)
   const uint32_t* act;
   int64_t nact;
 };

@@ -227,17 +227,25 @@ __global__ void __launch_bounds__(kBlock) k_level_range(const int* __restrict__ 
                                                         const int* __restrict__ refine_at,
                                                         const int* __restrict__ refine_level,
                                                         int64_t n,
-                                                        unsigned long long* __restrict__ cnt) {
+                                                        unsigned long long* __restrict__ cnt,
+                                                        unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int bins[32];
+  if (threadIdx.x < 32) bins[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned long long top = 0, bad = 0;
   if (i < n) {
     const int L = levels[i];
     if (L < 0 || L > 30) bad = 1; else top = (unsigned long long)L;
+    if (L >= 0 && L <= 30) atomicAdd(&bins[L], 1u);
     if (refine_at && refine_at[i] >= 0) {
       const int Lr = refine_level[i];
       if (!(Lr > L && Lr <= 30)) bad = 1; else top = top > (unsigned long long)Lr ? top : Lr;
+      atomicAdd(&bins[31], 1u);
     }
   }
+  __syncthreads();
+  if (threadIdx.x < 32 && bins[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)bins[threadIdx.x]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long t = __shfl_xor(top, o, 64);
@@ -304,9 +312,10 @@ void launch_hier_close(int64_t n, const int* levels, int lmax, int64_t jend, dou
 }
 
 void launch_level_range(const int* levels, const int* refine_at, const int* refine_level,
-                        int64_t n, unsigned long long* cnt, hipStream_t s) {
+                        int64_t n, unsigned long long* cnt, unsigned long long* hist,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_level_range, dim3(grid_for(n)), dim3(kBlock), 0, s, levels, refine_at,
-                     refine_level, n, cnt);
+                     refine_level, n, cnt, hist);
 }
 
 void launch_refine_grid(const int* refine_at, const int* refine_level, int64_t n, int lmax,
