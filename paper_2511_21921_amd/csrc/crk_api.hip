@@ -393,7 +393,8 @@ constexpr long long kRowsMax = 32768;
 // kernels take the list's own length).
 void set_rows(crk_ctx* ctx, int64_t n, long long na) {
   ctx->hl_nact = na;
-  ctx->hl_rows = ctx->hl_levels && na <= kRowsMax && na < n;
+  // (the list has room for every particle: the hierarchy step sizes it)
+  ctx->hl_rows = ctx->hl_levels && na <= kRowsMax && na < n && ctx->hl_act.bytes >= 4 * (size_t)n;
 }
 
 double bits_to_double(unsigned long long b) {

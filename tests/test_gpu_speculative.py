@@ -116,3 +116,30 @@ def test_set_params_keeps_or_drops_the_geometry():
     ctx.set_params(_gpu.params_for(ps, FP32, alpha=1.5, n_h=ps.n_h * 1.01))
     g, _ = _gpu.run(ps, FP32, ctx=ctx, alpha=1.5, n_h=ps.n_h * 1.01)
     assert g["stats"]["speculative"] == 0
+
+
+@pytest.mark.parametrize("precision", [FP32, FP64])
+def test_kept_cell_list_and_a_particle_that_changes_cell(precision):
+    """A speculative forward keeps the last cell list when a check found it
+    still sorted; once a particle has moved to another cell that forward is
+    rejected, equals a fresh context's, and the next one builds the list again."""
+    ps = synth.random_small(4000, 103)
+    print("case random4000 seed 103 precision=%d" % precision, flush=True)
+    g1, ctx = _gpu.run(ps, precision)          # careful: builds the list
+    g2, _ = _gpu.run(ps, precision, ctx=ctx)   # checks the list and builds it again
+    g3, _ = _gpu.run(ps, precision, ctx=ctx)   # keeps it
+    assert g2["stats"]["speculative"] == 1 and g3["stats"]["speculative"] == 1
+    _same(g1, g2)
+    _same(g1, g3)
+    grid = g1["stats"]["grid"]
+    assert grid >= 2
+    x2 = ps.x.copy()
+    x2[0, 7] = (x2[0, 7] + ps.box / grid) % ps.box  # one cell side along x
+    ps2 = dataclasses.replace(ps, x=x2)
+    fresh, _ = _gpu.run(ps2, precision)
+    g4, _ = _gpu.run(ps2, precision, ctx=ctx)
+    assert g4["stats"]["speculative"] == 0
+    _same(g4, fresh)
+    g5, _ = _gpu.run(ps2, precision, ctx=ctx)
+    assert g5["stats"]["speculative"] == 1
+    _same(g5, fresh)
