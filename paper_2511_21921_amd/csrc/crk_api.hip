@@ -448,11 +448,11 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   ctx->ell = P.box / 1024.0;
   ctx->cells_G = 0;  // the Morton sort below takes the key buffers
   {
-    // room for ~5x the expected neighbour count (4 pi / 3) n_h^3 before a
+    // room for ~4x the expected neighbour count (4 pi / 3) n_h^3 before a
     // radius shrinks (the cell path's capacity is its own: it is set again
     // there)
     const double expect = 4.18879 * P.n_h * P.n_h * P.n_h;
-    ctx->scr_cap = std::max(320, (int)((5.0 * expect + 31.0) / 32.0) * 32);
+    ctx->scr_cap = std::max(256, (int)((4.0 * expect + 31.0) / 32.0) * 32);
   }
   // levels of the implicit tree over the leaves
   const int nleaf = (int)((n + kLeaf - 1) / kLeaf);

@@ -367,7 +367,11 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
   wave_max_u64(cnt_at(S.cnt, CNT_HMAX_OUT_BITS), hbits);
 }
 
-constexpr int kStage = 320;  // LDS staging capacity of a row, in entries
+// LDS staging capacity of a row, in entries: 16 KB a block of 16 rows, which
+// leaves room in the LDS for the eight blocks per CU the registers allow
+// (320 entries gave six, and the search took 68.9 ms at clumps256 against
+// 66.4 with 256 and the retries of its larger overflow)
+constexpr int kStage = 256;
 
 // Candidates of every unsolved particle within its own radius ri (their
 // indices, in ascending j), kept contiguous in the candidate pool from entry
