@@ -51,7 +51,7 @@ struct crk_ctx {
   std::string err;
   // workspace
   Buf keys_a, keys_b, vals_a, vals_b, cell_start, sort_tmp, scan_tmp;
-  Buf pos4, vel4, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, slist, ng, ns, scr_r, scr_m,
+  Buf pv, mass, uu, hbuf, Vbuf, st4, gv4, kc4, mom, nlist, slist, ng, ns, scr_r, scr_m,
       cand, ccnt, cell3;
   Buf cnt;
   // tree path
@@ -232,8 +232,7 @@ hipError_t ensure_particles(crk_ctx* c, int64_t n) {
   ENS(vals_a, 4 * npad);
   ENS(vals_b, 4 * npad);
   ENS(sort_tmp, 4 * (size_t)radix_tmp_words(n));
-  ENS(pos4, 4 * R * npad);
-  ENS(vel4, 4 * R * npad);
+  ENS(pv, 8 * R * npad);
   ENS(mass, R * npad);
   ENS(uu, R * npad);
   ENS(hbuf, R * npad);
@@ -263,8 +262,7 @@ State<R> make_state(crk_ctx* c, int64_t n) {
   S.keys = (const uint32_t*)c->keys_a.p;
   S.cell_start = (const uint32_t*)c->cell_start.p;
   S.cell3 = (uint32_t*)c->cell3.p;
-  S.pos4 = (R4<R>*)c->pos4.p;
-  S.vel4 = (R4<R>*)c->vel4.p;
+  S.pv = (R4<R>*)c->pv.p;
   S.mass = (R*)c->mass.p;
   S.uu = (R*)c->uu.p;
   S.hbuf = (R*)c->hbuf.p;
@@ -1438,7 +1436,7 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
   if (n_max == 0) return CRK_OK;
   // a buffer that grows is reallocated: the state kept for crk_backward is
   // then gone
-  const void* before[] = {ctx->pos4.p, ctx->vel4.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
+  const void* before[] = {ctx->pv.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
                           ctx->mom.p, ctx->nlist.p, ctx->slist.p, ctx->ng.p, ctx->ns.p,
                           ctx->vals_a.p, ctx->cell3.p, ctx->mass.p, ctx->uu.p, ctx->hbuf.p,
                           ctx->Vbuf.p};
@@ -1449,7 +1447,7 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
   if (e == hipSuccess)
     e = ensure(ctx->scr_r, real_size(ctx->p.precision) * (size_t)npad * ctx->scr_cap);
   if (e == hipSuccess) e = ensure(ctx->cand, 4 * (size_t)npad * ctx->scr_cap);
-  const void* after[] = {ctx->pos4.p, ctx->vel4.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
+  const void* after[] = {ctx->pv.p, ctx->st4.p, ctx->kc4.p, ctx->gv4.p,
                          ctx->mom.p, ctx->nlist.p, ctx->slist.p, ctx->ng.p, ctx->ns.p,
                          ctx->vals_a.p, ctx->cell3.p, ctx->mass.p, ctx->uu.p, ctx->hbuf.p,
                          ctx->Vbuf.p};
@@ -1465,7 +1463,7 @@ crk_status crk_reserve(crk_ctx* ctx, long long n_max) {
 crk_status crk_destroy(crk_ctx* c) {
   if (!c) return CRK_OK;
   Buf* all[] = {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->cell_start,
-                &c->sort_tmp, &c->scan_tmp, &c->pos4, &c->vel4, &c->mass, &c->uu, &c->hbuf,
+                &c->sort_tmp, &c->scan_tmp, &c->pv, &c->mass, &c->uu, &c->hbuf,
                 &c->Vbuf, &c->st4, &c->gv4, &c->kc4, &c->mom, &c->nlist, &c->slist, &c->ng, &c->ns,
                 &c->scr_r, &c->scr_m, &c->cand, &c->ccnt, &c->cell3, &c->cnt, &c->vpred, &c->upred,
                 &c->hl_vh, &c->hl_uh, &c->hl_hdot, &c->hl_acc, &c->hl_du, &c->hl_need, &c->hl_act, &c->hl_hist,

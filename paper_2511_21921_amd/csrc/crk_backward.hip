@@ -68,8 +68,8 @@ __device__ inline void load_gv4(const State<R>& S, int64_t j, R gv[9], R& relaxe
 template <class R>
 __device__ inline void load_side(const State<R>& S, const AdjState<R>& G, int64_t j,
                                  PairSide<R>& o, R& relaxed) {
-  const R4<R> p = S.pos4[j];
-  const R4<R> v = S.vel4[j];
+  const R4<R> p = S.pos(j);
+  const R4<R> v = S.vel(j);
   const R4<R> st = S.st4[j];
   const R4<R> w = G.wgt4[j];
   load_kc4(S, j, o.kc);
@@ -155,13 +155,13 @@ __global__ void __launch_bounds__(kBlock) k_bwd_force(State<R> S, AdjState<R> G)
     __shared__ uint4 eslot[kBlock];  // the lane's list chunk (registers are scarce here)
     const NbrRef nb = nbr_ref(S, s);
     const int ng = nb.ng, ns = nb.ns;
-    const R4<R> pi = S.pos4[s];
+    const R4<R> pi = S.pos(s);
     for (int t = 0; t < ng + ns; ++t) {
       const uint32_t e = nbr_entry_lds(S, nb, t, &eslot[threadIdx.x]);
       const uint32_t j = e >> kCodeBits;
       load_side(S, G, j, J, relj);
       R x[3];
-      pair_x(S, s, pi, S.pos4[j], e, x);
+      pair_x(S, s, pi, S.pos(j), e, x);
       const bool plain = relax_on && (reli != R(0) || relj != R(0));
       if (plain) {
         kc_plain(I.kc);
@@ -229,8 +229,8 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
-  const R4<R> pi = S.pos4[s];
-  const R4<R> vi = S.vel4[s];
+  const R4<R> pi = S.pos(s);
+  const R4<R> vi = S.vel(s);
   const R mi = S.mass[s];
   KC<R> ki;
   load_kc4(S, s, ki);
@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   for (int t = 0; t < ng; ++t) {
     const uint32_t e = gather_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
-    const R4<R> vj = S.vel4[j];
+    const R4<R> pj = S.pos(j);
+    const R4<R> vj = S.vel(j);
     R x[3];
     pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
@@ -278,14 +278,14 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
   for (int t = 0; t < ng + ns; ++t) {
     const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
+    const R4<R> pj = S.pos(j);
     R x[3];
     pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
     if (!(r2 * (pj.w * pj.w) < R(1))) continue;
     const R rinv = Sc<R>::rsqrt(r2);
     const R r = r2 * rinv;
-    const R4<R> vj = S.vel4[j];
+    const R4<R> vj = S.vel(j);
     const R vij[3] = {vi.x - vj.x, vi.y - vj.y, vi.z - vj.z};
     KC<R> kj;
     load_kc4(S, j, kj);
@@ -307,22 +307,22 @@ __global__ void __launch_bounds__(kBlock) k_bwd_density(State<R> S, AdjState<R> 
 // Raw moment sums of particle s (the forward's k_moments accumulation).
 template <class R, int K>
 __device__ inline void moments_raw(const State<R>& S, int64_t s, double raw[40]) {
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R hinv = pi.w;
   R acc[40];
   for (int t = 0; t < 40; ++t) acc[t] = R(0);
   R W0, dW0;
   kernel_self<R, K>(hinv, W0, dW0);
-  acc[0] = S.vel4[s].w * W0;
+  acc[0] = S.vel(s).w * W0;
   const NbrRef nb = nbr_ref(S, s);
   uint4 ebuf;
   const int ng = nb.ng;
   for (int k = 0; k < ng; ++k) {
     const uint32_t e = gather_entry(S, nb, k, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R Vj = S.vel4[j].w;
+    const R Vj = S.vel(j).w;
     R x[3];
-    pair_x(S, s, pi, S.pos4[j], e, x);
+    pair_x(S, s, pi, S.pos(j), e, x);
     const R r2 = dot3b(x, x);
     const R rinv = Sc<R>::rsqrt(r2);
     R w, dw;
@@ -378,8 +378,8 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
-  const R4<R> pi = S.pos4[s];
-  const R Vi = S.vel4[s].w;
+  const R4<R> pi = S.pos(s);
+  const R Vi = S.vel(s).w;
   const R mi = S.mass[s];
   R mb[40];
   load_mom(G, s, mb);
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   for (int t = 0; t < ng; ++t) {
     const uint32_t e = gather_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
+    const R4<R> pj = S.pos(j);
     R x[3];
     pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
     kernel_eval<R, K>(r, rinv, pi.w, ev);
     R gx[3], gh;
     mom_pair_adj<R>(mb, x, rinv, ev, gx, gh);
-    const R Vj = S.vel4[j].w;
+    const R Vj = S.vel(j).w;
     for (int a = 0; a < 3; ++a) xb[a] += (double)(Vj * gx[a]);
     hb += (double)(Vj * gh);
     sh += (double)(S.mass[j] * ev.dWdh);
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_moments(State<R> S, AdjState<R> 
   for (int t = 0; t < ng + ns; ++t) {
     const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
+    const R4<R> pj = S.pos(j);
     R x[3];
     pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
   const int64_t s = particle_id();
   if (s >= S.n) return;
   const int64_t n = S.n;
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R mi = S.mass[s];
   const R ki = G.kap[s];
   double xb[3] = {0, 0, 0};
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd_volume(State<R> S, AdjState<R> G
   for (int t = 0; t < ng + ns; ++t) {
     const uint32_t e = nbr_entry(S, nb, t, ebuf);
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
+    const R4<R> pj = S.pos(j);
     R x[3];
     pair_x(S, s, pi, pj, e, x);
     const R r2 = dot3b(x, x);

@@ -228,13 +228,13 @@ __global__ void __launch_bounds__(kBlock) k_gather(State<R> S, const double* __r
   q.y = xi[1];
   q.z = xi[2];
   q.w = R(c[0]);  // the cell's x index until the h solve is done (then 1/h)
-  S.pos4[s] = q;
+  S.pos(s) = q;
   R4<R> w;
   w.x = v[p];
   w.y = v[n + p];
   w.z = v[2 * n + p];
   w.w = R(0);
-  S.vel4[s] = w;
+  S.vel(s) = w;
   S.mass[s] = m[p];
   S.uu[s] = u[p];
   S.hbuf[s] = h[p];
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
     return;
   }
   if (S.act) return;  // a listed active particle: k_candidates_rows
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
   const R rc2 = S.rcap * S.rcap;
   int cap;
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
   // cell is convex in dx), and consecutive cells of a row hold consecutive
   // particles, so the run is one contiguous range of particles (split where
   // the row wraps), read four at a time with the loads in flight together.
-  // A particle's cell within the run comes from the x index kept in pos4.w.
+  // A particle's cell within the run comes from the x index kept in its position record's w.
   // Accepted candidates are shifted into four registers per array and
   // written as one 16-byte store per array every fourth one: the lanes of a
   // wave run their tests in step, so whatever the accept path costs, the
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates(State<R> S) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const uint32_t j = j0 + u < e ? j0 + u : e - 1;
-        pj[u] = S.pos4[j];
+        pj[u] = S.pos(j);
         if (!EM) mj[u] = S.mass[j];
       }
       __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of their first use
@@ -549,8 +549,8 @@ __global__ void __launch_bounds__(kBlock) k_pack(State<R> S, R* __restrict__ h_o
   const uint32_t p = S.perm[s];
   const bool pas = is_passive(S, s);
   const R h = S.hbuf[s], V = pas ? S.pV[p] : S.Vbuf[s];
-  S.pos4[s].w = R(1) / h;
-  S.vel4[s].w = V;
+  S.pos(s).w = R(1) / h;
+  S.vel(s).w = V;
   if (!h_out || pas) return;  // an input still (a speculative forward), or stored
   h_out[p] = h;
   V_out[p] = V;
@@ -649,9 +649,9 @@ struct Moments {
 template <class R, int K>
 __device__ __forceinline__ void moments_start(const State<R>& S, int64_t s, bool self,
                                               Moments<R>& M) {
-  const R hinv = S.pos4[s].w;
+  const R hinv = S.pos(s).w;
   const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
-  M.m0 = self ? S.vel4[s].w * C3 * R(Shape<K>::w0) : R(0);
+  M.m0 = self ? S.vel(s).w * C3 * R(Shape<K>::w0) : R(0);
 #pragma unroll
   for (int t = 0; t < 3; ++t) M.m1[t] = M.dm0[t] = R(0);
 #pragma unroll
@@ -668,8 +668,8 @@ template <class R, int K>
 __device__ __forceinline__ void moment_term(const State<R>& S, int64_t s, const R4<R>& pi,
                                             R hinv, R C3, R C4, uint32_t e, Moments<R>& M) {
   const uint32_t j = e >> kCodeBits;
-  const R4<R> pj = S.pos4[j];
-  const R Vj = S.vel4[j].w;
+  const R4<R> pj = S.pos(j);
+  const R Vj = S.vel(j).w;
   R x[3];
   pair_x(S, s, pi, pj, e, x);
   const R r2 = dot3(x, x);
@@ -698,7 +698,7 @@ __device__ __forceinline__ void moment_term(const State<R>& S, int64_t s, const 
 
 template <class R, int K>
 __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<R>& M) {
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R hinv = pi.w;
   const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
   const R C4 = C3 * hinv;
@@ -715,7 +715,7 @@ __device__ inline void accumulate_moments(const State<R>& S, int64_t s, Moments<
 template <class R, int K>
 __device__ inline void accumulate_moments_row(const State<R>& S, int64_t s, int sub,
                                               Moments<R>& M) {
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R hinv = pi.w;
   const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
   const R C4 = C3 * hinv;
@@ -971,8 +971,8 @@ __device__ inline void load_gv(const State<R>& S, int64_t j, R gv[9], R& relaxed
 // (the self term with k0 = 0): Num, Den and the nine grad v sums.
 template <class R, int K, int DK>
 __device__ inline void density_sums(const State<R>& S, int64_t s, int k0, R sums[11]) {
-  const R4<R> pi = S.pos4[s];
-  const R4<R> vi = S.vel4[s];
+  const R4<R> pi = S.pos(s);
+  const R4<R> vi = S.vel(s);
   const R hinv = pi.w;
   const R C3 = R(Shape<K>::C) * hinv * hinv * hinv;
   const R C4 = C3 * hinv;
@@ -991,8 +991,8 @@ __device__ inline void density_sums(const State<R>& S, int64_t s, int k0, R sums
   for (int k = k0; k < ng; k += DK) {
     const uint32_t e = DK == 1 ? gather_entry(S, nb, k, ebuf) : S.nlist[slot_at(nb.gb, k)];
     const uint32_t j = e >> kCodeBits;
-    const R4<R> pj = S.pos4[j];
-    const R4<R> vj = S.vel4[j];
+    const R4<R> pj = S.pos(j);
+    const R4<R> vj = S.vel(j);
     const R mj = S.mass[j];
     R x[3];
     pair_x(S, s, pi, pj, e, x);
@@ -1168,8 +1168,8 @@ __device__ __forceinline__ void force_term(const State<R>& S, int64_t s, const R
                                            R alpha, R beta, R eps2, uint32_t e, double acc[3],
                                            double& du) {
   const uint32_t j = e >> kCodeBits;
-  const R4<R> pj = S.pos4[j];
-  const R4<R> vj = S.vel4[j];
+  const R4<R> pj = S.pos(j);
+  const R4<R> vj = S.vel(j);
   const R4<R> sj = S.st4[j];
   KC<R> kj;
   load_kc(S, j, kj);
@@ -1233,8 +1233,8 @@ __global__ void __launch_bounds__(kBlock) k_force(State<R> S, double* __restrict
   const int64_t s = particle_id();
   if (s >= S.n) return;
   if (HIER && (is_passive(S, s) || S.act)) return;  // (a list of active: k_force_rows)
-  const R4<R> pi = S.pos4[s];
-  const R4<R> vi = S.vel4[s];
+  const R4<R> pi = S.pos(s);
+  const R4<R> vi = S.vel(s);
   const R4<R> si = S.st4[s];
   KC<R> ki;
   load_kc(S, s, ki);
@@ -1269,8 +1269,8 @@ __global__ void __launch_bounds__(kBlock) k_force_rows(State<R> S, double* __res
   const int sub = threadIdx.x & 15;
   if (r >= (int64_t)S.cnt[CNT_ACTLIST * kCntSpread]) return;  // the whole row
   const int64_t s = S.act[r];
-  const R4<R> pi = S.pos4[s];
-  const R4<R> vi = S.vel4[s];
+  const R4<R> pi = S.pos(s);
+  const R4<R> vi = S.vel(s);
   const R4<R> si = S.st4[s];
   KC<R> ki;
   load_kc(S, s, ki);
@@ -1333,7 +1333,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_rows(State<R> S) {
   const uint64_t rowbits = 0xFFFFull << (lane & 48);
   const uint64_t below = rowbits & ((1ull << lane) - 1ull);
   const int64_t s = S.act[r];
-  const R4<R> pi = S.pos4[s];
+  const R4<R> pi = S.pos(s);
   const R mi_inv = EM ? R(1) : R(1) / S.mass[s];
   const R rc2 = S.rcap * S.rcap;
   int cap;
@@ -1359,7 +1359,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_rows(State<R> S) {
     for (uint32_t j0 = b; j0 < e; j0 += 16) {
       const uint32_t j = j0 + (uint32_t)sub;
       const bool valid = j < e;
-      const R4<R> pj = S.pos4[valid ? j : e - 1];
+      const R4<R> pj = S.pos(valid ? j : e - 1);
       const int dx = (int)pj.w + xoff;
       R x[3];
       x[0] = (pi.x - pj.x) - R(dx) * ell;

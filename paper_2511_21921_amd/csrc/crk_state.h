@@ -82,9 +82,11 @@ struct State {
   const uint32_t* keys;        // sorted cell keys
   const uint32_t* cell_start;  // [G^3 + 1]
   uint32_t* cell3;             // packed cell coordinates x | y << 10 | z << 20
-  // sorted particle data
-  R4<R>* pos4;  // (xi_x, xi_y, xi_z, 1/h)
-  R4<R>* vel4;  // (v_x, v_y, v_z, V)
+  // sorted particle data: position and velocity records side by side, so
+  // that a neighbour's pair (one aligned 2 x Real4) is one fetch
+  R4<R>* pv;    // [2 i]: (xi_x, xi_y, xi_z, 1/h); [2 i + 1]: (v_x, v_y, v_z, V)
+  __device__ R4<R>& pos(int64_t i) const { return pv[2 * i]; }
+  __device__ R4<R>& vel(int64_t i) const { return pv[2 * i + 1]; }
   R* mass;
   R* uu;
   R* hbuf;      // h (in: input or guess)

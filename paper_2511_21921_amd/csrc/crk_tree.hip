@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_leaf_boxes(State<R> S, const R* __re
   float lo[3] = {3e30f, 3e30f, 3e30f}, hi[3] = {-3e30f, -3e30f, -3e30f}, hm = 0.f;
   for (int64_t s = b; s < e; ++s) {
     float v[3];
-    abs_pos(S, S.cell3[s], S.pos4[s], v);
+    abs_pos(S, S.cell3[s], S.pos(s), v);
     absp[s] = make_float4(v[0], v[1], v[2], 0.f);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -146,13 +146,13 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
   R r = S.hbuf[sc];
   if (h_mode != 0) {
     const int lane = threadIdx.x & 63;
-    const R4<R> pi = S.pos4[sc];
+    const R4<R> pi = S.pos(sc);
     const uint32_t ci = S.cell3[sc];
     const int64_t b = wave * 64;
     const int cnt = (int)((b + 64 < S.n ? b + 64 : S.n) - b);
     // the wave's particles, broadcast to its lanes one at a time
     const int64_t jl = b + (lane < cnt ? lane : 0);
-    const R4<R> pl = S.pos4[jl];
+    const R4<R> pl = S.pos(jl);
     const int cl = (int)S.cell3[jl];
     float d[8];
 #pragma unroll
@@ -240,13 +240,13 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
     // the distance and mass ratio of kept entry e, as the candidate pass
     // computed them (the same separation arithmetic, so the same bits)
     const int64_t sc = s < S.n ? s : 0;
-    const R4<R> pi = S.pos4[sc];
+    const R4<R> pi = S.pos(sc);
     const uint32_t ci = S.cell3[sc];
     const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
     auto entry = [&](int e, R& r, R& mr) {
       const uint32_t j = S.cand[base + (e < cnt ? e : 0)] >> kCodeBits;
       R x[3];
-      lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+      lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
       r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
       mr = EM ? R(1) : S.mass[j] * mi_inv;
     };
@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   int np = 0, cnt = 0;  // uniform over the row
   if (__ballot(mine) != 0ull) {
     const R ri = mine ? S.rad[sc] : R(0);
-    const R4<R> pi = S.pos4[sc];
+    const R4<R> pi = S.pos(sc);
     const uint32_t ci = S.cell3[sc];
     int cap = 0;
     int64_t base = 0;
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         const bool in = e < np;
         const uint32_t j = in ? get(e) : (uint32_t)sc;
         R x[3];
-        lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+        lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
         const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const bool keep = in && r2 < r2cap && j != (uint32_t)s;
         // every lane of the row has read its entry (the ballot waits on
@@ -710,7 +710,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
   const int cnt = active ? S.ccnt[sc] : 0;  // uniform over the row
   const int64_t base = 4 * (int64_t)S.cpos[sc];
   const R h = S.hbuf[sc];
-  const R4<R> pi = S.pos4[sc];
+  const R4<R> pi = S.pos(sc);
   const uint32_t ci = S.cell3[sc];
   int64_t gb = 0;
   if (WRITE) gb = slot_base(S.grow[sc >> 6], sc);
@@ -721,7 +721,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
     const uint32_t ent = S.cand[base + (in ? e : 0)];
     const uint32_t j = in ? ent >> kCodeBits : (uint32_t)sc;
     R x[3];
-    lattice_sep(S, pi, ci, S.pos4[j], S.cell3[j], x);
+    lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
     const R r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     const bool g = in && r < h;
     const uint64_t b = __ballot(g) & rowbits;
