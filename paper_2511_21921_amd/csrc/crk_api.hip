@@ -59,6 +59,7 @@ struct crk_ctx {
   // tree path candidate pool: entries the last forward's rounds took, and the
   // placement of the current round (see State::pool_base4)
   size_t pool_hint = 0;
+  size_t adj_bytes = 0;  // the adjoint workspace carved from the pool (last backward)
   int64_t pool_base4 = 0;
   int64_t pool_cap = 0;
   uint32_t host_rows[2] = {};
@@ -542,8 +543,13 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
     }
     if (stage) {
       // room for every round, from what the last forward's rounds took (at
-      // first twice the expected neighbour count per particle)
-      const size_t want = std::max(ctx->pool_hint, (size_t)((double)n * 2.0 * expect) + 4096);
+      // first 2.5 times the expected neighbour count per particle, which
+      // leaves the retry rounds room enough not to grow the pool), and for
+      // the adjoint workspace carved from it; a pool an eighth or more
+      // larger than that is given back first
+      size_t want = ctx->pool_hint ? ctx->pool_hint : (size_t)((double)n * 2.5 * expect) + 4096;
+      want = std::max(want, (ctx->adj_bytes + 3) / 4);
+      if (ctx->cand.bytes > 4 * (want + want / 8)) release(ctx->cand);
       CRK_HIP(ensure(ctx->cand, 4 * want), "alloc candidates");
       CRK_HIP(hipMemsetAsync(dcnt + CNT_POOL * kCntSpread, 0, 8 * kCntSpread, s), "memset");
       ctx->pool_base4 = 0;
@@ -1036,6 +1042,7 @@ crk_status backward_impl(crk_ctx* ctx, hipStream_t s, int64_t n, const double* g
   if (!base) {
     CRK_HIP(ensure(ctx->cand, total), "adjoint workspace");
     base = (unsigned char*)ctx->cand.p;
+    ctx->adj_bytes = total;
   }
   for (int k = 0; k < kAdjArrays; ++k) ptr[k] = base + off[k];
   // no timing events on the allocation-free path (creating them allocates)
