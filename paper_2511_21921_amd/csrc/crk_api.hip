@@ -553,7 +553,10 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       CRK_HIP(ensure(ctx->cand, 4 * want), "alloc candidates");
       CRK_HIP(hipMemsetAsync(dcnt + CNT_POOL * kCntSpread, 0, 8 * kCntSpread, s), "memset");
       ctx->pool_base4 = 0;
-      ctx->pool_cap = (int64_t)(ctx->cand.bytes / 4) & ~(int64_t)3;
+      // (candidate positions are kept in 4-entry units in 32 bits: a larger
+      // pool leaves the rest to the retry rounds, which check their sizes)
+      ctx->pool_cap = std::min<int64_t>((int64_t)(ctx->cand.bytes / 4), ((int64_t)1 << 34) - 4) &
+                      ~(int64_t)3;
       staged = true;
     } else {
       const int64_t add4 = ctx->host_rows[1];

@@ -121,3 +121,23 @@ def test_tree_empty_input():
     out = ctx.forward(x[:, :0].contiguous(), v[:, :0].contiguous(), m[:0], u[:0], h[:0],
                       stats=True)
     assert out["stats"]["n_pairs_force"] == 0
+
+
+def test_tree_candidate_pool_that_must_grow():
+    """A context whose candidate pool was sized by a forward on a uniform set
+    with 16 neighbours per particle: the next forward, on clumps with more,
+    fills the pool in its first round, the blocks that find it full leave
+    their particles to the retry rounds (which grow it), and the results
+    equal a fresh context's."""
+    first = synth.random_small(20000, 64, n_ngb=16)
+    ps = _clumps(20000, 8, 63)
+    print("case uniform 20000 (16 neighbours) then clumps 20000 seed 63", flush=True)
+    _, ctx = _gpu.run(first, FP64, search=TREE)  # sizes the pool
+    ctx.set_params(_gpu.params_for(ps, FP64, search=TREE))
+    b, _ = _gpu.run(ps, FP64, ctx=ctx)
+    c, _ = _gpu.run(ps, FP64, search=TREE)
+    for k in ("h", "V", "rho", "accel", "dudt"):
+        assert np.abs(b[k] - c[k]).max() <= 1e-11 * np.abs(c[k]).max(), k
+    assert b["stats"]["n_pairs_force"] == c["stats"]["n_pairs_force"]
+    print("searched", b["stats"]["n_searched"], c["stats"]["n_searched"], flush=True)
+    assert b["stats"]["n_searched"] > c["stats"]["n_searched"]  # the full pool's retries
