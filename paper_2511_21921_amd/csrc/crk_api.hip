@@ -66,7 +66,7 @@ struct crk_ctx {
   int lvl_off[crk::kMaxLevels] = {}, lvl_cnt[crk::kMaxLevels] = {};
   int nlevels = 0;
   int lattice = 0;
-  // (the adjoint workspace is carved from the candidate scratch)
+  // (the adjoint workspace is carved from the candidate scratch or pool)
   // time step: the velocity and energy predicted for the end-of-step evaluation
   Buf vpred, upred;
   // timestep hierarchy: half-kicked velocity and energy, hdot, and the
@@ -434,8 +434,8 @@ crk_status build_cells(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x,
 
 // Tree path: Morton order over the 1024^3 lattice, search leaves of kLeaf
 // particles, per-particle candidate radii adapted until every h is bracketed;
-// the candidates of every particle are kept (rounds append to the scratch)
-// and its gather list is filtered from them.
+// the candidates of every particle are kept (rounds append to the candidate
+// pool) and its gather list is filtered from them.
 template <class R>
 crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, const R* v,
                       const R* m, const R* u, const R* h) {

@@ -12,9 +12,9 @@
 // sphere: a step tests the children of one node (one per lane) and keeps, as
 // bits of one 64-bit word, the children still to visit at each level, so the
 // walk needs no stack. The particles of a reached leaf are tested one per
-// lane. Candidates within a particle's radius are kept with their index and
-// distance: the h solve reads the distances, and the gather list is the
-// candidates within the solved h.
+// lane. Candidates within a particle's radius are kept as indices, each
+// particle's contiguous in one pool: the h solve recomputes their distances,
+// and the gather list is the candidates within the solved h.
 #include "crk_passes.h"
 
 namespace crk {
