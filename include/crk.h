@@ -161,6 +161,9 @@ const char *crk_last_error(const crk_ctx *ctx);
  * the counters once at the end; when they show that the careful order would
  * have chosen differently (another grid, clustering, an overflow, a capped h
  * root), it runs again the careful way. Either way the outputs are the same.
+ * Such a forward keeps the last cell list, without sorting again, once a
+ * check has found that no particle had left its cell; a particle that has
+ * left it since makes that forward run again the careful way.
  * n = 0 is a no-op returning CRK_OK. Input and output arrays must not
  * overlap. The context keeps the cell list, neighbour list and the sorted
  * intermediates for a following crk_backward. After a status other than
@@ -180,7 +183,10 @@ crk_status crk_forward(crk_ctx *ctx, void *hip_stream, long long n, const double
  *   g_alpha_beta [2]                            output (device, double)
  * With h_mode 1 the smoothing lengths are functions of the positions (the
  * implicit-function term is included); with h_mode 0 they are constants.
- * Masses are constants. Returns CRK_EINVAL if no matching forward exists. */
+ * Masses are constants. Returns CRK_EINVAL if no matching forward exists.
+ * The adjoint workspace (428 bytes per FP32 particle, 656 per FP64 one) is
+ * carved from the forward's candidate scratch, which is dead once the lists
+ * are built, and grows it when smaller. */
 crk_status crk_backward(crk_ctx *ctx, void *hip_stream, long long n, const double *g_accel,
                         const double *g_dudt, double *g_x, double *g_v, double *g_u,
                         double *g_alpha_beta);
@@ -273,9 +279,13 @@ crk_status crk_kdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
  * outside [0, 30], a refinement that breaks the rules above, null arrays
  * (refine_level null with refine_at given) or n above 2^25 - 1; otherwise those of
  * crk_forward, from any substep (after such an error the arrays may hold a
- * partly advanced state). The call reads the device a few times per substep
- * (the level range once, the refinements once, then the forward's checks).
- * n = 0 is a no-op. */
+ * partly advanced state). The call reads the device once for the level
+ * range and the particles per level, once for the refinements, then once per
+ * substep (the forward's check at its end, when the substep's forward keeps
+ * the cell list and geometry of the one before; more when it must run the
+ * careful way). A substep whose end finds few particles active (at most
+ * 32,768, counted from the levels) gives each of them a 16-lane row in every
+ * pass. n = 0 is a no-op. */
 crk_status crk_hkdk_step(crk_ctx *ctx, void *hip_stream, long long n, double dt,
                          double thacker_lambda, const int *levels, const int *refine_at,
                          const int *refine_level, double *x, void *v, const void *m, void *u,
