@@ -141,3 +141,19 @@ def test_tree_candidate_pool_that_must_grow():
     assert b["stats"]["n_pairs_force"] == c["stats"]["n_pairs_force"]
     print("searched", b["stats"]["n_searched"], c["stats"]["n_searched"], flush=True)
     assert b["stats"]["n_searched"] > c["stats"]["n_searched"]  # the full pool's retries
+
+
+@pytest.mark.parametrize("precision", [FP32, FP64])
+def test_tree_bitwise_deterministic(precision):
+    """Two fresh contexts on the same clumps give bitwise equal outputs: the
+    candidate pool's block placement and the scatter-only lists' fill order
+    follow the order of atomics, but every list is sorted (in registers, or
+    in LDS when long) before the pair passes sum over it."""
+    ps = _clumps(20000, 8, 65)
+    print("case clumps 20000 seed 65 precision=%d" % precision, flush=True)
+    a, _ = _gpu.run(ps, precision)
+    b, _ = _gpu.run(ps, precision)
+    assert a["stats"]["grid"] == 1024
+    for k in ("h", "V", "rho", "A", "B", "gradA", "gradB", "gradv", "accel", "dudt"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["stats"]["n_pairs_force"] > a["stats"]["n_pairs_gather"]  # scatter-only entries
