@@ -303,6 +303,58 @@ def test_relaxed_pairs_reduce_to_textbook_sph(oracle_lib):
     assert np.abs(a - o["accel"]).max() < 1e-12 * o["scale_a"].max()
 
 
+@pytest.mark.parametrize("h_mode", [0, 1])
+def test_compatible_energy_splits_work_equally(oracle_lib, h_mode):
+    """Compatible energy (Sec. 2.1): each pair's work (v_i - v_j).F_ij goes half to i, half to j.
+
+    With the viscosity off F_ij does not depend on v. Move one particle k with
+    w and hold the rest: the heat w.(m_k a_k) taken from k's kinetic energy
+    lands half on k and half on its neighbours together, -1/2 w.(m_k a_k) each.
+    Any other split (by P/rho^2, by mass) moves the mover's share off one half.
+    """
+    ps = synth.random_small(500, 21, mass_spread=0.5)
+    ps.h_mode = h_mode
+    p = oracle_lib.params_for(ps, alpha=0.0, beta=0.0)
+    zero = np.zeros_like(ps.x)
+    base = oracle_lib.forward(ps.x, zero, ps.m, ps.u, ps.h, p)
+    assert np.abs(base["dudt"]).max() == 0.0
+    rng = np.random.default_rng(5)
+    for k in rng.choice(ps.n, 4, replace=False):
+        v = zero.copy()
+        v[:, k] = rng.normal(size=3)
+        o = oracle_lib.forward(ps.x, v, ps.m, ps.u, ps.h, p)
+        assert np.abs(o["accel"] - base["accel"]).max() == 0.0
+        work = float(v[:, k] @ (ps.m[k] * o["accel"][:, k]))
+        assert abs(work) > 0
+        mdu = ps.m * o["dudt"]
+        assert abs(mdu[k] + 0.5 * work) <= 1e-12 * abs(work)
+        others = np.delete(mdu, k)
+        assert abs(others.sum() + 0.5 * work) <= 1e-12 * abs(work)
+        assert np.count_nonzero(others) >= 10
+
+
+def test_relaxed_pairs_compatible_energy_is_textbook(oracle_lib):
+    """Relaxed pairs (App. A.1): du_i/dt = -1/(2 m_i) sum_j (v_i - v_j).F_ij with textbook F_ij."""
+    ps = synth.random_small(300, 13)
+    ps.h_mode = 0
+    v = np.random.default_rng(2).normal(size=ps.x.shape)
+    p = oracle_lib.params_for(ps, alpha=0.0, beta=0.0, dt_relax=1e3)
+    o = oracle_lib.forward(ps.x, v, ps.m, ps.u, ps.h, p)
+    assert o["relaxed"] == ps.n
+    sym = oracle_lib.neighbours(ps.x, ps.h, kind=1, lists=True)
+    du = np.zeros(ps.n)
+    for i in range(ps.n):
+        js = sym[i]
+        if len(js) == 0:
+            continue
+        d = _pins.min_image(ps.x[:, [i]], ps.x[:, js], 1.0)
+        r = np.sqrt((d ** 2).sum(0))
+        g = 0.5 * (_pins.dWdr(r, ps.h[i]) + _pins.dWdr(r, ps.h[js])) * d / r
+        F = -o["V"][i] * o["V"][js] * (o["P"][i] + o["P"][js]) * g
+        du[i] = -0.5 * ((v[:, [i]] - v[:, js]) * F).sum() / ps.m[i]
+    assert np.abs(du - o["dudt"]).max() < 1e-12 * o["scale_u"].max()
+
+
 def test_equation_of_state(oracle_lib):
     ps = synth.random_small(200, 14)
     o = _fwd(oracle_lib, ps)
