@@ -427,6 +427,12 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   __shared__ uint4 stage4[STAGE ? kBlock / 16 : 1][STAGE ? kStage / 4 : 1];
   __shared__ uint32_t rcnt[kBlock / 16];
   __shared__ unsigned long long rbase[kBlock / 16];
+  // each wave's frontiers of the shared walk (the level being expanded and
+  // the next one)
+  constexpr int kFront = 32;
+  constexpr float kSharedReach = 4.0f;  // largest common radius over the rows' largest
+  __shared__ uint32_t front[kBlock / 64][2][kFront];
+  static_assert(kFan == 8, "the shared walk takes 8 frontier nodes of 8 children a step");
   const int64_t tid = particle_id();
   // a wave whose four rows are past the end leaves at once, unless the
   // block's barriers below still need it
@@ -498,6 +504,18 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         }
         return g2;
       };
+      auto gap_at = [&](float4 c, float4 w, const float* Q) {  // box2 from point Q
+        const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
+        float g2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float d = cc[a] - Q[a];
+          if constexpr (WRAP) d -= L * rintf(d * inv_L);
+          const float g = fmaxf(fabsf(d) - ww[a], 0.f);
+          g2 += g * g;
+        }
+        return g2;
+      };
       auto point2 = [&](float4 c) {  // squared distance to point c
         const float cc[3] = {c.x, c.y, c.z};
         float d2 = 0.f;
@@ -537,9 +555,159 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         nbuf = 0;
       };
       const int top = S.nlevels - 1;
+      auto wave_sync = [&]() {  // the wave's LDS writes before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
+      // The four rows of a wave walk the levels above the leaves together,
+      // breadth first, for one sphere that holds their four (centre C on
+      // their mean, radius Ru): a step tests the children of up to eight
+      // frontier nodes, one per lane, and compacts the reached ones, in
+      // order, into the next level's frontier. A box that a row's sphere
+      // reaches is reached by this sphere (triangle inequality, padded beyond
+      // the FP32 rounding), and so are all the boxes above it, which hold
+      // it. The level-1 children of the reached level-2 nodes are kept when
+      // one of the rows' own spheres reaches them, and each row tests the
+      // leaves of the kept ones against its own sphere (two nodes a step, a
+      // leaf per lane) and queues the reached leaves: the leaves and the
+      // order of its own walk, in far fewer steps (the rows' walks take one
+      // node a step, on half of their lanes, and the wave as many steps as
+      // its longest walk). Taken while the common sphere stays within
+      // kSharedReach times the rows' largest radius (consecutive particles
+      // of the first round lie well within it); rows further apart, or a
+      // frontier that outgrows its buffer before any leaf is queued, walk
+      // alone.
+      auto shared_walk = [&]() -> bool {
+        float C[3] = {0.f, 0.f, 0.f}, Q0[3];
+        float rq[4], off[4][3];
+        int f = -1, nm = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          rq[r] = __shfl(rp, 16 * r);  // -1 for a row without a particle
+          if (rq[r] > 0.f && f < 0) f = r;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Q0[a] = __shfl(P[a], 16 * (f < 0 ? 0 : f));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float d = __shfl(P[a], 16 * r) - Q0[a];
+            if constexpr (WRAP) d -= L * rintf(d * inv_L);
+            off[r][a] = rq[r] > 0.f ? d : 0.f;
+            C[a] += off[r][a];
+          }
+          nm += rq[r] > 0.f ? 1 : 0;
+        }
+        float Ru = 0.f, rmax = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) C[a] /= (float)(nm > 0 ? nm : 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float e2 = 0.f;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) e2 += (off[r][a] - C[a]) * (off[r][a] - C[a]);
+          if (rq[r] > 0.f) {
+            Ru = fmaxf(Ru, sqrtf(e2) + rq[r]);
+            rmax = fmaxf(rmax, rq[r]);
+          }
+        }
+        if (!(nm > 0 && Ru <= kSharedReach * rmax)) return false;
+        Ru = Ru * 1.00001f + 4e-6f * L;
+        const float Ru2 = Ru * Ru;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) C[a] += Q0[a];
+        auto boxu = [&](float4 c, float4 w) {  // squared gap from C to the box
+          const float cc[3] = {c.x, c.y, c.z}, ww[3] = {w.x, w.y, w.z};
+          float g2 = 0.f;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float d = cc[a] - C[a];
+            if constexpr (WRAP) d -= L * rintf(d * inv_L);
+            const float g = fmaxf(fabsf(d) - ww[a], 0.f);
+            g2 += g * g;
+          }
+          return g2;
+        };
+        const uint64_t lt = (1ull << lane) - 1ull;  // the wave's lanes before this one
+        uint32_t* fa_buf = front[threadIdx.x >> 6][0];
+        uint32_t* fb_buf = front[threadIdx.x >> 6][1];
+        // the reached children (level cl) of frontier nodes k0 .. k0 + 7,
+        // lane 8 k + c taking child c of node k0 + k; node index per lane
+        auto expand = [&](int k0, int fa, int cl, uint32_t& ch) -> bool {
+          const int k = k0 + (lane >> 3);
+          const bool vk = k < fa;
+          ch = fa_buf[vk ? k : 0] * (uint32_t)kFan + (uint32_t)(lane & 7);
+          const bool valid = vk && ch < (uint32_t)lv.cnt[cl];
+          const int node = lv.off[cl] + (valid ? (int)ch : 0);
+          return valid && boxu(S.ncen[node], S.nhw[node]) < Ru2;
+        };
+        int fa = 1;  // the root
+        if (lane == 0) fa_buf[0] = 0u;
+        wave_sync();
+        for (int lvl = top; lvl > 2; --lvl) {
+          int fb = 0;
+          for (int k0 = 0; k0 < fa; k0 += 8) {
+            uint32_t ch;
+            const bool reach = expand(k0, fa, lvl - 1, ch);
+            const uint64_t m = __ballot(reach);
+            const int at = fb + __popcll(m & lt);
+            if (reach && at < kFront) fb_buf[at] = ch;
+            fb += __popcll(m);
+          }
+          wave_sync();
+          if (fb > kFront) return false;
+          uint32_t* t = fa_buf;
+          fa_buf = fb_buf;
+          fb_buf = t;
+          fa = fb;
+        }
+        // fa_buf: the reached level-2 nodes, ascending. Their children (the
+        // level-1 nodes), one per lane, are kept when a row's own sphere
+        // reaches them (the bits of m); every row then tests the leaves of
+        // the kept nodes against its own sphere, two nodes a step (lanes
+        // 8-15 take the second), a leaf per lane.
+        for (int k0 = 0; k0 < fa; k0 += 8) {
+          const int k = k0 + (lane >> 3);
+          const bool vk = k < fa;
+          const uint32_t ch = fa_buf[vk ? k : 0] * (uint32_t)kFan + (uint32_t)(lane & 7);
+          const bool valid = vk && ch < (uint32_t)lv.cnt[1];
+          const int node = lv.off[1] + (valid ? (int)ch : 0);
+          const float4 bc = S.ncen[node], bw = S.nhw[node];
+          bool any = false;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float Qr[3] = {__shfl(P[0], 16 * r), __shfl(P[1], 16 * r),
+                                 __shfl(P[2], 16 * r)};
+            const float rr = __shfl(rp, 16 * r);
+            any = any || (rr > 0.f && gap_at(bc, bw, Qr) < rr * rr);
+          }
+          uint64_t m = __ballot(valid && any);
+          while (m != 0ull) {
+            const int b1 = __builtin_ctzll(m);
+            m &= m - 1;
+            const int b2 = m != 0ull ? __builtin_ctzll(m) : 64;
+            if (m != 0ull) m &= m - 1;
+            const int bb = sub < 8 ? b1 : b2;
+            const int bs = bb < 64 ? bb : b1;
+            const uint32_t l1 = fa_buf[k0 + (bs >> 3)] * (uint32_t)kFan + (uint32_t)(bs & 7);
+            const uint32_t leaf = l1 * (uint32_t)kFan + (uint32_t)(sub & 7);
+            const bool ok = mine && bb < 64 && leaf < (uint32_t)lv.cnt[0];
+            const int ln = lv.off[0] + (ok ? (int)leaf : 0);
+            const bool h = ok && box2(S.ncen[ln], S.nhw[ln]) < rp2;
+            const uint64_t hb = __ballot(h) & rowbits;
+            if (h) rbuf[nbuf + __popcll(hb & below)] = leaf;
+            nbuf += __popcll(hb);
+            if (__ballot(nbuf > kRowBuf - 16) != 0ull) drain();
+          }
+        }
+        return true;
+      };
+      const bool shared = top >= 2 && shared_walk();
       int cur = 0, cur_level = top;  // the node whose children are tested next
       uint64_t pend = 0;             // children still to visit, bit 8 l + c at level l
-      bool walking = mine && top > 0;
+      bool walking = !shared && mine && top > 0;
       if (mine && top == 0) {
         if (sub == 0) rbuf[0] = 0;
         nbuf = 1;
