@@ -11,8 +11,9 @@
 // its index one level down). A particle's 16-lane row walks the tree for its
 // sphere: a step tests the children of one node (one per lane) and keeps, as
 // bits of one 64-bit word, the children still to visit at each level, so the
-// walk needs no stack. The particles of a reached leaf are tested one per
-// lane. Candidates within a particle's radius are kept as indices, each
+// walk needs no stack (the four rows of a wave, consecutive particles, walk
+// the levels above the leaves together, breadth first, on all 64 lanes). The
+// particles of a reached leaf are tested one per lane. Candidates within a particle's (padded) radius are kept as indices, each
 // particle's contiguous in one pool: the h solve recomputes their distances,
 // and the gather list is the candidates within the solved h.
 #include "crk_passes.h"
@@ -190,7 +191,9 @@ __global__ void __launch_bounds__(kBlock) k_init_radius(State<R> S, int h_mode) 
     const double pad = 0.5 * S.ell_d;  // coincident lattice cells have no volume
     const double vol = ((double)(hi[0] - lo[0]) + pad) * ((double)(hi[1] - lo[1]) + pad) *
                        ((double)(hi[2] - lo[2]) + pad);
-    double est = cbrt(S.n_h3 * vol / (double)cnt);
+    // (a wave of fewer than nine particles, the ragged last one, tells
+    // nothing of the density: the mean density's h then)
+    double est = cnt >= 9 ? cbrt(S.n_h3 * vol / (double)cnt) : cbrt(S.n_h3 / (double)S.n) * S.box;
     if (cnt >= 9)  // (4 pi / 24)^(1/3)
       est = fmin(est, cbrt(S.n_h3) * sqrt((double)d[7]) * 0.80599597700823482);
     est = fmin(est, 1.5 * cbrt(S.n_h3 / (double)S.n) * S.box);
@@ -237,14 +240,21 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
       cnt = S.ccnt[s];
     }
     const int ngroups = (cnt + 15) >> 4;
-    // the distance and mass ratio of kept entry e, as the candidate pass
-    // computed them (the same separation arithmetic, so the same bits)
+    // the distance and mass ratio of kept entry e, from the exact
+    // separation (lattice offsets, as every later pass computes it)
     const int64_t sc = s < S.n ? s : 0;
     const R4<R> pi = S.pos(sc);
     const uint32_t ci = S.cell3[sc];
     const R mi_inv = EM ? R(1) : R(1) / S.mass[sc];
+    // Lanes past the count load entry 0 of the row, or of the pool when the
+    // row has no entry (the word at its position is then another row's or
+    // was never written); the index is clamped below n, so that whatever
+    // such a lane loaded addresses a particle (its terms are discarded).
+    const int64_t at0 = cnt > 0 ? base : 0;
+    const uint32_t jmax = (uint32_t)(S.n - 1);
     auto entry = [&](int e, R& r, R& mr) {
-      const uint32_t j = S.cand[base + (e < cnt ? e : 0)] >> kCodeBits;
+      const uint32_t w = S.cand[e < cnt ? base + e : at0] >> kCodeBits;
+      const uint32_t j = w < jmax ? w : jmax;
       R x[3];
       lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
       r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -252,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
     };
     R rk[kRegGroups], mk[kRegGroups];
     // all slots at once, without branches, so that their loads are in
-    // flight together (slots past the count read entry 0 and stay unused)
+    // flight together (slots past the count stay unused)
 #pragma unroll
     for (int it = 0; it < kRegGroups; ++it) entry(16 * it + sub, rk[it], mk[it]);
     auto sums = [&](R h, R& dsum) {
@@ -373,17 +383,20 @@ __global__ void __launch_bounds__(kBlock) k_hsolve_rows(State<R> S,
 // 66.4 with 256 and the retries of its larger overflow)
 constexpr int kStage = 256;
 
-// Candidates of every unsolved particle within its own radius ri (their
+// Candidates of every unsolved particle: the j != s whose FP32 absolute
+// position lies within its radius ri padded beyond the FP32 rounding (their
 // indices, in ascending j), kept contiguous in the candidate pool from entry
-// 4 cpos[s]. A 16-lane row takes one particle (order null: row t takes
-// particle t; else order[t], the unsolved particles of a retry round in rank
-// order). Two phases, which work in the row's room (room_for(need[s])
-// entries at pool_base4 + coff4[s]), or (STAGE) in the row's LDS stage of scr_cap
-// entries, after which every block takes the room its rows' kept candidates
-// need from the pool's bump counter and copies them there (a block that
-// finds the pool full leaves its particles to the next round, with room of
-// their own):
-//  1. The row walks the tree for the particle's sphere: a step tests the
+// 4 cpos[s]. They hold every j with r_ij < ri and at most a thin shell
+// beyond it, which adds nothing to the sums or lists of any h <= ri: the h
+// solve and the list filter compute the exact separations themselves. A
+// 16-lane row takes one particle (order null: row t takes particle t; else
+// order[t], the unsolved particles of a retry round in rank order). It works
+// in the row's room (room_for(need[s]) entries at pool_base4 + coff4[s]), or
+// (STAGE) in the row's LDS stage of scr_cap entries, after which every block
+// takes the room its rows' candidates need from the pool's bump counter and
+// copies them there (a block that finds the pool full leaves its particles
+// to the next round, with room of their own).
+//    The row walks the tree for the particle's sphere: a step tests the
 //     kFan children of the current node one per lane (a child is entered
 //     when the sphere, padded beyond the FP32 rounding, reaches its box),
 //     records the reached children as bits of pend (8 bits per level) and
@@ -395,9 +408,6 @@ constexpr int kStage = 256;
 //     particles are tested one per lane against the padded sphere as
 //     absolute FP32 positions; the passed indices are appended in order
 //     (prefix counts over the row's ballot).
-//  2. The row takes 16 passed indices at a time, one per lane, computes the
-//     separation exactly (lattice offsets, as every later pass does) and
-//     compacts those within ri in place.
 // A particle whose passed indices overflow its capacity is counted: the next
 // round takes the radius that would hold 1.3 (4 pi / 3) n_h^3 of them at the
 // density seen (at least half of ri), with capacity for 1.3 times what that
@@ -423,7 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
   __syncthreads();
   constexpr int kRowBuf = 32;  // leaves a row queues between drains
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
-  // STAGE: every row's passed indices, then its kept candidates, in LDS
+  // STAGE: every row's passed indices (its candidates), in LDS
   __shared__ uint4 stage4[STAGE ? kBlock / 16 : 1][STAGE ? kStage / 4 : 1];
   __shared__ uint32_t rcnt[kBlock / 16];
   __shared__ unsigned long long rbase[kBlock / 16];
@@ -470,19 +480,13 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
       else
         S.cand[base + at] = v;
     };
-    auto get = [&](int at) -> uint32_t {
-      if constexpr (STAGE)
-        return srow[at];
-      else
-        return S.cand[base + at];
-    };
     float P[3];
     abs_pos(S, ci, pi, P);
     const float L = (float)S.box;
     const float inv_L = 1.0f / L;
     const float rp = mine ? pad_radius((float)ri, L) : -1.f;
     const float rp2 = mine ? rp * rp : -1.f;
-    // ---- phase 1: walk, padded tests, passed indices in order ----
+    // ---- the walk and the padded tests, passed indices in order ----
     // A sphere that stays a padded radius away from every face of the box
     // reaches no periodic image (box centres and positions lie in the box),
     // so its tests need no nearest-image shift; rows whose sphere crosses a
@@ -532,10 +536,10 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
         const bool valid = sub < m;
         const int64_t j = j0 + (valid ? sub : 0);
-        const bool pass = valid && point2(absp[j]) < rp2;
+        const bool pass = valid && j != s && point2(absp[j]) < rp2;
         const uint64_t b = __ballot(pass) & rowbits;
         const int at = np + __popcll(b & below);
-        if (pass && at < cap) put(at, (uint32_t)j);
+        if (pass && at < cap) put(at, (uint32_t)j << kCodeBits);
         np += __popcll(b);
       };
       // Reached leaves are queued per row in LDS and tested by all rows in
@@ -745,30 +749,9 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
       phase1(std::false_type());
     else
       phase1(std::true_type());
-    // ---- phase 2: exact separations, 16 passed indices at a time ----
+    // every passed index fitted the row's room: they are its candidates
     fits = mine && np <= cap;
-    if constexpr (STAGE) {  // the row's entries, written by its lanes, read by the row
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (fits) {
-      const R r2cap = ri * ri;
-      for (int k = 0; k < np; k += 16) {
-        const int e = k + sub;
-        const bool in = e < np;
-        const uint32_t j = in ? get(e) : (uint32_t)sc;
-        R x[3];
-        lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
-        const R r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        const bool keep = in && r2 < r2cap && j != (uint32_t)s;
-        // every lane of the row has read its entry (the ballot waits on
-        // it); a kept entry moves to a position at or before its own
-        const uint64_t b = __ballot(keep) & rowbits;
-        if (keep) put(cnt + __popcll(b & below), j << kCodeBits);
-        cnt += __popcll(b);
-      }
-    }
+    if (fits) cnt = np;
     if (mine && sub == 0) {
       if (np > cap && S.shrink && S.rad[S.n + s] == R(0)) {
         const double want = 1.3 * 4.18879020478639098 * S.n_h3;

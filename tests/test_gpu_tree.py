@@ -114,6 +114,20 @@ def test_tree_fixed_h_unequal_masses():
     assert g["stats"]["n_pairs_force"] == o["pairs_force"]
 
 
+def test_tree_particle_without_candidates():
+    """Fixed h, one particle farther than h from every other: its row keeps no
+    candidate at all, and the h solve and the list filter read no entry of the
+    pool for it (the word at its position belongs to another row or was never
+    written). Regression test: reading it as a particle index went out of bounds."""
+    ps = synth.random_small(2000, 92, mass_spread=0.1)
+    ps.h_mode = 0
+    ps.x[0] *= 0.5
+    ps.x[:, 0] = (0.75, 0.5, 0.5)
+    g, o, _ = _compare(ps, FP64, FP64_BOUNDS, search=TREE)
+    assert g["stats"]["n_pairs_force"] == o["pairs_force"]
+    assert g["stats"]["m2_singular"] == 1
+
+
 def test_tree_empty_input():
     ps = synth.random_small(300, 91)
     g, ctx = _gpu.run(ps, FP32, search=TREE)
