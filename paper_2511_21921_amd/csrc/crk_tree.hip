@@ -486,6 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     const float inv_L = 1.0f / L;
     const float rp = mine ? pad_radius((float)ri, L) : -1.f;
     const float rp2 = mine ? rp * rp : -1.f;
+    const uint32_t n32 = (uint32_t)S.n, s32 = (uint32_t)s;
     // ---- the walk and the padded tests, passed indices in order ----
     // A sphere that stays a padded radius away from every face of the box
     // reaches no periodic image (box centres and positions lie in the box),
@@ -531,16 +532,17 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         }
         return d2;
       };
-      auto test_leaf = [&](int64_t leaf) {
-        const int64_t j0 = leaf * kLeaf;
-        const int m = (int)(S.n - j0 < kLeaf ? S.n - j0 : kLeaf);
-        const bool valid = sub < m;
-        const int64_t j = j0 + (valid ? sub : 0);
-        const bool pass = valid && j != s && point2(absp[j]) < rp2;
+      // (32-bit indices: the tree path takes fewer than 2^25 particles; absp
+      // has a whole number of waves of entries, so the last leaf's padding
+      // is loaded too, and its tests discarded, without a branch)
+      auto test_leaf = [&](uint32_t leaf) {
+        const uint32_t j = leaf * (uint32_t)kLeaf + (uint32_t)sub;
+        const float4 a = absp[j];
+        const bool pass = (j < n32) & (j != s32) & (point2(a) < rp2);
         const uint64_t b = __ballot(pass) & rowbits;
         const int at = np + __popcll(b & below);
-        if (pass && at < cap) put(at, (uint32_t)j << kCodeBits);
-        np += __popcll(b);
+        if (pass && at < cap) put(at, j << kCodeBits);
+        np += __popc((uint32_t)(b >> (lane & 48)));
       };
       // Reached leaves are queued per row in LDS and tested by all rows in
       // step (a row's q-th queued leaf at step q), so that a wave's leaf tests
