@@ -111,7 +111,8 @@ typedef struct {
                                and was accepted by its single end-of-call check */
   long long n_candidates;   /* candidate pairs the neighbour search kept: the cell list's
                                pairs within the cut of the solved h; the tree's pairs
-                               within each search radius, summed over its retry rounds */
+                               within each search radius (padded beyond the FP32 rounding
+                               of the leaf tests), summed over its retry rounds */
   long long n_searched;     /* particles the neighbour search launches took (n per cell-list
                                search; the particles of every tree round) */
 } crk_stats;
