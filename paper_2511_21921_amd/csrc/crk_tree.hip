@@ -535,10 +535,9 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
       // (32-bit indices: the tree path takes fewer than 2^25 particles; absp
       // has a whole number of waves of entries, so the last leaf's padding
       // is loaded too, and its tests discarded, without a branch)
-      auto test_leaf = [&](uint32_t leaf) {
-        const uint32_t j = leaf * (uint32_t)kLeaf + (uint32_t)sub;
-        const float4 a = absp[j];
-        const bool pass = (j < n32) & (j != s32) & (point2(a) < rp2);
+      // (the test of particle j at position a; on: the lane has a leaf)
+      auto test_at = [&](bool on, uint32_t j, float4 a) {
+        const bool pass = on & (j < n32) & (j != s32) & (point2(a) < rp2);
         const uint64_t b = __ballot(pass) & rowbits;
         const int at = np + __popcll(b & below);
         if (pass && at < cap) put(at, j << kCodeBits);
@@ -555,8 +554,16 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int q = 0; __ballot(q < nbuf) != 0ull; ++q)
-          if (q < nbuf) test_leaf(rbuf[q]);
+        // two queued leaves a step, their position loads in flight together
+        // (a row past its queue takes leaf 0 and discards its tests)
+        for (int q = 0; __ballot(q < nbuf) != 0ull; q += 2) {
+          const bool on0 = q < nbuf, on1 = q + 1 < nbuf;
+          const uint32_t j0 = (on0 ? rbuf[q] : 0u) * (uint32_t)kLeaf + (uint32_t)sub;
+          const uint32_t j1 = (on1 ? rbuf[q + 1] : 0u) * (uint32_t)kLeaf + (uint32_t)sub;
+          const float4 a0 = absp[j0], a1 = absp[j1];
+          test_at(on0, j0, a0);
+          test_at(on1, j1, a1);
+        }
         __builtin_amdgcn_wave_barrier();  // the reads above before the next writes
         nbuf = 0;
       };
