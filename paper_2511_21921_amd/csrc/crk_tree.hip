@@ -875,19 +875,16 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
   int64_t gb = 0;
   if (WRITE) gb = slot_base(S.grow[sc >> 6], sc);
   int ng = 0;  // uniform over the row
-  for (int k = 0; k < cnt; k += 16) {
-    const int e = k + sub;
-    const bool in = e < cnt;
-    const uint32_t ent = S.cand[base + (in ? e : 0)];
-    const uint32_t j = in ? ent >> kCodeBits : (uint32_t)sc;
+  // one group of 16 entries, one per lane, from its loaded records
+  auto group = [&](bool in, uint32_t ent, uint32_t j, const R4<R>& pj, uint32_t cj, R hj) {
     R x[3];
-    lattice_sep(S, pi, ci, S.pos(j), S.cell3[j], x);
+    lattice_sep(S, pi, ci, pj, cj, x);
     const R r = Sc<R>::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     const bool g = in && r < h;
     const uint64_t b = __ballot(g) & rowbits;
     if (WRITE && g) S.nlist[slot_at(gb, ng + __popcll(b & below))] = ent;
     ng += __popcll(b);
-    if (g && !(r < S.hbuf[j])) {  // this particle is in j's scatter-only list
+    if (g && !(r < hj)) {  // this particle is in j's scatter-only list
       if (WRITE) {
         const int u = atomicAdd(&fillc[j], 1);
         const int64_t wj = (int64_t)(j >> 6);
@@ -897,6 +894,21 @@ __global__ void __launch_bounds__(kBlock) k_filter_tree(State<R> S, int* __restr
         atomicAdd(&S.ns[j], 1);
       }
     }
+  };
+  // two groups a step, every load of both issued before either is used
+  // (lanes past the count take entry 0 of the row, whose records they
+  // load and discard: the row has an entry whenever the loop runs)
+  for (int k = 0; k < cnt; k += 32) {
+    const int e0 = k + sub, e1 = k + 16 + sub;
+    const bool in0 = e0 < cnt, in1 = e1 < cnt;
+    const uint32_t ent0 = S.cand[base + (in0 ? e0 : 0)];
+    const uint32_t ent1 = S.cand[base + (in1 ? e1 : 0)];
+    const uint32_t j0 = ent0 >> kCodeBits, j1 = ent1 >> kCodeBits;
+    const R4<R> p0 = S.pos(j0), p1 = S.pos(j1);
+    const uint32_t c0 = S.cell3[j0], c1 = S.cell3[j1];
+    const R h0 = S.hbuf[j0], h1 = S.hbuf[j1];
+    group(in0, ent0, j0, p0, c0, h0);
+    group(in1, ent1, j1, p1, c1, h1);
   }
   unsigned long long gsum = 0;
   if (active && sub == 0) {
