@@ -502,10 +502,12 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   // Rounds over the particles still unsolved. Each round ranks them (scan of
   // the todo flags, todo[n] = 0), runs the candidate walk and the h solve (or
   // the volume for fixed h) on them, and stops when none is left. The first
-  // round stages every row in LDS when its capacity fits there, and the
-  // blocks append the kept candidates to the pool; the others give each
-  // particle the room it asks for after what the earlier rounds took (the
-  // solved particles keep their candidates where they are).
+  // two rounds stage every row in LDS when its capacity fits there, and the
+  // blocks append the candidates to the pool (the second after what the
+  // first took; a row of the second whose candidates outgrow its stage, as
+  // one whose radius was grown may, is left to the third); the later rounds
+  // give each particle the room it asks for after what the earlier rounds
+  // took (the solved particles keep their candidates where they are).
   int* todo = (int*)ctx->todo.p;
   uint32_t* slot = (uint32_t*)ctx->tslot.p;
   uint32_t* need4 = (uint32_t*)ctx->need4.p;
@@ -517,7 +519,7 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
   unsigned long long pool_taken = 0;
   bool solved = false;
   for (int round = 0; round < 40; ++round) {
-    const bool stage = round == 0 && stage_fits(ctx->scr_cap);
+    const bool stage = stage_fits(ctx->scr_cap) && (round == 0 || (round == 1 && ctx->pool_cap > 0));
     CRK_HIP(exclusive_scan_u32((const uint32_t*)todo, slot, n + 1, (uint32_t*)ctx->scan_tmp.p,
                                s),
             "scan");
@@ -541,7 +543,9 @@ crk_status tree_solve(crk_ctx* ctx, hipStream_t s, int64_t n, const double* x, c
       solved = true;
       break;
     }
-    if (stage) {
+    if (stage && round > 0) {
+      staged = true;  // the pool and its counter go on from the first round
+    } else if (stage) {
       // room for every round, from what the last forward's rounds took (at
       // first 2.5 times the expected neighbour count per particle, which
       // leaves the retry rounds room enough not to grow the pool), and for
