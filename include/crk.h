@@ -92,7 +92,7 @@ typedef struct {
   int timing;        /* 1: time every pass with HIP events (see crk_pass_times) */
   int search;        /* neighbour search: 0 automatic, 1 periodic cell list (cells of at least
                         0.625 x the largest h, a 5x5x5 stencil), 2 tree of Morton-ordered
-                        64-particle leaves (for smoothing lengths spanning orders of
+                        16-particle leaves (for smoothing lengths spanning orders of
                         magnitude); automatic uses the cell list unless a cell holds more
                         than max(1024, 16 x the mean occupancy) particles or a particle more
                         than max(1024, 16 x the expected count) candidates */

@@ -1,6 +1,6 @@
 """GPU parity of the tree neighbour search (clustered particle sets).
 
-The tree path (Morton-ordered 64-particle leaves over a 1024^3 lattice) must
+The tree path (Morton-ordered 16-particle leaves over a 1024^3 lattice) must
 give the same results as the cell-list path and the oracle: the same bounds
 as test_gpu_forward.py, forced on uniform inputs and chosen automatically on
 Plummer-clump inputs whose smoothing lengths span more than an order of
@@ -91,6 +91,20 @@ def test_tree_and_cell_list_agree_fp64():
     for k in ("h", "V", "rho", "accel", "dudt"):
         assert np.abs(a[k] - b[k]).max() <= 1e-11 * np.abs(a[k]).max(), k
     assert a["stats"]["n_pairs_force"] == b["stats"]["n_pairs_force"]
+
+
+def test_tree_and_cell_list_agree_many_neighbours():
+    """~1000 neighbours on 100,000 uniform particles, FP64. The common sphere of a wave's
+    four rows reaches many level-2 nodes (a frontier that outgrows its buffer sends the rows
+    on alone), and every row takes hundreds of candidates: tree and cell list must give the
+    same pairs and outputs."""
+    ps = synth.random_small(100000, 93, n_ngb=1000)
+    a, _ = _gpu.run(ps, FP64, search=1)
+    b, _ = _gpu.run(ps, FP64, search=TREE)
+    for k in ("h", "V", "rho", "accel", "dudt"):
+        assert np.abs(a[k] - b[k]).max() <= 1e-11 * np.abs(a[k]).max(), k
+    assert a["stats"]["n_pairs_force"] == b["stats"]["n_pairs_force"]
+    assert b["stats"]["grid"] == 1024
 
 
 @pytest.mark.parametrize("n", [37, 64, 129])
