@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_candidates_tree(State<R> S,
     lv.cnt[t] = S.lvl_off[kMaxLevels + t];
   }
   __syncthreads();
-  constexpr int kRowBuf = 32;  // leaves a row queues between drains
+  constexpr int kRowBuf = 40;  // leaves a row queues between drains (the block then takes 20 KB of LDS: eight blocks per CU)
   __shared__ uint32_t lbuf[kBlock / 16][kRowBuf];
   // STAGE: every row's passed indices (its candidates), in LDS
   __shared__ uint4 stage4[STAGE ? kBlock / 16 : 1][STAGE ? kStage / 4 : 1];
