@@ -396,17 +396,20 @@ constexpr int kStage = 256;
 // takes the room its rows' candidates need from the pool's bump counter and
 // copies them there (a block that finds the pool full leaves its particles
 // to the next round, with room of their own).
-//    The row walks the tree for the particle's sphere: a step tests the
-//     kFan children of the current node one per lane (a child is entered
-//     when the sphere, padded beyond the FP32 rounding, reaches its box),
-//     records the reached children as bits of pend (8 bits per level) and
-//     moves to the deepest pending one, so the walk needs no stack. Reached
-//     leaves are queued per row in LDS and tested by all rows of the wave in
-//     step (a row's q-th queued leaf at step q), so that the wave's leaf
-//     tests take as many steps as its longest queue rather than, step by
-//     step of the walk, the most leaves any row reached. A leaf's 16
-//     particles are tested one per lane against the padded sphere as
-//     absolute FP32 positions; the passed indices are appended in order
+//    The four rows of a wave walk the levels above level 1 together, breadth
+//     first, for a sphere holding their four (see shared_walk below), and
+//     each row then tests the leaves of the level-1 nodes its own sphere
+//     reaches. Rows far apart walk alone: a step tests the kFan children of
+//     the current node one per lane (a child is entered when the sphere,
+//     padded beyond the FP32 rounding, reaches its box), records the reached
+//     children as bits of pend (8 bits per level) and moves to the deepest
+//     pending one, so the walk needs no stack. Either way reached leaves are
+//     queued per row in LDS and tested by all rows of the wave in step, two
+//     a step (a row's q-th and (q+1)-th queued leaves at step q / 2), so that
+//     the wave's leaf tests take as many steps as its longest queue rather
+//     than, step by step of the walk, the most leaves any row reached. A
+//     leaf's 16 particles are tested one per lane against the padded sphere
+//     as absolute FP32 positions; the passed indices are appended in order
 //     (prefix counts over the row's ballot).
 // A particle whose passed indices overflow its capacity is counted: the next
 // round takes the radius that would hold 1.3 (4 pi / 3) n_h^3 of them at the
